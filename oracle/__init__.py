@@ -1,0 +1,199 @@
+"""FP64 CPU oracle of the differentiable rigid-body step (test infrastructure).
+
+Only the test-suite, the smoke check and the benchmark's CPU-baseline leg may
+import this package.  The product library never does: it has its own host
+code and kernels and shares nothing with this oracle except the seeded input
+generators in ``paper_1611_01652_amd.workloads``.
+
+Parity pins: see tests/test_oracle_*.py (closed forms, invariants, LCP brute
+force, finite differences).  The 20-sweep sweep order and the warm start are
+readings of the paper (it fixes neither); those carry no external pin beyond
+the K -> infinity limits, which reach the order-independent LCP solution.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with the host compiler (g++, -O2, FP64)."""
+    if force or not os.path.exists(_LIB):
+        cmd = ["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-fno-fast-math", "-o", _LIB + ".tmp",
+               os.path.join(_HERE, "oracle.cpp"), "-lpthread"]
+        subprocess.check_call(cmd)
+        os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        _lib = C.CDLL(_LIB)
+        dp, ip = C.POINTER(C.c_double), C.POINTER(C.c_int)
+        _lib.oracle_lambda_size.argtypes = [C.c_void_p, ip]
+        _lib.oracle_order.argtypes = [C.c_void_p, C.c_int, ip, ip, C.c_int]
+        _lib.oracle_step.argtypes = [C.c_void_p, dp, dp, dp, dp, dp, C.c_int]
+        _lib.oracle_rollout.argtypes = [C.c_void_p, dp, dp, dp, dp, dp, C.c_int]
+        _lib.oracle_rollout_grad.argtypes = [C.c_void_p, dp, dp, dp, dp, dp, dp, dp, dp, dp, dp, C.c_int]
+        _lib.oracle_count_flops.argtypes = [C.c_void_p, C.c_int, dp, dp, dp, C.c_int]
+        _lib.oracle_count_flops.restype = C.c_longlong
+    return _lib
+
+
+class _Model(C.Structure):
+    _fields_ = [
+        ("n_envs", C.c_int),
+        ("env_body_off", C.c_void_p), ("env_joint_off", C.c_void_p), ("env_sphere_off", C.c_void_p),
+        ("inv_mass", C.c_void_p), ("inv_inertia", C.c_void_p),
+        ("sphere_body", C.c_void_p), ("sphere_offset", C.c_void_p), ("sphere_radius", C.c_void_p),
+        ("sphere_flags", C.c_void_p),
+        ("joint_parent", C.c_void_p), ("joint_child", C.c_void_p),
+        ("anchor_p", C.c_void_p), ("anchor_c", C.c_void_p), ("axis_p", C.c_void_p), ("axis_c", C.c_void_p),
+        ("perp_p", C.c_void_p), ("perp_c", C.c_void_p), ("damping", C.c_void_p),
+        ("mu", C.c_void_p), ("loss_body", C.c_void_p), ("target", C.c_void_p), ("T_env", C.c_void_p),
+        ("u", C.c_void_p), ("u_stride", C.c_int), ("T_max", C.c_int),
+        ("dt", C.c_double), ("gravity", C.c_double * 3), ("beta", C.c_double), ("gamma", C.c_double),
+        ("spec_margin", C.c_double),
+        ("n_iters", C.c_int), ("ground", C.c_int), ("loss_kind", C.c_int), ("loss_mask", C.c_int),
+        ("ctrl_kind", C.c_int),
+        ("mlp_in", C.c_int), ("mlp_h1", C.c_int), ("mlp_h2", C.c_int), ("mlp_out", C.c_int),
+        ("mlp_n_params", C.c_int), ("mlp_w", C.c_void_p), ("clock_hz", C.c_double),
+        ("warm", C.c_double),
+    ]
+
+
+def _dp(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double)) if a is not None else None
+
+
+class Oracle:
+    """Wraps one workload; arrays are converted to float64/int32 once."""
+
+    def __init__(self, w, mlp=None):
+        self.w = w
+        keep = {}
+
+        def d(name, a):
+            keep[name] = np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+            return keep[name].ctypes.data
+
+        def i(name, a):
+            keep[name] = np.ascontiguousarray(np.asarray(a, dtype=np.int32))
+            return keep[name].ctypes.data
+
+        m = _Model()
+        m.n_envs = w.n_envs
+        m.env_body_off = i("ebo", w.env_body_off)
+        m.env_joint_off = i("ejo", w.env_joint_off)
+        m.env_sphere_off = i("eso", w.env_sphere_off)
+        m.inv_mass = d("im", w.inv_mass)
+        m.inv_inertia = d("ii", w.inv_inertia)
+        m.sphere_body = i("sb", w.sphere_body)
+        m.sphere_offset = d("so", w.sphere_offset)
+        m.sphere_radius = d("sr", w.sphere_radius)
+        m.sphere_flags = i("sf", w.sphere_flags)
+        m.joint_parent = i("jp", w.joint_parent)
+        m.joint_child = i("jc", w.joint_child)
+        for k in ("anchor_p", "anchor_c", "axis_p", "axis_c", "perp_p", "perp_c", "damping"):
+            setattr(m, k, d(k, getattr(w, k)))
+        m.mu = d("mu", w.mu)
+        m.loss_body = i("lb", w.loss_body)
+        m.target = d("tg", w.target)
+        m.T_env = i("te", w.T_env)
+        if w.u is not None and w.u.size:
+            m.u = d("u", w.u)
+            m.u_stride = w.u.shape[1]
+        else:
+            m.u = d("u", np.zeros(1))
+            m.u_stride = 0
+        m.T_max = w.T_max
+        m.dt = w.dt
+        m.gravity = (C.c_double * 3)(*w.gravity)
+        m.beta, m.gamma, m.spec_margin = w.beta, w.gamma, w.spec_margin
+        m.n_iters, m.ground, m.loss_kind, m.loss_mask = w.n_iters, w.ground, w.loss_kind, w.loss_mask
+        if mlp is not None:
+            m.ctrl_kind = 1
+            m.mlp_in, m.mlp_h1, m.mlp_h2, m.mlp_out = mlp["sizes"]
+            m.mlp_n_params = len(mlp["w"])
+            m.mlp_w = d("mlpw", mlp["w"])
+            m.clock_hz = mlp.get("clock_hz", 1.5)
+        else:
+            m.ctrl_kind = 0
+            m.mlp_w = d("mlpw", np.zeros(1))
+        m.warm = getattr(w, 'warm', 1.0)
+        self._m = m
+        self._keep = keep
+        self.lib = _load()
+        offs = np.zeros(w.n_envs + 1, dtype=np.int32)
+        self.lam_size = self.lib.oracle_lambda_size(C.byref(m), offs.ctypes.data_as(C.POINTER(C.c_int)))
+        self.lam_offsets = offs
+
+    def order(self, env):
+        kinds = np.zeros(4096, np.int32)
+        idx = np.zeros(4096, np.int32)
+        n = self.lib.oracle_order(C.byref(self._m), env, kinds.ctypes.data_as(C.POINTER(C.c_int)),
+                                  idx.ctypes.data_as(C.POINTER(C.c_int)), 4096)
+        return list(zip(kinds[:n].tolist(), idx[:n].tolist()))
+
+    def step(self, x, lam=None, u=None, t=0):
+        w = self.w
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        lam = np.zeros(self.lam_size) if lam is None else np.ascontiguousarray(lam, dtype=np.float64)
+        u = np.zeros(max(w.n_joints, 1)) if u is None else np.ascontiguousarray(u, dtype=np.float64)
+        if u.size == 0:
+            u = np.zeros(1)
+        xn = np.zeros_like(x)
+        ln = np.zeros(max(self.lam_size, 1))
+        lam_in = lam if lam.size else np.zeros(1)
+        self.lib.oracle_step(C.byref(self._m), _dp(x), _dp(lam_in), _dp(u), _dp(xn), _dp(ln), int(t))
+        return xn, ln[: self.lam_size]
+
+    def rollout(self, x0=None, traj=False, threads=None):
+        w = self.w
+        x0 = np.ascontiguousarray(w.x0 if x0 is None else x0, dtype=np.float64)
+        loss = np.zeros(w.n_envs)
+        xf = np.zeros_like(x0)
+        lf = np.zeros(max(self.lam_size, 1))
+        tr = np.zeros((w.T_max + 1, w.n_bodies, 18)) if traj else None
+        self.lib.oracle_rollout(C.byref(self._m), _dp(x0), _dp(loss), _dp(xf), _dp(lf), _dp(tr),
+                                threads or os.cpu_count() or 1)
+        out = dict(loss=loss, x_final=xf, lam_final=lf[: self.lam_size])
+        if traj:
+            out["traj"] = tr
+        return out
+
+    def rollout_grad(self, dloss=None, x0=None, threads=None):
+        w = self.w
+        x0 = np.ascontiguousarray(w.x0 if x0 is None else x0, dtype=np.float64)
+        dloss = np.ones(w.n_envs) if dloss is None else np.ascontiguousarray(dloss, dtype=np.float64)
+        out = dict(loss=np.zeros(w.n_envs), g_x0=np.zeros_like(x0),
+                   g_u=np.zeros((w.T_max, max(w.n_joints, 1))),
+                   g_inv_mass=np.zeros(w.n_bodies), g_inv_inertia=np.zeros((w.n_bodies, 3)),
+                   g_mu=np.zeros(w.n_envs), g_damping=np.zeros(max(w.n_joints, 1)))
+        gw = np.zeros(self._m.mlp_n_params) if self._m.ctrl_kind == 1 else None
+        self.lib.oracle_rollout_grad(C.byref(self._m), _dp(x0), _dp(dloss), _dp(out["loss"]), _dp(out["g_x0"]),
+                                     _dp(out["g_u"]), _dp(out["g_inv_mass"]), _dp(out["g_inv_inertia"]),
+                                     _dp(out["g_mu"]), _dp(out["g_damping"]), _dp(gw),
+                                     threads or os.cpu_count() or 1)
+        out["g_u"] = out["g_u"][:, : w.n_joints]
+        out["g_damping"] = out["g_damping"][: w.n_joints]
+        if gw is not None:
+            out["g_w"] = gw
+        return out
+
+    def count_flops(self, env=0, x=None, lam=None, u=None, t=0):
+        w = self.w
+        x = np.ascontiguousarray(w.x0 if x is None else x, dtype=np.float64)
+        lam = np.zeros(max(self.lam_size, 1)) if lam is None else np.ascontiguousarray(lam, dtype=np.float64)
+        u = np.ascontiguousarray(np.zeros(max(w.n_joints, 1)) if u is None else u, dtype=np.float64)
+        return int(self.lib.oracle_count_flops(C.byref(self._m), env, _dp(x), _dp(lam), _dp(u), int(t)))

@@ -1,0 +1,433 @@
+"""Seeded synthetic workloads shaped like the paper's robot models.
+
+This module only *builds inputs*: body masses and inertias, sphere geometry,
+hinge frames, initial poses, control tapes and loss targets.  It contains no
+part of the time step itself (no forces, no constraint rows, no solver, no
+integration), so that both the FP64 oracle and the GPU path can consume the
+identical inputs without sharing any of the method's arithmetic.
+
+Every floating-point value is drawn in float64 and rounded to float32, then
+stored as float64 again: both sides therefore see exactly the same
+FP32-representable numbers, and input rounding is never part of a parity
+error.
+
+Model format (flat arrays over all environments, CSR offsets per env):
+
+=================  =========  ====================================================
+key                shape      meaning
+=================  =========  ====================================================
+env_body_off       [E+1]      first body of each env (global body index)
+env_joint_off      [E+1]      first joint of each env
+env_sphere_off     [E+1]      first collision sphere of each env
+inv_mass           [B]        1/m
+inv_inertia        [B,3]      inverse of the diagonal body-frame inertia
+sphere_body        [S]        global body index carrying the sphere
+sphere_offset      [S,3]      sphere centre in the body frame
+sphere_radius      [S]
+sphere_flags       [S]        bit 0: touches the ground, bit 1: touches spheres
+joint_parent       [J]        global body index, or -1 for the world
+joint_child        [J]        global body index
+anchor_p/anchor_c  [J,3]      hinge point in parent (or world) / child frame
+axis_p/axis_c      [J,3]      unit hinge axis in parent (or world) / child frame
+perp_p/perp_c      [J,3]      unit vector perpendicular to the axis, per frame
+damping            [J]        viscous joint damping [N m s / rad]
+mu                 [E]        Coulomb friction coefficient of the env
+loss_body          [E]        global body index whose centre enters the loss
+target             [E,3]      loss target
+T_env              [E]        steps simulated for the env (<= T_max)
+x0                 [B,18]     p(3), R(9, row-major), v(3), omega(3) per body
+u                  [T_max,J]  joint torque tape (None for a controller)
+=================  =========  ====================================================
+
+Scalars: dt, gravity (3), beta, gamma, spec_margin, n_iters, warm (factor on
+carried impulses), ground (0/1), loss_kind, loss_mask, T_max.  Bodies connected by a joint never collide.
+Each body carries at most one sphere with bit 1 set.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+from typing import Dict, Optional
+
+import numpy as np
+
+SEED_BASE = 1611016520
+
+# loss kinds (the per-env task cost l(x, p) of the paper's eq. (L))
+LOSS_FINAL_SQDIST = 0   # sum_k mask_k (p_k(T) - target_k)^2
+LOSS_MEAN_DIST = 1      # (1/T) sum_{t=1..T} |mask*(p(t) - target)|
+LOSS_NEG_MEAN_VELX = 2  # -(p_x(T) - p_x(0)) / (T dt)
+
+SPHERE_GROUND = 1
+SPHERE_PAIR = 2
+
+
+def f32(a):
+    """Round to float32 and widen back, so both sides see identical values."""
+    return np.asarray(a, dtype=np.float64).astype(np.float32).astype(np.float64)
+
+
+def rng_for(cfg: int, salt: int = 0) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(SEED_BASE + cfg + 1000 * salt))
+
+
+def _rot(axis, ang):
+    """Rotation matrix about a unit axis (Rodrigues), for building poses."""
+    a = np.asarray(axis, dtype=np.float64)
+    a = a / np.linalg.norm(a)
+    k = np.array([[0, -a[2], a[1]], [a[2], 0, -a[0]], [-a[1], a[0], 0]])
+    return np.eye(3) + math.sin(ang) * k + (1 - math.cos(ang)) * (k @ k)
+
+
+@dataclass
+class Workload:
+    name: str
+    n_envs: int
+    env_body_off: np.ndarray
+    env_joint_off: np.ndarray
+    env_sphere_off: np.ndarray
+    inv_mass: np.ndarray
+    inv_inertia: np.ndarray
+    sphere_body: np.ndarray
+    sphere_offset: np.ndarray
+    sphere_radius: np.ndarray
+    sphere_flags: np.ndarray
+    joint_parent: np.ndarray
+    joint_child: np.ndarray
+    anchor_p: np.ndarray
+    anchor_c: np.ndarray
+    axis_p: np.ndarray
+    axis_c: np.ndarray
+    perp_p: np.ndarray
+    perp_c: np.ndarray
+    damping: np.ndarray
+    mu: np.ndarray
+    loss_body: np.ndarray
+    target: np.ndarray
+    T_env: np.ndarray
+    x0: np.ndarray
+    u: Optional[np.ndarray]
+    dt: float = 0.01
+    gravity: tuple = (0.0, 0.0, -9.81)
+    beta: float = 0.2
+    gamma: float = 0.0
+    spec_margin: float = 0.05
+    n_iters: int = 20
+    warm: float = 0.85
+    ground: int = 1
+    loss_kind: int = LOSS_FINAL_SQDIST
+    loss_mask: int = 7
+    T_max: int = 0
+    ckpt_every: int = 50
+    extra: Dict = field(default_factory=dict)
+
+    @property
+    def n_bodies(self):
+        return int(self.env_body_off[-1])
+
+    @property
+    def n_joints(self):
+        return int(self.env_joint_off[-1])
+
+    @property
+    def n_spheres(self):
+        return int(self.env_sphere_off[-1])
+
+    def subset(self, envs) -> "Workload":
+        """A new workload holding only the listed envs (order kept)."""
+        envs = [int(e) for e in envs]
+        bo, jo, so = self.env_body_off, self.env_joint_off, self.env_sphere_off
+        bidx = np.concatenate([np.arange(bo[e], bo[e + 1]) for e in envs]) if envs else np.zeros(0, int)
+        jidx = np.concatenate([np.arange(jo[e], jo[e + 1]) for e in envs]) if envs else np.zeros(0, int)
+        sidx = np.concatenate([np.arange(so[e], so[e + 1]) for e in envs]) if envs else np.zeros(0, int)
+        bmap = -np.ones(self.n_bodies + 1, dtype=np.int64)
+        bmap[bidx] = np.arange(len(bidx))
+
+        def remap(a):
+            a = np.asarray(a, dtype=np.int64)
+            return np.where(a < 0, -1, bmap[np.maximum(a, 0)]).astype(np.int32)
+
+        def offs(o):
+            return np.concatenate([[0], np.cumsum([o[e + 1] - o[e] for e in envs])]).astype(np.int32)
+
+        return Workload(
+            name=self.name + "-subset", n_envs=len(envs),
+            env_body_off=offs(bo), env_joint_off=offs(jo), env_sphere_off=offs(so),
+            inv_mass=self.inv_mass[bidx], inv_inertia=self.inv_inertia[bidx],
+            sphere_body=remap(self.sphere_body[sidx]), sphere_offset=self.sphere_offset[sidx],
+            sphere_radius=self.sphere_radius[sidx], sphere_flags=self.sphere_flags[sidx],
+            joint_parent=remap(self.joint_parent[jidx]), joint_child=remap(self.joint_child[jidx]),
+            anchor_p=self.anchor_p[jidx], anchor_c=self.anchor_c[jidx],
+            axis_p=self.axis_p[jidx], axis_c=self.axis_c[jidx],
+            perp_p=self.perp_p[jidx], perp_c=self.perp_c[jidx], damping=self.damping[jidx],
+            mu=self.mu[envs], loss_body=remap(self.loss_body[envs]), target=self.target[envs],
+            T_env=self.T_env[envs], x0=self.x0[bidx],
+            u=None if self.u is None else self.u[:, jidx],
+            dt=self.dt, gravity=self.gravity, beta=self.beta, gamma=self.gamma,
+            spec_margin=self.spec_margin, n_iters=self.n_iters, warm=self.warm, ground=self.ground,
+            loss_kind=self.loss_kind, loss_mask=self.loss_mask, T_max=self.T_max,
+            ckpt_every=self.ckpt_every, extra=dict(self.extra))
+
+    def with_steps(self, T: int) -> "Workload":
+        """Same model, horizon cut to T steps (tape truncated)."""
+        import copy
+        w = copy.copy(self)
+        w.T_max = int(T)
+        w.T_env = np.minimum(self.T_env, T).astype(np.int32)
+        w.u = None if self.u is None else self.u[:T].copy()
+        return w
+
+
+class _Builder:
+    """Accumulates bodies/joints/spheres env by env."""
+
+    def __init__(self):
+        self.bodies = []   # (inv_mass, inv_inertia[3], x0[18])
+        self.joints = []   # dict
+        self.spheres = []  # (body, offset, radius, flags)
+        self.env_b = [0]
+        self.env_j = [0]
+        self.env_s = [0]
+
+    def body(self, mass, inertia_diag, p, R, v=(0, 0, 0), w=(0, 0, 0)):
+        x = np.zeros(18)
+        x[0:3] = p
+        x[3:12] = np.asarray(R).reshape(9)
+        x[12:15] = v
+        x[15:18] = w
+        self.bodies.append((1.0 / mass, 1.0 / np.asarray(inertia_diag, dtype=np.float64), x))
+        return len(self.bodies) - 1
+
+    def sphere(self, body, offset, radius, flags):
+        self.spheres.append((body, np.asarray(offset, dtype=np.float64), radius, flags))
+
+    def joint(self, parent, child, anchor_p, anchor_c, axis_p, axis_c, perp_p, perp_c, damping):
+        self.joints.append(dict(parent=parent, child=child, anchor_p=anchor_p, anchor_c=anchor_c,
+                                axis_p=axis_p, axis_c=axis_c, perp_p=perp_p, perp_c=perp_c,
+                                damping=damping))
+
+    def end_env(self):
+        self.env_b.append(len(self.bodies))
+        self.env_j.append(len(self.joints))
+        self.env_s.append(len(self.spheres))
+
+    def arrays(self):
+        B, J, S = len(self.bodies), len(self.joints), len(self.spheres)
+        out = dict(
+            env_body_off=np.array(self.env_b, np.int32), env_joint_off=np.array(self.env_j, np.int32),
+            env_sphere_off=np.array(self.env_s, np.int32),
+            inv_mass=f32([b[0] for b in self.bodies]),
+            inv_inertia=f32(np.array([b[1] for b in self.bodies]).reshape(B, 3)),
+            x0=f32(np.array([b[2] for b in self.bodies]).reshape(B, 18)),
+            sphere_body=np.array([s[0] for s in self.spheres], np.int32).reshape(S),
+            sphere_offset=f32(np.array([s[1] for s in self.spheres]).reshape(S, 3)),
+            sphere_radius=f32(np.array([s[2] for s in self.spheres]).reshape(S)),
+            sphere_flags=np.array([s[3] for s in self.spheres], np.int32).reshape(S),
+        )
+        jk = ["anchor_p", "anchor_c", "axis_p", "axis_c", "perp_p", "perp_c"]
+        out["joint_parent"] = np.array([j["parent"] for j in self.joints], np.int32).reshape(J)
+        out["joint_child"] = np.array([j["child"] for j in self.joints], np.int32).reshape(J)
+        for k in jk:
+            out[k] = f32(np.array([j[k] for j in self.joints], dtype=np.float64).reshape(J, 3))
+        out["damping"] = f32(np.array([j["damping"] for j in self.joints]).reshape(J))
+        return out
+
+
+def sphere_inertia(m, r):
+    return [0.4 * m * r * r] * 3
+
+
+def box_inertia(m, a, b, c):
+    return [m / 12 * (b * b + c * c), m / 12 * (a * a + c * c), m / 12 * (a * a + b * b)]
+
+
+def rod_inertia(m, L, eps=0.01):
+    return [m / 12 * eps * eps, m / 12 * L * L, m / 12 * L * L]
+
+
+# --------------------------------------------------------------------------
+# cfg1: ball throw (paper section 2.1.1, batch 1)
+# --------------------------------------------------------------------------
+def ball_throw(seed_salt: int = 0, T: int = 300) -> Workload:
+    rng = rng_for(1, seed_salt)
+    v0 = rng.uniform(-2.0, 6.0, size=3)
+    tgt = np.array([rng.uniform(1.0, 5.0), rng.uniform(-1.0, 1.0), 0.0])
+    r, m = 0.1, 1.0
+    b = _Builder()
+    b.body(m, sphere_inertia(m, r), p=(0, 0, r), R=np.eye(3), v=v0)
+    b.sphere(0, (0, 0, 0), r, SPHERE_GROUND)
+    b.end_env()
+    a = b.arrays()
+    return Workload(name="ball-throw", n_envs=1, **a, mu=f32([1.0]), loss_body=np.array([0], np.int32),
+                    target=f32(tgt[None]), T_env=np.array([T], np.int32), u=np.zeros((T, 0)),
+                    dt=0.01, ground=1, loss_kind=LOSS_FINAL_SQDIST, loss_mask=3, T_max=T,
+                    ckpt_every=50)
+
+
+# --------------------------------------------------------------------------
+# cfg2: planar 3-link arms, open-loop torque tape
+# --------------------------------------------------------------------------
+def planar_arms(n_envs: int = 4096, T: int = 1000, seed_salt: int = 0, n_links: int = 3) -> Workload:
+    rng = rng_for(2, seed_salt)
+    b = _Builder()
+    r_pt = 0.05
+    base = np.array([0.0, 0.0, 1.0])
+    targets = []
+    for e in range(n_envs):
+        L = rng.uniform(0.3, 0.6, size=n_links)
+        m = rng.uniform(0.5, 2.0, size=n_links)
+        th = rng.uniform(-0.5, 0.5, size=n_links)
+        phi = 0.0
+        pos = base.copy()
+        ids = []
+        for i in range(n_links):
+            phi += th[i]
+            Rz = _rot((0, 0, 1), phi)
+            pos = pos + L[i] * np.array([math.cos(phi), math.sin(phi), 0.0])
+            ids.append(b.body(m[i], sphere_inertia(m[i], r_pt), p=pos, R=Rz))
+        for i in range(n_links):
+            parent = ids[i - 1] if i > 0 else -1
+            anchor_p = (0, 0, 0) if i > 0 else tuple(base)
+            b.joint(parent, ids[i], anchor_p, (-L[i], 0, 0), (0, 0, 1), (0, 0, 1), (1, 0, 0), (1, 0, 0), 0.1)
+        rad = rng.uniform(0.2, 0.9 * L.sum())
+        ang = rng.uniform(-math.pi, math.pi)
+        targets.append([rad * math.cos(ang), rad * math.sin(ang), base[2]])
+        b.end_env()
+    a = b.arrays()
+    J = n_links * n_envs
+    u = f32(rng.normal(0.0, 0.5, size=(T, J)))
+    ee = a["env_body_off"][1:] - 1
+    return Workload(name="planar-arms", n_envs=n_envs, **a, mu=f32(np.zeros(n_envs)),
+                    loss_body=ee.astype(np.int32), target=f32(np.array(targets)),
+                    T_env=np.full(n_envs, T, np.int32), u=u, dt=0.005, ground=0, gravity=(0.0, 0.0, 0.0),
+                    loss_kind=LOSS_MEAN_DIST, loss_mask=7, T_max=T, ckpt_every=50)
+
+
+# --------------------------------------------------------------------------
+# cfg4: uneven 3D hinge chains of spheres with ground and self contact
+# --------------------------------------------------------------------------
+def chain_sizes(n_envs, rng, lo=2, hi=32):
+    return np.floor(np.exp(rng.uniform(math.log(lo), math.log(hi + 1), size=n_envs))).astype(int).clip(lo, hi)
+
+
+def uneven_chains(n_envs: int = 16384, T: int = 500, seed_salt: int = 0, sizes=None) -> Workload:
+    rng = rng_for(4, seed_salt)
+    if sizes is None:
+        sizes = chain_sizes(n_envs, rng)
+    b = _Builder()
+    targets, mus = [], []
+    for e in range(n_envs):
+        nb = int(sizes[e])
+        r = rng.uniform(0.05, 0.15, size=nb)
+        m = rng.uniform(0.5, 2.0, size=nb)
+        axes = [np.array([0.0, 1.0, 0.0]) if i % 2 == 0 else np.array([0.0, 0.0, 1.0]) for i in range(nb - 1)]
+        ang = rng.uniform(-0.5, 0.5, size=max(nb - 1, 0))
+        yaw0 = rng.uniform(-math.pi, math.pi)
+        clear = rng.uniform(0.2, 0.7)
+        Rs = [_rot((0, 0, 1), yaw0)]
+        ps = [np.zeros(3)]
+        d = [r[i] + r[i + 1] + 0.05 for i in range(nb - 1)]
+        for i in range(nb - 1):
+            Rn = Rs[i] @ _rot(axes[i], ang[i])
+            pn = ps[i] + Rs[i] @ np.array([d[i] / 2, 0, 0]) + Rn @ np.array([d[i] / 2, 0, 0])
+            Rs.append(Rn)
+            ps.append(pn)
+        lowest = min(ps[i][2] - r[i] for i in range(nb))
+        lift = clear - lowest
+        ids = []
+        for i in range(nb):
+            p = ps[i] + np.array([0, 0, lift])
+            ids.append(b.body(m[i], sphere_inertia(m[i], r[i]), p=p, R=Rs[i]))
+            b.sphere(ids[-1], (0, 0, 0), r[i], SPHERE_GROUND | SPHERE_PAIR)
+        for i in range(nb - 1):
+            b.joint(ids[i], ids[i + 1], (d[i] / 2, 0, 0), (-d[i] / 2, 0, 0), axes[i], axes[i],
+                    (1, 0, 0), (1, 0, 0), 0.05)
+        targets.append([rng.uniform(-1, 1), rng.uniform(-1, 1), rng.uniform(0.0, 0.5)])
+        mus.append(rng.uniform(0.3, 1.0))
+        b.end_env()
+    a = b.arrays()
+    J = int(a["env_joint_off"][-1])
+    u = f32(rng.normal(0.0, 0.2, size=(T, J)))
+    tip = a["env_body_off"][1:] - 1
+    return Workload(name="uneven-chains", n_envs=n_envs, **a, mu=f32(mus), loss_body=tip.astype(np.int32),
+                    target=f32(np.array(targets)), T_env=np.full(n_envs, T, np.int32), u=u,
+                    dt=0.005, ground=1, loss_kind=LOSS_FINAL_SQDIST, loss_mask=7, T_max=T,
+                    ckpt_every=50)
+
+
+# --------------------------------------------------------------------------
+# small hand-made models for closed-form checks
+# --------------------------------------------------------------------------
+def single_sphere(p, v=(0, 0, 0), w=(0, 0, 0), r=0.1, m=1.0, mu=1.0, ground=True, T=100, dt=0.01,
+                  gravity=(0.0, 0.0, -9.81), n_iters=20, R=None) -> Workload:
+    b = _Builder()
+    b.body(m, sphere_inertia(m, r), p=p, R=np.eye(3) if R is None else R, v=v, w=w)
+    b.sphere(0, (0, 0, 0), r, SPHERE_GROUND if ground else 0)
+    b.end_env()
+    a = b.arrays()
+    return Workload(name="sphere", n_envs=1, **a, mu=f32([mu]), loss_body=np.array([0], np.int32),
+                    target=f32(np.zeros((1, 3))), T_env=np.array([T], np.int32), u=np.zeros((T, 0)),
+                    dt=dt, gravity=tuple(gravity), ground=int(ground), loss_kind=LOSS_FINAL_SQDIST,
+                    loss_mask=7, T_max=T, n_iters=n_iters)
+
+
+def pendulum(L=1.0, m=1.0, r=0.05, theta0=0.1, T=200, dt=0.001, damping=0.0, n_iters=20,
+             beta=0.2) -> Workload:
+    """A sphere hanging from a world hinge whose axis is y; swings in the x-z plane."""
+    b = _Builder()
+    pivot = np.array([0.0, 0.0, 2.0])
+    # body hangs at angle theta0 from -z toward +x; the rotation of the
+    # body frame follows the rod so that the anchor stays at (0, 0, L) local.
+    Ry = _rot((0, 1, 0), -theta0)
+    p = pivot + Ry @ np.array([0.0, 0.0, -L])
+    bi = b.body(m, sphere_inertia(m, r), p=p, R=Ry)
+    b.joint(-1, bi, tuple(pivot), (0, 0, L), (0, 1, 0), (0, 1, 0), (1, 0, 0), (1, 0, 0), damping)
+    b.end_env()
+    a = b.arrays()
+    return Workload(name="pendulum", n_envs=1, **a, mu=f32([0.0]), loss_body=np.array([0], np.int32),
+                    target=f32(np.zeros((1, 3))), T_env=np.array([T], np.int32), u=np.zeros((T, 1)),
+                    dt=dt, ground=0, loss_kind=LOSS_FINAL_SQDIST, loss_mask=7, T_max=T,
+                    n_iters=n_iters, beta=beta)
+
+
+def free_chain(n=4, T=200, dt=0.005, seed_salt=0, gravity=(0.0, 0.0, 0.0), ground=False,
+               torque_sigma=0.3) -> Workload:
+    """A free-floating 3D chain (the uneven-chain recipe at a fixed size)."""
+    w = uneven_chains(n_envs=1, T=T, seed_salt=seed_salt, sizes=[n])
+    w.gravity = tuple(gravity)
+    w.ground = int(ground)
+    rng = rng_for(9, seed_salt)
+    w.u = f32(rng.normal(0.0, torque_sigma, size=(T, w.n_joints)))
+    w.dt = dt
+    w.x0 = w.x0.copy()
+    # random initial body velocities so that momentum is non-trivial
+    w.x0[:, 12:18] = f32(rng.normal(0.0, 0.5, size=(w.n_bodies, 6)))
+    return w
+
+
+def free_spheres(positions, radii, masses, velocities=None, mu=0.0, ground=True, T=1, dt=0.01,
+                 n_iters=20, gravity=(0.0, 0.0, -9.81)) -> Workload:
+    """Unjointed spheres in one env, each touching the ground and each other."""
+    b = _Builder()
+    n = len(positions)
+    velocities = np.zeros((n, 3)) if velocities is None else velocities
+    for i in range(n):
+        bi = b.body(masses[i], sphere_inertia(masses[i], radii[i]), p=positions[i], R=np.eye(3), v=velocities[i])
+        b.sphere(bi, (0, 0, 0), radii[i], SPHERE_GROUND | SPHERE_PAIR)
+    b.end_env()
+    a = b.arrays()
+    return Workload(name="spheres", n_envs=1, **a, mu=f32([mu]), loss_body=np.array([0], np.int32),
+                    target=f32(np.zeros((1, 3))), T_env=np.array([T], np.int32), u=np.zeros((T, 0)),
+                    dt=dt, gravity=tuple(gravity), ground=int(ground), loss_kind=LOSS_FINAL_SQDIST,
+                    loss_mask=7, T_max=T, n_iters=n_iters)
+
+
+def mlp_param_count(sizes, skip_input_to_output=False):
+    """Parameters of a dense net with biases (optionally the output layer also
+    reads the input layer, as the gait controller of section 3.3 does)."""
+    n = 0
+    for a, b in zip(sizes[:-1], sizes[1:]):
+        n += a * b + b
+    if skip_input_to_output:
+        n += sizes[0] * sizes[-1]
+    return n

@@ -1,0 +1,333 @@
+"""Pins of the FP64 oracle against closed forms, invariants and brute force.
+
+Each test pins a part of the oracle to something other than itself, so that a
+dropped term, a wrong sign or a transposed operand in the step fails one of
+them:
+
+* free fall / ballistic flight: discrete semi-implicit Euler closed form and
+  its derivative (gravity, integration order, the tape's chain rule)
+* ball at rest on the ground stays exactly at rest (normal row, bias at C=0)
+* a sliding ball ends rolling at v0 m r^2 / (m r^2 + I) (friction block, lever
+  arm sign, inertia, disk projection); angular momentum about the ground point
+* spin: R after n steps equals Rz(n atan(dt w)) up to the renormalisation's
+  scale error (skew sign, order of update, eq. (1) reading)
+* renormalisation: steady-state orthonormality error -0.75 (dt|w|)^4
+* free-floating jointed chain conserves linear momentum (equal and opposite
+  impulses and torques)
+* angular hinge rows remove exactly the rotation perpendicular to the axis
+* pendulum: small-angle period and energy (point-row lever arms, inertia)
+* frictionless sphere pile with K -> infinity sweeps equals the LCP solution
+  found by brute-force enumeration of active sets (projected Gauss-Seidel,
+  normal Jacobians, speculative / Baumgarte bias)
+* the reverse-mode gradient equals central finite differences (tape)
+* MLP parameter counts printed in the paper (sections 3.2.1, 3.2.2)
+"""
+import itertools
+import math
+
+import numpy as np
+import pytest
+
+from oracle import Oracle
+from paper_1611_01652_amd import workloads as W
+
+
+def test_free_fall_closed_form_and_gradient():
+    p0, v0, dt, n = np.array([0.3, -0.2, 5.0]), np.array([1.0, -0.5, 2.0]), 0.01, 60
+    w = W.single_sphere(p=p0, v=v0, ground=False, T=n, dt=dt)
+    w.target = W.f32([[0.1, 0.2, 0.3]])
+    o = Oracle(w)
+    r = o.rollout()
+    g = np.array([0, 0, -9.81])
+    # v_k = v0 + k dt g ; p_n = p0 + dt sum_{k=1..n} v_k
+    p_exp = W.f32(p0) + n * dt * W.f32(v0) + g * dt * dt * n * (n + 1) / 2
+    v_exp = W.f32(v0) + n * dt * g
+    np.testing.assert_allclose(r["x_final"][0, :3], p_exp, rtol=0, atol=1e-12)
+    np.testing.assert_allclose(r["x_final"][0, 12:15], v_exp, rtol=0, atol=1e-12)
+    # L = |p_n - tgt|^2  ->  dL/dv0 = 2 (p_n - tgt) n dt ; dL/dp0 = 2 (p_n - tgt)
+    gr = o.rollout_grad()
+    d = p_exp - w.target[0]
+    np.testing.assert_allclose(gr["g_x0"][0, 12:15], 2 * d * n * dt, rtol=1e-10)
+    np.testing.assert_allclose(gr["g_x0"][0, 0:3], 2 * d, rtol=1e-10)
+    assert abs(gr["loss"][0] - (d ** 2).sum()) < 1e-12
+
+
+def test_ball_at_rest_stays_exactly():
+    w = W.single_sphere(p=(0.2, -0.1, 0.1), T=200)
+    r = Oracle(w).rollout()
+    np.testing.assert_allclose(r["x_final"], w.x0, rtol=0, atol=1e-14)
+    # the carried normal impulse equals the weight impulse m g dt
+    m = 1.0 / w.inv_mass[0]
+    assert abs(r["lam_final"][0] - m * 9.81 * w.dt) < 1e-12
+    np.testing.assert_allclose(r["lam_final"][1:], 0.0, atol=1e-15)
+
+
+@pytest.mark.parametrize("v0,mu", [(2.0, 0.3), (-1.0, 1.0), (0.7, 0.05)])
+def test_sliding_ball_ends_rolling_at_five_sevenths(v0, mu):
+    r_ = 0.1
+    w = W.single_sphere(p=(0, 0, r_), v=(v0, 0.0, 0.0), mu=mu, T=600, r=r_)
+    out = Oracle(w).rollout(traj=True)
+    m = 1.0 / w.inv_mass[0]
+    I = 1.0 / w.inv_inertia[0, 1]
+    rr = w.sphere_radius[0]
+    v_roll = W.f32(v0) * m * rr * rr / (m * rr * rr + I)   # = 5/7 v0 for a solid sphere
+    xf = out["x_final"][0]
+    assert abs(xf[12] - v_roll) < 1e-9
+    assert abs(xf[16] * rr - xf[12]) < 1e-9       # rolling: w_y r = v_x
+    assert abs(xf[2] - rr) < 1e-12                # stays on the ground
+    # angular momentum about a ground point is conserved every step
+    tr = out["traj"]
+    Lg = m * tr[:, 0, 12] * rr + I * tr[:, 0, 16]
+    np.testing.assert_allclose(Lg, Lg[0], rtol=0, atol=1e-12)
+
+
+def test_spin_angle_is_n_atan_dt_w():
+    wz, dt, n = 3.0, 0.01, 500
+    w = W.single_sphere(p=(0, 0, 0), w=(0, 0, wz), ground=False, gravity=(0, 0, 0), T=n, dt=dt)
+    R = Oracle(w).rollout()["x_final"][0, 3:12].reshape(3, 3)
+    ang = math.atan2(R[1, 0], R[0, 0])
+    expect = math.remainder(n * math.atan(dt * W.f32(wz)), 2 * math.pi)
+    assert abs(ang - expect) < 1e-12
+    assert abs(R[0, 0] * R[0, 0] + R[1, 0] * R[1, 0] - 1.0) < 1e-6
+    assert abs(R[2, 2] - 1.0) < 1e-15
+
+
+def test_renormalisation_steady_state_error():
+    # A = (I + dt [w]x) R has two singular values sqrt(1+eps), eps = dt^2 |w|^2.
+    # One step of N(A) = (3A - A A^T A)/2 maps 1+x to 1 - 1.5 x^2 - ..., so the
+    # singular values settle at 1 - 0.375 eps^2 and R^T R - I at -0.75 eps^2
+    # on the two rotated directions: bounded, not drifting, over 10^4 steps.
+    wv, dt = np.array([1.3, -2.1, 0.7]), 0.01
+    w = W.single_sphere(p=(0, 0, 0), w=wv, ground=False, gravity=(0, 0, 0), T=10000, dt=dt)
+    R = Oracle(w).rollout()["x_final"][0, 3:12].reshape(3, 3)
+    eps = dt * dt * (W.f32(wv) ** 2).sum()
+    ev = np.sort(np.linalg.eigvalsh(R.T @ R - np.eye(3)))
+    np.testing.assert_allclose(ev[:2], -0.75 * eps * eps, rtol=0.02)
+    assert abs(ev[2]) < 1e-13
+    assert np.linalg.det(R) > 0
+
+
+@pytest.mark.parametrize("n", [2, 5, 9])
+def test_free_chain_conserves_linear_momentum(n):
+    w = W.free_chain(n=n, T=300)
+    tr = Oracle(w).rollout(traj=True)["traj"]
+    m = 1.0 / w.inv_mass
+    P = (tr[:, :, 12:15] * m[None, :, None]).sum(axis=1)
+    np.testing.assert_allclose(P, np.broadcast_to(P[0], P.shape), rtol=0, atol=1e-12 * max(1, np.abs(P).max()))
+    # the chain stays connected (a wrong Jacobian sign makes it fly apart)
+    xf = tr[-1]
+    for j in range(w.n_joints):
+        a, b = w.joint_parent[j], w.joint_child[j]
+        pa = xf[a, :3] + xf[a, 3:12].reshape(3, 3) @ w.anchor_p[j]
+        pb = xf[b, :3] + xf[b, 3:12].reshape(3, 3) @ w.anchor_c[j]
+        assert np.linalg.norm(pa - pb) < 5e-3
+
+
+def test_hinge_angular_rows_remove_perpendicular_rotation():
+    # a sphere centred on a world hinge (axis y): the point rows need no
+    # rotation, the two angular rows cancel exactly the x and z spin
+    w = W.pendulum(L=1.0, theta0=0.0, T=1)
+    w.anchor_c[:] = 0.0
+    w.x0[0, :3] = w.anchor_p[0]
+    w.x0[0, 15:18] = [0.7, -1.1, 0.4]
+    w.x0[0, 12:15] = 0.0
+    w.gravity = (0.0, 0.0, 0.0)
+    xn, lam = Oracle(w).step(w.x0, u=np.zeros(1))
+    np.testing.assert_allclose(xn[0, 15:18], [0.0, W.f32(-1.1), 0.0], atol=1e-14)
+    np.testing.assert_allclose(xn[0, 12:15], 0.0, atol=1e-14)
+
+
+def test_pendulum_small_angle_period_and_energy():
+    L, m, r = 1.0, 1.0, 0.05
+    w = W.pendulum(L=L, m=m, r=r, theta0=0.05, T=4000, dt=0.001, n_iters=200)
+    tr = Oracle(w).rollout(traj=True)["traj"]
+    x = tr[:, 0, 0] - w.anchor_p[0, 0]
+    s = np.sign(x)
+    idx = np.where(s[:-1] * s[1:] < 0)[0]
+    t_cross = []
+    for i in idx:   # linear interpolation of each zero crossing
+        t_cross.append((i + x[i] / (x[i] - x[i + 1])) * w.dt)
+    period = 2 * np.mean(np.diff(t_cross))
+    Icm = 1.0 / w.inv_inertia[0, 1]
+    mm = 1.0 / w.inv_mass[0]
+    expect = 2 * math.pi * math.sqrt((Icm + mm * L * L) / (mm * 9.81 * L))
+    assert abs(period / expect - 1) < 0.01
+    # energy: kinetic (translation + rotation) + potential, drift below 1%
+    v = tr[:, 0, 12:15]
+    om = tr[:, 0, 15:18]
+    E = 0.5 * mm * (v ** 2).sum(1) + 0.5 * Icm * (om ** 2).sum(1) + mm * 9.81 * tr[:, 0, 2]
+    E0 = mm * 9.81 * (w.anchor_p[0, 2] - L)
+    amp = E[0] - E0
+    assert np.abs(E[:2000] - E[0]).max() < 0.01 * amp
+
+
+def _lcp_brute_force(K, q):
+    m = len(q)
+    for k in range(m + 1):
+        for S in itertools.combinations(range(m), k):
+            S = list(S)
+            lam = np.zeros(m)
+            if S:
+                lam[S] = np.linalg.solve(K[np.ix_(S, S)], -q[S])
+            wv = K @ lam + q
+            if (lam >= -1e-12).all() and (wv >= -1e-10).all():
+                return lam
+    raise AssertionError("no LCP solution")
+
+
+def test_frictionless_pile_converges_to_lcp_solution():
+    r = 0.1
+    pos = np.array([[0.0, 0.0, r], [0.19, 0.0, r], [0.095, 0.0, r + 0.17]])
+    rng = np.random.default_rng(3)
+    vel = rng.normal(0, 0.5, size=(3, 3))
+    masses = [1.0, 2.0, 0.7]
+    w = W.free_spheres(pos, [r, r, r], masses, velocities=vel, mu=0.0, n_iters=4000, T=1)
+    xn, _ = Oracle(w).step(w.x0)
+    P = w.x0[:, :3]
+    rad = w.sphere_radius
+    invm = w.inv_mass
+    dt, beta = w.dt, w.beta
+    vstar = w.x0[:, 12:15] + dt * np.array([0, 0, -9.81])
+    rows = []
+    for i in range(3):   # ground candidates
+        C = P[i, 2] - rad[i]
+        if C < w.spec_margin:
+            J = np.zeros(9)
+            J[3 * i + 2] = 1.0
+            rows.append((J, C))
+    for i in range(3):
+        for j in range(i + 1, 3):
+            d = P[j] - P[i]
+            L = np.linalg.norm(d)
+            C = L - rad[i] - rad[j]
+            if C < w.spec_margin:
+                n = d / L
+                J = np.zeros(9)
+                J[3 * i:3 * i + 3] = -n
+                J[3 * j:3 * j + 3] = n
+                rows.append((J, C))
+    assert len(rows) == 5
+    Jm = np.array([r_[0] for r_ in rows])
+    b = np.array([(max(C, 0) + beta * min(C, 0)) / dt for _, C in rows])
+    Minv = np.repeat(invm, 3)
+    K = Jm @ (Minv[:, None] * Jm.T)
+    q = Jm @ vstar.reshape(9) + b
+    lam = _lcp_brute_force(K, q)
+    assert (lam > 1e-6).sum() >= 2 and (lam < 1e-12).sum() >= 1   # mixed active set
+    v_exp = vstar.reshape(9) + Minv * (Jm.T @ lam)
+    np.testing.assert_allclose(xn[:, 12:15].reshape(9), v_exp, rtol=0, atol=1e-8)
+    np.testing.assert_allclose(xn[:, 15:18], 0.0, atol=1e-12)
+
+
+def _fd(f, x, h):
+    g = np.zeros_like(x)
+    for i in range(x.size):
+        xp, xm = x.copy(), x.copy()
+        xp.flat[i] += h
+        xm.flat[i] -= h
+        g.flat[i] = (f(xp) - f(xm)) / (2 * h)
+    return g
+
+
+def test_gradient_matches_central_differences_ball():
+    w = W.ball_throw(T=60)
+    o = Oracle(w)
+    gr = o.rollout_grad()
+
+    def f(v0):
+        x0 = w.x0.copy()
+        x0[0, 12:15] = v0
+        return o.rollout(x0=x0)["loss"][0]
+
+    fd = _fd(f, w.x0[0, 12:15].copy(), 1e-6)
+    np.testing.assert_allclose(gr["g_x0"][0, 12:15], fd, rtol=1e-6, atol=1e-8)
+
+
+def test_gradient_matches_central_differences_arm():
+    w = W.planar_arms(n_envs=1, T=40)
+    o = Oracle(w)
+    gr = o.rollout_grad()
+
+    def fu(u):
+        w2 = w.with_steps(w.T_max)
+        w2.u = u.reshape(w.u.shape)
+        return Oracle(w2).rollout()["loss"][0]
+
+    idx = [0, 5, 17, 60, 100, 119]
+    u = w.u.copy()
+    for i in idx:
+        up, um = u.copy(), u.copy()
+        up.flat[i] += 1e-6
+        um.flat[i] -= 1e-6
+        fd = (fu(up) - fu(um)) / 2e-6
+        assert abs(gr["g_u"].flat[i] - fd) <= 1e-6 * abs(fd) + 1e-9, (i, gr["g_u"].flat[i], fd)
+
+    def fx(x0v):
+        x0 = x0v.reshape(w.x0.shape)
+        return o.rollout(x0=x0)["loss"][0]
+
+    sel = [(1, 12), (2, 13), (0, 15), (2, 17), (1, 0)]
+    for (b, k) in sel:
+        x0 = w.x0.copy()
+        xp, xm = x0.copy(), x0.copy()
+        xp[b, k] += 1e-6
+        xm[b, k] -= 1e-6
+        fd = (fx(xp) - fx(xm)) / 2e-6
+        assert abs(gr["g_x0"][b, k] - fd) <= 1e-6 * abs(fd) + 1e-9, (b, k, gr["g_x0"][b, k], fd)
+
+    def fd_param(name, i):
+        def f(val):
+            w2 = w.with_steps(w.T_max)
+            arr = getattr(w, name).copy()
+            arr.flat[i] = val
+            setattr(w2, name, arr)
+            return Oracle(w2).rollout()["loss"][0]
+        v = getattr(w, name).flat[i]
+        return (f(v + 1e-6) - f(v - 1e-6)) / 2e-6
+
+    assert abs(gr["g_damping"][1] - fd_param("damping", 1)) < 1e-6 * max(1, abs(gr["g_damping"][1]))
+    assert abs(gr["g_inv_mass"][2] - fd_param("inv_mass", 2)) < 1e-6 * max(1, abs(gr["g_inv_mass"][2]))
+    got = gr["g_inv_inertia"].flat[5]
+    assert abs(got - fd_param("inv_inertia", 5)) < 1e-6 * max(1, abs(got))
+
+
+def test_gradient_matches_central_differences_contact_chain():
+    w = W.uneven_chains(n_envs=1, T=120, seed_salt=5, sizes=[4])
+    o = Oracle(w)
+    r = o.rollout(traj=True)
+    assert (r["traj"][:, :, 2] - 0.15 < 0.05).any()   # ground contact happened
+    gr = o.rollout_grad()
+
+    def loss_with(**kw):
+        w2 = w.with_steps(w.T_max)
+        for k, v in kw.items():
+            setattr(w2, k, v)
+        return Oracle(w2).rollout()["loss"][0]
+
+    h = 1e-6
+    for i in [3, 40, 200, 355]:
+        up, um = w.u.copy(), w.u.copy()
+        up.flat[i] += h
+        um.flat[i] -= h
+        fd = (loss_with(u=up) - loss_with(u=um)) / (2 * h)
+        assert abs(gr["g_u"].flat[i] - fd) <= 1e-5 * max(abs(fd), 1e-3), (i, gr["g_u"].flat[i], fd)
+    mp, mm_ = w.mu.copy(), w.mu.copy()
+    mp[0] += h
+    mm_[0] -= h
+    fd = (loss_with(mu=mp) - loss_with(mu=mm_)) / (2 * h)
+    assert abs(gr["g_mu"][0] - fd) <= 1e-5 * max(abs(fd), 1e-3), (gr["g_mu"][0], fd)
+    for (b, k) in [(0, 2), (3, 12), (1, 16)]:
+        xp, xm = w.x0.copy(), w.x0.copy()
+        xp[b, k] += h
+        xm[b, k] -= h
+        fd = (o.rollout(x0=xp)["loss"][0] - o.rollout(x0=xm)["loss"][0]) / (2 * h)
+        assert abs(gr["g_x0"][b, k] - fd) <= 1e-5 * max(abs(fd), 1e-3), (b, k, gr["g_x0"][b, k], fd)
+
+
+def test_paper_mlp_parameter_counts():
+    # section 3.2.1: 1 -> 128 -> 128 -> 4 dense with biases
+    assert W.mlp_param_count([1, 128, 128, 4]) == 17284
+    # section 3.2.2: 3 -> 3 x 1024 -> 4
+    assert W.mlp_param_count([3, 1024, 1024, 1024, 4]) == 2107396
+    # the quadruped controller of the configs: 18 -> 128 -> 128 -> 8
+    assert W.mlp_param_count([18, 128, 128, 8]) == 19976
