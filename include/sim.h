@@ -1,0 +1,177 @@
+/* Batched differentiable rigid-body time step for MI355X (gfx950): C ABI.
+ *
+ * The library simulates E independent environments ("envs", robot models) at
+ * once.  Each env is a set of rigid bodies with 6 DOF (position, rotation
+ * matrix, linear and angular velocity), hinge joints, and collision spheres
+ * that touch the ground plane z = 0 and each other.  One time step
+ * x^{t+1} = f_ph(x^t, u^t) (paper, section 2.1 and eq. (L)) is:
+ *   joint torques u and damping -> velocity prediction with gravity ->
+ *   contact candidates and gap test -> constraint rows (Jacobians, effective
+ *   masses, Baumgarte / speculative bias) -> warm start from the previous
+ *   step's impulses -> a fixed number of projected Gauss-Seidel sweeps in a
+ *   fixed colour-major order -> semi-implicit Euler and rotation
+ *   renormalisation N(A) = (3A - A A^T A)/2 (eq. (1)).
+ * `rollout` unrolls T steps and accumulates the loss L = sum_t l(x^t, p)
+ * (eq. (L)); `rollout_grad` returns the exact reverse-mode derivative of the
+ * unrolled discrete map (back-propagation through time, section 2.1.1) with
+ * respect to the initial state, the control tape and model parameters
+ * (section 4: "masses and lengths" and friction).
+ *
+ * Conventions for every call:
+ *  - Arrays marked (device) are device pointers (hipMalloc / torch CUDA
+ *    tensors) owned by the caller; the library never frees them.  Arrays
+ *    marked (host) are read synchronously during the call.
+ *  - All floats are IEEE binary32; all arithmetic on the GPU is FP32.
+ *  - State layout is struct-of-arrays: x[18][B] with component k of body b
+ *    at x[k*B + b]; components p(0..2), R(3..11, row-major), v(12..14),
+ *    omega(15..17).  B = total bodies over all envs, bodies of an env are
+ *    contiguous (CSR offsets env_body_off).
+ *  - Warm-start impulse state ("lambda"), per env a contiguous block of
+ *    5*J_e + 4*G_e + 4*P_e floats at the offset sim_info.lam_off[e]:
+ *    5 hinge rows per joint (point x, y, z, angular t1, t2), then per ground
+ *    sphere (sphere order) [lambda_n, Lambda_t.x, .y, .z], then per sphere
+ *    pair candidate [lambda_n, Lambda_t(3)] in (body a, body b) lexicographic
+ *    order of the env's local body indices; Lambda_t is the tangent impulse
+ *    as a world vector.  Inactive candidates hold zeros.
+ *  - Control tape u[T_max][J] (device), joint-major within a step.
+ *  - Calls are asynchronous on the given HIP stream (NULL = default stream)
+ *    and never synchronise the device.  Argument, shape and descriptor errors
+ *    are detected on the host before any launch: they return a negative
+ *    status and set a thread-local message (sim_last_error).  A device fault
+ *    from an earlier launch surfaces as SIM_E_DEVICE.  Per-env numerical
+ *    events are not errors: they are reported in env_flags.
+ *  - A handle is not re-entrant: do not run two calls with one handle on
+ *    different streams concurrently.
+ *  - Results are bitwise deterministic for a given handle (no float atomics).
+ */
+#ifndef PAPER_1611_01652_SIM_H
+#define PAPER_1611_01652_SIM_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SIM_ABI_VERSION 1
+
+typedef struct sim_model* sim_handle;
+
+typedef enum {
+  SIM_OK = 0,
+  SIM_E_ARG = -1,         /* null pointer or invalid scalar */
+  SIM_E_SHAPE = -2,       /* inconsistent sizes / offsets / indices */
+  SIM_E_UNSUPPORTED = -3, /* model exceeds a device limit (e.g. LDS per env) */
+  SIM_E_NOMEM = -4,       /* device allocation failed, or workspace too small */
+  SIM_E_DEVICE = -5,      /* a HIP call failed (includes earlier async faults) */
+  SIM_E_STATE = -6        /* handle used in an invalid state */
+} sim_status;
+
+/* per-env flags written by rollout / rollout_grad / sim_step */
+#define SIM_FLAG_NONFINITE 1u        /* a state component became NaN/Inf */
+#define SIM_FLAG_CONTACT_OVERFLOW 2u /* more active contacts than the env's capacity */
+
+/* loss kinds l(x^t, p) of eq. (L); p = the env's target and loss body */
+#define SIM_LOSS_FINAL_SQDIST 0  /* sum_k mask_k (p_k(T_e) - target_k)^2                */
+#define SIM_LOSS_MEAN_DIST 1     /* (1/T_e) sum_{t=1..T_e} |mask*(p(t) - target)|          */
+#define SIM_LOSS_NEG_MEAN_VELX 2 /* -(p_x(T_e) - p_x(0)) / (T_e dt)  (mean forward speed) */
+
+/* Model description (host memory, read during sim_init; the caller keeps
+ * ownership).  Indices of bodies/joints/spheres are global (over all envs),
+ * and each env's items must lie inside its own CSR range. */
+typedef struct {
+  int32_t n_envs;
+  const int32_t* env_body_off;   /* [E+1] */
+  const int32_t* env_joint_off;  /* [E+1] */
+  const int32_t* env_sphere_off; /* [E+1] */
+  const float* inv_mass;         /* [B] 1/m (> 0) */
+  const float* inv_inertia;      /* [B][3] inverse diagonal body-frame inertia */
+  const int32_t* sphere_body;    /* [S] body carrying the sphere */
+  const float* sphere_offset;    /* [S][3] centre in the body frame */
+  const float* sphere_radius;    /* [S] */
+  const int32_t* sphere_flags;   /* [S] bit0 ground contact, bit1 sphere-sphere contact
+                                    (at most one bit1 sphere per body) */
+  const int32_t* joint_parent;   /* [J] body index or -1 (world) */
+  const int32_t* joint_child;    /* [J] body index */
+  const float* anchor_p;         /* [J][3] hinge point in the parent (world) frame */
+  const float* anchor_c;         /* [J][3] hinge point in the child frame */
+  const float* axis_p;           /* [J][3] unit hinge axis, parent (world) frame */
+  const float* axis_c;           /* [J][3] unit hinge axis, child frame */
+  const float* perp_p;           /* [J][3] unit vector normal to axis_p, parent frame */
+  const float* perp_c;           /* [J][3] unit vector normal to axis_c, child frame */
+  const float* damping;          /* [J] viscous damping about the hinge axis */
+  const float* mu;               /* [E] Coulomb friction coefficient */
+  const int32_t* loss_body;      /* [E] body whose centre enters the loss */
+  const float* target;           /* [E][3] loss target */
+  const int32_t* T_env;          /* [E] steps of each env, 0 <= T_e <= T_max */
+  int32_t T_max;                 /* rows of the control tape */
+  float dt;                      /* time step [s] (> 0) */
+  float gravity[3];
+  float beta;                    /* Baumgarte factor (softening of section 2.1) */
+  float gamma;                   /* constraint force mixing (>= 0) */
+  float spec_margin;             /* contact candidate is active iff gap < spec_margin */
+  float warm;                    /* factor on carried impulses at the warm start */
+  int32_t n_iters;               /* Gauss-Seidel sweeps per step (>= 0) */
+  int32_t ground;                /* 1: ground plane z = 0 present */
+  int32_t loss_kind;             /* SIM_LOSS_* */
+  int32_t loss_mask;             /* bit k: coordinate k enters the loss */
+  int32_t ckpt_every;            /* K_ck: rollout stores the state every K_ck steps */
+} sim_model_desc;
+
+/* Sizes derived by sim_init. */
+typedef struct {
+  int32_t n_envs, n_bodies, n_joints;
+  int32_t lam_size;           /* total floats of the warm-start state */
+  int32_t n_ckpt;             /* checkpoints per rollout: floor((T_max-1)/K_ck)+1 (1 if T_max=0) */
+  int64_t ckpt_floats;        /* floats of the checkpoint buffer: n_ckpt*(18*B + lam_size) */
+  int64_t workspace_bytes;    /* device workspace needed by rollout_grad */
+  int32_t max_lds_bytes;      /* largest LDS allocation per workgroup among the tiles */
+  int32_t n_tiles;            /* env tiles scheduled per rollout */
+} sim_info;
+
+int sim_abi_version(void);
+
+/* Thread-local description of the last failure on this thread ("" if none). */
+const char* sim_last_error(void);
+
+/* Validate the description, build per-env topology (contact candidates,
+ * colour-major sweep order), size-bucket and tile the envs, and upload all
+ * constants to the current device (synchronous).  On success *out owns the
+ * device copies; release with sim_destroy. */
+sim_status sim_init(const sim_model_desc* desc, sim_handle* out);
+sim_status sim_destroy(sim_handle h);
+sim_status sim_get_info(sim_handle h, sim_info* info);
+/* lam_off[E+1] (host): start of each env's warm-start block. */
+sim_status sim_lambda_offsets(sim_handle h, int32_t* lam_off);
+
+/* One step for all envs: x_out = f_ph(x_in, u) at step index t (device
+ * pointers, x[18][B], u[J], lambda[lam_size]).  lam_in may equal lam_out;
+ * x_in must not alias x_out.  env_flags[E] (device, may be NULL) is
+ * overwritten. */
+sim_status sim_step(sim_handle h, const float* x_in, float* x_out, const float* u, const float* lam_in,
+                    float* lam_out, uint32_t* env_flags, void* stream);
+
+/* Forward rollout from x0 (device, x[18][B]) with the control tape u
+ * (device, [T_max][J]); warm-start impulses start at zero.  Writes
+ * loss_env[E] (device), x_final[18][B] (device, may be NULL), lam_final
+ * (device, may be NULL), the checkpoint buffer ckpt (device, sim_info
+ * .ckpt_floats floats, may be NULL when no gradient will be asked for) and
+ * env_flags[E] (device, may be NULL). */
+sim_status rollout(sim_handle h, const float* x0, const float* u, float* loss_env, float* x_final,
+                   float* lam_final, float* ckpt, uint32_t* env_flags, void* stream);
+
+/* Reverse mode.  Given the checkpoints written by `rollout` with the same
+ * x0 and u, and dL/dloss_env (device [E]), writes (each may be NULL):
+ *   g_x0[18][B], g_u[T_max][J] (entries beyond an env's T_e are zero),
+ *   g_inv_mass[B], g_inv_inertia[B][3], g_mu[E], g_damping[J]   (device).
+ * workspace: device scratch of at least sim_info.workspace_bytes (the
+ * per-env segment buffer of the checkpoint recompute). */
+sim_status rollout_grad(sim_handle h, const float* x0, const float* u, const float* ckpt,
+                        const float* dloss_env, float* g_x0, float* g_u, float* g_inv_mass,
+                        float* g_inv_inertia, float* g_mu, float* g_damping, void* workspace,
+                        size_t workspace_bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

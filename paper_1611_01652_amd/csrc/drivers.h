@@ -1,0 +1,238 @@
+// Env-level drivers built from the step phases: a forward rollout with
+// checkpoints, a single step, and the reverse sweep over checkpointed
+// segments (back-propagation through time, paper section 2.1.1, without
+// keeping the whole unrolled trajectory: each segment of K_ck steps is
+// recomputed from its checkpoint into a small per-env buffer, then its steps
+// are reversed last to first).
+#pragma once
+#include "step_core.h"
+
+namespace sim {
+
+struct RolloutArgs {
+  const float* x0;     // [18][B]
+  const float* u;      // [T_max][J] or null
+  float* loss;         // [E]
+  float* x_final;      // [18][B] or null
+  float* lam_final;    // [lam_tot] or null
+  float* ckpt;         // [n_ckpt][18 B + lam_tot] or null
+  uint32_t* flags;     // [E] or null
+};
+
+struct GradArgs {
+  const float* x0;
+  const float* u;
+  const float* ckpt;
+  const float* dloss;  // [E]
+  float* g_x0;         // [18][B]
+  float* g_u;          // [T_max][J]
+  float* g_invm;       // [B]
+  float* g_invI;       // [B][3]
+  float* g_mu;         // [E]
+  float* g_damp;       // [J]
+  float* seg;          // per-env segment buffers
+};
+
+struct StepArgs {
+  const float* x_in;
+  float* x_out;
+  const float* u;      // [J]
+  const float* lam_in;
+  float* lam_out;
+  uint32_t* flags;
+};
+
+SHD size_t ckpt_stride(const DevModel& M) { return (size_t)18 * M.B + M.lam_tot; }
+
+template <class Team>
+SHD void write_ckpt(const Team& tm, const DevModel& M, const Env& E, float* dst) {
+  store_state(tm, E, dst, M.B);
+  store_ws(tm, E, dst + (size_t)18 * M.B);
+}
+template <class Team>
+SHD void read_ckpt(const Team& tm, const DevModel& M, const Env& E, const float* src) {
+  load_state(tm, E, src, M.B);
+  load_ws(tm, E, src + (size_t)18 * M.B);
+}
+
+template <class Team>
+SHD uint32_t nonfinite_flag(const Team& tm, const Env& E) {
+  bool bad = false;
+  for (int b = tm.tl; b < E.nb; b += tm.ts) {
+    const float* B = E.body(b);
+    for (int k = 0; k < 18; ++k) bad = bad || !(fabsf(B[k]) <= 3.0e38f);
+  }
+  return tm.team_any(bad) ? 1u : 0u;
+}
+
+template <class Team>
+SHD void env_rollout(const Team& tm, const DevModel& M, const Env& E, bool valid, const RolloutArgs& a) {
+  if (valid) {
+    load_env_static(tm, M, E);
+    load_state(tm, E, a.x0, M.B);
+    for (int i = tm.tl; i < E.lam_size; i += tm.ts) E.ws()[i] = 0.f;
+  }
+  tm.sync();
+  float p0x = valid ? E.body(E.lb)[BP] : 0.f;
+  float loss = 0.f;
+  const int K = M.ckpt_every;
+  const int T = valid ? E.T : 0;
+  for (int t = 0; tm.any(t < T); ++t) {
+    const bool act = t < T;
+    if (act && a.ckpt && t % K == 0) write_ckpt(tm, M, E, a.ckpt + (size_t)(t / K) * ckpt_stride(M));
+    tm.sync();
+    env_step(tm, M, E, a.u ? a.u + (size_t)t * M.J : nullptr, act);
+    if (act && tm.tl == 0) {
+      const float* p = E.body(E.lb) + BP;
+      const float p0[3] = {p0x, 0.f, 0.f};
+      loss += loss_term(M, E, t + 1, p, p0);
+    }
+  }
+  tm.sync();
+  uint32_t fl = valid ? nonfinite_flag(tm, E) : 0u;
+  if (valid) {
+    if (a.x_final) store_state(tm, E, a.x_final, M.B);
+    if (a.lam_final) store_ws(tm, E, a.lam_final);
+    if (tm.tl == 0) {
+      a.loss[E.e] = loss;
+      fl |= (uint32_t)((int*)E.misc())[MISC_FLAGS];
+      if (a.flags) a.flags[E.e] = fl;
+    }
+  }
+}
+
+template <class Team>
+SHD void env_single_step(const Team& tm, const DevModel& M, const Env& E, bool valid, const StepArgs& a) {
+  if (valid) {
+    load_env_static(tm, M, E);
+    load_state(tm, E, a.x_in, M.B);
+    load_ws(tm, E, a.lam_in);
+  }
+  tm.sync();
+  env_step(tm, M, E, a.u, valid);
+  tm.sync();
+  uint32_t fl = valid ? nonfinite_flag(tm, E) : 0u;
+  if (valid) {
+    store_state(tm, E, a.x_out, M.B);
+    store_ws(tm, E, a.lam_out);
+    if (tm.tl == 0 && a.flags) a.flags[E.e] = fl | (uint32_t)((int*)E.misc())[MISC_FLAGS];
+  }
+}
+
+// loss adjoint into pbar of the loss body for the state after step t1 (1-based)
+SHD void loss_adj(const DevModel& M, const Env& E, int t1, const float* p, float dl, float* pbar) {
+  const float* tg = M.target + 3 * E.e;
+  if (M.loss_kind == 0) {
+    if (t1 != E.T) return;
+    for (int k = 0; k < 3; ++k)
+      if (M.loss_mask & (1 << k)) pbar[k] += dl * 2.f * (p[k] - tg[k]);
+    return;
+  }
+  if (M.loss_kind == 1) {
+    float d[3] = {0.f, 0.f, 0.f}, q = 0.f;
+    for (int k = 0; k < 3; ++k)
+      if (M.loss_mask & (1 << k)) { d[k] = p[k] - tg[k]; q += d[k] * d[k]; }
+    if (q <= 0.f) return;
+    const float s = dl / (sqrtf(q) * (float)E.T);
+    for (int k = 0; k < 3; ++k) pbar[k] += s * d[k];
+    return;
+  }
+  if (t1 != E.T) return;
+  pbar[0] += -dl / ((float)E.T * M.dt);
+}
+
+template <class Team>
+SHD void env_rollout_grad(const Team& tm, const DevModel& M, const Env& E, bool valid, const GradArgs& a) {
+  if (valid) {
+    load_env_static(tm, M, E);
+    for (int i = tm.tl; i < E.nb * BSA; i += tm.ts) E.L[E.lay.bodyA + i] = 0.f;
+    for (int i = tm.tl; i < E.lam_size; i += tm.ts) E.wsA()[i] = 0.f;
+    for (int i = tm.tl; i < E.nj; i += tm.ts) E.jA()[i] = 0.f;
+    if (tm.tl == 0) E.misc()[MISC_GMU] = 0.f;
+  }
+  tm.sync();
+  const int K = M.ckpt_every;
+  const int T = valid ? E.T : 0;
+  const float dl = valid ? a.dloss[E.e] : 0.f;
+  const int nseg = (T + K - 1) / K;
+  const int sstride = 18 * (valid ? E.nb : 0) + (valid ? E.lam_size : 0);
+  float* seg = valid ? a.seg + E.seg_off : nullptr;
+  // zero the control gradient rows beyond T (and all rows of idle envs)
+  if (valid && a.g_u)
+    for (int t = T; t < M.T_max; ++t)
+      for (int j = tm.tl; j < E.nj; j += tm.ts) a.g_u[(size_t)t * M.J + E.j0 + j] = 0.f;
+  for (int sg = nseg - 1; tm.any(sg >= 0); --sg) {
+    const bool sact = sg >= 0;
+    const int t0 = sact ? sg * K : 0;
+    const int t1 = sact ? (t0 + K < T ? t0 + K : T) : 0;
+    if (sact) read_ckpt(tm, M, E, a.ckpt + (size_t)sg * ckpt_stride(M));
+    tm.sync();
+    // recompute the segment, keeping each step-start state
+    for (int t = t0; tm.any(t < t1); ++t) {
+      const bool act = t < t1;
+      if (act) {
+        float* dst = seg + (size_t)(t - t0) * sstride;
+        for (int i = tm.tl; i < 18 * E.nb; i += tm.ts) dst[i] = E.body(i / 18)[i % 18];
+        for (int i = tm.tl; i < E.lam_size; i += tm.ts) dst[18 * E.nb + i] = E.ws()[i];
+      }
+      tm.sync();
+      env_step(tm, M, E, a.u ? a.u + (size_t)t * M.J : nullptr, act);
+    }
+    tm.sync();
+    if (sact && sg == nseg - 1 && tm.tl == 0 && M.loss_kind != 1)
+      loss_adj(M, E, T, E.body(E.lb) + BP, dl, E.bodyA(E.lb) + AP);
+    tm.sync();
+    // reverse the segment's steps
+    for (int t = t1 - 1; tm.any(t >= t0 && sact); --t) {
+      const bool act = sact && t >= t0;
+      if (act) {
+        const float* src = seg + (size_t)(t - t0) * sstride;
+        for (int i = tm.tl; i < 18 * E.nb; i += tm.ts) E.body(i / 18)[i % 18] = src[i];
+        for (int i = tm.tl; i < E.lam_size; i += tm.ts) E.ws()[i] = src[18 * E.nb + i];
+      }
+      tm.sync();
+      // replay step t with recording (no integration, no store)
+      f_controls(tm, M, E, a.u ? a.u + (size_t)t * M.J : nullptr, act);
+      f_body_setup(tm, E, act, true);
+      tm.sync();
+      f_torques(tm, E, act);
+      f_predict(tm, M, E, act);
+      tm.sync();
+      f_rows(tm, M, E, act);
+      f_warm(tm, E, act);
+      f_pgs(tm, M, E, act, true);
+      // loss on x^{t+1}: p(t+1) = p(t) + dt v'
+      if (act && tm.tl == 0 && M.loss_kind == 1) {
+        const float* B = E.body(E.lb);
+        const float p1[3] = {B[BP] + M.dt * B[BV], B[BP + 1] + M.dt * B[BV + 1], B[BP + 2] + M.dt * B[BV + 2]};
+        loss_adj(M, E, t + 1, p1, dl, E.bodyA(E.lb) + AP);
+      }
+      a_clear_step(tm, E, act);
+      tm.sync();
+      a_store(tm, E, act);
+      a_integrate(tm, M, E, act);
+      a_pgs(tm, M, E, act);
+      a_warm(tm, M, E, act);
+      a_rows(tm, M, E, act);
+      a_predict_torques(tm, M, E, act, (act && a.g_u) ? a.g_u + (size_t)t * M.J : nullptr, nullptr);
+    }
+    tm.sync();
+  }
+  if (valid) {
+    if (M.loss_kind == 2 && T > 0 && tm.tl == 0) E.bodyA(E.lb)[AP] += dl / ((float)T * M.dt);
+    tm.sync();
+    for (int b = tm.tl; b < E.nb; b += tm.ts) {
+      const float* A = E.bodyA(b);
+      if (a.g_x0)
+        for (int k = 0; k < 18; ++k) a.g_x0[(size_t)k * M.B + E.b0 + b] = A[k];
+      if (a.g_invm) a.g_invm[E.b0 + b] = A[AIM];
+      if (a.g_invI)
+        for (int k = 0; k < 3; ++k) a.g_invI[3 * (E.b0 + b) + k] = A[AII + k];
+    }
+    if (a.g_damp)
+      for (int j = tm.tl; j < E.nj; j += tm.ts) a.g_damp[E.j0 + j] = E.jA()[j];
+    if (tm.tl == 0 && a.g_mu) a.g_mu[E.e] = E.misc()[MISC_GMU];
+  }
+}
+
+}  // namespace sim

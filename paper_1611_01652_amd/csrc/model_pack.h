@@ -1,0 +1,23 @@
+// Host-side packing of a model description (see model_pack.cpp).
+#pragma once
+#include <string>
+#include <vector>
+
+#include "../../include/sim.h"
+#include "step_core.h"
+
+namespace sim {
+
+struct PackedModel {
+  std::vector<int> hdr, topo, lam_off, team_of, fwd_of, adj_of;
+  std::vector<float> cst, target;
+  long long seg_total = 0;
+};
+
+// Validates the per-env parts of the description and builds, per env, the
+// header, topology ints (parents, children, ground bodies, pair codes, colour
+// starts, colour-major candidate list) and constants.  Global checks
+// (offsets, scalars) are done by the caller.
+sim_status pack_model(const sim_model_desc* d, PackedModel& P, std::string& err);
+
+}  // namespace sim

@@ -1,0 +1,303 @@
+// C ABI of the batched rigid-body step (declared in include/sim.h): model
+// validation, per-env topology (contact candidates and the colour-major sweep
+// order), size buckets and env tiles, device upload, and the launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/sim.h"
+#include "model_pack.h"
+#include "sim_internal.h"
+
+using namespace sim;
+
+namespace {
+
+thread_local std::string g_err;
+
+sim_status fail(sim_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+struct Bucket {
+  int team = 1;
+  std::vector<int> envs_host;   // tiles * (64/team)
+  int n_tiles = 0;
+  int floats_fwd = 0, floats_adj = 0;
+  int* envs_dev = nullptr;
+};
+
+}  // namespace
+
+struct sim_model {
+  DevModel M{};
+  sim_info info{};
+  std::vector<int> lam_off;     // [E+1]
+  std::vector<Bucket> buckets;
+  int* d_hdr = nullptr;
+  int* d_topo = nullptr;
+  float* d_cst = nullptr;
+  float* d_target = nullptr;
+  int* d_queue = nullptr;       // one counter per bucket
+  int n_cu = 256;
+  int max_lds = 65536;
+  int device = 0;
+};
+
+namespace {
+
+template <class T>
+sim_status upload(T** dst, const std::vector<T>& src) {
+  const size_t n = std::max<size_t>(src.size(), 1) * sizeof(T);
+  if (hipMalloc((void**)dst, n) != hipSuccess) return fail(SIM_E_NOMEM, "hipMalloc failed");
+  if (!src.empty() && hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice) != hipSuccess)
+    return fail(SIM_E_DEVICE, "hipMemcpy failed");
+  return SIM_OK;
+}
+
+void release(sim_model* h) {
+  if (!h) return;
+  for (auto& b : h->buckets)
+    if (b.envs_dev) (void)hipFree(b.envs_dev);
+  if (h->d_hdr) (void)hipFree(h->d_hdr);
+  if (h->d_topo) (void)hipFree(h->d_topo);
+  if (h->d_cst) (void)hipFree(h->d_cst);
+  if (h->d_target) (void)hipFree(h->d_target);
+  if (h->d_queue) (void)hipFree(h->d_queue);
+  delete h;
+}
+
+sim_status check_device(const char* what) {
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(SIM_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+  return SIM_OK;
+}
+
+int grid_for(const sim_model* h, const Bucket& b, int floats) {
+  const int bytes = (64 / b.team) * floats * 4;
+  int per_cu = bytes > 0 ? (160 * 1024) / bytes : 8;
+  per_cu = std::max(1, std::min(per_cu, 8));
+  return std::max(1, std::min(b.n_tiles, h->n_cu * per_cu));
+}
+
+}  // namespace
+
+extern "C" {
+
+int sim_abi_version(void) { return SIM_ABI_VERSION; }
+
+const char* sim_last_error(void) { return g_err.c_str(); }
+
+sim_status sim_init(const sim_model_desc* d, sim_handle* out) {
+  g_err.clear();
+  if (!d || !out) return fail(SIM_E_ARG, "sim_init: null argument");
+  *out = nullptr;
+  const int E = d->n_envs;
+  if (E < 0) return fail(SIM_E_ARG, "n_envs < 0");
+  if (!d->env_body_off || !d->env_joint_off || !d->env_sphere_off)
+    return fail(SIM_E_ARG, "null CSR offsets");
+  if (d->env_body_off[0] != 0 || d->env_joint_off[0] != 0 || d->env_sphere_off[0] != 0)
+    return fail(SIM_E_SHAPE, "CSR offsets must start at 0");
+  for (int e = 0; e < E; ++e)
+    if (d->env_body_off[e + 1] < d->env_body_off[e] || d->env_joint_off[e + 1] < d->env_joint_off[e] ||
+        d->env_sphere_off[e + 1] < d->env_sphere_off[e])
+      return fail(SIM_E_SHAPE, "CSR offsets must be non-decreasing (env " + std::to_string(e) + ")");
+  const int B = d->env_body_off[E], J = d->env_joint_off[E], S = d->env_sphere_off[E];
+  if ((B > 0 && (!d->inv_mass || !d->inv_inertia)) || (J > 0 && (!d->joint_parent || !d->joint_child ||
+      !d->anchor_p || !d->anchor_c || !d->axis_p || !d->axis_c || !d->perp_p || !d->perp_c || !d->damping)) ||
+      (S > 0 && (!d->sphere_body || !d->sphere_offset || !d->sphere_radius || !d->sphere_flags)) ||
+      (E > 0 && (!d->mu || !d->loss_body || !d->target || !d->T_env)))
+    return fail(SIM_E_ARG, "null model array");
+  if (!(d->dt > 0.f) || !std::isfinite(d->dt)) return fail(SIM_E_ARG, "dt must be > 0");
+  if (d->n_iters < 0) return fail(SIM_E_ARG, "n_iters < 0");
+  if (d->ckpt_every < 1) return fail(SIM_E_ARG, "ckpt_every < 1");
+  if (d->T_max < 0) return fail(SIM_E_ARG, "T_max < 0");
+  if (d->loss_kind < 0 || d->loss_kind > 2) return fail(SIM_E_ARG, "unknown loss_kind");
+  if (!(d->gamma >= 0.f)) return fail(SIM_E_ARG, "gamma < 0");
+  for (int e = 0; e < E; ++e) {
+    if (d->T_env[e] < 0 || d->T_env[e] > d->T_max) return fail(SIM_E_SHAPE, "T_env outside [0, T_max]");
+    if (d->loss_body[e] < d->env_body_off[e] || d->loss_body[e] >= d->env_body_off[e + 1])
+      return fail(SIM_E_SHAPE, "loss_body outside its env (env " + std::to_string(e) + ")");
+  }
+  for (int j = 0; j < J; ++j)
+    if (!(d->damping[j] >= 0.f) || !std::isfinite(d->damping[j])) return fail(SIM_E_ARG, "damping < 0");
+
+  sim_model* h = new sim_model();
+  if (hipGetDevice(&h->device) != hipSuccess) { release(h); return fail(SIM_E_DEVICE, "no HIP device"); }
+  (void)hipDeviceGetAttribute(&h->n_cu, hipDeviceAttributeMultiprocessorCount, h->device);
+  (void)hipDeviceGetAttribute(&h->max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, h->device);
+  DevModel& M = h->M;
+  M.n_envs = E; M.B = B; M.J = J; M.T_max = d->T_max; M.n_iters = d->n_iters; M.ground = d->ground;
+  M.loss_kind = d->loss_kind; M.loss_mask = d->loss_mask; M.ckpt_every = d->ckpt_every;
+  M.dt = d->dt; M.gx = d->gravity[0]; M.gy = d->gravity[1]; M.gz = d->gravity[2];
+  M.beta = d->beta; M.gamma = d->gamma; M.spec = d->spec_margin; M.warm = d->warm;
+
+  PackedModel P;
+  std::string perr;
+  {
+    const sim_status st = pack_model(d, P, perr);
+    if (st != SIM_OK) { release(h); return fail(st, perr); }
+  }
+  h->lam_off = P.lam_off;
+  std::vector<int>& team_of = P.team_of;
+  const std::vector<int>& fwd_of = P.fwd_of;
+  const std::vector<int>& adj_of = P.adj_of;
+  const long long seg_total = P.seg_total;
+  int max_lds = 0;
+  for (int e = 0; e < E; ++e) {
+    // widen the team while the tile does not fit in LDS
+    int team = team_of[e];
+    while (team < 64 && (64 / team) * (long long)adj_of[e] * 4 > h->max_lds) team *= 2;
+    if ((64 / team) * (long long)adj_of[e] * 4 > h->max_lds) {
+      release(h);
+      return fail(SIM_E_UNSUPPORTED, "env " + std::to_string(e) + " needs " + std::to_string(adj_of[e] * 4) +
+                                         " bytes of LDS, more than the device's " + std::to_string(h->max_lds));
+    }
+    team_of[e] = team;
+  }
+  M.lam_tot = h->lam_off[E];
+  // buckets by team size; tiles sorted longest episode first, then largest env
+  for (int team = 1; team <= 64; team *= 2) {
+    std::vector<int> ids;
+    for (int e = 0; e < E; ++e)
+      if (team_of[e] == team) ids.push_back(e);
+    if (ids.empty()) continue;
+    std::stable_sort(ids.begin(), ids.end(), [&](int a, int b) {
+      if (d->T_env[a] != d->T_env[b]) return d->T_env[a] > d->T_env[b];
+      return adj_of[a] > adj_of[b];
+    });
+    Bucket bk;
+    bk.team = team;
+    const int epw = 64 / team;
+    bk.n_tiles = ((int)ids.size() + epw - 1) / epw;
+    bk.envs_host.assign((size_t)bk.n_tiles * epw, -1);
+    for (size_t i = 0; i < ids.size(); ++i) {
+      bk.envs_host[i] = ids[i];
+      bk.floats_fwd = std::max(bk.floats_fwd, fwd_of[ids[i]]);
+      bk.floats_adj = std::max(bk.floats_adj, adj_of[ids[i]]);
+    }
+    max_lds = std::max(max_lds, epw * bk.floats_adj * 4);
+    h->buckets.push_back(bk);
+  }
+  sim_status st = SIM_OK;
+  if ((st = upload(&h->d_hdr, P.hdr)) != SIM_OK || (st = upload(&h->d_topo, P.topo)) != SIM_OK ||
+      (st = upload(&h->d_cst, P.cst)) != SIM_OK || (st = upload(&h->d_target, P.target)) != SIM_OK) {
+    release(h);
+    return st;
+  }
+  for (auto& b : h->buckets)
+    if ((st = upload(&b.envs_dev, b.envs_host)) != SIM_OK) { release(h); return st; }
+  if ((st = upload(&h->d_queue, std::vector<int>(std::max<size_t>(1, h->buckets.size()), 0))) != SIM_OK) {
+    release(h);
+    return st;
+  }
+  if (max_lds > 65536 && allow_large_lds(std::min(max_lds, h->max_lds)) != hipSuccess) {
+    release(h);
+    return fail(SIM_E_DEVICE, "cannot raise the dynamic LDS limit");
+  }
+  M.hdr = h->d_hdr; M.topo = h->d_topo; M.cst = h->d_cst; M.target = h->d_target;
+  sim_info& I = h->info;
+  I.n_envs = E; I.n_bodies = B; I.n_joints = J; I.lam_size = M.lam_tot;
+  I.n_ckpt = d->T_max > 0 ? (d->T_max - 1) / d->ckpt_every + 1 : 1;
+  I.ckpt_floats = (int64_t)I.n_ckpt * (18LL * B + M.lam_tot);
+  I.workspace_bytes = 4LL * std::max<long long>(seg_total, 1);
+  I.max_lds_bytes = max_lds;
+  I.n_tiles = 0;
+  for (auto& b : h->buckets) I.n_tiles += b.n_tiles;
+  *out = h;
+  return SIM_OK;
+}
+
+sim_status sim_destroy(sim_handle h) {
+  if (!h) return fail(SIM_E_ARG, "sim_destroy: null handle");
+  release(h);
+  return SIM_OK;
+}
+
+sim_status sim_get_info(sim_handle h, sim_info* info) {
+  if (!h || !info) return fail(SIM_E_ARG, "sim_get_info: null argument");
+  *info = h->info;
+  return SIM_OK;
+}
+
+sim_status sim_lambda_offsets(sim_handle h, int32_t* lam_off) {
+  if (!h || !lam_off) return fail(SIM_E_ARG, "sim_lambda_offsets: null argument");
+  std::copy(h->lam_off.begin(), h->lam_off.end(), lam_off);
+  return SIM_OK;
+}
+
+sim_status sim_step(sim_handle h, const float* x_in, float* x_out, const float* u, const float* lam_in,
+                    float* lam_out, uint32_t* env_flags, void* stream) {
+  if (!h) return fail(SIM_E_ARG, "sim_step: null handle");
+  if (h->M.n_envs == 0) return SIM_OK;
+  if (!x_in || !x_out || (h->M.lam_tot > 0 && (!lam_in || !lam_out)) || (h->M.J > 0 && !u))
+    return fail(SIM_E_ARG, "sim_step: null array");
+  if (x_in == x_out) return fail(SIM_E_ARG, "sim_step: x_in must not alias x_out");
+  sim_status s = check_device("sim_step (earlier fault)");
+  if (s != SIM_OK) return s;
+  hipStream_t st = (hipStream_t)stream;
+  StepArgs a{x_in, x_out, u, lam_in, lam_out, env_flags};
+  for (size_t i = 0; i < h->buckets.size(); ++i) {
+    const Bucket& b = h->buckets[i];
+    TileSet ts{b.envs_dev, b.n_tiles, b.floats_fwd, h->d_queue + i};
+    if (launch_zero(ts.queue, 1, st) != hipSuccess) return check_device("sim_step zero");
+    const size_t lds = (size_t)(64 / b.team) * b.floats_fwd * 4;
+    if (launch_step(h->M, ts, b.team, grid_for(h, b, b.floats_fwd), lds, a, st) != hipSuccess)
+      return check_device("sim_step launch");
+  }
+  return SIM_OK;
+}
+
+sim_status rollout(sim_handle h, const float* x0, const float* u, float* loss_env, float* x_final,
+                   float* lam_final, float* ckpt, uint32_t* env_flags, void* stream) {
+  if (!h) return fail(SIM_E_ARG, "rollout: null handle");
+  if (h->M.n_envs == 0) return SIM_OK;
+  if (!x0 || !loss_env) return fail(SIM_E_ARG, "rollout: null x0 or loss_env");
+  if (h->M.J > 0 && h->M.T_max > 0 && !u) return fail(SIM_E_ARG, "rollout: null control tape");
+  sim_status s = check_device("rollout (earlier fault)");
+  if (s != SIM_OK) return s;
+  hipStream_t st = (hipStream_t)stream;
+  RolloutArgs a{x0, u, loss_env, x_final, lam_final, ckpt, env_flags};
+  for (size_t i = 0; i < h->buckets.size(); ++i) {
+    const Bucket& b = h->buckets[i];
+    TileSet ts{b.envs_dev, b.n_tiles, b.floats_fwd, h->d_queue + i};
+    if (launch_zero(ts.queue, 1, st) != hipSuccess) return check_device("rollout zero");
+    const size_t lds = (size_t)(64 / b.team) * b.floats_fwd * 4;
+    if (launch_rollout(h->M, ts, b.team, grid_for(h, b, b.floats_fwd), lds, a, st) != hipSuccess)
+      return check_device("rollout launch");
+  }
+  return SIM_OK;
+}
+
+sim_status rollout_grad(sim_handle h, const float* x0, const float* u, const float* ckpt, const float* dloss_env,
+                        float* g_x0, float* g_u, float* g_inv_mass, float* g_inv_inertia, float* g_mu,
+                        float* g_damping, void* workspace, size_t workspace_bytes, void* stream) {
+  if (!h) return fail(SIM_E_ARG, "rollout_grad: null handle");
+  if (h->M.n_envs == 0) return SIM_OK;
+  if (!x0 || !ckpt || !dloss_env) return fail(SIM_E_ARG, "rollout_grad: null x0, ckpt or dloss_env");
+  if (h->M.J > 0 && h->M.T_max > 0 && !u) return fail(SIM_E_ARG, "rollout_grad: null control tape");
+  if (!workspace || (int64_t)workspace_bytes < h->info.workspace_bytes)
+    return fail(SIM_E_NOMEM, "rollout_grad: workspace smaller than sim_info.workspace_bytes (" +
+                                 std::to_string(h->info.workspace_bytes) + ")");
+  sim_status s = check_device("rollout_grad (earlier fault)");
+  if (s != SIM_OK) return s;
+  hipStream_t st = (hipStream_t)stream;
+  GradArgs a{x0, u, ckpt, dloss_env, g_x0, g_u, g_inv_mass, g_inv_inertia, g_mu, g_damping, (float*)workspace};
+  for (size_t i = 0; i < h->buckets.size(); ++i) {
+    const Bucket& b = h->buckets[i];
+    TileSet ts{b.envs_dev, b.n_tiles, b.floats_adj, h->d_queue + i};
+    if (launch_zero(ts.queue, 1, st) != hipSuccess) return check_device("rollout_grad zero");
+    const size_t lds = (size_t)(64 / b.team) * b.floats_adj * 4;
+    if (launch_rollout_grad(h->M, ts, b.team, grid_for(h, b, b.floats_adj), lds, a, st) != hipSuccess)
+      return check_device("rollout_grad launch");
+  }
+  return SIM_OK;
+}
+
+}  // extern "C"

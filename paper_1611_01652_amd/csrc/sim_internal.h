@@ -1,0 +1,26 @@
+// Host <-> kernel interface inside the library (not part of the C ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "drivers.h"
+
+namespace sim {
+
+// A bucket of env tiles that share one team size.
+struct TileSet {
+  const int* envs;   // [n_tiles * (64/TEAM)] env indices, -1 = idle team
+  int n_tiles;
+  int env_floats;    // LDS floats reserved per env
+  int* queue;        // device counter of the persistent tile queue
+};
+
+hipError_t launch_zero(int* p, int n, hipStream_t st);
+hipError_t launch_rollout(const DevModel& M, const TileSet& ts, int team, int grid, size_t lds,
+                          const RolloutArgs& a, hipStream_t st);
+hipError_t launch_step(const DevModel& M, const TileSet& ts, int team, int grid, size_t lds, const StepArgs& a,
+                       hipStream_t st);
+hipError_t launch_rollout_grad(const DevModel& M, const TileSet& ts, int team, int grid, size_t lds,
+                               const GradArgs& a, hipStream_t st);
+hipError_t allow_large_lds(int bytes);
+
+}  // namespace sim

@@ -1,0 +1,1351 @@
+// Per-environment time step and its hand-written adjoint, for one "team" of
+// lanes that owns one env.  All of the env's working set lives in LDS.
+//
+// The step (paper section 2.1): joint torques -> velocity prediction ->
+// contact candidates / gap test -> constraint rows -> warm start -> fixed
+// projected Gauss-Seidel sweeps in colour-major order -> semi-implicit Euler
+// + rotation renormalisation N(A) = (3A - A A^T A)/2 (eq. (1)).
+//
+// Parallelism inside a team: bodies, joints and candidates are strided over
+// the team's lanes; the Gauss-Seidel sweep runs colour by colour, and the
+// constraints of one colour (which touch disjoint bodies, so the result does
+// not depend on their order) run on different lanes at once.  The rows of one
+// constraint are updated in sequence by the lane that owns it.
+//
+// The adjoint reverses one step given dL/dx^{t+1} and dL/dlambda^t: the
+// forward step is first replayed on chip from the stored step-start state
+// while the pre-projection impulse of every row update is recorded; then the
+// integration, the sweeps (iterations, colours and rows exactly reversed,
+// velocities reconstructed by undoing each update, clamp / disk branches
+// taken from the recorded values), the warm start, the row set-up, the
+// velocity prediction and the torques are differentiated in turn.
+//
+// This header compiles both as HIP device code and as plain host C++ (a team
+// of one lane), so the arithmetic can be checked on a CPU during development.
+#pragma once
+#include <cmath>
+#include <cstdint>
+
+#if defined(__HIPCC__)
+#define SHD __host__ __device__ inline
+#else
+#define SHD inline
+#endif
+
+namespace sim {
+
+// ------------------------------------------------------------------ small vectors
+struct f3 { float x, y, z; };
+SHD f3 mk3(float x, float y, float z) { f3 r; r.x = x; r.y = y; r.z = z; return r; }
+SHD f3 operator+(f3 a, f3 b) { return mk3(a.x + b.x, a.y + b.y, a.z + b.z); }
+SHD f3 operator-(f3 a, f3 b) { return mk3(a.x - b.x, a.y - b.y, a.z - b.z); }
+SHD f3 operator-(f3 a) { return mk3(-a.x, -a.y, -a.z); }
+SHD f3 operator*(float s, f3 a) { return mk3(s * a.x, s * a.y, s * a.z); }
+SHD float dot(f3 a, f3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+SHD f3 cross(f3 a, f3 b) { return mk3(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x); }
+SHD f3 ld3(const float* p) { return mk3(p[0], p[1], p[2]); }
+SHD void st3(float* p, f3 v) { p[0] = v.x; p[1] = v.y; p[2] = v.z; }
+SHD void add3(float* p, f3 v) { p[0] += v.x; p[1] += v.y; p[2] += v.z; }
+// R (row-major 9) times v, and R^T times v
+SHD f3 mv(const float* R, f3 v) {
+  return mk3(R[0] * v.x + R[1] * v.y + R[2] * v.z, R[3] * v.x + R[4] * v.y + R[5] * v.z,
+             R[6] * v.x + R[7] * v.y + R[8] * v.z);
+}
+// symmetric 3x3 stored as xx yy zz xy xz yz
+SHD f3 sv(const float* S, f3 v) {
+  return mk3(S[0] * v.x + S[3] * v.y + S[4] * v.z, S[3] * v.x + S[1] * v.y + S[5] * v.z,
+             S[4] * v.x + S[5] * v.y + S[2] * v.z);
+}
+// M += a b^T  (full 3x3 row-major)
+SHD void add_outer(float* M, f3 a, f3 b) {
+  M[0] += a.x * b.x; M[1] += a.x * b.y; M[2] += a.x * b.z;
+  M[3] += a.y * b.x; M[4] += a.y * b.y; M[5] += a.y * b.z;
+  M[6] += a.z * b.x; M[7] += a.z * b.y; M[8] += a.z * b.z;
+}
+
+// ------------------------------------------------------------------ model in global memory
+enum { H_B0, H_NB, H_J0, H_NJ, H_LAMOFF, H_LAMSZ, H_G, H_P, H_NCOL, H_TOPO, H_CST, H_T, H_LB, H_CCAP,
+       H_NCAND, H_ENV, H_SEG, H_NSLOT, H_COUNT };
+// candidate code: kind in the top byte
+enum { K_JOINT = 0, K_GROUND = 1, K_PAIR = 2 };
+SHD int cand_kind(int c) { return c >> 24; }
+SHD int cand_idx(int c) { return c & 0xFFFFFF; }
+
+struct DevModel {
+  int n_envs, B, J, lam_tot, T_max, n_iters, ground, loss_kind, loss_mask, ckpt_every;
+  float dt, gx, gy, gz, beta, gamma, spec, warm;
+  const int* hdr;     // [E][H_COUNT]
+  const int* topo;    // per-env topology ints
+  const float* cst;   // per-env constants
+  const float* target;// [E][3]
+};
+
+// ------------------------------------------------------------------ LDS layout
+// body record (forward)
+enum { BP = 0, BR = 3, BV = 12, BW = 15, BI = 18, BIM = 24, BII = 25, BTQ = 28, BPR = 31, BPO = 32, BS = 36 };
+// body record (adjoint)
+enum { AP = 0, AR = 3, AV = 12, AW = 15, AIW = 18, AIM = 27, AII = 28, ATQ = 31, AW0 = 34, BSA = 40 };
+// joint constants
+enum { JAP = 0, JAC = 3, JXP = 6, JXC = 9, JUP = 12, JUC = 15, JD = 18, JU = 19, JS = 20 };
+// row slot; a contact uses 4 slots: normal, tangent 1, tangent 2, extras
+enum { RJL = 0, RJA = 3, RJB = 6, RWA = 9, RWB = 12, RM = 15, RBI = 16, RL = 17, RL0 = 18, RS = 20 };
+enum { XT1 = 0, XT2 = 3, XMT = 6, XGAP = 7, XSTORE = 8, XCODE = 9 };
+// row adjoint slot
+enum { QJL = 0, QJA = 3, QJB = 6, QWA = 9, QWB = 12, QM = 15, QB = 16, QL = 17, RSA = 20 };
+
+struct Lay {
+  int body, jc, gs, topo, ws, rows, act_cnt, act_slot, act_code, misc;   // forward
+  int bodyA, rowsA, hist, wsA, jA;                                        // adjoint
+  int total_fwd, total;
+};
+enum { MISC_LOSS = 0, MISC_FLAGS = 1, MISC_NCON = 2, MISC_MU = 3, MISC_GMU = 4, MISC_N = 8 };
+
+SHD int align4(int x) { return (x + 3) & ~3; }
+SHD Lay make_lay(int nb, int nj, int G, int P, int ncol, int ncand, int nslot, int lam, int n_iters, bool adj) {
+  Lay L;
+  int o = 0;
+  L.body = o; o += align4(nb * BS);
+  L.jc = o; o += align4(nj * JS);
+  L.gs = o; o += align4(G * 4);
+  L.topo = o; o += align4(2 * nj + G + P + ncol + 1 + ncand);
+  L.ws = o; o += align4(lam);
+  L.rows = o; o += align4(nslot * RS);
+  L.act_cnt = o; o += align4(ncol);
+  L.act_slot = o; o += align4(ncand);
+  L.act_code = o; o += align4(ncand);
+  L.misc = o; o += MISC_N;
+  L.total_fwd = o;
+  if (adj) {
+    L.bodyA = o; o += align4(nb * BSA);
+    L.rowsA = o; o += align4(nslot * RSA);
+    L.hist = o; o += align4(n_iters * nslot);
+    L.wsA = o; o += align4(lam);
+    L.jA = o; o += align4(nj);
+  } else {
+    L.bodyA = L.rowsA = L.hist = L.wsA = L.jA = o;
+  }
+  L.total = o;
+  return L;
+}
+
+// ------------------------------------------------------------------ env view
+struct Env {
+  int b0, nb, j0, nj, lam_off, lam_size, G, P, ncol, T, lb, ccap, ncand, e, nslot, seg_off;
+  const int* gtopo;   // global topology of the env
+  const float* gcst;  // global constants of the env
+  float* L;           // LDS base of the env
+  Lay lay;
+  // LDS accessors
+  SHD float* body(int b) const { return L + lay.body + b * BS; }
+  SHD float* bodyA(int b) const { return L + lay.bodyA + b * BSA; }
+  SHD float* jc(int j) const { return L + lay.jc + j * JS; }
+  SHD float* gsph(int g) const { return L + lay.gs + 4 * g; }
+  SHD int* topo() const { return (int*)(L + lay.topo); }
+  SHD int jpar(int j) const { return topo()[j]; }
+  SHD int jchi(int j) const { return topo()[nj + j]; }
+  SHD int gbody(int g) const { return topo()[2 * nj + g]; }
+  SHD int pcode(int p) const { return topo()[2 * nj + G + p]; }
+  SHD int colstart(int c) const { return topo()[2 * nj + G + P + c]; }
+  SHD int cand(int i) const { return topo()[2 * nj + G + P + ncol + 1 + i]; }
+  SHD float* ws() const { return L + lay.ws; }
+  SHD float* wsA() const { return L + lay.wsA; }
+  SHD float* row(int s) const { return L + lay.rows + s * RS; }
+  SHD float* rowA(int s) const { return L + lay.rowsA + s * RSA; }
+  SHD float* hist(int it) const { return L + lay.hist + it * nslot; }
+  SHD int* act_cnt() const { return (int*)(L + lay.act_cnt); }
+  SHD int* act_slot() const { return (int*)(L + lay.act_slot); }
+  SHD int* act_code() const { return (int*)(L + lay.act_code); }
+  SHD float* misc() const { return L + lay.misc; }
+  SHD float* jA() const { return L + lay.jA; }
+  // warm-start store offset of a candidate
+  SHD int store_of(int code) const {
+    const int k = cand_kind(code), i = cand_idx(code);
+    if (k == K_JOINT) return 5 * i;
+    if (k == K_GROUND) return 5 * nj + 4 * i;
+    return 5 * nj + 4 * G + 4 * i;
+  }
+};
+
+SHD Env make_env(const DevModel& M, int ie, float* lds, int n_iters, bool adj) {
+  const int* h = M.hdr + (size_t)ie * H_COUNT;
+  Env E;
+  E.b0 = h[H_B0]; E.nb = h[H_NB]; E.j0 = h[H_J0]; E.nj = h[H_NJ];
+  E.lam_off = h[H_LAMOFF]; E.lam_size = h[H_LAMSZ]; E.G = h[H_G]; E.P = h[H_P]; E.ncol = h[H_NCOL];
+  E.T = h[H_T]; E.lb = h[H_LB]; E.ccap = h[H_CCAP]; E.ncand = h[H_NCAND]; E.e = h[H_ENV];
+  E.nslot = h[H_NSLOT]; E.seg_off = h[H_SEG];
+  E.gtopo = M.topo + h[H_TOPO];
+  E.gcst = M.cst + h[H_CST];
+  E.L = lds;
+  E.lay = make_lay(E.nb, E.nj, E.G, E.P, E.ncol, E.ncand, E.nslot, E.lam_size, n_iters, adj);
+  return E;
+}
+
+// per-env constants in global memory:
+//   bodies  invm[nb], invI[3][nb], pair-sphere offset[3][nb], pair-sphere radius[nb]
+//   joints  20 floats each (JAP..JD layout, JU unused)
+//   ground  offset(3), radius  per ground sphere
+//   env     mu
+SHD int cst_joint(const Env& E) { return 8 * E.nb; }
+SHD int cst_ground(const Env& E) { return 8 * E.nb + JS * E.nj; }
+SHD int cst_env(const Env& E) { return 8 * E.nb + JS * E.nj + 4 * E.G; }
+SHD int cst_size(int nb, int nj, int G) { return 8 * nb + JS * nj + 4 * G + 4; }
+SHD int topo_size(int nj, int G, int P, int ncol, int ncand) { return 2 * nj + G + P + ncol + 1 + ncand; }
+
+// Load topology and constants of the env into LDS (team-parallel).
+template <class Team>
+SHD void load_env_static(const Team& tm, const DevModel& M, const Env& E) {
+  const int ntopo = topo_size(E.nj, E.G, E.P, E.ncol, E.ncand);
+  int* tp = E.topo();
+  for (int i = tm.tl; i < ntopo; i += tm.ts) tp[i] = E.gtopo[i];
+  for (int b = tm.tl; b < E.nb; b += tm.ts) {
+    float* B = E.body(b);
+    B[BIM] = E.gcst[b];
+    for (int k = 0; k < 3; ++k) B[BII + k] = E.gcst[E.nb + 3 * b + k];
+    for (int k = 0; k < 3; ++k) B[BPO + k] = E.gcst[4 * E.nb + 3 * b + k];
+    B[BPR] = E.gcst[7 * E.nb + b];
+  }
+  for (int i = tm.tl; i < JS * E.nj; i += tm.ts) E.L[E.lay.jc + i] = E.gcst[cst_joint(E) + i];
+  for (int i = tm.tl; i < 4 * E.G; i += tm.ts) E.L[E.lay.gs + i] = E.gcst[cst_ground(E) + i];
+  if (tm.tl == 0) {
+    E.misc()[MISC_MU] = E.gcst[cst_env(E)];
+    E.misc()[MISC_LOSS] = 0.f;
+    ((int*)E.misc())[MISC_FLAGS] = 0;
+  }
+}
+
+// state x[18][B] (SoA, global) <-> LDS body records
+template <class Team>
+SHD void load_state(const Team& tm, const Env& E, const float* x, int B) {
+  for (int b = tm.tl; b < E.nb; b += tm.ts) {
+    float* R = E.body(b);
+    for (int k = 0; k < 18; ++k) R[k] = x[(size_t)k * B + E.b0 + b];
+  }
+}
+template <class Team>
+SHD void store_state(const Team& tm, const Env& E, float* x, int B) {
+  for (int b = tm.tl; b < E.nb; b += tm.ts) {
+    const float* R = E.body(b);
+    for (int k = 0; k < 18; ++k) x[(size_t)k * B + E.b0 + b] = R[k];
+  }
+}
+template <class Team>
+SHD void load_ws(const Team& tm, const Env& E, const float* lam) {
+  for (int i = tm.tl; i < E.lam_size; i += tm.ts) E.ws()[i] = lam[E.lam_off + i];
+}
+template <class Team>
+SHD void store_ws(const Team& tm, const Env& E, float* lam) {
+  for (int i = tm.tl; i < E.lam_size; i += tm.ts) lam[E.lam_off + i] = E.ws()[i];
+}
+
+// ------------------------------------------------------------------ row helpers
+// two-body row: a may be -1 (world)
+struct RowB { int a, b; };
+
+SHD float row_jv(const float* r, const float* va, const float* wa, const float* vb, const float* wb, bool has_a) {
+  // J v = Jl.(vb - va) + Jaa.wa + Jab.wb
+  float s = r[RJL] * vb[0] + r[RJL + 1] * vb[1] + r[RJL + 2] * vb[2];
+  s += r[RJB] * wb[0] + r[RJB + 1] * wb[1] + r[RJB + 2] * wb[2];
+  if (has_a) {
+    s -= r[RJL] * va[0] + r[RJL + 1] * va[1] + r[RJL + 2] * va[2];
+    s += r[RJA] * wa[0] + r[RJA + 1] * wa[1] + r[RJA + 2] * wa[2];
+  }
+  return s;
+}
+SHD void row_apply(const float* r, float* va, float* wa, float* vb, float* wb, bool has_a, float ima, float imb,
+                   float d) {
+  const float cb = imb * d;
+  vb[0] += cb * r[RJL]; vb[1] += cb * r[RJL + 1]; vb[2] += cb * r[RJL + 2];
+  wb[0] += d * r[RWB]; wb[1] += d * r[RWB + 1]; wb[2] += d * r[RWB + 2];
+  if (has_a) {
+    const float ca = ima * d;
+    va[0] -= ca * r[RJL]; va[1] -= ca * r[RJL + 1]; va[2] -= ca * r[RJL + 2];
+    wa[0] += d * r[RWA]; wa[1] += d * r[RWA + 1]; wa[2] += d * r[RWA + 2];
+  }
+}
+// W = M^-1 J^T (angular parts stored), returns K = J W
+SHD float row_finish(float* r, const float* Ba, const float* Bb, bool has_a) {
+  const f3 jl = ld3(r + RJL);
+  const f3 jb = ld3(r + RJB);
+  const f3 wb = sv(Bb + BI, jb);
+  st3(r + RWB, wb);
+  float im = Bb[BIM];
+  float k = dot(jb, wb);
+  if (has_a) {
+    const f3 ja = ld3(r + RJA);
+    const f3 wa = sv(Ba + BI, ja);
+    st3(r + RWA, wa);
+    k += dot(ja, wa);
+    im += Ba[BIM];
+  } else {
+    st3(r + RWA, mk3(0.f, 0.f, 0.f));
+  }
+  return k + im * dot(jl, jl);
+}
+
+// The lane-local copy of the two bodies' velocities used while one lane
+// updates the rows of one constraint.
+struct Vel {
+  float va[3], wa[3], vb[3], wb[3];
+};
+SHD void vel_load(Vel& V, const Env& E, int a, int b) {
+  const float* Bb = E.body(b);
+  for (int k = 0; k < 3; ++k) { V.vb[k] = Bb[BV + k]; V.wb[k] = Bb[BW + k]; }
+  if (a >= 0) {
+    const float* Ba = E.body(a);
+    for (int k = 0; k < 3; ++k) { V.va[k] = Ba[BV + k]; V.wa[k] = Ba[BW + k]; }
+  } else {
+    for (int k = 0; k < 3; ++k) { V.va[k] = 0.f; V.wa[k] = 0.f; }
+  }
+}
+SHD void vel_store(const Vel& V, const Env& E, int a, int b) {
+  float* Bb = E.body(b);
+  for (int k = 0; k < 3; ++k) { Bb[BV + k] = V.vb[k]; Bb[BW + k] = V.wb[k]; }
+  if (a >= 0) {
+    float* Ba = E.body(a);
+    for (int k = 0; k < 3; ++k) { Ba[BV + k] = V.va[k]; Ba[BW + k] = V.wa[k]; }
+  }
+}
+
+// bodies of a candidate constraint
+SHD RowB cand_bodies(const Env& E, int code) {
+  const int k = cand_kind(code), i = cand_idx(code);
+  RowB r;
+  if (k == K_JOINT) { r.a = E.jpar(i); r.b = E.jchi(i); }
+  else if (k == K_GROUND) { r.a = -1; r.b = E.gbody(i); }
+  else { const int pc = E.pcode(i); r.a = pc & 0xFFFF; r.b = pc >> 16; }
+  return r;
+}
+
+// disk projection of the tangent impulse: inside iff |l| <= rho
+SHD void disk(float l1, float l2, float rho, float& o1, float& o2) {
+  const float n = sqrtf(l1 * l1 + l2 * l2);
+  if (n <= rho) { o1 = l1; o2 = l2; }
+  else { const float s = rho / n; o1 = s * l1; o2 = s * l2; }
+}
+
+// ------------------------------------------------------------------ forward phases
+// F1: world inverse inertia R diag(1/I) R^T; torque accumulators cleared.
+template <class Team>
+SHD void f_body_setup(const Team& tm, const Env& E, bool act, bool rec) {
+  const int nb = act ? E.nb : 0;
+  for (int b = tm.tl; b < nb; b += tm.ts) {
+    float* B = E.body(b);
+    const float* R = B + BR;
+    const float d0 = B[BII], d1 = B[BII + 1], d2 = B[BII + 2];
+    // S = R D R^T
+    float S[6];
+    S[0] = R[0] * R[0] * d0 + R[1] * R[1] * d1 + R[2] * R[2] * d2;
+    S[1] = R[3] * R[3] * d0 + R[4] * R[4] * d1 + R[5] * R[5] * d2;
+    S[2] = R[6] * R[6] * d0 + R[7] * R[7] * d1 + R[8] * R[8] * d2;
+    S[3] = R[0] * R[3] * d0 + R[1] * R[4] * d1 + R[2] * R[5] * d2;
+    S[4] = R[0] * R[6] * d0 + R[1] * R[7] * d1 + R[2] * R[8] * d2;
+    S[5] = R[3] * R[6] * d0 + R[4] * R[7] * d1 + R[5] * R[8] * d2;
+    for (int k = 0; k < 6; ++k) B[BI + k] = S[k];
+    B[BTQ] = B[BTQ + 1] = B[BTQ + 2] = 0.f;
+    if (rec) {
+      float* A = E.bodyA(b);
+      A[AW0] = B[BW]; A[AW0 + 1] = B[BW + 1]; A[AW0 + 2] = B[BW + 2];
+    }
+  }
+}
+
+// hinge axis in world coordinates (parent frame rotated, or the world axis)
+SHD f3 joint_axis_w(const Env& E, int j) {
+  const float* C = E.jc(j);
+  const int a = E.jpar(j);
+  const f3 n = ld3(C + JXP);
+  return a >= 0 ? mv(E.body(a) + BR, n) : n;
+}
+
+// F2: motor torque minus viscous damping, equal and opposite on child and
+// parent.  Joints run colour by colour so no two lanes touch one body.
+template <class Team>
+SHD void f_torques(const Team& tm, const Env& E, bool act) {
+  const int ncj = act ? E.nj : 0;
+  // joints occupy the first colours of the canonical order; a joint colour
+  // holds only joints
+  for (int c = 0; tm.any(c < E.ncol && act); ++c) {
+    int lo = 0, hi = 0;
+    if (act && c < E.ncol) {
+      lo = E.colstart(c); hi = E.colstart(c + 1);
+      if (lo >= ncj || cand_kind(E.cand(lo)) != K_JOINT) hi = lo;
+    }
+    for (int i = lo + tm.tl; i < hi; i += tm.ts) {
+      const int j = cand_idx(E.cand(i));
+      const float* C = E.jc(j);
+      const int a = E.jpar(j), b = E.jchi(j);
+      const f3 n = joint_axis_w(E, j);
+      float* Bb = E.body(b);
+      f3 wrel = ld3(Bb + BW);
+      if (a >= 0) wrel = wrel - ld3(E.body(a) + BW);
+      const float tau = C[JU] - C[JD] * dot(wrel, n);
+      add3(Bb + BTQ, tau * n);
+      if (a >= 0) add3(E.body(a) + BTQ, -(tau * n));
+    }
+    tm.sync();
+  }
+}
+
+// F3: v* = v + dt g ; w* = w + dt Iw tq
+template <class Team>
+SHD void f_predict(const Team& tm, const DevModel& M, const Env& E, bool act) {
+  const int nb = act ? E.nb : 0;
+  for (int b = tm.tl; b < nb; b += tm.ts) {
+    float* B = E.body(b);
+    B[BV] += M.dt * M.gx; B[BV + 1] += M.dt * M.gy; B[BV + 2] += M.dt * M.gz;
+    const f3 dw = sv(B + BI, ld3(B + BTQ));
+    B[BW] += M.dt * dw.x; B[BW + 1] += M.dt * dw.y; B[BW + 2] += M.dt * dw.z;
+  }
+}
+
+// Build the rows of one joint into slots s..s+4.
+SHD void build_joint(const DevModel& M, const Env& E, int j, int s) {
+  const float* C = E.jc(j);
+  const int a = E.jpar(j), b = E.jchi(j);
+  const float* Bb = E.body(b);
+  const float* Ba = a >= 0 ? E.body(a) : nullptr;
+  const f3 rb = mv(Bb + BR, ld3(C + JAC));
+  f3 ra = mk3(0.f, 0.f, 0.f), Pa = ld3(C + JAP);
+  if (a >= 0) { ra = mv(Ba + BR, Pa); Pa = ld3(Ba + BP) + ra; }
+  const f3 err = (ld3(Bb + BP) + rb) - Pa;
+  const float kb = M.beta / M.dt;
+  const float ev[3] = {err.x, err.y, err.z};
+  for (int q = 0; q < 3; ++q) {
+    float* r = E.row(s + q);
+    const f3 e = mk3(q == 0 ? 1.f : 0.f, q == 1 ? 1.f : 0.f, q == 2 ? 1.f : 0.f);
+    st3(r + RJL, e);
+    st3(r + RJA, cross(e, ra));
+    st3(r + RJB, cross(rb, e));
+    r[RBI] = kb * ev[q];
+  }
+  f3 na = ld3(C + JXP), ua = ld3(C + JUP);
+  f3 t2 = cross(na, ua);
+  if (a >= 0) { na = mv(Ba + BR, na); ua = mv(Ba + BR, ua); t2 = mv(Ba + BR, t2); }
+  const f3 nbw = mv(Bb + BR, ld3(C + JXC));
+  const f3 ax = cross(na, nbw);
+  for (int q = 0; q < 2; ++q) {
+    float* r = E.row(s + 3 + q);
+    const f3 tk = q == 0 ? ua : t2;
+    st3(r + RJL, mk3(0.f, 0.f, 0.f));
+    st3(r + RJA, -tk);
+    st3(r + RJB, tk);
+    r[RBI] = kb * dot(tk, ax);
+  }
+  const int st = 5 * j;
+  for (int q = 0; q < 5; ++q) {
+    float* r = E.row(s + q);
+    const float K = row_finish(r, Ba, Bb, a >= 0);
+    r[RM] = 1.f / (K + M.gamma);
+    const float l0 = M.warm * E.ws()[st + q];
+    r[RL] = l0;
+    r[RL0] = l0;
+  }
+}
+
+// Gap and geometry of a contact candidate; returns the gap.
+struct CGeo {
+  f3 n, ra, rb;   // normal, lever arms (contact point minus body centre)
+  f3 ca, cb;      // sphere centres (pair), or cb for ground
+  float L, gap;
+};
+SHD CGeo contact_geo(const Env& E, int code) {
+  CGeo g;
+  const int k = cand_kind(code), i = cand_idx(code);
+  if (k == K_GROUND) {
+    const int b = E.gbody(i);
+    const float* Bb = E.body(b);
+    const float* S = E.gsph(i);
+    g.cb = ld3(Bb + BP) + mv(Bb + BR, ld3(S));
+    g.gap = g.cb.z - S[3];
+    g.n = mk3(0.f, 0.f, 1.f);
+    g.rb = (g.cb - S[3] * g.n) - ld3(Bb + BP);
+    g.ra = mk3(0.f, 0.f, 0.f);
+    g.ca = g.ra;
+    g.L = 0.f;
+  } else {
+    const int pc = E.pcode(i), a = pc & 0xFFFF, b = pc >> 16;
+    const float* Ba = E.body(a);
+    const float* Bb = E.body(b);
+    g.ca = ld3(Ba + BP) + mv(Ba + BR, ld3(Ba + BPO));
+    g.cb = ld3(Bb + BP) + mv(Bb + BR, ld3(Bb + BPO));
+    const f3 d = g.cb - g.ca;
+    g.L = sqrtf(dot(d, d));
+    g.gap = g.L - Ba[BPR] - Bb[BPR];
+    g.n = g.L < 1e-9f ? mk3(0.f, 0.f, 1.f) : (1.f / g.L) * d;
+    g.ra = (g.ca + Ba[BPR] * g.n) - ld3(Ba + BP);
+    g.rb = (g.cb - Bb[BPR] * g.n) - ld3(Bb + BP);
+  }
+  return g;
+}
+SHD void tangents(f3 n, bool ground, f3& t1, f3& t2) {
+  if (ground) { t1 = mk3(1.f, 0.f, 0.f); t2 = mk3(0.f, 1.f, 0.f); return; }
+  const f3 w = fabsf(n.z) < 0.9f ? cross(n, mk3(0.f, 0.f, 1.f)) : cross(n, mk3(1.f, 0.f, 0.f));
+  t1 = (1.f / sqrtf(dot(w, w))) * w;
+  t2 = cross(n, t1);
+}
+
+// Build an active contact into slots s..s+3.
+SHD void build_contact(const DevModel& M, const Env& E, int code, int s, const CGeo& g) {
+  const RowB rb = cand_bodies(E, code);
+  const bool ground = cand_kind(code) == K_GROUND;
+  const float* Bb = E.body(rb.b);
+  const float* Ba = rb.a >= 0 ? E.body(rb.a) : nullptr;
+  f3 t1, t2;
+  tangents(g.n, ground, t1, t2);
+  const f3 dirs[3] = {g.n, t1, t2};
+  float K[3];
+  for (int q = 0; q < 3; ++q) {
+    float* r = E.row(s + q);
+    st3(r + RJL, dirs[q]);
+    st3(r + RJA, ground ? mk3(0.f, 0.f, 0.f) : cross(dirs[q], g.ra));
+    st3(r + RJB, cross(g.rb, dirs[q]));
+    K[q] = row_finish(r, Ba, Bb, !ground);
+  }
+  float* x = E.row(s + 3);
+  st3(x + XT1, t1);
+  st3(x + XT2, t2);
+  x[XMT] = 2.f / (K[1] + K[2]);
+  x[XGAP] = g.gap;
+  const int st = E.store_of(code);
+  ((int*)x)[XSTORE] = st;
+  ((int*)x)[XCODE] = code;
+  float* rn = E.row(s);
+  rn[RM] = 1.f / (K[0] + M.gamma);
+  rn[RBI] = (g.gap > 0.f ? g.gap : M.beta * g.gap) / M.dt;
+  const float* w = E.ws() + st;
+  const f3 Lt = mk3(w[1], w[2], w[3]);
+  rn[RL] = rn[RL0] = M.warm * w[0];
+  E.row(s + 1)[RL] = E.row(s + 1)[RL0] = M.warm * dot(t1, Lt);
+  E.row(s + 2)[RL] = E.row(s + 2)[RL0] = M.warm * dot(t2, Lt);
+  E.row(s + 1)[RM] = x[XMT];
+  E.row(s + 2)[RM] = x[XMT];
+  E.row(s + 1)[RBI] = 0.f;
+  E.row(s + 2)[RBI] = 0.f;
+}
+
+// F4: per colour, test candidates, compact the active ones, build rows.
+// Inactive contact candidates have their stored impulses cleared.  A colour
+// holds only joints or only contacts.
+template <class Team>
+SHD void f_rows(const Team& tm, const DevModel& M, const Env& E, bool act) {
+  int ncon = 0;  // contacts placed so far (team-uniform)
+  for (int c = 0; tm.any(c < E.ncol && act); ++c) {
+    int lo = 0, hi = 0;
+    if (act && c < E.ncol) { lo = E.colstart(c); hi = E.colstart(c + 1); }
+    const bool jcol = hi > lo && cand_kind(E.cand(lo)) == K_JOINT;
+    int cnt = 0;
+    for (int base = lo; tm.any(base < hi); base += tm.ts) {
+      const int i = base + tm.tl;
+      const bool live = i < hi;
+      const int code = live ? E.cand(i) : 0;
+      bool on = false;
+      CGeo g;
+      if (live) {
+        if (jcol) on = true;
+        else {
+          g = contact_geo(E, code);
+          on = g.gap < M.spec;
+          if (!on) {
+            float* w = E.ws() + E.store_of(code);
+            w[0] = w[1] = w[2] = w[3] = 0.f;
+          }
+        }
+      }
+      int total = 0;
+      const int pos = tm.prefix(on, total);
+      if (on) {
+        const int li = lo + cnt + pos;   // position in the colour's active list
+        E.act_code()[li] = code;
+        if (jcol) {
+          const int j = cand_idx(code);
+          E.act_slot()[li] = 5 * j;
+          build_joint(M, E, j, 5 * j);
+        } else if (ncon + pos < E.ccap) {
+          const int s = 5 * E.nj + 4 * (ncon + pos);
+          E.act_slot()[li] = s;
+          build_contact(M, E, code, s, g);
+        } else {
+          // beyond the env's contact capacity: dropped, env flagged
+          E.act_slot()[li] = -1;
+          float* w = E.ws() + E.store_of(code);
+          w[0] = w[1] = w[2] = w[3] = 0.f;
+          ((int*)E.misc())[MISC_FLAGS] |= 2;
+        }
+      }
+      cnt += total;
+      if (!jcol) ncon += total;
+    }
+    if (act && c < E.ncol) E.act_cnt()[c] = cnt;
+  }
+  tm.sync();
+}
+
+// F5: warm start, v += W lambda0 for every row, colour by colour.
+template <class Team>
+SHD void f_warm(const Team& tm, const Env& E, bool act) {
+  for (int c = 0; tm.any(c < E.ncol && act); ++c) {
+    const int n = (act && c < E.ncol) ? E.act_cnt()[c] : 0;
+    const int lo = (act && c < E.ncol) ? E.colstart(c) : 0;
+    for (int k = tm.tl; k < n; k += tm.ts) {
+      const int s = E.act_slot()[lo + k];
+      if (s < 0) continue;
+      const int code = E.act_code()[lo + k];
+      const RowB rb = cand_bodies(E, code);
+      const int nr = cand_kind(code) == K_JOINT ? 5 : 3;
+      Vel V;
+      vel_load(V, E, rb.a, rb.b);
+      const float ima = rb.a >= 0 ? E.body(rb.a)[BIM] : 0.f, imb = E.body(rb.b)[BIM];
+      for (int q = 0; q < nr; ++q) {
+        const float* r = E.row(s + q);
+        row_apply(r, V.va, V.wa, V.vb, V.wb, rb.a >= 0, ima, imb, r[RL0]);
+      }
+      vel_store(V, E, rb.a, rb.b);
+    }
+    tm.sync();
+  }
+}
+
+// F6: projected Gauss-Seidel sweeps.  With rec, the pre-projection impulse of
+// every row update is recorded per iteration.
+template <class Team>
+SHD void f_pgs(const Team& tm, const DevModel& M, const Env& E, bool act, bool rec) {
+  const float mu = E.misc()[MISC_MU];
+  for (int it = 0; it < M.n_iters; ++it) {
+    float* H = rec ? E.hist(it) : nullptr;
+    for (int c = 0; tm.any(c < E.ncol && act); ++c) {
+      const int n = (act && c < E.ncol) ? E.act_cnt()[c] : 0;
+      const int lo = (act && c < E.ncol) ? E.colstart(c) : 0;
+      for (int k = tm.tl; k < n; k += tm.ts) {
+        const int s = E.act_slot()[lo + k];
+        if (s < 0) continue;
+        const int code = E.act_code()[lo + k];
+        const RowB rb = cand_bodies(E, code);
+        const bool ha = rb.a >= 0;
+        const bool joint = cand_kind(code) == K_JOINT;
+        Vel V;
+        vel_load(V, E, rb.a, rb.b);
+        const float ima = ha ? E.body(rb.a)[BIM] : 0.f, imb = E.body(rb.b)[BIM];
+        const int nsc = joint ? 5 : 1;
+        for (int q = 0; q < nsc; ++q) {
+          float* r = E.row(s + q);
+          const float sv_ = row_jv(r, V.va, V.wa, V.vb, V.wb, ha) + r[RBI] + M.gamma * r[RL];
+          const float lt = r[RL] - r[RM] * sv_;
+          float ln = lt;
+          if (!joint && lt <= 0.f) ln = 0.f;
+          if (rec) H[s + q] = lt;
+          row_apply(r, V.va, V.wa, V.vb, V.wb, ha, ima, imb, ln - r[RL]);
+          r[RL] = ln;
+        }
+        if (!joint) {
+          float* r1 = E.row(s + 1);
+          float* r2 = E.row(s + 2);
+          const float mt = E.row(s + 3)[XMT];
+          const float l1 = r1[RL] - mt * row_jv(r1, V.va, V.wa, V.vb, V.wb, ha);
+          const float l2 = r2[RL] - mt * row_jv(r2, V.va, V.wa, V.vb, V.wb, ha);
+          float n1, n2;
+          disk(l1, l2, mu * E.row(s)[RL], n1, n2);
+          if (rec) { H[s + 1] = l1; H[s + 2] = l2; }
+          row_apply(r1, V.va, V.wa, V.vb, V.wb, ha, ima, imb, n1 - r1[RL]);
+          row_apply(r2, V.va, V.wa, V.vb, V.wb, ha, ima, imb, n2 - r2[RL]);
+          r1[RL] = n1;
+          r2[RL] = n2;
+        }
+        vel_store(V, E, rb.a, rb.b);
+      }
+      tm.sync();
+    }
+  }
+}
+
+// F7: semi-implicit Euler and renormalisation of R.
+template <class Team>
+SHD void f_integrate(const Team& tm, const DevModel& M, const Env& E, bool act) {
+  const int nb = act ? E.nb : 0;
+  for (int b = tm.tl; b < nb; b += tm.ts) {
+    float* B = E.body(b);
+    for (int k = 0; k < 3; ++k) B[BP + k] += M.dt * B[BV + k];
+    const float* R = B + BR;
+    const float h = M.dt, w0 = B[BW], w1 = B[BW + 1], w2 = B[BW + 2];
+    // A = R + dt [w]x R
+    float A[9];
+    for (int j = 0; j < 3; ++j) {
+      const float r0 = R[j], r1 = R[3 + j], r2 = R[6 + j];
+      A[j] = r0 + h * (-w2 * r1 + w1 * r2);
+      A[3 + j] = r1 + h * (w2 * r0 - w0 * r2);
+      A[6 + j] = r2 + h * (-w1 * r0 + w0 * r1);
+    }
+    // G = A^T A ; N = (3A - A G)/2
+    float G[9];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) G[3 * i + j] = A[i] * A[j] + A[3 + i] * A[3 + j] + A[6 + i] * A[6 + j];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) {
+        const float ag = A[3 * i] * G[j] + A[3 * i + 1] * G[3 + j] + A[3 * i + 2] * G[6 + j];
+        B[BR + 3 * i + j] = 0.5f * (3.f * A[3 * i + j] - ag);
+      }
+  }
+}
+
+// F8: store impulses for the next warm start.
+template <class Team>
+SHD void f_store(const Team& tm, const Env& E, bool act) {
+  for (int c = 0; tm.any(c < E.ncol && act); ++c) {
+    const int n = (act && c < E.ncol) ? E.act_cnt()[c] : 0;
+    const int lo = (act && c < E.ncol) ? E.colstart(c) : 0;
+    for (int k = tm.tl; k < n; k += tm.ts) {
+      const int s = E.act_slot()[lo + k];
+      if (s < 0) continue;
+      const int code = E.act_code()[lo + k];
+      float* w = E.ws() + E.store_of(code);
+      if (cand_kind(code) == K_JOINT) {
+        for (int q = 0; q < 5; ++q) w[q] = E.row(s + q)[RL];
+      } else {
+        const float* x = E.row(s + 3);
+        const float l1 = E.row(s + 1)[RL], l2 = E.row(s + 2)[RL];
+        w[0] = E.row(s)[RL];
+        const f3 Lt = l1 * ld3(x + XT1) + l2 * ld3(x + XT2);
+        w[1] = Lt.x; w[2] = Lt.y; w[3] = Lt.z;
+      }
+    }
+  }
+  tm.sync();
+}
+
+// Controls of this step into the joint records (tape row t).
+template <class Team>
+SHD void f_controls(const Team& tm, const DevModel& M, const Env& E, const float* u_row, bool act) {
+  const int nj = act ? E.nj : 0;
+  for (int j = tm.tl; j < nj; j += tm.ts) E.jc(j)[JU] = u_row ? u_row[E.j0 + j] : 0.f;
+}
+
+// Loss term of the state after step t (1-based) for the loss body.
+SHD float loss_term(const DevModel& M, const Env& E, int t1, const float* p, const float* p0) {
+  const float* tg = M.target + 3 * E.e;
+  if (M.loss_kind == 0) {
+    if (t1 != E.T) return 0.f;
+    float L = 0.f;
+    for (int k = 0; k < 3; ++k)
+      if (M.loss_mask & (1 << k)) { const float d = p[k] - tg[k]; L += d * d; }
+    return L;
+  }
+  if (M.loss_kind == 1) {
+    float q = 0.f;
+    for (int k = 0; k < 3; ++k)
+      if (M.loss_mask & (1 << k)) { const float d = p[k] - tg[k]; q += d * d; }
+    return q > 0.f ? sqrtf(q) / (float)E.T : 0.f;
+  }
+  if (t1 != E.T) return 0.f;
+  return -(p[0] - p0[0]) / ((float)E.T * M.dt);
+}
+
+// One full forward step (no recording): x^t (LDS) -> x^{t+1} (LDS).
+template <class Team>
+SHD void env_step(const Team& tm, const DevModel& M, const Env& E, const float* u_row, bool act) {
+  f_controls(tm, M, E, u_row, act);
+  f_body_setup(tm, E, act, false);
+  tm.sync();
+  f_torques(tm, E, act);
+  f_predict(tm, M, E, act);
+  tm.sync();
+  f_rows(tm, M, E, act);
+  f_warm(tm, E, act);
+  f_pgs(tm, M, E, act, false);
+  f_integrate(tm, M, E, act);
+  f_store(tm, E, act);
+}
+
+// ------------------------------------------------------------------ adjoint
+// Adjoint of the linear part of W = M^-1 J^T folded at accumulation time:
+// W_lin_a = -invm_a Jl, W_lin_b = invm_b Jl.
+struct VelA {
+  float va[3], wa[3], vb[3], wb[3];
+};
+SHD void vela_load(VelA& V, const Env& E, int a, int b) {
+  const float* Bb = E.bodyA(b);
+  for (int k = 0; k < 3; ++k) { V.vb[k] = Bb[AV + k]; V.wb[k] = Bb[AW + k]; }
+  if (a >= 0) {
+    const float* Ba = E.bodyA(a);
+    for (int k = 0; k < 3; ++k) { V.va[k] = Ba[AV + k]; V.wa[k] = Ba[AW + k]; }
+  } else {
+    for (int k = 0; k < 3; ++k) { V.va[k] = 0.f; V.wa[k] = 0.f; }
+  }
+}
+SHD void vela_store(const VelA& V, const Env& E, int a, int b) {
+  float* Bb = E.bodyA(b);
+  for (int k = 0; k < 3; ++k) { Bb[AV + k] = V.vb[k]; Bb[AW + k] = V.wb[k]; }
+  if (a >= 0) {
+    float* Ba = E.bodyA(a);
+    for (int k = 0; k < 3; ++k) { Ba[AV + k] = V.va[k]; Ba[AW + k] = V.wa[k]; }
+  }
+}
+// W . vbar (the adjoint seen through v += W d)
+SHD float row_wvbar(const float* r, const VelA& A, bool ha, float ima, float imb) {
+  float s = imb * (r[RJL] * A.vb[0] + r[RJL + 1] * A.vb[1] + r[RJL + 2] * A.vb[2]);
+  s += r[RWB] * A.wb[0] + r[RWB + 1] * A.wb[1] + r[RWB + 2] * A.wb[2];
+  if (ha) {
+    s -= ima * (r[RJL] * A.va[0] + r[RJL + 1] * A.va[1] + r[RJL + 2] * A.va[2]);
+    s += r[RWA] * A.wa[0] + r[RWA + 1] * A.wa[1] + r[RWA + 2] * A.wa[2];
+  }
+  return s;
+}
+// accumulate the adjoint of W from v += W d (given vbar after the update)
+SHD void row_wbar(float* q, const float* r, const VelA& A, bool ha, float ima, float imb, float d,
+                  float* imbar_a, float* imbar_b) {
+  // angular parts
+  q[QWB] += A.wb[0] * d; q[QWB + 1] += A.wb[1] * d; q[QWB + 2] += A.wb[2] * d;
+  // linear parts: W_lin_b = imb Jl
+  q[QJL] += imb * A.vb[0] * d; q[QJL + 1] += imb * A.vb[1] * d; q[QJL + 2] += imb * A.vb[2] * d;
+  *imbar_b += d * (r[RJL] * A.vb[0] + r[RJL + 1] * A.vb[1] + r[RJL + 2] * A.vb[2]);
+  if (ha) {
+    q[QWA] += A.wa[0] * d; q[QWA + 1] += A.wa[1] * d; q[QWA + 2] += A.wa[2] * d;
+    q[QJL] -= ima * A.va[0] * d; q[QJL + 1] -= ima * A.va[1] * d; q[QJL + 2] -= ima * A.va[2] * d;
+    *imbar_a -= d * (r[RJL] * A.va[0] + r[RJL + 1] * A.va[1] + r[RJL + 2] * A.va[2]);
+  }
+}
+// vbar += J^T sb ; Jbar += sb v
+SHD void row_jbar(float* q, const float* r, VelA& A, const Vel& V, bool ha, float sb) {
+  for (int k = 0; k < 3; ++k) {
+    A.vb[k] += r[RJL + k] * sb;
+    A.wb[k] += r[RJB + k] * sb;
+    q[QJL + k] += sb * V.vb[k];
+    q[QJB + k] += sb * V.wb[k];
+    if (ha) {
+      A.va[k] -= r[RJL + k] * sb;
+      A.wa[k] += r[RJA + k] * sb;
+      q[QJL + k] -= sb * V.va[k];
+      q[QJA + k] += sb * V.wa[k];
+    }
+  }
+}
+// undo v += W d
+SHD void row_unapply(const float* r, Vel& V, bool ha, float ima, float imb, float d) {
+  row_apply(r, V.va, V.wa, V.vb, V.wb, ha, ima, imb, -d);
+}
+
+// Clear the per-step adjoint accumulators (rows, body extras).
+template <class Team>
+SHD void a_clear_step(const Team& tm, const Env& E, bool act) {
+  const int ns = act ? E.nslot * RSA : 0;
+  for (int i = tm.tl; i < ns; i += tm.ts) E.L[E.lay.rowsA + i] = 0.f;
+  const int nb = act ? E.nb : 0;
+  for (int b = tm.tl; b < nb; b += tm.ts) {
+    float* A = E.bodyA(b);
+    for (int k = 0; k < 9; ++k) A[AIW + k] = 0.f;
+    A[ATQ] = A[ATQ + 1] = A[ATQ + 2] = 0.f;
+  }
+}
+
+// B8: adjoint of the impulse store; lambda bar of each active row starts from
+// the stored output's adjoint.  Inactive candidates' stored outputs were
+// constants (zeros): their adjoint is dropped here.
+template <class Team>
+SHD void a_store(const Team& tm, const Env& E, bool act) {
+  for (int c = 0; tm.any(c < E.ncol && act); ++c) {
+    const int n = (act && c < E.ncol) ? E.act_cnt()[c] : 0;
+    const int lo = (act && c < E.ncol) ? E.colstart(c) : 0;
+    for (int k = tm.tl; k < n; k += tm.ts) {
+      const int s = E.act_slot()[lo + k];
+      if (s < 0) continue;
+      const int code = E.act_code()[lo + k];
+      float* wA = E.wsA() + E.store_of(code);
+      if (cand_kind(code) == K_JOINT) {
+        for (int q = 0; q < 5; ++q) E.rowA(s + q)[QL] = wA[q];
+      } else {
+        const float* x = E.row(s + 3);
+        float* xa = E.rowA(s + 3);
+        const f3 Lb = mk3(wA[1], wA[2], wA[3]);
+        const f3 t1 = ld3(x + XT1), t2 = ld3(x + XT2);
+        const float l1 = E.row(s + 1)[RL], l2 = E.row(s + 2)[RL];
+        E.rowA(s)[QL] = wA[0];
+        E.rowA(s + 1)[QL] = dot(t1, Lb);
+        E.rowA(s + 2)[QL] = dot(t2, Lb);
+        add3(xa + XT1, l1 * Lb);
+        add3(xa + XT2, l2 * Lb);
+      }
+    }
+  }
+  tm.sync();
+  // the adjoint of the incoming store is rebuilt by the warm-start reverse
+  const int nl = act ? E.lam_size : 0;
+  for (int i = tm.tl; i < nl; i += tm.ts) E.wsA()[i] = 0.f;
+  tm.sync();
+}
+
+// B7: adjoint of integration and renormalisation (per body); leaves
+// vbar, wbar of the post-sweep velocities and pbar, Rbar of x^t.
+template <class Team>
+SHD void a_integrate(const Team& tm, const DevModel& M, const Env& E, bool act) {
+  const int nb = act ? E.nb : 0;
+  for (int b = tm.tl; b < nb; b += tm.ts) {
+    float* B = E.body(b);
+    float* A = E.bodyA(b);
+    const float h = M.dt;
+    for (int k = 0; k < 3; ++k) A[AV + k] += h * A[AP + k];   // p' = p + h v'
+    const float* R = B + BR;
+    const float w0 = B[BW], w1 = B[BW + 1], w2 = B[BW + 2];
+    float Am[9];
+    for (int j = 0; j < 3; ++j) {
+      const float r0 = R[j], r1 = R[3 + j], r2 = R[6 + j];
+      Am[j] = r0 + h * (-w2 * r1 + w1 * r2);
+      Am[3 + j] = r1 + h * (w2 * r0 - w0 * r2);
+      Am[6 + j] = r2 + h * (-w1 * r0 + w0 * r1);
+    }
+    float Nb[9];
+    for (int k = 0; k < 9; ++k) Nb[k] = A[AR + k];
+    // Abar = 1.5 Nb - 0.5 (Nb A^T A + A Nb^T A + A A^T Nb)
+    float AtA[9], AAt[9], NtA[9];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) {
+        AtA[3 * i + j] = Am[i] * Am[j] + Am[3 + i] * Am[3 + j] + Am[6 + i] * Am[6 + j];
+        AAt[3 * i + j] = Am[3 * i] * Am[3 * j] + Am[3 * i + 1] * Am[3 * j + 1] + Am[3 * i + 2] * Am[3 * j + 2];
+        NtA[3 * i + j] = Nb[i] * Am[j] + Nb[3 + i] * Am[3 + j] + Nb[6 + i] * Am[6 + j];   // Nb^T A
+      }
+    float Ab[9];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) {
+        float t1 = 0.f, t2 = 0.f, t3 = 0.f;
+        for (int k = 0; k < 3; ++k) {
+          t1 += Nb[3 * i + k] * AtA[3 * k + j];
+          t2 += Am[3 * i + k] * NtA[3 * k + j];
+          t3 += AAt[3 * i + k] * Nb[3 * k + j];
+        }
+        Ab[3 * i + j] = 1.5f * Nb[3 * i + j] - 0.5f * (t1 + t2 + t3);
+      }
+    // A = R + h S(w) R : Rbar = Abar - h S(w) Abar ; wbar += h * d<Abar, S R>/dw
+    float Mx[9];   // Abar R^T
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) Mx[3 * i + j] = Ab[3 * i] * R[3 * j] + Ab[3 * i + 1] * R[3 * j + 1] + Ab[3 * i + 2] * R[3 * j + 2];
+    A[AW] += h * (Mx[7] - Mx[5]);
+    A[AW + 1] += h * (Mx[2] - Mx[6]);
+    A[AW + 2] += h * (Mx[3] - Mx[1]);
+    for (int j = 0; j < 3; ++j) {
+      const float a0 = Ab[j], a1 = Ab[3 + j], a2 = Ab[6 + j];
+      A[AR + j] = a0 - h * (-w2 * a1 + w1 * a2);
+      A[AR + 3 + j] = a1 - h * (w2 * a0 - w0 * a2);
+      A[AR + 6 + j] = a2 - h * (-w1 * a0 + w0 * a1);
+    }
+  }
+  tm.sync();
+}
+
+// B6: adjoint of the sweeps.
+template <class Team>
+SHD void a_pgs(const Team& tm, const DevModel& M, const Env& E, bool act) {
+  const float mu = E.misc()[MISC_MU];
+  float gmu = 0.f;
+  for (int it = M.n_iters - 1; it >= 0; --it) {
+    const float* H = E.hist(it);
+    const float* Hp = it > 0 ? E.hist(it - 1) : nullptr;
+    for (int c = E.ncol - 1; tm.any(c >= 0 && act); --c) {
+      const int n = (act && c >= 0) ? E.act_cnt()[c] : 0;
+      const int lo = (act && c >= 0) ? E.colstart(c) : 0;
+      for (int k = tm.tl; k < n; k += tm.ts) {
+        const int s = E.act_slot()[lo + k];
+        if (s < 0) continue;
+        const int code = E.act_code()[lo + k];
+        const RowB rb = cand_bodies(E, code);
+        const bool ha = rb.a >= 0;
+        const bool joint = cand_kind(code) == K_JOINT;
+        Vel V;
+        vel_load(V, E, rb.a, rb.b);
+        VelA A;
+        vela_load(A, E, rb.a, rb.b);
+        float imA = 0.f, imB = 0.f;
+        const float ima = ha ? E.body(rb.a)[BIM] : 0.f, imb = E.body(rb.b)[BIM];
+        // impulses after this iteration's update (proj of H) and before (proj of Hp or init)
+        if (!joint) {
+          // friction block (last in forward, first here)
+          const float* r1 = E.row(s + 1);
+          const float* r2 = E.row(s + 2);
+          float* q1 = E.rowA(s + 1);
+          float* q2 = E.rowA(s + 2);
+          const float mt = E.row(s + 3)[XMT];
+          const float ln = fmaxf(H[s], 0.f);
+          const float rho = mu * ln;
+          const float l1t = H[s + 1], l2t = H[s + 2];
+          float n1, n2;
+          disk(l1t, l2t, rho, n1, n2);
+          float p1, p2;
+          if (Hp) {
+            const float rhop = mu * fmaxf(Hp[s], 0.f);
+            disk(Hp[s + 1], Hp[s + 2], rhop, p1, p2);
+          } else {
+            p1 = r1[RL0]; p2 = r2[RL0];
+          }
+          const float d1 = n1 - p1, d2 = n2 - p2;
+          // reconstruct v before the block
+          row_unapply(r2, V, ha, ima, imb, d2);
+          row_unapply(r1, V, ha, ima, imb, d1);
+          // W bar and g = lambda'bar + W.vbar
+          row_wbar(q1, r1, A, ha, ima, imb, d1, &imA, &imB);
+          row_wbar(q2, r2, A, ha, ima, imb, d2, &imA, &imB);
+          const float wv1 = row_wvbar(r1, A, ha, ima, imb);
+          const float wv2 = row_wvbar(r2, A, ha, ima, imb);
+          const float g1 = q1[QL] + wv1, g2 = q2[QL] + wv2;
+          float lb1 = -wv1, lb2 = -wv2;
+          const float nrm = sqrtf(l1t * l1t + l2t * l2t);
+          float tb1, tb2;
+          if (nrm <= rho) { tb1 = g1; tb2 = g2; }
+          else {
+            const float u1 = l1t / nrm, u2 = l2t / nrm, sc = rho / nrm;
+            const float ug = u1 * g1 + u2 * g2;
+            tb1 = sc * (g1 - u1 * ug);
+            tb2 = sc * (g2 - u2 * ug);
+            const float rhob = ug;
+            gmu += rhob * ln;
+            E.rowA(s)[QL] += rhob * mu;   // adjoint of the normal impulse of this iteration
+          }
+          lb1 += tb1; lb2 += tb2;
+          // lt = l - mt (J v)
+          const float jv1 = row_jv(r1, V.va, V.wa, V.vb, V.wb, ha);
+          const float jv2 = row_jv(r2, V.va, V.wa, V.vb, V.wb, ha);
+          E.rowA(s + 3)[XMT] += -(tb1 * jv1 + tb2 * jv2);
+          row_jbar(q1, r1, A, V, ha, -mt * tb1);
+          row_jbar(q2, r2, A, V, ha, -mt * tb2);
+          q1[QL] = lb1;
+          q2[QL] = lb2;
+        }
+        const int nsc = joint ? 5 : 1;
+        for (int q = nsc - 1; q >= 0; --q) {
+          const float* r = E.row(s + q);
+          float* qa = E.rowA(s + q);
+          const float lt = H[s + q];
+          const float ln = joint ? lt : fmaxf(lt, 0.f);
+          float lp;
+          if (Hp) lp = joint ? Hp[s + q] : fmaxf(Hp[s + q], 0.f);
+          else lp = r[RL0];
+          const float d = ln - lp;
+          row_unapply(r, V, ha, ima, imb, d);
+          row_wbar(qa, r, A, ha, ima, imb, d, &imA, &imB);
+          const float wv = row_wvbar(r, A, ha, ima, imb);
+          const float g = qa[QL] + wv;
+          const bool free_ = joint || lt > 0.f;
+          const float ltb = free_ ? g : 0.f;
+          const float sb = -r[RM] * ltb;
+          // s = J v + bias + gamma lp
+          const float sval = row_jv(r, V.va, V.wa, V.vb, V.wb, ha) + r[RBI] + M.gamma * lp;
+          qa[QM] += -sval * ltb;
+          qa[QB] += sb;
+          row_jbar(qa, r, A, V, ha, sb);
+          qa[QL] = -wv + ltb + M.gamma * sb;
+        }
+        vel_store(V, E, rb.a, rb.b);
+        vela_store(A, E, rb.a, rb.b);
+        if (ha) E.bodyA(rb.a)[AIM] += imA;
+        E.bodyA(rb.b)[AIM] += imB;
+      }
+      tm.sync();
+    }
+  }
+  // friction coefficient adjoint (one lane per team holds it after a reduction)
+  float tot = tm.team_sum(gmu);
+  if (tm.tl == 0 && act) E.misc()[MISC_GMU] += tot;
+  tm.sync();
+}
+
+// B5: adjoint of the warm start v += W lambda0 and of lambda0 = warm * store.
+template <class Team>
+SHD void a_warm(const Team& tm, const DevModel& M, const Env& E, bool act) {
+  for (int c = E.ncol - 1; tm.any(c >= 0 && act); --c) {
+    const int n = (act && c >= 0) ? E.act_cnt()[c] : 0;
+    const int lo = (act && c >= 0) ? E.colstart(c) : 0;
+    for (int k = tm.tl; k < n; k += tm.ts) {
+      const int s = E.act_slot()[lo + k];
+      if (s < 0) continue;
+      const int code = E.act_code()[lo + k];
+      const RowB rb = cand_bodies(E, code);
+      const bool ha = rb.a >= 0;
+      const int nr = cand_kind(code) == K_JOINT ? 5 : 3;
+      VelA A;
+      vela_load(A, E, rb.a, rb.b);
+      float imA = 0.f, imB = 0.f;
+      const float ima = ha ? E.body(rb.a)[BIM] : 0.f, imb = E.body(rb.b)[BIM];
+      float l0b[5];
+      for (int q = 0; q < nr; ++q) {
+        const float* r = E.row(s + q);
+        float* qa = E.rowA(s + q);
+        row_wbar(qa, r, A, ha, ima, imb, r[RL0], &imA, &imB);
+        l0b[q] = qa[QL] + row_wvbar(r, A, ha, ima, imb);
+      }
+      float* wA = E.wsA() + E.store_of(code);
+      if (nr == 5) {
+        for (int q = 0; q < 5; ++q) wA[q] += M.warm * l0b[q];
+      } else {
+        const float* x = E.row(s + 3);
+        float* xa = E.rowA(s + 3);
+        const float* w = E.ws() + E.store_of(code);
+        const f3 Lt = mk3(w[1], w[2], w[3]);
+        const f3 t1 = ld3(x + XT1), t2 = ld3(x + XT2);
+        wA[0] += M.warm * l0b[0];
+        const f3 Lb = (M.warm * l0b[1]) * t1 + (M.warm * l0b[2]) * t2;
+        wA[1] += Lb.x; wA[2] += Lb.y; wA[3] += Lb.z;
+        add3(xa + XT1, (M.warm * l0b[1]) * Lt);
+        add3(xa + XT2, (M.warm * l0b[2]) * Lt);
+      }
+      if (ha) E.bodyA(rb.a)[AIM] += imA;
+      E.bodyA(rb.b)[AIM] += imB;
+    }
+    tm.sync();
+  }
+}
+
+// Adjoint of row_finish: K = im |Jl|^2 + Ja^T Iw_a Ja + Jb^T Iw_b Jb, W = Iw J.
+// Kb is the adjoint of K; adds into Jbar and body Iw-bar / invm-bar.
+SHD void a_row_finish(const Env& E, const float* r, float* q, int a, int b, float Kb) {
+  const bool ha = a >= 0;
+  float* Ab = E.bodyA(b);
+  const float* Bb = E.body(b);
+  const f3 jl = ld3(r + RJL), jb = ld3(r + RJB);
+  float im = Bb[BIM];
+  const float jl2 = dot(jl, jl);
+  Ab[AIM] += Kb * jl2;
+  // Jb: W = Iw Jb, K += Jb.W  ->  Jbbar += Iw (Wbar + 2 Kb Jb); Iwbar += (Wbar + Kb Jb) Jb^T
+  {
+    const f3 wbb = ld3(q + QWB);
+    const f3 tmp = wbb + (2.f * Kb) * jb;
+    add3(q + QJB, sv(Bb + BI, tmp));
+    add_outer(Ab + AIW, wbb + Kb * jb, jb);
+  }
+  if (ha) {
+    float* Aa = E.bodyA(a);
+    const float* Ba = E.body(a);
+    const f3 ja = ld3(r + RJA);
+    im += Ba[BIM];
+    Aa[AIM] += Kb * jl2;
+    const f3 wab = ld3(q + QWA);
+    const f3 tmp = wab + (2.f * Kb) * ja;
+    add3(q + QJA, sv(Ba + BI, tmp));
+    add_outer(Aa + AIW, wab + Kb * ja, ja);
+  }
+  add3(q + QJL, (2.f * Kb * im) * jl);
+}
+
+// Adjoint of build_joint.
+SHD void a_joint(const DevModel& M, const Env& E, int j, int s) {
+  const float* C = E.jc(j);
+  const int a = E.jpar(j), b = E.jchi(j);
+  const float* Bb = E.body(b);
+  const float* Ba = a >= 0 ? E.body(a) : nullptr;
+  float* Ab = E.bodyA(b);
+  float* Aa = a >= 0 ? E.bodyA(a) : nullptr;
+  for (int q = 0; q < 5; ++q) {
+    const float* r = E.row(s + q);
+    float* qa = E.rowA(s + q);
+    const float m = r[RM];
+    a_row_finish(E, r, qa, a, b, -m * m * qa[QM]);
+  }
+  const float kb = M.beta / M.dt;
+  const f3 rbl = ld3(C + JAC), ral = ld3(C + JAP);
+  const f3 rb = mv(Bb + BR, rbl);
+  const f3 ra = a >= 0 ? mv(Ba + BR, ral) : mk3(0.f, 0.f, 0.f);
+  f3 rbb = mk3(0.f, 0.f, 0.f), rab = mk3(0.f, 0.f, 0.f), errb = mk3(0.f, 0.f, 0.f);
+  for (int q = 0; q < 3; ++q) {
+    const float* qa = E.rowA(s + q);
+    const f3 e = mk3(q == 0 ? 1.f : 0.f, q == 1 ? 1.f : 0.f, q == 2 ? 1.f : 0.f);
+    // Ja = e x ra ; Jb = rb x e
+    rab = rab + cross(ld3(qa + QJA), e);
+    rbb = rbb + cross(e, ld3(qa + QJB));
+    errb = errb + (kb * qa[QB]) * e;
+  }
+  add3(Ab + AP, errb);
+  rbb = rbb + errb;
+  add_outer(Ab + AR, rbb, rbl);
+  if (a >= 0) {
+    add3(Aa + AP, -errb);
+    rab = rab - errb;
+    add_outer(Aa + AR, rab, ral);
+  }
+  // angular rows
+  f3 na = ld3(C + JXP), ua = ld3(C + JUP);
+  const f3 t2l = cross(na, ua);
+  f3 t2 = t2l;
+  const f3 nal = na, ual = ua;
+  if (a >= 0) { na = mv(Ba + BR, na); ua = mv(Ba + BR, ua); t2 = mv(Ba + BR, t2); }
+  const f3 nbl = ld3(C + JXC);
+  const f3 nbw = mv(Bb + BR, nbl);
+  const f3 ax = cross(na, nbw);
+  f3 axb = mk3(0.f, 0.f, 0.f), tb[2];
+  for (int q = 0; q < 2; ++q) {
+    const float* qa = E.rowA(s + 3 + q);
+    const float cb = kb * qa[QB];
+    const f3 tk = q == 0 ? ua : t2;
+    tb[q] = ld3(qa + QJB) - ld3(qa + QJA) + cb * ax;
+    axb = axb + cb * tk;
+  }
+  // ax = na x nbw
+  const f3 nab = cross(nbw, axb);
+  const f3 nbb = cross(axb, na);
+  add_outer(Ab + AR, nbb, nbl);
+  if (a >= 0) {
+    add_outer(Aa + AR, nab, nal);
+    add_outer(Aa + AR, tb[0], ual);
+    add_outer(Aa + AR, tb[1], t2l);
+  }
+}
+
+// Adjoint of build_contact (+ the tangent adjoints collected from the store
+// and warm-start reverses).
+SHD void a_contact(const DevModel& M, const Env& E, int code, int s) {
+  const RowB rb = cand_bodies(E, code);
+  const bool ground = cand_kind(code) == K_GROUND;
+  const CGeo g = contact_geo(E, code);
+  const float* x = E.row(s + 3);
+  const float* xa = E.rowA(s + 3);
+  // row_finish adjoints: normal via m, tangents via mt = 2/(K1+K2)
+  {
+    const float m = E.row(s)[RM];
+    a_row_finish(E, E.row(s), E.rowA(s), rb.a, rb.b, -m * m * E.rowA(s)[QM]);
+    const float mt = x[XMT];
+    const float Kt = -0.5f * mt * mt * xa[XMT];
+    a_row_finish(E, E.row(s + 1), E.rowA(s + 1), rb.a, rb.b, Kt);
+    a_row_finish(E, E.row(s + 2), E.rowA(s + 2), rb.a, rb.b, Kt);
+  }
+  const f3 t1 = ld3(x + XT1), t2 = ld3(x + XT2);
+  const f3 dirs[3] = {g.n, t1, t2};
+  f3 dirb[3], rab = mk3(0.f, 0.f, 0.f), rbb = mk3(0.f, 0.f, 0.f);
+  for (int q = 0; q < 3; ++q) {
+    const float* qa = E.rowA(s + q);
+    const f3 jab = ld3(qa + QJA), jbb = ld3(qa + QJB);
+    dirb[q] = ld3(qa + QJL);
+    // Jb = rb x dir
+    rbb = rbb + cross(dirs[q], jbb);
+    dirb[q] = dirb[q] + cross(jbb, g.rb);
+    if (!ground) {
+      // Ja = dir x ra
+      dirb[q] = dirb[q] + cross(g.ra, jab);
+      rab = rab + cross(jab, dirs[q]);
+    }
+  }
+  const float gapb = E.rowA(s)[QB] * (g.gap > 0.f ? 1.f : M.beta) / M.dt;
+  float* Ab = E.bodyA(rb.b);
+  const float* Bb = E.body(rb.b);
+  if (ground) {
+    const int i = cand_idx(code);
+    const f3 off = ld3(E.gsph(i));
+    // rb = R o - r n (n constant) ; gap = p_z + (R o)_z - r
+    add_outer(Ab + AR, rbb, off);
+    Ab[AP + 2] += gapb;
+    add_outer(Ab + AR, mk3(0.f, 0.f, gapb), off);
+    return;
+  }
+  float* Aa = E.bodyA(rb.a);
+  const float* Ba = E.body(rb.a);
+  f3 nb_ = dirb[0];
+  f3 t1b = dirb[1] + ld3(xa + XT1);
+  const f3 t2b = dirb[2] + ld3(xa + XT2);
+  // t2 = n x t1
+  nb_ = nb_ + cross(t1, t2b);
+  t1b = t1b + cross(t2b, g.n);
+  // t1 = w / |w|, w = n x e
+  {
+    const bool zsel = fabsf(g.n.z) < 0.9f;
+    const f3 e = zsel ? mk3(0.f, 0.f, 1.f) : mk3(1.f, 0.f, 0.f);
+    const f3 w = cross(g.n, e);
+    const float wl = sqrtf(dot(w, w));
+    const f3 wb = (1.f / wl) * (t1b - dot(t1, t1b) * t1);
+    nb_ = nb_ + cross(e, wb);
+  }
+  // ra = R_a o_a + r_a n ; rb = R_b o_b - r_b n
+  const f3 oa = ld3(Ba + BPO), ob = ld3(Bb + BPO);
+  add_outer(Aa + AR, rab, oa);
+  add_outer(Ab + AR, rbb, ob);
+  nb_ = nb_ + Ba[BPR] * rab - Bb[BPR] * rbb;
+  // n = d / L, gap = L - r_a - r_b
+  f3 db = gapb * g.n;
+  if (g.L >= 1e-9f) db = db + (1.f / g.L) * (nb_ - dot(g.n, nb_) * g.n);
+  // d = c_b - c_a, c = p + R o
+  add3(Ab + AP, db);
+  add_outer(Ab + AR, db, ob);
+  add3(Aa + AP, -db);
+  add_outer(Aa + AR, -db, oa);
+}
+
+// B4: adjoint of the row set-up, colour by colour (disjoint bodies).
+template <class Team>
+SHD void a_rows(const Team& tm, const DevModel& M, const Env& E, bool act) {
+  for (int c = E.ncol - 1; tm.any(c >= 0 && act); --c) {
+    const int n = (act && c >= 0) ? E.act_cnt()[c] : 0;
+    const int lo = (act && c >= 0) ? E.colstart(c) : 0;
+    for (int k = tm.tl; k < n; k += tm.ts) {
+      const int s = E.act_slot()[lo + k];
+      if (s < 0) continue;
+      const int code = E.act_code()[lo + k];
+      if (cand_kind(code) == K_JOINT) a_joint(M, E, cand_idx(code), s);
+      else a_contact(M, E, code, s);
+    }
+    tm.sync();
+  }
+}
+
+// B3: adjoint of the prediction; B2: torques (per joint colour); B1: Iw.
+template <class Team>
+SHD void a_predict_torques(const Team& tm, const DevModel& M, const Env& E, bool act, float* g_u_row,
+                           float* g_damp) {
+  const int nb = act ? E.nb : 0;
+  for (int b = tm.tl; b < nb; b += tm.ts) {
+    const float* B = E.body(b);
+    float* A = E.bodyA(b);
+    const f3 wb = ld3(A + AW);
+    // w* = w + dt Iw tq
+    const f3 tqb = M.dt * sv(B + BI, wb);
+    st3(A + ATQ, tqb);
+    add_outer(A + AIW, M.dt * wb, ld3(B + BTQ));
+  }
+  tm.sync();
+  for (int c = 0; tm.any(c < E.ncol && act); ++c) {
+    int lo = 0, hi = 0;
+    if (act && c < E.ncol) {
+      lo = E.colstart(c); hi = E.colstart(c + 1);
+      if (lo >= E.nj || cand_kind(E.cand(lo)) != K_JOINT) hi = lo;
+    }
+    for (int i = lo + tm.tl; i < hi; i += tm.ts) {
+      const int j = cand_idx(E.cand(i));
+      const float* C = E.jc(j);
+      const int a = E.jpar(j), b = E.jchi(j);
+      const f3 n = joint_axis_w(E, j);
+      float* Ab = E.bodyA(b);
+      f3 wrel = ld3(Ab + AW0);
+      f3 tqd = ld3(Ab + ATQ);
+      if (a >= 0) { wrel = wrel - ld3(E.bodyA(a) + AW0); tqd = tqd - ld3(E.bodyA(a) + ATQ); }
+      const float dmp = C[JD];
+      const float tau = C[JU] - dmp * dot(wrel, n);
+      const float taub = dot(n, tqd);
+      f3 nb_ = tau * tqd - (taub * dmp) * wrel;
+      if (g_u_row) g_u_row[E.j0 + j] = taub;
+      E.jA()[j] += -taub * dot(wrel, n);
+      add3(Ab + AW, -(taub * dmp) * n);
+      if (a >= 0) {
+        float* Aa = E.bodyA(a);
+        add3(Aa + AW, (taub * dmp) * n);
+        add_outer(Aa + AR, nb_, ld3(C + JXP));
+      }
+    }
+    tm.sync();
+  }
+  (void)g_damp;
+  // B1: Iw = R D R^T -> Rbar += (Iwbar + Iwbar^T) R D ; invIbar_k += (R^T Iwbar R)_kk
+  for (int b = tm.tl; b < nb; b += tm.ts) {
+    const float* B = E.body(b);
+    float* A = E.bodyA(b);
+    const float* R = B + BR;
+    const float* G = A + AIW;
+    float Sy[9];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) Sy[3 * i + j] = G[3 * i + j] + G[3 * j + i];
+    for (int i = 0; i < 3; ++i)
+      for (int k = 0; k < 3; ++k) {
+        const float srk = Sy[3 * i] * R[k] + Sy[3 * i + 1] * R[3 + k] + Sy[3 * i + 2] * R[6 + k];
+        A[AR + 3 * i + k] += srk * B[BII + k];
+      }
+    for (int k = 0; k < 3; ++k) {
+      // (R^T G R)_kk = sum_ij R_ik G_ij R_jk
+      float acc = 0.f;
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) acc += R[3 * i + k] * G[3 * i + j] * R[3 * j + k];
+      A[AII + k] += acc;
+    }
+  }
+  tm.sync();
+}
+
+}  // namespace sim

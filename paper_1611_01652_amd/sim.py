@@ -1,0 +1,224 @@
+"""ctypes binding of the C ABI in include/sim.h (argument marshalling only).
+
+Every step of the simulation runs in the HIP library ``libsim_hip.so``; this
+module only converts a workload description into ``sim_model_desc``, owns the
+handle, and passes device pointers of torch tensors.  There is no CPU path:
+loading fails loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsim_hip.so")
+
+SIM_OK = 0
+FLAG_NONFINITE = 1
+FLAG_CONTACT_OVERFLOW = 2
+
+_I32P = C.POINTER(C.c_int32)
+_F32P = C.POINTER(C.c_float)
+
+
+class SimDesc(C.Structure):
+    _fields_ = [
+        ("n_envs", C.c_int32),
+        ("env_body_off", _I32P), ("env_joint_off", _I32P), ("env_sphere_off", _I32P),
+        ("inv_mass", _F32P), ("inv_inertia", _F32P),
+        ("sphere_body", _I32P), ("sphere_offset", _F32P), ("sphere_radius", _F32P), ("sphere_flags", _I32P),
+        ("joint_parent", _I32P), ("joint_child", _I32P),
+        ("anchor_p", _F32P), ("anchor_c", _F32P), ("axis_p", _F32P), ("axis_c", _F32P),
+        ("perp_p", _F32P), ("perp_c", _F32P), ("damping", _F32P),
+        ("mu", _F32P), ("loss_body", _I32P), ("target", _F32P), ("T_env", _I32P),
+        ("T_max", C.c_int32), ("dt", C.c_float), ("gravity", C.c_float * 3),
+        ("beta", C.c_float), ("gamma", C.c_float), ("spec_margin", C.c_float), ("warm", C.c_float),
+        ("n_iters", C.c_int32), ("ground", C.c_int32), ("loss_kind", C.c_int32), ("loss_mask", C.c_int32),
+        ("ckpt_every", C.c_int32),
+    ]
+
+
+class SimInfo(C.Structure):
+    _fields_ = [
+        ("n_envs", C.c_int32), ("n_bodies", C.c_int32), ("n_joints", C.c_int32),
+        ("lam_size", C.c_int32), ("n_ckpt", C.c_int32),
+        ("ckpt_floats", C.c_int64), ("workspace_bytes", C.c_int64),
+        ("max_lds_bytes", C.c_int32), ("n_tiles", C.c_int32),
+    ]
+
+
+def make_desc(w):
+    """Build a SimDesc for a workload; returns (desc, keepalive list)."""
+    keep = []
+
+    def f(a):
+        arr = np.ascontiguousarray(np.asarray(a, dtype=np.float32)).reshape(-1)
+        if arr.size == 0:
+            arr = np.zeros(1, np.float32)
+        keep.append(arr)
+        return arr.ctypes.data_as(_F32P)
+
+    def i(a):
+        arr = np.ascontiguousarray(np.asarray(a, dtype=np.int32)).reshape(-1)
+        if arr.size == 0:
+            arr = np.zeros(1, np.int32)
+        keep.append(arr)
+        return arr.ctypes.data_as(_I32P)
+
+    d = SimDesc()
+    d.n_envs = w.n_envs
+    d.env_body_off = i(w.env_body_off)
+    d.env_joint_off = i(w.env_joint_off)
+    d.env_sphere_off = i(w.env_sphere_off)
+    d.inv_mass = f(w.inv_mass)
+    d.inv_inertia = f(w.inv_inertia)
+    d.sphere_body = i(w.sphere_body)
+    d.sphere_offset = f(w.sphere_offset)
+    d.sphere_radius = f(w.sphere_radius)
+    d.sphere_flags = i(w.sphere_flags)
+    d.joint_parent = i(w.joint_parent)
+    d.joint_child = i(w.joint_child)
+    for k in ("anchor_p", "anchor_c", "axis_p", "axis_c", "perp_p", "perp_c", "damping"):
+        setattr(d, k, f(getattr(w, k)))
+    d.mu = f(w.mu)
+    d.loss_body = i(w.loss_body)
+    d.target = f(w.target)
+    d.T_env = i(w.T_env)
+    d.T_max = w.T_max
+    d.dt = w.dt
+    d.gravity = (C.c_float * 3)(*w.gravity)
+    d.beta, d.gamma, d.spec_margin, d.warm = w.beta, w.gamma, w.spec_margin, w.warm
+    d.n_iters, d.ground, d.loss_kind, d.loss_mask = w.n_iters, w.ground, w.loss_kind, w.loss_mask
+    d.ckpt_every = w.ckpt_every
+    return d, keep
+
+
+_lib = None
+
+
+def library():
+    """Load the HIP library; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"HIP library not built: {LIB_PATH} is missing (run __graft_entry__.build())")
+    lib = C.CDLL(LIB_PATH)
+    vp = C.c_void_p
+    lib.sim_abi_version.restype = C.c_int
+    lib.sim_last_error.restype = C.c_char_p
+    lib.sim_init.argtypes = [C.POINTER(SimDesc), C.POINTER(vp)]
+    lib.sim_destroy.argtypes = [vp]
+    lib.sim_get_info.argtypes = [vp, C.POINTER(SimInfo)]
+    lib.sim_lambda_offsets.argtypes = [vp, _I32P]
+    lib.sim_step.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.rollout.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.rollout_grad.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, C.c_size_t, vp]
+    for fn in ("sim_init", "sim_destroy", "sim_get_info", "sim_lambda_offsets", "sim_step", "rollout",
+               "rollout_grad"):
+        getattr(lib, fn).restype = C.c_int
+    _lib = lib
+    return lib
+
+
+EXPORTED = ["sim_abi_version", "sim_last_error", "sim_init", "sim_destroy", "sim_get_info",
+            "sim_lambda_offsets", "sim_step", "rollout", "rollout_grad"]
+
+
+class SimError(RuntimeError):
+    pass
+
+
+def _check(lib, st, what):
+    if st != SIM_OK:
+        raise SimError(f"{what} failed ({st}): {lib.sim_last_error().decode()}")
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def soa(x_b18):
+    """[B,18] -> [18,B] (contiguous)."""
+    return x_b18.transpose(0, 1).contiguous() if hasattr(x_b18, "transpose") else np.ascontiguousarray(x_b18.T)
+
+
+class Simulator:
+    """One model on the current HIP device.  Tensors are torch CUDA tensors."""
+
+    def __init__(self, w):
+        import torch  # device memory and streams only
+        self.torch = torch
+        self.lib = library()
+        self.w = w
+        desc, keep = make_desc(w)
+        h = C.c_void_p()
+        _check(self.lib, self.lib.sim_init(C.byref(desc), C.byref(h)), "sim_init")
+        self.h = h
+        info = SimInfo()
+        _check(self.lib, self.lib.sim_get_info(h, C.byref(info)), "sim_get_info")
+        self.info = info
+        lo = np.zeros(w.n_envs + 1, np.int32)
+        _check(self.lib, self.lib.sim_lambda_offsets(h, lo.ctypes.data_as(_I32P)), "sim_lambda_offsets")
+        self.lam_off = lo
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.sim_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _stream(self):
+        return C.c_void_p(self.torch.cuda.current_stream().cuda_stream)
+
+    def _f32(self, n):
+        return self.torch.zeros(max(int(n), 1), dtype=self.torch.float32, device="cuda")
+
+    def rollout(self, x0, u, want_ckpt=True, want_final=True):
+        """x0 [18,B] and u [T_max,J] CUDA float32 tensors."""
+        t = self.torch
+        E = self.info.n_envs
+        out = dict(loss=self._f32(E), flags=t.zeros(max(E, 1), dtype=t.int32, device="cuda"))
+        out["x_final"] = self._f32(18 * self.info.n_bodies).view(18, -1) if want_final else None
+        out["lam_final"] = self._f32(self.info.lam_size) if want_final else None
+        out["ckpt"] = self._f32(self.info.ckpt_floats) if want_ckpt else None
+        st = self.lib.rollout(self.h, _ptr(x0), _ptr(u), _ptr(out["loss"]), _ptr(out["x_final"]),
+                              _ptr(out["lam_final"]), _ptr(out["ckpt"]), _ptr(out["flags"]), self._stream())
+        _check(self.lib, st, "rollout")
+        out["loss"] = out["loss"][:E]
+        return out
+
+    def workspace(self):
+        return self.torch.empty(int(self.info.workspace_bytes) // 4 + 1, dtype=self.torch.float32, device="cuda")
+
+    def rollout_grad(self, x0, u, ckpt, dloss, workspace=None):
+        E, B, J = self.info.n_envs, self.info.n_bodies, self.info.n_joints
+        ws = workspace if workspace is not None else self.workspace()
+        g = dict(g_x0=self._f32(18 * B).view(18, -1), g_u=self._f32(self.w.T_max * J),
+                 g_inv_mass=self._f32(B), g_inv_inertia=self._f32(3 * B), g_mu=self._f32(E), g_damping=self._f32(J))
+        st = self.lib.rollout_grad(self.h, _ptr(x0), _ptr(u), _ptr(ckpt), _ptr(dloss), _ptr(g["g_x0"]),
+                                   _ptr(g["g_u"]), _ptr(g["g_inv_mass"]), _ptr(g["g_inv_inertia"]), _ptr(g["g_mu"]),
+                                   _ptr(g["g_damping"]), _ptr(ws), ws.numel() * 4, self._stream())
+        _check(self.lib, st, "rollout_grad")
+        g["g_u"] = g["g_u"][: self.w.T_max * J].view(self.w.T_max, J) if J else g["g_u"][:0]
+        g["g_inv_mass"] = g["g_inv_mass"][:B]
+        g["g_inv_inertia"] = g["g_inv_inertia"][: 3 * B].view(B, 3)
+        g["g_mu"] = g["g_mu"][:E]
+        g["g_damping"] = g["g_damping"][:J]
+        return g
+
+    def step(self, x, u, lam):
+        t = self.torch
+        xo = t.empty_like(x)
+        lo = t.empty_like(lam)
+        flags = t.zeros(max(self.info.n_envs, 1), dtype=t.int32, device="cuda")
+        st = self.lib.sim_step(self.h, _ptr(x), _ptr(xo), _ptr(u), _ptr(lam), _ptr(lo), _ptr(flags), self._stream())
+        _check(self.lib, st, "sim_step")
+        return xo, lo, flags
