@@ -116,6 +116,8 @@ typedef struct {
   int32_t loss_kind;             /* SIM_LOSS_* */
   int32_t loss_mask;             /* bit k: coordinate k enters the loss */
   int32_t ckpt_every;            /* K_ck: rollout stores the state every K_ck steps */
+  int32_t min_team;              /* 0: automatic; else lanes per env are at least this
+                                    (power of two <= 64).  Results do not depend on it. */
 } sim_model_desc;
 
 /* Sizes derived by sim_init. */
@@ -143,6 +145,15 @@ sim_status sim_destroy(sim_handle h);
 sim_status sim_get_info(sim_handle h, sim_info* info);
 /* lam_off[E+1] (host): start of each env's warm-start block. */
 sim_status sim_lambda_offsets(sim_handle h, int32_t* lam_off);
+
+/* Host only (touches no device): the canonical sweep order of env `env` of
+ * a description.  Writes up to `cap` codes (kind << 24 | index; kind 0 =
+ * joint (global index), 1 = ground contact (global sphere index), 2 = sphere
+ * pair (local body a | local body b << 12)) and colour ids into codes[] and
+ * colours[] (host, may be NULL) and returns the number of constraints, or a
+ * negative sim_status.  Inside one colour no two constraints share a body. */
+int32_t sim_describe_order(const sim_model_desc* desc, int32_t env, int32_t* codes, int32_t* colours,
+                           int32_t cap);
 
 /* One step for all envs: x_out = f_ph(x_in, u) at step index t (device
  * pointers, x[18][B], u[J], lambda[lam_size]).  lam_in may equal lam_out;

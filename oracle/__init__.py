@@ -47,6 +47,8 @@ def _load():
         _lib.oracle_rollout_grad.argtypes = [C.c_void_p, dp, dp, dp, dp, dp, dp, dp, dp, dp, dp, C.c_int]
         _lib.oracle_count_flops.argtypes = [C.c_void_p, C.c_int, dp, dp, dp, C.c_int]
         _lib.oracle_count_flops.restype = C.c_longlong
+        _lib.oracle_count_tape_edges.argtypes = [C.c_void_p, C.c_int, dp, dp, dp, C.c_int]
+        _lib.oracle_count_tape_edges.restype = C.c_longlong
     return _lib
 
 
@@ -68,7 +70,7 @@ class _Model(C.Structure):
         ("ctrl_kind", C.c_int),
         ("mlp_in", C.c_int), ("mlp_h1", C.c_int), ("mlp_h2", C.c_int), ("mlp_out", C.c_int),
         ("mlp_n_params", C.c_int), ("mlp_w", C.c_void_p), ("clock_hz", C.c_double),
-        ("warm", C.c_double),
+        ("warm", C.c_double), ("noise", C.c_double), ("noise_seed", C.c_int),
     ]
 
 
@@ -79,7 +81,7 @@ def _dp(a):
 class Oracle:
     """Wraps one workload; arrays are converted to float64/int32 once."""
 
-    def __init__(self, w, mlp=None):
+    def __init__(self, w, mlp=None, noise=0.0, noise_seed=0):
         self.w = w
         keep = {}
 
@@ -131,6 +133,8 @@ class Oracle:
             m.ctrl_kind = 0
             m.mlp_w = d("mlpw", np.zeros(1))
         m.warm = getattr(w, 'warm', 1.0)
+        m.noise = float(noise)
+        m.noise_seed = int(noise_seed)
         self._m = m
         self._keep = keep
         self.lib = _load()
@@ -197,3 +201,10 @@ class Oracle:
         lam = np.zeros(max(self.lam_size, 1)) if lam is None else np.ascontiguousarray(lam, dtype=np.float64)
         u = np.ascontiguousarray(np.zeros(max(w.n_joints, 1)) if u is None else u, dtype=np.float64)
         return int(self.lib.oracle_count_flops(C.byref(self._m), env, _dp(x), _dp(lam), _dp(u), int(t)))
+
+    def count_tape_edges(self, env=0, x=None, lam=None, u=None, t=0):
+        w = self.w
+        x = np.ascontiguousarray(w.x0 if x is None else x, dtype=np.float64)
+        lam = np.zeros(max(self.lam_size, 1)) if lam is None else np.ascontiguousarray(lam, dtype=np.float64)
+        u = np.ascontiguousarray(np.zeros(max(w.n_joints, 1)) if u is None else u, dtype=np.float64)
+        return int(self.lib.oracle_count_tape_edges(C.byref(self._m), env, _dp(x), _dp(lam), _dp(u), int(t)))

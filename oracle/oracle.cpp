@@ -594,6 +594,20 @@ template <class S> static std::vector<S> to_s(const double* p, int n) {
   return v;
 }
 
+// Test aid for judging conditioning (never part of the method): multiply each
+// state component after a step by (1 + noise * r), r in [-1, 1) from a
+// counter-based hash of (env, step, component) (splitmix64), which mimics
+// the rounding of a single-precision run.
+static double noise_r(uint64_t seed, uint64_t e, uint64_t t, uint64_t i) {
+  uint64_t z = (e * 0x9E3779B97F4A7C15ULL) ^ (t * 0xBF58476D1CE4E5B9ULL) ^ (i * 0x94D049BB133111EBULL) ^
+               (seed * 0xD6E8FEB86659FD93ULL);
+  z += 0x9E3779B97F4A7C15ULL;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+  z = z ^ (z >> 31);
+  return (double)(z >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+}
+
 // Forward rollout of one env in type S; optionally records step-start states.
 template <class S>
 static S rollout_env(const Ctx& C, int e, std::vector<S>& x, std::vector<S>& lam,
@@ -617,6 +631,8 @@ static S rollout_env(const Ctx& C, int e, std::vector<S>& x, std::vector<S>& lam
       for (int j = 0; j < E.nj; ++j) u[j] = S(c.u[(size_t)t * c.u_stride + E.j0 + j]);
     StepIn<S> in{x.data(), lam.data(), u.data(), invm.data(), invI.data(), damp.data(), S(c.mu[e])};
     step_env(C.M, E, in, xn.data(), ln.data(), W.data(), t);
+    if (c.noise > 0.0)
+      for (int i = 0; i < n; ++i) xn[i] = xn[i] * S(1.0 + c.noise * noise_r(c.noise_seed, e, t, i));
     x.swap(xn);
     lam.swap(ln);
     L = L + loss_term(C.M, E, e, t + 1, T, x.data(), x0.data());
@@ -791,6 +807,35 @@ long long oracle_count_flops(const oracle_model* m, int env, const double* x, co
   flop_counter() = 0;
   step_env<Cnt>(C.M, E, in, xn.data(), ln.data(), Wv.data(), t);
   return (long long)flop_counter();
+}
+
+// Reverse-mode cost of one step: edges of its tape (one multiply-add each in
+// the reverse sweep); also returns the forward operation count.
+long long oracle_count_tape_edges(const oracle_model* m, int env, const double* x, const double* lam,
+                                  const double* u, int t) {
+  Ctx C;
+  build_ctx(m, C);
+  const EnvTopo& E = C.topo[env];
+  Tape tp;
+  tape() = &tp;
+  std::vector<Var> xv(18 * E.nb), lv(E.lam_size), uv(E.nj), mv(E.nb), Iv(3 * E.nb), dv(E.nj), Wv;
+  for (int i = 0; i < 18 * E.nb; ++i) xv[i] = Var::input(x[18 * E.b0 + i]);
+  for (int i = 0; i < E.lam_size; ++i) lv[i] = Var::input(lam[E.lam_off + i]);
+  for (int j = 0; j < E.nj; ++j) uv[j] = Var::input(u ? u[E.j0 + j] : 0.0);
+  for (int b = 0; b < E.nb; ++b) mv[b] = Var::input(m->inv_mass[E.b0 + b]);
+  for (int i = 0; i < 3 * E.nb; ++i) Iv[i] = Var::input(m->inv_inertia[3 * E.b0 + i]);
+  for (int j = 0; j < E.nj; ++j) dv[j] = Var::input(m->damping[E.j0 + j]);
+  if (m->ctrl_kind == 1) {
+    Wv.resize(m->mlp_n_params);
+    for (int i = 0; i < m->mlp_n_params; ++i) Wv[i] = Var::input(m->mlp_w[i]);
+  }
+  std::vector<Var> xn(18 * E.nb), ln(E.lam_size);
+  StepIn<Var> in{xv.data(), lv.data(), uv.data(), mv.data(), Iv.data(), dv.data(), Var::input(m->mu[env])};
+  step_env<Var>(C.M, E, in, xn.data(), ln.data(), Wv.data(), t);
+  long long edges = 0;
+  for (const auto& n : tp.nodes) edges += (n.a >= 0) + (n.b >= 0);
+  tape() = nullptr;
+  return edges;
 }
 
 }  // extern "C"

@@ -35,6 +35,8 @@ typedef struct {
   const double *mlp_w;        /* W1[h1][in] b1 W2[h2][h1] b2 W3[out][h2] b3 */
   double clock_hz;
   double warm;                /* warm-start factor applied to carried impulses */
+  double noise;               /* test aid: relative rounding-sized noise added to the state after every step */
+  int noise_seed;
 } oracle_model;
 
 int oracle_lambda_size(const oracle_model* m, int* out_offsets /* [E+1] or NULL */);
@@ -48,6 +50,9 @@ int oracle_rollout_grad(const oracle_model* m, const double* x0, const double* d
                         double* g_mu, double* g_damping, double* g_w, int n_threads);
 long long oracle_count_flops(const oracle_model* m, int env, const double* x, const double* lam,
                              const double* u, int t);
+
+long long oracle_count_tape_edges(const oracle_model* m, int env, const double* x, const double* lam,
+                                  const double* u, int t);
 
 #ifdef __cplusplus
 }

@@ -95,7 +95,7 @@ SHD void env_rollout(const Team& tm, const DevModel& M, const Env& E, bool valid
     if (a.lam_final) store_ws(tm, E, a.lam_final);
     if (tm.tl == 0) {
       a.loss[E.e] = loss;
-      fl |= (uint32_t)((int*)E.misc())[MISC_FLAGS];
+      fl |= (uint32_t)(*reinterpret_cast<int*>(E.misc() + MISC_FLAGS));
       if (a.flags) a.flags[E.e] = fl;
     }
   }
@@ -115,7 +115,7 @@ SHD void env_single_step(const Team& tm, const DevModel& M, const Env& E, bool v
   if (valid) {
     store_state(tm, E, a.x_out, M.B);
     store_ws(tm, E, a.lam_out);
-    if (tm.tl == 0 && a.flags) a.flags[E.e] = fl | (uint32_t)((int*)E.misc())[MISC_FLAGS];
+    if (tm.tl == 0 && a.flags) a.flags[E.e] = fl | (uint32_t)(*reinterpret_cast<int*>(E.misc() + MISC_FLAGS));
   }
 }
 
@@ -147,8 +147,8 @@ SHD void env_rollout_grad(const Team& tm, const DevModel& M, const Env& E, bool 
     load_env_static(tm, M, E);
     for (int i = tm.tl; i < E.nb * BSA; i += tm.ts) E.L[E.lay.bodyA + i] = 0.f;
     for (int i = tm.tl; i < E.lam_size; i += tm.ts) E.wsA()[i] = 0.f;
-    for (int i = tm.tl; i < E.nj; i += tm.ts) E.jA()[i] = 0.f;
-    if (tm.tl == 0) E.misc()[MISC_GMU] = 0.f;
+    for (int i = tm.tl; i < 2 * E.nj; i += tm.ts) E.jA()[i] = 0.f;
+    if (tm.tl == 0) E.misc()[MISC_GMU] = E.misc()[MISC_GMUC] = 0.f;
   }
   tm.sync();
   const int K = M.ckpt_every;
@@ -225,9 +225,9 @@ SHD void env_rollout_grad(const Team& tm, const DevModel& M, const Env& E, bool 
       const float* A = E.bodyA(b);
       if (a.g_x0)
         for (int k = 0; k < 18; ++k) a.g_x0[(size_t)k * M.B + E.b0 + b] = A[k];
-      if (a.g_invm) a.g_invm[E.b0 + b] = A[AIM];
+      if (a.g_invm) a.g_invm[E.b0 + b] = A[ATM];
       if (a.g_invI)
-        for (int k = 0; k < 3; ++k) a.g_invI[3 * (E.b0 + b) + k] = A[AII + k];
+        for (int k = 0; k < 3; ++k) a.g_invI[3 * (E.b0 + b) + k] = A[ATI + k];
     }
     if (a.g_damp)
       for (int j = tm.tl; j < E.nj; j += tm.ts) a.g_damp[E.j0 + j] = E.jA()[j];

@@ -141,8 +141,8 @@ sim_status build_env(const sim_model_desc& d, int e, HostEnv& H) {
   colstart.push_back((int)cand.size());
   H.ncand = (int)cand.size();
   H.lam = 5 * H.nj + 4 * H.G + 4 * H.P;
-  // contact capacity per env: every candidate when few, else 3 per body + 4
-  H.ccap = std::min(H.G + H.P, 3 * H.nb + 4);
+  // contact capacity per env: every candidate when few, else 2 per body + 4
+  H.ccap = std::min(H.G + H.P, 2 * H.nb + 4);
   H.nslot = 5 * H.nj + 4 * H.ccap;
   H.topo.clear();
   H.topo.insert(H.topo.end(), jpar.begin(), jpar.end());

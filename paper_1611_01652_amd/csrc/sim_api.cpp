@@ -48,6 +48,9 @@ struct sim_model {
   int n_cu = 256;
   int max_lds = 65536;
   int device = 0;
+  std::vector<hipStream_t> streams;  // one per bucket when there are several
+  std::vector<hipEvent_t> joins;
+  hipEvent_t fork = nullptr;
 };
 
 namespace {
@@ -70,12 +73,34 @@ void release(sim_model* h) {
   if (h->d_cst) (void)hipFree(h->d_cst);
   if (h->d_target) (void)hipFree(h->d_target);
   if (h->d_queue) (void)hipFree(h->d_queue);
+  for (auto sx : h->streams) (void)hipStreamDestroy(sx);
+  for (auto ex : h->joins) (void)hipEventDestroy(ex);
+  if (h->fork) (void)hipEventDestroy(h->fork);
   delete h;
 }
 
 sim_status check_device(const char* what) {
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(SIM_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+  return SIM_OK;
+}
+
+// Launch every bucket: directly on the caller's stream when there is one,
+// else forked onto the bucket streams and joined back.
+template <class F>
+sim_status run_buckets(sim_model* h, hipStream_t st, F launch, const char* what) {
+  if (h->buckets.size() == 1) {
+    if (!launch(0, st)) return check_device(what);
+    return SIM_OK;
+  }
+  if (hipEventRecord(h->fork, st) != hipSuccess) return check_device(what);
+  for (size_t i = 0; i < h->buckets.size(); ++i) {
+    if (hipStreamWaitEvent(h->streams[i], h->fork, 0) != hipSuccess) return check_device(what);
+    if (!launch(i, h->streams[i])) return check_device(what);
+    if (hipEventRecord(h->joins[i], h->streams[i]) != hipSuccess) return check_device(what);
+  }
+  for (size_t i = 0; i < h->buckets.size(); ++i)
+    if (hipStreamWaitEvent(st, h->joins[i], 0) != hipSuccess) return check_device(what);
   return SIM_OK;
 }
 
@@ -120,6 +145,8 @@ sim_status sim_init(const sim_model_desc* d, sim_handle* out) {
   if (d->T_max < 0) return fail(SIM_E_ARG, "T_max < 0");
   if (d->loss_kind < 0 || d->loss_kind > 2) return fail(SIM_E_ARG, "unknown loss_kind");
   if (!(d->gamma >= 0.f)) return fail(SIM_E_ARG, "gamma < 0");
+  if (d->min_team < 0 || d->min_team > 64 || (d->min_team & (d->min_team - 1)) != 0)
+    return fail(SIM_E_ARG, "min_team must be 0 or a power of two <= 64");
   for (int e = 0; e < E; ++e) {
     if (d->T_env[e] < 0 || d->T_env[e] > d->T_max) return fail(SIM_E_SHAPE, "T_env outside [0, T_max]");
     if (d->loss_body[e] < d->env_body_off[e] || d->loss_body[e] >= d->env_body_off[e + 1])
@@ -128,6 +155,13 @@ sim_status sim_init(const sim_model_desc* d, sim_handle* out) {
   for (int j = 0; j < J; ++j)
     if (!(d->damping[j] >= 0.f) || !std::isfinite(d->damping[j])) return fail(SIM_E_ARG, "damping < 0");
 
+  // per-env validation and packing happen on the host before any device call
+  PackedModel P;
+  {
+    std::string perr;
+    const sim_status st = pack_model(d, P, perr);
+    if (st != SIM_OK) return fail(st, perr);
+  }
   sim_model* h = new sim_model();
   if (hipGetDevice(&h->device) != hipSuccess) { release(h); return fail(SIM_E_DEVICE, "no HIP device"); }
   (void)hipDeviceGetAttribute(&h->n_cu, hipDeviceAttributeMultiprocessorCount, h->device);
@@ -138,12 +172,6 @@ sim_status sim_init(const sim_model_desc* d, sim_handle* out) {
   M.dt = d->dt; M.gx = d->gravity[0]; M.gy = d->gravity[1]; M.gz = d->gravity[2];
   M.beta = d->beta; M.gamma = d->gamma; M.spec = d->spec_margin; M.warm = d->warm;
 
-  PackedModel P;
-  std::string perr;
-  {
-    const sim_status st = pack_model(d, P, perr);
-    if (st != SIM_OK) { release(h); return fail(st, perr); }
-  }
   h->lam_off = P.lam_off;
   std::vector<int>& team_of = P.team_of;
   const std::vector<int>& fwd_of = P.fwd_of;
@@ -152,7 +180,10 @@ sim_status sim_init(const sim_model_desc* d, sim_handle* out) {
   int max_lds = 0;
   for (int e = 0; e < E; ++e) {
     // widen the team while the tile does not fit in LDS
-    int team = team_of[e];
+    // narrowest team the topology allows: a wave's step time is set by its
+    // latency chain, not by how many envs share the wave
+    int team = std::max(team_of[e], d->min_team);
+    if (team > 64) team = 64;
     while (team < 64 && (64 / team) * (long long)adj_of[e] * 4 > h->max_lds) team *= 2;
     if ((64 / team) * (long long)adj_of[e] * 4 > h->max_lds) {
       release(h);
@@ -162,12 +193,18 @@ sim_status sim_init(const sim_model_desc* d, sim_handle* out) {
     team_of[e] = team;
   }
   M.lam_tot = h->lam_off[E];
-  // buckets by team size; tiles sorted longest episode first, then largest env
-  for (int team = 1; team <= 64; team *= 2) {
+  // buckets by team size and LDS size class (a quarter octave), so a tile
+  // reserves about what its envs need; tiles sorted longest episode first
+  auto lds_class = [&](int e) { return (int)std::floor(4.0 * std::log2((double)std::max(adj_of[e], 1))); };
+  std::vector<std::pair<int, int>> keys;
+  for (int e = 0; e < E; ++e) keys.push_back({team_of[e], lds_class(e)});
+  std::sort(keys.begin(), keys.end());
+  keys.erase(std::unique(keys.begin(), keys.end()), keys.end());
+  for (const auto& key : keys) {
+    const int team = key.first;
     std::vector<int> ids;
     for (int e = 0; e < E; ++e)
-      if (team_of[e] == team) ids.push_back(e);
-    if (ids.empty()) continue;
+      if (team_of[e] == team && lds_class(e) == key.second) ids.push_back(e);
     std::stable_sort(ids.begin(), ids.end(), [&](int a, int b) {
       if (d->T_env[a] != d->T_env[b]) return d->T_env[a] > d->T_env[b];
       return adj_of[a] > adj_of[b];
@@ -184,6 +221,25 @@ sim_status sim_init(const sim_model_desc* d, sim_handle* out) {
     }
     max_lds = std::max(max_lds, epw * bk.floats_adj * 4);
     h->buckets.push_back(bk);
+  }
+  // buckets run concurrently: one stream each (default priority), forked from
+  // and joined back to the caller's stream with events
+  if (h->buckets.size() > 1) {
+    for (size_t i = 0; i < h->buckets.size(); ++i) {
+      hipStream_t sx;
+      hipEvent_t ex;
+      if (hipStreamCreateWithFlags(&sx, hipStreamNonBlocking) != hipSuccess ||
+          hipEventCreateWithFlags(&ex, hipEventDisableTiming) != hipSuccess) {
+        release(h);
+        return fail(SIM_E_DEVICE, "cannot create bucket streams");
+      }
+      h->streams.push_back(sx);
+      h->joins.push_back(ex);
+    }
+    if (hipEventCreateWithFlags(&h->fork, hipEventDisableTiming) != hipSuccess) {
+      release(h);
+      return fail(SIM_E_DEVICE, "cannot create fork event");
+    }
   }
   sim_status st = SIM_OK;
   if ((st = upload(&h->d_hdr, P.hdr)) != SIM_OK || (st = upload(&h->d_topo, P.topo)) != SIM_OK ||
@@ -212,6 +268,37 @@ sim_status sim_init(const sim_model_desc* d, sim_handle* out) {
   for (auto& b : h->buckets) I.n_tiles += b.n_tiles;
   *out = h;
   return SIM_OK;
+}
+
+int32_t sim_describe_order(const sim_model_desc* d, int32_t env, int32_t* codes, int32_t* colours, int32_t cap) {
+  if (!d || env < 0 || env >= d->n_envs) return fail(SIM_E_ARG, "sim_describe_order: bad arguments");
+  PackedModel P;
+  std::string perr;
+  const sim_status st = pack_model(d, P, perr);
+  if (st != SIM_OK) return fail(st, perr);
+  const int* hd = &P.hdr[(size_t)env * H_COUNT];
+  const int nj = hd[H_NJ], G = hd[H_G], Pn = hd[H_P], ncol = hd[H_NCOL], ncand = hd[H_NCAND];
+  const int* tp = P.topo.data() + hd[H_TOPO];
+  const int* gbody = tp + 2 * nj;
+  const int* pcode = gbody + G;
+  const int* colstart = pcode + Pn;
+  const int* cand = colstart + ncol + 1;
+  // ground index -> global sphere index
+  std::vector<int> gsph;
+  for (int s = d->env_sphere_off[env]; s < d->env_sphere_off[env + 1]; ++s)
+    if ((d->sphere_flags[s] & 1) && d->ground) gsph.push_back(s);
+  for (int c = 0; c < ncol; ++c)
+    for (int i = colstart[c]; i < colstart[c + 1]; ++i) {
+      if (i >= cap) continue;
+      const int k = cand_kind(cand[i]), x = cand_idx(cand[i]);
+      int v = x;
+      if (k == K_JOINT) v = hd[H_J0] + x;
+      else if (k == K_GROUND) v = gsph[x];
+      else v = (pcode[x] & 0xFFFF) | ((pcode[x] >> 16) << 12);
+      if (codes) codes[i] = (k << 24) | v;
+      if (colours) colours[i] = c;
+    }
+  return ncand;
 }
 
 sim_status sim_destroy(sim_handle h) {
@@ -243,15 +330,13 @@ sim_status sim_step(sim_handle h, const float* x_in, float* x_out, const float* 
   if (s != SIM_OK) return s;
   hipStream_t st = (hipStream_t)stream;
   StepArgs a{x_in, x_out, u, lam_in, lam_out, env_flags};
-  for (size_t i = 0; i < h->buckets.size(); ++i) {
+  return run_buckets(h, st, [&](size_t i, hipStream_t sx) {
     const Bucket& b = h->buckets[i];
     TileSet ts{b.envs_dev, b.n_tiles, b.floats_fwd, h->d_queue + i};
-    if (launch_zero(ts.queue, 1, st) != hipSuccess) return check_device("sim_step zero");
+    if (launch_zero(ts.queue, 1, sx) != hipSuccess) return false;
     const size_t lds = (size_t)(64 / b.team) * b.floats_fwd * 4;
-    if (launch_step(h->M, ts, b.team, grid_for(h, b, b.floats_fwd), lds, a, st) != hipSuccess)
-      return check_device("sim_step launch");
-  }
-  return SIM_OK;
+    return launch_step(h->M, ts, b.team, grid_for(h, b, b.floats_fwd), lds, a, sx) == hipSuccess;
+  }, "sim_step launch");
 }
 
 sim_status rollout(sim_handle h, const float* x0, const float* u, float* loss_env, float* x_final,
@@ -264,15 +349,13 @@ sim_status rollout(sim_handle h, const float* x0, const float* u, float* loss_en
   if (s != SIM_OK) return s;
   hipStream_t st = (hipStream_t)stream;
   RolloutArgs a{x0, u, loss_env, x_final, lam_final, ckpt, env_flags};
-  for (size_t i = 0; i < h->buckets.size(); ++i) {
+  return run_buckets(h, st, [&](size_t i, hipStream_t sx) {
     const Bucket& b = h->buckets[i];
     TileSet ts{b.envs_dev, b.n_tiles, b.floats_fwd, h->d_queue + i};
-    if (launch_zero(ts.queue, 1, st) != hipSuccess) return check_device("rollout zero");
+    if (launch_zero(ts.queue, 1, sx) != hipSuccess) return false;
     const size_t lds = (size_t)(64 / b.team) * b.floats_fwd * 4;
-    if (launch_rollout(h->M, ts, b.team, grid_for(h, b, b.floats_fwd), lds, a, st) != hipSuccess)
-      return check_device("rollout launch");
-  }
-  return SIM_OK;
+    return launch_rollout(h->M, ts, b.team, grid_for(h, b, b.floats_fwd), lds, a, sx) == hipSuccess;
+  }, "rollout launch");
 }
 
 sim_status rollout_grad(sim_handle h, const float* x0, const float* u, const float* ckpt, const float* dloss_env,
@@ -289,15 +372,13 @@ sim_status rollout_grad(sim_handle h, const float* x0, const float* u, const flo
   if (s != SIM_OK) return s;
   hipStream_t st = (hipStream_t)stream;
   GradArgs a{x0, u, ckpt, dloss_env, g_x0, g_u, g_inv_mass, g_inv_inertia, g_mu, g_damping, (float*)workspace};
-  for (size_t i = 0; i < h->buckets.size(); ++i) {
+  return run_buckets(h, st, [&](size_t i, hipStream_t sx) {
     const Bucket& b = h->buckets[i];
     TileSet ts{b.envs_dev, b.n_tiles, b.floats_adj, h->d_queue + i};
-    if (launch_zero(ts.queue, 1, st) != hipSuccess) return check_device("rollout_grad zero");
+    if (launch_zero(ts.queue, 1, sx) != hipSuccess) return false;
     const size_t lds = (size_t)(64 / b.team) * b.floats_adj * 4;
-    if (launch_rollout_grad(h->M, ts, b.team, grid_for(h, b, b.floats_adj), lds, a, st) != hipSuccess)
-      return check_device("rollout_grad launch");
-  }
-  return SIM_OK;
+    return launch_rollout_grad(h->M, ts, b.team, grid_for(h, b, b.floats_adj), lds, a, sx) == hipSuccess;
+  }, "rollout_grad launch");
 }
 
 }  // extern "C"

@@ -28,8 +28,10 @@
 
 #if defined(__HIPCC__)
 #define SHD __host__ __device__ inline
+#define SHD_NOINLINE __host__ __device__ __attribute__((noinline))
 #else
 #define SHD inline
+#define SHD_NOINLINE inline
 #endif
 
 namespace sim {
@@ -63,6 +65,14 @@ SHD void add_outer(float* M, f3 a, f3 b) {
   M[6] += a.z * b.x; M[7] += a.z * b.y; M[8] += a.z * b.z;
 }
 
+// compensated accumulation: *sum += x, with the rounding error kept in *c
+SHD void kahan_add(float* sum, float* c, float x) {
+  const float y = x - *c;
+  const float t = *sum + y;
+  *c = (t - *sum) - y;
+  *sum = t;
+}
+
 // ------------------------------------------------------------------ model in global memory
 enum { H_B0, H_NB, H_J0, H_NJ, H_LAMOFF, H_LAMSZ, H_G, H_P, H_NCOL, H_TOPO, H_CST, H_T, H_LB, H_CCAP,
        H_NCAND, H_ENV, H_SEG, H_NSLOT, H_COUNT };
@@ -84,7 +94,12 @@ struct DevModel {
 // body record (forward)
 enum { BP = 0, BR = 3, BV = 12, BW = 15, BI = 18, BIM = 24, BII = 25, BTQ = 28, BPR = 31, BPO = 32, BS = 36 };
 // body record (adjoint)
-enum { AP = 0, AR = 3, AV = 12, AW = 15, AIW = 18, AIM = 27, AII = 28, ATQ = 31, AW0 = 34, BSA = 40 };
+// AIM/AII collect the current step's parameter adjoints; ATM/ATI hold the
+// running totals over the trajectory and ACM/ACI their compensation terms
+// (Kahan summation: a trajectory's parameter gradient is a long sum of terms
+// that largely cancel).
+enum { AP = 0, AR = 3, AV = 12, AW = 15, AIW = 18, AIM = 27, AII = 28, ATQ = 31, AW0 = 34,
+       ATM = 37, ATI = 38, ACM = 41, ACI = 42, BSA = 48 };
 // joint constants
 enum { JAP = 0, JAC = 3, JXP = 6, JXC = 9, JUP = 12, JUC = 15, JD = 18, JU = 19, JS = 20 };
 // row slot; a contact uses 4 slots: normal, tangent 1, tangent 2, extras
@@ -98,7 +113,7 @@ struct Lay {
   int bodyA, rowsA, hist, wsA, jA;                                        // adjoint
   int total_fwd, total;
 };
-enum { MISC_LOSS = 0, MISC_FLAGS = 1, MISC_NCON = 2, MISC_MU = 3, MISC_GMU = 4, MISC_N = 8 };
+enum { MISC_LOSS = 0, MISC_FLAGS = 1, MISC_NCON = 2, MISC_MU = 3, MISC_GMU = 4, MISC_GMUC = 5, MISC_N = 8 };
 
 SHD int align4(int x) { return (x + 3) & ~3; }
 SHD Lay make_lay(int nb, int nj, int G, int P, int ncol, int ncand, int nslot, int lam, int n_iters, bool adj) {
@@ -120,7 +135,7 @@ SHD Lay make_lay(int nb, int nj, int G, int P, int ncol, int ncand, int nslot, i
     L.rowsA = o; o += align4(nslot * RSA);
     L.hist = o; o += align4(n_iters * nslot);
     L.wsA = o; o += align4(lam);
-    L.jA = o; o += align4(nj);
+    L.jA = o; o += align4(2 * nj);   // damping adjoint total and compensation
   } else {
     L.bodyA = L.rowsA = L.hist = L.wsA = L.jA = o;
   }
@@ -209,7 +224,7 @@ SHD void load_env_static(const Team& tm, const DevModel& M, const Env& E) {
   if (tm.tl == 0) {
     E.misc()[MISC_MU] = E.gcst[cst_env(E)];
     E.misc()[MISC_LOSS] = 0.f;
-    ((int*)E.misc())[MISC_FLAGS] = 0;
+    (*reinterpret_cast<int*>(E.misc() + MISC_FLAGS)) = 0;
   }
 }
 
@@ -507,8 +522,8 @@ SHD void build_contact(const DevModel& M, const Env& E, int code, int s, const C
   x[XMT] = 2.f / (K[1] + K[2]);
   x[XGAP] = g.gap;
   const int st = E.store_of(code);
-  ((int*)x)[XSTORE] = st;
-  ((int*)x)[XCODE] = code;
+  *reinterpret_cast<int*>(x + XSTORE) = st;
+  *reinterpret_cast<int*>(x + XCODE) = code;
   float* rn = E.row(s);
   rn[RM] = 1.f / (K[0] + M.gamma);
   rn[RBI] = (g.gap > 0.f ? g.gap : M.beta * g.gap) / M.dt;
@@ -569,7 +584,7 @@ SHD void f_rows(const Team& tm, const DevModel& M, const Env& E, bool act) {
           E.act_slot()[li] = -1;
           float* w = E.ws() + E.store_of(code);
           w[0] = w[1] = w[2] = w[3] = 0.f;
-          ((int*)E.misc())[MISC_FLAGS] |= 2;
+          (*reinterpret_cast<int*>(E.misc() + MISC_FLAGS)) |= 2;
         }
       }
       cnt += total;
@@ -605,6 +620,112 @@ SHD void f_warm(const Team& tm, const Env& E, bool act) {
   }
 }
 
+// 16-byte vector for batched LDS access (ds_read_b128 / ds_write_b128)
+struct alignas(16) f4 { float x, y, z, w; };
+SHD f4 ld4(const float* p) { return *reinterpret_cast<const f4*>(p); }
+SHD void st4(float* p, f4 v) { *reinterpret_cast<f4*>(p) = v; }
+
+// Velocities of a constraint's two bodies in registers.
+struct VR { float va[3], wa[3], vb[3], wb[3]; };
+SHD void vr_load(VR& V, const Env& E, int a, int b) {
+  const float* Bb = E.body(b) + BV;   // v(3), w(3) contiguous, 16-byte aligned
+  const f4 q0 = ld4(Bb);
+  V.vb[0] = q0.x; V.vb[1] = q0.y; V.vb[2] = q0.z; V.wb[0] = q0.w; V.wb[1] = Bb[4]; V.wb[2] = Bb[5];
+  if (a >= 0) {
+    const float* Ba = E.body(a) + BV;
+    const f4 p0 = ld4(Ba);
+    V.va[0] = p0.x; V.va[1] = p0.y; V.va[2] = p0.z; V.wa[0] = p0.w; V.wa[1] = Ba[4]; V.wa[2] = Ba[5];
+  } else {
+    for (int k = 0; k < 3; ++k) { V.va[k] = 0.f; V.wa[k] = 0.f; }
+  }
+}
+SHD void vr_store(const VR& V, const Env& E, int a, int b) {
+  float* Bb = E.body(b) + BV;
+  f4 q0; q0.x = V.vb[0]; q0.y = V.vb[1]; q0.z = V.vb[2]; q0.w = V.wb[0];
+  st4(Bb, q0); Bb[4] = V.wb[1]; Bb[5] = V.wb[2];
+  if (a >= 0) {
+    float* Ba = E.body(a) + BV;
+    f4 p0; p0.x = V.va[0]; p0.y = V.va[1]; p0.z = V.va[2]; p0.w = V.wa[0];
+    st4(Ba, p0); Ba[4] = V.wa[1]; Ba[5] = V.wa[2];
+  }
+}
+// One row slot in registers: Jl, Ja, Jb, Wa, Wb, m, bias, lam (lam0 not needed).
+struct RR { float jl[3], ja[3], jb[3], wa[3], wb[3], m, bias, lam; };
+SHD void rr_load(RR& R, const float* p) {
+  const f4 a = ld4(p), b = ld4(p + 4), c = ld4(p + 8), d = ld4(p + 12), e = ld4(p + 16);
+  R.jl[0] = a.x; R.jl[1] = a.y; R.jl[2] = a.z; R.ja[0] = a.w;
+  R.ja[1] = b.x; R.ja[2] = b.y; R.jb[0] = b.z; R.jb[1] = b.w;
+  R.jb[2] = c.x; R.wa[0] = c.y; R.wa[1] = c.z; R.wa[2] = c.w;
+  R.wb[0] = d.x; R.wb[1] = d.y; R.wb[2] = d.z; R.m = d.w;
+  R.bias = e.x; R.lam = e.y;
+}
+SHD float rr_jv(const RR& R, const VR& V, bool ha) {
+  float s = R.jl[0] * V.vb[0] + R.jl[1] * V.vb[1] + R.jl[2] * V.vb[2];
+  s += R.jb[0] * V.wb[0] + R.jb[1] * V.wb[1] + R.jb[2] * V.wb[2];
+  if (ha) {
+    s -= R.jl[0] * V.va[0] + R.jl[1] * V.va[1] + R.jl[2] * V.va[2];
+    s += R.ja[0] * V.wa[0] + R.ja[1] * V.wa[1] + R.ja[2] * V.wa[2];
+  }
+  return s;
+}
+SHD void rr_apply(const RR& R, VR& V, bool ha, float ima, float imb, float d) {
+  const float cb = imb * d;
+  for (int k = 0; k < 3; ++k) { V.vb[k] += cb * R.jl[k]; V.wb[k] += d * R.wb[k]; }
+  if (ha) {
+    const float ca = ima * d;
+    for (int k = 0; k < 3; ++k) { V.va[k] -= ca * R.jl[k]; V.wa[k] += d * R.wa[k]; }
+  }
+}
+
+// One visit of a hinge (5 unbounded rows) with all data in registers.
+SHD void pgs_joint(const DevModel& M, const Env& E, int s, int a, int b, float* H) {
+  const bool ha = a >= 0;
+  VR V;
+  vr_load(V, E, a, b);
+  RR R[5];
+  for (int q = 0; q < 5; ++q) rr_load(R[q], E.row(s + q));
+  const float ima = ha ? E.body(a)[BIM] : 0.f, imb = E.body(b)[BIM];
+  for (int q = 0; q < 5; ++q) {
+    const float sv_ = rr_jv(R[q], V, ha) + R[q].bias + M.gamma * R[q].lam;
+    const float lt = R[q].lam - R[q].m * sv_;
+    if (H) H[s + q] = lt;
+    rr_apply(R[q], V, ha, ima, imb, lt - R[q].lam);
+    R[q].lam = lt;
+  }
+  for (int q = 0; q < 5; ++q) E.row(s + q)[RL] = R[q].lam;
+  vr_store(V, E, a, b);
+}
+
+// One visit of a contact: normal row clamped at 0, then the friction disk.
+SHD void pgs_contact(const DevModel& M, const Env& E, int s, int a, int b, float mu, float* H) {
+  const bool ha = a >= 0;
+  VR V;
+  vr_load(V, E, a, b);
+  RR R[3];
+  for (int q = 0; q < 3; ++q) rr_load(R[q], E.row(s + q));
+  const float mt = E.row(s + 3)[XMT];
+  const float ima = ha ? E.body(a)[BIM] : 0.f, imb = E.body(b)[BIM];
+  {
+    const float sv_ = rr_jv(R[0], V, ha) + R[0].bias + M.gamma * R[0].lam;
+    const float lt = R[0].lam - R[0].m * sv_;
+    const float ln = lt <= 0.f ? 0.f : lt;
+    if (H) H[s] = lt;
+    rr_apply(R[0], V, ha, ima, imb, ln - R[0].lam);
+    R[0].lam = ln;
+  }
+  const float l1 = R[1].lam - mt * rr_jv(R[1], V, ha);
+  const float l2 = R[2].lam - mt * rr_jv(R[2], V, ha);
+  float n1, n2;
+  disk(l1, l2, mu * R[0].lam, n1, n2);
+  if (H) { H[s + 1] = l1; H[s + 2] = l2; }
+  rr_apply(R[1], V, ha, ima, imb, n1 - R[1].lam);
+  rr_apply(R[2], V, ha, ima, imb, n2 - R[2].lam);
+  E.row(s)[RL] = R[0].lam;
+  E.row(s + 1)[RL] = n1;
+  E.row(s + 2)[RL] = n2;
+  vr_store(V, E, a, b);
+}
+
 // F6: projected Gauss-Seidel sweeps.  With rec, the pre-projection impulse of
 // every row update is recorded per iteration.
 template <class Team>
@@ -620,37 +741,8 @@ SHD void f_pgs(const Team& tm, const DevModel& M, const Env& E, bool act, bool r
         if (s < 0) continue;
         const int code = E.act_code()[lo + k];
         const RowB rb = cand_bodies(E, code);
-        const bool ha = rb.a >= 0;
-        const bool joint = cand_kind(code) == K_JOINT;
-        Vel V;
-        vel_load(V, E, rb.a, rb.b);
-        const float ima = ha ? E.body(rb.a)[BIM] : 0.f, imb = E.body(rb.b)[BIM];
-        const int nsc = joint ? 5 : 1;
-        for (int q = 0; q < nsc; ++q) {
-          float* r = E.row(s + q);
-          const float sv_ = row_jv(r, V.va, V.wa, V.vb, V.wb, ha) + r[RBI] + M.gamma * r[RL];
-          const float lt = r[RL] - r[RM] * sv_;
-          float ln = lt;
-          if (!joint && lt <= 0.f) ln = 0.f;
-          if (rec) H[s + q] = lt;
-          row_apply(r, V.va, V.wa, V.vb, V.wb, ha, ima, imb, ln - r[RL]);
-          r[RL] = ln;
-        }
-        if (!joint) {
-          float* r1 = E.row(s + 1);
-          float* r2 = E.row(s + 2);
-          const float mt = E.row(s + 3)[XMT];
-          const float l1 = r1[RL] - mt * row_jv(r1, V.va, V.wa, V.vb, V.wb, ha);
-          const float l2 = r2[RL] - mt * row_jv(r2, V.va, V.wa, V.vb, V.wb, ha);
-          float n1, n2;
-          disk(l1, l2, mu * E.row(s)[RL], n1, n2);
-          if (rec) { H[s + 1] = l1; H[s + 2] = l2; }
-          row_apply(r1, V.va, V.wa, V.vb, V.wb, ha, ima, imb, n1 - r1[RL]);
-          row_apply(r2, V.va, V.wa, V.vb, V.wb, ha, ima, imb, n2 - r2[RL]);
-          r1[RL] = n1;
-          r2[RL] = n2;
-        }
-        vel_store(V, E, rb.a, rb.b);
+        if (cand_kind(code) == K_JOINT) pgs_joint(M, E, s, rb.a, rb.b, H);
+        else pgs_contact(M, E, s, rb.a, rb.b, mu, H);
       }
       tm.sync();
     }
@@ -832,6 +924,7 @@ SHD void a_clear_step(const Team& tm, const Env& E, bool act) {
     float* A = E.bodyA(b);
     for (int k = 0; k < 9; ++k) A[AIW + k] = 0.f;
     A[ATQ] = A[ATQ + 1] = A[ATQ + 2] = 0.f;
+    A[AIM] = A[AII] = A[AII + 1] = A[AII + 2] = 0.f;
   }
 }
 
@@ -928,7 +1021,205 @@ SHD void a_integrate(const Team& tm, const DevModel& M, const Env& E, bool act) 
   tm.sync();
 }
 
-// B6: adjoint of the sweeps.
+// Row adjoint accumulators in registers (layout of a row adjoint slot).
+struct QR { float jl[3], ja[3], jb[3], wa[3], wb[3], m, b, l; };
+SHD void qr_load(QR& Q, const float* p) {
+  const f4 a = ld4(p), b = ld4(p + 4), c = ld4(p + 8), d = ld4(p + 12), e = ld4(p + 16);
+  Q.jl[0] = a.x; Q.jl[1] = a.y; Q.jl[2] = a.z; Q.ja[0] = a.w;
+  Q.ja[1] = b.x; Q.ja[2] = b.y; Q.jb[0] = b.z; Q.jb[1] = b.w;
+  Q.jb[2] = c.x; Q.wa[0] = c.y; Q.wa[1] = c.z; Q.wa[2] = c.w;
+  Q.wb[0] = d.x; Q.wb[1] = d.y; Q.wb[2] = d.z; Q.m = d.w;
+  Q.b = e.x; Q.l = e.y;
+}
+SHD void qr_store(const QR& Q, float* p) {
+  f4 a, b, c, d, e;
+  a.x = Q.jl[0]; a.y = Q.jl[1]; a.z = Q.jl[2]; a.w = Q.ja[0];
+  b.x = Q.ja[1]; b.y = Q.ja[2]; b.z = Q.jb[0]; b.w = Q.jb[1];
+  c.x = Q.jb[2]; c.y = Q.wa[0]; c.z = Q.wa[1]; c.w = Q.wa[2];
+  d.x = Q.wb[0]; d.y = Q.wb[1]; d.z = Q.wb[2]; d.w = Q.m;
+  e.x = Q.b; e.y = Q.l; e.z = 0.f; e.w = 0.f;
+  st4(p, a); st4(p + 4, b); st4(p + 8, c); st4(p + 12, d); st4(p + 16, e);
+}
+SHD void vra_load(VR& A, const Env& E, int a, int b) {
+  const float* Bb = E.bodyA(b) + AV;   // vbar(3), wbar(3) contiguous, 16-byte aligned
+  const f4 q0 = ld4(Bb);
+  A.vb[0] = q0.x; A.vb[1] = q0.y; A.vb[2] = q0.z; A.wb[0] = q0.w; A.wb[1] = Bb[4]; A.wb[2] = Bb[5];
+  if (a >= 0) {
+    const float* Ba = E.bodyA(a) + AV;
+    const f4 p0 = ld4(Ba);
+    A.va[0] = p0.x; A.va[1] = p0.y; A.va[2] = p0.z; A.wa[0] = p0.w; A.wa[1] = Ba[4]; A.wa[2] = Ba[5];
+  } else {
+    for (int k = 0; k < 3; ++k) { A.va[k] = 0.f; A.wa[k] = 0.f; }
+  }
+}
+SHD void vra_store(const VR& A, const Env& E, int a, int b) {
+  float* Bb = E.bodyA(b) + AV;
+  f4 q0; q0.x = A.vb[0]; q0.y = A.vb[1]; q0.z = A.vb[2]; q0.w = A.wb[0];
+  st4(Bb, q0); Bb[4] = A.wb[1]; Bb[5] = A.wb[2];
+  if (a >= 0) {
+    float* Ba = E.bodyA(a) + AV;
+    f4 p0; p0.x = A.va[0]; p0.y = A.va[1]; p0.z = A.va[2]; p0.w = A.wa[0];
+    st4(Ba, p0); Ba[4] = A.wa[1]; Ba[5] = A.wa[2];
+  }
+}
+// W . vbar through v += W d
+SHD float rr_wv(const RR& R, const VR& A, bool ha, float ima, float imb) {
+  float s = imb * (R.jl[0] * A.vb[0] + R.jl[1] * A.vb[1] + R.jl[2] * A.vb[2]);
+  s += R.wb[0] * A.wb[0] + R.wb[1] * A.wb[1] + R.wb[2] * A.wb[2];
+  if (ha) {
+    s -= ima * (R.jl[0] * A.va[0] + R.jl[1] * A.va[1] + R.jl[2] * A.va[2]);
+    s += R.wa[0] * A.wa[0] + R.wa[1] * A.wa[1] + R.wa[2] * A.wa[2];
+  }
+  return s;
+}
+// adjoint of W from v += W d (linear parts folded into Jl and the inverse masses)
+SHD void rr_wbar(QR& Q, const RR& R, const VR& A, bool ha, float ima, float imb, float d, float& imA, float& imB) {
+  for (int k = 0; k < 3; ++k) { Q.wb[k] += A.wb[k] * d; Q.jl[k] += imb * A.vb[k] * d; }
+  imB += d * (R.jl[0] * A.vb[0] + R.jl[1] * A.vb[1] + R.jl[2] * A.vb[2]);
+  if (ha) {
+    for (int k = 0; k < 3; ++k) { Q.wa[k] += A.wa[k] * d; Q.jl[k] -= ima * A.va[k] * d; }
+    imA -= d * (R.jl[0] * A.va[0] + R.jl[1] * A.va[1] + R.jl[2] * A.va[2]);
+  }
+}
+// vbar += J^T sb ; Jbar += sb v
+SHD void rr_jbar(QR& Q, const RR& R, VR& A, const VR& V, bool ha, float sb) {
+  for (int k = 0; k < 3; ++k) {
+    A.vb[k] += R.jl[k] * sb;
+    A.wb[k] += R.jb[k] * sb;
+    Q.jl[k] += sb * V.vb[k];
+    Q.jb[k] += sb * V.wb[k];
+  }
+  if (ha)
+    for (int k = 0; k < 3; ++k) {
+      A.va[k] -= R.jl[k] * sb;
+      A.wa[k] += R.ja[k] * sb;
+      Q.jl[k] -= sb * V.va[k];
+      Q.ja[k] += sb * V.wa[k];
+    }
+}
+// Reverse of one scalar row update; lt is the recorded pre-projection
+// impulse, lp the impulse before the update, unbounded for hinge rows.
+SHD void rev_scalar(const RR& R, QR& Q, VR& V, VR& A, bool ha, float ima, float imb, float lt, float lp,
+                    bool unbounded, float gamma, float& imA, float& imB) {
+  const float ln = unbounded ? lt : fmaxf(lt, 0.f);
+  const float d = ln - lp;
+  rr_apply(R, V, ha, ima, imb, -d);   // v before the update
+  rr_wbar(Q, R, A, ha, ima, imb, d, imA, imB);
+  const float wv = rr_wv(R, A, ha, ima, imb);
+  const float g = Q.l + wv;
+  const float ltb = (unbounded || lt > 0.f) ? g : 0.f;
+  const float sb = -R.m * ltb;
+  const float sval = rr_jv(R, V, ha) + R.bias + gamma * lp;
+  Q.m += -sval * ltb;
+  Q.b += sb;
+  rr_jbar(Q, R, A, V, ha, sb);
+  Q.l = -wv + ltb + gamma * sb;
+}
+
+// Reverse of one hinge visit (rows 4..0).  Row data and row adjoint
+// accumulators are streamed: row q-1 is loaded while row q is reversed.
+SHD void rev_joint(const DevModel& M, const Env& E, int s, int a, int b, const float* H, const float* Hp) {
+  const bool ha = a >= 0;
+  VR V, A;
+  vr_load(V, E, a, b);
+  vra_load(A, E, a, b);
+  const float ima = ha ? E.body(a)[BIM] : 0.f, imb = E.body(b)[BIM];
+  float imA = 0.f, imB = 0.f;
+  RR Rc;
+  QR Qc;
+  rr_load(Rc, E.row(s + 4));
+  qr_load(Qc, E.rowA(s + 4));
+  float ltc = H[s + 4], lpc = Hp ? Hp[s + 4] : E.row(s + 4)[RL0];
+  for (int q = 4; q >= 0; --q) {
+    RR Rn;
+    QR Qn;
+    float ltn = 0.f, lpn = 0.f;
+    if (q > 0) {
+      rr_load(Rn, E.row(s + q - 1));
+      qr_load(Qn, E.rowA(s + q - 1));
+      ltn = H[s + q - 1];
+      lpn = Hp ? Hp[s + q - 1] : E.row(s + q - 1)[RL0];
+    }
+    rev_scalar(Rc, Qc, V, A, ha, ima, imb, ltc, lpc, true, M.gamma, imA, imB);
+    qr_store(Qc, E.rowA(s + q));
+    if (q > 0) { Rc = Rn; Qc = Qn; ltc = ltn; lpc = lpn; }
+  }
+  vr_store(V, E, a, b);
+  vra_store(A, E, a, b);
+  if (ha) E.bodyA(a)[AIM] += imA;
+  E.bodyA(b)[AIM] += imB;
+}
+
+// Reverse of one contact visit: friction disk, then the normal row.
+SHD void rev_contact(const DevModel& M, const Env& E, int s, int a, int b, float mu, const float* H,
+                     const float* Hp, float& gmu) {
+  const bool ha = a >= 0;
+  VR V, A;
+  vr_load(V, E, a, b);
+  vra_load(A, E, a, b);
+  RR R1, R2;
+  QR Q1, Q2;
+  rr_load(R1, E.row(s + 1));
+  rr_load(R2, E.row(s + 2));
+  qr_load(Q1, E.rowA(s + 1));
+  qr_load(Q2, E.rowA(s + 2));
+  float* xa = E.rowA(s + 3);
+  const float mt = E.row(s + 3)[XMT];
+  const float ima = ha ? E.body(a)[BIM] : 0.f, imb = E.body(b)[BIM];
+  float imA = 0.f, imB = 0.f;
+  const float ltn = H[s], l1t = H[s + 1], l2t = H[s + 2];
+  const float ln = fmaxf(ltn, 0.f);
+  const float rho = mu * ln;
+  float n1, n2, p1, p2, lpn;
+  disk(l1t, l2t, rho, n1, n2);
+  if (Hp) {
+    lpn = fmaxf(Hp[s], 0.f);
+    disk(Hp[s + 1], Hp[s + 2], mu * lpn, p1, p2);
+  } else {
+    lpn = E.row(s)[RL0];
+    p1 = E.row(s + 1)[RL0];
+    p2 = E.row(s + 2)[RL0];
+  }
+  const float d1 = n1 - p1, d2 = n2 - p2;
+  rr_apply(R2, V, ha, ima, imb, -d2);
+  rr_apply(R1, V, ha, ima, imb, -d1);
+  rr_wbar(Q1, R1, A, ha, ima, imb, d1, imA, imB);
+  rr_wbar(Q2, R2, A, ha, ima, imb, d2, imA, imB);
+  const float wv1 = rr_wv(R1, A, ha, ima, imb);
+  const float wv2 = rr_wv(R2, A, ha, ima, imb);
+  const float g1 = Q1.l + wv1, g2 = Q2.l + wv2;
+  const float nrm = sqrtf(l1t * l1t + l2t * l2t);
+  float tb1 = g1, tb2 = g2, lnb = 0.f;
+  if (!(nrm <= rho)) {
+    const float u1 = l1t / nrm, u2 = l2t / nrm, sc = rho / nrm;
+    const float ug = u1 * g1 + u2 * g2;
+    tb1 = sc * (g1 - u1 * ug);
+    tb2 = sc * (g2 - u2 * ug);
+    gmu += ug * ln;
+    lnb = ug * mu;   // adjoint of this iteration's normal impulse
+  }
+  const float jv1 = rr_jv(R1, V, ha), jv2 = rr_jv(R2, V, ha);
+  xa[XMT] += -(tb1 * jv1 + tb2 * jv2);
+  rr_jbar(Q1, R1, A, V, ha, -mt * tb1);
+  rr_jbar(Q2, R2, A, V, ha, -mt * tb2);
+  Q1.l = -wv1 + tb1;
+  Q2.l = -wv2 + tb2;
+  qr_store(Q1, E.rowA(s + 1));
+  qr_store(Q2, E.rowA(s + 2));
+  RR R0;
+  QR Q0;
+  rr_load(R0, E.row(s));
+  qr_load(Q0, E.rowA(s));
+  Q0.l += lnb;
+  rev_scalar(R0, Q0, V, A, ha, ima, imb, ltn, lpn, false, M.gamma, imA, imB);
+  qr_store(Q0, E.rowA(s));
+  vr_store(V, E, a, b);
+  vra_store(A, E, a, b);
+  if (ha) E.bodyA(a)[AIM] += imA;
+  E.bodyA(b)[AIM] += imB;
+}
+
+// B6: adjoint of the sweeps (iterations, colours and rows exactly reversed).
 template <class Team>
 SHD void a_pgs(const Team& tm, const DevModel& M, const Env& E, bool act) {
   const float mu = E.misc()[MISC_MU];
@@ -944,102 +1235,15 @@ SHD void a_pgs(const Team& tm, const DevModel& M, const Env& E, bool act) {
         if (s < 0) continue;
         const int code = E.act_code()[lo + k];
         const RowB rb = cand_bodies(E, code);
-        const bool ha = rb.a >= 0;
-        const bool joint = cand_kind(code) == K_JOINT;
-        Vel V;
-        vel_load(V, E, rb.a, rb.b);
-        VelA A;
-        vela_load(A, E, rb.a, rb.b);
-        float imA = 0.f, imB = 0.f;
-        const float ima = ha ? E.body(rb.a)[BIM] : 0.f, imb = E.body(rb.b)[BIM];
-        // impulses after this iteration's update (proj of H) and before (proj of Hp or init)
-        if (!joint) {
-          // friction block (last in forward, first here)
-          const float* r1 = E.row(s + 1);
-          const float* r2 = E.row(s + 2);
-          float* q1 = E.rowA(s + 1);
-          float* q2 = E.rowA(s + 2);
-          const float mt = E.row(s + 3)[XMT];
-          const float ln = fmaxf(H[s], 0.f);
-          const float rho = mu * ln;
-          const float l1t = H[s + 1], l2t = H[s + 2];
-          float n1, n2;
-          disk(l1t, l2t, rho, n1, n2);
-          float p1, p2;
-          if (Hp) {
-            const float rhop = mu * fmaxf(Hp[s], 0.f);
-            disk(Hp[s + 1], Hp[s + 2], rhop, p1, p2);
-          } else {
-            p1 = r1[RL0]; p2 = r2[RL0];
-          }
-          const float d1 = n1 - p1, d2 = n2 - p2;
-          // reconstruct v before the block
-          row_unapply(r2, V, ha, ima, imb, d2);
-          row_unapply(r1, V, ha, ima, imb, d1);
-          // W bar and g = lambda'bar + W.vbar
-          row_wbar(q1, r1, A, ha, ima, imb, d1, &imA, &imB);
-          row_wbar(q2, r2, A, ha, ima, imb, d2, &imA, &imB);
-          const float wv1 = row_wvbar(r1, A, ha, ima, imb);
-          const float wv2 = row_wvbar(r2, A, ha, ima, imb);
-          const float g1 = q1[QL] + wv1, g2 = q2[QL] + wv2;
-          float lb1 = -wv1, lb2 = -wv2;
-          const float nrm = sqrtf(l1t * l1t + l2t * l2t);
-          float tb1, tb2;
-          if (nrm <= rho) { tb1 = g1; tb2 = g2; }
-          else {
-            const float u1 = l1t / nrm, u2 = l2t / nrm, sc = rho / nrm;
-            const float ug = u1 * g1 + u2 * g2;
-            tb1 = sc * (g1 - u1 * ug);
-            tb2 = sc * (g2 - u2 * ug);
-            const float rhob = ug;
-            gmu += rhob * ln;
-            E.rowA(s)[QL] += rhob * mu;   // adjoint of the normal impulse of this iteration
-          }
-          lb1 += tb1; lb2 += tb2;
-          // lt = l - mt (J v)
-          const float jv1 = row_jv(r1, V.va, V.wa, V.vb, V.wb, ha);
-          const float jv2 = row_jv(r2, V.va, V.wa, V.vb, V.wb, ha);
-          E.rowA(s + 3)[XMT] += -(tb1 * jv1 + tb2 * jv2);
-          row_jbar(q1, r1, A, V, ha, -mt * tb1);
-          row_jbar(q2, r2, A, V, ha, -mt * tb2);
-          q1[QL] = lb1;
-          q2[QL] = lb2;
-        }
-        const int nsc = joint ? 5 : 1;
-        for (int q = nsc - 1; q >= 0; --q) {
-          const float* r = E.row(s + q);
-          float* qa = E.rowA(s + q);
-          const float lt = H[s + q];
-          const float ln = joint ? lt : fmaxf(lt, 0.f);
-          float lp;
-          if (Hp) lp = joint ? Hp[s + q] : fmaxf(Hp[s + q], 0.f);
-          else lp = r[RL0];
-          const float d = ln - lp;
-          row_unapply(r, V, ha, ima, imb, d);
-          row_wbar(qa, r, A, ha, ima, imb, d, &imA, &imB);
-          const float wv = row_wvbar(r, A, ha, ima, imb);
-          const float g = qa[QL] + wv;
-          const bool free_ = joint || lt > 0.f;
-          const float ltb = free_ ? g : 0.f;
-          const float sb = -r[RM] * ltb;
-          // s = J v + bias + gamma lp
-          const float sval = row_jv(r, V.va, V.wa, V.vb, V.wb, ha) + r[RBI] + M.gamma * lp;
-          qa[QM] += -sval * ltb;
-          qa[QB] += sb;
-          row_jbar(qa, r, A, V, ha, sb);
-          qa[QL] = -wv + ltb + M.gamma * sb;
-        }
-        vel_store(V, E, rb.a, rb.b);
-        vela_store(A, E, rb.a, rb.b);
-        if (ha) E.bodyA(rb.a)[AIM] += imA;
-        E.bodyA(rb.b)[AIM] += imB;
+        if (cand_kind(code) == K_JOINT) rev_joint(M, E, s, rb.a, rb.b, H, Hp);
+        else rev_contact(M, E, s, rb.a, rb.b, mu, H, Hp, gmu);
       }
       tm.sync();
     }
   }
   // friction coefficient adjoint (one lane per team holds it after a reduction)
   float tot = tm.team_sum(gmu);
-  if (tm.tl == 0 && act) E.misc()[MISC_GMU] += tot;
+  if (tm.tl == 0 && act) kahan_add(E.misc() + MISC_GMU, E.misc() + MISC_GMUC, tot);
   tm.sync();
 }
 
@@ -1312,7 +1516,7 @@ SHD void a_predict_torques(const Team& tm, const DevModel& M, const Env& E, bool
       const float taub = dot(n, tqd);
       f3 nb_ = tau * tqd - (taub * dmp) * wrel;
       if (g_u_row) g_u_row[E.j0 + j] = taub;
-      E.jA()[j] += -taub * dot(wrel, n);
+      kahan_add(E.jA() + j, E.jA() + E.nj + j, -taub * dot(wrel, n));
       add3(Ab + AW, -(taub * dmp) * n);
       if (a >= 0) {
         float* Aa = E.bodyA(a);
@@ -1344,6 +1548,8 @@ SHD void a_predict_torques(const Team& tm, const DevModel& M, const Env& E, bool
         for (int j = 0; j < 3; ++j) acc += R[3 * i + k] * G[3 * i + j] * R[3 * j + k];
       A[AII + k] += acc;
     }
+    kahan_add(A + ATM, A + ACM, A[AIM]);
+    for (int k = 0; k < 3; ++k) kahan_add(A + ATI + k, A + ACI + k, A[AII + k]);
   }
   tm.sync();
 }

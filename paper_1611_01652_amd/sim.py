@@ -36,7 +36,7 @@ class SimDesc(C.Structure):
         ("T_max", C.c_int32), ("dt", C.c_float), ("gravity", C.c_float * 3),
         ("beta", C.c_float), ("gamma", C.c_float), ("spec_margin", C.c_float), ("warm", C.c_float),
         ("n_iters", C.c_int32), ("ground", C.c_int32), ("loss_kind", C.c_int32), ("loss_mask", C.c_int32),
-        ("ckpt_every", C.c_int32),
+        ("ckpt_every", C.c_int32), ("min_team", C.c_int32),
     ]
 
 
@@ -92,6 +92,7 @@ def make_desc(w):
     d.beta, d.gamma, d.spec_margin, d.warm = w.beta, w.gamma, w.spec_margin, w.warm
     d.n_iters, d.ground, d.loss_kind, d.loss_mask = w.n_iters, w.ground, w.loss_kind, w.loss_mask
     d.ckpt_every = w.ckpt_every
+    d.min_team = int(getattr(w, 'min_team', 0) or 0)
     return d, keep
 
 
@@ -116,6 +117,8 @@ def library():
     lib.sim_step.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
     lib.rollout.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp]
     lib.rollout_grad.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, C.c_size_t, vp]
+    lib.sim_describe_order.argtypes = [C.POINTER(SimDesc), C.c_int32, _I32P, _I32P, C.c_int32]
+    lib.sim_describe_order.restype = C.c_int32
     for fn in ("sim_init", "sim_destroy", "sim_get_info", "sim_lambda_offsets", "sim_step", "rollout",
                "rollout_grad"):
         getattr(lib, fn).restype = C.c_int
@@ -124,7 +127,20 @@ def library():
 
 
 EXPORTED = ["sim_abi_version", "sim_last_error", "sim_init", "sim_destroy", "sim_get_info",
-            "sim_lambda_offsets", "sim_step", "rollout", "rollout_grad"]
+            "sim_lambda_offsets", "sim_describe_order", "sim_step", "rollout", "rollout_grad"]
+
+
+def describe_order(w, env):
+    """Canonical sweep order of one env as computed by the library (host only)."""
+    lib = library()
+    d, keep = make_desc(w)
+    cap = 1 << 16
+    codes = np.zeros(cap, np.int32)
+    cols = np.zeros(cap, np.int32)
+    n = lib.sim_describe_order(C.byref(d), env, codes.ctypes.data_as(_I32P), cols.ctypes.data_as(_I32P), cap)
+    if n < 0:
+        raise SimError(f"sim_describe_order failed ({n}): {lib.sim_last_error().decode()}")
+    return codes[:n].copy(), cols[:n].copy()
 
 
 class SimError(RuntimeError):
