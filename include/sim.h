@@ -76,6 +76,12 @@ typedef enum {
 #define SIM_LOSS_MEAN_DIST 1     /* (1/T_e) sum_{t=1..T_e} |mask*(p(t) - target)|          */
 #define SIM_LOSS_NEG_MEAN_VELX 2 /* -(p_x(T_e) - p_x(0)) / (T_e dt)  (mean forward speed) */
 
+/* control kinds (eq. (g) of section 2.2 without the recurrent state) */
+#define SIM_CTRL_TAPE 0 /* open-loop torques u[T_max][J] */
+#define SIM_CTRL_MLP 1  /* u^t = g(s(x^t)) shared by all envs: s = [joint angles (J_e), joint rates
+                           (J_e), sin, cos of 2 pi f t dt]; tanh hidden layers, linear output (J_e);
+                           weights W1[h1][in] b1 W2[h2][h1] b2 W3[out][h2] b3 */
+
 /* Model description (host memory, read during sim_init; the caller keeps
  * ownership).  Indices of bodies/joints/spheres are global (over all envs),
  * and each env's items must lie inside its own CSR range. */
@@ -118,6 +124,10 @@ typedef struct {
   int32_t ckpt_every;            /* K_ck: rollout stores the state every K_ck steps */
   int32_t min_team;              /* 0: automatic; else lanes per env are at least this
                                     (power of two <= 64).  Results do not depend on it. */
+  int32_t ctrl_kind;             /* SIM_CTRL_* */
+  int32_t mlp_sizes[4];          /* in, h1, h2, out; every env has out = J_e, in = 2 J_e + 2;
+                                    h1, h2 <= 256 */
+  float clock_hz;                /* clock frequency f of the controller inputs */
 } sim_model_desc;
 
 /* Sizes derived by sim_init. */
@@ -129,6 +139,7 @@ typedef struct {
   int64_t workspace_bytes;    /* device workspace needed by rollout_grad */
   int32_t max_lds_bytes;      /* largest LDS allocation per workgroup among the tiles */
   int32_t n_tiles;            /* env tiles scheduled per rollout */
+  int32_t n_params;           /* controller parameters (0 for a control tape) */
 } sim_info;
 
 int sim_abi_version(void);
@@ -155,15 +166,17 @@ sim_status sim_lambda_offsets(sim_handle h, int32_t* lam_off);
 int32_t sim_describe_order(const sim_model_desc* desc, int32_t env, int32_t* codes, int32_t* colours,
                            int32_t cap);
 
-/* One step for all envs: x_out = f_ph(x_in, u) at step index t (device
- * pointers, x[18][B], u[J], lambda[lam_size]).  lam_in may equal lam_out;
- * x_in must not alias x_out.  env_flags[E] (device, may be NULL) is
- * overwritten. */
+/* One step for all envs: x_out = f_ph(x_in, u) (device pointers, x[18][B],
+ * u[J] torques or, for SIM_CTRL_MLP, the controller weights [n_params];
+ * lambda[lam_size]).  t is the step index (it selects the clock input of a
+ * controller; 0 <= t < T_max then).  lam_in may equal lam_out; x_in must not
+ * alias x_out.  env_flags[E] (device, may be NULL) is overwritten. */
 sim_status sim_step(sim_handle h, const float* x_in, float* x_out, const float* u, const float* lam_in,
-                    float* lam_out, uint32_t* env_flags, void* stream);
+                    float* lam_out, int32_t t, uint32_t* env_flags, void* stream);
 
 /* Forward rollout from x0 (device, x[18][B]) with the control tape u
- * (device, [T_max][J]); warm-start impulses start at zero.  Writes
+ * (device, [T_max][J]) or, for SIM_CTRL_MLP, the controller weights
+ * (device, [n_params]); warm-start impulses start at zero.  Writes
  * loss_env[E] (device), x_final[18][B] (device, may be NULL), lam_final
  * (device, may be NULL), the checkpoint buffer ckpt (device, sim_info
  * .ckpt_floats floats, may be NULL when no gradient will be asked for) and
@@ -173,10 +186,14 @@ sim_status rollout(sim_handle h, const float* x0, const float* u, float* loss_en
 
 /* Reverse mode.  Given the checkpoints written by `rollout` with the same
  * x0 and u, and dL/dloss_env (device [E]), writes (each may be NULL):
- *   g_x0[18][B], g_u[T_max][J] (entries beyond an env's T_e are zero),
- *   g_inv_mass[B], g_inv_inertia[B][3], g_mu[E], g_damping[J]   (device).
+ *   g_x0[18][B], g_u[T_max][J] (entries beyond an env's T_e are zero) or,
+ *   for SIM_CTRL_MLP, dL/dW [n_params] summed over envs (the paper's dL/dW,
+ *   section 2.2), g_inv_mass[B], g_inv_inertia[B][3], g_mu[E], g_damping[J]
+ *   (device).
  * workspace: device scratch of at least sim_info.workspace_bytes (the
- * per-env segment buffer of the checkpoint recompute). */
+ * per-env segment buffer of the checkpoint recompute and, with a controller,
+ * the per env-step activations and deltas plus the split-K partial sums of
+ * the weight-gradient contraction). */
 sim_status rollout_grad(sim_handle h, const float* x0, const float* u, const float* ckpt,
                         const float* dloss_env, float* g_x0, float* g_u, float* g_inv_mass,
                         float* g_inv_inertia, float* g_mu, float* g_damping, void* workspace,

@@ -123,6 +123,8 @@ class Oracle:
         m.gravity = (C.c_double * 3)(*w.gravity)
         m.beta, m.gamma, m.spec_margin = w.beta, w.gamma, w.spec_margin
         m.n_iters, m.ground, m.loss_kind, m.loss_mask = w.n_iters, w.ground, w.loss_kind, w.loss_mask
+        if mlp is None and getattr(w, 'extra', None):
+            mlp = w.extra.get('mlp')
         if mlp is not None:
             m.ctrl_kind = 1
             m.mlp_in, m.mlp_h1, m.mlp_h2, m.mlp_out = mlp["sizes"]

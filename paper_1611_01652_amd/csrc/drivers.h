@@ -36,10 +36,11 @@ struct GradArgs {
 struct StepArgs {
   const float* x_in;
   float* x_out;
-  const float* u;      // [J]
+  const float* u;      // [J] (null with a controller)
   const float* lam_in;
   float* lam_out;
   uint32_t* flags;
+  int t;               // step index (clock input of a controller)
 };
 
 SHD size_t ckpt_stride(const DevModel& M) { return (size_t)18 * M.B + M.lam_tot; }
@@ -66,7 +67,7 @@ SHD uint32_t nonfinite_flag(const Team& tm, const Env& E) {
 }
 
 template <class Team>
-SHD void env_rollout(const Team& tm, const DevModel& M, const Env& E, bool valid, const RolloutArgs& a) {
+SHD_FLAT void env_rollout(const Team& tm, const DevModel& M, const Env& E, bool valid, const RolloutArgs& a) {
   if (valid) {
     load_env_static(tm, M, E);
     load_state(tm, E, a.x0, M.B);
@@ -81,7 +82,7 @@ SHD void env_rollout(const Team& tm, const DevModel& M, const Env& E, bool valid
     const bool act = t < T;
     if (act && a.ckpt && t % K == 0) write_ckpt(tm, M, E, a.ckpt + (size_t)(t / K) * ckpt_stride(M));
     tm.sync();
-    env_step(tm, M, E, a.u ? a.u + (size_t)t * M.J : nullptr, act);
+    env_step(tm, M, E, (a.u && !M.ctrl) ? a.u + (size_t)t * M.J : nullptr, act, t);
     if (act && tm.tl == 0) {
       const float* p = E.body(E.lb) + BP;
       const float p0[3] = {p0x, 0.f, 0.f};
@@ -102,14 +103,14 @@ SHD void env_rollout(const Team& tm, const DevModel& M, const Env& E, bool valid
 }
 
 template <class Team>
-SHD void env_single_step(const Team& tm, const DevModel& M, const Env& E, bool valid, const StepArgs& a) {
+SHD_FLAT void env_single_step(const Team& tm, const DevModel& M, const Env& E, bool valid, const StepArgs& a) {
   if (valid) {
     load_env_static(tm, M, E);
     load_state(tm, E, a.x_in, M.B);
     load_ws(tm, E, a.lam_in);
   }
   tm.sync();
-  env_step(tm, M, E, a.u, valid);
+  env_step(tm, M, E, a.u, valid, a.t);
   tm.sync();
   uint32_t fl = valid ? nonfinite_flag(tm, E) : 0u;
   if (valid) {
@@ -142,7 +143,7 @@ SHD void loss_adj(const DevModel& M, const Env& E, int t1, const float* p, float
 }
 
 template <class Team>
-SHD void env_rollout_grad(const Team& tm, const DevModel& M, const Env& E, bool valid, const GradArgs& a) {
+SHD_FLAT void env_rollout_grad(const Team& tm, const DevModel& M, const Env& E, bool valid, const GradArgs& a) {
   if (valid) {
     load_env_static(tm, M, E);
     for (int i = tm.tl; i < E.nb * BSA; i += tm.ts) E.L[E.lay.bodyA + i] = 0.f;
@@ -158,7 +159,7 @@ SHD void env_rollout_grad(const Team& tm, const DevModel& M, const Env& E, bool 
   const int sstride = 18 * (valid ? E.nb : 0) + (valid ? E.lam_size : 0);
   float* seg = valid ? a.seg + E.seg_off : nullptr;
   // zero the control gradient rows beyond T (and all rows of idle envs)
-  if (valid && a.g_u)
+  if (valid && a.g_u && !M.ctrl)
     for (int t = T; t < M.T_max; ++t)
       for (int j = tm.tl; j < E.nj; j += tm.ts) a.g_u[(size_t)t * M.J + E.j0 + j] = 0.f;
   for (int sg = nseg - 1; tm.any(sg >= 0); --sg) {
@@ -176,7 +177,7 @@ SHD void env_rollout_grad(const Team& tm, const DevModel& M, const Env& E, bool 
         for (int i = tm.tl; i < E.lam_size; i += tm.ts) dst[18 * E.nb + i] = E.ws()[i];
       }
       tm.sync();
-      env_step(tm, M, E, a.u ? a.u + (size_t)t * M.J : nullptr, act);
+      env_step(tm, M, E, (a.u && !M.ctrl) ? a.u + (size_t)t * M.J : nullptr, act, t);
     }
     tm.sync();
     if (sact && sg == nseg - 1 && tm.tl == 0 && M.loss_kind != 1)
@@ -192,7 +193,7 @@ SHD void env_rollout_grad(const Team& tm, const DevModel& M, const Env& E, bool 
       }
       tm.sync();
       // replay step t with recording (no integration, no store)
-      f_controls(tm, M, E, a.u ? a.u + (size_t)t * M.J : nullptr, act);
+      f_controls(tm, M, E, (a.u && !M.ctrl) ? a.u + (size_t)t * M.J : nullptr, act, t);
       f_body_setup(tm, E, act, true);
       tm.sync();
       f_torques(tm, E, act);
@@ -214,7 +215,8 @@ SHD void env_rollout_grad(const Team& tm, const DevModel& M, const Env& E, bool 
       a_pgs(tm, M, E, act);
       a_warm(tm, M, E, act);
       a_rows(tm, M, E, act);
-      a_predict_torques(tm, M, E, act, (act && a.g_u) ? a.g_u + (size_t)t * M.J : nullptr, nullptr);
+      a_predict_torques(tm, M, E, act, (act && a.g_u && !M.ctrl) ? a.g_u + (size_t)t * M.J : nullptr, nullptr);
+      a_controller(tm, M, E, act, t);
     }
     tm.sync();
   }

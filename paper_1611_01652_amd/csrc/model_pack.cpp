@@ -188,8 +188,15 @@ sim_status build_env(const sim_model_desc& d, int e, HostEnv& H) {
   H.cst[8 * H.nb + JS * H.nj + 4 * H.G] = d.mu[e];
   // team size: enough lanes for the widest joint colour and half the bodies
   H.team = std::min(64, next_pow2(std::max({1, max_col, (H.nb + 1) / 2})));
-  H.fwd_floats = make_lay(H.nb, H.nj, H.G, H.P, H.ncol, H.ncand, H.nslot, H.lam, d.n_iters, false).total;
-  H.adj_floats = make_lay(H.nb, H.nj, H.G, H.P, H.ncol, H.ncand, H.nslot, H.lam, d.n_iters, true).total;
+  int mf = 0, ma = 0;
+  if (d.ctrl_kind == 1) {
+    if (d.mlp_sizes[3] != H.nj || d.mlp_sizes[0] != 2 * H.nj + 2)
+      return fail(SIM_E_SHAPE, "env " + std::to_string(e) + ": controller needs out = joints and in = 2 joints + 2");
+    mf = d.mlp_sizes[0] + d.mlp_sizes[1] + d.mlp_sizes[2];
+    ma = d.mlp_sizes[3] + d.mlp_sizes[2] + d.mlp_sizes[1] + d.mlp_sizes[0];
+  }
+  H.fwd_floats = make_lay(H.nb, H.nj, H.G, H.P, H.ncol, H.ncand, H.nslot, H.lam, d.n_iters, false, mf, ma).total;
+  H.adj_floats = make_lay(H.nb, H.nj, H.G, H.P, H.ncol, H.ncand, H.nslot, H.lam, d.n_iters, true, mf, ma).total;
   return SIM_OK;
 }
 
@@ -207,6 +214,13 @@ sim_status pack_model(const sim_model_desc* d, PackedModel& P, std::string& err)
   P.fwd_of.assign(E, 0);
   P.adj_of.assign(E, 0);
   P.seg_total = 0;
+  P.tape_rows = 0;
+  if (d->ctrl_kind != 0 && d->ctrl_kind != 1) { g_msg = nullptr; err = "unknown ctrl_kind"; return SIM_E_ARG; }
+  if (d->ctrl_kind == 1) {
+    for (int k = 0; k < 4; ++k)
+      if (d->mlp_sizes[k] <= 0) { g_msg = nullptr; err = "controller sizes must be > 0"; return SIM_E_ARG; }
+    if (d->mlp_sizes[1] > 256 || d->mlp_sizes[2] > 256) { g_msg = nullptr; err = "controller hidden width > 256"; return SIM_E_UNSUPPORTED; }
+  }
   for (int e = 0; e < E; ++e) {
     HostEnv H;
     const sim_status st = build_env(*d, e, H);
@@ -217,6 +231,8 @@ sim_status pack_model(const sim_model_desc* d, PackedModel& P, std::string& err)
     hd[H_TOPO] = (int)P.topo.size(); hd[H_CST] = (int)P.cst.size(); hd[H_T] = d->T_env[e];
     hd[H_LB] = d->loss_body[e] - d->env_body_off[e]; hd[H_CCAP] = H.ccap; hd[H_NCAND] = H.ncand;
     hd[H_ENV] = e; hd[H_SEG] = (int)P.seg_total; hd[H_NSLOT] = H.nslot;
+    hd[H_TAPE] = (int)P.tape_rows;
+    if (d->ctrl_kind == 1) P.tape_rows += d->T_env[e];
     P.seg_total += (long long)d->ckpt_every * (18 * H.nb + H.lam);
     if (P.seg_total > 0x7fffffffLL) { g_msg = nullptr; err = "segment buffer exceeds 2^31 floats"; return SIM_E_UNSUPPORTED; }
     P.topo.insert(P.topo.end(), H.topo.begin(), H.topo.end());

@@ -12,6 +12,7 @@ struct PackedModel {
   std::vector<int> hdr, topo, lam_off, team_of, fwd_of, adj_of;
   std::vector<float> cst, target;
   long long seg_total = 0;
+  long long tape_rows = 0;   // env-steps of the controller tape (sum of T_e)
 };
 
 // Validates the per-env parts of the description and builds, per env, the

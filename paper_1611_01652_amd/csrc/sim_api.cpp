@@ -51,6 +51,12 @@ struct sim_model {
   std::vector<hipStream_t> streams;  // one per bucket when there are several
   std::vector<hipEvent_t> joins;
   hipEvent_t fork = nullptr;
+  // controller
+  float* d_clock = nullptr;
+  WgradTile* d_tiles = nullptr;
+  int* d_map = nullptr;
+  int n_wtiles = 0, n_params = 0, chunk = 2048;
+  long long tape_rows = 0, seg_floats = 0, tape_floats = 0;
 };
 
 namespace {
@@ -73,6 +79,9 @@ void release(sim_model* h) {
   if (h->d_cst) (void)hipFree(h->d_cst);
   if (h->d_target) (void)hipFree(h->d_target);
   if (h->d_queue) (void)hipFree(h->d_queue);
+  if (h->d_clock) (void)hipFree(h->d_clock);
+  if (h->d_tiles) (void)hipFree(h->d_tiles);
+  if (h->d_map) (void)hipFree(h->d_map);
   for (auto sx : h->streams) (void)hipStreamDestroy(sx);
   for (auto ex : h->joins) (void)hipEventDestroy(ex);
   if (h->fork) (void)hipEventDestroy(h->fork);
@@ -125,6 +134,7 @@ sim_status sim_init(const sim_model_desc* d, sim_handle* out) {
   *out = nullptr;
   const int E = d->n_envs;
   if (E < 0) return fail(SIM_E_ARG, "n_envs < 0");
+  if (d->ctrl_kind == 1 && d->T_max > 0 && !(d->clock_hz == d->clock_hz)) return fail(SIM_E_ARG, "clock_hz is NaN");
   if (!d->env_body_off || !d->env_joint_off || !d->env_sphere_off)
     return fail(SIM_E_ARG, "null CSR offsets");
   if (d->env_body_off[0] != 0 || d->env_joint_off[0] != 0 || d->env_sphere_off[0] != 0)
@@ -253,6 +263,49 @@ sim_status sim_init(const sim_model_desc* d, sim_handle* out) {
     release(h);
     return st;
   }
+  // controller: clock table, weight-gradient tiles and parameter map
+  if (d->ctrl_kind == 1) {
+    const int in = d->mlp_sizes[0], n1 = d->mlp_sizes[1], n2 = d->mlp_sizes[2], no = d->mlp_sizes[3];
+    M.ctrl = 1; M.mlp_in = in; M.mlp_h1 = n1; M.mlp_h2 = n2; M.mlp_out = no;
+    M.tape_stride = tape_len(in, n1, n2, no);
+    std::vector<float> clock(2 * (size_t)std::max(d->T_max, 1));
+    for (int t = 0; t < d->T_max; ++t) {
+      const double ph = 2.0 * M_PI * (double)d->clock_hz * (double)t * (double)d->dt;
+      clock[2 * t] = (float)std::sin(ph);
+      clock[2 * t + 1] = (float)std::cos(ph);
+    }
+    if ((st = upload(&h->d_clock, clock)) != SIM_OK) { release(h); return st; }
+    M.clock = h->d_clock;
+    // layers: (delta offset, rows, activation offset, columns, weight offset, bias offset)
+    const int lay[3][6] = {{tape_d1(M), n1, tape_s(M), in, 0, n1 * in},
+                           {tape_d2(M), n2, tape_h1(M), n1, n1 * in + n1, n1 * in + n1 + n2 * n1},
+                           {tape_du(M), no, tape_h2(M), n2, n1 * in + n1 + n2 * n1 + n2,
+                            n1 * in + n1 + n2 * n1 + n2 + no * n2}};
+    h->n_params = n1 * in + n1 + n2 * n1 + n2 + no * n2 + no;
+    std::vector<WgradTile> tiles;
+    std::vector<int> map(h->n_params, 0);
+    for (int l = 0; l < 3; ++l) {
+      const int Mr = lay[l][1], Kc = lay[l][3];
+      for (int i0 = 0; i0 < Mr; i0 += 32)
+        for (int k0 = 0; k0 <= Kc; k0 += 32) {
+          const int tid = (int)tiles.size();
+          tiles.push_back({lay[l][0], lay[l][2], Mr, Kc, i0, k0});
+          for (int i = i0; i < std::min(Mr, i0 + 32); ++i)
+            for (int k = k0; k <= std::min(Kc, k0 + 31); ++k) {
+              const int p = k < Kc ? lay[l][4] + i * Kc + k : lay[l][5] + i;
+              map[p] = tid * 1024 + (i - i0) * 32 + (k - k0);
+            }
+        }
+    }
+    h->n_wtiles = (int)tiles.size();
+    if ((st = upload(&h->d_tiles, tiles)) != SIM_OK || (st = upload(&h->d_map, map)) != SIM_OK) {
+      release(h);
+      return st;
+    }
+  }
+  h->tape_rows = P.tape_rows;
+  h->seg_floats = (P.seg_total + 63) & ~63LL;
+  h->tape_floats = M.ctrl ? ((P.tape_rows * M.tape_stride + 63) & ~63LL) : 0;
   if (max_lds > 65536 && allow_large_lds(std::min(max_lds, h->max_lds)) != hipSuccess) {
     release(h);
     return fail(SIM_E_DEVICE, "cannot raise the dynamic LDS limit");
@@ -262,7 +315,12 @@ sim_status sim_init(const sim_model_desc* d, sim_handle* out) {
   I.n_envs = E; I.n_bodies = B; I.n_joints = J; I.lam_size = M.lam_tot;
   I.n_ckpt = d->T_max > 0 ? (d->T_max - 1) / d->ckpt_every + 1 : 1;
   I.ckpt_floats = (int64_t)I.n_ckpt * (18LL * B + M.lam_tot);
-  I.workspace_bytes = 4LL * std::max<long long>(seg_total, 1);
+  {
+    const long long n_chunks = M.ctrl ? (h->tape_rows + h->chunk - 1) / h->chunk : 0;
+    I.workspace_bytes = 4LL * (std::max<long long>(h->seg_floats, 1) + h->tape_floats +
+                               n_chunks * h->n_wtiles * 1024LL);
+  }
+  I.n_params = h->n_params;
   I.max_lds_bytes = max_lds;
   I.n_tiles = 0;
   for (auto& b : h->buckets) I.n_tiles += b.n_tiles;
@@ -320,7 +378,7 @@ sim_status sim_lambda_offsets(sim_handle h, int32_t* lam_off) {
 }
 
 sim_status sim_step(sim_handle h, const float* x_in, float* x_out, const float* u, const float* lam_in,
-                    float* lam_out, uint32_t* env_flags, void* stream) {
+                    float* lam_out, int32_t t, uint32_t* env_flags, void* stream) {
   if (!h) return fail(SIM_E_ARG, "sim_step: null handle");
   if (h->M.n_envs == 0) return SIM_OK;
   if (!x_in || !x_out || (h->M.lam_tot > 0 && (!lam_in || !lam_out)) || (h->M.J > 0 && !u))
@@ -328,14 +386,17 @@ sim_status sim_step(sim_handle h, const float* x_in, float* x_out, const float* 
   if (x_in == x_out) return fail(SIM_E_ARG, "sim_step: x_in must not alias x_out");
   sim_status s = check_device("sim_step (earlier fault)");
   if (s != SIM_OK) return s;
+  if (t < 0 || (h->M.ctrl && t >= std::max(h->M.T_max, 1))) return fail(SIM_E_ARG, "sim_step: step index out of range");
   hipStream_t st = (hipStream_t)stream;
-  StepArgs a{x_in, x_out, u, lam_in, lam_out, env_flags};
+  StepArgs a{x_in, x_out, h->M.ctrl ? nullptr : u, lam_in, lam_out, env_flags, t};
+  DevModel M = h->M;
+  M.W = u;
   return run_buckets(h, st, [&](size_t i, hipStream_t sx) {
     const Bucket& b = h->buckets[i];
     TileSet ts{b.envs_dev, b.n_tiles, b.floats_fwd, h->d_queue + i};
     if (launch_zero(ts.queue, 1, sx) != hipSuccess) return false;
     const size_t lds = (size_t)(64 / b.team) * b.floats_fwd * 4;
-    return launch_step(h->M, ts, b.team, grid_for(h, b, b.floats_fwd), lds, a, sx) == hipSuccess;
+    return launch_step(M, ts, b.team, grid_for(h, b, b.floats_fwd), lds, a, sx) == hipSuccess;
   }, "sim_step launch");
 }
 
@@ -349,12 +410,14 @@ sim_status rollout(sim_handle h, const float* x0, const float* u, float* loss_en
   if (s != SIM_OK) return s;
   hipStream_t st = (hipStream_t)stream;
   RolloutArgs a{x0, u, loss_env, x_final, lam_final, ckpt, env_flags};
+  DevModel M = h->M;
+  M.W = u;
   return run_buckets(h, st, [&](size_t i, hipStream_t sx) {
     const Bucket& b = h->buckets[i];
     TileSet ts{b.envs_dev, b.n_tiles, b.floats_fwd, h->d_queue + i};
     if (launch_zero(ts.queue, 1, sx) != hipSuccess) return false;
     const size_t lds = (size_t)(64 / b.team) * b.floats_fwd * 4;
-    return launch_rollout(h->M, ts, b.team, grid_for(h, b, b.floats_fwd), lds, a, sx) == hipSuccess;
+    return launch_rollout(M, ts, b.team, grid_for(h, b, b.floats_fwd), lds, a, sx) == hipSuccess;
   }, "rollout launch");
 }
 
@@ -371,14 +434,24 @@ sim_status rollout_grad(sim_handle h, const float* x0, const float* u, const flo
   sim_status s = check_device("rollout_grad (earlier fault)");
   if (s != SIM_OK) return s;
   hipStream_t st = (hipStream_t)stream;
-  GradArgs a{x0, u, ckpt, dloss_env, g_x0, g_u, g_inv_mass, g_inv_inertia, g_mu, g_damping, (float*)workspace};
-  return run_buckets(h, st, [&](size_t i, hipStream_t sx) {
+  float* ws = (float*)workspace;
+  GradArgs a{x0, u, ckpt, dloss_env, g_x0, g_u, g_inv_mass, g_inv_inertia, g_mu, g_damping, ws};
+  DevModel M = h->M;
+  M.W = u;
+  M.tape = ws + h->seg_floats;
+  s = run_buckets(h, st, [&](size_t i, hipStream_t sx) {
     const Bucket& b = h->buckets[i];
     TileSet ts{b.envs_dev, b.n_tiles, b.floats_adj, h->d_queue + i};
     if (launch_zero(ts.queue, 1, sx) != hipSuccess) return false;
     const size_t lds = (size_t)(64 / b.team) * b.floats_adj * 4;
-    return launch_rollout_grad(h->M, ts, b.team, grid_for(h, b, b.floats_adj), lds, a, sx) == hipSuccess;
+    return launch_rollout_grad(M, ts, b.team, grid_for(h, b, b.floats_adj), lds, a, sx) == hipSuccess;
   }, "rollout_grad launch");
+  if (s != SIM_OK || !M.ctrl || !g_u) return s;
+  // dL/dW: contraction of the per env-step deltas and activations
+  if (launch_wgrad(M.tape, M.tape_stride, (int)h->tape_rows, h->chunk, h->d_tiles, h->n_wtiles,
+                   M.tape + h->tape_floats, h->d_map, h->n_params, g_u, st) != hipSuccess)
+    return check_device("rollout_grad weight gradient");
+  return SIM_OK;
 }
 
 }  // extern "C"

@@ -14,7 +14,16 @@ struct TileSet {
   int* queue;        // device counter of the persistent tile queue
 };
 
+// One 32x32 output tile of the controller's weight-gradient contraction:
+// rows i0.. of delta (M rows valid) against columns k0.. of the activations
+// (K columns valid, column K is the bias).
+struct WgradTile {
+  int a_off, b_off, M, K, i0, k0;
+};
+
 hipError_t launch_zero(int* p, int n, hipStream_t st);
+hipError_t launch_wgrad(const float* tape, int stride, int n_rows, int chunk, const WgradTile* tiles, int n_tiles,
+                        float* partial, const int* map, int n_params, float* g, hipStream_t st);
 hipError_t launch_rollout(const DevModel& M, const TileSet& ts, int team, int grid, size_t lds,
                           const RolloutArgs& a, hipStream_t st);
 hipError_t launch_step(const DevModel& M, const TileSet& ts, int team, int grid, size_t lds, const StepArgs& a,

@@ -91,6 +91,71 @@ __global__ __launch_bounds__(64) void k_rollout_grad(DevModel M, TileSet ts, Gra
   }
 }
 
+// Weight gradient of the controller as a contraction over env-steps:
+//   dW_l[i][k] = sum_n delta_l[n][i] * act_l[n][k],  db_l[i] = sum_n delta_l[n][i]
+// (act_1 = s, act_2 = h1, act_3 = h2; delta_1 = d1, delta_2 = d2, delta_3 = du).
+// One wave computes one 32x32 output tile of one layer over one chunk of
+// env-steps with v_mfma_f32_32x32x2f32 (A = delta rows, B = activations with
+// an all-ones column for the bias), and writes the partial tile; the chunks
+// are summed in a fixed order by k_wgrad_reduce (no atomics).
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+__global__ __launch_bounds__(64) void k_wgrad_mfma(const float* __restrict__ tape, int stride, int n_rows, int chunk,
+                                                   const WgradTile* __restrict__ tiles, int n_tiles,
+                                                   float* __restrict__ partial) {
+  const int tile = blockIdx.x, c = blockIdx.y, lane = threadIdx.x;
+  const WgradTile T = tiles[tile];
+  const int li = lane & 31, lk = lane >> 5;
+  const int i = T.i0 + li, j = T.k0 + li;
+  const bool ia = i < T.M;
+  const bool jb = j < T.K;
+  const float one = (j == T.K) ? 1.f : 0.f;
+  const int n0 = c * chunk;
+  const int n1 = min(n_rows, n0 + chunk);
+  floatx16 acc;
+  for (int r = 0; r < 16; ++r) acc[r] = 0.f;
+  for (int n = n0; n < n1; n += 2) {
+    const int row = n + lk;
+    float a = 0.f, b = 0.f;
+    if (row < n1) {
+      const float* rp = tape + (size_t)row * stride;
+      a = ia ? rp[T.a_off + i] : 0.f;
+      b = jb ? rp[T.b_off + j] : one;
+    }
+    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc, 0, 0, 0);
+  }
+  // D[row][col], col = lane % 32, row = 8 (r / 4) + 4 (lane / 32) + r % 4
+  float* out = partial + ((size_t)c * n_tiles + tile) * 1024;
+  for (int r = 0; r < 16; ++r) {
+    const int row = 8 * (r >> 2) + 4 * lk + (r & 3);
+    out[row * 32 + li] = acc[r];
+  }
+}
+
+__global__ void k_wgrad_reduce(const float* __restrict__ partial, int n_chunks, int n_tiles,
+                               const int* __restrict__ map, int n_params, float* __restrict__ g) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n_params) return;
+  const int m = map[p];
+  float acc = 0.f, comp = 0.f;
+  for (int c = 0; c < n_chunks; ++c) kahan_add(&acc, &comp, partial[(size_t)c * n_tiles * 1024 + m]);
+  g[p] = acc;
+}
+
+hipError_t launch_wgrad(const float* tape, int stride, int n_rows, int chunk, const WgradTile* tiles, int n_tiles,
+                        float* partial, const int* map, int n_params, float* g, hipStream_t st) {
+  const int n_chunks = (n_rows + chunk - 1) / chunk;
+  if (n_chunks > 0) {
+    hipLaunchKernelGGL(k_wgrad_mfma, dim3(n_tiles, n_chunks), dim3(64), 0, st, tape, stride, n_rows, chunk, tiles,
+                       n_tiles, partial);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_wgrad_reduce, dim3((n_params + 255) / 256), dim3(256), 0, st, partial, n_chunks, n_tiles,
+                     map, n_params, g);
+  return hipGetLastError();
+}
+
 __global__ void k_zero_ints(int* p, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0;

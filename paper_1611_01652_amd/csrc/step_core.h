@@ -29,9 +29,14 @@
 #if defined(__HIPCC__)
 #define SHD __host__ __device__ inline
 #define SHD_NOINLINE __host__ __device__ __attribute__((noinline))
+// The per-env drivers are inlined into their kernels: as real calls they keep
+// the caller's live state in a stack frame (hundreds of bytes of scratch per
+// lane).
+#define SHD_FLAT __host__ __device__ inline __attribute__((always_inline))
 #else
 #define SHD inline
 #define SHD_NOINLINE inline
+#define SHD_FLAT inline
 #endif
 
 namespace sim {
@@ -75,7 +80,7 @@ SHD void kahan_add(float* sum, float* c, float x) {
 
 // ------------------------------------------------------------------ model in global memory
 enum { H_B0, H_NB, H_J0, H_NJ, H_LAMOFF, H_LAMSZ, H_G, H_P, H_NCOL, H_TOPO, H_CST, H_T, H_LB, H_CCAP,
-       H_NCAND, H_ENV, H_SEG, H_NSLOT, H_COUNT };
+       H_NCAND, H_ENV, H_SEG, H_NSLOT, H_TAPE, H_COUNT };
 // candidate code: kind in the top byte
 enum { K_JOINT = 0, K_GROUND = 1, K_PAIR = 2 };
 SHD int cand_kind(int c) { return c >> 24; }
@@ -88,7 +93,20 @@ struct DevModel {
   const int* topo;    // per-env topology ints
   const float* cst;   // per-env constants
   const float* target;// [E][3]
+  // controller (ctrl == 1): u = MLP(s(x)), weights W shared by all envs
+  int ctrl, mlp_in, mlp_h1, mlp_h2, mlp_out, tape_stride;
+  const float* clock; // [T_max][2] sin, cos of 2 pi f t dt
+  const float* W;     // weights (set per call)
+  float* tape;        // per env-step activations and deltas (reverse only)
 };
+// tape row: s, h1, h2, du, d2, d1 (pre-activation adjoints)
+SHD int tape_s(const DevModel&) { return 0; }
+SHD int tape_h1(const DevModel& M) { return M.mlp_in; }
+SHD int tape_h2(const DevModel& M) { return M.mlp_in + M.mlp_h1; }
+SHD int tape_du(const DevModel& M) { return M.mlp_in + M.mlp_h1 + M.mlp_h2; }
+SHD int tape_d2(const DevModel& M) { return tape_du(M) + M.mlp_out; }
+SHD int tape_d1(const DevModel& M) { return tape_d2(M) + M.mlp_h2; }
+SHD int tape_len(int in, int h1, int h2, int out) { return (in + 2 * h1 + 2 * h2 + out + 3) & ~3; }
 
 // ------------------------------------------------------------------ LDS layout
 // body record (forward)
@@ -109,14 +127,16 @@ enum { XT1 = 0, XT2 = 3, XMT = 6, XGAP = 7, XSTORE = 8, XCODE = 9 };
 enum { QJL = 0, QJA = 3, QJB = 6, QWA = 9, QWB = 12, QM = 15, QB = 16, QL = 17, RSA = 20 };
 
 struct Lay {
-  int body, jc, gs, topo, ws, rows, act_cnt, act_slot, act_code, misc;   // forward
-  int bodyA, rowsA, hist, wsA, jA;                                        // adjoint
+  int body, jc, gs, topo, ws, rows, act_cnt, act_slot, act_code, misc, mlp;  // forward
+  int bodyA, rowsA, hist, wsA, jA, mlpA;                                     // adjoint
   int total_fwd, total;
 };
 enum { MISC_LOSS = 0, MISC_FLAGS = 1, MISC_NCON = 2, MISC_MU = 3, MISC_GMU = 4, MISC_GMUC = 5, MISC_N = 8 };
 
 SHD int align4(int x) { return (x + 3) & ~3; }
-SHD Lay make_lay(int nb, int nj, int G, int P, int ncol, int ncand, int nslot, int lam, int n_iters, bool adj) {
+// mlp_f / mlp_a: controller floats per env (s, h1, h2 / du, d2, d1, sbar), 0 without one
+SHD Lay make_lay(int nb, int nj, int G, int P, int ncol, int ncand, int nslot, int lam, int n_iters, bool adj,
+                 int mlp_f = 0, int mlp_a = 0) {
   Lay L;
   int o = 0;
   L.body = o; o += align4(nb * BS);
@@ -129,6 +149,7 @@ SHD Lay make_lay(int nb, int nj, int G, int P, int ncol, int ncand, int nslot, i
   L.act_slot = o; o += align4(ncand);
   L.act_code = o; o += align4(ncand);
   L.misc = o; o += MISC_N;
+  L.mlp = o; o += align4(mlp_f);
   L.total_fwd = o;
   if (adj) {
     L.bodyA = o; o += align4(nb * BSA);
@@ -136,8 +157,9 @@ SHD Lay make_lay(int nb, int nj, int G, int P, int ncol, int ncand, int nslot, i
     L.hist = o; o += align4(n_iters * nslot);
     L.wsA = o; o += align4(lam);
     L.jA = o; o += align4(2 * nj);   // damping adjoint total and compensation
+    L.mlpA = o; o += align4(mlp_a);
   } else {
-    L.bodyA = L.rowsA = L.hist = L.wsA = L.jA = o;
+    L.bodyA = L.rowsA = L.hist = L.wsA = L.jA = L.mlpA = o;
   }
   L.total = o;
   return L;
@@ -145,7 +167,7 @@ SHD Lay make_lay(int nb, int nj, int G, int P, int ncol, int ncand, int nslot, i
 
 // ------------------------------------------------------------------ env view
 struct Env {
-  int b0, nb, j0, nj, lam_off, lam_size, G, P, ncol, T, lb, ccap, ncand, e, nslot, seg_off;
+  int b0, nb, j0, nj, lam_off, lam_size, G, P, ncol, T, lb, ccap, ncand, e, nslot, seg_off, tape_off;
   const int* gtopo;   // global topology of the env
   const float* gcst;  // global constants of the env
   float* L;           // LDS base of the env
@@ -172,6 +194,8 @@ struct Env {
   SHD int* act_code() const { return (int*)(L + lay.act_code); }
   SHD float* misc() const { return L + lay.misc; }
   SHD float* jA() const { return L + lay.jA; }
+  SHD float* mlp() const { return L + lay.mlp; }
+  SHD float* mlpA() const { return L + lay.mlpA; }
   // warm-start store offset of a candidate
   SHD int store_of(int code) const {
     const int k = cand_kind(code), i = cand_idx(code);
@@ -181,17 +205,21 @@ struct Env {
   }
 };
 
+SHD int mlp_floats_fwd(const DevModel& M) { return M.ctrl ? M.mlp_in + M.mlp_h1 + M.mlp_h2 : 0; }
+SHD int mlp_floats_adj(const DevModel& M) { return M.ctrl ? M.mlp_out + M.mlp_h2 + M.mlp_h1 + M.mlp_in : 0; }
+
 SHD Env make_env(const DevModel& M, int ie, float* lds, int n_iters, bool adj) {
   const int* h = M.hdr + (size_t)ie * H_COUNT;
   Env E;
   E.b0 = h[H_B0]; E.nb = h[H_NB]; E.j0 = h[H_J0]; E.nj = h[H_NJ];
   E.lam_off = h[H_LAMOFF]; E.lam_size = h[H_LAMSZ]; E.G = h[H_G]; E.P = h[H_P]; E.ncol = h[H_NCOL];
   E.T = h[H_T]; E.lb = h[H_LB]; E.ccap = h[H_CCAP]; E.ncand = h[H_NCAND]; E.e = h[H_ENV];
-  E.nslot = h[H_NSLOT]; E.seg_off = h[H_SEG];
+  E.nslot = h[H_NSLOT]; E.seg_off = h[H_SEG]; E.tape_off = h[H_TAPE];
   E.gtopo = M.topo + h[H_TOPO];
   E.gcst = M.cst + h[H_CST];
   E.L = lds;
-  E.lay = make_lay(E.nb, E.nj, E.G, E.P, E.ncol, E.ncand, E.nslot, E.lam_size, n_iters, adj);
+  E.lay = make_lay(E.nb, E.nj, E.G, E.P, E.ncol, E.ncand, E.nslot, E.lam_size, n_iters, adj, mlp_floats_fwd(M),
+                   mlp_floats_adj(M));
   return E;
 }
 
@@ -803,11 +831,76 @@ SHD void f_store(const Team& tm, const Env& E, bool act) {
   tm.sync();
 }
 
-// Controls of this step into the joint records (tape row t).
+// Joint sensor of the controller: hinge angle (from the perpendicular unit
+// vectors of the two frames, about the parent's axis) and hinge rate.
+struct Sensor { f3 na, ua, ub, wrel; float y, x; };
+SHD Sensor joint_sensor(const Env& E, int j, const float* wa_src, const float* wb_src) {
+  const float* C = E.jc(j);
+  const int a = E.jpar(j), b = E.jchi(j);
+  Sensor S;
+  S.na = ld3(C + JXP);
+  S.ua = ld3(C + JUP);
+  f3 wa = mk3(0.f, 0.f, 0.f);
+  if (a >= 0) {
+    S.na = mv(E.body(a) + BR, S.na);
+    S.ua = mv(E.body(a) + BR, S.ua);
+    wa = ld3(wa_src == nullptr ? E.body(a) + BW : wa_src);
+  }
+  S.ub = mv(E.body(b) + BR, ld3(C + JUC));
+  S.wrel = ld3(wb_src == nullptr ? E.body(b) + BW : wb_src) - wa;
+  S.y = dot(cross(S.ua, S.ub), S.na);
+  S.x = dot(S.ua, S.ub);
+  return S;
+}
+
+// Controls of step t into the joint records: the tape row, or the
+// controller evaluated on x^t (eq. (g) without the recurrent state).
 template <class Team>
-SHD void f_controls(const Team& tm, const DevModel& M, const Env& E, const float* u_row, bool act) {
+SHD void f_controls(const Team& tm, const DevModel& M, const Env& E, const float* u_row, bool act, int t = 0) {
   const int nj = act ? E.nj : 0;
-  for (int j = tm.tl; j < nj; j += tm.ts) E.jc(j)[JU] = u_row ? u_row[E.j0 + j] : 0.f;
+  if (!M.ctrl) {
+    for (int j = tm.tl; j < nj; j += tm.ts) E.jc(j)[JU] = u_row ? u_row[E.j0 + j] : 0.f;
+    return;
+  }
+  float* sv_ = E.mlp();
+  float* h1 = sv_ + M.mlp_in;
+  float* h2 = h1 + M.mlp_h1;
+  for (int j = tm.tl; j < nj; j += tm.ts) {
+    const Sensor S = joint_sensor(E, j, nullptr, nullptr);
+    sv_[j] = atan2f(S.y, S.x);
+    sv_[E.nj + j] = dot(S.wrel, S.na);
+  }
+  if (act && tm.tl == 0) {
+    sv_[2 * E.nj] = M.clock[2 * t];
+    sv_[2 * E.nj + 1] = M.clock[2 * t + 1];
+  }
+  tm.sync();
+  const int in = M.mlp_in, n1 = M.mlp_h1, n2 = M.mlp_h2;
+  const float* W1 = M.W;
+  const float* b1 = W1 + n1 * in;
+  const float* W2 = b1 + n1;
+  const float* b2 = W2 + n2 * n1;
+  const float* W3 = b2 + n2;
+  const float* b3 = W3 + M.mlp_out * n2;
+  for (int i = tm.tl; i < (act ? n1 : 0); i += tm.ts) {
+    float a = b1[i];
+    for (int k = 0; k < in; ++k) a += W1[i * in + k] * sv_[k];
+    h1[i] = tanhf(a);
+  }
+  tm.sync();
+  for (int i = tm.tl; i < (act ? n2 : 0); i += tm.ts) {
+    float a = b2[i];
+    const float* w = W2 + i * n1;
+    for (int k = 0; k < n1; ++k) a += w[k] * h1[k];
+    h2[i] = tanhf(a);
+  }
+  tm.sync();
+  for (int i = tm.tl; i < nj; i += tm.ts) {
+    float a = b3[i];
+    const float* w = W3 + i * n2;
+    for (int k = 0; k < n2; ++k) a += w[k] * h2[k];
+    E.jc(i)[JU] = a;
+  }
 }
 
 // Loss term of the state after step t (1-based) for the loss body.
@@ -832,8 +925,8 @@ SHD float loss_term(const DevModel& M, const Env& E, int t1, const float* p, con
 
 // One full forward step (no recording): x^t (LDS) -> x^{t+1} (LDS).
 template <class Team>
-SHD void env_step(const Team& tm, const DevModel& M, const Env& E, const float* u_row, bool act) {
-  f_controls(tm, M, E, u_row, act);
+SHD void env_step(const Team& tm, const DevModel& M, const Env& E, const float* u_row, bool act, int t = 0) {
+  f_controls(tm, M, E, u_row, act, t);
   f_body_setup(tm, E, act, false);
   tm.sync();
   f_torques(tm, E, act);
@@ -1515,7 +1608,8 @@ SHD void a_predict_torques(const Team& tm, const DevModel& M, const Env& E, bool
       const float tau = C[JU] - dmp * dot(wrel, n);
       const float taub = dot(n, tqd);
       f3 nb_ = tau * tqd - (taub * dmp) * wrel;
-      if (g_u_row) g_u_row[E.j0 + j] = taub;
+      if (M.ctrl) E.mlpA()[j] = taub;
+      else if (g_u_row) g_u_row[E.j0 + j] = taub;
       kahan_add(E.jA() + j, E.jA() + E.nj + j, -taub * dot(wrel, n));
       add3(Ab + AW, -(taub * dmp) * n);
       if (a >= 0) {
@@ -1552,6 +1646,85 @@ SHD void a_predict_torques(const Team& tm, const DevModel& M, const Env& E, bool
     for (int k = 0; k < 3; ++k) kahan_add(A + ATI + k, A + ACI + k, A[AII + k]);
   }
   tm.sync();
+}
+
+// Adjoint of the controller of step t: layer deltas (written with the
+// activations to the env-step tape for the weight-gradient contraction) and
+// the adjoint of the sensors into the state adjoint of x^t.
+template <class Team>
+SHD void a_controller(const Team& tm, const DevModel& M, const Env& E, bool act, int t) {
+  if (!M.ctrl) return;
+  const int in = M.mlp_in, n1 = M.mlp_h1, n2 = M.mlp_h2, no = M.mlp_out;
+  const float* sv_ = E.mlp();
+  const float* h1 = sv_ + in;
+  const float* h2 = h1 + n1;
+  float* du = E.mlpA();
+  float* d2 = du + no;
+  float* d1 = d2 + n2;
+  float* sb = d1 + n1;
+  const float* W1 = M.W;
+  const float* W2 = W1 + n1 * in + n1;
+  const float* W3 = W2 + n2 * n1 + n2;
+  tm.sync();
+  for (int k = tm.tl; k < (act ? n2 : 0); k += tm.ts) {
+    float g = 0.f;
+    for (int i = 0; i < no; ++i) g += W3[i * n2 + k] * du[i];
+    d2[k] = g * (1.f - h2[k] * h2[k]);
+  }
+  tm.sync();
+  for (int k = tm.tl; k < (act ? n1 : 0); k += tm.ts) {
+    float g = 0.f;
+    for (int i = 0; i < n2; ++i) g += W2[i * n1 + k] * d2[i];
+    d1[k] = g * (1.f - h1[k] * h1[k]);
+  }
+  tm.sync();
+  for (int k = tm.tl; k < (act ? in : 0); k += tm.ts) {
+    float g = 0.f;
+    for (int i = 0; i < n1; ++i) g += W1[i * in + k] * d1[i];
+    sb[k] = g;
+  }
+  if (act) {
+    float* row = M.tape + (size_t)(E.tape_off + t) * M.tape_stride;
+    const int len = tape_d1(M) + n1;
+    for (int k = tm.tl; k < len; k += tm.ts) {
+      float v;
+      if (k < tape_du(M)) v = sv_[k];                 // s, h1, h2 are contiguous in LDS
+      else v = du[k - tape_du(M)];                    // du, d2, d1 are contiguous in LDS
+      row[k] = v;
+    }
+  }
+  tm.sync();
+  // sensors: theta = atan2(y, x), y = (ua x ub).na, x = ua.ub ; rate = wrel.na
+  for (int c = 0; tm.any(c < E.ncol && act); ++c) {
+    int lo = 0, hi = 0;
+    if (act && c < E.ncol) {
+      lo = E.colstart(c); hi = E.colstart(c + 1);
+      if (lo >= E.nj || cand_kind(E.cand(lo)) != K_JOINT) hi = lo;
+    }
+    for (int i = lo + tm.tl; i < hi; i += tm.ts) {
+      const int j = cand_idx(E.cand(i));
+      const int a = E.jpar(j), b = E.jchi(j);
+      const Sensor S = joint_sensor(E, j, a >= 0 ? E.bodyA(a) + AW0 : nullptr, E.bodyA(b) + AW0);
+      const float thb = sb[j], rb = sb[E.nj + j];
+      const float r2 = S.x * S.x + S.y * S.y;
+      const float yb = r2 > 0.f ? thb * S.x / r2 : 0.f;
+      const float xb = r2 > 0.f ? -thb * S.y / r2 : 0.f;
+      const f3 uab = yb * cross(S.ub, S.na) + xb * S.ub;
+      const f3 ubb = yb * cross(S.na, S.ua) + xb * S.ua;
+      const f3 nab = yb * cross(S.ua, S.ub) + rb * S.wrel;
+      const float* C = E.jc(j);
+      float* Ab = E.bodyA(b);
+      add3(Ab + AW, rb * S.na);
+      add_outer(Ab + AR, ubb, ld3(C + JUC));
+      if (a >= 0) {
+        float* Aa = E.bodyA(a);
+        add3(Aa + AW, -(rb * S.na));
+        add_outer(Aa + AR, uab, ld3(C + JUP));
+        add_outer(Aa + AR, nab, ld3(C + JXP));
+      }
+    }
+    tm.sync();
+  }
 }
 
 }  // namespace sim

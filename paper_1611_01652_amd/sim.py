@@ -37,6 +37,7 @@ class SimDesc(C.Structure):
         ("beta", C.c_float), ("gamma", C.c_float), ("spec_margin", C.c_float), ("warm", C.c_float),
         ("n_iters", C.c_int32), ("ground", C.c_int32), ("loss_kind", C.c_int32), ("loss_mask", C.c_int32),
         ("ckpt_every", C.c_int32), ("min_team", C.c_int32),
+        ("ctrl_kind", C.c_int32), ("mlp_sizes", C.c_int32 * 4), ("clock_hz", C.c_float),
     ]
 
 
@@ -45,7 +46,7 @@ class SimInfo(C.Structure):
         ("n_envs", C.c_int32), ("n_bodies", C.c_int32), ("n_joints", C.c_int32),
         ("lam_size", C.c_int32), ("n_ckpt", C.c_int32),
         ("ckpt_floats", C.c_int64), ("workspace_bytes", C.c_int64),
-        ("max_lds_bytes", C.c_int32), ("n_tiles", C.c_int32),
+        ("max_lds_bytes", C.c_int32), ("n_tiles", C.c_int32), ("n_params", C.c_int32),
     ]
 
 
@@ -93,6 +94,11 @@ def make_desc(w):
     d.n_iters, d.ground, d.loss_kind, d.loss_mask = w.n_iters, w.ground, w.loss_kind, w.loss_mask
     d.ckpt_every = w.ckpt_every
     d.min_team = int(getattr(w, 'min_team', 0) or 0)
+    mlp = w.extra.get("mlp") if getattr(w, "extra", None) else None
+    if mlp is not None:
+        d.ctrl_kind = 1
+        d.mlp_sizes = (C.c_int32 * 4)(*[int(v) for v in mlp["sizes"]])
+        d.clock_hz = float(mlp.get("clock_hz", 1.5))
     return d, keep
 
 
@@ -114,7 +120,7 @@ def library():
     lib.sim_destroy.argtypes = [vp]
     lib.sim_get_info.argtypes = [vp, C.POINTER(SimInfo)]
     lib.sim_lambda_offsets.argtypes = [vp, _I32P]
-    lib.sim_step.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.sim_step.argtypes = [vp, vp, vp, vp, vp, vp, C.c_int32, vp, vp]
     lib.rollout.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp]
     lib.rollout_grad.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, C.c_size_t, vp]
     lib.sim_describe_order.argtypes = [C.POINTER(SimDesc), C.c_int32, _I32P, _I32P, C.c_int32]
@@ -217,24 +223,29 @@ class Simulator:
     def rollout_grad(self, x0, u, ckpt, dloss, workspace=None):
         E, B, J = self.info.n_envs, self.info.n_bodies, self.info.n_joints
         ws = workspace if workspace is not None else self.workspace()
-        g = dict(g_x0=self._f32(18 * B).view(18, -1), g_u=self._f32(self.w.T_max * J),
+        nu = self.info.n_params if self.info.n_params else self.w.T_max * J
+        g = dict(g_x0=self._f32(18 * B).view(18, -1), g_u=self._f32(nu),
                  g_inv_mass=self._f32(B), g_inv_inertia=self._f32(3 * B), g_mu=self._f32(E), g_damping=self._f32(J))
         st = self.lib.rollout_grad(self.h, _ptr(x0), _ptr(u), _ptr(ckpt), _ptr(dloss), _ptr(g["g_x0"]),
                                    _ptr(g["g_u"]), _ptr(g["g_inv_mass"]), _ptr(g["g_inv_inertia"]), _ptr(g["g_mu"]),
                                    _ptr(g["g_damping"]), _ptr(ws), ws.numel() * 4, self._stream())
         _check(self.lib, st, "rollout_grad")
-        g["g_u"] = g["g_u"][: self.w.T_max * J].view(self.w.T_max, J) if J else g["g_u"][:0]
+        if self.info.n_params:
+            g["g_u"] = g["g_u"][: self.info.n_params]
+        else:
+            g["g_u"] = g["g_u"][: self.w.T_max * J].view(self.w.T_max, J) if J else g["g_u"][:0]
         g["g_inv_mass"] = g["g_inv_mass"][:B]
         g["g_inv_inertia"] = g["g_inv_inertia"][: 3 * B].view(B, 3)
         g["g_mu"] = g["g_mu"][:E]
         g["g_damping"] = g["g_damping"][:J]
         return g
 
-    def step(self, x, u, lam):
+    def step(self, x, u, lam, t_index=0):
         t = self.torch
         xo = t.empty_like(x)
         lo = t.empty_like(lam)
         flags = t.zeros(max(self.info.n_envs, 1), dtype=t.int32, device="cuda")
-        st = self.lib.sim_step(self.h, _ptr(x), _ptr(xo), _ptr(u), _ptr(lam), _ptr(lo), _ptr(flags), self._stream())
+        st = self.lib.sim_step(self.h, _ptr(x), _ptr(xo), _ptr(u), _ptr(lam), _ptr(lo), int(t_index), _ptr(flags),
+                               self._stream())
         _check(self.lib, st, "sim_step")
         return xo, lo, flags

@@ -432,3 +432,75 @@ def mlp_param_count(sizes, skip_input_to_output=False):
     if skip_input_to_output:
         n += sizes[0] * sizes[-1]
     return n
+
+
+# --------------------------------------------------------------------------
+# quadruped with a neural controller (sections 3.1, 3.3)
+# --------------------------------------------------------------------------
+MLP_SIZES = (18, 128, 128, 8)
+
+
+def cylinder_z_inertia(m, L, r):
+    """Solid cylinder of length L and radius r along the body z axis."""
+    return [m * (3 * r * r + L * L) / 12, m * (3 * r * r + L * L) / 12, m * r * r / 2]
+
+
+def mlp_init(sizes=MLP_SIZES, seed_salt=0, zero_output=True, scale=1.0, out_scale=1.0):
+    """Dense net parameters in the order W1[h1][in] b1 W2[h2][h1] b2 W3[out][h2] b3;
+    hidden weights N(0, scale^2/fan_in), biases zero, output layer zero
+    (the controller starts as the zero policy, section 3.2) or, for tests,
+    N(0, out_scale^2/fan_in)."""
+    rng = rng_for(3, 100 + seed_salt)
+    parts = []
+    n = len(sizes) - 1
+    for li, (a, b) in enumerate(zip(sizes[:-1], sizes[1:])):
+        if li == n - 1 and zero_output:
+            W = np.zeros((b, a))
+        elif li == n - 1:
+            W = rng.normal(0.0, out_scale / math.sqrt(a), size=(b, a))
+        else:
+            W = rng.normal(0.0, scale / math.sqrt(a), size=(b, a))
+        parts += [W.reshape(-1), np.zeros(b)]
+    return f32(np.concatenate(parts))
+
+
+def quadruped(n_envs: int = 1024, T_min: int = 500, T_max: int = 2000, seed_salt: int = 0,
+              mlp_w=None) -> Workload:
+    """Box torso (1 kg, 0.30 x 0.15 x 0.06 m) and four legs of two 0.10 m
+    cylinders (r 0.025, 0.125 kg each), hips and knees hinged about the body y
+    axis with damping 0.01, sphere feet r = 0.05 touching the ground; legs
+    straight and feet on the ground at t = 0.  Four spheres (r = 0.03) inside
+    the torso touch the ground too.  (With 75 % of the mass in the torso the
+    42 g legs make the explicit damping term unstable at dt = 0.01,
+    dt c / I > 2, and the 20-sweep solve diverge under any active policy.)"""
+    rng = rng_for(3, seed_salt)
+    b = _Builder()
+    L, mleg, r_leg, r_foot = 0.10, 0.125, 0.025, 0.05
+    hips = [(0.12, 0.09), (0.12, -0.09), (-0.12, 0.09), (-0.12, -0.09)]
+    h = 2 * L + r_foot
+    mus = []
+    for e in range(n_envs):
+        yaw = 0.0
+        R0 = np.eye(3)
+        torso = b.body(1.0, box_inertia(1.0, 0.30, 0.15, 0.06), p=(0, 0, h), R=R0)
+        # four spheres inside the cuboid let the spine touch the ground (section 3.1)
+        for (sx, sy) in ((0.12, 0.045), (0.12, -0.045), (-0.12, 0.045), (-0.12, -0.045)):
+            b.sphere(torso, (sx, sy, 0.0), 0.03, SPHERE_GROUND)
+        for (hx, hy) in hips:
+            up = b.body(mleg, cylinder_z_inertia(mleg, L, r_leg), p=(hx, hy, h - L / 2), R=R0)
+            lo = b.body(mleg, cylinder_z_inertia(mleg, L, r_leg), p=(hx, hy, h - 1.5 * L), R=R0)
+            b.sphere(lo, (0, 0, -L / 2), r_foot, SPHERE_GROUND)
+            b.joint(torso, up, (hx, hy, 0.0), (0, 0, L / 2), (0, 1, 0), (0, 1, 0), (1, 0, 0), (1, 0, 0), 0.01)
+            b.joint(up, lo, (0, 0, -L / 2), (0, 0, L / 2), (0, 1, 0), (0, 1, 0), (1, 0, 0), (1, 0, 0), 0.01)
+        mus.append(rng.uniform(0.5, 1.0))
+        b.end_env()
+        del yaw
+    a = b.arrays()
+    T_env = rng.integers(T_min, T_max + 1, size=n_envs).astype(np.int32)
+    w = Workload(name="quadruped", n_envs=n_envs, **a, mu=f32(mus),
+                 loss_body=a["env_body_off"][:-1].astype(np.int32), target=f32(np.zeros((n_envs, 3))),
+                 T_env=T_env, u=None, dt=0.01, ground=1, loss_kind=LOSS_NEG_MEAN_VELX, loss_mask=1,
+                 T_max=int(T_env.max()), ckpt_every=50)
+    w.extra["mlp"] = dict(sizes=MLP_SIZES, w=mlp_init() if mlp_w is None else np.asarray(mlp_w, np.float64),
+                          clock_hz=1.5)
+    return w

@@ -217,3 +217,77 @@ def test_autograd_function_matches_rollout_grad():
     o = Oracle(w).rollout_grad(dloss=np.linspace(0.5, 1.5, 8))
     assert rel(u.grad.cpu().numpy().astype(np.float64), o["g_u"]) <= GRAD_TOL
     assert rel(x0.grad.cpu().numpy().T.astype(np.float64), o["g_x0"]) <= GRAD_TOL
+
+
+def _quadruped_run(w, grad=True):
+    import torch
+    from paper_1611_01652_amd.sim import Simulator
+    s = Simulator(w)
+    x0, _ = to_dev(w)
+    wt = torch.tensor(w.extra["mlp"]["w"], dtype=torch.float32, device="cuda")
+    r = s.rollout(x0, wt)
+    out = dict(loss=r["loss"].cpu().numpy().astype(np.float64), x_final=r["x_final"].cpu().numpy().T.astype(np.float64),
+               flags=r["flags"].cpu().numpy()[: w.n_envs])
+    if grad:
+        g = s.rollout_grad(x0, wt, r["ckpt"], torch.ones(w.n_envs, device="cuda"))
+        out["g_w"] = g["g_u"].cpu().numpy().astype(np.float64)
+        out["g_x0"] = g["g_x0"].cpu().numpy().T.astype(np.float64)
+        out["g_mu"] = g["g_mu"].cpu().numpy().astype(np.float64)
+    torch.cuda.synchronize()
+    return s, out
+
+
+def test_quadruped_controller_forward_and_weight_gradient():
+    # ragged episode lengths; controller output layer small but non-zero so
+    # that every layer's gradient is exercised
+    w = W.quadruped(n_envs=64, T_min=30, T_max=60, mlp_w=W.mlp_init(zero_output=False, out_scale=0.1))
+    _say("case quadruped + MLP controller 64 envs, T 30..60")
+    s, got = _quadruped_run(w)
+    assert s.info.n_params == 19976
+    o = Oracle(w)
+    roll = o.rollout()
+    ref = o.rollout_grad()
+    se = state_errors(w, got["x_final"], roll["x_final"])
+    assert np.median(se) <= STATE_TOL and (se <= 10 * STATE_TOL).mean() >= 0.9, (np.median(se), se.max())
+    np.testing.assert_allclose(got["loss"], roll["loss"], rtol=1e-3, atol=1e-5)
+    # dL/dW summed over envs: every layer and bias block within 1e-3
+    sizes = w.extra["mlp"]["sizes"]
+    off = 0
+    for a_, b_ in zip(sizes[:-1], sizes[1:]):
+        for n in (a_ * b_, b_):
+            blk = slice(off, off + n)
+            assert rel(got["g_w"][blk], ref["g_w"][blk]) <= GRAD_TOL, (off, rel(got["g_w"][blk], ref["g_w"][blk]))
+            off += n
+    assert off == len(ref["g_w"])
+
+
+def test_quadruped_zero_policy_gradient_reaches_output_layer_only():
+    # the zero-initialised output layer (section 3.2) passes no gradient to the
+    # hidden layers at the first update; only W3 and b3 move
+    w = W.quadruped(n_envs=16, T_min=40, T_max=40)
+    _say("case quadruped zero policy")
+    s, got = _quadruped_run(w)
+    ref = Oracle(w).rollout_grad()
+    n_hidden = 128 * 18 + 128 + 128 * 128 + 128
+    assert np.abs(got["g_w"][:n_hidden]).max() == 0.0
+    assert rel(got["g_w"][n_hidden:], ref["g_w"][n_hidden:]) <= GRAD_TOL
+
+
+def test_quadruped_sim_step_with_controller():
+    import torch
+    w = W.quadruped(n_envs=8, T_min=40, T_max=40, mlp_w=W.mlp_init(zero_output=False, out_scale=0.1))
+    o = Oracle(w)
+    x, lam = w.x0.copy(), np.zeros(o.lam_size)
+    for t in range(25):
+        x, lam = o.step(x, lam, None, t)
+    xn, ln = o.step(x, lam, None, 25)
+    from paper_1611_01652_amd.sim import Simulator
+    _say("case quadruped sim_step t=25")
+    s = Simulator(w)
+    xd = torch.tensor(np.ascontiguousarray(x.T), dtype=torch.float32, device="cuda")
+    wt = torch.tensor(w.extra["mlp"]["w"], dtype=torch.float32, device="cuda")
+    ld = torch.tensor(lam, dtype=torch.float32, device="cuda")
+    xo, lo, flags = s.step(xd, wt, ld, t_index=25)
+    torch.cuda.synchronize()
+    se = state_errors(w, xo.cpu().numpy().T.astype(np.float64), xn)
+    assert (se <= STATE_TOL).all(), se.max()

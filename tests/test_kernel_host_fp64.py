@@ -46,8 +46,10 @@ def _desc64(w):
             typ = C.POINTER(C.c_double)
         elif typ is C.c_float:
             typ = C.c_double
-        elif name == "gravity":
+        elif name in ("gravity",):
             typ = C.c_double * 3
+        elif name == "clock_hz":
+            typ = C.c_double
         fields.append((name, typ))
 
     class D(C.Structure):
@@ -72,6 +74,11 @@ def _desc64(w):
     d.beta, d.gamma, d.spec_margin, d.warm = w.beta, w.gamma, w.spec_margin, w.warm
     d.n_iters, d.ground, d.loss_kind, d.loss_mask = w.n_iters, w.ground, w.loss_kind, w.loss_mask
     d.ckpt_every, d.min_team = w.ckpt_every, 0
+    mlp = w.extra.get("mlp") if getattr(w, "extra", None) else None
+    if mlp is not None:
+        d.ctrl_kind = 1
+        d.mlp_sizes = (C.c_int32 * 4)(*[int(v) for v in mlp["sizes"]])
+        d.clock_hz = float(mlp.get("clock_hz", 1.5))
     return d, keep
 
 
@@ -81,9 +88,15 @@ def host_fp64(w):
     E, B, J = w.n_envs, w.n_bodies, w.n_joints
     p = lambda a: a.ctypes.data_as(C.c_void_p)   # noqa: E731
     x0 = np.ascontiguousarray(w.x0.T)
-    u = np.ascontiguousarray(w.u if w.u is not None and w.u.size else np.zeros((max(w.T_max, 1), 1)))
+    mlp = w.extra.get("mlp") if getattr(w, "extra", None) else None
+    if mlp is not None:
+        u = np.ascontiguousarray(np.asarray(mlp["w"], np.float64))
+        gu0 = np.zeros(len(u))
+    else:
+        u = np.ascontiguousarray(w.u if w.u is not None and w.u.size else np.zeros((max(w.T_max, 1), 1)))
+        gu0 = np.zeros((max(w.T_max, 1), max(J, 1)))
     out = dict(loss=np.zeros(E), x_final=np.zeros((18, B)), g_x0=np.zeros((18, B)),
-               g_u=np.zeros((max(w.T_max, 1), max(J, 1))), g_inv_mass=np.zeros(B), g_inv_inertia=np.zeros((B, 3)),
+               g_u=gu0, g_inv_mass=np.zeros(B), g_inv_inertia=np.zeros((B, 3)),
                g_mu=np.zeros(E), g_damping=np.zeros(max(J, 1)))
     st = lib.kh_rollout_grad(C.byref(d), p(x0), p(u), p(np.ones(E)), p(out["loss"]), p(out["x_final"]),
                              p(out["g_x0"]), p(out["g_u"]), p(out["g_inv_mass"]), p(out["g_inv_inertia"]),
@@ -91,7 +104,10 @@ def host_fp64(w):
     assert st == 0
     out["x_final"] = out["x_final"].T
     out["g_x0"] = out["g_x0"].T
-    out["g_u"] = out["g_u"][:, :J]
+    if mlp is not None:
+        out["g_w"] = out.pop("g_u")
+    else:
+        out["g_u"] = out["g_u"][:, :J]
     out["g_damping"] = out["g_damping"][:J]
     return out
 
@@ -107,6 +123,7 @@ def _rel(a, b):
     (lambda: W.uneven_chains(n_envs=10, T=300, seed_salt=2), 1e-7),
     (lambda: W.free_spheres(np.array([[0, 0, .1], [.19, 0, .1], [.095, 0, .27]]), [.1] * 3, [1., 2., .7],
                             mu=0.5, T=80), 1e-9),
+    (lambda: W.quadruped(n_envs=3, T_min=30, T_max=45, mlp_w=W.mlp_init(zero_output=False, out_scale=0.3)), 1e-8),
 ])
 def test_kernel_source_in_fp64_equals_oracle(maker, tol):
     w = maker()
@@ -116,6 +133,6 @@ def test_kernel_source_in_fp64_equals_oracle(maker, tol):
     roll = o.rollout()
     assert _rel(got["loss"], ref["loss"]) < tol
     assert _rel(got["x_final"], roll["x_final"]) < tol
-    for k in ("g_x0", "g_u", "g_inv_mass", "g_inv_inertia", "g_mu", "g_damping"):
-        if ref[k].size:
+    for k in ("g_x0", "g_u", "g_inv_mass", "g_inv_inertia", "g_mu", "g_damping", "g_w"):
+        if k in ref and k in got and ref[k].size:
             assert _rel(got[k], ref[k]) < tol, (k, _rel(got[k], ref[k]))
