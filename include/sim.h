@@ -199,6 +199,50 @@ sim_status rollout_grad(sim_handle h, const float* x0, const float* u, const flo
                         float* g_inv_inertia, float* g_mu, float* g_damping, void* workspace,
                         size_t workspace_bytes, void* stream);
 
+/* ---- Replayable step sequences (HIP graphs). ----
+ * Captures n_steps consecutive sim_step calls into a HIP graph, for callers
+ * that step the simulation in a loop (a policy in the loop, serving): one
+ * sim_graph_launch then costs one graph launch instead of n_steps x (queue
+ * reset + kernel) launches per bucket.  Nothing runs at capture time.
+ *   x: device [2][18][B]; step k reads x[k % 2] and writes x[(k + 1) % 2],
+ *      so the result is in x[n_steps % 2].
+ *   u: device control tape [n_steps][J] (step k uses row k) or, for
+ *      SIM_CTRL_MLP, the controller weights [n_params].
+ *   lam: device [lam_size], carried in place from step to step.
+ *   t0: step index of the first step (the controller's clock input);
+ *      with a controller t0 + n_steps <= T_max.
+ *   env_flags: device [E] or NULL; holds the flags of the last step (a
+ *      non-finite state stays non-finite, so it is still flagged).
+ * The pointers are baked into the graph: every launch reads and writes the
+ * same buffers.  A graph must not run concurrently with another call on the
+ * same handle (they share the tile queues).  Release with sim_graph_destroy;
+ * while graphs of a handle are alive, sim_destroy, sim_tune and
+ * sim_set_teams refuse with SIM_E_STATE (the graphs use its tile lists). */
+typedef struct sim_graph_s* sim_graph;
+sim_status sim_step_graph(sim_handle h, int32_t n_steps, float* x, const float* u, float* lam, int32_t t0,
+                          uint32_t* env_flags, sim_graph* out);
+sim_status sim_graph_launch(sim_graph g, void* stream);
+sim_status sim_graph_destroy(sim_graph g);
+
+/* ---- Tile autotuning. ----
+ * Envs are scheduled in buckets of equal team width (lanes per env) and LDS
+ * class.  Results never depend on the width (the sweep order is fixed), only
+ * the speed does.  sim_tune times, for each bucket, the forward rollout (and,
+ * if with_grad, rollout_grad) of that bucket alone at each admissible width
+ * (powers of two from the narrowest the bucket's envs allow whose tile fits
+ * LDS; the first max_candidates of them), keeps the fastest, and writes the
+ * chosen widths to teams[] (host, up to cap entries, may be NULL).  x0 and u
+ * are as for rollout.  Synchronous; allocates and frees its own temporaries
+ * (checkpoints, workspace).  Returns the number of buckets or a negative
+ * sim_status.
+ * sim_get_teams returns the bucket count and writes the current widths;
+ * sim_set_teams applies widths (for instance cached from an earlier
+ * sim_tune; each must be admissible), after synchronising the device. */
+int32_t sim_tune(sim_handle h, const float* x0, const float* u, int32_t with_grad, int32_t max_candidates,
+                 int32_t* teams, int32_t cap, void* stream);
+int32_t sim_get_teams(sim_handle h, int32_t* teams, int32_t cap);
+sim_status sim_set_teams(sim_handle h, const int32_t* teams, int32_t n);
+
 #ifdef __cplusplus
 }
 #endif

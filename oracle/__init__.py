@@ -49,6 +49,10 @@ def _load():
         _lib.oracle_count_flops.restype = C.c_longlong
         _lib.oracle_count_tape_edges.argtypes = [C.c_void_p, C.c_int, dp, dp, dp, C.c_int]
         _lib.oracle_count_tape_edges.restype = C.c_longlong
+        _lib.oracle_rollout_ex.argtypes = [C.c_void_p, dp, dp, dp, dp, ip, ip, C.c_int, dp, C.c_longlong, C.c_int]
+        _lib.oracle_rollout_ex.restype = C.c_longlong
+        _lib.oracle_bf16.argtypes = [C.c_double]
+        _lib.oracle_bf16.restype = C.c_double
     return _lib
 
 
@@ -71,7 +75,12 @@ class _Model(C.Structure):
         ("mlp_in", C.c_int), ("mlp_h1", C.c_int), ("mlp_h2", C.c_int), ("mlp_out", C.c_int),
         ("mlp_n_params", C.c_int), ("mlp_w", C.c_void_p), ("clock_hz", C.c_double),
         ("warm", C.c_double), ("noise", C.c_double), ("noise_seed", C.c_int),
+        ("solve_mode", C.c_int), ("tol", C.c_double), ("max_iters", C.c_int),
+        ("ws_kind", C.c_int), ("ws_w", C.c_void_p), ("fb_iters", C.c_int), ("fb_tol", C.c_double),
     ]
+
+
+WSN_IN, WSN_HID, WSN_OUT, WSN_PARAMS, REC = 7, 64, 3, 4867, 16
 
 
 def _dp(a):
@@ -81,7 +90,7 @@ def _dp(a):
 class Oracle:
     """Wraps one workload; arrays are converted to float64/int32 once."""
 
-    def __init__(self, w, mlp=None, noise=0.0, noise_seed=0):
+    def __init__(self, w, mlp=None, noise=0.0, noise_seed=0, ws_w=None):
         self.w = w
         keep = {}
 
@@ -119,9 +128,11 @@ class Oracle:
             m.u = d("u", np.zeros(1))
             m.u_stride = 0
         m.T_max = w.T_max
-        m.dt = w.dt
-        m.gravity = (C.c_double * 3)(*w.gravity)
-        m.beta, m.gamma, m.spec_margin = w.beta, w.gamma, w.spec_margin
+        # scalars as the FP32 values the GPU library receives
+        f = lambda v: float(np.float32(v))
+        m.dt = f(w.dt)
+        m.gravity = (C.c_double * 3)(*[f(g) for g in w.gravity])
+        m.beta, m.gamma, m.spec_margin = f(w.beta), f(w.gamma), f(w.spec_margin)
         m.n_iters, m.ground, m.loss_kind, m.loss_mask = w.n_iters, w.ground, w.loss_kind, w.loss_mask
         if mlp is None and getattr(w, 'extra', None):
             mlp = w.extra.get('mlp')
@@ -134,9 +145,24 @@ class Oracle:
         else:
             m.ctrl_kind = 0
             m.mlp_w = d("mlpw", np.zeros(1))
-        m.warm = getattr(w, 'warm', 1.0)
+        m.warm = f(getattr(w, 'warm', 1.0))
         m.noise = float(noise)
         m.noise_seed = int(noise_seed)
+        solve = (getattr(w, 'extra', None) or {}).get('solve')
+        if solve is not None:
+            m.solve_mode = int(solve.get("mode", 1))
+            m.tol = float(solve.get("tol", 1e-5))
+            m.max_iters = int(solve.get("max_iters", 1000))
+        ws = (getattr(w, 'extra', None) or {}).get('ws')
+        if ws_w is None and ws is not None:
+            ws_w = ws.get("w")
+        if ws_w is not None:
+            m.ws_kind = 1
+            m.ws_w = d("wsw", ws_w)
+            m.fb_iters = int((ws or {}).get("fb_iters", 5))
+            m.fb_tol = float((ws or {}).get("fb_tol", 1e-3))
+        else:
+            m.ws_w = d("wsw", np.zeros(1))
         self._m = m
         self._keep = keep
         self.lib = _load()
@@ -176,6 +202,28 @@ class Oracle:
         out = dict(loss=loss, x_final=xf, lam_final=lf[: self.lam_size])
         if traj:
             out["traj"] = tr
+        return out
+
+    def rollout_ex(self, x0=None, rec_every=0, rec_cap=0, threads=None):
+        """Forward rollout with solver statistics (sweeps and fallbacks per env)
+        and, with rec_every > 0, the training records [n, 16] of every
+        converged step t with t % rec_every == 0."""
+        w = self.w
+        x0 = np.ascontiguousarray(w.x0 if x0 is None else x0, dtype=np.float64)
+        loss = np.zeros(w.n_envs)
+        xf = np.zeros_like(x0)
+        lf = np.zeros(max(self.lam_size, 1))
+        it = np.zeros(max(w.n_envs, 1), np.int32)
+        fb = np.zeros(max(w.n_envs, 1), np.int32)
+        recs = np.zeros((max(int(rec_cap), 1), REC)) if rec_every > 0 else None
+        ip = C.POINTER(C.c_int)
+        n = self.lib.oracle_rollout_ex(C.byref(self._m), _dp(x0), _dp(loss), _dp(xf), _dp(lf),
+                                       it.ctypes.data_as(ip), fb.ctypes.data_as(ip), int(rec_every),
+                                       _dp(recs), int(rec_cap), threads or os.cpu_count() or 1)
+        out = dict(loss=loss, x_final=xf, lam_final=lf[: self.lam_size], iters=it[: w.n_envs],
+                   fallbacks=fb[: w.n_envs], n_records=int(n))
+        if recs is not None:
+            out["records"] = recs[: min(int(n), int(rec_cap))]
         return out
 
     def rollout_grad(self, dloss=None, x0=None, threads=None):

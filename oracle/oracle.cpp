@@ -208,7 +208,53 @@ template <class S> struct ConRows {
   Row<S> r[5];
   V3<S> t1, t2;   // contact tangents (for the tangent impulse carry)
   S mt = S(0.0);  // friction block effective mass
+  S gap = S(0.0); // contact gap
+  int code = 0;   // candidate code: kind << 24 | id (ground: global sphere, pair: local a | local b << 12)
 };
+
+// Solver statistics and training records of one step (tolerance mode).
+struct StepStats {
+  int env = 0;
+  int sweeps = 0;                      // Gauss-Seidel sweeps, discarded ones included
+  int fallbacks = 0;                   // learned warm starts rejected
+  int rec_every = 0;                   // records at steps t with t % rec_every == 0 (0: none)
+  std::vector<double>* recs = nullptr;
+};
+
+// bfloat16: 8 significant bits, nearest with ties to even (the default
+// floating-point rounding mode of nearbyint).  Values below the bfloat16
+// normal range are not expected here and are rounded as if normal.
+static double bf16(double x) {
+  if (!std::isfinite(x) || x == 0.0) return x;
+  int e;
+  (void)std::frexp(x, &e);
+  const double q = std::ldexp(1.0, e - 8);
+  return std::nearbyint(x / q) * q;
+}
+
+// Warm-start network: y = W3 h2 + b3, h2 = relu(W2 h1 + b2), h1 = relu(W1 x + b1)
+// with weights, input and hidden activations rounded to bfloat16.
+static void wsn_eval(const double* w, const double* f, double* y) {
+  const int I = ORACLE_WSN_IN, H = ORACLE_WSN_HID, O = ORACLE_WSN_OUT;
+  const double *W1 = w, *b1 = W1 + H * I, *W2 = b1 + H, *b2 = W2 + H * H, *W3 = b2 + H, *b3 = W3 + O * H;
+  double x[ORACLE_WSN_IN], h1[ORACLE_WSN_HID], h2[ORACLE_WSN_HID];
+  for (int k = 0; k < I; ++k) x[k] = bf16(f[k]);
+  for (int i = 0; i < H; ++i) {
+    double s = bf16(b1[i]);
+    for (int k = 0; k < I; ++k) s += bf16(W1[i * I + k]) * x[k];
+    h1[i] = bf16(std::max(s, 0.0));
+  }
+  for (int i = 0; i < H; ++i) {
+    double s = bf16(b2[i]);
+    for (int k = 0; k < H; ++k) s += bf16(W2[i * H + k]) * h1[k];
+    h2[i] = bf16(std::max(s, 0.0));
+  }
+  for (int o = 0; o < O; ++o) {
+    double s = bf16(b3[o]);
+    for (int k = 0; k < H; ++k) s += bf16(W3[o * H + k]) * h2[k];
+    y[o] = s;
+  }
+}
 
 template <class S> struct Bodies {
   std::vector<V3<S>> p, v, w;
@@ -298,7 +344,7 @@ template <class S> struct StepIn {
 
 template <class S>
 void step_env(const Model& M, const EnvTopo& E, const StepIn<S>& in, S* xn, S* lamn,
-              const S* W = nullptr, int t = 0) {
+              const S* W = nullptr, int t = 0, StepStats* stats = nullptr) {
   const oracle_model& c = M.c;
   const int nb = E.nb;
   const S dt = S(c.dt);
@@ -403,6 +449,7 @@ void step_env(const Model& M, const EnvTopo& E, const StepIn<S>& in, S* xn, S* l
         n = ez;
         rb_ = (cen[s] - rad * n) - B.p[b];
         store = 5 * E.nj + 4 * k.idx;
+        C.code = (1 << 24) | gs;
       } else {
         const PairCand& pc = E.pairs[k.idx];
         a = pc.ba - E.b0; b = pc.bb - E.b0;
@@ -413,12 +460,13 @@ void step_env(const Model& M, const EnvTopo& E, const StepIn<S>& in, S* xn, S* l
         gap = L - raa - rbb;
         if (!(val(gap) < c.spec_margin)) continue;
         active_pair[k.idx] = 1;
+        C.code = (2 << 24) | (pc.ba - E.b0) | ((pc.bb - E.b0) << 12);
         n = val(L) < 1e-9 ? ez : (S(1.0) / L) * d;
         ra_ = (ca + raa * n) - B.p[a];
         rb_ = (cb - rbb * n) - B.p[b];
         store = 5 * E.nj + 4 * (int)E.ground.size() + 4 * k.idx;
       }
-      C.kind = 1; C.nrows = 3; C.store = store;
+      C.kind = 1; C.nrows = 3; C.store = store; C.gap = gap;
       // tangent basis
       V3<S> t1, t2;
       if (k.kind == 1) { t1 = ex; t2 = ey; }
@@ -453,12 +501,50 @@ void step_env(const Model& M, const EnvTopo& E, const StepIn<S>& in, S* xn, S* l
     }
     cons.push_back(C);
   }
-  // S6 warm start: apply the carried impulses
+  // S6 warm start.  Plain: the carried impulses.  Learned (tolerance mode):
+  // contact impulses from the warm-start network on per-contact features,
+  // projected onto lambda_n >= 0, |lambda_t| <= mu lambda_n.
+  const S mu = in.mu;
+  const bool tolmode = c.solve_mode == 1;
+  const size_t nc = cons.size();
+  std::vector<std::array<S, 5>> plain(nc);
+  for (size_t i = 0; i < nc; ++i)
+    for (int q = 0; q < cons[i].nrows; ++q) plain[i][q] = cons[i].r[q].lam;
+  std::vector<V3<S>> v_pred, w_pred;
+  std::vector<std::array<double, ORACLE_WSN_IN>> feat(nc);
+  if (tolmode) {
+    v_pred = B.v;
+    w_pred = B.w;
+    for (size_t i = 0; i < nc; ++i) {
+      const ConRows<S>& C = cons[i];
+      if (C.kind != 1) continue;
+      const double mn = val(C.r[0].m), mt = val(C.mt);
+      feat[i] = {val(C.gap) / c.dt, val(jdotv(C.r[0], B)), val(jdotv(C.r[1], B)), val(jdotv(C.r[2], B)),
+                 val(plain[i][0]) / mn, val(plain[i][1]) / mt, val(plain[i][2]) / mt};
+    }
+  }
+  if (tolmode && c.ws_kind == 1) {
+    for (size_t i = 0; i < nc; ++i) {
+      ConRows<S>& C = cons[i];
+      if (C.kind != 1) continue;
+      double y[ORACLE_WSN_OUT];
+      wsn_eval(c.ws_w, feat[i].data(), y);
+      const double ln = std::max(val(C.r[0].m) * y[0], 0.0);
+      double l1 = val(C.mt) * y[1], l2 = val(C.mt) * y[2];
+      const double rho = val(mu) * ln, nrm = std::sqrt(l1 * l1 + l2 * l2);
+      if (!(nrm <= rho)) { l1 *= rho / nrm; l2 *= rho / nrm; }
+      C.r[0].lam = S(ln);
+      C.r[1].lam = S(l1);
+      C.r[2].lam = S(l2);
+    }
+  }
   for (auto& C : cons)
     for (int q = 0; q < C.nrows; ++q) apply(C.r[q], B, C.r[q].lam);
-  // S7 projected Gauss-Seidel, fixed number of sweeps
-  const S mu = in.mu;
-  for (int it = 0; it < c.n_iters; ++it) {
+  // S7 projected Gauss-Seidel.  One sweep visits every constraint in the
+  // canonical order and returns the residual: the largest |delta lambda| / m
+  // over the scalar rows and |delta lambda_t| / m_t over the friction blocks.
+  auto sweep = [&]() -> double {
+    double res = 0.0;
     for (auto& C : cons) {
       const int nscalar = C.kind == 0 ? 5 : 1;
       for (int q = 0; q < nscalar; ++q) {
@@ -470,6 +556,7 @@ void step_env(const Model& M, const EnvTopo& E, const StepIn<S>& in, S* xn, S* l
         else if (val(lt) >= r.hi) ln = S(r.hi);
         else ln = lt;
         apply(r, B, ln - r.lam);
+        res = std::max(res, std::fabs(val(ln) - val(r.lam)) / val(r.m));
         r.lam = ln;
       }
       if (C.kind == 1) {
@@ -488,8 +575,52 @@ void step_env(const Model& M, const EnvTopo& E, const StepIn<S>& in, S* xn, S* l
         }
         apply(r1, B, n1 - r1.lam);
         apply(r2, B, n2 - r2.lam);
+        const double d1 = val(n1) - val(r1.lam), d2 = val(n2) - val(r2.lam);
+        res = std::max(res, std::sqrt(d1 * d1 + d2 * d2) / val(C.mt));
         r1.lam = n1;
         r2.lam = n2;
+      }
+    }
+    return res;
+  };
+  if (!tolmode) {
+    for (int it = 0; it < c.n_iters; ++it) (void)sweep();
+  } else if (nc > 0) {
+    int it = 0;
+    double res = INFINITY;
+    if (c.ws_kind == 1) {
+      while (it < c.fb_iters && res > c.tol) { res = sweep(); ++it; }
+      if (res > c.tol && res > c.fb_tol) {
+        // rejected: restart this env's solve from the plain warm start
+        if (stats) { stats->sweeps += it; stats->fallbacks += 1; }
+        B.v = v_pred;
+        B.w = w_pred;
+        for (size_t i = 0; i < nc; ++i)
+          for (int q = 0; q < cons[i].nrows; ++q) cons[i].r[q].lam = plain[i][q];
+        for (auto& C : cons)
+          for (int q = 0; q < C.nrows; ++q) apply(C.r[q], B, C.r[q].lam);
+        it = 0;
+        res = INFINITY;
+      }
+    }
+    while (res > c.tol && it < c.max_iters) { res = sweep(); ++it; }
+    if (stats) stats->sweeps += it;
+    if (stats && stats->recs && stats->rec_every > 0 && t % stats->rec_every == 0 && res <= c.tol) {
+      for (size_t i = 0; i < nc; ++i) {
+        const ConRows<S>& C = cons[i];
+        if (C.kind != 1) continue;
+        const double mn = val(C.r[0].m), mt = val(C.mt);
+        std::vector<double>& R = *stats->recs;
+        for (int k = 0; k < ORACLE_WSN_IN; ++k) R.push_back(feat[i][k]);
+        R.push_back(val(C.r[0].lam) / mn);
+        R.push_back(val(C.r[1].lam) / mt);
+        R.push_back(val(C.r[2].lam) / mt);
+        R.push_back(mn);
+        R.push_back(mt);
+        R.push_back(stats->env);
+        R.push_back(t);
+        R.push_back(C.code);
+        R.push_back(0.0);
       }
     }
   }
@@ -611,7 +742,8 @@ static double noise_r(uint64_t seed, uint64_t e, uint64_t t, uint64_t i) {
 // Forward rollout of one env in type S; optionally records step-start states.
 template <class S>
 static S rollout_env(const Ctx& C, int e, std::vector<S>& x, std::vector<S>& lam,
-                     std::vector<double>* xs, std::vector<double>* ls, double* traj) {
+                     std::vector<double>* xs, std::vector<double>* ls, double* traj,
+                     StepStats* stats = nullptr) {
   const oracle_model& c = C.M.c;
   const EnvTopo& E = C.topo[e];
   const int T = c.T_env[e];
@@ -630,7 +762,7 @@ static S rollout_env(const Ctx& C, int e, std::vector<S>& x, std::vector<S>& lam
     if (c.ctrl_kind == 0)
       for (int j = 0; j < E.nj; ++j) u[j] = S(c.u[(size_t)t * c.u_stride + E.j0 + j]);
     StepIn<S> in{x.data(), lam.data(), u.data(), invm.data(), invI.data(), damp.data(), S(c.mu[e])};
-    step_env(C.M, E, in, xn.data(), ln.data(), W.data(), t);
+    step_env(C.M, E, in, xn.data(), ln.data(), W.data(), t, stats);
     if (c.noise > 0.0)
       for (int i = 0; i < n; ++i) xn[i] = xn[i] * S(1.0 + c.noise * noise_r(c.noise_seed, e, t, i));
     x.swap(xn);
@@ -702,12 +834,43 @@ int oracle_rollout(const oracle_model* m, const double* x0, double* loss_env, do
   return 0;
 }
 
+long long oracle_rollout_ex(const oracle_model* m, const double* x0, double* loss_env, double* x_final,
+                            double* lam_final, int* iters_env, int* fallbacks_env, int rec_every, double* recs,
+                            long long rec_cap, int n_threads) {
+  Ctx C;
+  build_ctx(m, C);
+  std::vector<std::vector<double>> rec_env(m->n_envs);
+  parallel_envs(m->n_envs, n_threads, [&](int e) {
+    const EnvTopo& E = C.topo[e];
+    std::vector<double> x(x0 + 18 * E.b0, x0 + 18 * (E.b0 + E.nb));
+    std::vector<double> lam(E.lam_size, 0.0);
+    StepStats st;
+    st.env = e;
+    st.rec_every = recs ? rec_every : 0;
+    st.recs = &rec_env[e];
+    const double L = rollout_env<double>(C, e, x, lam, nullptr, nullptr, nullptr, &st);
+    if (loss_env) loss_env[e] = L;
+    if (x_final) std::copy(x.begin(), x.end(), x_final + 18 * E.b0);
+    if (lam_final) std::copy(lam.begin(), lam.end(), lam_final + E.lam_off);
+    if (iters_env) iters_env[e] = st.sweeps;
+    if (fallbacks_env) fallbacks_env[e] = st.fallbacks;
+  });
+  long long n = 0;
+  for (const auto& r : rec_env)
+    for (size_t k = 0; k < r.size(); k += ORACLE_REC, ++n)
+      if (recs && n < rec_cap) std::copy(r.begin() + k, r.begin() + k + ORACLE_REC, recs + n * ORACLE_REC);
+  return n;
+}
+
+double oracle_bf16(double x) { return bf16(x); }
+
 // Reverse mode over the unrolled trajectory: forward once storing step-start
 // states, then one tape per step, last step first, carrying the adjoints of
 // the state and of the warm-start impulses.
 int oracle_rollout_grad(const oracle_model* m, const double* x0, const double* dloss, double* loss_env,
                         double* g_x0, double* g_u, double* g_inv_mass, double* g_inv_inertia, double* g_mu,
                         double* g_damping, double* g_w, int n_threads) {
+  if (m->solve_mode != 0) return -1;  // the gradient is of the fixed-sweep map
   Ctx C;
   build_ctx(m, C);
   const oracle_model& c = C.M.c;

@@ -37,7 +37,34 @@ typedef struct {
   double warm;                /* warm-start factor applied to carried impulses */
   double noise;               /* test aid: relative rounding-sized noise added to the state after every step */
   int noise_seed;
+  /* solve to a tolerance (forward only): after each sweep the residual is the
+     largest |change of impulse| / effective mass over the active rows (for a
+     friction block the norm of the tangent change over its mass), in m/s;
+     sweeps stop at the first residual <= tol, or after max_iters sweeps. */
+  int solve_mode;             /* 0 fixed n_iters sweeps, 1 to tolerance */
+  double tol;
+  int max_iters;
+  /* learned warm start of contacts (tolerance mode): per-contact network
+     7 -> 64 -> 64 -> 3 with ReLU, weights, inputs and hidden activations
+     rounded to bfloat16; if the residual after fb_iters sweeps exceeds fb_tol
+     the env's solve restarts from the plain warm start. */
+  int ws_kind;                /* 0 plain, 1 learned */
+  const double *ws_w;         /* W1[64][7] b1[64] W2[64][64] b2[64] W3[3][64] b3[3] */
+  int fb_iters;
+  double fb_tol;
 } oracle_model;
+
+/* Warm-start network shape and training-record layout. */
+#define ORACLE_WSN_IN 7
+#define ORACLE_WSN_HID 64
+#define ORACLE_WSN_OUT 3
+#define ORACLE_WSN_PARAMS 4867
+/* record: features f[7] (gap/dt, J_n v, J_t1 v, J_t2 v at the predicted
+   velocities, plain warm-start impulses over their effective masses), target
+   y[3] (converged impulses over their effective masses), m_n, m_t, env, step,
+   candidate code (kind << 24 | id; ground: global sphere, pair: local body a |
+   local body b << 12), 0 */
+#define ORACLE_REC 16
 
 int oracle_lambda_size(const oracle_model* m, int* out_offsets /* [E+1] or NULL */);
 int oracle_order(const oracle_model* m, int env, int* kinds, int* idx, int cap);
@@ -48,6 +75,17 @@ int oracle_rollout(const oracle_model* m, const double* x0, double* loss_env, do
 int oracle_rollout_grad(const oracle_model* m, const double* x0, const double* dloss, double* loss_env,
                         double* g_x0, double* g_u, double* g_inv_mass, double* g_inv_inertia,
                         double* g_mu, double* g_damping, double* g_w, int n_threads);
+/* Forward rollout with solver statistics: sweeps per env summed over its
+   steps (sweeps discarded by a fallback included), fallbacks per env, and,
+   with recs, one record per active contact of every converged step t with
+   t % rec_every == 0 (envs in order).  Returns the number of records (only
+   the first rec_cap are written). */
+long long oracle_rollout_ex(const oracle_model* m, const double* x0, double* loss_env, double* x_final,
+                            double* lam_final, int* iters_env, int* fallbacks_env, int rec_every, double* recs,
+                            long long rec_cap, int n_threads);
+/* bfloat16 rounding (nearest, ties to even) of a double */
+double oracle_bf16(double x);
+
 long long oracle_count_flops(const oracle_model* m, int env, const double* x, const double* lam,
                              const double* u, int t);
 

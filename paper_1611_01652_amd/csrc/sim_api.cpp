@@ -27,6 +27,7 @@ sim_status fail(sim_status s, const std::string& msg) {
 
 struct Bucket {
   int team = 1;
+  int team_min = 1;             // narrowest team the bucket's envs allow
   std::vector<int> envs_host;   // tiles * (64/team)
   int n_tiles = 0;
   int floats_fwd = 0, floats_adj = 0;
@@ -57,6 +58,14 @@ struct sim_model {
   int* d_map = nullptr;
   int n_wtiles = 0, n_params = 0, chunk = 2048;
   long long tape_rows = 0, seg_floats = 0, tape_floats = 0;
+  int lds_allowed = 65536;      // dynamic LDS limit set on the kernels
+  int n_graphs = 0;             // live step graphs (they hold the tile lists)
+};
+
+struct sim_graph_s {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  sim_model* h = nullptr;
 };
 
 namespace {
@@ -118,6 +127,80 @@ int grid_for(const sim_model* h, const Bucket& b, int floats) {
   int per_cu = bytes > 0 ? (160 * 1024) / bytes : 8;
   per_cu = std::max(1, std::min(per_cu, 8));
   return std::max(1, std::min(b.n_tiles, h->n_cu * per_cu));
+}
+
+// One bucket's kernels (queue reset + launch) on stream sx.
+bool bucket_step(sim_model* h, size_t i, const DevModel& M, const StepArgs& a, hipStream_t sx) {
+  const Bucket& b = h->buckets[i];
+  TileSet ts{b.envs_dev, b.n_tiles, b.floats_fwd, h->d_queue + i};
+  if (launch_zero(ts.queue, 1, sx) != hipSuccess) return false;
+  const size_t lds = (size_t)(64 / b.team) * b.floats_fwd * 4;
+  return launch_step(M, ts, b.team, grid_for(h, b, b.floats_fwd), lds, a, sx) == hipSuccess;
+}
+bool bucket_rollout(sim_model* h, size_t i, const DevModel& M, const RolloutArgs& a, hipStream_t sx) {
+  const Bucket& b = h->buckets[i];
+  TileSet ts{b.envs_dev, b.n_tiles, b.floats_fwd, h->d_queue + i};
+  if (launch_zero(ts.queue, 1, sx) != hipSuccess) return false;
+  const size_t lds = (size_t)(64 / b.team) * b.floats_fwd * 4;
+  return launch_rollout(M, ts, b.team, grid_for(h, b, b.floats_fwd), lds, a, sx) == hipSuccess;
+}
+bool bucket_grad(sim_model* h, size_t i, const DevModel& M, const GradArgs& a, hipStream_t sx) {
+  const Bucket& b = h->buckets[i];
+  TileSet ts{b.envs_dev, b.n_tiles, b.floats_adj, h->d_queue + i};
+  if (launch_zero(ts.queue, 1, sx) != hipSuccess) return false;
+  const size_t lds = (size_t)(64 / b.team) * b.floats_adj * 4;
+  return launch_rollout_grad(M, ts, b.team, grid_for(h, b, b.floats_adj), lds, a, sx) == hipSuccess;
+}
+
+sim_status launch_steps(sim_model* h, const float* x_in, float* x_out, const float* u, const float* lam_in,
+                        float* lam_out, int32_t t, uint32_t* env_flags, hipStream_t st) {
+  StepArgs a{x_in, x_out, h->M.ctrl ? nullptr : u, lam_in, lam_out, env_flags, t};
+  DevModel M = h->M;
+  M.W = u;
+  return run_buckets(h, st, [&](size_t i, hipStream_t sx) { return bucket_step(h, i, M, a, sx); },
+                     "sim_step launch");
+}
+
+// Team widths a bucket may use: powers of two from its narrowest whose tile
+// fits the device's LDS.
+std::vector<int> admissible_teams(const sim_model* h, const Bucket& b) {
+  std::vector<int> out;
+  for (int t = b.team_min; t <= 64; t *= 2)
+    if ((64 / t) * (long long)b.floats_adj * 4 <= h->max_lds) out.push_back(t);
+  return out;
+}
+
+// Re-tile a bucket for another team width, keeping its env order.
+sim_status retile(sim_model* h, Bucket& b, int team) {
+  if (team == b.team) return SIM_OK;
+  std::vector<int> ids;
+  for (int e : b.envs_host)
+    if (e >= 0) ids.push_back(e);
+  const int epw = 64 / team;
+  const int n_tiles = ((int)ids.size() + epw - 1) / epw;
+  std::vector<int> host((size_t)n_tiles * epw, -1);
+  std::copy(ids.begin(), ids.end(), host.begin());
+  const int bytes = epw * b.floats_adj * 4;
+  if (bytes > h->lds_allowed) {
+    if (allow_large_lds(std::min(bytes, h->max_lds)) != hipSuccess)
+      return fail(SIM_E_DEVICE, "cannot raise the dynamic LDS limit");
+    h->lds_allowed = bytes;
+  }
+  int* dev = nullptr;
+  const sim_status st = upload(&dev, host);
+  if (st != SIM_OK) return st;
+  if (b.envs_dev) (void)hipFree(b.envs_dev);
+  b.envs_dev = dev;
+  b.envs_host.swap(host);
+  b.n_tiles = n_tiles;
+  b.team = team;
+  h->info.n_tiles = 0;
+  h->info.max_lds_bytes = 0;
+  for (const auto& x : h->buckets) {
+    h->info.n_tiles += x.n_tiles;
+    h->info.max_lds_bytes = std::max(h->info.max_lds_bytes, (64 / x.team) * x.floats_adj * 4);
+  }
+  return SIM_OK;
 }
 
 }  // namespace
@@ -221,6 +304,7 @@ sim_status sim_init(const sim_model_desc* d, sim_handle* out) {
     });
     Bucket bk;
     bk.team = team;
+    bk.team_min = team;
     const int epw = 64 / team;
     bk.n_tiles = ((int)ids.size() + epw - 1) / epw;
     bk.envs_host.assign((size_t)bk.n_tiles * epw, -1);
@@ -310,6 +394,7 @@ sim_status sim_init(const sim_model_desc* d, sim_handle* out) {
     release(h);
     return fail(SIM_E_DEVICE, "cannot raise the dynamic LDS limit");
   }
+  h->lds_allowed = std::max(65536, max_lds);
   M.hdr = h->d_hdr; M.topo = h->d_topo; M.cst = h->d_cst; M.target = h->d_target;
   sim_info& I = h->info;
   I.n_envs = E; I.n_bodies = B; I.n_joints = J; I.lam_size = M.lam_tot;
@@ -361,6 +446,7 @@ int32_t sim_describe_order(const sim_model_desc* d, int32_t env, int32_t* codes,
 
 sim_status sim_destroy(sim_handle h) {
   if (!h) return fail(SIM_E_ARG, "sim_destroy: null handle");
+  if (h->n_graphs > 0) return fail(SIM_E_STATE, "sim_destroy: step graphs of this handle are still alive");
   release(h);
   return SIM_OK;
 }
@@ -387,17 +473,7 @@ sim_status sim_step(sim_handle h, const float* x_in, float* x_out, const float* 
   sim_status s = check_device("sim_step (earlier fault)");
   if (s != SIM_OK) return s;
   if (t < 0 || (h->M.ctrl && t >= std::max(h->M.T_max, 1))) return fail(SIM_E_ARG, "sim_step: step index out of range");
-  hipStream_t st = (hipStream_t)stream;
-  StepArgs a{x_in, x_out, h->M.ctrl ? nullptr : u, lam_in, lam_out, env_flags, t};
-  DevModel M = h->M;
-  M.W = u;
-  return run_buckets(h, st, [&](size_t i, hipStream_t sx) {
-    const Bucket& b = h->buckets[i];
-    TileSet ts{b.envs_dev, b.n_tiles, b.floats_fwd, h->d_queue + i};
-    if (launch_zero(ts.queue, 1, sx) != hipSuccess) return false;
-    const size_t lds = (size_t)(64 / b.team) * b.floats_fwd * 4;
-    return launch_step(M, ts, b.team, grid_for(h, b, b.floats_fwd), lds, a, sx) == hipSuccess;
-  }, "sim_step launch");
+  return launch_steps(h, x_in, x_out, u, lam_in, lam_out, t, env_flags, (hipStream_t)stream);
 }
 
 sim_status rollout(sim_handle h, const float* x0, const float* u, float* loss_env, float* x_final,
@@ -412,13 +488,8 @@ sim_status rollout(sim_handle h, const float* x0, const float* u, float* loss_en
   RolloutArgs a{x0, u, loss_env, x_final, lam_final, ckpt, env_flags};
   DevModel M = h->M;
   M.W = u;
-  return run_buckets(h, st, [&](size_t i, hipStream_t sx) {
-    const Bucket& b = h->buckets[i];
-    TileSet ts{b.envs_dev, b.n_tiles, b.floats_fwd, h->d_queue + i};
-    if (launch_zero(ts.queue, 1, sx) != hipSuccess) return false;
-    const size_t lds = (size_t)(64 / b.team) * b.floats_fwd * 4;
-    return launch_rollout(M, ts, b.team, grid_for(h, b, b.floats_fwd), lds, a, sx) == hipSuccess;
-  }, "rollout launch");
+  return run_buckets(h, st, [&](size_t i, hipStream_t sx) { return bucket_rollout(h, i, M, a, sx); },
+                     "rollout launch");
 }
 
 sim_status rollout_grad(sim_handle h, const float* x0, const float* u, const float* ckpt, const float* dloss_env,
@@ -439,19 +510,166 @@ sim_status rollout_grad(sim_handle h, const float* x0, const float* u, const flo
   DevModel M = h->M;
   M.W = u;
   M.tape = ws + h->seg_floats;
-  s = run_buckets(h, st, [&](size_t i, hipStream_t sx) {
-    const Bucket& b = h->buckets[i];
-    TileSet ts{b.envs_dev, b.n_tiles, b.floats_adj, h->d_queue + i};
-    if (launch_zero(ts.queue, 1, sx) != hipSuccess) return false;
-    const size_t lds = (size_t)(64 / b.team) * b.floats_adj * 4;
-    return launch_rollout_grad(M, ts, b.team, grid_for(h, b, b.floats_adj), lds, a, sx) == hipSuccess;
-  }, "rollout_grad launch");
+  s = run_buckets(h, st, [&](size_t i, hipStream_t sx) { return bucket_grad(h, i, M, a, sx); },
+                  "rollout_grad launch");
   if (s != SIM_OK || !M.ctrl || !g_u) return s;
   // dL/dW: contraction of the per env-step deltas and activations
   if (launch_wgrad(M.tape, M.tape_stride, (int)h->tape_rows, h->chunk, h->d_tiles, h->n_wtiles,
                    M.tape + h->tape_floats, h->d_map, h->n_params, g_u, st) != hipSuccess)
     return check_device("rollout_grad weight gradient");
   return SIM_OK;
+}
+
+// ------------------------------------------------------------- graphs, tuning
+sim_status sim_step_graph(sim_handle h, int32_t n_steps, float* x, const float* u, float* lam, int32_t t0,
+                          uint32_t* env_flags, sim_graph* out) {
+  if (!h || !out) return fail(SIM_E_ARG, "sim_step_graph: null argument");
+  *out = nullptr;
+  if (n_steps < 1) return fail(SIM_E_ARG, "sim_step_graph: n_steps < 1");
+  const DevModel& M = h->M;
+  if (M.n_envs > 0 && (!x || (M.lam_tot > 0 && !lam) || (M.J > 0 && !u)))
+    return fail(SIM_E_ARG, "sim_step_graph: null array");
+  if (t0 < 0 || (M.ctrl && (long long)t0 + n_steps > std::max(M.T_max, 1)))
+    return fail(SIM_E_ARG, "sim_step_graph: step indices outside [0, T_max)");
+  sim_status s = check_device("sim_step_graph (earlier fault)");
+  if (s != SIM_OK) return s;
+  sim_graph_s* g = new sim_graph_s();
+  g->h = h;
+  ++h->n_graphs;
+  if (M.n_envs == 0) {
+    if (hipGraphCreate(&g->graph, 0) != hipSuccess ||
+        hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0) != hipSuccess) {
+      sim_graph_destroy(g);
+      return check_device("sim_step_graph instantiate");
+    }
+    *out = g;
+    return SIM_OK;
+  }
+  hipStream_t cs = nullptr;
+  if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) {
+    sim_graph_destroy(g);
+    return fail(SIM_E_DEVICE, "sim_step_graph: cannot create the capture stream");
+  }
+  if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    (void)hipStreamDestroy(cs);
+    sim_graph_destroy(g);
+    return check_device("sim_step_graph begin capture");
+  }
+  const size_t xs = (size_t)18 * M.B;
+  for (int k = 0; k < n_steps && s == SIM_OK; ++k) {
+    const float* uk = M.ctrl ? u : (u ? u + (size_t)k * M.J : nullptr);
+    s = launch_steps(h, x + (k & 1) * xs, x + ((k + 1) & 1) * xs, uk, lam, lam, t0 + k, env_flags, cs);
+  }
+  const hipError_t ec = hipStreamEndCapture(cs, &g->graph);
+  (void)hipStreamDestroy(cs);
+  if (s != SIM_OK || ec != hipSuccess || hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0) != hipSuccess) {
+    sim_graph_destroy(g);
+    return s != SIM_OK ? s : check_device("sim_step_graph capture");
+  }
+  *out = g;
+  return SIM_OK;
+}
+
+sim_status sim_graph_launch(sim_graph g, void* stream) {
+  if (!g || !g->exec) return fail(SIM_E_ARG, "sim_graph_launch: null graph");
+  if (hipGraphLaunch(g->exec, (hipStream_t)stream) != hipSuccess) return check_device("sim_graph_launch");
+  return SIM_OK;
+}
+
+sim_status sim_graph_destroy(sim_graph g) {
+  if (!g) return fail(SIM_E_ARG, "sim_graph_destroy: null graph");
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  if (g->h) --g->h->n_graphs;
+  delete g;
+  return SIM_OK;
+}
+
+int32_t sim_get_teams(sim_handle h, int32_t* teams, int32_t cap) {
+  if (!h) return fail(SIM_E_ARG, "sim_get_teams: null handle");
+  const int n = (int)h->buckets.size();
+  for (int i = 0; i < n && teams && i < cap; ++i) teams[i] = h->buckets[i].team;
+  return n;
+}
+
+sim_status sim_set_teams(sim_handle h, const int32_t* teams, int32_t n) {
+  if (!h || (n > 0 && !teams)) return fail(SIM_E_ARG, "sim_set_teams: null argument");
+  if (h->n_graphs > 0) return fail(SIM_E_STATE, "sim_set_teams: destroy the step graphs of this handle first");
+  if (n != (int)h->buckets.size())
+    return fail(SIM_E_SHAPE, "sim_set_teams: expected " + std::to_string(h->buckets.size()) + " team widths");
+  for (int i = 0; i < n; ++i) {
+    const auto ok = admissible_teams(h, h->buckets[i]);
+    if (std::find(ok.begin(), ok.end(), teams[i]) == ok.end())
+      return fail(SIM_E_ARG, "sim_set_teams: team " + std::to_string(teams[i]) + " not admissible for bucket " +
+                                 std::to_string(i));
+  }
+  if (hipDeviceSynchronize() != hipSuccess) return check_device("sim_set_teams");
+  for (int i = 0; i < n; ++i) {
+    const sim_status s = retile(h, h->buckets[i], teams[i]);
+    if (s != SIM_OK) return s;
+  }
+  return SIM_OK;
+}
+
+int32_t sim_tune(sim_handle h, const float* x0, const float* u, int32_t with_grad, int32_t max_candidates,
+                 int32_t* teams, int32_t cap, void* stream) {
+  if (!h) return fail(SIM_E_ARG, "sim_tune: null handle");
+  const DevModel& M0 = h->M;
+  const int n = (int)h->buckets.size();
+  if (M0.n_envs == 0) return n;
+  if (!x0 || (M0.J > 0 && M0.T_max > 0 && !u)) return fail(SIM_E_ARG, "sim_tune: null x0 or controls");
+  if (max_candidates < 1) return fail(SIM_E_ARG, "sim_tune: max_candidates < 1");
+  if (h->n_graphs > 0) return fail(SIM_E_STATE, "sim_tune: destroy the step graphs of this handle first");
+  sim_status s = check_device("sim_tune (earlier fault)");
+  if (s != SIM_OK) return s;
+  hipStream_t st = (hipStream_t)stream;
+  float *loss = nullptr, *dl = nullptr, *ck = nullptr, *ws = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  auto cleanup = [&]() {
+    (void)hipStreamSynchronize(st);
+    for (float* p : {loss, dl, ck, ws})
+      if (p) (void)hipFree(p);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+  };
+  const int E = M0.n_envs;
+  if (upload(&loss, std::vector<float>(E, 0.f)) != SIM_OK || upload(&dl, std::vector<float>(E, 1.f)) != SIM_OK ||
+      hipMalloc((void**)&ck, (size_t)std::max<int64_t>(h->info.ckpt_floats, 1) * 4) != hipSuccess ||
+      (with_grad && hipMalloc((void**)&ws, (size_t)h->info.workspace_bytes) != hipSuccess) ||
+      hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    cleanup();
+    return fail(SIM_E_NOMEM, "sim_tune: cannot allocate temporaries");
+  }
+  DevModel M = M0;
+  M.W = u;
+  M.tape = ws ? ws + h->seg_floats : nullptr;
+  const RolloutArgs ra{x0, u, loss, nullptr, nullptr, ck, nullptr};
+  const GradArgs ga{x0, u, ck, dl, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, ws};
+  // every bucket once at its current width: warms the code and writes the checkpoints
+  for (int i = 0; i < n; ++i)
+    if (!bucket_rollout(h, i, M, ra, st)) { cleanup(); return check_device("sim_tune rollout"); }
+  if (hipStreamSynchronize(st) != hipSuccess) { cleanup(); return check_device("sim_tune rollout"); }
+  for (int i = 0; i < n; ++i) {
+    const std::vector<int> cand = admissible_teams(h, h->buckets[i]);
+    int best = h->buckets[i].team;
+    float best_ms = -1.f;
+    for (int c = 0; c < (int)cand.size() && c < max_candidates; ++c) {
+      if ((s = retile(h, h->buckets[i], cand[c])) != SIM_OK) { cleanup(); return s; }
+      if (hipEventRecord(e0, st) != hipSuccess || !bucket_rollout(h, i, M, ra, st) ||
+          (with_grad && !bucket_grad(h, i, M, ga, st)) || hipEventRecord(e1, st) != hipSuccess ||
+          hipEventSynchronize(e1) != hipSuccess) {
+        cleanup();
+        return check_device("sim_tune timing");
+      }
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      if (best_ms < 0.f || ms < best_ms) { best_ms = ms; best = cand[c]; }
+    }
+    if ((s = retile(h, h->buckets[i], best)) != SIM_OK) { cleanup(); return s; }
+  }
+  cleanup();
+  for (int i = 0; i < n && teams && i < cap; ++i) teams[i] = h->buckets[i].team;
+  return n;
 }
 
 }  // extern "C"

@@ -125,15 +125,25 @@ def library():
     lib.rollout_grad.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, C.c_size_t, vp]
     lib.sim_describe_order.argtypes = [C.POINTER(SimDesc), C.c_int32, _I32P, _I32P, C.c_int32]
     lib.sim_describe_order.restype = C.c_int32
+    lib.sim_step_graph.argtypes = [vp, C.c_int32, vp, vp, vp, C.c_int32, vp, C.POINTER(vp)]
+    lib.sim_graph_launch.argtypes = [vp, vp]
+    lib.sim_graph_destroy.argtypes = [vp]
+    lib.sim_tune.argtypes = [vp, vp, vp, C.c_int32, C.c_int32, _I32P, C.c_int32, vp]
+    lib.sim_tune.restype = C.c_int32
+    lib.sim_get_teams.argtypes = [vp, _I32P, C.c_int32]
+    lib.sim_get_teams.restype = C.c_int32
+    lib.sim_set_teams.argtypes = [vp, _I32P, C.c_int32]
     for fn in ("sim_init", "sim_destroy", "sim_get_info", "sim_lambda_offsets", "sim_step", "rollout",
-               "rollout_grad"):
+               "rollout_grad", "sim_step_graph", "sim_graph_launch", "sim_graph_destroy", "sim_set_teams"):
         getattr(lib, fn).restype = C.c_int
     _lib = lib
     return lib
 
 
 EXPORTED = ["sim_abi_version", "sim_last_error", "sim_init", "sim_destroy", "sim_get_info",
-            "sim_lambda_offsets", "sim_describe_order", "sim_step", "rollout", "rollout_grad"]
+            "sim_lambda_offsets", "sim_describe_order", "sim_step", "rollout", "rollout_grad",
+            "sim_step_graph", "sim_graph_launch", "sim_graph_destroy", "sim_tune", "sim_get_teams",
+            "sim_set_teams"]
 
 
 def describe_order(w, env):
@@ -185,8 +195,11 @@ class Simulator:
         lo = np.zeros(w.n_envs + 1, np.int32)
         _check(self.lib, self.lib.sim_lambda_offsets(h, lo.ctypes.data_as(_I32P)), "sim_lambda_offsets")
         self.lam_off = lo
+        self._graphs = []
 
     def close(self):
+        for g in list(getattr(self, "_graphs", [])):
+            g.close()
         if getattr(self, "h", None):
             self.lib.sim_destroy(self.h)
             self.h = None
@@ -249,3 +262,54 @@ class Simulator:
                                self._stream())
         _check(self.lib, st, "sim_step")
         return xo, lo, flags
+
+    def step_graph(self, n_steps, x, u, lam, t0=0, flags=None):
+        """Capture n_steps steps into a replayable HIP graph.  x is a [2, 18, B]
+        CUDA tensor (step k reads x[k % 2], writes x[(k + 1) % 2]); u the
+        control rows [n_steps, J] or the controller weights; lam [lam_size],
+        updated in place.  The tensors must outlive the graph."""
+        g = C.c_void_p()
+        st = self.lib.sim_step_graph(self.h, int(n_steps), _ptr(x), _ptr(u), _ptr(lam), int(t0), _ptr(flags),
+                                     C.byref(g))
+        _check(self.lib, st, "sim_step_graph")
+        sg = StepGraph(self, g, (x, u, lam, flags))
+        self._graphs.append(sg)
+        return sg
+
+    def teams(self):
+        n = self.lib.sim_get_teams(self.h, None, 0)
+        _check(self.lib, min(n, 0), "sim_get_teams")
+        out = np.zeros(max(n, 1), np.int32)
+        self.lib.sim_get_teams(self.h, out.ctypes.data_as(_I32P), n)
+        return out[:n].copy()
+
+    def set_teams(self, teams):
+        teams = np.ascontiguousarray(teams, dtype=np.int32)
+        _check(self.lib, self.lib.sim_set_teams(self.h, teams.ctypes.data_as(_I32P), len(teams)), "sim_set_teams")
+
+    def tune(self, x0, u, with_grad=True, max_candidates=3):
+        """Time each bucket at its admissible team widths and keep the fastest;
+        returns the chosen widths.  Results do not depend on them."""
+        n = self.lib.sim_get_teams(self.h, None, 0)
+        out = np.zeros(max(n, 1), np.int32)
+        r = self.lib.sim_tune(self.h, _ptr(x0), _ptr(u), int(bool(with_grad)), int(max_candidates),
+                              out.ctypes.data_as(_I32P), n, self._stream())
+        _check(self.lib, min(r, 0), "sim_tune")
+        return out[:n].copy()
+
+
+class StepGraph:
+    """A captured sequence of steps (see Simulator.step_graph)."""
+
+    def __init__(self, sim, g, keep):
+        self.sim, self.g, self._keep = sim, g, keep
+
+    def launch(self):
+        _check(self.sim.lib, self.sim.lib.sim_graph_launch(self.g, self.sim._stream()), "sim_graph_launch")
+
+    def close(self):
+        if self.g:
+            self.sim.lib.sim_graph_destroy(self.g)
+            self.g = None
+            if self in self.sim._graphs:
+                self.sim._graphs.remove(self)

@@ -356,6 +356,37 @@ def uneven_chains(n_envs: int = 16384, T: int = 500, seed_salt: int = 0, sizes=N
                     ckpt_every=50)
 
 
+WSN_SIZES = (7, 64, 64, 3)     # per-contact warm-start network
+WSN_PARAMS = 7 * 64 + 64 + 64 * 64 + 64 + 64 * 3 + 3
+
+
+def warm_start_chains(n_envs: int = 16384, T: int = 500, seed_salt: int = 0, tol: float = 1e-5,
+                      max_iters: int = 1000, ws_w=None, fb_iters: int = 5, fb_tol: float = 1e-3) -> Workload:
+    """The uneven-chain distribution solved to a residual tolerance instead of
+    a fixed sweep count, with the plain warm start at factor 1 (the carried
+    impulses themselves) or, with ws_w, the learned warm start of contacts."""
+    w = uneven_chains(n_envs=n_envs, T=T, seed_salt=seed_salt)
+    w.name = "warm-start-chains"
+    w.warm = 1.0
+    w.extra = dict(w.extra or {})
+    w.extra["solve"] = dict(mode=1, tol=float(tol), max_iters=int(max_iters))
+    if ws_w is not None:
+        w.extra["ws"] = dict(w=np.asarray(ws_w, np.float64), fb_iters=int(fb_iters), fb_tol=float(fb_tol))
+    return w
+
+
+def wsn_init(seed_salt: int = 0, scale: float = 1.0) -> np.ndarray:
+    """Seeded He-uniform initial weights of the warm-start network, FP32
+    values: W1[64][7] b1[64] W2[64][64] b2[64] W3[3][64] b3[3]."""
+    rng = rng_for(5, seed_salt)
+    parts = []
+    for fan_in, fan_out in ((7, 64), (64, 64), (64, 3)):
+        lim = scale * math.sqrt(6.0 / fan_in)
+        parts.append(rng.uniform(-lim, lim, size=fan_out * fan_in))
+        parts.append(np.zeros(fan_out))
+    return f32(np.concatenate(parts))
+
+
 # --------------------------------------------------------------------------
 # small hand-made models for closed-form checks
 # --------------------------------------------------------------------------

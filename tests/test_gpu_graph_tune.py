@@ -1,0 +1,139 @@
+"""Replayable step graphs and the tile autotuner (GPU).
+
+A captured step sequence must reproduce the eager sim_step loop bit for bit
+on every replay (the graph holds only kernels: queue resets are fill
+kernels, not memsets), with the program's own eager work and
+synchronisations between replays.  Re-tiling by the autotuner must not change
+any result bit, since the sweep order does not depend on the team width.
+"""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+import pytest
+
+from gpu_helpers import to_dev
+from paper_1611_01652_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _eager_steps(s, x0, u_rows, lam0, t0, n):
+    x, lam = x0.clone(), lam0.clone()
+    for k in range(n):
+        uk = u_rows if s.info.n_params else u_rows[k]
+        x, lam, flags = s.step(x, uk, lam, t0 + k)
+    return x, lam, flags
+
+
+def _check_graph_replays(s, x0, u_rows, t0, n, reps=3):
+    import torch
+    lam0 = torch.zeros(max(s.info.lam_size, 1), device="cuda")
+    xe, le, fe = _eager_steps(s, x0, u_rows, lam0, t0, n)
+    torch.cuda.synchronize()
+    xbuf = torch.zeros((2,) + tuple(x0.shape), device="cuda")
+    lam = torch.zeros_like(lam0)
+    flags = torch.zeros(max(s.info.n_envs, 1), dtype=torch.int32, device="cuda")
+    g = s.step_graph(n, xbuf, u_rows, lam, t0=t0, flags=flags)
+    try:
+        for r in range(reps):
+            xbuf[0].copy_(x0)
+            xbuf[1].zero_()
+            lam.zero_()
+            flags.fill_(7)
+            g.launch()
+            torch.cuda.synchronize()
+            assert torch.equal(xbuf[n % 2], xe), ("replay", r, (xbuf[n % 2] - xe).abs().max().item())
+            assert torch.equal(lam, le), ("replay lambda", r)
+            assert torch.equal(flags[: s.info.n_envs], fe[: s.info.n_envs]), ("replay flags", r)
+            # the program's own eager work between replays
+            xe2, _, _ = _eager_steps(s, x0, u_rows, lam0, t0, 1)
+            torch.cuda.synchronize()
+            assert torch.isfinite(xe2).all()
+    finally:
+        g.close()
+
+
+def test_step_graph_matches_eager_steps_on_several_buckets():
+    import torch
+    from paper_1611_01652_amd.sim import Simulator
+    w = W.uneven_chains(n_envs=160, T=40, seed_salt=21)
+    s = Simulator(w)
+    assert len(s.teams()) > 1, "want several buckets (fork/join inside the graph)"
+    x0, u = to_dev(w)
+    _say("case step graph, chains 160 envs x 12 steps, buckets", s.teams().tolist())
+    _check_graph_replays(s, x0, u[:12].contiguous(), 0, 12)
+    _say("case step graph, odd step count 5 from row 3")
+    _check_graph_replays(s, x0, u[3:8].contiguous(), 3, 5)
+    s.close()
+
+
+def test_step_graph_with_controller_and_clock_offset():
+    import torch
+    from paper_1611_01652_amd.sim import Simulator
+    w = W.quadruped(n_envs=24, T_min=40, T_max=40, mlp_w=W.mlp_init(zero_output=False, out_scale=0.1))
+    s = Simulator(w)
+    x0, _ = to_dev(w)
+    wt = torch.tensor(w.extra["mlp"]["w"], dtype=torch.float32, device="cuda")
+    _say("case step graph with controller, t0 = 7, 9 steps")
+    _check_graph_replays(s, x0, wt, 7, 9)
+    from paper_1611_01652_amd.sim import SimError
+    xbuf = torch.zeros((2,) + tuple(x0.shape), device="cuda")
+    lam = torch.zeros(max(s.info.lam_size, 1), device="cuda")
+    with pytest.raises(SimError):
+        s.step_graph(5, xbuf, wt, lam, t0=38)     # t0 + n_steps > T_max
+    s.close()
+
+
+def test_tune_keeps_every_result_bit():
+    import torch
+    from paper_1611_01652_amd.sim import SimError, Simulator
+    w = W.uneven_chains(n_envs=256, T=60, seed_salt=22)
+    s = Simulator(w)
+    x0, u = to_dev(w)
+    dl = torch.ones(w.n_envs, device="cuda")
+
+    def run():
+        r = s.rollout(x0, u)
+        g = s.rollout_grad(x0, u, r["ckpt"], dl)
+        torch.cuda.synchronize()
+        return [r["loss"], r["x_final"], r["ckpt"]] + [g[k] for k in sorted(g)]
+
+    before_teams = s.teams()
+    ref = run()
+    _say("case tune, chains 256 envs x 60 steps, teams", before_teams.tolist())
+    chosen = s.tune(x0, u, with_grad=True, max_candidates=3)
+    _say("  chosen", chosen.tolist())
+    assert len(chosen) == len(before_teams)
+    assert (chosen >= before_teams).all() and all(int(t) & (int(t) - 1) == 0 for t in chosen)
+    assert np.array_equal(s.teams(), chosen)
+    for a, b in zip(run(), ref):
+        assert torch.equal(a, b)
+    wide = np.minimum(before_teams * 2, 64)
+    s.set_teams(wide)
+    for a, b in zip(run(), ref):
+        assert torch.equal(a, b)
+    bad = before_teams.copy()
+    if bad[0] > 1:
+        bad[0] //= 2
+        with pytest.raises(SimError):
+            s.set_teams(bad)
+    with pytest.raises(SimError):
+        s.set_teams(before_teams[:-1])
+    # a live graph holds the tile lists: re-tiling is refused until it is gone
+    xbuf = torch.zeros((2,) + tuple(x0.shape), device="cuda")
+    lam = torch.zeros(max(s.info.lam_size, 1), device="cuda")
+    g = s.step_graph(2, xbuf, u[:2].contiguous(), lam)
+    with pytest.raises(SimError):
+        s.set_teams(before_teams)
+    g.close()
+    s.set_teams(before_teams)
+    for a, b in zip(run(), ref):
+        assert torch.equal(a, b)
+    s.close()

@@ -69,9 +69,11 @@ def _desc64(w):
             a = a if a.size else np.zeros(1)
             keep.append(a)
             setattr(d, name, a.ctypes.data_as(C.POINTER(C.c_double)))
-    d.n_envs, d.T_max, d.dt = w.n_envs, w.T_max, w.dt
-    d.gravity = (C.c_double * 3)(*w.gravity)
-    d.beta, d.gamma, d.spec_margin, d.warm = w.beta, w.gamma, w.spec_margin, w.warm
+    # scalars as the FP32 values the GPU library receives (the oracle does the same)
+    f = lambda v: float(np.float32(v))
+    d.n_envs, d.T_max, d.dt = w.n_envs, w.T_max, f(w.dt)
+    d.gravity = (C.c_double * 3)(*[f(g) for g in w.gravity])
+    d.beta, d.gamma, d.spec_margin, d.warm = f(w.beta), f(w.gamma), f(w.spec_margin), f(w.warm)
     d.n_iters, d.ground, d.loss_kind, d.loss_mask = w.n_iters, w.ground, w.loss_kind, w.loss_mask
     d.ckpt_every, d.min_team = w.ckpt_every, 0
     mlp = w.extra.get("mlp") if getattr(w, "extra", None) else None

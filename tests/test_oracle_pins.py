@@ -32,13 +32,19 @@ from oracle import Oracle
 from paper_1611_01652_amd import workloads as W
 
 
+# The oracle receives the scalar constants (dt, gravity, softening) as the
+# FP32 values the GPU library gets; closed forms use the same values.
+F32 = lambda v: float(np.float32(v))
+
+
 def test_free_fall_closed_form_and_gradient():
-    p0, v0, dt, n = np.array([0.3, -0.2, 5.0]), np.array([1.0, -0.5, 2.0]), 0.01, 60
-    w = W.single_sphere(p=p0, v=v0, ground=False, T=n, dt=dt)
+    p0, v0, n = np.array([0.3, -0.2, 5.0]), np.array([1.0, -0.5, 2.0]), 60
+    w = W.single_sphere(p=p0, v=v0, ground=False, T=n, dt=0.01)
+    dt = F32(0.01)
     w.target = W.f32([[0.1, 0.2, 0.3]])
     o = Oracle(w)
     r = o.rollout()
-    g = np.array([0, 0, -9.81])
+    g = np.array([0, 0, -F32(9.81)])
     # v_k = v0 + k dt g ; p_n = p0 + dt sum_{k=1..n} v_k
     p_exp = W.f32(p0) + n * dt * W.f32(v0) + g * dt * dt * n * (n + 1) / 2
     v_exp = W.f32(v0) + n * dt * g
@@ -58,7 +64,7 @@ def test_ball_at_rest_stays_exactly():
     np.testing.assert_allclose(r["x_final"], w.x0, rtol=0, atol=1e-14)
     # the carried normal impulse equals the weight impulse m g dt
     m = 1.0 / w.inv_mass[0]
-    assert abs(r["lam_final"][0] - m * 9.81 * w.dt) < 1e-12
+    assert abs(r["lam_final"][0] - m * F32(9.81) * F32(w.dt)) < 1e-12
     np.testing.assert_allclose(r["lam_final"][1:], 0.0, atol=1e-15)
 
 
@@ -82,8 +88,9 @@ def test_sliding_ball_ends_rolling_at_five_sevenths(v0, mu):
 
 
 def test_spin_angle_is_n_atan_dt_w():
-    wz, dt, n = 3.0, 0.01, 500
-    w = W.single_sphere(p=(0, 0, 0), w=(0, 0, wz), ground=False, gravity=(0, 0, 0), T=n, dt=dt)
+    wz, n = 3.0, 500
+    w = W.single_sphere(p=(0, 0, 0), w=(0, 0, wz), ground=False, gravity=(0, 0, 0), T=n, dt=0.01)
+    dt = F32(0.01)
     R = Oracle(w).rollout()["x_final"][0, 3:12].reshape(3, 3)
     ang = math.atan2(R[1, 0], R[0, 0])
     expect = math.remainder(n * math.atan(dt * W.f32(wz)), 2 * math.pi)
@@ -186,8 +193,8 @@ def test_frictionless_pile_converges_to_lcp_solution():
     P = w.x0[:, :3]
     rad = w.sphere_radius
     invm = w.inv_mass
-    dt, beta = w.dt, w.beta
-    vstar = w.x0[:, 12:15] + dt * np.array([0, 0, -9.81])
+    dt, beta = float(np.float32(w.dt)), float(np.float32(w.beta))   # the FP32 inputs
+    vstar = w.x0[:, 12:15] + dt * np.array([0, 0, -float(np.float32(9.81))])
     rows = []
     for i in range(3):   # ground candidates
         C = P[i, 2] - rad[i]
