@@ -243,6 +243,35 @@ int32_t sim_tune(sim_handle h, const float* x0, const float* u, int32_t with_gra
 int32_t sim_get_teams(sim_handle h, int32_t* teams, int32_t cap);
 sim_status sim_set_teams(sim_handle h, const int32_t* teams, int32_t n);
 
+/* ---- Learned warm start: the per-contact network. ----
+ * 7 features -> 64 ReLU -> 64 ReLU -> 3 outputs; the 4,867 parameters are
+ * packed W1[64][7] b1[64] W2[64][64] b2[64] W3[3][64] b3[3].  The kernels
+ * use bfloat16 weights, inputs and hidden activations with FP32
+ * accumulation on matrix cores.  Training records (SIM_REC_FLOATS floats,
+ * written by rollout_solve) hold the features in floats 0..6 and the
+ * targets in floats 7..9; see rollout_solve for their meaning.  All pointers
+ * are device memory; calls are asynchronous on `stream`. */
+#define SIM_WSN_IN 7
+#define SIM_WSN_HID 64
+#define SIM_WSN_OUT 3
+#define SIM_WSN_PARAMS 4867
+#define SIM_REC_FLOATS 16
+/* w_bf16[p] = bfloat16(w[p]) (nearest, ties to even). */
+sim_status wsn_to_bf16(const float* w, uint16_t* w_bf16, void* stream);
+/* y[i][0..2] = net(x[i * stride + 0..6]) for i < n. */
+sim_status wsn_forward(const uint16_t* w_bf16, const float* x, int64_t stride, int64_t n, float* y, void* stream);
+/* Bytes of workspace wsn_loss_grad needs for n records. */
+int64_t wsn_workspace_bytes(int64_t n);
+/* Mean-squared error over n records rec[i * stride + ...] (features 0..6,
+ * targets 7..9): *loss = (1/n) sum_i |net(x_i) - t_i|^2 and grad[4867] its
+ * gradient (either may be NULL).  Deterministic (fixed reduction order). */
+sim_status wsn_loss_grad(const uint16_t* w_bf16, const float* rec, int64_t stride, int64_t n, float* loss,
+                         float* grad, void* workspace, size_t workspace_bytes, void* stream);
+/* One Adam step (Kingma and Ba, with bias correction; step counts from 1) on
+ * the FP32 master weights w, moments m and v, then w_bf16 = bfloat16(w). */
+sim_status wsn_adam(float* w, uint16_t* w_bf16, const float* grad, float* m, float* v, int32_t step, float lr,
+                    float beta1, float beta2, float eps, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

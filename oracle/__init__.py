@@ -53,6 +53,8 @@ def _load():
         _lib.oracle_rollout_ex.restype = C.c_longlong
         _lib.oracle_bf16.argtypes = [C.c_double]
         _lib.oracle_bf16.restype = C.c_double
+        _lib.oracle_wsn_forward.argtypes = [dp, dp, C.c_int, C.c_int, dp]
+        _lib.oracle_wsn_forward.restype = None
     return _lib
 
 
@@ -258,3 +260,15 @@ class Oracle:
         lam = np.zeros(max(self.lam_size, 1)) if lam is None else np.ascontiguousarray(lam, dtype=np.float64)
         u = np.ascontiguousarray(np.zeros(max(w.n_joints, 1)) if u is None else u, dtype=np.float64)
         return int(self.lib.oracle_count_tape_edges(C.byref(self._m), env, _dp(x), _dp(lam), _dp(u), int(t)))
+
+
+def wsn_forward_bf16(w, x):
+    """The warm-start network with bfloat16 rounding of weights, inputs and
+    hidden activations (as the learned warm start evaluates it), FP64
+    otherwise.  x: [n, >= 7]."""
+    lib = _load()
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    y = np.zeros((max(x.shape[0], 1), 3))
+    lib.oracle_wsn_forward(_dp(w), _dp(x), x.shape[1], x.shape[0], _dp(y))
+    return y[: x.shape[0]]

@@ -864,6 +864,10 @@ long long oracle_rollout_ex(const oracle_model* m, const double* x0, double* los
 
 double oracle_bf16(double x) { return bf16(x); }
 
+void oracle_wsn_forward(const double* w, const double* x, int stride, int n, double* y) {
+  for (int i = 0; i < n; ++i) wsn_eval(w, x + (size_t)i * stride, y + 3 * (size_t)i);
+}
+
 // Reverse mode over the unrolled trajectory: forward once storing step-start
 // states, then one tape per step, last step first, carrying the adjoints of
 // the state and of the warm-start impulses.

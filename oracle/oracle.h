@@ -85,6 +85,9 @@ long long oracle_rollout_ex(const oracle_model* m, const double* x0, double* los
                             long long rec_cap, int n_threads);
 /* bfloat16 rounding (nearest, ties to even) of a double */
 double oracle_bf16(double x);
+/* the warm-start network as used by the learned warm start (bfloat16
+   weights, inputs and hidden activations): y[i][0..2] = net(x[i*stride..]) */
+void oracle_wsn_forward(const double* w, const double* x, int stride, int n, double* y);
 
 long long oracle_count_flops(const oracle_model* m, int env, const double* x, const double* lam,
                              const double* u, int t);

@@ -672,4 +672,64 @@ int32_t sim_tune(sim_handle h, const float* x0, const float* u, int32_t with_gra
   return n;
 }
 
+// ------------------------------------------------------------- warm-start network
+namespace {
+int device_cus() {
+  static int cus[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  if (!cus[dev]) {
+    int n = 0;
+    (void)hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev);
+    cus[dev] = n > 0 ? n : 256;
+  }
+  return cus[dev];
+}
+}  // namespace
+
+int64_t wsn_workspace_bytes(int64_t n) {
+  if (n < 0) return fail(SIM_E_ARG, "wsn_workspace_bytes: n < 0");
+  return (int64_t)wsn_parts(n, device_cus()) * (SIM_WSN_PARAMS + 1) * (int64_t)sizeof(float);
+}
+
+sim_status wsn_to_bf16(const float* w, uint16_t* w_bf16, void* stream) {
+  if (!w || !w_bf16) return fail(SIM_E_ARG, "wsn_to_bf16: null argument");
+  if (launch_wsn_to_bf16(w, w_bf16, (hipStream_t)stream) != hipSuccess) return check_device("wsn_to_bf16");
+  return SIM_OK;
+}
+
+sim_status wsn_forward(const uint16_t* w_bf16, const float* x, int64_t stride, int64_t n, float* y, void* stream) {
+  if (n < 0 || stride < SIM_WSN_IN) return fail(SIM_E_ARG, "wsn_forward: n < 0 or stride < 7");
+  if (n == 0) return SIM_OK;
+  if (!w_bf16 || !x || !y) return fail(SIM_E_ARG, "wsn_forward: null argument");
+  if (launch_wsn_forward(w_bf16, x, stride, n, y, device_cus(), (hipStream_t)stream) != hipSuccess)
+    return check_device("wsn_forward");
+  return SIM_OK;
+}
+
+sim_status wsn_loss_grad(const uint16_t* w_bf16, const float* rec, int64_t stride, int64_t n, float* loss,
+                         float* grad, void* workspace, size_t workspace_bytes, void* stream) {
+  if (n < 0 || stride < SIM_WSN_IN + SIM_WSN_OUT) return fail(SIM_E_ARG, "wsn_loss_grad: n < 0 or stride < 10");
+  if (!w_bf16 || (n > 0 && !rec) || !workspace) return fail(SIM_E_ARG, "wsn_loss_grad: null argument");
+  const int parts = wsn_parts(n, device_cus());
+  if (workspace_bytes < (size_t)parts * (SIM_WSN_PARAMS + 1) * sizeof(float))
+    return fail(SIM_E_NOMEM, "wsn_loss_grad: workspace smaller than wsn_workspace_bytes(n)");
+  if (launch_wsn_loss_grad(w_bf16, rec, stride, n, (float*)workspace, parts, grad, loss, (hipStream_t)stream) !=
+      hipSuccess)
+    return check_device("wsn_loss_grad");
+  return SIM_OK;
+}
+
+sim_status wsn_adam(float* w, uint16_t* w_bf16, const float* grad, float* m, float* v, int32_t step, float lr,
+                    float beta1, float beta2, float eps, void* stream) {
+  if (!w || !w_bf16 || !grad || !m || !v) return fail(SIM_E_ARG, "wsn_adam: null argument");
+  if (step < 1 || !(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f))
+    return fail(SIM_E_ARG, "wsn_adam: step < 1 or beta outside [0, 1)");
+  const float c1 = (float)(1.0 / (1.0 - std::pow((double)beta1, step)));
+  const float c2 = (float)(1.0 / (1.0 - std::pow((double)beta2, step)));
+  if (launch_wsn_adam(w, w_bf16, grad, m, v, lr, beta1, beta2, eps, c1, c2, (hipStream_t)stream) != hipSuccess)
+    return check_device("wsn_adam");
+  return SIM_OK;
+}
+
 }  // extern "C"

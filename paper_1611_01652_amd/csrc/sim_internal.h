@@ -32,4 +32,14 @@ hipError_t launch_rollout_grad(const DevModel& M, const TileSet& ts, int team, i
                                const GradArgs& a, hipStream_t st);
 hipError_t allow_large_lds(int bytes);
 
+// warm-start network (wsn_kernels.hip)
+int wsn_parts(long long n, int n_cu);
+hipError_t launch_wsn_loss_grad(const uint16_t* w, const float* rec, long long stride, long long n, float* partial,
+                                int n_parts, float* grad, float* loss, hipStream_t st);
+hipError_t launch_wsn_forward(const uint16_t* w, const float* x, long long stride, long long n, float* y,
+                              int n_cu, hipStream_t st);
+hipError_t launch_wsn_adam(float* w, uint16_t* wb, const float* g, float* m, float* v, float lr, float b1, float b2,
+                           float eps, float c1, float c2, hipStream_t st);
+hipError_t launch_wsn_to_bf16(const float* w, uint16_t* wb, hipStream_t st);
+
 }  // namespace sim

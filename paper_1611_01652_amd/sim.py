@@ -133,8 +133,15 @@ def library():
     lib.sim_get_teams.argtypes = [vp, _I32P, C.c_int32]
     lib.sim_get_teams.restype = C.c_int32
     lib.sim_set_teams.argtypes = [vp, _I32P, C.c_int32]
+    lib.wsn_to_bf16.argtypes = [vp, vp, vp]
+    lib.wsn_forward.argtypes = [vp, vp, C.c_int64, C.c_int64, vp, vp]
+    lib.wsn_workspace_bytes.argtypes = [C.c_int64]
+    lib.wsn_workspace_bytes.restype = C.c_int64
+    lib.wsn_loss_grad.argtypes = [vp, vp, C.c_int64, C.c_int64, vp, vp, vp, C.c_size_t, vp]
+    lib.wsn_adam.argtypes = [vp, vp, vp, vp, vp, C.c_int32, C.c_float, C.c_float, C.c_float, C.c_float, vp]
     for fn in ("sim_init", "sim_destroy", "sim_get_info", "sim_lambda_offsets", "sim_step", "rollout",
-               "rollout_grad", "sim_step_graph", "sim_graph_launch", "sim_graph_destroy", "sim_set_teams"):
+               "rollout_grad", "sim_step_graph", "sim_graph_launch", "sim_graph_destroy", "sim_set_teams",
+               "wsn_to_bf16", "wsn_forward", "wsn_loss_grad", "wsn_adam"):
         getattr(lib, fn).restype = C.c_int
     _lib = lib
     return lib
@@ -143,7 +150,7 @@ def library():
 EXPORTED = ["sim_abi_version", "sim_last_error", "sim_init", "sim_destroy", "sim_get_info",
             "sim_lambda_offsets", "sim_describe_order", "sim_step", "rollout", "rollout_grad",
             "sim_step_graph", "sim_graph_launch", "sim_graph_destroy", "sim_tune", "sim_get_teams",
-            "sim_set_teams"]
+            "sim_set_teams", "wsn_to_bf16", "wsn_forward", "wsn_workspace_bytes", "wsn_loss_grad", "wsn_adam"]
 
 
 def describe_order(w, env):
@@ -313,3 +320,65 @@ class StepGraph:
             self.g = None
             if self in self.sim._graphs:
                 self.sim._graphs.remove(self)
+
+
+# ---------------------------------------------------------------- warm-start network
+WSN_PARAMS = 4867
+REC_FLOATS = 16
+
+
+def _stream():
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class WarmStartNet:
+    """The per-contact warm-start network on the GPU: FP32 master weights, their
+    bfloat16 copy used by the kernels, Adam moments.  Tensors are torch CUDA
+    tensors; every step runs in the library's kernels."""
+
+    def __init__(self, w0):
+        import torch
+        self.torch = torch
+        self.lib = library()
+        self.w = torch.tensor(np.asarray(w0, np.float32), device="cuda").contiguous()
+        assert self.w.numel() == WSN_PARAMS
+        self.wb = torch.empty(WSN_PARAMS, dtype=torch.int16, device="cuda")
+        self.m = torch.zeros_like(self.w)
+        self.v = torch.zeros_like(self.w)
+        self.grad = torch.zeros_like(self.w)
+        self.loss = torch.zeros(1, device="cuda")
+        self.step_count = 0
+        self._ws = None
+        _check(self.lib, self.lib.wsn_to_bf16(_ptr(self.w), _ptr(self.wb), _stream()), "wsn_to_bf16")
+
+    def weights_bf16_as_float(self):
+        """The bfloat16 weights the kernels use, as FP32 values (host numpy)."""
+        b = self.wb.cpu().numpy().view(np.uint16).astype(np.uint32) << 16
+        return b.view(np.float32).astype(np.float64)
+
+    def forward(self, x):
+        """x: [n, >= 7] CUDA float32 (features in columns 0..6) -> [n, 3]"""
+        t = self.torch
+        n = x.shape[0]
+        y = t.empty((max(n, 1), 3), device="cuda")
+        _check(self.lib, self.lib.wsn_forward(_ptr(self.wb), _ptr(x), x.stride(0), n, _ptr(y), _stream()),
+               "wsn_forward")
+        return y[:n]
+
+    def loss_grad(self, rec):
+        """rec: [n, >= 10] CUDA float32 records; returns (loss tensor [1], grad [4867])."""
+        n = rec.shape[0]
+        need = int(self.lib.wsn_workspace_bytes(n))
+        if self._ws is None or self._ws.numel() * 4 < need:
+            self._ws = self.torch.empty(need // 4 + 1, device="cuda")
+        st = self.lib.wsn_loss_grad(_ptr(self.wb), _ptr(rec), rec.stride(0), n, _ptr(self.loss), _ptr(self.grad),
+                                    _ptr(self._ws), self._ws.numel() * 4, _stream())
+        _check(self.lib, st, "wsn_loss_grad")
+        return self.loss, self.grad
+
+    def adam(self, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+        self.step_count += 1
+        st = self.lib.wsn_adam(_ptr(self.w), _ptr(self.wb), _ptr(self.grad), _ptr(self.m), _ptr(self.v),
+                               self.step_count, lr, beta1, beta2, eps, _stream())
+        _check(self.lib, st, "wsn_adam")

@@ -1,0 +1,127 @@
+"""GPU kernels of the warm-start network against the oracle.
+
+* forward: equal to the oracle's network with the same bfloat16 rounding of
+  weights, inputs and hidden activations up to FP32 accumulation order (an
+  activation that lands on a rounding tie can round the other way: bounded
+  by 1e-3 of the output scale), and within 2e-2 of the plain FP64 network;
+* loss and gradient: within 2e-2 (per parameter block, relative norm) of the
+  plain FP64 mean-squared-error gradient: the backward pass rounds its deltas
+  to bfloat16 as well (8 significant bits, 4e-3 per operand);
+* Adam: equal to the FP64 update within FP32 rounding;
+* ragged record counts (not a multiple of the 16-row tile), n = 0 and n = 1.
+"""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import wsn_forward_bf16, wsnet
+from paper_1611_01652_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _records(n, seed=0, stride=16):
+    rng = np.random.default_rng(seed)
+    R = np.zeros((n, stride), np.float32)
+    R[:, 0] = rng.uniform(-2, 10, n)          # gap / dt
+    R[:, 1:4] = rng.normal(0, 0.5, (n, 3))    # J v
+    R[:, 4] = np.abs(rng.normal(0, 0.1, n))   # carried impulses / mass
+    R[:, 5:7] = rng.normal(0, 0.05, (n, 2))
+    R[:, 7] = np.maximum(R[:, 4] - 0.3 * R[:, 1], 0)   # a smooth target
+    R[:, 8:10] = 0.5 * R[:, 5:7] - 0.1 * R[:, 2:4]
+    R[:, 10:] = 1.0
+    return R
+
+
+def _net(seed=1):
+    from paper_1611_01652_amd.sim import WarmStartNet
+    rng = np.random.default_rng(seed)
+    w = W.wsn_init(seed_salt=seed) + W.f32(rng.normal(0, 0.02, W.WSN_PARAMS))
+    return WarmStartNet(w)
+
+
+def test_forward_matches_the_rounding_oracle():
+    import torch
+    net = _net()
+    wb = net.weights_bf16_as_float()
+    for n in (1, 16, 1000, 4099):
+        R = _records(n, seed=n)
+        _say("case wsn forward, n =", n)
+        y = net.forward(torch.tensor(R, device="cuda")).cpu().numpy().astype(np.float64)
+        ref = wsn_forward_bf16(wb, R.astype(np.float64))
+        scale = np.abs(ref).max()
+        assert np.abs(y - ref).max() <= 1e-3 * scale, (np.abs(y - ref).max(), scale)
+        rel = np.linalg.norm(y - ref, axis=1) / np.maximum(np.linalg.norm(ref, axis=1), 1e-3 * scale)
+        assert np.median(rel) < 1e-5
+        plain = wsnet.forward(wb, R[:, :7].astype(np.float64))
+        assert np.linalg.norm(y - plain) <= 2e-2 * np.linalg.norm(plain)
+
+
+def test_loss_gradient_matches_fp64_and_is_deterministic():
+    import torch
+    net = _net(2)
+    wb = net.weights_bf16_as_float()
+    for n in (1, 1000, 8197):
+        R = _records(n, seed=10 + n)
+        _say("case wsn loss/grad, n =", n)
+        Rd = torch.tensor(R, device="cuda")
+        L, g = net.loss_grad(Rd)
+        L1, g1 = float(L.item()), g.cpu().numpy().astype(np.float64)
+        L2, g2 = net.loss_grad(Rd)
+        assert float(L2.item()) == L1 and np.array_equal(g2.cpu().numpy(), g1.astype(np.float32))
+        Lr, gr = wsnet.loss_grad(wb, R[:, :7].astype(np.float64), R[:, 7:10].astype(np.float64))
+        assert abs(L1 - Lr) <= 1e-2 * Lr, (L1, Lr)
+        offs = [0, 448, 512, 4608, 4672, 4864, 4867]
+        for a, b in zip(offs[:-1], offs[1:]):
+            d = np.linalg.norm(g1[a:b] - gr[a:b])
+            assert d <= 2e-2 * np.linalg.norm(gr[a:b]) + 1e-9, (a, b, d, np.linalg.norm(gr[a:b]))
+
+
+def test_empty_batch_gives_zero_loss_and_gradient():
+    import torch
+    net = _net(3)
+    R = torch.zeros((0, 16), device="cuda")
+    net.grad.fill_(7.0)
+    L, g = net.loss_grad(R)
+    assert float(L.item()) == 0.0 and float(g.abs().max().item()) == 0.0
+
+
+def test_adam_matches_fp64_update():
+    import torch
+    net = _net(4)
+    w = net.w.cpu().numpy().astype(np.float64)
+    m = np.zeros_like(w)
+    v = np.zeros_like(w)
+    rng = np.random.default_rng(4)
+    for step in range(1, 4):
+        g = W.f32(rng.normal(0, 1e-2, W.WSN_PARAMS))
+        net.grad.copy_(torch.tensor(g, device="cuda"))
+        net.adam(1e-3)
+        w, m, v = wsnet.adam(w, g.astype(np.float64), m, v, step, 1e-3)
+    got = net.w.cpu().numpy().astype(np.float64)
+    np.testing.assert_allclose(got, w, rtol=1e-5, atol=1e-7)
+    np.testing.assert_array_equal(net.weights_bf16_as_float(),
+                                  torch.tensor(got, dtype=torch.float32).to(torch.bfloat16).double().numpy())
+
+
+def test_training_on_the_gpu_reduces_the_loss():
+    import torch
+    net = _net(5)
+    R = torch.tensor(_records(20000, seed=5), device="cuda")
+    L0 = float(net.loss_grad(R)[0].item())
+    gen = torch.Generator(device="cuda").manual_seed(0)
+    for it in range(300):
+        idx = torch.randint(0, R.shape[0], (1024,), device="cuda", generator=gen)
+        net.loss_grad(R.index_select(0, idx).contiguous())
+        net.adam(3e-3)
+    L1 = float(net.loss_grad(R)[0].item())
+    _say("  loss", L0, "->", L1)
+    assert L1 < 0.1 * L0
