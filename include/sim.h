@@ -82,6 +82,12 @@ typedef enum {
                            (J_e), sin, cos of 2 pi f t dt]; tanh hidden layers, linear output (J_e);
                            weights W1[h1][in] b1 W2[h2][h1] b2 W3[out][h2] b3 */
 
+/* solver and warm-start kinds */
+#define SIM_SOLVE_FIXED 0 /* n_iters sweeps per step */
+#define SIM_SOLVE_TOL 1   /* sweeps until the residual is at most tol */
+#define SIM_WS_PLAIN 0    /* warm start: the previous step's impulses times `warm` */
+#define SIM_WS_LEARNED 1  /* contacts: the warm-start network, with fallback */
+
 /* Model description (host memory, read during sim_init; the caller keeps
  * ownership).  Indices of bodies/joints/spheres are global (over all envs),
  * and each env's items must lie inside its own CSR range. */
@@ -128,6 +134,22 @@ typedef struct {
   int32_t mlp_sizes[4];          /* in, h1, h2, out; every env has out = J_e, in = 2 J_e + 2;
                                     h1, h2 <= 256 */
   float clock_hz;                /* clock frequency f of the controller inputs */
+  /* Solve to a residual tolerance (forward only; rollout_grad refuses): after
+     each sweep the residual is the largest |change of impulse| / effective
+     mass over the active rows (a friction block: the norm of its tangent
+     change over its mass), in m/s; sweeps stop at the first residual <= tol
+     or after max_iters sweeps. */
+  int32_t solve_mode;            /* SIM_SOLVE_FIXED (n_iters sweeps) or SIM_SOLVE_TOL */
+  float tol;
+  int32_t max_iters;
+  /* Learned warm start of contacts (tolerance mode only): contact impulses
+     from the warm-start network (SIM_WSN_*), projected onto lambda_n >= 0,
+     |lambda_t| <= mu lambda_n; if the residual after fb_iters sweeps exceeds
+     fb_tol, that env's solve restarts from the plain warm start. */
+  int32_t ws_kind;               /* SIM_WS_PLAIN or SIM_WS_LEARNED */
+  const float* ws_net;           /* host [SIM_WSN_PARAMS] FP32 weights (rounded to bfloat16 by sim_init) */
+  int32_t fb_iters;
+  float fb_tol;
 } sim_model_desc;
 
 /* Sizes derived by sim_init. */
@@ -183,6 +205,27 @@ sim_status sim_step(sim_handle h, const float* x_in, float* x_out, const float* 
  * env_flags[E] (device, may be NULL). */
 sim_status rollout(sim_handle h, const float* x0, const float* u, float* loss_env, float* x_final,
                    float* lam_final, float* ckpt, uint32_t* env_flags, void* stream);
+
+/* Forward rollout of a model in tolerance mode (solve_mode SIM_SOLVE_TOL),
+ * as `rollout` without checkpoints, plus (each may be NULL, all device):
+ *   iters_env[E]: Gauss-Seidel sweeps summed over the env's steps, counting
+ *     the sweeps a rejected learned warm start cost;
+ *   fallbacks_env[E]: steps whose learned warm start was rejected;
+ *   records[rec_cap][SIM_REC_FLOATS]: one training record per placed contact
+ *     of every step t with t % rec_every == 0 whose solve converged: floats
+ *     0..6 the features (gap / dt, J v of the normal and both tangent rows at
+ *     the velocities before the warm start, the plain warm-start impulses over
+ *     their effective masses), 7..9 the converged impulses over their
+ *     effective masses, 10 m_n, 11 m_t, then env, step and candidate code
+ *     (kind << 24 | id; ground: index of the sphere among the env's ground
+ *     spheres, pair: local body a | local body b << 12) as int32 bit
+ *     patterns, 15 zero.  *rec_count (device,
+ *     zeroed by the caller) is advanced atomically by the number of records
+ *     wanted; only the first rec_cap are written, in no fixed order.
+ * Returns SIM_E_STATE for a fixed-sweep model. */
+sim_status rollout_solve(sim_handle h, const float* x0, const float* u, float* loss_env, float* x_final,
+                         float* lam_final, uint32_t* env_flags, int32_t* iters_env, int32_t* fallbacks_env,
+                         float* records, int64_t rec_cap, uint64_t* rec_count, int32_t rec_every, void* stream);
 
 /* Reverse mode.  Given the checkpoints written by `rollout` with the same
  * x0 and u, and dL/dloss_env (device [E]), writes (each may be NULL):

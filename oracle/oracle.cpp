@@ -209,7 +209,7 @@ template <class S> struct ConRows {
   V3<S> t1, t2;   // contact tangents (for the tangent impulse carry)
   S mt = S(0.0);  // friction block effective mass
   S gap = S(0.0); // contact gap
-  int code = 0;   // candidate code: kind << 24 | id (ground: global sphere, pair: local a | local b << 12)
+  int code = 0;   // candidate code: kind << 24 | id (ground: the env's ground-sphere index, pair: local a | local b << 12)
 };
 
 // Solver statistics and training records of one step (tolerance mode).
@@ -449,7 +449,7 @@ void step_env(const Model& M, const EnvTopo& E, const StepIn<S>& in, S* xn, S* l
         n = ez;
         rb_ = (cen[s] - rad * n) - B.p[b];
         store = 5 * E.nj + 4 * k.idx;
-        C.code = (1 << 24) | gs;
+        C.code = (1 << 24) | k.idx;
       } else {
         const PairCand& pc = E.pairs[k.idx];
         a = pc.ba - E.b0; b = pc.bb - E.b0;

@@ -62,8 +62,8 @@ typedef struct {
 /* record: features f[7] (gap/dt, J_n v, J_t1 v, J_t2 v at the predicted
    velocities, plain warm-start impulses over their effective masses), target
    y[3] (converged impulses over their effective masses), m_n, m_t, env, step,
-   candidate code (kind << 24 | id; ground: global sphere, pair: local body a |
-   local body b << 12), 0 */
+   candidate code (kind << 24 | id; ground: index of the sphere among the env's
+   ground spheres, pair: local body a | local body b << 12), 0 */
 #define ORACLE_REC 16
 
 int oracle_lambda_size(const oracle_model* m, int* out_offsets /* [E+1] or NULL */);

@@ -17,6 +17,10 @@ struct RolloutArgs {
   float* lam_final;    // [lam_tot] or null
   float* ckpt;         // [n_ckpt][18 B + lam_tot] or null
   uint32_t* flags;     // [E] or null
+  // tolerance mode: sweeps and fallbacks per env, training records
+  int* iters;          // [E] or null
+  int* fallbacks;      // [E] or null
+  RecArgs rec;
 };
 
 struct GradArgs {
@@ -66,7 +70,9 @@ SHD uint32_t nonfinite_flag(const Team& tm, const Env& E) {
   return tm.team_any(bad) ? 1u : 0u;
 }
 
-template <class Team>
+// SOLVE: the model solves to a residual tolerance (a separate instantiation,
+// so the fixed-sweep kernels carry none of its state).
+template <class Team, bool SOLVE = false>
 SHD_FLAT void env_rollout(const Team& tm, const DevModel& M, const Env& E, bool valid, const RolloutArgs& a) {
   if (valid) {
     load_env_static(tm, M, E);
@@ -82,7 +88,9 @@ SHD_FLAT void env_rollout(const Team& tm, const DevModel& M, const Env& E, bool 
     const bool act = t < T;
     if (act && a.ckpt && t % K == 0) write_ckpt(tm, M, E, a.ckpt + (size_t)(t / K) * ckpt_stride(M));
     tm.sync();
-    env_step(tm, M, E, (a.u && !M.ctrl) ? a.u + (size_t)t * M.J : nullptr, act, t);
+    const float* u_row = (a.u && !M.ctrl) ? a.u + (size_t)t * M.J : nullptr;
+    if (SOLVE) env_step_solve(tm, M, E, u_row, act, t, &a.rec);
+    else env_step(tm, M, E, u_row, act, t);
     if (act && tm.tl == 0) {
       const float* p = E.body(E.lb) + BP;
       const float p0[3] = {p0x, 0.f, 0.f};
@@ -98,11 +106,13 @@ SHD_FLAT void env_rollout(const Team& tm, const DevModel& M, const Env& E, bool 
       a.loss[E.e] = loss;
       fl |= (uint32_t)(*reinterpret_cast<int*>(E.misc() + MISC_FLAGS));
       if (a.flags) a.flags[E.e] = fl;
+      if (a.iters) a.iters[E.e] = *reinterpret_cast<int*>(E.misc() + MISC_ITERS);
+      if (a.fallbacks) a.fallbacks[E.e] = *reinterpret_cast<int*>(E.misc() + MISC_FB);
     }
   }
 }
 
-template <class Team>
+template <class Team, bool SOLVE = false>
 SHD_FLAT void env_single_step(const Team& tm, const DevModel& M, const Env& E, bool valid, const StepArgs& a) {
   if (valid) {
     load_env_static(tm, M, E);
@@ -110,7 +120,8 @@ SHD_FLAT void env_single_step(const Team& tm, const DevModel& M, const Env& E, b
     load_ws(tm, E, a.lam_in);
   }
   tm.sync();
-  env_step(tm, M, E, a.u, valid, a.t);
+  if (SOLVE) env_step_solve(tm, M, E, a.u, valid, a.t, nullptr);
+  else env_step(tm, M, E, a.u, valid, a.t);
   tm.sync();
   uint32_t fl = valid ? nonfinite_flag(tm, E) : 0u;
   if (valid) {

@@ -195,8 +195,9 @@ sim_status build_env(const sim_model_desc& d, int e, HostEnv& H) {
     mf = d.mlp_sizes[0] + d.mlp_sizes[1] + d.mlp_sizes[2];
     ma = d.mlp_sizes[3] + d.mlp_sizes[2] + d.mlp_sizes[1] + d.mlp_sizes[0];
   }
-  H.fwd_floats = make_lay(H.nb, H.nj, H.G, H.P, H.ncol, H.ncand, H.nslot, H.lam, d.n_iters, false, mf, ma).total;
-  H.adj_floats = make_lay(H.nb, H.nj, H.G, H.P, H.ncol, H.ncand, H.nslot, H.lam, d.n_iters, true, mf, ma).total;
+  const int vs = vsave_floats(d.ws_kind, H.nb);
+  H.fwd_floats = make_lay(H.nb, H.nj, H.G, H.P, H.ncol, H.ncand, H.nslot, H.lam, d.n_iters, false, mf, ma, vs).total;
+  H.adj_floats = make_lay(H.nb, H.nj, H.G, H.P, H.ncol, H.ncand, H.nslot, H.lam, d.n_iters, true, mf, ma, vs).total;
   return SIM_OK;
 }
 
@@ -213,6 +214,7 @@ sim_status pack_model(const sim_model_desc* d, PackedModel& P, std::string& err)
   P.team_of.assign(E, 1);
   P.fwd_of.assign(E, 0);
   P.adj_of.assign(E, 0);
+  P.ccap_of.assign(E, 0);
   P.seg_total = 0;
   P.tape_rows = 0;
   if (d->ctrl_kind != 0 && d->ctrl_kind != 1) { g_msg = nullptr; err = "unknown ctrl_kind"; return SIM_E_ARG; }
@@ -242,6 +244,7 @@ sim_status pack_model(const sim_model_desc* d, PackedModel& P, std::string& err)
     P.team_of[e] = H.team;
     P.fwd_of[e] = H.fwd_floats;
     P.adj_of[e] = H.adj_floats;
+    P.ccap_of[e] = H.ccap;
   }
   g_msg = nullptr;
   return SIM_OK;

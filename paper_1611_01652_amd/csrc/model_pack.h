@@ -9,7 +9,7 @@
 namespace sim {
 
 struct PackedModel {
-  std::vector<int> hdr, topo, lam_off, team_of, fwd_of, adj_of;
+  std::vector<int> hdr, topo, lam_off, team_of, fwd_of, adj_of, ccap_of;
   std::vector<float> cst, target;
   long long seg_total = 0;
   long long tape_rows = 0;   // env-steps of the controller tape (sum of T_e)

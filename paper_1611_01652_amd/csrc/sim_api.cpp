@@ -31,6 +31,7 @@ struct Bucket {
   std::vector<int> envs_host;   // tiles * (64/team)
   int n_tiles = 0;
   int floats_fwd = 0, floats_adj = 0;
+  int ccap_max = 0;             // largest contact capacity of its envs
   int* envs_dev = nullptr;
 };
 
@@ -60,6 +61,7 @@ struct sim_model {
   long long tape_rows = 0, seg_floats = 0, tape_floats = 0;
   int lds_allowed = 65536;      // dynamic LDS limit set on the kernels
   int n_graphs = 0;             // live step graphs (they hold the tile lists)
+  uint16_t* d_wsn = nullptr;    // warm-start network, bfloat16
 };
 
 struct sim_graph_s {
@@ -91,6 +93,7 @@ void release(sim_model* h) {
   if (h->d_clock) (void)hipFree(h->d_clock);
   if (h->d_tiles) (void)hipFree(h->d_tiles);
   if (h->d_map) (void)hipFree(h->d_map);
+  if (h->d_wsn) (void)hipFree(h->d_wsn);
   for (auto sx : h->streams) (void)hipStreamDestroy(sx);
   for (auto ex : h->joins) (void)hipEventDestroy(ex);
   if (h->fork) (void)hipEventDestroy(h->fork);
@@ -122,9 +125,17 @@ sim_status run_buckets(sim_model* h, hipStream_t st, F launch, const char* what)
   return SIM_OK;
 }
 
-int grid_for(const sim_model* h, const Bucket& b, int floats) {
-  const int bytes = (64 / b.team) * floats * 4;
-  int per_cu = bytes > 0 ? (160 * 1024) / bytes : 8;
+// LDS bytes of a workgroup: the env tiles and, for the forward kernels of a
+// learned warm start, the shared network region.
+long long fwd_bytes(const DevModel& M, int team, int floats_fwd, int ccap_max) {
+  const int epw = 64 / team;
+  return 4LL * ((long long)epw * floats_fwd + (M.ws_kind ? wsn_shared_floats(epw * ccap_max) : 0));
+}
+long long adj_bytes(int team, int floats_adj) { return 4LL * (64 / team) * floats_adj; }
+long long fwd_bytes(const sim_model* h, const Bucket& b) { return fwd_bytes(h->M, b.team, b.floats_fwd, b.ccap_max); }
+
+int grid_for(const sim_model* h, const Bucket& b, long long bytes) {
+  int per_cu = bytes > 0 ? (int)((160 * 1024) / bytes) : 8;
   per_cu = std::max(1, std::min(per_cu, 8));
   return std::max(1, std::min(b.n_tiles, h->n_cu * per_cu));
 }
@@ -134,22 +145,22 @@ bool bucket_step(sim_model* h, size_t i, const DevModel& M, const StepArgs& a, h
   const Bucket& b = h->buckets[i];
   TileSet ts{b.envs_dev, b.n_tiles, b.floats_fwd, h->d_queue + i};
   if (launch_zero(ts.queue, 1, sx) != hipSuccess) return false;
-  const size_t lds = (size_t)(64 / b.team) * b.floats_fwd * 4;
-  return launch_step(M, ts, b.team, grid_for(h, b, b.floats_fwd), lds, a, sx) == hipSuccess;
+  const long long lds = fwd_bytes(h, b);
+  return launch_step(M, ts, b.team, grid_for(h, b, lds), (size_t)lds, a, sx) == hipSuccess;
 }
 bool bucket_rollout(sim_model* h, size_t i, const DevModel& M, const RolloutArgs& a, hipStream_t sx) {
   const Bucket& b = h->buckets[i];
   TileSet ts{b.envs_dev, b.n_tiles, b.floats_fwd, h->d_queue + i};
   if (launch_zero(ts.queue, 1, sx) != hipSuccess) return false;
-  const size_t lds = (size_t)(64 / b.team) * b.floats_fwd * 4;
-  return launch_rollout(M, ts, b.team, grid_for(h, b, b.floats_fwd), lds, a, sx) == hipSuccess;
+  const long long lds = fwd_bytes(h, b);
+  return launch_rollout(M, ts, b.team, grid_for(h, b, lds), (size_t)lds, a, sx) == hipSuccess;
 }
 bool bucket_grad(sim_model* h, size_t i, const DevModel& M, const GradArgs& a, hipStream_t sx) {
   const Bucket& b = h->buckets[i];
   TileSet ts{b.envs_dev, b.n_tiles, b.floats_adj, h->d_queue + i};
   if (launch_zero(ts.queue, 1, sx) != hipSuccess) return false;
-  const size_t lds = (size_t)(64 / b.team) * b.floats_adj * 4;
-  return launch_rollout_grad(M, ts, b.team, grid_for(h, b, b.floats_adj), lds, a, sx) == hipSuccess;
+  const long long lds = adj_bytes(b.team, b.floats_adj);
+  return launch_rollout_grad(M, ts, b.team, grid_for(h, b, lds), (size_t)lds, a, sx) == hipSuccess;
 }
 
 sim_status launch_steps(sim_model* h, const float* x_in, float* x_out, const float* u, const float* lam_in,
@@ -166,7 +177,8 @@ sim_status launch_steps(sim_model* h, const float* x_in, float* x_out, const flo
 std::vector<int> admissible_teams(const sim_model* h, const Bucket& b) {
   std::vector<int> out;
   for (int t = b.team_min; t <= 64; t *= 2)
-    if ((64 / t) * (long long)b.floats_adj * 4 <= h->max_lds) out.push_back(t);
+    if (std::max(adj_bytes(t, b.floats_adj), fwd_bytes(h->M, t, b.floats_fwd, b.ccap_max)) <= h->max_lds)
+      out.push_back(t);
   return out;
 }
 
@@ -180,7 +192,7 @@ sim_status retile(sim_model* h, Bucket& b, int team) {
   const int n_tiles = ((int)ids.size() + epw - 1) / epw;
   std::vector<int> host((size_t)n_tiles * epw, -1);
   std::copy(ids.begin(), ids.end(), host.begin());
-  const int bytes = epw * b.floats_adj * 4;
+  const int bytes = (int)std::max(adj_bytes(team, b.floats_adj), fwd_bytes(h->M, team, b.floats_fwd, b.ccap_max));
   if (bytes > h->lds_allowed) {
     if (allow_large_lds(std::min(bytes, h->max_lds)) != hipSuccess)
       return fail(SIM_E_DEVICE, "cannot raise the dynamic LDS limit");
@@ -198,7 +210,8 @@ sim_status retile(sim_model* h, Bucket& b, int team) {
   h->info.max_lds_bytes = 0;
   for (const auto& x : h->buckets) {
     h->info.n_tiles += x.n_tiles;
-    h->info.max_lds_bytes = std::max(h->info.max_lds_bytes, (64 / x.team) * x.floats_adj * 4);
+    h->info.max_lds_bytes = std::max(h->info.max_lds_bytes, (int)std::max(adj_bytes(x.team, x.floats_adj),
+                                                                           fwd_bytes(h, x)));
   }
   return SIM_OK;
 }
@@ -240,6 +253,13 @@ sim_status sim_init(const sim_model_desc* d, sim_handle* out) {
   if (!(d->gamma >= 0.f)) return fail(SIM_E_ARG, "gamma < 0");
   if (d->min_team < 0 || d->min_team > 64 || (d->min_team & (d->min_team - 1)) != 0)
     return fail(SIM_E_ARG, "min_team must be 0 or a power of two <= 64");
+  if (d->solve_mode != SIM_SOLVE_FIXED && d->solve_mode != SIM_SOLVE_TOL) return fail(SIM_E_ARG, "unknown solve_mode");
+  if (d->solve_mode == SIM_SOLVE_TOL && (!(d->tol >= 0.f) || !std::isfinite(d->tol) || d->max_iters < 1))
+    return fail(SIM_E_ARG, "tolerance mode needs tol >= 0 and max_iters >= 1");
+  if (d->ws_kind != SIM_WS_PLAIN && d->ws_kind != SIM_WS_LEARNED) return fail(SIM_E_ARG, "unknown ws_kind");
+  if (d->ws_kind == SIM_WS_LEARNED && (d->solve_mode != SIM_SOLVE_TOL || !d->ws_net || d->fb_iters < 0 ||
+                                       !(d->fb_tol == d->fb_tol)))
+    return fail(SIM_E_ARG, "the learned warm start needs tolerance mode, ws_net, fb_iters >= 0 and a fb_tol");
   for (int e = 0; e < E; ++e) {
     if (d->T_env[e] < 0 || d->T_env[e] > d->T_max) return fail(SIM_E_SHAPE, "T_env outside [0, T_max]");
     if (d->loss_body[e] < d->env_body_off[e] || d->loss_body[e] >= d->env_body_off[e + 1])
@@ -264,6 +284,8 @@ sim_status sim_init(const sim_model_desc* d, sim_handle* out) {
   M.loss_kind = d->loss_kind; M.loss_mask = d->loss_mask; M.ckpt_every = d->ckpt_every;
   M.dt = d->dt; M.gx = d->gravity[0]; M.gy = d->gravity[1]; M.gz = d->gravity[2];
   M.beta = d->beta; M.gamma = d->gamma; M.spec = d->spec_margin; M.warm = d->warm;
+  M.solve_mode = d->solve_mode; M.tol = d->tol; M.max_iters = d->max_iters;
+  M.ws_kind = d->ws_kind; M.fb_iters = d->fb_iters; M.fb_tol = d->fb_tol;
 
   h->lam_off = P.lam_off;
   std::vector<int>& team_of = P.team_of;
@@ -277,8 +299,11 @@ sim_status sim_init(const sim_model_desc* d, sim_handle* out) {
     // latency chain, not by how many envs share the wave
     int team = std::max(team_of[e], d->min_team);
     if (team > 64) team = 64;
-    while (team < 64 && (64 / team) * (long long)adj_of[e] * 4 > h->max_lds) team *= 2;
-    if ((64 / team) * (long long)adj_of[e] * 4 > h->max_lds) {
+    auto need = [&](int t) {
+      return std::max(adj_bytes(t, adj_of[e]), fwd_bytes(M, t, P.fwd_of[e], P.ccap_of[e]));
+    };
+    while (team < 64 && need(team) > h->max_lds) team *= 2;
+    if (need(team) > h->max_lds) {
       release(h);
       return fail(SIM_E_UNSUPPORTED, "env " + std::to_string(e) + " needs " + std::to_string(adj_of[e] * 4) +
                                          " bytes of LDS, more than the device's " + std::to_string(h->max_lds));
@@ -312,8 +337,10 @@ sim_status sim_init(const sim_model_desc* d, sim_handle* out) {
       bk.envs_host[i] = ids[i];
       bk.floats_fwd = std::max(bk.floats_fwd, fwd_of[ids[i]]);
       bk.floats_adj = std::max(bk.floats_adj, adj_of[ids[i]]);
+      bk.ccap_max = std::max(bk.ccap_max, P.ccap_of[ids[i]]);
     }
-    max_lds = std::max(max_lds, epw * bk.floats_adj * 4);
+    max_lds = std::max(max_lds, (int)std::max(adj_bytes(team, bk.floats_adj),
+                                              fwd_bytes(M, team, bk.floats_fwd, bk.ccap_max)));
     h->buckets.push_back(bk);
   }
   // buckets run concurrently: one stream each (default priority), forked from
@@ -386,6 +413,18 @@ sim_status sim_init(const sim_model_desc* d, sim_handle* out) {
       release(h);
       return st;
     }
+  }
+  if (d->ws_kind == SIM_WS_LEARNED) {
+    std::vector<uint16_t> wb(SIM_WSN_PARAMS);
+    for (int p = 0; p < SIM_WSN_PARAMS; ++p) {
+      // bfloat16, nearest with ties to even
+      uint32_t u;
+      std::memcpy(&u, &d->ws_net[p], 4);
+      u += 0x7FFFu + ((u >> 16) & 1u);
+      wb[p] = (uint16_t)(u >> 16);
+    }
+    if ((st = upload(&h->d_wsn, wb)) != SIM_OK) { release(h); return st; }
+    M.wsn = h->d_wsn;
   }
   h->tape_rows = P.tape_rows;
   h->seg_floats = (P.seg_total + 63) & ~63LL;
@@ -485,11 +524,32 @@ sim_status rollout(sim_handle h, const float* x0, const float* u, float* loss_en
   sim_status s = check_device("rollout (earlier fault)");
   if (s != SIM_OK) return s;
   hipStream_t st = (hipStream_t)stream;
-  RolloutArgs a{x0, u, loss_env, x_final, lam_final, ckpt, env_flags};
+  RolloutArgs a{x0, u, loss_env, x_final, lam_final, ckpt, env_flags, nullptr, nullptr, RecArgs{nullptr, 0, nullptr, 0}};
   DevModel M = h->M;
   M.W = u;
   return run_buckets(h, st, [&](size_t i, hipStream_t sx) { return bucket_rollout(h, i, M, a, sx); },
                      "rollout launch");
+}
+
+sim_status rollout_solve(sim_handle h, const float* x0, const float* u, float* loss_env, float* x_final,
+                         float* lam_final, uint32_t* env_flags, int32_t* iters_env, int32_t* fallbacks_env,
+                         float* records, int64_t rec_cap, uint64_t* rec_count, int32_t rec_every, void* stream) {
+  if (!h) return fail(SIM_E_ARG, "rollout_solve: null handle");
+  if (h->M.solve_mode != SIM_SOLVE_TOL) return fail(SIM_E_STATE, "rollout_solve: the model is not in tolerance mode");
+  if (h->M.n_envs == 0) return SIM_OK;
+  if (!x0 || !loss_env) return fail(SIM_E_ARG, "rollout_solve: null x0 or loss_env");
+  if (h->M.J > 0 && h->M.T_max > 0 && !u) return fail(SIM_E_ARG, "rollout_solve: null control tape");
+  if (records && (rec_cap < 0 || !rec_count || rec_every < 1))
+    return fail(SIM_E_ARG, "rollout_solve: records need rec_cap >= 0, rec_count and rec_every >= 1");
+  sim_status s = check_device("rollout_solve (earlier fault)");
+  if (s != SIM_OK) return s;
+  hipStream_t st = (hipStream_t)stream;
+  RolloutArgs a{x0, u, loss_env, x_final, lam_final, nullptr, env_flags, iters_env, fallbacks_env,
+                RecArgs{records, (long long)rec_cap, (unsigned long long*)rec_count, records ? rec_every : 0}};
+  DevModel M = h->M;
+  M.W = u;
+  return run_buckets(h, st, [&](size_t i, hipStream_t sx) { return bucket_rollout(h, i, M, a, sx); },
+                     "rollout_solve launch");
 }
 
 sim_status rollout_grad(sim_handle h, const float* x0, const float* u, const float* ckpt, const float* dloss_env,
@@ -497,6 +557,8 @@ sim_status rollout_grad(sim_handle h, const float* x0, const float* u, const flo
                         float* g_damping, void* workspace, size_t workspace_bytes, void* stream) {
   if (!h) return fail(SIM_E_ARG, "rollout_grad: null handle");
   if (h->M.n_envs == 0) return SIM_OK;
+  if (h->M.solve_mode != SIM_SOLVE_FIXED)
+    return fail(SIM_E_UNSUPPORTED, "rollout_grad: the gradient is of the fixed-sweep step (solve_mode 0)");
   if (!x0 || !ckpt || !dloss_env) return fail(SIM_E_ARG, "rollout_grad: null x0, ckpt or dloss_env");
   if (h->M.J > 0 && h->M.T_max > 0 && !u) return fail(SIM_E_ARG, "rollout_grad: null control tape");
   if (!workspace || (int64_t)workspace_bytes < h->info.workspace_bytes)
@@ -619,6 +681,8 @@ int32_t sim_tune(sim_handle h, const float* x0, const float* u, int32_t with_gra
   if (M0.n_envs == 0) return n;
   if (!x0 || (M0.J > 0 && M0.T_max > 0 && !u)) return fail(SIM_E_ARG, "sim_tune: null x0 or controls");
   if (max_candidates < 1) return fail(SIM_E_ARG, "sim_tune: max_candidates < 1");
+  if (with_grad && M0.solve_mode != SIM_SOLVE_FIXED)
+    return fail(SIM_E_UNSUPPORTED, "sim_tune: no gradient in tolerance mode (use with_grad = 0)");
   if (h->n_graphs > 0) return fail(SIM_E_STATE, "sim_tune: destroy the step graphs of this handle first");
   sim_status s = check_device("sim_tune (earlier fault)");
   if (s != SIM_OK) return s;
@@ -643,7 +707,7 @@ int32_t sim_tune(sim_handle h, const float* x0, const float* u, int32_t with_gra
   DevModel M = M0;
   M.W = u;
   M.tape = ws ? ws + h->seg_floats : nullptr;
-  const RolloutArgs ra{x0, u, loss, nullptr, nullptr, ck, nullptr};
+  const RolloutArgs ra{x0, u, loss, nullptr, nullptr, ck, nullptr, nullptr, nullptr, RecArgs{nullptr, 0, nullptr, 0}};
   const GradArgs ga{x0, u, ck, dl, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, ws};
   // every bucket once at its current width: warms the code and writes the checkpoints
   for (int i = 0; i < n; ++i)

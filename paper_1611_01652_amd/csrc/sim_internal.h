@@ -34,6 +34,9 @@ hipError_t allow_large_lds(int bytes);
 
 // warm-start network (wsn_kernels.hip)
 int wsn_parts(long long n, int n_cu);
+// LDS floats of the shared region a forward workgroup needs for the learned
+// warm start with a contact list of n_list entries
+int wsn_shared_floats(int n_list);
 hipError_t launch_wsn_loss_grad(const uint16_t* w, const float* rec, long long stride, long long n, float* partial,
                                 int n_parts, float* grad, float* loss, hipStream_t st);
 hipError_t launch_wsn_forward(const uint16_t* w, const float* x, long long stride, long long n, float* y,

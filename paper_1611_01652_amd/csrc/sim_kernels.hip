@@ -7,13 +7,52 @@
 
 #include "drivers.h"
 #include "sim_internal.h"
+#include "wsn_core.h"
 
 namespace sim {
 
 struct TeamGPU {
   int tl, ts, lane;
   unsigned long long mask;
+  int team, n_teams;
+  // learned warm start: workgroup LDS base, per-team contact counts and the
+  // wave's contact list (extras-slot offsets from lds0), network image, tiles
+  float* lds0;
+  int *cnt, *map;
+  WsnNet net;
+  uint16_t *H1, *H2;
   __device__ void sync() const { __syncthreads(); }
+  __device__ float team_max(float v) const {
+    for (int o = ts >> 1; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, ts));
+    return v;
+  }
+  __device__ int* shared_cnt() const { return cnt; }
+  __device__ int* shared_map() const { return map; }
+  // The network on the wave's `total` listed contacts, 16 per tile: inputs at
+  // lds0[map[i] + XF .. +6], outputs to lds0[map[i] + XY .. +2].  Every lane
+  // of the wave calls it with the same total.
+  __device__ void wsn_rows(int total, const int* mp) const {
+    const int kq = 4 * (lane >> 4), c16 = lane & 15;
+    for (int t0 = 0; t0 < total; t0 += 16) {
+      const int i = t0 + c16;
+      const float* xrow = i < total ? lds0 + mp[i] + XF : nullptr;
+      const floatx4 y = wsn_forward_tile(net, xrow, H1, H2, lane);
+      for (int r = 0; r < 4; ++r) {
+        const int i2 = t0 + kq + r;
+        if (i2 < total && c16 < WSN_OUT) lds0[mp[i2] + XY + c16] = y[r];
+      }
+    }
+  }
+  // n records reserved by the team's first lane; the base index is returned
+  // to every lane of the team
+  __device__ unsigned long long reserve(unsigned long long* ctr, int n) const {
+    unsigned long long v = 0;
+    if (tl == 0 && n > 0) v = atomicAdd(ctr, (unsigned long long)n);
+    const int src = lane - tl;
+    const unsigned lo = __shfl((unsigned)(v & 0xffffffffull), src);
+    const unsigned hi = __shfl((unsigned)(v >> 32), src);
+    return ((unsigned long long)hi << 32) | lo;
+  }
   __device__ bool any(bool p) const { return __any((int)p) != 0; }
   // exclusive prefix count of p over the team's lanes, and the team total
   __device__ int prefix(bool p, int& total) const {
@@ -36,7 +75,27 @@ __device__ __forceinline__ TeamGPU make_team() {
   t.ts = TEAM;
   const int team = threadIdx.x / TEAM;
   t.mask = TEAM == 64 ? ~0ull : (((1ull << TEAM) - 1ull) << (team * TEAM));
+  t.team = team;
+  t.n_teams = 64 / TEAM;
+  t.lds0 = nullptr;
+  t.cnt = t.map = nullptr;
+  t.H1 = t.H2 = nullptr;
   return t;
+}
+
+// Shared region of the learned warm start after the env tiles: network
+// image, two activation tiles, per-team counts, contact list.
+__device__ __forceinline__ void setup_ws(TeamGPU& tm, const DevModel& M, float* lds, int env_floats) {
+  tm.lds0 = lds;
+  if (!M.ws_kind) return;
+  float* sh = lds + tm.n_teams * env_floats;
+  tm.net = wsn_net_at(sh);
+  tm.H1 = reinterpret_cast<uint16_t*>(sh + WSN_NET_FLOATS);
+  tm.H2 = tm.H1 + 16 * WSN_SH;
+  tm.cnt = reinterpret_cast<int*>(sh + WSN_NET_FLOATS + WSN_TILE_FLOATS);
+  tm.map = tm.cnt + 64;
+  wsn_stage(M.wsn, tm.net, threadIdx.x, 64);
+  __syncthreads();
 }
 
 // Take the next tile index; every lane of the wave gets the same value.
@@ -46,32 +105,34 @@ __device__ __forceinline__ int next_tile(int* queue) {
   return __shfl(v, 0);
 }
 
-template <int TEAM>
+template <int TEAM, int SOLVE>
 __global__ __launch_bounds__(64) void k_rollout(DevModel M, TileSet ts, RolloutArgs a) {
   extern __shared__ float lds[];
-  const TeamGPU tm = make_team<TEAM>();
+  TeamGPU tm = make_team<TEAM>();
+  if (SOLVE) setup_ws(tm, M, lds, ts.env_floats);
   const int team = threadIdx.x / TEAM;
   constexpr int EPW = 64 / TEAM;
   for (int tile = next_tile(ts.queue); tile < ts.n_tiles; tile = next_tile(ts.queue)) {
     const int ie = ts.envs[tile * EPW + team];
     const bool valid = ie >= 0;
     Env E = make_env(M, valid ? ie : 0, lds + team * ts.env_floats, M.n_iters, false);
-    env_rollout(tm, M, E, valid, a);
+    env_rollout<TeamGPU, SOLVE != 0>(tm, M, E, valid, a);
     __syncthreads();
   }
 }
 
-template <int TEAM>
+template <int TEAM, int SOLVE>
 __global__ __launch_bounds__(64) void k_step(DevModel M, TileSet ts, StepArgs a) {
   extern __shared__ float lds[];
-  const TeamGPU tm = make_team<TEAM>();
+  TeamGPU tm = make_team<TEAM>();
+  if (SOLVE) setup_ws(tm, M, lds, ts.env_floats);
   const int team = threadIdx.x / TEAM;
   constexpr int EPW = 64 / TEAM;
   for (int tile = next_tile(ts.queue); tile < ts.n_tiles; tile = next_tile(ts.queue)) {
     const int ie = ts.envs[tile * EPW + team];
     const bool valid = ie >= 0;
     Env E = make_env(M, valid ? ie : 0, lds + team * ts.env_floats, M.n_iters, false);
-    env_single_step(tm, M, E, valid, a);
+    env_single_step<TeamGPU, SOLVE != 0>(tm, M, E, valid, a);
     __syncthreads();
   }
 }
@@ -180,6 +241,18 @@ static hipError_t launch_one(K kern, const DevModel& M, const TileSet& ts, const
     case 64: return launch_one<64>(KNAME<64>, M, ts, ARGS, grid, lds, st);                      \
     default: return hipErrorInvalidValue;                                                       \
   }
+// forward kernels: instantiated for the fixed-sweep (S = 0) and the tolerance (S = 1) solve
+#define SIM_DISPATCH_S(TEAMV, KNAME, ARGS, S)                                                   \
+  switch (TEAMV) {                                                                              \
+    case 1: return launch_one<1>(KNAME<1, S>, M, ts, ARGS, grid, lds, st);                      \
+    case 2: return launch_one<2>(KNAME<2, S>, M, ts, ARGS, grid, lds, st);                      \
+    case 4: return launch_one<4>(KNAME<4, S>, M, ts, ARGS, grid, lds, st);                      \
+    case 8: return launch_one<8>(KNAME<8, S>, M, ts, ARGS, grid, lds, st);                      \
+    case 16: return launch_one<16>(KNAME<16, S>, M, ts, ARGS, grid, lds, st);                   \
+    case 32: return launch_one<32>(KNAME<32, S>, M, ts, ARGS, grid, lds, st);                   \
+    case 64: return launch_one<64>(KNAME<64, S>, M, ts, ARGS, grid, lds, st);                   \
+    default: return hipErrorInvalidValue;                                                       \
+  }
 
 hipError_t launch_zero(int* p, int n, hipStream_t st) {
   if (n <= 0) return hipSuccess;
@@ -189,11 +262,13 @@ hipError_t launch_zero(int* p, int n, hipStream_t st) {
 
 hipError_t launch_rollout(const DevModel& M, const TileSet& ts, int team, int grid, size_t lds,
                           const RolloutArgs& a, hipStream_t st) {
-  SIM_DISPATCH(team, k_rollout, a)
+  if (M.solve_mode) { SIM_DISPATCH_S(team, k_rollout, a, 1) }
+  SIM_DISPATCH_S(team, k_rollout, a, 0)
 }
 hipError_t launch_step(const DevModel& M, const TileSet& ts, int team, int grid, size_t lds, const StepArgs& a,
                        hipStream_t st) {
-  SIM_DISPATCH(team, k_step, a)
+  if (M.solve_mode) { SIM_DISPATCH_S(team, k_step, a, 1) }
+  SIM_DISPATCH_S(team, k_step, a, 0)
 }
 hipError_t launch_rollout_grad(const DevModel& M, const TileSet& ts, int team, int grid, size_t lds,
                                const GradArgs& a, hipStream_t st) {
@@ -214,10 +289,21 @@ hipError_t allow_large_lds(int bytes) {
   if ((e = allow_lds(K<16>, bytes)) != hipSuccess) return e;                                    \
   if ((e = allow_lds(K<32>, bytes)) != hipSuccess) return e;                                    \
   if ((e = allow_lds(K<64>, bytes)) != hipSuccess) return e;
-  SIM_ALLOW(k_rollout)
-  SIM_ALLOW(k_step)
+#define SIM_ALLOW_S(K, S)                                                                       \
+  if ((e = allow_lds(K<1, S>, bytes)) != hipSuccess) return e;                                  \
+  if ((e = allow_lds(K<2, S>, bytes)) != hipSuccess) return e;                                  \
+  if ((e = allow_lds(K<4, S>, bytes)) != hipSuccess) return e;                                  \
+  if ((e = allow_lds(K<8, S>, bytes)) != hipSuccess) return e;                                  \
+  if ((e = allow_lds(K<16, S>, bytes)) != hipSuccess) return e;                                 \
+  if ((e = allow_lds(K<32, S>, bytes)) != hipSuccess) return e;                                 \
+  if ((e = allow_lds(K<64, S>, bytes)) != hipSuccess) return e;
+  SIM_ALLOW_S(k_rollout, 0)
+  SIM_ALLOW_S(k_rollout, 1)
+  SIM_ALLOW_S(k_step, 0)
+  SIM_ALLOW_S(k_step, 1)
   SIM_ALLOW(k_rollout_grad)
 #undef SIM_ALLOW
+#undef SIM_ALLOW_S
   return e;
 }
 

@@ -98,6 +98,10 @@ struct DevModel {
   const float* clock; // [T_max][2] sin, cos of 2 pi f t dt
   const float* W;     // weights (set per call)
   float* tape;        // per env-step activations and deltas (reverse only)
+  // solve to a residual tolerance (forward only) and learned warm start
+  int solve_mode, max_iters, ws_kind, fb_iters;
+  float tol, fb_tol;
+  const uint16_t* wsn; // warm-start network, bfloat16 [4867]
 };
 // tape row: s, h1, h2, du, d2, d1 (pre-activation adjoints)
 SHD int tape_s(const DevModel&) { return 0; }
@@ -122,21 +126,25 @@ enum { AP = 0, AR = 3, AV = 12, AW = 15, AIW = 18, AIM = 27, AII = 28, ATQ = 31,
 enum { JAP = 0, JAC = 3, JXP = 6, JXC = 9, JUP = 12, JUC = 15, JD = 18, JU = 19, JS = 20 };
 // row slot; a contact uses 4 slots: normal, tangent 1, tangent 2, extras
 enum { RJL = 0, RJA = 3, RJB = 6, RWA = 9, RWB = 12, RM = 15, RBI = 16, RL = 17, RL0 = 18, RS = 20 };
-enum { XT1 = 0, XT2 = 3, XMT = 6, XGAP = 7, XSTORE = 8, XCODE = 9 };
+// contact extras slot: tangents, friction mass, gap, store offset, code, and
+// (tolerance mode) the warm-start features XF[7] and network outputs XY[3]
+enum { XT1 = 0, XT2 = 3, XMT = 6, XGAP = 7, XSTORE = 8, XCODE = 9, XF = 10, XY = 17 };
 // row adjoint slot
 enum { QJL = 0, QJA = 3, QJB = 6, QWA = 9, QWB = 12, QM = 15, QB = 16, QL = 17, RSA = 20 };
 
 struct Lay {
-  int body, jc, gs, topo, ws, rows, act_cnt, act_slot, act_code, misc, mlp;  // forward
+  int body, jc, gs, topo, ws, rows, act_cnt, act_slot, act_code, misc, mlp, vsave;  // forward
   int bodyA, rowsA, hist, wsA, jA, mlpA;                                     // adjoint
   int total_fwd, total;
 };
-enum { MISC_LOSS = 0, MISC_FLAGS = 1, MISC_NCON = 2, MISC_MU = 3, MISC_GMU = 4, MISC_GMUC = 5, MISC_N = 8 };
+enum { MISC_LOSS = 0, MISC_FLAGS = 1, MISC_NCON = 2, MISC_MU = 3, MISC_GMU = 4, MISC_GMUC = 5, MISC_ITERS = 6,
+       MISC_FB = 7, MISC_N = 8 };
 
 SHD int align4(int x) { return (x + 3) & ~3; }
 // mlp_f / mlp_a: controller floats per env (s, h1, h2 / du, d2, d1, sbar), 0 without one
+// vs_f: floats of saved predicted velocities (learned warm start), 0 without
 SHD Lay make_lay(int nb, int nj, int G, int P, int ncol, int ncand, int nslot, int lam, int n_iters, bool adj,
-                 int mlp_f = 0, int mlp_a = 0) {
+                 int mlp_f = 0, int mlp_a = 0, int vs_f = 0) {
   Lay L;
   int o = 0;
   L.body = o; o += align4(nb * BS);
@@ -150,6 +158,7 @@ SHD Lay make_lay(int nb, int nj, int G, int P, int ncol, int ncand, int nslot, i
   L.act_code = o; o += align4(ncand);
   L.misc = o; o += MISC_N;
   L.mlp = o; o += align4(mlp_f);
+  L.vsave = o; o += align4(vs_f);
   L.total_fwd = o;
   if (adj) {
     L.bodyA = o; o += align4(nb * BSA);
@@ -196,6 +205,7 @@ struct Env {
   SHD float* jA() const { return L + lay.jA; }
   SHD float* mlp() const { return L + lay.mlp; }
   SHD float* mlpA() const { return L + lay.mlpA; }
+  SHD float* vsave(int b) const { return L + lay.vsave + 6 * b; }
   // warm-start store offset of a candidate
   SHD int store_of(int code) const {
     const int k = cand_kind(code), i = cand_idx(code);
@@ -207,6 +217,7 @@ struct Env {
 
 SHD int mlp_floats_fwd(const DevModel& M) { return M.ctrl ? M.mlp_in + M.mlp_h1 + M.mlp_h2 : 0; }
 SHD int mlp_floats_adj(const DevModel& M) { return M.ctrl ? M.mlp_out + M.mlp_h2 + M.mlp_h1 + M.mlp_in : 0; }
+SHD int vsave_floats(int ws_kind, int nb) { return ws_kind ? 6 * nb : 0; }
 
 SHD Env make_env(const DevModel& M, int ie, float* lds, int n_iters, bool adj) {
   const int* h = M.hdr + (size_t)ie * H_COUNT;
@@ -219,7 +230,7 @@ SHD Env make_env(const DevModel& M, int ie, float* lds, int n_iters, bool adj) {
   E.gcst = M.cst + h[H_CST];
   E.L = lds;
   E.lay = make_lay(E.nb, E.nj, E.G, E.P, E.ncol, E.ncand, E.nslot, E.lam_size, n_iters, adj, mlp_floats_fwd(M),
-                   mlp_floats_adj(M));
+                   mlp_floats_adj(M), vsave_floats(M.ws_kind, E.nb));
   return E;
 }
 
@@ -253,6 +264,8 @@ SHD void load_env_static(const Team& tm, const DevModel& M, const Env& E) {
     E.misc()[MISC_MU] = E.gcst[cst_env(E)];
     E.misc()[MISC_LOSS] = 0.f;
     (*reinterpret_cast<int*>(E.misc() + MISC_FLAGS)) = 0;
+    (*reinterpret_cast<int*>(E.misc() + MISC_ITERS)) = 0;
+    (*reinterpret_cast<int*>(E.misc() + MISC_FB)) = 0;
   }
 }
 
@@ -706,7 +719,8 @@ SHD void rr_apply(const RR& R, VR& V, bool ha, float ima, float imb, float d) {
 }
 
 // One visit of a hinge (5 unbounded rows) with all data in registers.
-SHD void pgs_joint(const DevModel& M, const Env& E, int s, int a, int b, float* H) {
+// rmax (tolerance mode): running maximum of |delta lambda| / m over the rows.
+SHD void pgs_joint(const DevModel& M, const Env& E, int s, int a, int b, float* H, float* rmax = nullptr) {
   const bool ha = a >= 0;
   VR V;
   vr_load(V, E, a, b);
@@ -717,6 +731,7 @@ SHD void pgs_joint(const DevModel& M, const Env& E, int s, int a, int b, float* 
     const float sv_ = rr_jv(R[q], V, ha) + R[q].bias + M.gamma * R[q].lam;
     const float lt = R[q].lam - R[q].m * sv_;
     if (H) H[s + q] = lt;
+    if (rmax) *rmax = fmaxf(*rmax, fabsf(lt - R[q].lam) / R[q].m);
     rr_apply(R[q], V, ha, ima, imb, lt - R[q].lam);
     R[q].lam = lt;
   }
@@ -725,7 +740,8 @@ SHD void pgs_joint(const DevModel& M, const Env& E, int s, int a, int b, float* 
 }
 
 // One visit of a contact: normal row clamped at 0, then the friction disk.
-SHD void pgs_contact(const DevModel& M, const Env& E, int s, int a, int b, float mu, float* H) {
+SHD void pgs_contact(const DevModel& M, const Env& E, int s, int a, int b, float mu, float* H,
+                     float* rmax = nullptr) {
   const bool ha = a >= 0;
   VR V;
   vr_load(V, E, a, b);
@@ -738,6 +754,7 @@ SHD void pgs_contact(const DevModel& M, const Env& E, int s, int a, int b, float
     const float lt = R[0].lam - R[0].m * sv_;
     const float ln = lt <= 0.f ? 0.f : lt;
     if (H) H[s] = lt;
+    if (rmax) *rmax = fmaxf(*rmax, fabsf(ln - R[0].lam) / R[0].m);
     rr_apply(R[0], V, ha, ima, imb, ln - R[0].lam);
     R[0].lam = ln;
   }
@@ -746,6 +763,10 @@ SHD void pgs_contact(const DevModel& M, const Env& E, int s, int a, int b, float
   float n1, n2;
   disk(l1, l2, mu * R[0].lam, n1, n2);
   if (H) { H[s + 1] = l1; H[s + 2] = l2; }
+  if (rmax) {
+    const float d1 = n1 - R[1].lam, d2 = n2 - R[2].lam;
+    *rmax = fmaxf(*rmax, sqrtf(d1 * d1 + d2 * d2) / mt);
+  }
   rr_apply(R[1], V, ha, ima, imb, n1 - R[1].lam);
   rr_apply(R[2], V, ha, ima, imb, n2 - R[2].lam);
   E.row(s)[RL] = R[0].lam;
@@ -935,6 +956,263 @@ SHD void env_step(const Team& tm, const DevModel& M, const Env& E, const float* 
   f_rows(tm, M, E, act);
   f_warm(tm, E, act);
   f_pgs(tm, M, E, act, false);
+  f_integrate(tm, M, E, act);
+  f_store(tm, E, act);
+}
+
+// ------------------------------------------------------------------ solve to a tolerance
+// Training records of converged contacts (tolerance mode).
+struct RecArgs {
+  float* rec;                    // [cap][16] or null
+  long long cap;
+  unsigned long long* count;     // device counter
+  int every;                     // steps t with t % every == 0
+};
+
+SHD bool is_contact_colour(const Env& E, int c) {
+  const int lo = E.colstart(c), hi = E.colstart(c + 1);
+  return hi > lo && cand_kind(E.cand(lo)) != K_JOINT;
+}
+
+// Warm-start features of every active contact, at the predicted velocities
+// and the plain warm-start impulses, into its extras slot: gap / dt, J v of the
+// normal and both tangent rows, and the three plain impulses over their
+// effective masses.
+template <class Team>
+SHD void f_features(const Team& tm, const DevModel& M, const Env& E, bool act) {
+  for (int c = 0; tm.any(c < E.ncol && act); ++c) {
+    const bool cc = act && c < E.ncol && is_contact_colour(E, c);
+    const int n = cc ? E.act_cnt()[c] : 0;
+    const int lo = cc ? E.colstart(c) : 0;
+    for (int k = tm.tl; k < n; k += tm.ts) {
+      const int s = E.act_slot()[lo + k];
+      if (s < 0) continue;
+      const RowB rb = cand_bodies(E, E.act_code()[lo + k]);
+      const bool ha = rb.a >= 0;
+      VR V;
+      vr_load(V, E, rb.a, rb.b);
+      RR R0, R1, R2;
+      rr_load(R0, E.row(s));
+      rr_load(R1, E.row(s + 1));
+      rr_load(R2, E.row(s + 2));
+      float* x = E.row(s + 3);
+      const float mt = x[XMT];
+      x[XF + 0] = x[XGAP] / M.dt;
+      x[XF + 1] = rr_jv(R0, V, ha);
+      x[XF + 2] = rr_jv(R1, V, ha);
+      x[XF + 3] = rr_jv(R2, V, ha);
+      x[XF + 4] = E.row(s)[RL0] / R0.m;
+      x[XF + 5] = E.row(s + 1)[RL0] / mt;
+      x[XF + 6] = E.row(s + 2)[RL0] / mt;
+    }
+  }
+  tm.sync();
+}
+
+// Predicted velocities, kept for a restart from the plain warm start.
+template <class Team>
+SHD void f_save_vel(const Team& tm, const Env& E, bool act) {
+  if (act)
+    for (int b = tm.tl; b < E.nb; b += tm.ts)
+      for (int k = 0; k < 6; ++k) E.vsave(b)[k] = E.body(b)[BV + k];
+}
+
+// Learned warm start: the network on the features of every contact of the
+// wave (matrix cores, 16 contacts per tile), then the outputs, scaled by the
+// effective masses and projected onto lambda_n >= 0, |lambda_t| <= mu
+// lambda_n, replace the contacts' warm-start impulses.
+// Contacts placed in row slots (team-uniform): the first ccap active contacts
+// in colour-major order; any beyond the capacity were dropped and flagged.
+SHD int placed_contacts(const Env& E, bool act) {
+  int n = 0;
+  for (int c = 0; c < E.ncol && act; ++c)
+    if (is_contact_colour(E, c)) n += E.act_cnt()[c];
+  return n < E.ccap ? n : E.ccap;
+}
+
+template <class Team>
+SHD void f_learned_ws(const Team& tm, const DevModel& M, const Env& E, bool act) {
+  const int n_e = placed_contacts(E, act);
+  int* cnt = tm.shared_cnt();
+  int* map = tm.shared_map();
+  if (tm.tl == 0) cnt[tm.team] = act ? n_e : 0;
+  tm.sync();
+  int base = 0, total = 0;
+  for (int q = 0; q < tm.n_teams; ++q) {
+    const int v = cnt[q];
+    if (q < tm.team) base += v;
+    total += v;
+  }
+  int idx = base;
+  for (int c = 0; tm.any(c < E.ncol && act); ++c) {
+    const bool cc = act && c < E.ncol && is_contact_colour(E, c);
+    const int n = cc ? E.act_cnt()[c] : 0;
+    const int lo = cc ? E.colstart(c) : 0;
+    for (int k = tm.tl; k < n; k += tm.ts)
+      if (idx + k < base + n_e) map[idx + k] = (int)(E.row(E.act_slot()[lo + k] + 3) - tm.lds0);
+    idx += n;
+  }
+  tm.sync();
+  tm.wsn_rows(total, map);
+  tm.sync();
+  const float mu = E.misc()[MISC_MU];
+  for (int c = 0; tm.any(c < E.ncol && act); ++c) {
+    const bool cc = act && c < E.ncol && is_contact_colour(E, c);
+    const int n = cc ? E.act_cnt()[c] : 0;
+    const int lo = cc ? E.colstart(c) : 0;
+    for (int k = tm.tl; k < n; k += tm.ts) {
+      const int s = E.act_slot()[lo + k];
+      if (s < 0) continue;
+      const float* x = E.row(s + 3);
+      const float ln = fmaxf(E.row(s)[RM] * x[XY], 0.f);
+      float l1 = x[XMT] * x[XY + 1], l2 = x[XMT] * x[XY + 2];
+      const float rho = mu * ln, nrm = sqrtf(l1 * l1 + l2 * l2);
+      if (!(nrm <= rho)) { l1 *= rho / nrm; l2 *= rho / nrm; }
+      E.row(s)[RL] = E.row(s)[RL0] = ln;
+      E.row(s + 1)[RL] = E.row(s + 1)[RL0] = l1;
+      E.row(s + 2)[RL] = E.row(s + 2)[RL0] = l2;
+    }
+  }
+  tm.sync();
+}
+
+// Restart from the plain warm start: predicted velocities back, every row's
+// impulse back to the carried one (joints never changed theirs).
+template <class Team>
+SHD void f_restart(const Team& tm, const DevModel& M, const Env& E, bool act) {
+  if (act)
+    for (int b = tm.tl; b < E.nb; b += tm.ts)
+      for (int k = 0; k < 6; ++k) E.body(b)[BV + k] = E.vsave(b)[k];
+  for (int c = 0; tm.any(c < E.ncol && act); ++c) {
+    const int n = (act && c < E.ncol) ? E.act_cnt()[c] : 0;
+    const int lo = (act && c < E.ncol) ? E.colstart(c) : 0;
+    for (int k = tm.tl; k < n; k += tm.ts) {
+      const int s = E.act_slot()[lo + k];
+      if (s < 0) continue;
+      if (cand_kind(E.act_code()[lo + k]) == K_JOINT) {
+        for (int q = 0; q < 5; ++q) E.row(s + q)[RL] = E.row(s + q)[RL0];
+      } else {
+        const float* x = E.row(s + 3);
+        const float* w = E.ws() + *reinterpret_cast<const int*>(x + XSTORE);
+        const f3 Lt = mk3(w[1], w[2], w[3]);
+        E.row(s)[RL] = E.row(s)[RL0] = M.warm * w[0];
+        E.row(s + 1)[RL] = E.row(s + 1)[RL0] = M.warm * dot(ld3(x + XT1), Lt);
+        E.row(s + 2)[RL] = E.row(s + 2)[RL0] = M.warm * dot(ld3(x + XT2), Lt);
+      }
+    }
+  }
+  tm.sync();
+}
+
+// Sweeps until the residual (largest |delta lambda| / m of a sweep) is at most
+// tol or `limit` sweeps have run; it / res carry the count and the last
+// residual (team-uniform).
+template <class Team>
+SHD void f_pgs_tol(const Team& tm, const DevModel& M, const Env& E, bool live, int& it, float& res, int limit) {
+  const float mu = E.misc()[MISC_MU];
+  for (;;) {
+    const bool run = live && res > M.tol && it < limit;
+    if (!tm.any(run)) break;
+    float r = 0.f;
+    for (int c = 0; tm.any(c < E.ncol && run); ++c) {
+      const int n = (run && c < E.ncol) ? E.act_cnt()[c] : 0;
+      const int lo = (run && c < E.ncol) ? E.colstart(c) : 0;
+      for (int k = tm.tl; k < n; k += tm.ts) {
+        const int s = E.act_slot()[lo + k];
+        if (s < 0) continue;
+        const int code = E.act_code()[lo + k];
+        const RowB rb = cand_bodies(E, code);
+        if (cand_kind(code) == K_JOINT) pgs_joint(M, E, s, rb.a, rb.b, nullptr, &r);
+        else pgs_contact(M, E, s, rb.a, rb.b, mu, nullptr, &r);
+      }
+      tm.sync();
+    }
+    if (run) {
+      res = tm.team_max(r);
+      ++it;
+    }
+  }
+}
+
+// One record per active contact of a converged step: features, converged
+// impulses over their effective masses, m_n, m_t, env, step, code (the last
+// three as int32 bit patterns).
+template <class Team>
+SHD void f_records(const Team& tm, const DevModel& M, const Env& E, bool act, int t, const RecArgs& ra) {
+  const int n_e = placed_contacts(E, act);
+  const unsigned long long base = tm.reserve(ra.count, act ? n_e : 0);
+  long long idx = (long long)base;
+  for (int c = 0; tm.any(c < E.ncol && act); ++c) {
+    const bool cc = act && c < E.ncol && is_contact_colour(E, c);
+    const int n = cc ? E.act_cnt()[c] : 0;
+    const int lo = cc ? E.colstart(c) : 0;
+    for (int k = tm.tl; k < n; k += tm.ts) {
+      const int s = E.act_slot()[lo + k];
+      const long long i = idx + k;
+      if (s < 0 || i >= ra.cap) continue;
+      const float* x = E.row(s + 3);
+      const float mn = E.row(s)[RM], mt = x[XMT];
+      float* o = ra.rec + (size_t)i * 16;
+      for (int q = 0; q < 7; ++q) o[q] = x[XF + q];
+      o[7] = E.row(s)[RL] / mn;
+      o[8] = E.row(s + 1)[RL] / mt;
+      o[9] = E.row(s + 2)[RL] / mt;
+      o[10] = mn;
+      o[11] = mt;
+      *reinterpret_cast<int*>(o + 12) = E.e;
+      *reinterpret_cast<int*>(o + 13) = t;
+      *reinterpret_cast<int*>(o + 14) = E.act_code()[lo + k];
+      o[15] = 0.f;
+    }
+    idx += n;
+  }
+}
+
+// One forward step solved to the residual tolerance, with the plain or the
+// learned warm start (and its fallback); counts sweeps and fallbacks in the
+// env's misc slots and writes training records when asked.
+template <class Team>
+SHD void env_step_solve(const Team& tm, const DevModel& M, const Env& E, const float* u_row, bool act, int t,
+                        const RecArgs* ra) {
+  f_controls(tm, M, E, u_row, act, t);
+  f_body_setup(tm, E, act, false);
+  tm.sync();
+  f_torques(tm, E, act);
+  f_predict(tm, M, E, act);
+  tm.sync();
+  f_rows(tm, M, E, act);
+  const bool rec = ra && ra->rec && ra->every > 0 && t % ra->every == 0;
+  if (M.ws_kind || rec) f_features(tm, M, E, act);
+  if (M.ws_kind) {
+    f_save_vel(tm, E, act);
+    f_learned_ws(tm, M, E, act);
+  }
+  f_warm(tm, E, act);
+  int nrows = 0;
+  for (int c = 0; c < E.ncol && act; ++c) nrows += E.act_cnt()[c];
+  const bool live = act && nrows > 0;
+  int it = 0, wasted = 0, fb = 0;
+  float res = 3.0e38f;
+  if (M.ws_kind) {
+    f_pgs_tol(tm, M, E, live, it, res, M.fb_iters);
+    const bool rej = live && res > M.tol && res > M.fb_tol;
+    if (tm.any(rej)) {
+      f_restart(tm, M, E, rej);
+      f_warm(tm, E, rej);
+      if (rej) {
+        wasted = it;
+        fb = 1;
+        it = 0;
+        res = 3.0e38f;
+      }
+    }
+  }
+  f_pgs_tol(tm, M, E, live, it, res, M.max_iters);
+  if (act && tm.tl == 0) {
+    *reinterpret_cast<int*>(E.misc() + MISC_ITERS) += it + wasted;
+    *reinterpret_cast<int*>(E.misc() + MISC_FB) += fb;
+  }
+  if (tm.any(rec && live && res <= M.tol)) f_records(tm, M, E, rec && live && res <= M.tol, t, *ra);
   f_integrate(tm, M, E, act);
   f_store(tm, E, act);
 }

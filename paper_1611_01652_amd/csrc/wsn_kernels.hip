@@ -299,4 +299,6 @@ hipError_t launch_wsn_to_bf16(const float* w, uint16_t* wb, hipStream_t st) {
 
 size_t wsn_train_lds_bytes() { return WSN_TRAIN_FLOATS * sizeof(float); }
 
+int wsn_shared_floats(int n_list) { return WSN_NET_FLOATS + WSN_TILE_FLOATS + 64 + ((n_list + 3) & ~3); }
+
 }  // namespace sim

@@ -38,6 +38,8 @@ class SimDesc(C.Structure):
         ("n_iters", C.c_int32), ("ground", C.c_int32), ("loss_kind", C.c_int32), ("loss_mask", C.c_int32),
         ("ckpt_every", C.c_int32), ("min_team", C.c_int32),
         ("ctrl_kind", C.c_int32), ("mlp_sizes", C.c_int32 * 4), ("clock_hz", C.c_float),
+        ("solve_mode", C.c_int32), ("tol", C.c_float), ("max_iters", C.c_int32),
+        ("ws_kind", C.c_int32), ("ws_net", _F32P), ("fb_iters", C.c_int32), ("fb_tol", C.c_float),
     ]
 
 
@@ -99,6 +101,18 @@ def make_desc(w):
         d.ctrl_kind = 1
         d.mlp_sizes = (C.c_int32 * 4)(*[int(v) for v in mlp["sizes"]])
         d.clock_hz = float(mlp.get("clock_hz", 1.5))
+    extra = getattr(w, "extra", None) or {}
+    solve = extra.get("solve")
+    if solve is not None:
+        d.solve_mode = int(solve.get("mode", 1))
+        d.tol = float(solve.get("tol", 1e-5))
+        d.max_iters = int(solve.get("max_iters", 1000))
+    ws = extra.get("ws")
+    if ws is not None:
+        d.ws_kind = 1
+        d.ws_net = f(ws["w"])
+        d.fb_iters = int(ws.get("fb_iters", 5))
+        d.fb_tol = float(ws.get("fb_tol", 1e-3))
     return d, keep
 
 
@@ -123,6 +137,7 @@ def library():
     lib.sim_step.argtypes = [vp, vp, vp, vp, vp, vp, C.c_int32, vp, vp]
     lib.rollout.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp]
     lib.rollout_grad.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, C.c_size_t, vp]
+    lib.rollout_solve.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, C.c_int64, vp, C.c_int32, vp]
     lib.sim_describe_order.argtypes = [C.POINTER(SimDesc), C.c_int32, _I32P, _I32P, C.c_int32]
     lib.sim_describe_order.restype = C.c_int32
     lib.sim_step_graph.argtypes = [vp, C.c_int32, vp, vp, vp, C.c_int32, vp, C.POINTER(vp)]
@@ -141,7 +156,7 @@ def library():
     lib.wsn_adam.argtypes = [vp, vp, vp, vp, vp, C.c_int32, C.c_float, C.c_float, C.c_float, C.c_float, vp]
     for fn in ("sim_init", "sim_destroy", "sim_get_info", "sim_lambda_offsets", "sim_step", "rollout",
                "rollout_grad", "sim_step_graph", "sim_graph_launch", "sim_graph_destroy", "sim_set_teams",
-               "wsn_to_bf16", "wsn_forward", "wsn_loss_grad", "wsn_adam"):
+               "wsn_to_bf16", "wsn_forward", "wsn_loss_grad", "wsn_adam", "rollout_solve"):
         getattr(lib, fn).restype = C.c_int
     _lib = lib
     return lib
@@ -150,7 +165,8 @@ def library():
 EXPORTED = ["sim_abi_version", "sim_last_error", "sim_init", "sim_destroy", "sim_get_info",
             "sim_lambda_offsets", "sim_describe_order", "sim_step", "rollout", "rollout_grad",
             "sim_step_graph", "sim_graph_launch", "sim_graph_destroy", "sim_tune", "sim_get_teams",
-            "sim_set_teams", "wsn_to_bf16", "wsn_forward", "wsn_workspace_bytes", "wsn_loss_grad", "wsn_adam"]
+            "sim_set_teams", "wsn_to_bf16", "wsn_forward", "wsn_workspace_bytes", "wsn_loss_grad", "wsn_adam",
+            "rollout_solve"]
 
 
 def describe_order(w, env):
@@ -235,6 +251,31 @@ class Simulator:
                               _ptr(out["lam_final"]), _ptr(out["ckpt"]), _ptr(out["flags"]), self._stream())
         _check(self.lib, st, "rollout")
         out["loss"] = out["loss"][:E]
+        return out
+
+    def rollout_solve(self, x0, u, rec_cap=0, rec_every=1, want_final=True):
+        """Tolerance-mode rollout with sweep / fallback counts per env and, with
+        rec_cap > 0, training records (a [n, 16] float32 tensor; columns 12..14
+        hold int32 bit patterns of env, step, code)."""
+        t = self.torch
+        E = self.info.n_envs
+        out = dict(loss=self._f32(E), flags=t.zeros(max(E, 1), dtype=t.int32, device="cuda"),
+                   iters=t.zeros(max(E, 1), dtype=t.int32, device="cuda"),
+                   fallbacks=t.zeros(max(E, 1), dtype=t.int32, device="cuda"))
+        out["x_final"] = self._f32(18 * self.info.n_bodies).view(18, -1) if want_final else None
+        out["lam_final"] = self._f32(self.info.lam_size) if want_final else None
+        rec = t.zeros((max(int(rec_cap), 1), 16), device="cuda") if rec_cap > 0 else None
+        cnt = t.zeros(1, dtype=t.int64, device="cuda")
+        st = self.lib.rollout_solve(self.h, _ptr(x0), _ptr(u), _ptr(out["loss"]), _ptr(out["x_final"]),
+                                    _ptr(out["lam_final"]), _ptr(out["flags"]), _ptr(out["iters"]),
+                                    _ptr(out["fallbacks"]), _ptr(rec), int(rec_cap), _ptr(cnt), int(rec_every),
+                                    self._stream())
+        _check(self.lib, st, "rollout_solve")
+        for k in ("loss", "flags", "iters", "fallbacks"):
+            out[k] = out[k][:E]
+        if rec is not None:
+            out["n_records"] = cnt
+            out["records"] = rec
         return out
 
     def workspace(self):

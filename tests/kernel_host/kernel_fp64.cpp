@@ -21,13 +21,59 @@
 #include "../../paper_1611_01652_amd/csrc/model_pack.cpp"
 using namespace sim;
 namespace {
+// bfloat16 rounding of a double: 8 significant bits, nearest, ties to even
+double bf16r(double x) {
+  if (!std::isfinite(x) || x == 0.0) return x;
+  int e;
+  (void)std::frexp(x, &e);
+  const double q = std::ldexp(1.0, e - 8);
+  return std::nearbyint(x / q) * q;
+}
 struct TeamHost {
-  int tl = 0, ts = 1;
+  int tl = 0, ts = 1, team = 0, n_teams = 1;
+  double* lds0 = nullptr;
+  int* cnt = nullptr;
+  int* map = nullptr;
+  const double* net = nullptr;   // warm-start network parameters (bfloat16 values)
   void sync() const {}
   bool any(bool p) const { return p; }
   int prefix(bool p, int& total) const { total = p ? 1 : 0; return 0; }
   double team_sum(double v) const { return v; }
+  double team_max(double v) const { return v; }
   bool team_any(bool p) const { return p; }
+  int* shared_cnt() const { return cnt; }
+  int* shared_map() const { return map; }
+  // the network in plain loops, with the rounding of the matrix-core kernel
+  // (bfloat16 inputs and hidden activations); accumulation in double
+  void wsn_rows(int total, const int* mp) const {
+    for (int i = 0; i < total; ++i) {
+      const double* x = lds0 + mp[i] + XF;
+      double* y = lds0 + mp[i] + XY;
+      const double *W1 = net, *b1 = W1 + 448, *W2 = b1 + 64, *b2 = W2 + 4096, *W3 = b2 + 64, *b3 = W3 + 192;
+      double xi[7], h1[64], h2[64];
+      for (int k = 0; k < 7; ++k) xi[k] = bf16r(x[k]);
+      for (int h = 0; h < 64; ++h) {
+        double s = b1[h];
+        for (int k = 0; k < 7; ++k) s += W1[h * 7 + k] * xi[k];
+        h1[h] = bf16r(std::max(s, 0.0));
+      }
+      for (int h = 0; h < 64; ++h) {
+        double s = b2[h];
+        for (int k = 0; k < 64; ++k) s += W2[h * 64 + k] * h1[k];
+        h2[h] = bf16r(std::max(s, 0.0));
+      }
+      for (int o = 0; o < 3; ++o) {
+        double s = b3[o];
+        for (int k = 0; k < 64; ++k) s += W3[o * 64 + k] * h2[k];
+        y[o] = s;
+      }
+    }
+  }
+  unsigned long long reserve(unsigned long long* ctr, int n) const {
+    const unsigned long long v = *ctr;
+    *ctr += (unsigned long long)n;
+    return v;
+  }
 };
 struct Host { PackedModel P; DevModel M; std::vector<double> clock; };
 bool make(const sim_model_desc* d, Host& h) {
@@ -41,6 +87,8 @@ bool make(const sim_model_desc* d, Host& h) {
   M.warm = d->warm; M.lam_tot = h.P.lam_off[d->n_envs];
   M.hdr = h.P.hdr.data(); M.topo = h.P.topo.data(); M.cst = h.P.cst.data(); M.target = h.P.target.data();
   M.ctrl = d->ctrl_kind;
+  M.solve_mode = d->solve_mode; M.tol = d->tol; M.max_iters = d->max_iters;
+  M.ws_kind = d->ws_kind; M.fb_iters = d->fb_iters; M.fb_tol = d->fb_tol;
   if (M.ctrl) {
     M.mlp_in = d->mlp_sizes[0]; M.mlp_h1 = d->mlp_sizes[1]; M.mlp_h2 = d->mlp_sizes[2]; M.mlp_out = d->mlp_sizes[3];
     M.tape_stride = tape_len(M.mlp_in, M.mlp_h1, M.mlp_h2, M.mlp_out);
@@ -76,7 +124,7 @@ int kh_rollout_grad(const sim_model_desc* d, const double* x0, const double* u, 
     h.M.W = u;
     h.M.tape = tape.data();
   }
-  RolloutArgs ra{x0, u, loss, xf, lf.data(), ckpt.data(), nullptr};
+  RolloutArgs ra{x0, u, loss, xf, lf.data(), ckpt.data(), nullptr, nullptr, nullptr, RecArgs{nullptr, 0, nullptr, 0}};
   GradArgs ga{x0, u, ckpt.data(), dloss, gx0, gu, gm, gI, gmu, gd, seg.data()};
   for (int ie = 0; ie < d->n_envs; ++ie) {
     std::vector<double> lds(h.P.adj_of[ie] + 16);
@@ -106,5 +154,31 @@ int kh_rollout_grad(const sim_model_desc* d, const double* x0, const double* u, 
     }
   }
   return 0;
+}
+
+// Tolerance-mode forward rollout (plain or learned warm start) with sweep and
+// fallback counts and training records; returns the number of records.
+long long kh_rollout_solve(const sim_model_desc* d, const double* x0, const double* u, double* loss, double* xf,
+                           int* iters, int* fbs, double* rec, long long rec_cap, int rec_every) {
+  Host h;
+  if (!make(d, h)) return -1;
+  std::vector<double> lf(h.M.lam_tot + 1), net(4867, 0.0);
+  if (d->ws_kind)
+    for (int p = 0; p < 4867; ++p) net[p] = bf16r(d->ws_net[p]);
+  unsigned long long count = 0;
+  RolloutArgs ra{x0, u, loss, xf, lf.data(), nullptr, nullptr, iters, fbs,
+                 RecArgs{rec, rec_cap, &count, rec ? rec_every : 0}};
+  for (int ie = 0; ie < d->n_envs; ++ie) {
+    std::vector<double> lds(h.P.fwd_of[ie] + 16);
+    std::vector<int> cnt(64), map(h.P.ccap_of[ie] + 1);
+    TeamHost tm;
+    tm.lds0 = lds.data();
+    tm.cnt = cnt.data();
+    tm.map = map.data();
+    tm.net = net.data();
+    Env E = make_env(h.M, ie, lds.data(), h.M.n_iters, false);
+    env_rollout<TeamHost, true>(tm, h.M, E, true, ra);
+  }
+  return (long long)count;
 }
 }

@@ -64,7 +64,7 @@ def _desc64(w):
             a = a if a.size else np.zeros(1, np.int32)
             keep.append(a)
             setattr(d, name, a.ctypes.data_as(C.POINTER(C.c_int32)))
-        elif typ == C.POINTER(C.c_double):
+        elif typ == C.POINTER(C.c_double) and hasattr(w, name):
             a = np.ascontiguousarray(np.asarray(getattr(w, name), np.float64)).reshape(-1)
             a = a if a.size else np.zeros(1)
             keep.append(a)
@@ -81,6 +81,15 @@ def _desc64(w):
         d.ctrl_kind = 1
         d.mlp_sizes = (C.c_int32 * 4)(*[int(v) for v in mlp["sizes"]])
         d.clock_hz = float(mlp.get("clock_hz", 1.5))
+    solve = w.extra.get("solve") if getattr(w, "extra", None) else None
+    if solve is not None:
+        d.solve_mode, d.tol, d.max_iters = 1, f(solve["tol"]), int(solve["max_iters"])
+    ws = w.extra.get("ws") if getattr(w, "extra", None) else None
+    if ws is not None:
+        a = np.ascontiguousarray(np.asarray(ws["w"], np.float32).astype(np.float64))
+        keep.append(a)
+        d.ws_kind, d.ws_net = 1, a.ctypes.data_as(C.POINTER(C.c_double))
+        d.fb_iters, d.fb_tol = int(ws["fb_iters"]), f(ws["fb_tol"])
     return d, keep
 
 
@@ -138,3 +147,46 @@ def test_kernel_source_in_fp64_equals_oracle(maker, tol):
     for k in ("g_x0", "g_u", "g_inv_mass", "g_inv_inertia", "g_mu", "g_damping", "g_w"):
         if k in ref and k in got and ref[k].size:
             assert _rel(got[k], ref[k]) < tol, (k, _rel(got[k], ref[k]))
+
+
+def host_fp64_solve(w, rec_every=0, rec_cap=0):
+    lib = _load()
+    d, keep = _desc64(w)
+    E, B = w.n_envs, w.n_bodies
+    p = lambda a: a.ctypes.data_as(C.c_void_p)   # noqa: E731
+    x0 = np.ascontiguousarray(w.x0.T)
+    u = np.ascontiguousarray(w.u if w.u is not None and w.u.size else np.zeros((max(w.T_max, 1), 1)))
+    loss, xf = np.zeros(E), np.zeros((18, B))
+    it, fb = np.zeros(E, np.int32), np.zeros(E, np.int32)
+    rec = np.zeros((max(rec_cap, 1), 16))
+    lib.kh_rollout_solve.restype = C.c_longlong
+    n = lib.kh_rollout_solve(C.byref(d), p(x0), p(u), p(loss), p(xf), p(it), p(fb),
+                             p(rec) if rec_every else None, C.c_longlong(rec_cap), C.c_int(rec_every))
+    assert n >= 0
+    rec = rec[: min(n, rec_cap)].copy()
+    # env, step and code are written as int32 bit patterns into the (zeroed) doubles
+    rec[:, 12:15] = rec[:, 12:15].copy().view(np.int64)
+    return dict(loss=loss, x_final=xf.T, iters=it, fallbacks=fb, records=rec, n_records=n)
+
+
+@pytest.mark.parametrize("learned,fb_tol", [(False, 1e-3), (True, 1e-3), (True, -1.0)])
+def test_tolerance_mode_kernel_source_in_fp64_equals_oracle(learned, fb_tol):
+    # plain, learned (random network: rejected or accepted by its residual),
+    # and learned with every start rejected after five sweeps
+    ws = W.wsn_init(seed_salt=2) if learned else None
+    w = W.warm_start_chains(n_envs=5, T=90, seed_salt=3, ws_w=ws, fb_tol=fb_tol)
+    got = host_fp64_solve(w, rec_every=3, rec_cap=20000)
+    ref = Oracle(w).rollout_ex(rec_every=3, rec_cap=20000)
+    assert _rel(got["x_final"], ref["x_final"]) < 1e-8
+    assert _rel(got["loss"], ref["loss"]) < 1e-8
+    # the same arithmetic up to rounding order: the same stopping decisions
+    np.testing.assert_array_equal(got["iters"], ref["iters"])
+    np.testing.assert_array_equal(got["fallbacks"], ref["fallbacks"])
+    if learned:
+        assert got["fallbacks"].sum() > 0
+    assert got["n_records"] == ref["n_records"] > 50
+    key = lambda R: np.lexsort((R[:, 14], R[:, 13], R[:, 12]))   # noqa: E731
+    G = got["records"][key(got["records"])]
+    Rf = ref["records"][key(ref["records"])]
+    np.testing.assert_array_equal(G[:, 12:15], Rf[:, 12:15])
+    assert _rel(G[:, :12], Rf[:, :12]) < 1e-8
