@@ -142,10 +142,13 @@ typedef struct {
   int32_t solve_mode;            /* SIM_SOLVE_FIXED (n_iters sweeps) or SIM_SOLVE_TOL */
   float tol;
   int32_t max_iters;
-  /* Learned warm start of contacts (tolerance mode only): contact impulses
-     from the warm-start network (SIM_WSN_*), projected onto lambda_n >= 0,
-     |lambda_t| <= mu lambda_n; if the residual after fb_iters sweeps exceeds
-     fb_tol, that env's solve restarts from the plain warm start. */
+  /* Learned warm start of contacts (tolerance mode only): the warm-start
+     network (SIM_WSN_*) maps a contact's features to corrections of its
+     carried impulses (impulse over effective mass); the corrected impulses,
+     projected onto lambda_n >= 0, |lambda_t| <= mu lambda_n, start the solve.
+     If after fb_iters sweeps the solve has not converged and the residual of
+     the contact rows exceeds fb_tol, that env's solve restarts from the plain
+     warm start (fb_iters = 0: always). */
   int32_t ws_kind;               /* SIM_WS_PLAIN or SIM_WS_LEARNED */
   const float* ws_net;           /* host [SIM_WSN_PARAMS] FP32 weights (rounded to bfloat16 by sim_init) */
   int32_t fb_iters;
@@ -305,11 +308,18 @@ sim_status wsn_to_bf16(const float* w, uint16_t* w_bf16, void* stream);
 sim_status wsn_forward(const uint16_t* w_bf16, const float* x, int64_t stride, int64_t n, float* y, void* stream);
 /* Bytes of workspace wsn_loss_grad needs for n records. */
 int64_t wsn_workspace_bytes(int64_t n);
-/* Mean-squared error over n records rec[i * stride + ...] (features 0..6,
- * targets 7..9): *loss = (1/n) sum_i |net(x_i) - t_i|^2 and grad[4867] its
- * gradient (either may be NULL).  Deterministic (fixed reduction order). */
-sim_status wsn_loss_grad(const uint16_t* w_bf16, const float* rec, int64_t stride, int64_t n, float* loss,
-                         float* grad, void* workspace, size_t workspace_bytes, void* stream);
+/* Training loss over n records rec[i * stride + ...] (features x = floats
+ * 0..6, targets t = floats 7..9, or, with relative != 0, floats 7..9 minus
+ * floats 4..6: the correction to the carried impulses that the learned warm
+ * start adds the network's output to):
+ *   *loss = (1/n) sum_i sum_k rho(net(x_i)_k - t_ik),
+ *   rho(e) = e^2 for |e| <= huber (every e when huber = 0), else
+ *   2 huber |e| - huber^2,
+ * and grad[4867] its gradient (either may be NULL).  Deterministic (fixed
+ * reduction order). */
+sim_status wsn_loss_grad(const uint16_t* w_bf16, const float* rec, int64_t stride, int64_t n, float huber,
+                         int32_t relative, float* loss, float* grad, void* workspace, size_t workspace_bytes,
+                         void* stream);
 /* One Adam step (Kingma and Ba, with bias correction; step counts from 1) on
  * the FP32 master weights w, moments m and v, then w_bf16 = bfloat16(w). */
 sim_status wsn_adam(float* w, uint16_t* w_bf16, const float* grad, float* m, float* v, int32_t step, float lr,

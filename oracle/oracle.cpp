@@ -527,10 +527,12 @@ void step_env(const Model& M, const EnvTopo& E, const StepIn<S>& in, S* xn, S* l
     for (size_t i = 0; i < nc; ++i) {
       ConRows<S>& C = cons[i];
       if (C.kind != 1) continue;
+      // the network predicts the correction to the carried impulses, in
+      // velocity units (impulse over effective mass)
       double y[ORACLE_WSN_OUT];
       wsn_eval(c.ws_w, feat[i].data(), y);
-      const double ln = std::max(val(C.r[0].m) * y[0], 0.0);
-      double l1 = val(C.mt) * y[1], l2 = val(C.mt) * y[2];
+      const double ln = std::max(val(C.r[0].m) * (feat[i][4] + y[0]), 0.0);
+      double l1 = val(C.mt) * (feat[i][5] + y[1]), l2 = val(C.mt) * (feat[i][6] + y[2]);
       const double rho = val(mu) * ln, nrm = std::sqrt(l1 * l1 + l2 * l2);
       if (!(nrm <= rho)) { l1 *= rho / nrm; l2 *= rho / nrm; }
       C.r[0].lam = S(ln);
@@ -543,8 +545,10 @@ void step_env(const Model& M, const EnvTopo& E, const StepIn<S>& in, S* xn, S* l
   // S7 projected Gauss-Seidel.  One sweep visits every constraint in the
   // canonical order and returns the residual: the largest |delta lambda| / m
   // over the scalar rows and |delta lambda_t| / m_t over the friction blocks.
+  double res_c = 0.0;   // residual of the contact rows in the last sweep
   auto sweep = [&]() -> double {
     double res = 0.0;
+    res_c = 0.0;
     for (auto& C : cons) {
       const int nscalar = C.kind == 0 ? 5 : 1;
       for (int q = 0; q < nscalar; ++q) {
@@ -556,7 +560,9 @@ void step_env(const Model& M, const EnvTopo& E, const StepIn<S>& in, S* xn, S* l
         else if (val(lt) >= r.hi) ln = S(r.hi);
         else ln = lt;
         apply(r, B, ln - r.lam);
-        res = std::max(res, std::fabs(val(ln) - val(r.lam)) / val(r.m));
+        const double rr = std::fabs(val(ln) - val(r.lam)) / val(r.m);
+        res = std::max(res, rr);
+        if (C.kind == 1) res_c = std::max(res_c, rr);
         r.lam = ln;
       }
       if (C.kind == 1) {
@@ -576,7 +582,9 @@ void step_env(const Model& M, const EnvTopo& E, const StepIn<S>& in, S* xn, S* l
         apply(r1, B, n1 - r1.lam);
         apply(r2, B, n2 - r2.lam);
         const double d1 = val(n1) - val(r1.lam), d2 = val(n2) - val(r2.lam);
-        res = std::max(res, std::sqrt(d1 * d1 + d2 * d2) / val(C.mt));
+        const double rt = std::sqrt(d1 * d1 + d2 * d2) / val(C.mt);
+        res = std::max(res, rt);
+        res_c = std::max(res_c, rt);
         r1.lam = n1;
         r2.lam = n2;
       }
@@ -589,8 +597,10 @@ void step_env(const Model& M, const EnvTopo& E, const StepIn<S>& in, S* xn, S* l
     int it = 0;
     double res = INFINITY;
     if (c.ws_kind == 1) {
+      // the test looks at the rows the network started: the contacts
       while (it < c.fb_iters && res > c.tol) { res = sweep(); ++it; }
-      if (res > c.tol && res > c.fb_tol) {
+      const double test = it > 0 ? res_c : INFINITY;
+      if (res > c.tol && test > c.fb_tol) {
         // rejected: restart this env's solve from the plain warm start
         if (stats) { stats->sweeps += it; stats->fallbacks += 1; }
         B.v = v_pred;

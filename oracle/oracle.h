@@ -46,8 +46,10 @@ typedef struct {
   int max_iters;
   /* learned warm start of contacts (tolerance mode): per-contact network
      7 -> 64 -> 64 -> 3 with ReLU, weights, inputs and hidden activations
-     rounded to bfloat16; if the residual after fb_iters sweeps exceeds fb_tol
-     the env's solve restarts from the plain warm start. */
+     rounded to bfloat16, predicting the correction to the carried impulses
+     (over their effective masses); if, after fb_iters sweeps, the solve has
+     not converged and the residual of the contact rows exceeds fb_tol, the
+     env's solve restarts from the plain warm start. */
   int ws_kind;                /* 0 plain, 1 learned */
   const double *ws_w;         /* W1[64][7] b1[64] W2[64][64] b2[64] W3[3][64] b3[3] */
   int fb_iters;

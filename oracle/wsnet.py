@@ -8,7 +8,7 @@ Network (the learned warm start of contacts): 7 inputs -> 64 ReLU -> 64 ReLU
 -> 3 linear outputs; parameters packed as W1[64][7] b1[64] W2[64][64] b2[64]
 W3[3][64] b3[3] (4,867 values).  Training loss over a batch of N records:
 
-    L = (1/N) sum_n sum_k (y_nk - t_nk)^2
+    L = (1/N) sum_n sum_k (y_nk - t_nk)^2      (optionally Huber's loss)
 
 Plain definitions in float64 without rounding: the GPU kernels round weights,
 inputs, activations and backward deltas to bfloat16 (FP32 accumulation), and
@@ -42,9 +42,11 @@ def forward(w, X):
     return h2 @ W3.T + b3
 
 
-def loss_grad(w, X, T):
+def loss_grad(w, X, T, huber=0.0):
     """Loss and its gradient with respect to the packed parameters, by the
-    chain rule through the three layers (ReLU derivative 0 at 0)."""
+    chain rule through the three layers (ReLU derivative 0 at 0).  With
+    huber = h > 0 each squared error e^2 with |e| > h is replaced by
+    2 h |e| - h^2 (Huber's loss, written so that it equals e^2 inside)."""
     W1, b1, W2, b2, W3, b3 = unpack(w)
     X = np.asarray(X, dtype=np.float64)
     T = np.asarray(T, dtype=np.float64)
@@ -55,8 +57,13 @@ def loss_grad(w, X, T):
     h2 = np.maximum(z2, 0.0)
     y = h2 @ W3.T + b3
     r = y - T
-    L = float((r * r).sum() / N)
-    dy = 2.0 * r / N
+    if huber > 0.0:
+        out = np.abs(r) > huber
+        L = float(np.where(out, 2.0 * huber * np.abs(r) - huber * huber, r * r).sum() / N)
+        dy = 2.0 * np.where(out, huber * np.sign(r), r) / N
+    else:
+        L = float((r * r).sum() / N)
+        dy = 2.0 * r / N
     gW3 = dy.T @ h2
     gb3 = dy.sum(0)
     dz2 = (dy @ W3) * (z2 > 0)

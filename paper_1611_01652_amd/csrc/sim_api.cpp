@@ -771,15 +771,17 @@ sim_status wsn_forward(const uint16_t* w_bf16, const float* x, int64_t stride, i
   return SIM_OK;
 }
 
-sim_status wsn_loss_grad(const uint16_t* w_bf16, const float* rec, int64_t stride, int64_t n, float* loss,
-                         float* grad, void* workspace, size_t workspace_bytes, void* stream) {
+sim_status wsn_loss_grad(const uint16_t* w_bf16, const float* rec, int64_t stride, int64_t n, float huber,
+                         int32_t relative, float* loss, float* grad, void* workspace, size_t workspace_bytes,
+                         void* stream) {
   if (n < 0 || stride < SIM_WSN_IN + SIM_WSN_OUT) return fail(SIM_E_ARG, "wsn_loss_grad: n < 0 or stride < 10");
+  if (!(huber >= 0.f)) return fail(SIM_E_ARG, "wsn_loss_grad: huber < 0");
   if (!w_bf16 || (n > 0 && !rec) || !workspace) return fail(SIM_E_ARG, "wsn_loss_grad: null argument");
   const int parts = wsn_parts(n, device_cus());
   if (workspace_bytes < (size_t)parts * (SIM_WSN_PARAMS + 1) * sizeof(float))
     return fail(SIM_E_NOMEM, "wsn_loss_grad: workspace smaller than wsn_workspace_bytes(n)");
-  if (launch_wsn_loss_grad(w_bf16, rec, stride, n, (float*)workspace, parts, grad, loss, (hipStream_t)stream) !=
-      hipSuccess)
+  if (launch_wsn_loss_grad(w_bf16, rec, stride, n, huber, relative ? 1 : 0, (float*)workspace, parts, grad, loss,
+                           (hipStream_t)stream) != hipSuccess)
     return check_device("wsn_loss_grad");
   return SIM_OK;
 }

@@ -37,8 +37,8 @@ int wsn_parts(long long n, int n_cu);
 // LDS floats of the shared region a forward workgroup needs for the learned
 // warm start with a contact list of n_list entries
 int wsn_shared_floats(int n_list);
-hipError_t launch_wsn_loss_grad(const uint16_t* w, const float* rec, long long stride, long long n, float* partial,
-                                int n_parts, float* grad, float* loss, hipStream_t st);
+hipError_t launch_wsn_loss_grad(const uint16_t* w, const float* rec, long long stride, long long n, float huber,
+                                int relative, float* partial, int n_parts, float* grad, float* loss, hipStream_t st);
 hipError_t launch_wsn_forward(const uint16_t* w, const float* x, long long stride, long long n, float* y,
                               int n_cu, hipStream_t st);
 hipError_t launch_wsn_adam(float* w, uint16_t* wb, const float* g, float* m, float* v, float lr, float b1, float b2,

@@ -1018,9 +1018,10 @@ SHD void f_save_vel(const Team& tm, const Env& E, bool act) {
 }
 
 // Learned warm start: the network on the features of every contact of the
-// wave (matrix cores, 16 contacts per tile), then the outputs, scaled by the
-// effective masses and projected onto lambda_n >= 0, |lambda_t| <= mu
-// lambda_n, replace the contacts' warm-start impulses.
+// wave (matrix cores, 16 contacts per tile); its outputs correct the carried
+// impulses (in velocity units: impulse over effective mass), and the result,
+// projected onto lambda_n >= 0, |lambda_t| <= mu lambda_n, replaces the
+// contacts' warm-start impulses.
 // Contacts placed in row slots (team-uniform): the first ccap active contacts
 // in colour-major order; any beyond the capacity were dropped and flagged.
 SHD int placed_contacts(const Env& E, bool act) {
@@ -1063,9 +1064,10 @@ SHD void f_learned_ws(const Team& tm, const DevModel& M, const Env& E, bool act)
     for (int k = tm.tl; k < n; k += tm.ts) {
       const int s = E.act_slot()[lo + k];
       if (s < 0) continue;
+      // outputs: corrections to the carried impulses over their effective masses
       const float* x = E.row(s + 3);
-      const float ln = fmaxf(E.row(s)[RM] * x[XY], 0.f);
-      float l1 = x[XMT] * x[XY + 1], l2 = x[XMT] * x[XY + 2];
+      const float ln = fmaxf(E.row(s)[RM] * (x[XF + 4] + x[XY]), 0.f);
+      float l1 = x[XMT] * (x[XF + 5] + x[XY + 1]), l2 = x[XMT] * (x[XF + 6] + x[XY + 2]);
       const float rho = mu * ln, nrm = sqrtf(l1 * l1 + l2 * l2);
       if (!(nrm <= rho)) { l1 *= rho / nrm; l2 *= rho / nrm; }
       E.row(s)[RL] = E.row(s)[RL0] = ln;
@@ -1106,14 +1108,16 @@ SHD void f_restart(const Team& tm, const DevModel& M, const Env& E, bool act) {
 
 // Sweeps until the residual (largest |delta lambda| / m of a sweep) is at most
 // tol or `limit` sweeps have run; it / res carry the count and the last
-// residual (team-uniform).
+// residual, res_c (if given) the last residual of the contact rows alone
+// (team-uniform).
 template <class Team>
-SHD void f_pgs_tol(const Team& tm, const DevModel& M, const Env& E, bool live, int& it, float& res, int limit) {
+SHD void f_pgs_tol(const Team& tm, const DevModel& M, const Env& E, bool live, int& it, float& res, int limit,
+                   float* res_c = nullptr) {
   const float mu = E.misc()[MISC_MU];
   for (;;) {
     const bool run = live && res > M.tol && it < limit;
     if (!tm.any(run)) break;
-    float r = 0.f;
+    float r = 0.f, rc = 0.f;
     for (int c = 0; tm.any(c < E.ncol && run); ++c) {
       const int n = (run && c < E.ncol) ? E.act_cnt()[c] : 0;
       const int lo = (run && c < E.ncol) ? E.colstart(c) : 0;
@@ -1123,12 +1127,13 @@ SHD void f_pgs_tol(const Team& tm, const DevModel& M, const Env& E, bool live, i
         const int code = E.act_code()[lo + k];
         const RowB rb = cand_bodies(E, code);
         if (cand_kind(code) == K_JOINT) pgs_joint(M, E, s, rb.a, rb.b, nullptr, &r);
-        else pgs_contact(M, E, s, rb.a, rb.b, mu, nullptr, &r);
+        else pgs_contact(M, E, s, rb.a, rb.b, mu, nullptr, &rc);
       }
       tm.sync();
     }
     if (run) {
-      res = tm.team_max(r);
+      res = tm.team_max(fmaxf(r, rc));
+      if (res_c) *res_c = tm.team_max(rc);
       ++it;
     }
   }
@@ -1194,8 +1199,10 @@ SHD void env_step_solve(const Team& tm, const DevModel& M, const Env& E, const f
   int it = 0, wasted = 0, fb = 0;
   float res = 3.0e38f;
   if (M.ws_kind) {
-    f_pgs_tol(tm, M, E, live, it, res, M.fb_iters);
-    const bool rej = live && res > M.tol && res > M.fb_tol;
+    // the test of the learned start looks at the rows it started: the contacts
+    float res_c = 3.0e38f;
+    f_pgs_tol(tm, M, E, live, it, res, M.fb_iters, &res_c);
+    const bool rej = live && res > M.tol && (it > 0 ? res_c : 3.0e38f) > M.fb_tol;
     if (tm.any(rej)) {
       f_restart(tm, M, E, rej);
       f_warm(tm, E, rej);

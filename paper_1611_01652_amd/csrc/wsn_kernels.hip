@@ -2,9 +2,10 @@
 // matrix cores (bfloat16 operands, FP32 accumulation).
 //
 // k_wsn_loss_grad: each one-wave workgroup takes 16-record tiles, runs the
-// forward pass, the mean-squared-error adjoint and the backward pass, and
-// accumulates its share of the weight gradient in registers:
-//   dY  = 2 (Y - T) / N                      (T: converged impulses over their masses)
+// forward pass, the adjoint of the mean (Huber) loss and the backward pass,
+// and accumulates its share of the weight gradient in registers:
+//   dY  = 2 clamp(Y - T, -h, h) / N          (T: converged impulses over their
+//                                             masses, optionally minus the carried ones)
 //   gW3 = dY^T H2,  dZ2 = (dY W3) . [H2 > 0]
 //   gW2 = dZ2^T H1, dZ1 = (dZ2 W2) . [H1 > 0]
 //   gW1 = dZ1^T [X 1]                         (the ones column gives gb1)
@@ -64,8 +65,8 @@ __device__ __forceinline__ float col_sum(floatx4 d) {
 }
 
 __global__ __launch_bounds__(64) void k_wsn_loss_grad(const uint16_t* __restrict__ w, const float* __restrict__ rec,
-                                                      long long stride, long long n, float inv_n,
-                                                      float* __restrict__ partial) {
+                                                      long long stride, long long n, float inv_n, float huber,
+                                                      int relative, float* __restrict__ partial) {
   extern __shared__ float lds[];
   const WsnTrainLds L = wsn_train_at(lds);
   const int lane = threadIdx.x, kq = 4 * (lane >> 4), c16 = lane & 15;
@@ -126,9 +127,16 @@ __global__ __launch_bounds__(64) void k_wsn_loss_grad(const uint16_t* __restrict
       const long long s = r0 + kq + r;
       float d = 0.f;
       if (s < n && c16 < WSN_OUT) {
-        const float e = y[r] + L.net.b3[c16] - rec[s * stride + WSN_IN + c16];
-        loss += e * e;
-        d = 2.f * e * inv_n;
+        const float* q = rec + s * stride;
+        const float t = q[WSN_IN + c16] - (relative ? q[4 + c16] : 0.f);
+        const float e = y[r] + L.net.b3[c16] - t;
+        if (huber > 0.f && fabsf(e) > huber) {
+          loss += 2.f * huber * fabsf(e) - huber * huber;
+          d = 2.f * copysignf(huber, e) * inv_n;
+        } else {
+          loss += e * e;
+          d = 2.f * e * inv_n;
+        }
       }
       dy[r] = d;
       const uint16_t hb = f2bf(d);
@@ -263,12 +271,12 @@ int wsn_parts(long long n, int n_cu) {
   return (int)std::max<long long>(1, std::min<long long>(tiles, 2LL * n_cu));
 }
 
-hipError_t launch_wsn_loss_grad(const uint16_t* w, const float* rec, long long stride, long long n, float* partial,
-                                int n_parts, float* grad, float* loss, hipStream_t st) {
+hipError_t launch_wsn_loss_grad(const uint16_t* w, const float* rec, long long stride, long long n, float huber,
+                                int relative, float* partial, int n_parts, float* grad, float* loss, hipStream_t st) {
   const size_t lds = WSN_TRAIN_FLOATS * sizeof(float);
   if (n > 0) {
-    hipLaunchKernelGGL(k_wsn_loss_grad, dim3(n_parts), dim3(64), lds, st, w, rec, stride, n, 1.f / (float)n,
-                       partial);
+    hipLaunchKernelGGL(k_wsn_loss_grad, dim3(n_parts), dim3(64), lds, st, w, rec, stride, n, 1.f / (float)n, huber,
+                       relative, partial);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

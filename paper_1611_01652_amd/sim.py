@@ -152,7 +152,7 @@ def library():
     lib.wsn_forward.argtypes = [vp, vp, C.c_int64, C.c_int64, vp, vp]
     lib.wsn_workspace_bytes.argtypes = [C.c_int64]
     lib.wsn_workspace_bytes.restype = C.c_int64
-    lib.wsn_loss_grad.argtypes = [vp, vp, C.c_int64, C.c_int64, vp, vp, vp, C.c_size_t, vp]
+    lib.wsn_loss_grad.argtypes = [vp, vp, C.c_int64, C.c_int64, C.c_float, C.c_int32, vp, vp, vp, C.c_size_t, vp]
     lib.wsn_adam.argtypes = [vp, vp, vp, vp, vp, C.c_int32, C.c_float, C.c_float, C.c_float, C.c_float, vp]
     for fn in ("sim_init", "sim_destroy", "sim_get_info", "sim_lambda_offsets", "sim_step", "rollout",
                "rollout_grad", "sim_step_graph", "sim_graph_launch", "sim_graph_destroy", "sim_set_teams",
@@ -407,14 +407,17 @@ class WarmStartNet:
                "wsn_forward")
         return y[:n]
 
-    def loss_grad(self, rec):
-        """rec: [n, >= 10] CUDA float32 records; returns (loss tensor [1], grad [4867])."""
+    def loss_grad(self, rec, huber=0.0, relative=False):
+        """rec: [n, >= 10] CUDA float32 records; returns (loss tensor [1], grad [4867]).
+        huber > 0: Huber loss with that threshold; relative: targets are the
+        corrections to the carried impulses (record columns 7..9 minus 4..6)."""
         n = rec.shape[0]
         need = int(self.lib.wsn_workspace_bytes(n))
         if self._ws is None or self._ws.numel() * 4 < need:
             self._ws = self.torch.empty(need // 4 + 1, device="cuda")
-        st = self.lib.wsn_loss_grad(_ptr(self.wb), _ptr(rec), rec.stride(0), n, _ptr(self.loss), _ptr(self.grad),
-                                    _ptr(self._ws), self._ws.numel() * 4, _stream())
+        st = self.lib.wsn_loss_grad(_ptr(self.wb), _ptr(rec), rec.stride(0), n, float(huber), int(bool(relative)),
+                                    _ptr(self.loss), _ptr(self.grad), _ptr(self._ws), self._ws.numel() * 4,
+                                    _stream())
         _check(self.lib, st, "wsn_loss_grad")
         return self.loss, self.grad
 

@@ -375,14 +375,17 @@ def warm_start_chains(n_envs: int = 16384, T: int = 500, seed_salt: int = 0, tol
     return w
 
 
-def wsn_init(seed_salt: int = 0, scale: float = 1.0) -> np.ndarray:
+def wsn_init(seed_salt: int = 0, scale: float = 1.0, zero_output: bool = False) -> np.ndarray:
     """Seeded He-uniform initial weights of the warm-start network, FP32
-    values: W1[64][7] b1[64] W2[64][64] b2[64] W3[3][64] b3[3]."""
+    values: W1[64][7] b1[64] W2[64][64] b2[64] W3[3][64] b3[3].  With
+    zero_output the output layer is zero: the network then leaves the carried
+    impulses unchanged (the plain warm start)."""
     rng = rng_for(5, seed_salt)
     parts = []
     for fan_in, fan_out in ((7, 64), (64, 64), (64, 3)):
         lim = scale * math.sqrt(6.0 / fan_in)
-        parts.append(rng.uniform(-lim, lim, size=fan_out * fan_in))
+        wl = rng.uniform(-lim, lim, size=fan_out * fan_in)
+        parts.append(np.zeros_like(wl) if (zero_output and fan_out == 3) else wl)
         parts.append(np.zeros(fan_out))
     return f32(np.concatenate(parts))
 

@@ -85,6 +85,21 @@ def test_loss_gradient_matches_fp64_and_is_deterministic():
             assert d <= 2e-2 * np.linalg.norm(gr[a:b]) + 1e-9, (a, b, d, np.linalg.norm(gr[a:b]))
 
 
+def test_huber_loss_on_corrections_matches_fp64():
+    import torch
+    net = _net(6)
+    wb = net.weights_bf16_as_float()
+    R = _records(3001, seed=33)
+    R[:50, 7] += 5.0            # a few large targets in the Huber regime
+    _say("case wsn Huber loss on corrections, n = 3001")
+    L, g = net.loss_grad(torch.tensor(R, device="cuda"), huber=0.1, relative=True)
+    L, g = float(L.item()), g.cpu().numpy().astype(np.float64)
+    Rd = R.astype(np.float64)
+    Lr, gr = wsnet.loss_grad(wb, Rd[:, :7], Rd[:, 7:10] - Rd[:, 4:7], huber=0.1)
+    assert abs(L - Lr) <= 1e-2 * Lr, (L, Lr)
+    assert np.linalg.norm(g - gr) <= 2e-2 * np.linalg.norm(gr)
+
+
 def test_empty_batch_gives_zero_loss_and_gradient():
     import torch
     net = _net(3)

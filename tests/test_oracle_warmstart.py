@@ -4,7 +4,8 @@ training records, against closed forms, brute force and library routines.
 * bfloat16 rounding equals torch's float32 -> bfloat16 conversion (nearest,
   ties to even) on float32 values, ties included.
 * the network's index layout: weights that route input k to hidden unit k and
-  back out reproduce the (rounded) input exactly.
+  back out reproduce the (rounded) input exactly; its outputs correct the
+  carried impulses (a zero network is the plain warm start).
 * a ball at rest: one sweep per step once warm (two on the first step), and
   2 T with a carried impulse scaled by 0.85; its records are the closed forms
   v_n = -g dt, target lambda_n / m_n = g dt, m_n = m, m_t = 2 m / 7.
@@ -12,6 +13,7 @@ training records, against closed forms, brute force and library routines.
   found by enumerating active sets.
 * a learned warm start rejected before any sweep reproduces the plain solve
   bit for bit; rejected after 5 sweeps it costs exactly 5 sweeps per fallback.
+* the network reference's Huber loss and gradient against finite differences.
 """
 from __future__ import annotations
 
@@ -100,16 +102,29 @@ def test_ball_at_rest_records_are_closed_form():
     np.testing.assert_array_equal(rec[:, 14], (1 << 24) | 0)
 
 
-def test_routing_network_returns_the_plain_warm_start():
-    # on the resting ball the learned start built from the routing net equals
-    # the plain one up to the bfloat16 rounding of g dt, so after the first
-    # step each solve needs at most two sweeps and none is rejected
+def test_zero_network_is_the_plain_warm_start():
+    # the network corrects the carried impulses: zero outputs leave them as
+    # they are, so the resting ball needs one sweep per step once warm
+    T = 30
+    w = _rest(T, 1.0)
+    w.extra["ws"] = dict(w=np.zeros(W.WSN_PARAMS), fb_iters=5, fb_tol=1e-3)
+    r = Oracle(w).rollout_ex()
+    assert r["fallbacks"][0] == 0
+    assert r["iters"][0] == T + 1
+    xp = Oracle(_rest(T, 1.0)).rollout_ex()["x_final"]
+    np.testing.assert_allclose(r["x_final"], xp, rtol=0, atol=1e-12)
+
+
+def test_routing_network_doubles_the_carried_impulse():
+    # the routing net returns the rounded carried impulse over its mass, so the
+    # learned start is twice the carried one (up to bfloat16 rounding): on the
+    # resting ball the first sweep removes the excess, the second confirms
     T = 30
     w = _rest(T, 1.0)
     w.extra["ws"] = dict(w=_routing_net(), fb_iters=5, fb_tol=1e-3)
     r = Oracle(w).rollout_ex()
     assert r["fallbacks"][0] == 0
-    assert r["iters"][0] <= 2 * T
+    assert r["iters"][0] == 2 * T
     xp = Oracle(_rest(T, 1.0)).rollout_ex()["x_final"]
     np.testing.assert_allclose(r["x_final"], xp, rtol=0, atol=1e-9)
 
@@ -168,8 +183,11 @@ def test_rejection_before_any_sweep_reproduces_the_plain_solve():
 
 def test_rejection_after_five_sweeps_costs_five_sweeps_each():
     plain = Oracle(_chains()).rollout_ex()
-    # the zero network starts every contact from zero impulses
-    rej = Oracle(_chains(ws_w=np.zeros(W.WSN_PARAMS), fb_iters=5, fb_tol=-1.0)).rollout_ex()
+    # a network whose normal output is -1000 m/s starts every contact from
+    # zero impulses (the projection then zeroes the tangential ones)
+    wz = np.zeros(W.WSN_PARAMS)
+    wz[4864] = -1000.0
+    rej = Oracle(_chains(ws_w=wz, fb_iters=5, fb_tol=-1.0)).rollout_ex()
     off = _chains().env_body_off
     same = np.array([np.array_equal(rej["x_final"][a:b], plain["x_final"][a:b]) for a, b in zip(off[:-1], off[1:])])
     assert same.sum() >= 4, same
@@ -223,3 +241,22 @@ def test_adam_first_step_moves_each_weight_by_lr():
     g = np.array([3.0, -0.5, 1e-3])
     w, m, v = wsnet.adam(np.zeros(3), g, np.zeros(3), np.zeros(3), 1, 0.01, eps=0.0)
     np.testing.assert_allclose(w, -0.01 * np.sign(g), rtol=1e-12)
+
+
+def test_network_reference_huber_gradient_matches_finite_differences():
+    from oracle import wsnet
+    rng = np.random.default_rng(8)
+    w = W.wsn_init(seed_salt=4).astype(np.float64)
+    X = rng.normal(0, 1, (11, 7))
+    T = rng.normal(0, 2, (11, 3))
+    L, g = wsnet.loss_grad(w, X, T, huber=0.5)
+    L2, _ = wsnet.loss_grad(w, X, T)
+    assert L < L2                                  # the errors beyond 0.5 are damped
+    idx = np.concatenate([rng.choice(W.WSN_PARAMS, 200, replace=False), np.arange(4864, 4867)])
+    h = 1e-6
+    for i in idx:
+        wp, wm = w.copy(), w.copy()
+        wp[i] += h
+        wm[i] -= h
+        fd = (wsnet.loss_grad(wp, X, T, huber=0.5)[0] - wsnet.loss_grad(wm, X, T, huber=0.5)[0]) / (2 * h)
+        assert abs(fd - g[i]) <= 1e-6 * max(1.0, abs(g[i])), (i, fd, g[i])
