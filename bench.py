@@ -76,7 +76,16 @@ def make_workload(name):
         return W.planar_arms(n_envs=4096, T=1000)
     if name == "chains":
         return W.uneven_chains(n_envs=16384, T=500)
+    if name == "quadruped":
+        # the controller as initialised for training: zero output layer
+        return W.quadruped(n_envs=1024)
     raise SystemExit(f"unknown workload {name}")
+
+
+def controls(w):
+    """The control input of rollout: the torque tape, or the controller weights."""
+    mlp = (getattr(w, "extra", None) or {}).get("mlp")
+    return np.asarray(mlp["w"] if mlp is not None else w.u, dtype=np.float32)
 
 
 def grad_check(w, got_gu, got_gx0, n=4):
@@ -126,7 +135,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="arms", choices=["arms", "chains"])
+    ap.add_argument("--workload", default="arms", choices=["arms", "chains", "quadruped"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
     args = ap.parse_args()
@@ -142,7 +151,7 @@ def main():
     w = make_workload(args.workload)
     sim = Simulator(w)
     x0 = torch.tensor(np.ascontiguousarray(w.x0.T), dtype=torch.float32, device="cuda")
-    u = torch.tensor(np.ascontiguousarray(w.u), dtype=torch.float32, device="cuda")
+    u = torch.tensor(np.ascontiguousarray(controls(w)), dtype=torch.float32, device="cuda")
     dl = torch.ones(w.n_envs, dtype=torch.float32, device="cuda")
     ws_buf = sim.workspace()
     env_steps = float(np.sum(w.T_env))
@@ -179,8 +188,9 @@ def main():
     value = env_steps / (el / args.steps)
     flags = r["flags"].cpu().numpy()[: w.n_envs]
 
-    check = None
-    if not args.no_check:
+    check, n_checked = None, None
+    # the controller's weight gradient is a sum over all envs: no sampled check
+    if not args.no_check and args.workload != "quadruped":
         check, n_checked = grad_check(w, g["g_u"].cpu().numpy().astype(np.float64),
                                       g["g_x0"].cpu().numpy().T.astype(np.float64))
     fl_fwd, fl_rev = flops_per_env_step(w)
@@ -188,13 +198,8 @@ def main():
     grad_flops = (2 * fl_fwd + fl_rev) * env_steps
     achieved_tflops = grad_flops / (grad_ms * 1e-3) / 1e12
     hbm_gbs = by["total"] * env_steps / (el / args.steps) / 1e9
-    traffic = None
-    tfile = os.path.join(ROOT, "profiles", f"traffic_{args.workload}.json")
-    if os.path.exists(tfile):
-        try:
-            traffic = json.load(open(tfile)).get("bytes_per_launch")
-        except Exception:
-            traffic = None
+    from paper_1611_01652_amd import traffic as TR
+    traffic = TR.load(args.workload)   # None unless measured on the current kernel sources
     line = {
         "metric": METRIC,
         "value": value,
@@ -208,7 +213,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "planar-arms" if args.workload == "arms" else "uneven-chains",
+        "config": {"workload": {"arms": "planar-arms", "chains": "uneven-chains",
+                                "quadruped": "quadruped-mlp-controller"}[args.workload],
                    "envs": w.n_envs, "T": int(w.T_max), "bodies": w.n_bodies, "joints": w.n_joints,
                    "pgs_iters": w.n_iters, "dt": w.dt, "ckpt_every": w.ckpt_every,
                    "parallelism": "single GPU, envs over one-wave workgroups"},

@@ -1,0 +1,132 @@
+"""HBM traffic of the gradient kernel from rocprofv3 hardware counters.
+
+Each counter is read in its own profiled run (FETCH_SIZE, then WRITE_SIZE),
+for the benchmark and for a plain device copy of known size; the copy gives
+the scale of each counter (KiB it reports per KiB really moved), which turns
+the kernel's counts into bytes:
+
+    cd /tmp && export TMPDIR=/tmp
+    rocprofv3 --pmc FETCH_SIZE --output-format csv -d $R/gpurun_out/pmc_copy_f -o c -- \\
+        python3 -m paper_1611_01652_amd.traffic copy
+    rocprofv3 --pmc WRITE_SIZE --output-format csv -d $R/gpurun_out/pmc_copy_w -o c -- \\
+        python3 -m paper_1611_01652_amd.traffic copy
+    rocprofv3 --pmc FETCH_SIZE --output-format csv -d $R/gpurun_out/pmc_arms_f -o b -- \\
+        python3 $R/bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-check
+    rocprofv3 --pmc WRITE_SIZE ... (same, pmc_arms_w)
+    python3 -m paper_1611_01652_amd.traffic summarize --workload arms --dir $R/gpurun_out
+
+The summary (profiles/traffic_<workload>.json) holds the bytes per launch of
+k_rollout_grad and a hash of the kernel sources it was measured with; the
+benchmark reports it only while the sources are unchanged.
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import glob
+import hashlib
+import json
+import os
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+KERNEL_SOURCES = ["csrc/sim_kernels.hip", "csrc/step_core.h", "csrc/drivers.h"]
+COPY_MIB = 1024
+
+
+def source_hash():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(HERE, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def copy_main(mib=COPY_MIB, reps=4):
+    """A plain device-to-device copy of `mib` MiB, `reps` times (nothing else
+    runs on the device in this process)."""
+    import torch
+    n = mib * (1 << 20) // 4
+    a = torch.empty(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_mib": mib, "reps": reps}))
+
+
+def read_counters(d, counter):
+    """{kernel name: [per-dispatch values]} from the counter CSVs under d."""
+    out = {}
+    files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+    if not files:
+        raise FileNotFoundError(f"no counter_collection.csv under {d}")
+    for f in files:
+        with open(f) as fh:
+            for row in csv.DictReader(fh):
+                if row.get("Counter_Name") != counter:
+                    continue
+                out.setdefault(row["Kernel_Name"], []).append(float(row["Counter_Value"]))
+    return out
+
+
+def per_dispatch(vals, match):
+    ks = [k for k in vals if match(k)]
+    if not ks:
+        raise KeyError("kernel not found among " + ", ".join(sorted(vals)[:10]))
+    v = [x for k in ks for x in vals[k]]
+    return sum(v) / len(v), len(v), ks
+
+
+def summarize(workload, d, kernel="k_rollout_grad"):
+    expect_kib = COPY_MIB * 1024.0
+    is_copy = lambda k: "copy" in k.lower() or "elementwise" in k.lower()   # noqa: E731
+    cf, ncf, _ = per_dispatch(read_counters(os.path.join(d, "pmc_copy_f"), "FETCH_SIZE"), is_copy)
+    cw, ncw, _ = per_dispatch(read_counters(os.path.join(d, "pmc_copy_w"), "WRITE_SIZE"), is_copy)
+    kf, nkf, names = per_dispatch(read_counters(os.path.join(d, f"pmc_{workload}_f"), "FETCH_SIZE"),
+                                  lambda k: kernel in k)
+    kw, nkw, _ = per_dispatch(read_counters(os.path.join(d, f"pmc_{workload}_w"), "WRITE_SIZE"),
+                              lambda k: kernel in k)
+    sf, sw = cf / expect_kib, cw / expect_kib
+    out = dict(workload=workload, kernel=kernel, kernel_names=names,
+               fetch_kib_per_dispatch=kf, write_kib_per_dispatch=kw, dispatches=[nkf, nkw],
+               copy_kib_expected=expect_kib, copy_fetch_kib=cf, copy_write_kib=cw,
+               fetch_scale=sf, write_scale=sw,
+               bytes_per_launch=(kf / sf + kw / sw) * 1024.0,
+               fetch_bytes_per_launch=kf / sf * 1024.0, write_bytes_per_launch=kw / sw * 1024.0,
+               kernel_source_hash=source_hash())
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
+    with open(path, "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(json.dumps(out))
+    return out
+
+
+def load(workload):
+    """Bytes per launch, or None when missing or measured on other kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        t = json.load(open(path))
+    except Exception:
+        return None
+    if t.get("kernel_source_hash") != source_hash():
+        return None
+    return t.get("bytes_per_launch")
+
+
+if __name__ == "__main__":
+    ap = argparse.ArgumentParser()
+    ap.add_argument("cmd", choices=["copy", "summarize", "hash"])
+    ap.add_argument("--workload", default="arms")
+    ap.add_argument("--dir", default=os.path.join(ROOT, "gpurun_out"))
+    a = ap.parse_args()
+    if a.cmd == "copy":
+        copy_main()
+    elif a.cmd == "summarize":
+        summarize(a.workload, a.dir)
+    else:
+        print(source_hash())
+    sys.exit(0)
