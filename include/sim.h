@@ -70,6 +70,7 @@ typedef enum {
 /* per-env flags written by rollout / rollout_grad / sim_step */
 #define SIM_FLAG_NONFINITE 1u        /* a state component became NaN/Inf */
 #define SIM_FLAG_CONTACT_OVERFLOW 2u /* more active contacts than the env's capacity */
+#define SIM_FLAG_GRAD_NONFINITE 4u   /* rollout_grad: the env's adjoint overflowed; its gradient is zeroed */
 
 /* loss kinds l(x^t, p) of eq. (L); p = the env's target and loss body */
 #define SIM_LOSS_FINAL_SQDIST 0  /* sum_k mask_k (p_k(T_e) - target_k)^2                */
@@ -236,6 +237,11 @@ sim_status rollout_solve(sim_handle h, const float* x0, const float* u, float* l
  *   for SIM_CTRL_MLP, dL/dW [n_params] summed over envs (the paper's dL/dW,
  *   section 2.2), g_inv_mass[B], g_inv_inertia[B][3], g_mu[E], g_damping[J]
  *   (device).
+ * env_flags[E] (device, may be NULL) is overwritten: SIM_FLAG_GRAD_NONFINITE
+ * for an env whose adjoint overflowed or exceeded 1e30 (the gradient of a
+ * chaotic trajectory grows exponentially with its length; beyond 1e30 its sums
+ * over env-steps are no longer representable); that env's gradients are
+ * written as zeros and it contributes nothing to dL/dW.
  * workspace: device scratch of at least sim_info.workspace_bytes (the
  * per-env segment buffer of the checkpoint recompute and, with a controller,
  * the per env-step activations and deltas plus the split-K partial sums of
@@ -243,7 +249,7 @@ sim_status rollout_solve(sim_handle h, const float* x0, const float* u, float* l
 sim_status rollout_grad(sim_handle h, const float* x0, const float* u, const float* ckpt,
                         const float* dloss_env, float* g_x0, float* g_u, float* g_inv_mass,
                         float* g_inv_inertia, float* g_mu, float* g_damping, void* workspace,
-                        size_t workspace_bytes, void* stream);
+                        size_t workspace_bytes, uint32_t* env_flags, void* stream);
 
 /* ---- Replayable step sequences (HIP graphs). ----
  * Captures n_steps consecutive sim_step calls into a HIP graph, for callers
@@ -324,6 +330,18 @@ sim_status wsn_loss_grad(const uint16_t* w_bf16, const float* rec, int64_t strid
  * the FP32 master weights w, moments m and v, then w_bf16 = bfloat16(w). */
 sim_status wsn_adam(float* w, uint16_t* w_bf16, const float* grad, float* m, float* v, int32_t step, float lr,
                     float beta1, float beta2, float eps, void* stream);
+
+/* ---- Optimiser for the controller (section 2.2 policy search). ----
+ * One Adam step (Kingma and Ba, with bias correction; step counts from 1) on
+ * n FP32 parameters w with moments m and v, after scaling the gradient to a
+ * norm of at most max_norm (0: no clipping).  A non-finite gradient norm
+ * skips the step.  scratch: device, at least 513 floats (SIM_ADAM_SCRATCH);
+ * grad_norm (device, may be NULL) receives the norm before clipping.  All
+ * pointers are device memory; asynchronous on `stream`. */
+#define SIM_ADAM_SCRATCH 513
+sim_status sim_adam(float* w, const float* grad, float* m, float* v, int64_t n, int32_t step, float lr,
+                    float beta1, float beta2, float eps, float max_norm, float* scratch, float* grad_norm,
+                    void* stream);
 
 #ifdef __cplusplus
 }

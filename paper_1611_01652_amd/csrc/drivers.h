@@ -35,6 +35,7 @@ struct GradArgs {
   float* g_mu;         // [E]
   float* g_damp;       // [J]
   float* seg;          // per-env segment buffers
+  uint32_t* flags;     // [E] or null: SIM_FLAG_GRAD_NONFINITE for envs whose adjoint overflowed
 };
 
 struct StepArgs {
@@ -153,6 +154,11 @@ SHD void loss_adj(const DevModel& M, const Env& E, int t1, const float* p, float
   pbar[0] += -dl / ((float)E.T * M.dt);
 }
 
+// Largest adjoint magnitude kept.  Beyond it an env's gradient is treated as
+// overflowed: its products with the controller's activations (|s| up to ~1e2),
+// summed over ~1e6 env-steps, would no longer be representable in FP32.
+#define ADJ_LIMIT 1.0e30f
+
 template <class Team>
 SHD_FLAT void env_rollout_grad(const Team& tm, const DevModel& M, const Env& E, bool valid, const GradArgs& a) {
   if (valid) {
@@ -173,6 +179,7 @@ SHD_FLAT void env_rollout_grad(const Team& tm, const DevModel& M, const Env& E, 
   if (valid && a.g_u && !M.ctrl)
     for (int t = T; t < M.T_max; ++t)
       for (int j = tm.tl; j < E.nj; j += tm.ts) a.g_u[(size_t)t * M.J + E.j0 + j] = 0.f;
+  bool bad = false;   // this lane saw a non-finite adjoint (checked after every reversed step)
   for (int sg = nseg - 1; tm.any(sg >= 0); --sg) {
     const bool sact = sg >= 0;
     const int t0 = sact ? sg * K : 0;
@@ -228,23 +235,62 @@ SHD_FLAT void env_rollout_grad(const Team& tm, const DevModel& M, const Env& E, 
       a_rows(tm, M, E, act);
       a_predict_torques(tm, M, E, act, (act && a.g_u && !M.ctrl) ? a.g_u + (size_t)t * M.J : nullptr, nullptr);
       a_controller(tm, M, E, act, t);
+      tm.sync();
+      // an overflow can later be dropped by a clamp's or a contact's select,
+      // so it is caught where it appears: in x-bar and in the controller's deltas
+      if (act) {
+        for (int b = tm.tl; b < E.nb; b += tm.ts) {
+          const float* A = E.bodyA(b);
+          for (int k = 0; k < 18; ++k) bad = bad || !(fabsf(A[k]) <= ADJ_LIMIT);
+        }
+        if (M.ctrl) {
+          const float* row = M.tape + (size_t)(E.tape_off + t) * M.tape_stride;
+          for (int c = tape_du(M) + tm.tl; c < tape_d1(M) + M.mlp_h1; c += tm.ts) bad = bad || !(fabsf(row[c]) <= ADJ_LIMIT);
+        }
+      }
     }
     tm.sync();
   }
+  if (valid && M.loss_kind == 2 && T > 0 && tm.tl == 0) E.bodyA(E.lb)[AP] += dl / ((float)T * M.dt);
+  tm.sync();
+  // An adjoint that overflowed (the gradient of a chaotic trajectory grows
+  // exponentially with the horizon) carries inf / NaN, or values beyond
+  // ADJ_LIMIT, back to x0 and into the parameter totals: such an env's
+  // gradient is zeroed and flagged, so that it cannot poison sums over envs.
   if (valid) {
-    if (M.loss_kind == 2 && T > 0 && tm.tl == 0) E.bodyA(E.lb)[AP] += dl / ((float)T * M.dt);
-    tm.sync();
+    for (int b = tm.tl; b < E.nb; b += tm.ts) {
+      const float* A = E.bodyA(b);
+      for (int k = 0; k < 18; ++k) bad = bad || !(fabsf(A[k]) <= ADJ_LIMIT);
+      for (int k = 0; k < 4; ++k) bad = bad || !(fabsf(A[ATM + k]) <= ADJ_LIMIT);
+    }
+    for (int j = tm.tl; j < E.nj; j += tm.ts) bad = bad || !(fabsf(E.jA()[j]) <= ADJ_LIMIT);
+    if (tm.tl == 0) bad = bad || !(fabsf(E.misc()[MISC_GMU]) <= ADJ_LIMIT);
+  }
+  bad = tm.team_any(bad);
+  if (valid) {
     for (int b = tm.tl; b < E.nb; b += tm.ts) {
       const float* A = E.bodyA(b);
       if (a.g_x0)
-        for (int k = 0; k < 18; ++k) a.g_x0[(size_t)k * M.B + E.b0 + b] = A[k];
-      if (a.g_invm) a.g_invm[E.b0 + b] = A[ATM];
+        for (int k = 0; k < 18; ++k) a.g_x0[(size_t)k * M.B + E.b0 + b] = bad ? 0.f : A[k];
+      if (a.g_invm) a.g_invm[E.b0 + b] = bad ? 0.f : A[ATM];
       if (a.g_invI)
-        for (int k = 0; k < 3; ++k) a.g_invI[3 * (E.b0 + b) + k] = A[ATI + k];
+        for (int k = 0; k < 3; ++k) a.g_invI[3 * (E.b0 + b) + k] = bad ? 0.f : A[ATI + k];
     }
     if (a.g_damp)
-      for (int j = tm.tl; j < E.nj; j += tm.ts) a.g_damp[E.j0 + j] = E.jA()[j];
-    if (tm.tl == 0 && a.g_mu) a.g_mu[E.e] = E.misc()[MISC_GMU];
+      for (int j = tm.tl; j < E.nj; j += tm.ts) a.g_damp[E.j0 + j] = bad ? 0.f : E.jA()[j];
+    if (tm.tl == 0 && a.g_mu) a.g_mu[E.e] = bad ? 0.f : E.misc()[MISC_GMU];
+    if (tm.tl == 0 && a.flags) a.flags[E.e] = bad ? 4u : 0u;
+    if (bad && a.g_u && !M.ctrl)
+      for (int t = 0; t < T; ++t)
+        for (int j = tm.tl; j < E.nj; j += tm.ts) a.g_u[(size_t)t * M.J + E.j0 + j] = 0.f;
+    if (bad && M.ctrl) {
+      // the env's deltas leave the weight-gradient contraction
+      const int c0 = tape_du(M), c1 = tape_d1(M) + M.mlp_h1;
+      for (int t = 0; t < T; ++t) {
+        float* row = M.tape + (size_t)(E.tape_off + t) * M.tape_stride;
+        for (int c = c0 + tm.tl; c < c1; c += tm.ts) row[c] = 0.f;
+      }
+    }
   }
 }
 

@@ -554,7 +554,8 @@ sim_status rollout_solve(sim_handle h, const float* x0, const float* u, float* l
 
 sim_status rollout_grad(sim_handle h, const float* x0, const float* u, const float* ckpt, const float* dloss_env,
                         float* g_x0, float* g_u, float* g_inv_mass, float* g_inv_inertia, float* g_mu,
-                        float* g_damping, void* workspace, size_t workspace_bytes, void* stream) {
+                        float* g_damping, void* workspace, size_t workspace_bytes, uint32_t* env_flags,
+                        void* stream) {
   if (!h) return fail(SIM_E_ARG, "rollout_grad: null handle");
   if (h->M.n_envs == 0) return SIM_OK;
   if (h->M.solve_mode != SIM_SOLVE_FIXED)
@@ -568,7 +569,7 @@ sim_status rollout_grad(sim_handle h, const float* x0, const float* u, const flo
   if (s != SIM_OK) return s;
   hipStream_t st = (hipStream_t)stream;
   float* ws = (float*)workspace;
-  GradArgs a{x0, u, ckpt, dloss_env, g_x0, g_u, g_inv_mass, g_inv_inertia, g_mu, g_damping, ws};
+  GradArgs a{x0, u, ckpt, dloss_env, g_x0, g_u, g_inv_mass, g_inv_inertia, g_mu, g_damping, ws, env_flags};
   DevModel M = h->M;
   M.W = u;
   M.tape = ws + h->seg_floats;
@@ -708,7 +709,7 @@ int32_t sim_tune(sim_handle h, const float* x0, const float* u, int32_t with_gra
   M.W = u;
   M.tape = ws ? ws + h->seg_floats : nullptr;
   const RolloutArgs ra{x0, u, loss, nullptr, nullptr, ck, nullptr, nullptr, nullptr, RecArgs{nullptr, 0, nullptr, 0}};
-  const GradArgs ga{x0, u, ck, dl, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, ws};
+  const GradArgs ga{x0, u, ck, dl, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, ws, nullptr};
   // every bucket once at its current width: warms the code and writes the checkpoints
   for (int i = 0; i < n; ++i)
     if (!bucket_rollout(h, i, M, ra, st)) { cleanup(); return check_device("sim_tune rollout"); }
@@ -795,6 +796,22 @@ sim_status wsn_adam(float* w, uint16_t* w_bf16, const float* grad, float* m, flo
   const float c2 = (float)(1.0 / (1.0 - std::pow((double)beta2, step)));
   if (launch_wsn_adam(w, w_bf16, grad, m, v, lr, beta1, beta2, eps, c1, c2, (hipStream_t)stream) != hipSuccess)
     return check_device("wsn_adam");
+  return SIM_OK;
+}
+
+sim_status sim_adam(float* w, const float* grad, float* m, float* v, int64_t n, int32_t step, float lr,
+                    float beta1, float beta2, float eps, float max_norm, float* scratch, float* grad_norm,
+                    void* stream) {
+  if (n < 0) return fail(SIM_E_ARG, "sim_adam: n < 0");
+  if (n == 0) return SIM_OK;
+  if (!w || !grad || !m || !v || !scratch) return fail(SIM_E_ARG, "sim_adam: null argument");
+  if (step < 1 || !(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f) || !(max_norm >= 0.f))
+    return fail(SIM_E_ARG, "sim_adam: step < 1, beta outside [0, 1) or max_norm < 0");
+  const float c1 = (float)(1.0 / (1.0 - std::pow((double)beta1, step)));
+  const float c2 = (float)(1.0 / (1.0 - std::pow((double)beta2, step)));
+  hipStream_t st = (hipStream_t)stream;
+  if (launch_adam(w, grad, m, v, n, lr, beta1, beta2, eps, c1, c2, max_norm, scratch, grad_norm, st) != hipSuccess)
+    return check_device("sim_adam");
   return SIM_OK;
 }
 

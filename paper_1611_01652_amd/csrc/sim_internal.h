@@ -44,5 +44,10 @@ hipError_t launch_wsn_forward(const uint16_t* w, const float* x, long long strid
 hipError_t launch_wsn_adam(float* w, uint16_t* wb, const float* g, float* m, float* v, float lr, float b1, float b2,
                            float eps, float c1, float c2, hipStream_t st);
 hipError_t launch_wsn_to_bf16(const float* w, uint16_t* wb, hipStream_t st);
+// Adam with gradient-norm clipping for any parameter vector
+int adam_scratch_floats();
+hipError_t launch_adam(float* w, const float* g, float* m, float* v, long long n, float lr, float b1, float b2,
+                       float eps, float c1, float c2, float max_norm, float* scratch, float* norm_out,
+                       hipStream_t st);
 
 }  // namespace sim

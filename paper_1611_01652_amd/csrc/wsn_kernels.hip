@@ -265,6 +265,75 @@ __global__ void k_wsn_to_bf16(const float* __restrict__ w, uint16_t* __restrict_
   if (p < n) wb[p] = f2bf(w[p]);
 }
 
+// ------------------------------------------------------------------ Adam for any parameter vector
+// |g| in two fixed-order passes that cannot overflow: per block the largest
+// |g_i| (m_b) and the sum of (g_i / m_b)^2 (s_b); then one thread combines
+// |g| = M sqrt(sum_b s_b (m_b / M)^2), M = max_b m_b, and writes the clip scale
+// min(1, max_norm / |g|) (0 for a non-finite gradient: the step is skipped).
+__global__ void k_sq_partial(const float* __restrict__ g, long long n, float* __restrict__ part) {
+  __shared__ float sh[256];
+  float m = 0.f;
+  for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long long)gridDim.x * 256)
+    m = fmaxf(m, fabsf(g[i]) <= 3.0e38f ? fabsf(g[i]) : __builtin_inff());
+  sh[threadIdx.x] = m;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) sh[threadIdx.x] = fmaxf(sh[threadIdx.x], sh[threadIdx.x + o]);
+    __syncthreads();
+  }
+  const float mb = sh[0];
+  __syncthreads();
+  float s = 0.f;
+  if (mb > 0.f && mb <= 3.0e38f)
+    for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long long)gridDim.x * 256) {
+      const float q = g[i] / mb;
+      s += q * q;
+    }
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = mb;
+    part[2 * blockIdx.x + 1] = sh[0];
+  }
+}
+
+__global__ void k_clip_scale(float* __restrict__ part, int n_part, float max_norm, float* __restrict__ norm_out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  float M = 0.f;
+  for (int i = 0; i < n_part; ++i) M = fmaxf(M, part[2 * i]);
+  float s = 0.f;
+  if (M > 0.f && M <= 3.0e38f)
+    for (int i = 0; i < n_part; ++i) {
+      const float r = part[2 * i] / M;
+      s += part[2 * i + 1] * r * r;
+    }
+  const float nrm = M <= 3.0e38f ? M * sqrtf(s) : M;
+  float sc = 1.f;
+  if (!(nrm <= 3.0e38f)) sc = 0.f;
+  else if (max_norm > 0.f && nrm > max_norm) sc = max_norm / nrm;
+  part[2 * n_part] = sc;
+  if (norm_out) *norm_out = nrm;
+}
+
+__global__ void k_adam(float* __restrict__ w, const float* __restrict__ g, float* __restrict__ m,
+                       float* __restrict__ v, long long n, const float* __restrict__ scale, float lr, float b1,
+                       float b2, float eps, float c1, float c2) {
+  const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const float sc = scale ? *scale : 1.f;
+  if (sc == 0.f) return;
+  const float gp = g[p] * sc;
+  const float mp = b1 * m[p] + (1.f - b1) * gp;
+  const float vp = b2 * v[p] + (1.f - b2) * gp * gp;
+  m[p] = mp;
+  v[p] = vp;
+  w[p] -= lr * (mp * c1) / (sqrtf(vp * c2) + eps);
+}
+
 // ------------------------------------------------------------------ launchers
 int wsn_parts(long long n, int n_cu) {
   const long long tiles = (n + 15) / 16;
@@ -308,5 +377,19 @@ hipError_t launch_wsn_to_bf16(const float* w, uint16_t* wb, hipStream_t st) {
 size_t wsn_train_lds_bytes() { return WSN_TRAIN_FLOATS * sizeof(float); }
 
 int wsn_shared_floats(int n_list) { return WSN_NET_FLOATS + WSN_TILE_FLOATS + 64 + ((n_list + 3) & ~3); }
+
+int adam_scratch_floats() { return 2 * 256 + 1; }
+
+hipError_t launch_adam(float* w, const float* g, float* m, float* v, long long n, float lr, float b1, float b2,
+                       float eps, float c1, float c2, float max_norm, float* scratch, float* norm_out,
+                       hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  const int nb = (int)std::min<long long>(256, (n + 255) / 256);
+  hipLaunchKernelGGL(k_sq_partial, dim3(nb), dim3(256), 0, st, g, n, scratch);
+  hipLaunchKernelGGL(k_clip_scale, dim3(1), dim3(64), 0, st, scratch, nb, max_norm, norm_out);
+  hipLaunchKernelGGL(k_adam, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, w, g, m, v, n, scratch + 2 * nb,
+                     lr, b1, b2, eps, c1, c2);
+  return hipGetLastError();
+}
 
 }  // namespace sim

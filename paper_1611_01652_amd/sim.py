@@ -136,7 +136,7 @@ def library():
     lib.sim_lambda_offsets.argtypes = [vp, _I32P]
     lib.sim_step.argtypes = [vp, vp, vp, vp, vp, vp, C.c_int32, vp, vp]
     lib.rollout.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp]
-    lib.rollout_grad.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, C.c_size_t, vp]
+    lib.rollout_grad.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, C.c_size_t, vp, vp]
     lib.rollout_solve.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, C.c_int64, vp, C.c_int32, vp]
     lib.sim_describe_order.argtypes = [C.POINTER(SimDesc), C.c_int32, _I32P, _I32P, C.c_int32]
     lib.sim_describe_order.restype = C.c_int32
@@ -154,9 +154,11 @@ def library():
     lib.wsn_workspace_bytes.restype = C.c_int64
     lib.wsn_loss_grad.argtypes = [vp, vp, C.c_int64, C.c_int64, C.c_float, C.c_int32, vp, vp, vp, C.c_size_t, vp]
     lib.wsn_adam.argtypes = [vp, vp, vp, vp, vp, C.c_int32, C.c_float, C.c_float, C.c_float, C.c_float, vp]
+    lib.sim_adam.argtypes = [vp, vp, vp, vp, C.c_int64, C.c_int32, C.c_float, C.c_float, C.c_float, C.c_float,
+                             C.c_float, vp, vp, vp]
     for fn in ("sim_init", "sim_destroy", "sim_get_info", "sim_lambda_offsets", "sim_step", "rollout",
                "rollout_grad", "sim_step_graph", "sim_graph_launch", "sim_graph_destroy", "sim_set_teams",
-               "wsn_to_bf16", "wsn_forward", "wsn_loss_grad", "wsn_adam", "rollout_solve"):
+               "wsn_to_bf16", "wsn_forward", "wsn_loss_grad", "wsn_adam", "rollout_solve", "sim_adam"):
         getattr(lib, fn).restype = C.c_int
     _lib = lib
     return lib
@@ -166,7 +168,7 @@ EXPORTED = ["sim_abi_version", "sim_last_error", "sim_init", "sim_destroy", "sim
             "sim_lambda_offsets", "sim_describe_order", "sim_step", "rollout", "rollout_grad",
             "sim_step_graph", "sim_graph_launch", "sim_graph_destroy", "sim_tune", "sim_get_teams",
             "sim_set_teams", "wsn_to_bf16", "wsn_forward", "wsn_workspace_bytes", "wsn_loss_grad", "wsn_adam",
-            "rollout_solve"]
+            "rollout_solve", "sim_adam"]
 
 
 def describe_order(w, env):
@@ -286,10 +288,11 @@ class Simulator:
         ws = workspace if workspace is not None else self.workspace()
         nu = self.info.n_params if self.info.n_params else self.w.T_max * J
         g = dict(g_x0=self._f32(18 * B).view(18, -1), g_u=self._f32(nu),
-                 g_inv_mass=self._f32(B), g_inv_inertia=self._f32(3 * B), g_mu=self._f32(E), g_damping=self._f32(J))
+                 g_inv_mass=self._f32(B), g_inv_inertia=self._f32(3 * B), g_mu=self._f32(E), g_damping=self._f32(J),
+                 flags=self.torch.zeros(max(E, 1), dtype=self.torch.int32, device="cuda"))
         st = self.lib.rollout_grad(self.h, _ptr(x0), _ptr(u), _ptr(ckpt), _ptr(dloss), _ptr(g["g_x0"]),
                                    _ptr(g["g_u"]), _ptr(g["g_inv_mass"]), _ptr(g["g_inv_inertia"]), _ptr(g["g_mu"]),
-                                   _ptr(g["g_damping"]), _ptr(ws), ws.numel() * 4, self._stream())
+                                   _ptr(g["g_damping"]), _ptr(ws), ws.numel() * 4, _ptr(g["flags"]), self._stream())
         _check(self.lib, st, "rollout_grad")
         if self.info.n_params:
             g["g_u"] = g["g_u"][: self.info.n_params]
@@ -298,6 +301,7 @@ class Simulator:
         g["g_inv_mass"] = g["g_inv_mass"][:B]
         g["g_inv_inertia"] = g["g_inv_inertia"][: 3 * B].view(B, 3)
         g["g_mu"] = g["g_mu"][:E]
+        g["flags"] = g["flags"][:E]
         g["g_damping"] = g["g_damping"][:J]
         return g
 
@@ -426,3 +430,27 @@ class WarmStartNet:
         st = self.lib.wsn_adam(_ptr(self.w), _ptr(self.wb), _ptr(self.grad), _ptr(self.m), _ptr(self.v),
                                self.step_count, lr, beta1, beta2, eps, _stream())
         _check(self.lib, st, "wsn_adam")
+
+
+class Adam:
+    """Adam with gradient-norm clipping on a CUDA float32 parameter tensor,
+    in the library's kernels."""
+
+    def __init__(self, w, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, max_norm=0.0):
+        import torch
+        self.torch = torch
+        self.lib = library()
+        self.w = w
+        self.m = torch.zeros_like(w)
+        self.v = torch.zeros_like(w)
+        self.scratch = torch.zeros(513, device="cuda")
+        self.grad_norm = torch.zeros(1, device="cuda")
+        self.lr, self.b1, self.b2, self.eps, self.max_norm = lr, beta1, beta2, eps, max_norm
+        self.step_count = 0
+
+    def step(self, grad):
+        self.step_count += 1
+        st = self.lib.sim_adam(_ptr(self.w), _ptr(grad), _ptr(self.m), _ptr(self.v), self.w.numel(),
+                               self.step_count, self.lr, self.b1, self.b2, self.eps, self.max_norm,
+                               _ptr(self.scratch), _ptr(self.grad_norm), _stream())
+        _check(self.lib, st, "sim_adam")

@@ -125,7 +125,7 @@ int kh_rollout_grad(const sim_model_desc* d, const double* x0, const double* u, 
     h.M.tape = tape.data();
   }
   RolloutArgs ra{x0, u, loss, xf, lf.data(), ckpt.data(), nullptr, nullptr, nullptr, RecArgs{nullptr, 0, nullptr, 0}};
-  GradArgs ga{x0, u, ckpt.data(), dloss, gx0, gu, gm, gI, gmu, gd, seg.data()};
+  GradArgs ga{x0, u, ckpt.data(), dloss, gx0, gu, gm, gI, gmu, gd, seg.data(), nullptr};
   for (int ie = 0; ie < d->n_envs; ++ie) {
     std::vector<double> lds(h.P.adj_of[ie] + 16);
     Env E = make_env(h.M, ie, lds.data(), h.M.n_iters, false);
