@@ -154,11 +154,6 @@ SHD void loss_adj(const DevModel& M, const Env& E, int t1, const float* p, float
   pbar[0] += -dl / ((float)E.T * M.dt);
 }
 
-// Largest adjoint magnitude kept.  Beyond it an env's gradient is treated as
-// overflowed: its products with the controller's activations (|s| up to ~1e2),
-// summed over ~1e6 env-steps, would no longer be representable in FP32.
-#define ADJ_LIMIT 1.0e30f
-
 template <class Team>
 SHD_FLAT void env_rollout_grad(const Team& tm, const DevModel& M, const Env& E, bool valid, const GradArgs& a) {
   if (valid) {
@@ -233,21 +228,12 @@ SHD_FLAT void env_rollout_grad(const Team& tm, const DevModel& M, const Env& E, 
       a_pgs(tm, M, E, act);
       a_warm(tm, M, E, act);
       a_rows(tm, M, E, act);
-      a_predict_torques(tm, M, E, act, (act && a.g_u && !M.ctrl) ? a.g_u + (size_t)t * M.J : nullptr, nullptr);
-      a_controller(tm, M, E, act, t);
-      tm.sync();
       // an overflow can later be dropped by a clamp's or a contact's select,
-      // so it is caught where it appears: in x-bar and in the controller's deltas
-      if (act) {
-        for (int b = tm.tl; b < E.nb; b += tm.ts) {
-          const float* A = E.bodyA(b);
-          for (int k = 0; k < 18; ++k) bad = bad || !(fabsf(A[k]) <= ADJ_LIMIT);
-        }
-        if (M.ctrl) {
-          const float* row = M.tape + (size_t)(E.tape_off + t) * M.tape_stride;
-          for (int c = tape_du(M) + tm.tl; c < tape_d1(M) + M.mlp_h1; c += tm.ts) bad = bad || !(fabsf(row[c]) <= ADJ_LIMIT);
-        }
-      }
+      // so it is caught where it leaves the env: in the control adjoints and
+      // the controller's deltas, as each lane writes them
+      a_predict_torques(tm, M, E, act, (act && a.g_u && !M.ctrl) ? a.g_u + (size_t)t * M.J : nullptr, nullptr,
+                        &bad);
+      a_controller(tm, M, E, act, t, &bad);
     }
     tm.sync();
   }

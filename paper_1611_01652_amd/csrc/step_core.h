@@ -133,7 +133,7 @@ enum { XT1 = 0, XT2 = 3, XMT = 6, XGAP = 7, XSTORE = 8, XCODE = 9, XF = 10, XY =
 enum { QJL = 0, QJA = 3, QJB = 6, QWA = 9, QWB = 12, QM = 15, QB = 16, QL = 17, RSA = 20 };
 
 struct Lay {
-  int body, jc, gs, topo, ws, rows, act_cnt, act_slot, act_code, misc, mlp, vsave;  // forward
+  int body, jc, gs, topo, ws, rows, act_cnt, act_slot, act_code, live, misc, mlp, vsave;  // forward
   int bodyA, rowsA, hist, wsA, jA, mlpA;                                     // adjoint
   int total_fwd, total;
 };
@@ -156,6 +156,7 @@ SHD Lay make_lay(int nb, int nj, int G, int P, int ncol, int ncand, int nslot, i
   L.act_cnt = o; o += align4(ncol);
   L.act_slot = o; o += align4(ncand);
   L.act_code = o; o += align4(ncand);
+  L.live = o; o += align4(ncol + 2);
   L.misc = o; o += MISC_N;
   L.mlp = o; o += align4(mlp_f);
   L.vsave = o; o += align4(vs_f);
@@ -201,6 +202,9 @@ struct Env {
   SHD int* act_cnt() const { return (int*)(L + lay.act_cnt); }
   SHD int* act_slot() const { return (int*)(L + lay.act_slot); }
   SHD int* act_code() const { return (int*)(L + lay.act_code); }
+  // [0] colours with an active constraint this step, [1] joint colours (the
+  // first colours of the canonical order), [2..] the active colours in order
+  SHD int* live() const { return (int*)(L + lay.live); }
   SHD float* misc() const { return L + lay.misc; }
   SHD float* jA() const { return L + lay.jA; }
   SHD float* mlp() const { return L + lay.mlp; }
@@ -234,6 +238,13 @@ SHD Env make_env(const DevModel& M, int ie, float* lds, int n_iters, bool adj) {
   return E;
 }
 
+// Colours with at least one active constraint this step (built by f_rows):
+// the sweeps visit only these, in canonical order, which changes nothing but
+// the number of (empty) colour passes.
+SHD int n_live(const Env& E, bool act) { return act ? E.live()[0] : 0; }
+SHD int live_col(const Env& E, int i) { return E.live()[2 + i]; }
+SHD int n_joint_cols(const Env& E, bool act) { return act ? E.live()[1] : 0; }
+
 // per-env constants in global memory:
 //   bodies  invm[nb], invI[3][nb], pair-sphere offset[3][nb], pair-sphere radius[nb]
 //   joints  20 floats each (JAP..JD layout, JU unused)
@@ -261,6 +272,12 @@ SHD void load_env_static(const Team& tm, const DevModel& M, const Env& E) {
   for (int i = tm.tl; i < JS * E.nj; i += tm.ts) E.L[E.lay.jc + i] = E.gcst[cst_joint(E) + i];
   for (int i = tm.tl; i < 4 * E.G; i += tm.ts) E.L[E.lay.gs + i] = E.gcst[cst_ground(E) + i];
   if (tm.tl == 0) {
+    int m = 0;
+    while (m < E.ncol && E.gtopo[2 * E.nj + E.G + E.P + m] < E.gtopo[2 * E.nj + E.G + E.P + m + 1] &&
+           cand_kind(E.gtopo[2 * E.nj + E.G + E.P + E.ncol + 1 + E.gtopo[2 * E.nj + E.G + E.P + m]]) == K_JOINT)
+      ++m;
+    E.live()[0] = 0;
+    E.live()[1] = m;
     E.misc()[MISC_MU] = E.gcst[cst_env(E)];
     E.misc()[MISC_LOSS] = 0.f;
     (*reinterpret_cast<int*>(E.misc() + MISC_FLAGS)) = 0;
@@ -417,15 +434,12 @@ SHD f3 joint_axis_w(const Env& E, int j) {
 // parent.  Joints run colour by colour so no two lanes touch one body.
 template <class Team>
 SHD void f_torques(const Team& tm, const Env& E, bool act) {
-  const int ncj = act ? E.nj : 0;
   // joints occupy the first colours of the canonical order; a joint colour
   // holds only joints
-  for (int c = 0; tm.any(c < E.ncol && act); ++c) {
+  const int njc = n_joint_cols(E, act);
+  for (int c = 0; tm.any(c < njc); ++c) {
     int lo = 0, hi = 0;
-    if (act && c < E.ncol) {
-      lo = E.colstart(c); hi = E.colstart(c + 1);
-      if (lo >= ncj || cand_kind(E.cand(lo)) != K_JOINT) hi = lo;
-    }
+    if (c < njc) { lo = E.colstart(c); hi = E.colstart(c + 1); }
     for (int i = lo + tm.tl; i < hi; i += tm.ts) {
       const int j = cand_idx(E.cand(i));
       const float* C = E.jc(j);
@@ -634,14 +648,23 @@ SHD void f_rows(const Team& tm, const DevModel& M, const Env& E, bool act) {
     if (act && c < E.ncol) E.act_cnt()[c] = cnt;
   }
   tm.sync();
+  if (act && tm.tl == 0) {
+    int m = 0;
+    for (int c = 0; c < E.ncol; ++c)
+      if (E.act_cnt()[c] > 0) E.live()[2 + m++] = c;
+    E.live()[0] = m;
+  }
+  tm.sync();
 }
 
 // F5: warm start, v += W lambda0 for every row, colour by colour.
 template <class Team>
 SHD void f_warm(const Team& tm, const Env& E, bool act) {
-  for (int c = 0; tm.any(c < E.ncol && act); ++c) {
-    const int n = (act && c < E.ncol) ? E.act_cnt()[c] : 0;
-    const int lo = (act && c < E.ncol) ? E.colstart(c) : 0;
+  const int nl = n_live(E, act);
+  for (int ci = 0; tm.any(ci < nl); ++ci) {
+    const int c = ci < nl ? live_col(E, ci) : 0;
+    const int n = ci < nl ? E.act_cnt()[c] : 0;
+    const int lo = ci < nl ? E.colstart(c) : 0;
     for (int k = tm.tl; k < n; k += tm.ts) {
       const int s = E.act_slot()[lo + k];
       if (s < 0) continue;
@@ -718,6 +741,40 @@ SHD void rr_apply(const RR& R, VR& V, bool ha, float ima, float imb, float d) {
   }
 }
 
+// Row shapes of a hinge: its point rows have Jl = e_k (the row's axis k), its
+// angular rows Jl = 0.  The shape-specialised helpers below do the generic
+// row arithmetic with the exact multiplications by 0 and 1 left out (same
+// operations, same order), and skip the adjoint of Jl, which for a hinge is a
+// constant.  S = 0, 1, 2: point row along axis S; S = 3: angular row.
+template <int S>
+SHD float rs_jv(const RR& R, const VR& V, bool ha) {
+  float s = S < 3 ? V.vb[S] : 0.f;
+  s += R.jb[0] * V.wb[0] + R.jb[1] * V.wb[1] + R.jb[2] * V.wb[2];
+  if (ha) {
+    if (S < 3) s -= V.va[S];
+    s += R.ja[0] * V.wa[0] + R.ja[1] * V.wa[1] + R.ja[2] * V.wa[2];
+  }
+  return s;
+}
+template <int S>
+SHD void rs_apply(const RR& R, VR& V, bool ha, float ima, float imb, float d) {
+  if (S < 3) V.vb[S] += imb * d;
+  for (int k = 0; k < 3; ++k) V.wb[k] += d * R.wb[k];
+  if (ha) {
+    if (S < 3) V.va[S] -= ima * d;
+    for (int k = 0; k < 3; ++k) V.wa[k] += d * R.wa[k];
+  }
+}
+template <int S>
+SHD void pgs_hinge_row(const DevModel& M, RR& R, VR& V, bool ha, float ima, float imb, float* h, float* rmax) {
+  const float sv_ = rs_jv<S>(R, V, ha) + R.bias + M.gamma * R.lam;
+  const float lt = R.lam - R.m * sv_;
+  if (h) *h = lt;
+  if (rmax) *rmax = fmaxf(*rmax, fabsf(lt - R.lam) / R.m);
+  rs_apply<S>(R, V, ha, ima, imb, lt - R.lam);
+  R.lam = lt;
+}
+
 // One visit of a hinge (5 unbounded rows) with all data in registers.
 // rmax (tolerance mode): running maximum of |delta lambda| / m over the rows.
 SHD void pgs_joint(const DevModel& M, const Env& E, int s, int a, int b, float* H, float* rmax = nullptr) {
@@ -727,14 +784,11 @@ SHD void pgs_joint(const DevModel& M, const Env& E, int s, int a, int b, float* 
   RR R[5];
   for (int q = 0; q < 5; ++q) rr_load(R[q], E.row(s + q));
   const float ima = ha ? E.body(a)[BIM] : 0.f, imb = E.body(b)[BIM];
-  for (int q = 0; q < 5; ++q) {
-    const float sv_ = rr_jv(R[q], V, ha) + R[q].bias + M.gamma * R[q].lam;
-    const float lt = R[q].lam - R[q].m * sv_;
-    if (H) H[s + q] = lt;
-    if (rmax) *rmax = fmaxf(*rmax, fabsf(lt - R[q].lam) / R[q].m);
-    rr_apply(R[q], V, ha, ima, imb, lt - R[q].lam);
-    R[q].lam = lt;
-  }
+  pgs_hinge_row<0>(M, R[0], V, ha, ima, imb, H ? H + s : nullptr, rmax);
+  pgs_hinge_row<1>(M, R[1], V, ha, ima, imb, H ? H + s + 1 : nullptr, rmax);
+  pgs_hinge_row<2>(M, R[2], V, ha, ima, imb, H ? H + s + 2 : nullptr, rmax);
+  pgs_hinge_row<3>(M, R[3], V, ha, ima, imb, H ? H + s + 3 : nullptr, rmax);
+  pgs_hinge_row<3>(M, R[4], V, ha, ima, imb, H ? H + s + 4 : nullptr, rmax);
   for (int q = 0; q < 5; ++q) E.row(s + q)[RL] = R[q].lam;
   vr_store(V, E, a, b);
 }
@@ -780,11 +834,13 @@ SHD void pgs_contact(const DevModel& M, const Env& E, int s, int a, int b, float
 template <class Team>
 SHD void f_pgs(const Team& tm, const DevModel& M, const Env& E, bool act, bool rec) {
   const float mu = E.misc()[MISC_MU];
+  const int nl = n_live(E, act);
   for (int it = 0; it < M.n_iters; ++it) {
     float* H = rec ? E.hist(it) : nullptr;
-    for (int c = 0; tm.any(c < E.ncol && act); ++c) {
-      const int n = (act && c < E.ncol) ? E.act_cnt()[c] : 0;
-      const int lo = (act && c < E.ncol) ? E.colstart(c) : 0;
+    for (int ci = 0; tm.any(ci < nl); ++ci) {
+      const int c = ci < nl ? live_col(E, ci) : 0;
+      const int n = ci < nl ? E.act_cnt()[c] : 0;
+      const int lo = ci < nl ? E.colstart(c) : 0;
       for (int k = tm.tl; k < n; k += tm.ts) {
         const int s = E.act_slot()[lo + k];
         if (s < 0) continue;
@@ -830,9 +886,11 @@ SHD void f_integrate(const Team& tm, const DevModel& M, const Env& E, bool act) 
 // F8: store impulses for the next warm start.
 template <class Team>
 SHD void f_store(const Team& tm, const Env& E, bool act) {
-  for (int c = 0; tm.any(c < E.ncol && act); ++c) {
-    const int n = (act && c < E.ncol) ? E.act_cnt()[c] : 0;
-    const int lo = (act && c < E.ncol) ? E.colstart(c) : 0;
+  const int nl = n_live(E, act);
+  for (int ci = 0; tm.any(ci < nl); ++ci) {
+    const int c = ci < nl ? live_col(E, ci) : 0;
+    const int n = ci < nl ? E.act_cnt()[c] : 0;
+    const int lo = ci < nl ? E.colstart(c) : 0;
     for (int k = tm.tl; k < n; k += tm.ts) {
       const int s = E.act_slot()[lo + k];
       if (s < 0) continue;
@@ -980,8 +1038,10 @@ SHD bool is_contact_colour(const Env& E, int c) {
 // effective masses.
 template <class Team>
 SHD void f_features(const Team& tm, const DevModel& M, const Env& E, bool act) {
-  for (int c = 0; tm.any(c < E.ncol && act); ++c) {
-    const bool cc = act && c < E.ncol && is_contact_colour(E, c);
+  const int nl = n_live(E, act);
+  for (int ci = 0; tm.any(ci < nl); ++ci) {
+    const int c = ci < nl ? live_col(E, ci) : 0;
+    const bool cc = ci < nl && is_contact_colour(E, c);
     const int n = cc ? E.act_cnt()[c] : 0;
     const int lo = cc ? E.colstart(c) : 0;
     for (int k = tm.tl; k < n; k += tm.ts) {
@@ -1045,8 +1105,10 @@ SHD void f_learned_ws(const Team& tm, const DevModel& M, const Env& E, bool act)
     total += v;
   }
   int idx = base;
-  for (int c = 0; tm.any(c < E.ncol && act); ++c) {
-    const bool cc = act && c < E.ncol && is_contact_colour(E, c);
+  const int nl = n_live(E, act);
+  for (int ci = 0; tm.any(ci < nl); ++ci) {
+    const int c = ci < nl ? live_col(E, ci) : 0;
+    const bool cc = ci < nl && is_contact_colour(E, c);
     const int n = cc ? E.act_cnt()[c] : 0;
     const int lo = cc ? E.colstart(c) : 0;
     for (int k = tm.tl; k < n; k += tm.ts)
@@ -1057,8 +1119,9 @@ SHD void f_learned_ws(const Team& tm, const DevModel& M, const Env& E, bool act)
   tm.wsn_rows(total, map);
   tm.sync();
   const float mu = E.misc()[MISC_MU];
-  for (int c = 0; tm.any(c < E.ncol && act); ++c) {
-    const bool cc = act && c < E.ncol && is_contact_colour(E, c);
+  for (int ci = 0; tm.any(ci < nl); ++ci) {
+    const int c = ci < nl ? live_col(E, ci) : 0;
+    const bool cc = ci < nl && is_contact_colour(E, c);
     const int n = cc ? E.act_cnt()[c] : 0;
     const int lo = cc ? E.colstart(c) : 0;
     for (int k = tm.tl; k < n; k += tm.ts) {
@@ -1085,9 +1148,11 @@ SHD void f_restart(const Team& tm, const DevModel& M, const Env& E, bool act) {
   if (act)
     for (int b = tm.tl; b < E.nb; b += tm.ts)
       for (int k = 0; k < 6; ++k) E.body(b)[BV + k] = E.vsave(b)[k];
-  for (int c = 0; tm.any(c < E.ncol && act); ++c) {
-    const int n = (act && c < E.ncol) ? E.act_cnt()[c] : 0;
-    const int lo = (act && c < E.ncol) ? E.colstart(c) : 0;
+  const int nl = n_live(E, act);
+  for (int ci = 0; tm.any(ci < nl); ++ci) {
+    const int c = ci < nl ? live_col(E, ci) : 0;
+    const int n = ci < nl ? E.act_cnt()[c] : 0;
+    const int lo = ci < nl ? E.colstart(c) : 0;
     for (int k = tm.tl; k < n; k += tm.ts) {
       const int s = E.act_slot()[lo + k];
       if (s < 0) continue;
@@ -1118,9 +1183,11 @@ SHD void f_pgs_tol(const Team& tm, const DevModel& M, const Env& E, bool live, i
     const bool run = live && res > M.tol && it < limit;
     if (!tm.any(run)) break;
     float r = 0.f, rc = 0.f;
-    for (int c = 0; tm.any(c < E.ncol && run); ++c) {
-      const int n = (run && c < E.ncol) ? E.act_cnt()[c] : 0;
-      const int lo = (run && c < E.ncol) ? E.colstart(c) : 0;
+    const int nl = n_live(E, run);
+    for (int ci = 0; tm.any(ci < nl); ++ci) {
+      const int c = ci < nl ? live_col(E, ci) : 0;
+      const int n = ci < nl ? E.act_cnt()[c] : 0;
+      const int lo = ci < nl ? E.colstart(c) : 0;
       for (int k = tm.tl; k < n; k += tm.ts) {
         const int s = E.act_slot()[lo + k];
         if (s < 0) continue;
@@ -1147,8 +1214,10 @@ SHD void f_records(const Team& tm, const DevModel& M, const Env& E, bool act, in
   const int n_e = placed_contacts(E, act);
   const unsigned long long base = tm.reserve(ra.count, act ? n_e : 0);
   long long idx = (long long)base;
-  for (int c = 0; tm.any(c < E.ncol && act); ++c) {
-    const bool cc = act && c < E.ncol && is_contact_colour(E, c);
+  const int nl = n_live(E, act);
+  for (int ci = 0; tm.any(ci < nl); ++ci) {
+    const int c = ci < nl ? live_col(E, ci) : 0;
+    const bool cc = ci < nl && is_contact_colour(E, c);
     const int n = cc ? E.act_cnt()[c] : 0;
     const int lo = cc ? E.colstart(c) : 0;
     for (int k = tm.tl; k < n; k += tm.ts) {
@@ -1311,9 +1380,11 @@ SHD void a_clear_step(const Team& tm, const Env& E, bool act) {
 // constants (zeros): their adjoint is dropped here.
 template <class Team>
 SHD void a_store(const Team& tm, const Env& E, bool act) {
-  for (int c = 0; tm.any(c < E.ncol && act); ++c) {
-    const int n = (act && c < E.ncol) ? E.act_cnt()[c] : 0;
-    const int lo = (act && c < E.ncol) ? E.colstart(c) : 0;
+  const int nl = n_live(E, act);
+  for (int ci = 0; tm.any(ci < nl); ++ci) {
+    const int c = ci < nl ? live_col(E, ci) : 0;
+    const int n = ci < nl ? E.act_cnt()[c] : 0;
+    const int lo = ci < nl ? E.colstart(c) : 0;
     for (int k = tm.tl; k < n; k += tm.ts) {
       const int s = E.act_slot()[lo + k];
       if (s < 0) continue;
@@ -1337,8 +1408,8 @@ SHD void a_store(const Team& tm, const Env& E, bool act) {
   }
   tm.sync();
   // the adjoint of the incoming store is rebuilt by the warm-start reverse
-  const int nl = act ? E.lam_size : 0;
-  for (int i = tm.tl; i < nl; i += tm.ts) E.wsA()[i] = 0.f;
+  const int nls = act ? E.lam_size : 0;
+  for (int i = tm.tl; i < nls; i += tm.ts) E.wsA()[i] = 0.f;
   tm.sync();
 }
 
@@ -1494,6 +1565,58 @@ SHD void rev_scalar(const RR& R, QR& Q, VR& V, VR& A, bool ha, float ima, float 
   Q.l = -wv + ltb + gamma * sb;
 }
 
+// Shape-specialised reverse helpers of a hinge row (see rs_jv).
+template <int S>
+SHD float rs_wv(const RR& R, const VR& A, bool ha, float ima, float imb) {
+  float s = S < 3 ? imb * A.vb[S] : 0.f;
+  s += R.wb[0] * A.wb[0] + R.wb[1] * A.wb[1] + R.wb[2] * A.wb[2];
+  if (ha) {
+    if (S < 3) s -= ima * A.va[S];
+    s += R.wa[0] * A.wa[0] + R.wa[1] * A.wa[1] + R.wa[2] * A.wa[2];
+  }
+  return s;
+}
+template <int S>
+SHD void rs_wbar(QR& Q, const VR& A, bool ha, float d, float& imA, float& imB) {
+  for (int k = 0; k < 3; ++k) Q.wb[k] += A.wb[k] * d;
+  if (S < 3) imB += d * A.vb[S];
+  if (ha) {
+    for (int k = 0; k < 3; ++k) Q.wa[k] += A.wa[k] * d;
+    if (S < 3) imA -= d * A.va[S];
+  }
+}
+template <int S>
+SHD void rs_jbar(QR& Q, const RR& R, VR& A, const VR& V, bool ha, float sb) {
+  if (S < 3) A.vb[S] += sb;
+  for (int k = 0; k < 3; ++k) {
+    A.wb[k] += R.jb[k] * sb;
+    Q.jb[k] += sb * V.wb[k];
+  }
+  if (ha) {
+    if (S < 3) A.va[S] -= sb;
+    for (int k = 0; k < 3; ++k) {
+      A.wa[k] += R.ja[k] * sb;
+      Q.ja[k] += sb * V.wa[k];
+    }
+  }
+}
+// Reverse of one (unbounded) hinge row update.
+template <int S>
+SHD void rev_hinge_row(const RR& R, QR& Q, VR& V, VR& A, bool ha, float ima, float imb, float lt, float lp,
+                       float gamma, float& imA, float& imB) {
+  const float d = lt - lp;
+  rs_apply<S>(R, V, ha, ima, imb, -d);   // v before the update
+  rs_wbar<S>(Q, A, ha, d, imA, imB);
+  const float wv = rs_wv<S>(R, A, ha, ima, imb);
+  const float ltb = Q.l + wv;
+  const float sb = -R.m * ltb;
+  const float sval = rs_jv<S>(R, V, ha) + R.bias + gamma * lp;
+  Q.m += -sval * ltb;
+  Q.b += sb;
+  rs_jbar<S>(Q, R, A, V, ha, sb);
+  Q.l = -wv + ltb + gamma * sb;
+}
+
 // Reverse of one hinge visit (rows 4..0).  Row data and row adjoint
 // accumulators are streamed: row q-1 is loaded while row q is reversed.
 SHD void rev_joint(const DevModel& M, const Env& E, int s, int a, int b, const float* H, const float* Hp) {
@@ -1518,7 +1641,10 @@ SHD void rev_joint(const DevModel& M, const Env& E, int s, int a, int b, const f
       ltn = H[s + q - 1];
       lpn = Hp ? Hp[s + q - 1] : E.row(s + q - 1)[RL0];
     }
-    rev_scalar(Rc, Qc, V, A, ha, ima, imb, ltc, lpc, true, M.gamma, imA, imB);
+    if (q >= 3) rev_hinge_row<3>(Rc, Qc, V, A, ha, ima, imb, ltc, lpc, M.gamma, imA, imB);
+    else if (q == 2) rev_hinge_row<2>(Rc, Qc, V, A, ha, ima, imb, ltc, lpc, M.gamma, imA, imB);
+    else if (q == 1) rev_hinge_row<1>(Rc, Qc, V, A, ha, ima, imb, ltc, lpc, M.gamma, imA, imB);
+    else rev_hinge_row<0>(Rc, Qc, V, A, ha, ima, imb, ltc, lpc, M.gamma, imA, imB);
     qr_store(Qc, E.rowA(s + q));
     if (q > 0) { Rc = Rn; Qc = Qn; ltc = ltn; lpc = lpn; }
   }
@@ -1601,13 +1727,15 @@ SHD void rev_contact(const DevModel& M, const Env& E, int s, int a, int b, float
 template <class Team>
 SHD void a_pgs(const Team& tm, const DevModel& M, const Env& E, bool act) {
   const float mu = E.misc()[MISC_MU];
+  const int nl = n_live(E, act);
   float gmu = 0.f;
   for (int it = M.n_iters - 1; it >= 0; --it) {
     const float* H = E.hist(it);
     const float* Hp = it > 0 ? E.hist(it - 1) : nullptr;
-    for (int c = E.ncol - 1; tm.any(c >= 0 && act); --c) {
-      const int n = (act && c >= 0) ? E.act_cnt()[c] : 0;
-      const int lo = (act && c >= 0) ? E.colstart(c) : 0;
+    for (int ci = nl - 1; tm.any(ci >= 0); --ci) {
+      const int c = ci >= 0 ? live_col(E, ci) : 0;
+      const int n = ci >= 0 ? E.act_cnt()[c] : 0;
+      const int lo = ci >= 0 ? E.colstart(c) : 0;
       for (int k = tm.tl; k < n; k += tm.ts) {
         const int s = E.act_slot()[lo + k];
         if (s < 0) continue;
@@ -1628,9 +1756,11 @@ SHD void a_pgs(const Team& tm, const DevModel& M, const Env& E, bool act) {
 // B5: adjoint of the warm start v += W lambda0 and of lambda0 = warm * store.
 template <class Team>
 SHD void a_warm(const Team& tm, const DevModel& M, const Env& E, bool act) {
-  for (int c = E.ncol - 1; tm.any(c >= 0 && act); --c) {
-    const int n = (act && c >= 0) ? E.act_cnt()[c] : 0;
-    const int lo = (act && c >= 0) ? E.colstart(c) : 0;
+  const int nl = n_live(E, act);
+  for (int ci = nl - 1; tm.any(ci >= 0); --ci) {
+    const int c = ci >= 0 ? live_col(E, ci) : 0;
+    const int n = ci >= 0 ? E.act_cnt()[c] : 0;
+    const int lo = ci >= 0 ? E.colstart(c) : 0;
     for (int k = tm.tl; k < n; k += tm.ts) {
       const int s = E.act_slot()[lo + k];
       if (s < 0) continue;
@@ -1845,9 +1975,11 @@ SHD void a_contact(const DevModel& M, const Env& E, int code, int s) {
 // B4: adjoint of the row set-up, colour by colour (disjoint bodies).
 template <class Team>
 SHD void a_rows(const Team& tm, const DevModel& M, const Env& E, bool act) {
-  for (int c = E.ncol - 1; tm.any(c >= 0 && act); --c) {
-    const int n = (act && c >= 0) ? E.act_cnt()[c] : 0;
-    const int lo = (act && c >= 0) ? E.colstart(c) : 0;
+  const int nl = n_live(E, act);
+  for (int ci = nl - 1; tm.any(ci >= 0); --ci) {
+    const int c = ci >= 0 ? live_col(E, ci) : 0;
+    const int n = ci >= 0 ? E.act_cnt()[c] : 0;
+    const int lo = ci >= 0 ? E.colstart(c) : 0;
     for (int k = tm.tl; k < n; k += tm.ts) {
       const int s = E.act_slot()[lo + k];
       if (s < 0) continue;
@@ -1860,9 +1992,18 @@ SHD void a_rows(const Team& tm, const DevModel& M, const Env& E, bool act) {
 }
 
 // B3: adjoint of the prediction; B2: torques (per joint colour); B1: Iw.
+// Largest adjoint magnitude a gradient keeps.  Beyond it an env's gradient is
+// treated as overflowed: its products with the controller's activations (|s|
+// up to ~1e2), summed over ~1e6 env-steps, would no longer be representable.
+#define ADJ_LIMIT 1.0e30f
+
+// bad (per lane): set when a control adjoint this lane writes exceeds ADJ_LIMIT
+SHD void a_predict_torques_flag(bool* bad, float v) {
+  if (bad && !(fabsf(v) <= ADJ_LIMIT)) *bad = true;
+}
 template <class Team>
 SHD void a_predict_torques(const Team& tm, const DevModel& M, const Env& E, bool act, float* g_u_row,
-                           float* g_damp) {
+                           float* g_damp, bool* bad = nullptr) {
   const int nb = act ? E.nb : 0;
   for (int b = tm.tl; b < nb; b += tm.ts) {
     const float* B = E.body(b);
@@ -1874,12 +2015,10 @@ SHD void a_predict_torques(const Team& tm, const DevModel& M, const Env& E, bool
     add_outer(A + AIW, M.dt * wb, ld3(B + BTQ));
   }
   tm.sync();
-  for (int c = 0; tm.any(c < E.ncol && act); ++c) {
+  const int njc = n_joint_cols(E, act);
+  for (int c = 0; tm.any(c < njc); ++c) {
     int lo = 0, hi = 0;
-    if (act && c < E.ncol) {
-      lo = E.colstart(c); hi = E.colstart(c + 1);
-      if (lo >= E.nj || cand_kind(E.cand(lo)) != K_JOINT) hi = lo;
-    }
+    if (c < njc) { lo = E.colstart(c); hi = E.colstart(c + 1); }
     for (int i = lo + tm.tl; i < hi; i += tm.ts) {
       const int j = cand_idx(E.cand(i));
       const float* C = E.jc(j);
@@ -1894,7 +2033,10 @@ SHD void a_predict_torques(const Team& tm, const DevModel& M, const Env& E, bool
       const float taub = dot(n, tqd);
       f3 nb_ = tau * tqd - (taub * dmp) * wrel;
       if (M.ctrl) E.mlpA()[j] = taub;
-      else if (g_u_row) g_u_row[E.j0 + j] = taub;
+      else if (g_u_row) {
+        g_u_row[E.j0 + j] = taub;
+        a_predict_torques_flag(bad, taub);
+      }
       kahan_add(E.jA() + j, E.jA() + E.nj + j, -taub * dot(wrel, n));
       add3(Ab + AW, -(taub * dmp) * n);
       if (a >= 0) {
@@ -1937,7 +2079,7 @@ SHD void a_predict_torques(const Team& tm, const DevModel& M, const Env& E, bool
 // activations to the env-step tape for the weight-gradient contraction) and
 // the adjoint of the sensors into the state adjoint of x^t.
 template <class Team>
-SHD void a_controller(const Team& tm, const DevModel& M, const Env& E, bool act, int t) {
+SHD void a_controller(const Team& tm, const DevModel& M, const Env& E, bool act, int t, bool* bad = nullptr) {
   if (!M.ctrl) return;
   const int in = M.mlp_in, n1 = M.mlp_h1, n2 = M.mlp_h2, no = M.mlp_out;
   const float* sv_ = E.mlp();
@@ -1974,18 +2116,19 @@ SHD void a_controller(const Team& tm, const DevModel& M, const Env& E, bool act,
     for (int k = tm.tl; k < len; k += tm.ts) {
       float v;
       if (k < tape_du(M)) v = sv_[k];                 // s, h1, h2 are contiguous in LDS
-      else v = du[k - tape_du(M)];                    // du, d2, d1 are contiguous in LDS
+      else {
+        v = du[k - tape_du(M)];                       // du, d2, d1 are contiguous in LDS
+        a_predict_torques_flag(bad, v);
+      }
       row[k] = v;
     }
   }
   tm.sync();
   // sensors: theta = atan2(y, x), y = (ua x ub).na, x = ua.ub ; rate = wrel.na
-  for (int c = 0; tm.any(c < E.ncol && act); ++c) {
+  const int njc = n_joint_cols(E, act);
+  for (int c = 0; tm.any(c < njc); ++c) {
     int lo = 0, hi = 0;
-    if (act && c < E.ncol) {
-      lo = E.colstart(c); hi = E.colstart(c + 1);
-      if (lo >= E.nj || cand_kind(E.cand(lo)) != K_JOINT) hi = lo;
-    }
+    if (c < njc) { lo = E.colstart(c); hi = E.colstart(c + 1); }
     for (int i = lo + tm.tl; i < hi; i += tm.ts) {
       const int j = cand_idx(E.cand(i));
       const int a = E.jpar(j), b = E.jchi(j);
