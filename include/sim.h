@@ -154,6 +154,11 @@ typedef struct {
   const float* ws_net;           /* host [SIM_WSN_PARAMS] FP32 weights (rounded to bfloat16 by sim_init) */
   int32_t fb_iters;
   float fb_tol;
+  /* Reverse sweep memory: 0 = automatic (each step's working set after its
+     sweeps is saved during the segment recompute when these buffers fit
+     4 GiB, which saves replaying the step; else step-start states only and a
+     replay), 1 = always replay (least memory).  Results are the same. */
+  int32_t grad_replay;
 } sim_model_desc;
 
 /* Sizes derived by sim_init. */

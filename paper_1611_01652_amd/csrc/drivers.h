@@ -154,6 +154,46 @@ SHD void loss_adj(const DevModel& M, const Env& E, int t1, const float* p, float
   pbar[0] += -dl / ((float)E.T * M.dt);
 }
 
+// Saved working set of one step (reverse sweep without replays): the forward
+// LDS region, the sweep history and the step-start angular velocities, as
+// they stand after the sweeps (before integration and the impulse store).
+template <class Team>
+SHD void save_step(const Team& tm, const DevModel& M, const Env& E, float* dst) {
+  const int nf = E.lay.total_fwd, nh = align4(M.n_iters * E.nslot);
+  for (int i = tm.tl; i < nf / 4; i += tm.ts) st4(dst + 4 * i, ld4(E.L + 4 * i));
+  const float* hs = E.L + E.lay.hist;
+  for (int i = tm.tl; i < nh / 4; i += tm.ts) st4(dst + nf + 4 * i, ld4(hs + 4 * i));
+  for (int b = tm.tl; b < E.nb; b += tm.ts)
+    for (int k = 0; k < 3; ++k) dst[nf + nh + 3 * b + k] = E.bodyA(b)[AW0 + k];
+}
+// The misc slots are not restored: the reverse keeps running totals there
+// (the friction coefficient's adjoint).
+template <class Team>
+SHD void load_step(const Team& tm, const DevModel& M, const Env& E, const float* src) {
+  const int nf = E.lay.total_fwd, nh = align4(M.n_iters * E.nslot);
+  const int m0 = E.lay.misc / 4, m1 = (E.lay.misc + MISC_N) / 4;
+  for (int i = tm.tl; i < nf / 4; i += tm.ts)
+    if (i < m0 || i >= m1) st4(E.L + 4 * i, ld4(src + 4 * i));
+  float* hs = E.L + E.lay.hist;
+  for (int i = tm.tl; i < nh / 4; i += tm.ts) st4(hs + 4 * i, ld4(src + nf + 4 * i));
+  for (int b = tm.tl; b < E.nb; b += tm.ts)
+    for (int k = 0; k < 3; ++k) E.bodyA(b)[AW0 + k] = src[nf + nh + 3 * b + k];
+}
+
+// Step t up to the end of its sweeps, recording what the reverse needs.
+template <class Team>
+SHD void replay_to_sweeps(const Team& tm, const DevModel& M, const Env& E, const GradArgs& a, bool act, int t) {
+  f_controls(tm, M, E, (a.u && !M.ctrl) ? a.u + (size_t)t * M.J : nullptr, act, t);
+  f_body_setup(tm, E, act, true);
+  tm.sync();
+  f_torques(tm, E, act);
+  f_predict(tm, M, E, act);
+  tm.sync();
+  f_rows(tm, M, E, act);
+  f_warm(tm, E, act);
+  f_pgs(tm, M, E, act, true);
+}
+
 template <class Team>
 SHD_FLAT void env_rollout_grad(const Team& tm, const DevModel& M, const Env& E, bool valid, const GradArgs& a) {
   if (valid) {
@@ -168,7 +208,8 @@ SHD_FLAT void env_rollout_grad(const Team& tm, const DevModel& M, const Env& E, 
   const int T = valid ? E.T : 0;
   const float dl = valid ? a.dloss[E.e] : 0.f;
   const int nseg = (T + K - 1) / K;
-  const int sstride = 18 * (valid ? E.nb : 0) + (valid ? E.lam_size : 0);
+  const int sstride = !valid ? 0 : (M.dump ? dump_stride_of(E.lay.total_fwd, M.n_iters, E.nslot, E.nb)
+                                            : 18 * E.nb + E.lam_size);
   float* seg = valid ? a.seg + E.seg_off : nullptr;
   // zero the control gradient rows beyond T (and all rows of idle envs)
   if (valid && a.g_u && !M.ctrl)
@@ -181,9 +222,19 @@ SHD_FLAT void env_rollout_grad(const Team& tm, const DevModel& M, const Env& E, 
     const int t1 = sact ? (t0 + K < T ? t0 + K : T) : 0;
     if (sact) read_ckpt(tm, M, E, a.ckpt + (size_t)sg * ckpt_stride(M));
     tm.sync();
-    // recompute the segment, keeping each step-start state
+    // recompute the segment, keeping each step-start state, or (M.dump) each
+    // step's working set after its sweeps
     for (int t = t0; tm.any(t < t1); ++t) {
       const bool act = t < t1;
+      if (M.dump) {
+        replay_to_sweeps(tm, M, E, a, act, t);
+        if (act) save_step(tm, M, E, seg + (size_t)(t - t0) * sstride);
+        tm.sync();   // the copy reads bodies and rows that integration rewrites
+        f_integrate(tm, M, E, act);
+        f_store(tm, E, act);
+        tm.sync();
+        continue;
+      }
       if (act) {
         float* dst = seg + (size_t)(t - t0) * sstride;
         for (int i = tm.tl; i < 18 * E.nb; i += tm.ts) dst[i] = E.body(i / 18)[i % 18];
@@ -199,22 +250,20 @@ SHD_FLAT void env_rollout_grad(const Team& tm, const DevModel& M, const Env& E, 
     // reverse the segment's steps
     for (int t = t1 - 1; tm.any(t >= t0 && sact); --t) {
       const bool act = sact && t >= t0;
-      if (act) {
-        const float* src = seg + (size_t)(t - t0) * sstride;
-        for (int i = tm.tl; i < 18 * E.nb; i += tm.ts) E.body(i / 18)[i % 18] = src[i];
-        for (int i = tm.tl; i < E.lam_size; i += tm.ts) E.ws()[i] = src[18 * E.nb + i];
+      if (M.dump) {
+        // the saved working set of step t replaces its replay
+        if (act) load_step(tm, M, E, seg + (size_t)(t - t0) * sstride);
+        tm.sync();
+      } else {
+        if (act) {
+          const float* src = seg + (size_t)(t - t0) * sstride;
+          for (int i = tm.tl; i < 18 * E.nb; i += tm.ts) E.body(i / 18)[i % 18] = src[i];
+          for (int i = tm.tl; i < E.lam_size; i += tm.ts) E.ws()[i] = src[18 * E.nb + i];
+        }
+        tm.sync();
+        // replay step t with recording (no integration, no store)
+        replay_to_sweeps(tm, M, E, a, act, t);
       }
-      tm.sync();
-      // replay step t with recording (no integration, no store)
-      f_controls(tm, M, E, (a.u && !M.ctrl) ? a.u + (size_t)t * M.J : nullptr, act, t);
-      f_body_setup(tm, E, act, true);
-      tm.sync();
-      f_torques(tm, E, act);
-      f_predict(tm, M, E, act);
-      tm.sync();
-      f_rows(tm, M, E, act);
-      f_warm(tm, E, act);
-      f_pgs(tm, M, E, act, true);
       // loss on x^{t+1}: p(t+1) = p(t) + dt v'
       if (act && tm.tl == 0 && M.loss_kind == 1) {
         const float* B = E.body(E.lb);

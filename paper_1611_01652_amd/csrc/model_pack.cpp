@@ -22,6 +22,7 @@ struct HostEnv {
   std::vector<float> cst;
   int team = 1;
   int fwd_floats = 0, adj_floats = 0;
+  int dump_floats = 0;     // one step's saved working set (see drivers.h)
 };
 
 std::string* g_msg = nullptr;
@@ -198,6 +199,7 @@ sim_status build_env(const sim_model_desc& d, int e, HostEnv& H) {
   const int vs = vsave_floats(d.ws_kind, H.nb);
   H.fwd_floats = make_lay(H.nb, H.nj, H.G, H.P, H.ncol, H.ncand, H.nslot, H.lam, d.n_iters, false, mf, ma, vs).total;
   H.adj_floats = make_lay(H.nb, H.nj, H.G, H.P, H.ncol, H.ncand, H.nslot, H.lam, d.n_iters, true, mf, ma, vs).total;
+  H.dump_floats = dump_stride_of(H.fwd_floats, d.n_iters, H.nslot, H.nb);
   return SIM_OK;
 }
 
@@ -223,6 +225,8 @@ sim_status pack_model(const sim_model_desc* d, PackedModel& P, std::string& err)
       if (d->mlp_sizes[k] <= 0) { g_msg = nullptr; err = "controller sizes must be > 0"; return SIM_E_ARG; }
     if (d->mlp_sizes[1] > 256 || d->mlp_sizes[2] > 256) { g_msg = nullptr; err = "controller hidden width > 256"; return SIM_E_UNSUPPORTED; }
   }
+  std::vector<long long> seg_replay, seg_dump;
+  long long dump_total = 0;
   for (int e = 0; e < E; ++e) {
     HostEnv H;
     const sim_status st = build_env(*d, e, H);
@@ -232,7 +236,10 @@ sim_status pack_model(const sim_model_desc* d, PackedModel& P, std::string& err)
     hd[H_LAMOFF] = P.lam_off[e]; hd[H_LAMSZ] = H.lam; hd[H_G] = H.G; hd[H_P] = H.P; hd[H_NCOL] = H.ncol;
     hd[H_TOPO] = (int)P.topo.size(); hd[H_CST] = (int)P.cst.size(); hd[H_T] = d->T_env[e];
     hd[H_LB] = d->loss_body[e] - d->env_body_off[e]; hd[H_CCAP] = H.ccap; hd[H_NCAND] = H.ncand;
-    hd[H_ENV] = e; hd[H_SEG] = (int)P.seg_total; hd[H_NSLOT] = H.nslot;
+    hd[H_ENV] = e; hd[H_NSLOT] = H.nslot;
+    seg_replay.push_back(P.seg_total);
+    seg_dump.push_back(dump_total);
+    dump_total += (long long)d->ckpt_every * H.dump_floats;
     hd[H_TAPE] = (int)P.tape_rows;
     if (d->ctrl_kind == 1) P.tape_rows += d->T_env[e];
     P.seg_total += (long long)d->ckpt_every * (18 * H.nb + H.lam);
@@ -246,6 +253,12 @@ sim_status pack_model(const sim_model_desc* d, PackedModel& P, std::string& err)
     P.adj_of[e] = H.adj_floats;
     P.ccap_of[e] = H.ccap;
   }
+  // The reverse sweep replays each step to recover its working set, unless the
+  // working sets of a whole segment fit the budget: then the recompute saves
+  // them and the replay is skipped.
+  P.dump = (!d->grad_replay && dump_total <= kDumpBudgetFloats) ? 1 : 0;
+  if (P.dump) P.seg_total = dump_total;
+  for (int e = 0; e < E; ++e) P.hdr[(size_t)e * H_COUNT + H_SEG] = (int)(P.dump ? seg_dump[e] : seg_replay[e]);
   g_msg = nullptr;
   return SIM_OK;
 }

@@ -13,7 +13,12 @@ struct PackedModel {
   std::vector<float> cst, target;
   long long seg_total = 0;
   long long tape_rows = 0;   // env-steps of the controller tape (sum of T_e)
+  int dump = 0;              // segment buffer holds saved step working sets (no replay)
 };
+
+// Largest segment buffer (floats) for which the reverse sweep saves each
+// step's working set instead of replaying the step: 2^30 floats (4 GiB).
+constexpr long long kDumpBudgetFloats = 1LL << 30;
 
 // Validates the per-env parts of the description and builds, per env, the
 // header, topology ints (parents, children, ground bodies, pair codes, colour

@@ -426,6 +426,7 @@ sim_status sim_init(const sim_model_desc* d, sim_handle* out) {
     if ((st = upload(&h->d_wsn, wb)) != SIM_OK) { release(h); return st; }
     M.wsn = h->d_wsn;
   }
+  M.dump = P.dump;
   h->tape_rows = P.tape_rows;
   h->seg_floats = (P.seg_total + 63) & ~63LL;
   h->tape_floats = M.ctrl ? ((P.tape_rows * M.tape_stride + 63) & ~63LL) : 0;

@@ -102,6 +102,7 @@ struct DevModel {
   int solve_mode, max_iters, ws_kind, fb_iters;
   float tol, fb_tol;
   const uint16_t* wsn; // warm-start network, bfloat16 [4867]
+  int dump;           // reverse sweep: saved step working sets instead of replays
 };
 // tape row: s, h1, h2, du, d2, d1 (pre-activation adjoints)
 SHD int tape_s(const DevModel&) { return 0; }
@@ -222,6 +223,11 @@ struct Env {
 SHD int mlp_floats_fwd(const DevModel& M) { return M.ctrl ? M.mlp_in + M.mlp_h1 + M.mlp_h2 : 0; }
 SHD int mlp_floats_adj(const DevModel& M) { return M.ctrl ? M.mlp_out + M.mlp_h2 + M.mlp_h1 + M.mlp_in : 0; }
 SHD int vsave_floats(int ws_kind, int nb) { return ws_kind ? 6 * nb : 0; }
+// Floats of one step's saved working set: the forward LDS region, the sweep
+// history and the step-start angular velocities.
+SHD int dump_stride_of(int total_fwd, int n_iters, int nslot, int nb) {
+  return total_fwd + align4(n_iters * nslot) + align4(3 * nb);
+}
 
 SHD Env make_env(const DevModel& M, int ie, float* lds, int n_iters, bool adj) {
   const int* h = M.hdr + (size_t)ie * H_COUNT;

@@ -40,6 +40,7 @@ class SimDesc(C.Structure):
         ("ctrl_kind", C.c_int32), ("mlp_sizes", C.c_int32 * 4), ("clock_hz", C.c_float),
         ("solve_mode", C.c_int32), ("tol", C.c_float), ("max_iters", C.c_int32),
         ("ws_kind", C.c_int32), ("ws_net", _F32P), ("fb_iters", C.c_int32), ("fb_tol", C.c_float),
+        ("grad_replay", C.c_int32),
     ]
 
 
@@ -102,6 +103,7 @@ def make_desc(w):
         d.mlp_sizes = (C.c_int32 * 4)(*[int(v) for v in mlp["sizes"]])
         d.clock_hz = float(mlp.get("clock_hz", 1.5))
     extra = getattr(w, "extra", None) or {}
+    d.grad_replay = int(bool(extra.get("grad_replay", False)))
     solve = extra.get("solve")
     if solve is not None:
         d.solve_mode = int(solve.get("mode", 1))

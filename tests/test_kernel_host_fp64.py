@@ -76,6 +76,7 @@ def _desc64(w):
     d.beta, d.gamma, d.spec_margin, d.warm = f(w.beta), f(w.gamma), f(w.spec_margin), f(w.warm)
     d.n_iters, d.ground, d.loss_kind, d.loss_mask = w.n_iters, w.ground, w.loss_kind, w.loss_mask
     d.ckpt_every, d.min_team = w.ckpt_every, 0
+    d.grad_replay = int(bool((getattr(w, "extra", None) or {}).get("grad_replay", False)))
     mlp = w.extra.get("mlp") if getattr(w, "extra", None) else None
     if mlp is not None:
         d.ctrl_kind = 1
@@ -128,7 +129,15 @@ def _rel(a, b):
     return np.linalg.norm(a - b) / n if n > 1e-12 else np.linalg.norm(a - b)
 
 
+def _replay(w):
+    w.extra = dict(w.extra or {})
+    w.extra["grad_replay"] = True
+    return w
+
+
 @pytest.mark.parametrize("maker,tol", [
+    (lambda: _replay(W.planar_arms(n_envs=4, T=300)), 1e-9),
+    (lambda: _replay(W.uneven_chains(n_envs=6, T=150, seed_salt=2)), 1e-7),
     (lambda: W.ball_throw(), 1e-10),
     (lambda: W.planar_arms(n_envs=6, T=1000), 1e-9),
     (lambda: W.uneven_chains(n_envs=10, T=300, seed_salt=2), 1e-7),
