@@ -53,7 +53,7 @@
 extern "C" {
 #endif
 
-#define SIM_ABI_VERSION 1
+#define SIM_ABI_VERSION 2
 
 typedef struct sim_model* sim_handle;
 
@@ -86,6 +86,21 @@ typedef enum {
 /* solver and warm-start kinds */
 #define SIM_SOLVE_FIXED 0 /* n_iters sweeps per step */
 #define SIM_SOLVE_TOL 1   /* sweeps until the residual is at most tol */
+/* Reverse sweep memory modes (sim_model_desc.grad_store).  Rollouts keep a
+   checkpoint every K_ck steps; rollout_grad then
+   - REPLAY: recomputes one segment at a time keeping step-start states, and
+     replays each step up to its sweeps before reversing it (least memory:
+     K_ck states per env);
+   - SEGMENT: recomputes one segment at a time saving each step's working set
+     after its sweeps, which the reverse reloads (K_ck working sets per env);
+   - TRAJECTORY: recomputes all segments of all envs at once in a separate
+     launch, saving every step's working set, then reverses the whole
+     trajectory from them (T working sets per env). */
+#define SIM_GRAD_AUTO 0
+#define SIM_GRAD_REPLAY 1
+#define SIM_GRAD_SEGMENT 2
+#define SIM_GRAD_TRAJECTORY 3
+
 #define SIM_WS_PLAIN 0    /* warm start: the previous step's impulses times `warm` */
 #define SIM_WS_LEARNED 1  /* contacts: the warm-start network, with fallback */
 
@@ -154,11 +169,12 @@ typedef struct {
   const float* ws_net;           /* host [SIM_WSN_PARAMS] FP32 weights (rounded to bfloat16 by sim_init) */
   int32_t fb_iters;
   float fb_tol;
-  /* Reverse sweep memory: 0 = automatic (each step's working set after its
-     sweeps is saved during the segment recompute when these buffers fit
-     4 GiB, which saves replaying the step; else step-start states only and a
-     replay), 1 = always replay (least memory).  Results are the same. */
-  int32_t grad_replay;
+  /* Reverse sweep memory (the rollout_grad workspace), one of SIM_GRAD_*.
+     SIM_GRAD_AUTO takes the first of TRAJECTORY, SEGMENT, REPLAY whose
+     buffers fit grad_mem_limit bytes (0: 32 GiB).  Every mode gives the same
+     result bits; they trade memory for recomputation. */
+  int32_t grad_store;
+  int64_t grad_mem_limit;
 } sim_model_desc;
 
 /* Sizes derived by sim_init. */
@@ -171,6 +187,7 @@ typedef struct {
   int32_t max_lds_bytes;      /* largest LDS allocation per workgroup among the tiles */
   int32_t n_tiles;            /* env tiles scheduled per rollout */
   int32_t n_params;           /* controller parameters (0 for a control tape) */
+  int32_t grad_store;         /* reverse sweep memory mode chosen (SIM_GRAD_REPLAY, _SEGMENT or _TRAJECTORY) */
 } sim_info;
 
 int sim_abi_version(void);
@@ -248,13 +265,23 @@ sim_status rollout_solve(sim_handle h, const float* x0, const float* u, float* l
  * over env-steps are no longer representable); that env's gradients are
  * written as zeros and it contributes nothing to dL/dW.
  * workspace: device scratch of at least sim_info.workspace_bytes (the
- * per-env segment buffer of the checkpoint recompute and, with a controller,
- * the per env-step activations and deltas plus the split-K partial sums of
- * the weight-gradient contraction). */
+ * per-env buffer of the checkpoint recompute, see SIM_GRAD_*, and, with a
+ * controller, the per env-step activations and deltas plus the split-K
+ * partial sums of the weight-gradient contraction).
+ * In trajectory mode the call makes two launches per bucket: the recompute
+ * of all segments (k_recompute), then the reverse sweep (k_rollout_grad). */
 sim_status rollout_grad(sim_handle h, const float* x0, const float* u, const float* ckpt,
                         const float* dloss_env, float* g_x0, float* g_u, float* g_inv_mass,
                         float* g_inv_inertia, float* g_mu, float* g_damping, void* workspace,
                         size_t workspace_bytes, uint32_t* env_flags, void* stream);
+
+/* Device timing of rollout_grad's phases.  While set, every rollout_grad call
+ * on h records, on its stream, ev[0] and ev[1] around the recompute of all
+ * segments (back to back when the mode has no such phase) and ev[2] and ev[3]
+ * around the reverse sweep (the weight-gradient contraction of a controller
+ * comes after ev[3]).  ev: 4 hipEvent_t created by the caller, which keeps
+ * them alive while they are set; ev = NULL stops the recording. */
+sim_status sim_time_grad(sim_handle h, void* const* ev);
 
 /* ---- Replayable step sequences (HIP graphs). ----
  * Captures n_steps consecutive sim_step calls into a HIP graph, for callers

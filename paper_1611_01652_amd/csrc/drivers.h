@@ -1,9 +1,10 @@
 // Env-level drivers built from the step phases: a forward rollout with
 // checkpoints, a single step, and the reverse sweep over checkpointed
-// segments (back-propagation through time, paper section 2.1.1, without
-// keeping the whole unrolled trajectory: each segment of K_ck steps is
-// recomputed from its checkpoint into a small per-env buffer, then its steps
-// are reversed last to first).
+// segments (back-propagation through time, paper section 2.1.1).  The reverse
+// recovers each step's working set from the checkpoints in one of three ways
+// (DUMP_*): a segment at a time, replaying every step; a segment at a time,
+// saving every step's working set during the recompute; or all segments
+// recomputed at once by env_recompute in an earlier launch.
 #pragma once
 #include "step_core.h"
 
@@ -166,32 +167,94 @@ SHD void save_step(const Team& tm, const DevModel& M, const Env& E, float* dst) 
   for (int b = tm.tl; b < E.nb; b += tm.ts)
     for (int k = 0; k < 3; ++k) dst[nf + nh + 3 * b + k] = E.bodyA(b)[AW0 + k];
 }
+// Copy n4 float4 from global memory to LDS, skipping float4 [s0, s1): each
+// lane issues LOAD_BATCH loads before it waits for the first, so a copy costs
+// a few memory round trips instead of one per float4.
+constexpr int LOAD_BATCH = 8;
+template <class Team>
+SHD void copy_to_lds(const Team& tm, float* dst, const float* src, int n4, int s0 = 0, int s1 = 0) {
+  for (int i0 = tm.tl; i0 < n4; i0 += LOAD_BATCH * tm.ts) {
+    f4 v[LOAD_BATCH];
+#pragma unroll
+    for (int u = 0; u < LOAD_BATCH; ++u) {
+      const int i = i0 + u * tm.ts;
+      if (i < n4) v[u] = ld4(src + 4 * i);
+    }
+#pragma unroll
+    for (int u = 0; u < LOAD_BATCH; ++u) {
+      const int i = i0 + u * tm.ts;
+      if (i < n4 && (i < s0 || i >= s1)) st4(dst + 4 * i, v[u]);
+    }
+  }
+}
 // The misc slots are not restored: the reverse keeps running totals there
 // (the friction coefficient's adjoint).
 template <class Team>
 SHD void load_step(const Team& tm, const DevModel& M, const Env& E, const float* src) {
   const int nf = E.lay.total_fwd, nh = align4(M.n_iters * E.nslot);
-  const int m0 = E.lay.misc / 4, m1 = (E.lay.misc + MISC_N) / 4;
-  for (int i = tm.tl; i < nf / 4; i += tm.ts)
-    if (i < m0 || i >= m1) st4(E.L + 4 * i, ld4(src + 4 * i));
-  float* hs = E.L + E.lay.hist;
-  for (int i = tm.tl; i < nh / 4; i += tm.ts) st4(hs + 4 * i, ld4(src + nf + 4 * i));
-  for (int b = tm.tl; b < E.nb; b += tm.ts)
-    for (int k = 0; k < 3; ++k) E.bodyA(b)[AW0 + k] = src[nf + nh + 3 * b + k];
+  copy_to_lds(tm, E.L, src, nf / 4, E.lay.misc / 4, (E.lay.misc + MISC_N) / 4);
+  copy_to_lds(tm, E.L + E.lay.hist, src + nf, nh / 4);
+  for (int b = tm.tl; b < E.nb; b += tm.ts) {
+    const float w0 = src[nf + nh + 3 * b], w1 = src[nf + nh + 3 * b + 1], w2 = src[nf + nh + 3 * b + 2];
+    float* A = E.bodyA(b);
+    A[AW0] = w0; A[AW0 + 1] = w1; A[AW0 + 2] = w2;
+  }
 }
 
-// Step t up to the end of its sweeps, recording what the reverse needs.
+// Step t up to the end of its sweeps, recording what the reverse needs: the
+// sweep history at hist and, with rec_w0, the step-start angular velocities
+// in the adjoint body slots.
 template <class Team>
-SHD void replay_to_sweeps(const Team& tm, const DevModel& M, const Env& E, const GradArgs& a, bool act, int t) {
+SHD void replay_to_sweeps(const Team& tm, const DevModel& M, const Env& E, const GradArgs& a, bool act, int t,
+                          float* hist, bool rec_w0) {
   f_controls(tm, M, E, (a.u && !M.ctrl) ? a.u + (size_t)t * M.J : nullptr, act, t);
-  f_body_setup(tm, E, act, true);
+  f_body_setup(tm, E, act, rec_w0);
   tm.sync();
   f_torques(tm, E, act);
   f_predict(tm, M, E, act);
   tm.sync();
   f_rows(tm, M, E, act);
   f_warm(tm, E, act);
-  f_pgs(tm, M, E, act, true);
+  f_pgs(tm, M, E, act, hist);
+}
+
+// Trajectory mode: recompute segment sg of the env from its checkpoint with
+// the forward LDS layout, writing each step's working set straight into the
+// env's block (the sweep history and step-start angular velocities go to
+// global memory as they are produced), and, for the last segment, the loss
+// body's final position after it.
+template <class Team>
+SHD_FLAT void env_recompute(const Team& tm, const DevModel& M, const Env& E, bool valid, const GradArgs& a, int sg) {
+  const int K = M.ckpt_every;
+  const int T = valid ? E.T : 0;
+  const int t0 = sg * K;
+  const bool live = t0 < T;
+  if (live) {
+    load_env_static(tm, M, E);
+    read_ckpt(tm, M, E, a.ckpt + (size_t)sg * ckpt_stride(M));
+  }
+  tm.sync();
+  const int t1 = live ? (t0 + K < T ? t0 + K : T) : 0;
+  const int nf = E.lay.total_fwd, nh = align4(M.n_iters * E.nslot);
+  const int sstride = live ? dump_stride_of(nf, M.n_iters, E.nslot, E.nb) : 0;
+  float* seg = live ? a.seg + E.seg_base() : nullptr;
+  for (int t = t0; tm.any(t < t1); ++t) {
+    const bool act = t < t1;
+    float* dst = act ? seg + (size_t)t * sstride : nullptr;
+    if (act)
+      for (int b = tm.tl; b < E.nb; b += tm.ts)
+        for (int k = 0; k < 3; ++k) dst[nf + nh + 3 * b + k] = E.body(b)[BW + k];
+    replay_to_sweeps(tm, M, E, a, act, t, dst ? dst + nf : nullptr, false);
+    tm.sync();
+    if (act)
+      for (int i = tm.tl; i < nf / 4; i += tm.ts) st4(dst + 4 * i, ld4(E.L + 4 * i));
+    tm.sync();   // the copy reads bodies and rows that integration rewrites
+    f_integrate(tm, M, E, act);
+    f_store(tm, E, act);
+    tm.sync();
+  }
+  if (live && t1 == T && tm.tl == 0)
+    for (int k = 0; k < 3; ++k) seg[(size_t)T * sstride + k] = E.body(E.lb)[BP + k];
 }
 
 template <class Team>
@@ -208,9 +271,10 @@ SHD_FLAT void env_rollout_grad(const Team& tm, const DevModel& M, const Env& E, 
   const int T = valid ? E.T : 0;
   const float dl = valid ? a.dloss[E.e] : 0.f;
   const int nseg = (T + K - 1) / K;
-  const int sstride = !valid ? 0 : (M.dump ? dump_stride_of(E.lay.total_fwd, M.n_iters, E.nslot, E.nb)
-                                            : 18 * E.nb + E.lam_size);
-  float* seg = valid ? a.seg + E.seg_off : nullptr;
+  const bool traj = M.dump == DUMP_TRAJECTORY;
+  const int sstride = !valid ? 0 : (M.dump != DUMP_REPLAY ? dump_stride_of(E.lay.total_fwd, M.n_iters, E.nslot, E.nb)
+                                                          : 18 * E.nb + E.lam_size);
+  float* seg = valid ? a.seg + E.seg_base() : nullptr;
   // zero the control gradient rows beyond T (and all rows of idle envs)
   if (valid && a.g_u && !M.ctrl)
     for (int t = T; t < M.T_max; ++t)
@@ -220,14 +284,14 @@ SHD_FLAT void env_rollout_grad(const Team& tm, const DevModel& M, const Env& E, 
     const bool sact = sg >= 0;
     const int t0 = sact ? sg * K : 0;
     const int t1 = sact ? (t0 + K < T ? t0 + K : T) : 0;
-    if (sact) read_ckpt(tm, M, E, a.ckpt + (size_t)sg * ckpt_stride(M));
+    if (sact && !traj) read_ckpt(tm, M, E, a.ckpt + (size_t)sg * ckpt_stride(M));
     tm.sync();
-    // recompute the segment, keeping each step-start state, or (M.dump) each
-    // step's working set after its sweeps
-    for (int t = t0; tm.any(t < t1); ++t) {
+    // recompute the segment, keeping each step-start state, or (segment mode)
+    // each step's working set after its sweeps; in trajectory mode it is done
+    for (int t = t0; !traj && tm.any(t < t1); ++t) {
       const bool act = t < t1;
-      if (M.dump) {
-        replay_to_sweeps(tm, M, E, a, act, t);
+      if (M.dump == DUMP_SEGMENT) {
+        replay_to_sweeps(tm, M, E, a, act, t, E.hist(0), true);
         if (act) save_step(tm, M, E, seg + (size_t)(t - t0) * sstride);
         tm.sync();   // the copy reads bodies and rows that integration rewrites
         f_integrate(tm, M, E, act);
@@ -245,14 +309,14 @@ SHD_FLAT void env_rollout_grad(const Team& tm, const DevModel& M, const Env& E, 
     }
     tm.sync();
     if (sact && sg == nseg - 1 && tm.tl == 0 && M.loss_kind != 1)
-      loss_adj(M, E, T, E.body(E.lb) + BP, dl, E.bodyA(E.lb) + AP);
+      loss_adj(M, E, T, traj ? seg + (size_t)T * sstride : E.body(E.lb) + BP, dl, E.bodyA(E.lb) + AP);
     tm.sync();
     // reverse the segment's steps
     for (int t = t1 - 1; tm.any(t >= t0 && sact); --t) {
       const bool act = sact && t >= t0;
-      if (M.dump) {
+      if (M.dump != DUMP_REPLAY) {
         // the saved working set of step t replaces its replay
-        if (act) load_step(tm, M, E, seg + (size_t)(t - t0) * sstride);
+        if (act) load_step(tm, M, E, seg + (size_t)(traj ? t : t - t0) * sstride);
         tm.sync();
       } else {
         if (act) {
@@ -262,7 +326,7 @@ SHD_FLAT void env_rollout_grad(const Team& tm, const DevModel& M, const Env& E, 
         }
         tm.sync();
         // replay step t with recording (no integration, no store)
-        replay_to_sweeps(tm, M, E, a, act, t);
+        replay_to_sweeps(tm, M, E, a, act, t, E.hist(0), true);
       }
       // loss on x^{t+1}: p(t+1) = p(t) + dt v'
       if (act && tm.tl == 0 && M.loss_kind == 1) {

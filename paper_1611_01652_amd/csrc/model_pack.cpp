@@ -225,8 +225,8 @@ sim_status pack_model(const sim_model_desc* d, PackedModel& P, std::string& err)
       if (d->mlp_sizes[k] <= 0) { g_msg = nullptr; err = "controller sizes must be > 0"; return SIM_E_ARG; }
     if (d->mlp_sizes[1] > 256 || d->mlp_sizes[2] > 256) { g_msg = nullptr; err = "controller hidden width > 256"; return SIM_E_UNSUPPORTED; }
   }
-  std::vector<long long> seg_replay, seg_dump;
-  long long dump_total = 0;
+  // per-env buffer sizes of the three reverse sweep modes
+  std::vector<long long> sz_replay(E), sz_segment(E), sz_traj(E);
   for (int e = 0; e < E; ++e) {
     HostEnv H;
     const sim_status st = build_env(*d, e, H);
@@ -237,13 +237,11 @@ sim_status pack_model(const sim_model_desc* d, PackedModel& P, std::string& err)
     hd[H_TOPO] = (int)P.topo.size(); hd[H_CST] = (int)P.cst.size(); hd[H_T] = d->T_env[e];
     hd[H_LB] = d->loss_body[e] - d->env_body_off[e]; hd[H_CCAP] = H.ccap; hd[H_NCAND] = H.ncand;
     hd[H_ENV] = e; hd[H_NSLOT] = H.nslot;
-    seg_replay.push_back(P.seg_total);
-    seg_dump.push_back(dump_total);
-    dump_total += (long long)d->ckpt_every * H.dump_floats;
+    sz_replay[e] = (long long)d->ckpt_every * (18 * H.nb + H.lam);
+    sz_segment[e] = (long long)d->ckpt_every * H.dump_floats;
+    sz_traj[e] = (long long)d->T_env[e] * H.dump_floats + SEG_TAIL;
     hd[H_TAPE] = (int)P.tape_rows;
     if (d->ctrl_kind == 1) P.tape_rows += d->T_env[e];
-    P.seg_total += (long long)d->ckpt_every * (18 * H.nb + H.lam);
-    if (P.seg_total > 0x7fffffffLL) { g_msg = nullptr; err = "segment buffer exceeds 2^31 floats"; return SIM_E_UNSUPPORTED; }
     P.topo.insert(P.topo.end(), H.topo.begin(), H.topo.end());
     P.cst.insert(P.cst.end(), H.cst.begin(), H.cst.end());
     for (int k = 0; k < 3; ++k) P.target[3 * e + k] = d->target[3 * e + k];
@@ -253,12 +251,33 @@ sim_status pack_model(const sim_model_desc* d, PackedModel& P, std::string& err)
     P.adj_of[e] = H.adj_floats;
     P.ccap_of[e] = H.ccap;
   }
-  // The reverse sweep replays each step to recover its working set, unless the
-  // working sets of a whole segment fit the budget: then the recompute saves
-  // them and the replay is skipped.
-  P.dump = (!d->grad_replay && dump_total <= kDumpBudgetFloats) ? 1 : 0;
-  if (P.dump) P.seg_total = dump_total;
-  for (int e = 0; e < E; ++e) P.hdr[(size_t)e * H_COUNT + H_SEG] = (int)(P.dump ? seg_dump[e] : seg_replay[e]);
+  // Each env's block starts on a SEG_UNIT boundary; the header holds its
+  // offset in those units.
+  auto total_of = [&](const std::vector<long long>& sz) {
+    long long t = 0;
+    for (int e = 0; e < E; ++e) t += (sz[e] + SEG_UNIT - 1) / SEG_UNIT * SEG_UNIT;
+    return t;
+  };
+  const long long tot[3] = {total_of(sz_replay), total_of(sz_segment), total_of(sz_traj)};
+  const long long limit = (d->grad_mem_limit > 0 ? d->grad_mem_limit : kGradMemDefault) / 4;
+  if (d->grad_store == SIM_GRAD_AUTO) {
+    // the fastest mode that fits: no replay, and recomputes in parallel
+    P.dump = tot[2] <= limit ? DUMP_TRAJECTORY : (tot[1] <= limit ? DUMP_SEGMENT : DUMP_REPLAY);
+  } else {
+    P.dump = d->grad_store == SIM_GRAD_TRAJECTORY ? DUMP_TRAJECTORY
+             : d->grad_store == SIM_GRAD_SEGMENT  ? DUMP_SEGMENT
+                                                  : DUMP_REPLAY;
+  }
+  const std::vector<long long>& sz = P.dump == DUMP_TRAJECTORY ? sz_traj
+                                     : P.dump == DUMP_SEGMENT  ? sz_segment
+                                                               : sz_replay;
+  long long off = 0;
+  for (int e = 0; e < E; ++e) {
+    if (off / SEG_UNIT > 0x7fffffffLL) { g_msg = nullptr; err = "reverse sweep buffer exceeds 2^31 x 64 floats"; return SIM_E_UNSUPPORTED; }
+    P.hdr[(size_t)e * H_COUNT + H_SEG] = (int)(off / SEG_UNIT);
+    off += (sz[e] + SEG_UNIT - 1) / SEG_UNIT * SEG_UNIT;
+  }
+  P.seg_total = off;
   g_msg = nullptr;
   return SIM_OK;
 }

@@ -11,14 +11,13 @@ namespace sim {
 struct PackedModel {
   std::vector<int> hdr, topo, lam_off, team_of, fwd_of, adj_of, ccap_of;
   std::vector<float> cst, target;
-  long long seg_total = 0;
+  long long seg_total = 0;   // floats of the reverse sweep's buffer (all envs)
   long long tape_rows = 0;   // env-steps of the controller tape (sum of T_e)
-  int dump = 0;              // segment buffer holds saved step working sets (no replay)
+  int dump = 0;              // reverse sweep buffer: DUMP_REPLAY, DUMP_SEGMENT or DUMP_TRAJECTORY
 };
 
-// Largest segment buffer (floats) for which the reverse sweep saves each
-// step's working set instead of replaying the step: 2^30 floats (4 GiB).
-constexpr long long kDumpBudgetFloats = 1LL << 30;
+// Default memory limit of the automatic choice of reverse sweep mode: 32 GiB.
+constexpr long long kGradMemDefault = 32LL << 30;
 
 // Validates the per-env parts of the description and builds, per env, the
 // header, topology ints (parents, children, ground bodies, pair codes, colour

@@ -62,6 +62,7 @@ struct sim_model {
   int lds_allowed = 65536;      // dynamic LDS limit set on the kernels
   int n_graphs = 0;             // live step graphs (they hold the tile lists)
   uint16_t* d_wsn = nullptr;    // warm-start network, bfloat16
+  hipEvent_t tev[4] = {};       // rollout_grad phase events (sim_time_grad), owned by the caller
 };
 
 struct sim_graph_s {
@@ -134,33 +135,50 @@ long long fwd_bytes(const DevModel& M, int team, int floats_fwd, int ccap_max) {
 long long adj_bytes(int team, int floats_adj) { return 4LL * (64 / team) * floats_adj; }
 long long fwd_bytes(const sim_model* h, const Bucket& b) { return fwd_bytes(h->M, b.team, b.floats_fwd, b.ccap_max); }
 
-int grid_for(const sim_model* h, const Bucket& b, long long bytes) {
+int grid_for(const sim_model* h, long long units, long long bytes) {
   int per_cu = bytes > 0 ? (int)((160 * 1024) / bytes) : 8;
   per_cu = std::max(1, std::min(per_cu, 8));
-  return std::max(1, std::min(b.n_tiles, h->n_cu * per_cu));
+  return (int)std::max(1LL, std::min(units, (long long)h->n_cu * per_cu));
 }
+int grid_for(const sim_model* h, const Bucket& b, long long bytes) { return grid_for(h, b.n_tiles, bytes); }
 
 // One bucket's kernels (queue reset + launch) on stream sx.
 bool bucket_step(sim_model* h, size_t i, const DevModel& M, const StepArgs& a, hipStream_t sx) {
   const Bucket& b = h->buckets[i];
-  TileSet ts{b.envs_dev, b.n_tiles, b.floats_fwd, h->d_queue + i};
+  TileSet ts{b.envs_dev, b.n_tiles, b.floats_fwd, h->d_queue + i, 1};
   if (launch_zero(ts.queue, 1, sx) != hipSuccess) return false;
   const long long lds = fwd_bytes(h, b);
   return launch_step(M, ts, b.team, grid_for(h, b, lds), (size_t)lds, a, sx) == hipSuccess;
 }
 bool bucket_rollout(sim_model* h, size_t i, const DevModel& M, const RolloutArgs& a, hipStream_t sx) {
   const Bucket& b = h->buckets[i];
-  TileSet ts{b.envs_dev, b.n_tiles, b.floats_fwd, h->d_queue + i};
+  TileSet ts{b.envs_dev, b.n_tiles, b.floats_fwd, h->d_queue + i, 1};
   if (launch_zero(ts.queue, 1, sx) != hipSuccess) return false;
   const long long lds = fwd_bytes(h, b);
   return launch_rollout(M, ts, b.team, grid_for(h, b, lds), (size_t)lds, a, sx) == hipSuccess;
 }
-bool bucket_grad(sim_model* h, size_t i, const DevModel& M, const GradArgs& a, hipStream_t sx) {
+// Trajectory mode: the recompute of every segment of one bucket's envs into
+// the workspace (a no-op in the other modes).
+bool bucket_recompute(sim_model* h, size_t i, const DevModel& M, const GradArgs& a, hipStream_t sx) {
   const Bucket& b = h->buckets[i];
-  TileSet ts{b.envs_dev, b.n_tiles, b.floats_adj, h->d_queue + i};
+  const int n_seg = M.T_max > 0 ? (M.T_max + M.ckpt_every - 1) / M.ckpt_every : 0;
+  if (M.dump != DUMP_TRAJECTORY || n_seg == 0) return true;
+  TileSet tr{b.envs_dev, b.n_tiles, b.floats_fwd, h->d_queue + i, n_seg};
+  if (launch_zero(tr.queue, 1, sx) != hipSuccess) return false;
+  const long long lf = fwd_bytes(M, b.team, b.floats_fwd, 0);
+  return launch_recompute(M, tr, b.team, grid_for(h, (long long)b.n_tiles * n_seg, lf), (size_t)lf, a, sx) ==
+         hipSuccess;
+}
+// The reverse sweep of one bucket (after its recompute in trajectory mode).
+bool bucket_reverse(sim_model* h, size_t i, const DevModel& M, const GradArgs& a, hipStream_t sx) {
+  const Bucket& b = h->buckets[i];
+  TileSet ts{b.envs_dev, b.n_tiles, b.floats_adj, h->d_queue + i, 1};
   if (launch_zero(ts.queue, 1, sx) != hipSuccess) return false;
   const long long lds = adj_bytes(b.team, b.floats_adj);
   return launch_rollout_grad(M, ts, b.team, grid_for(h, b, lds), (size_t)lds, a, sx) == hipSuccess;
+}
+bool bucket_grad(sim_model* h, size_t i, const DevModel& M, const GradArgs& a, hipStream_t sx) {
+  return bucket_recompute(h, i, M, a, sx) && bucket_reverse(h, i, M, a, sx);
 }
 
 sim_status launch_steps(sim_model* h, const float* x_in, float* x_out, const float* u, const float* lam_in,
@@ -260,6 +278,8 @@ sim_status sim_init(const sim_model_desc* d, sim_handle* out) {
   if (d->ws_kind == SIM_WS_LEARNED && (d->solve_mode != SIM_SOLVE_TOL || !d->ws_net || d->fb_iters < 0 ||
                                        !(d->fb_tol == d->fb_tol)))
     return fail(SIM_E_ARG, "the learned warm start needs tolerance mode, ws_net, fb_iters >= 0 and a fb_tol");
+  if (d->grad_store < SIM_GRAD_AUTO || d->grad_store > SIM_GRAD_TRAJECTORY || d->grad_mem_limit < 0)
+    return fail(SIM_E_ARG, "grad_store must be one of SIM_GRAD_* and grad_mem_limit >= 0");
   for (int e = 0; e < E; ++e) {
     if (d->T_env[e] < 0 || d->T_env[e] > d->T_max) return fail(SIM_E_SHAPE, "T_env outside [0, T_max]");
     if (d->loss_body[e] < d->env_body_off[e] || d->loss_body[e] >= d->env_body_off[e + 1])
@@ -446,6 +466,9 @@ sim_status sim_init(const sim_model_desc* d, sim_handle* out) {
                                n_chunks * h->n_wtiles * 1024LL);
   }
   I.n_params = h->n_params;
+  I.grad_store = M.dump == DUMP_TRAJECTORY ? SIM_GRAD_TRAJECTORY
+                 : M.dump == DUMP_SEGMENT  ? SIM_GRAD_SEGMENT
+                                           : SIM_GRAD_REPLAY;
   I.max_lds_bytes = max_lds;
   I.n_tiles = 0;
   for (auto& b : h->buckets) I.n_tiles += b.n_tiles;
@@ -574,13 +597,31 @@ sim_status rollout_grad(sim_handle h, const float* x0, const float* u, const flo
   DevModel M = h->M;
   M.W = u;
   M.tape = ws + h->seg_floats;
-  s = run_buckets(h, st, [&](size_t i, hipStream_t sx) { return bucket_grad(h, i, M, a, sx); },
+  auto mark = [&](int k) { return !h->tev[k] || hipEventRecord(h->tev[k], st) == hipSuccess; };
+  if (!mark(0)) return check_device("rollout_grad timing event");
+  if (M.dump == DUMP_TRAJECTORY)
+    s = run_buckets(h, st, [&](size_t i, hipStream_t sx) { return bucket_recompute(h, i, M, a, sx); },
+                    "rollout_grad recompute launch");
+  if (s != SIM_OK) return s;
+  if (!mark(1) || !mark(2)) return check_device("rollout_grad timing event");
+  s = run_buckets(h, st, [&](size_t i, hipStream_t sx) { return bucket_reverse(h, i, M, a, sx); },
                   "rollout_grad launch");
-  if (s != SIM_OK || !M.ctrl || !g_u) return s;
+  if (s != SIM_OK) return s;
+  if (!mark(3)) return check_device("rollout_grad timing event");
+  if (!M.ctrl || !g_u) return s;
   // dL/dW: contraction of the per env-step deltas and activations
   if (launch_wgrad(M.tape, M.tape_stride, (int)h->tape_rows, h->chunk, h->d_tiles, h->n_wtiles,
                    M.tape + h->tape_floats, h->d_map, h->n_params, g_u, st) != hipSuccess)
     return check_device("rollout_grad weight gradient");
+  return SIM_OK;
+}
+
+sim_status sim_time_grad(sim_handle h, void* const* ev) {
+  if (!h) return fail(SIM_E_ARG, "sim_time_grad: null handle");
+  for (int k = 0; k < 4; ++k) {
+    if (ev && !ev[k]) return fail(SIM_E_ARG, "sim_time_grad: null event");
+    h->tev[k] = ev ? (hipEvent_t)ev[k] : nullptr;
+  }
   return SIM_OK;
 }
 

@@ -12,6 +12,7 @@ struct TileSet {
   int n_tiles;
   int env_floats;    // LDS floats reserved per env
   int* queue;        // device counter of the persistent tile queue
+  int n_seg;         // trajectory recompute: segments per tile (units = n_tiles * n_seg)
 };
 
 // One 32x32 output tile of the controller's weight-gradient contraction:
@@ -30,6 +31,8 @@ hipError_t launch_step(const DevModel& M, const TileSet& ts, int team, int grid,
                        hipStream_t st);
 hipError_t launch_rollout_grad(const DevModel& M, const TileSet& ts, int team, int grid, size_t lds,
                                const GradArgs& a, hipStream_t st);
+hipError_t launch_recompute(const DevModel& M, const TileSet& ts, int team, int grid, size_t lds,
+                            const GradArgs& a, hipStream_t st);
 hipError_t allow_large_lds(int bytes);
 
 // warm-start network (wsn_kernels.hip)

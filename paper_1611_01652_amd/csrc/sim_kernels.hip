@@ -152,6 +152,26 @@ __global__ __launch_bounds__(64) void k_rollout_grad(DevModel M, TileSet ts, Gra
   }
 }
 
+// Trajectory-mode recompute: the work units are (segment, tile) pairs, all
+// segments of all tiles at once, each team recomputing one segment of one env
+// from its checkpoint with the forward LDS layout.
+template <int TEAM>
+__global__ __launch_bounds__(64) void k_recompute(DevModel M, TileSet ts, GradArgs a) {
+  extern __shared__ float lds[];
+  const TeamGPU tm = make_team<TEAM>();
+  const int team = threadIdx.x / TEAM;
+  constexpr int EPW = 64 / TEAM;
+  const int n_units = ts.n_tiles * ts.n_seg;
+  for (int u = next_tile(ts.queue); u < n_units; u = next_tile(ts.queue)) {
+    const int sg = u / ts.n_tiles, tile = u - sg * ts.n_tiles;
+    const int ie = ts.envs[tile * EPW + team];
+    const bool valid = ie >= 0;
+    Env E = make_env(M, valid ? ie : 0, lds + team * ts.env_floats, M.n_iters, false);
+    env_recompute(tm, M, E, valid, a, sg);
+    __syncthreads();
+  }
+}
+
 // Weight gradient of the controller as a contraction over env-steps:
 //   dW_l[i][k] = sum_n delta_l[n][i] * act_l[n][k],  db_l[i] = sum_n delta_l[n][i]
 // (act_1 = s, act_2 = h1, act_3 = h2; delta_1 = d1, delta_2 = d2, delta_3 = du).
@@ -274,6 +294,10 @@ hipError_t launch_rollout_grad(const DevModel& M, const TileSet& ts, int team, i
                                const GradArgs& a, hipStream_t st) {
   SIM_DISPATCH(team, k_rollout_grad, a)
 }
+hipError_t launch_recompute(const DevModel& M, const TileSet& ts, int team, int grid, size_t lds,
+                            const GradArgs& a, hipStream_t st) {
+  SIM_DISPATCH(team, k_recompute, a)
+}
 
 template <class K>
 static hipError_t allow_lds(K kern, int bytes) {
@@ -302,6 +326,7 @@ hipError_t allow_large_lds(int bytes) {
   SIM_ALLOW_S(k_step, 0)
   SIM_ALLOW_S(k_step, 1)
   SIM_ALLOW(k_rollout_grad)
+  SIM_ALLOW(k_recompute)
 #undef SIM_ALLOW
 #undef SIM_ALLOW_S
   return e;

@@ -102,8 +102,15 @@ struct DevModel {
   int solve_mode, max_iters, ws_kind, fb_iters;
   float tol, fb_tol;
   const uint16_t* wsn; // warm-start network, bfloat16 [4867]
-  int dump;           // reverse sweep: saved step working sets instead of replays
+  int dump;           // reverse sweep buffer: DUMP_REPLAY, DUMP_SEGMENT or DUMP_TRAJECTORY
 };
+// Reverse sweep buffer modes: step-start states of one segment (each step is
+// replayed), saved working sets of one segment, or of the whole trajectory
+// (all segments recomputed in a separate launch).  An env's block starts on a
+// SEG_UNIT-float boundary; in trajectory mode its last SEG_TAIL floats hold
+// the loss body's final position.
+enum { DUMP_REPLAY = 0, DUMP_SEGMENT = 1, DUMP_TRAJECTORY = 2 };
+enum { SEG_UNIT = 64, SEG_TAIL = 4 };
 // tape row: s, h1, h2, du, d2, d1 (pre-activation adjoints)
 SHD int tape_s(const DevModel&) { return 0; }
 SHD int tape_h1(const DevModel& M) { return M.mlp_in; }
@@ -133,8 +140,12 @@ enum { XT1 = 0, XT2 = 3, XMT = 6, XGAP = 7, XSTORE = 8, XCODE = 9, XF = 10, XY =
 // row adjoint slot
 enum { QJL = 0, QJA = 3, QJB = 6, QWA = 9, QWB = 12, QM = 15, QB = 16, QL = 17, RSA = 20 };
 
+// Sweep plan entries (16 bytes, one LDS load): per live colour (start in the
+// active list, count, -, -); per active constraint (slot, body a, body b, code).
+struct alignas(16) i4 { int x, y, z, w; };
+
 struct Lay {
-  int body, jc, gs, topo, ws, rows, act_cnt, act_slot, act_code, live, misc, mlp, vsave;  // forward
+  int body, jc, gs, topo, ws, rows, act_cnt, act_slot, act_code, live, plan, vis, misc, mlp, vsave;  // forward
   int bodyA, rowsA, hist, wsA, jA, mlpA;                                     // adjoint
   int total_fwd, total;
 };
@@ -158,6 +169,8 @@ SHD Lay make_lay(int nb, int nj, int G, int P, int ncol, int ncand, int nslot, i
   L.act_slot = o; o += align4(ncand);
   L.act_code = o; o += align4(ncand);
   L.live = o; o += align4(ncol + 2);
+  L.plan = o; o += 4 * ncol;
+  L.vis = o; o += 4 * ncand;
   L.misc = o; o += MISC_N;
   L.mlp = o; o += align4(mlp_f);
   L.vsave = o; o += align4(vs_f);
@@ -206,11 +219,17 @@ struct Env {
   // [0] colours with an active constraint this step, [1] joint colours (the
   // first colours of the canonical order), [2..] the active colours in order
   SHD int* live() const { return (int*)(L + lay.live); }
+  // sweep plan of the step (built with the live list): plan()[ci] for live
+  // colour ci, vis()[i] parallel to act_slot / act_code
+  SHD i4* plan() const { return (i4*)(L + lay.plan); }
+  SHD i4* vis() const { return (i4*)(L + lay.vis); }
   SHD float* misc() const { return L + lay.misc; }
   SHD float* jA() const { return L + lay.jA; }
   SHD float* mlp() const { return L + lay.mlp; }
   SHD float* mlpA() const { return L + lay.mlpA; }
   SHD float* vsave(int b) const { return L + lay.vsave + 6 * b; }
+  // first float of the env's block of the reverse sweep buffer
+  SHD size_t seg_base() const { return (size_t)seg_off * SEG_UNIT; }
   // warm-start store offset of a candidate
   SHD int store_of(int code) const {
     const int k = cand_kind(code), i = cand_idx(code);
@@ -632,21 +651,23 @@ SHD void f_rows(const Team& tm, const DevModel& M, const Env& E, bool act) {
       if (on) {
         const int li = lo + cnt + pos;   // position in the colour's active list
         E.act_code()[li] = code;
+        int s = -1;
         if (jcol) {
           const int j = cand_idx(code);
-          E.act_slot()[li] = 5 * j;
-          build_joint(M, E, j, 5 * j);
+          s = 5 * j;
+          build_joint(M, E, j, s);
         } else if (ncon + pos < E.ccap) {
-          const int s = 5 * E.nj + 4 * (ncon + pos);
-          E.act_slot()[li] = s;
+          s = 5 * E.nj + 4 * (ncon + pos);
           build_contact(M, E, code, s, g);
         } else {
           // beyond the env's contact capacity: dropped, env flagged
-          E.act_slot()[li] = -1;
           float* w = E.ws() + E.store_of(code);
           w[0] = w[1] = w[2] = w[3] = 0.f;
           (*reinterpret_cast<int*>(E.misc() + MISC_FLAGS)) |= 2;
         }
+        E.act_slot()[li] = s;
+        const RowB rb = cand_bodies(E, code);
+        E.vis()[li] = i4{s, rb.a, rb.b, code};
       }
       cnt += total;
       if (!jcol) ncon += total;
@@ -657,11 +678,64 @@ SHD void f_rows(const Team& tm, const DevModel& M, const Env& E, bool act) {
   if (act && tm.tl == 0) {
     int m = 0;
     for (int c = 0; c < E.ncol; ++c)
-      if (E.act_cnt()[c] > 0) E.live()[2 + m++] = c;
+      if (E.act_cnt()[c] > 0) {
+        E.plan()[m] = i4{E.colstart(c), E.act_cnt()[c], 0, 0};
+        E.live()[2 + m++] = c;
+      }
     E.live()[0] = m;
   }
   tm.sync();
 }
+
+// The colour visits of n_iters sweeps over the live colours, first to last
+// (DIR = 1) or last to first (DIR = -1).  The plan does not change during the
+// sweeps, so the loads of the next visit's entries (this lane's first
+// constraint of the next colour, the plan of the colour after it) are issued
+// before the current visit runs and are not waited for at its start.
+template <int DIR>
+struct SweepCursor {
+  int nl, left;   // live colours; visits left, the current one included
+  int it, ci;     // iteration and live colour of the current visit
+  int cn, c2;     // live colours of the next two visits
+  i4 pc, vc, pn;  // plan and this lane's first entry of the current colour, plan of the next
+  SHD int step(int c) const { return DIR > 0 ? (c + 1 == nl ? 0 : c + 1) : (c == 0 ? nl - 1 : c - 1); }
+  template <class Team>
+  SHD i4 first(const Team& tm, const Env& E, const i4& p, bool ok) const {
+    return (ok && tm.tl < p.y) ? E.vis()[p.x + tm.tl] : i4{-1, 0, 0, 0};
+  }
+  template <class Team>
+  SHD void start(const Team& tm, const Env& E, int n_iters, int n_live_cols) {
+    nl = n_live_cols;
+    left = nl * n_iters;
+    it = DIR > 0 ? 0 : n_iters - 1;
+    ci = DIR > 0 ? 0 : nl - 1;
+    cn = step(ci);
+    c2 = step(cn);
+    pc = left > 0 ? E.plan()[ci] : i4{0, 0, 0, 0};
+    vc = first(tm, E, pc, left > 0);
+    pn = left > 1 ? E.plan()[cn] : i4{0, 0, 0, 0};
+  }
+  // loads for the next visit (call before the current one runs)
+  template <class Team>
+  SHD void prefetch(const Team& tm, const Env& E, i4& vn, i4& p2) const {
+    vn = first(tm, E, pn, left > 1);
+    p2 = left > 2 ? E.plan()[c2] : i4{0, 0, 0, 0};
+  }
+  // this lane's k-th constraint of the current colour, at tl + k ts (k >= 1:
+  // not prefetched)
+  template <class Team>
+  SHD i4 entry(const Team& tm, const Env& E, int k) const { return k == 0 ? vc : E.vis()[pc.x + tm.tl + k * tm.ts]; }
+  SHD void advance(const i4& vn, const i4& p2) {
+    if (cn == (DIR > 0 ? 0 : nl - 1)) it += DIR;
+    --left;
+    ci = cn;
+    cn = c2;
+    c2 = step(c2);
+    pc = pn;
+    vc = vn;
+    pn = p2;
+  }
+};
 
 // F5: warm start, v += W lambda0 for every row, colour by colour.
 template <class Team>
@@ -835,28 +909,27 @@ SHD void pgs_contact(const DevModel& M, const Env& E, int s, int a, int b, float
   vr_store(V, E, a, b);
 }
 
-// F6: projected Gauss-Seidel sweeps.  With rec, the pre-projection impulse of
-// every row update is recorded per iteration.
+// F6: projected Gauss-Seidel sweeps.  With hist, the pre-projection impulse of
+// every row update is recorded there, n_iters rows of nslot floats (in LDS or
+// global memory).
 template <class Team>
-SHD void f_pgs(const Team& tm, const DevModel& M, const Env& E, bool act, bool rec) {
+SHD void f_pgs(const Team& tm, const DevModel& M, const Env& E, bool act, float* hist) {
   const float mu = E.misc()[MISC_MU];
-  const int nl = n_live(E, act);
-  for (int it = 0; it < M.n_iters; ++it) {
-    float* H = rec ? E.hist(it) : nullptr;
-    for (int ci = 0; tm.any(ci < nl); ++ci) {
-      const int c = ci < nl ? live_col(E, ci) : 0;
-      const int n = ci < nl ? E.act_cnt()[c] : 0;
-      const int lo = ci < nl ? E.colstart(c) : 0;
-      for (int k = tm.tl; k < n; k += tm.ts) {
-        const int s = E.act_slot()[lo + k];
-        if (s < 0) continue;
-        const int code = E.act_code()[lo + k];
-        const RowB rb = cand_bodies(E, code);
-        if (cand_kind(code) == K_JOINT) pgs_joint(M, E, s, rb.a, rb.b, H);
-        else pgs_contact(M, E, s, rb.a, rb.b, mu, H);
-      }
-      tm.sync();
+  SweepCursor<1> sw;
+  sw.start(tm, E, M.n_iters, n_live(E, act));
+  while (tm.any(sw.left > 0)) {
+    i4 vn, p2;
+    sw.prefetch(tm, E, vn, p2);
+    const int n = sw.left > 0 ? sw.pc.y : 0;
+    float* H = hist ? hist + (size_t)sw.it * E.nslot : nullptr;
+    for (int k = 0; tm.tl + k * tm.ts < n; ++k) {
+      const i4 v = sw.entry(tm, E, k);
+      if (v.x < 0) continue;
+      if (cand_kind(v.w) == K_JOINT) pgs_joint(M, E, v.x, v.y, v.z, H);
+      else pgs_contact(M, E, v.x, v.y, v.z, mu, H);
     }
+    tm.sync();
+    sw.advance(vn, p2);
   }
 }
 
@@ -1019,7 +1092,7 @@ SHD void env_step(const Team& tm, const DevModel& M, const Env& E, const float* 
   tm.sync();
   f_rows(tm, M, E, act);
   f_warm(tm, E, act);
-  f_pgs(tm, M, E, act, false);
+  f_pgs(tm, M, E, act, nullptr);
   f_integrate(tm, M, E, act);
   f_store(tm, E, act);
 }
@@ -1733,25 +1806,23 @@ SHD void rev_contact(const DevModel& M, const Env& E, int s, int a, int b, float
 template <class Team>
 SHD void a_pgs(const Team& tm, const DevModel& M, const Env& E, bool act) {
   const float mu = E.misc()[MISC_MU];
-  const int nl = n_live(E, act);
   float gmu = 0.f;
-  for (int it = M.n_iters - 1; it >= 0; --it) {
-    const float* H = E.hist(it);
-    const float* Hp = it > 0 ? E.hist(it - 1) : nullptr;
-    for (int ci = nl - 1; tm.any(ci >= 0); --ci) {
-      const int c = ci >= 0 ? live_col(E, ci) : 0;
-      const int n = ci >= 0 ? E.act_cnt()[c] : 0;
-      const int lo = ci >= 0 ? E.colstart(c) : 0;
-      for (int k = tm.tl; k < n; k += tm.ts) {
-        const int s = E.act_slot()[lo + k];
-        if (s < 0) continue;
-        const int code = E.act_code()[lo + k];
-        const RowB rb = cand_bodies(E, code);
-        if (cand_kind(code) == K_JOINT) rev_joint(M, E, s, rb.a, rb.b, H, Hp);
-        else rev_contact(M, E, s, rb.a, rb.b, mu, H, Hp, gmu);
-      }
-      tm.sync();
+  SweepCursor<-1> sw;
+  sw.start(tm, E, M.n_iters, n_live(E, act));
+  while (tm.any(sw.left > 0)) {
+    i4 vn, p2;
+    sw.prefetch(tm, E, vn, p2);
+    const int n = sw.left > 0 ? sw.pc.y : 0;
+    const float* H = E.hist(sw.it);
+    const float* Hp = sw.it > 0 ? E.hist(sw.it - 1) : nullptr;
+    for (int k = 0; tm.tl + k * tm.ts < n; ++k) {
+      const i4 v = sw.entry(tm, E, k);
+      if (v.x < 0) continue;
+      if (cand_kind(v.w) == K_JOINT) rev_joint(M, E, v.x, v.y, v.z, H, Hp);
+      else rev_contact(M, E, v.x, v.y, v.z, mu, H, Hp, gmu);
     }
+    tm.sync();
+    sw.advance(vn, p2);
   }
   // friction coefficient adjoint (one lane per team holds it after a reduction)
   float tot = tm.team_sum(gmu);

@@ -19,6 +19,12 @@ SIM_OK = 0
 FLAG_NONFINITE = 1
 FLAG_CONTACT_OVERFLOW = 2
 
+# layout of the descriptor and info structs below (SIM_ABI_VERSION)
+ABI_VERSION = 2
+
+# reverse sweep memory modes (sim_model_desc.grad_store)
+GRAD_STORE = {"auto": 0, "replay": 1, "segment": 2, "trajectory": 3}
+
 _I32P = C.POINTER(C.c_int32)
 _F32P = C.POINTER(C.c_float)
 
@@ -40,7 +46,7 @@ class SimDesc(C.Structure):
         ("ctrl_kind", C.c_int32), ("mlp_sizes", C.c_int32 * 4), ("clock_hz", C.c_float),
         ("solve_mode", C.c_int32), ("tol", C.c_float), ("max_iters", C.c_int32),
         ("ws_kind", C.c_int32), ("ws_net", _F32P), ("fb_iters", C.c_int32), ("fb_tol", C.c_float),
-        ("grad_replay", C.c_int32),
+        ("grad_store", C.c_int32), ("grad_mem_limit", C.c_int64),
     ]
 
 
@@ -50,6 +56,7 @@ class SimInfo(C.Structure):
         ("lam_size", C.c_int32), ("n_ckpt", C.c_int32),
         ("ckpt_floats", C.c_int64), ("workspace_bytes", C.c_int64),
         ("max_lds_bytes", C.c_int32), ("n_tiles", C.c_int32), ("n_params", C.c_int32),
+        ("grad_store", C.c_int32),
     ]
 
 
@@ -103,7 +110,8 @@ def make_desc(w):
         d.mlp_sizes = (C.c_int32 * 4)(*[int(v) for v in mlp["sizes"]])
         d.clock_hz = float(mlp.get("clock_hz", 1.5))
     extra = getattr(w, "extra", None) or {}
-    d.grad_replay = int(bool(extra.get("grad_replay", False)))
+    d.grad_store = GRAD_STORE[extra.get("grad_store", "auto")]
+    d.grad_mem_limit = int(extra.get("grad_mem_limit", 0))
     solve = extra.get("solve")
     if solve is not None:
         d.solve_mode = int(solve.get("mode", 1))
@@ -158,10 +166,14 @@ def library():
     lib.wsn_adam.argtypes = [vp, vp, vp, vp, vp, C.c_int32, C.c_float, C.c_float, C.c_float, C.c_float, vp]
     lib.sim_adam.argtypes = [vp, vp, vp, vp, C.c_int64, C.c_int32, C.c_float, C.c_float, C.c_float, C.c_float,
                              C.c_float, vp, vp, vp]
-    for fn in ("sim_init", "sim_destroy", "sim_get_info", "sim_lambda_offsets", "sim_step", "rollout",
+    lib.sim_time_grad.argtypes = [vp, C.POINTER(vp)]
+    for fn in ("sim_time_grad", "sim_init", "sim_destroy", "sim_get_info", "sim_lambda_offsets", "sim_step", "rollout",
                "rollout_grad", "sim_step_graph", "sim_graph_launch", "sim_graph_destroy", "sim_set_teams",
                "wsn_to_bf16", "wsn_forward", "wsn_loss_grad", "wsn_adam", "rollout_solve", "sim_adam"):
         getattr(lib, fn).restype = C.c_int
+    if lib.sim_abi_version() != ABI_VERSION:
+        raise RuntimeError(f"{LIB_PATH} has ABI version {lib.sim_abi_version()}, this binding expects "
+                           f"{ABI_VERSION}: rebuild it (__graft_entry__.build())")
     _lib = lib
     return lib
 
@@ -170,7 +182,7 @@ EXPORTED = ["sim_abi_version", "sim_last_error", "sim_init", "sim_destroy", "sim
             "sim_lambda_offsets", "sim_describe_order", "sim_step", "rollout", "rollout_grad",
             "sim_step_graph", "sim_graph_launch", "sim_graph_destroy", "sim_tune", "sim_get_teams",
             "sim_set_teams", "wsn_to_bf16", "wsn_forward", "wsn_workspace_bytes", "wsn_loss_grad", "wsn_adam",
-            "rollout_solve", "sim_adam"]
+            "rollout_solve", "sim_adam", "sim_time_grad"]
 
 
 def describe_order(w, env):
@@ -306,6 +318,21 @@ class Simulator:
         g["flags"] = g["flags"][:E]
         g["g_damping"] = g["g_damping"][:J]
         return g
+
+    def time_grad(self, events):
+        """Record rollout_grad's phases on 4 torch.cuda.Events (recompute start
+        and end, reverse start and end) in every later call; None stops it.
+        The events must have been recorded once (torch creates them lazily)
+        and must stay alive while set."""
+        if events is None:
+            st = self.lib.sim_time_grad(self.h, None)
+        else:
+            raw = [int(e.cuda_event) for e in events]
+            if len(raw) != 4 or not all(raw):
+                raise ValueError("time_grad needs 4 created events (record each once first)")
+            arr = (C.c_void_p * 4)(*raw)
+            st = self.lib.sim_time_grad(self.h, arr)
+        _check(self.lib, st, "sim_time_grad")
 
     def step(self, x, u, lam, t_index=0):
         t = self.torch

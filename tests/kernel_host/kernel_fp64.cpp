@@ -110,6 +110,7 @@ int kh_sizes(const sim_model_desc* d, long long* out) {
   if (!make(d, h)) return -1;
   const int n_ckpt = d->T_max > 0 ? (d->T_max - 1) / d->ckpt_every + 1 : 1;
   out[0] = h.M.lam_tot; out[1] = h.P.seg_total; out[2] = (long long)n_ckpt * (18LL * h.M.B + h.M.lam_tot);
+  out[3] = h.P.dump;
   return 0;
 }
 int kh_rollout_grad(const sim_model_desc* d, const double* x0, const double* u, const double* dloss, double* loss,
@@ -131,6 +132,17 @@ int kh_rollout_grad(const sim_model_desc* d, const double* x0, const double* u, 
     std::vector<double> lds(h.P.adj_of[ie] + 16);
     Env E = make_env(h.M, ie, lds.data(), h.M.n_iters, false);
     env_rollout(tm, h.M, E, true, ra);
+    if (h.M.dump == DUMP_TRAJECTORY) {
+      // every segment recomputed on its own from its checkpoint (last first:
+      // the order must not matter)
+      const int K = h.M.ckpt_every, nseg = (d->T_env[ie] + K - 1) / K;
+      for (int sg = nseg - 1; sg >= 0; --sg) {
+        std::fill(lds.begin(), lds.end(), std::nan(""));
+        Env ER = make_env(h.M, ie, lds.data(), h.M.n_iters, false);
+        env_recompute(tm, h.M, ER, true, ga, sg);
+      }
+      std::fill(lds.begin(), lds.end(), std::nan(""));
+    }
     Env EA = make_env(h.M, ie, lds.data(), h.M.n_iters, true);
     env_rollout_grad(tm, h.M, EA, true, ga);
   }

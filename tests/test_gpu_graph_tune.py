@@ -139,19 +139,24 @@ def test_tune_keeps_every_result_bit():
     s.close()
 
 
-def test_saved_working_sets_and_replays_give_the_same_gradient_bits():
-    # the reverse sweep either replays each step or reloads the working set the
-    # recompute saved; the arithmetic is the same, so every bit must agree
+def test_reverse_sweep_memory_modes_give_the_same_gradient_bits():
+    # the reverse sweep replays each step, or reloads the working set saved by
+    # the recompute of its segment, or by the recompute of all segments at
+    # once in a separate launch; the arithmetic is the same, so every bit must
+    # agree (chains: several buckets and a ragged last segment; quadruped:
+    # controller, episode lengths that differ per env)
     import torch
     from paper_1611_01652_amd.sim import Simulator
-    cases = (W.uneven_chains(n_envs=64, T=60, seed_salt=23),
-             W.quadruped(n_envs=16, T_min=30, T_max=45, mlp_w=W.mlp_init(zero_output=False, out_scale=0.1)))
+    quad = W.quadruped(n_envs=16, T_min=30, T_max=45, mlp_w=W.mlp_init(zero_output=False, out_scale=0.1))
+    quad.ckpt_every = 8
+    cases = (W.uneven_chains(n_envs=64, T=60, seed_salt=23), quad)
     for w in cases:
         outs = []
-        for replay in (False, True):
+        for mode in ("trajectory", "segment", "replay"):
             w.extra = dict(w.extra or {})
-            w.extra["grad_replay"] = replay
+            w.extra["grad_store"] = mode
             s = Simulator(w)
+            assert s.info.grad_store == {"replay": 1, "segment": 2, "trajectory": 3}[mode]
             x0, u = to_dev(w)
             if "mlp" in w.extra:
                 u = torch.tensor(w.extra["mlp"]["w"], dtype=torch.float32, device="cuda")
@@ -159,7 +164,8 @@ def test_saved_working_sets_and_replays_give_the_same_gradient_bits():
             g = s.rollout_grad(x0, u, r["ckpt"], torch.ones(w.n_envs, device="cuda"))
             torch.cuda.synchronize()
             outs.append({k: v.clone() for k, v in g.items()})
-            _say("case reverse sweep", w.name, "replay =", replay, "workspace MB", s.info.workspace_bytes / 1e6)
+            _say("case reverse sweep", w.name, "mode", mode, "workspace MB", s.info.workspace_bytes / 1e6)
             s.close()
-        for k in outs[0]:
-            assert torch.equal(outs[0][k], outs[1][k]), k
+        for o in outs[1:]:
+            for k in outs[0]:
+                assert torch.equal(outs[0][k], o[k]), k

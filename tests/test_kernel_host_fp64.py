@@ -17,7 +17,7 @@ import pytest
 
 from oracle import Oracle
 from paper_1611_01652_amd import workloads as W
-from paper_1611_01652_amd.sim import SimDesc, _F32P
+from paper_1611_01652_amd.sim import GRAD_STORE, SimDesc, _F32P
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "kernel_host", "kernel_fp64.cpp")
@@ -33,8 +33,9 @@ def _load():
         deps = [SRC] + [os.path.join(ROOT, "paper_1611_01652_amd", "csrc", f)
                         for f in ("step_core.h", "drivers.h", "model_pack.cpp", "model_pack.h")]
         if not os.path.exists(LIB) or os.path.getmtime(LIB) < max(os.path.getmtime(p) for p in deps):
-            subprocess.check_call(["g++", "-O1", "-std=c++17", "-fPIC", "-shared", "-w", "-o", LIB + ".tmp", SRC])
-            os.replace(LIB + ".tmp", LIB)
+            tmp = f"{LIB}.{os.getpid()}.tmp"   # parallel test workers each build their own, then swap it in
+            subprocess.check_call(["g++", "-O1", "-std=c++17", "-fPIC", "-shared", "-w", "-o", tmp, SRC])
+            os.replace(tmp, LIB)
         _lib = C.CDLL(LIB)
     return _lib
 
@@ -76,7 +77,8 @@ def _desc64(w):
     d.beta, d.gamma, d.spec_margin, d.warm = f(w.beta), f(w.gamma), f(w.spec_margin), f(w.warm)
     d.n_iters, d.ground, d.loss_kind, d.loss_mask = w.n_iters, w.ground, w.loss_kind, w.loss_mask
     d.ckpt_every, d.min_team = w.ckpt_every, 0
-    d.grad_replay = int(bool((getattr(w, "extra", None) or {}).get("grad_replay", False)))
+    d.grad_store = GRAD_STORE[(getattr(w, "extra", None) or {}).get("grad_store", "auto")]
+    d.grad_mem_limit = int((getattr(w, "extra", None) or {}).get("grad_mem_limit", 0))
     mlp = w.extra.get("mlp") if getattr(w, "extra", None) else None
     if mlp is not None:
         d.ctrl_kind = 1
@@ -129,15 +131,47 @@ def _rel(a, b):
     return np.linalg.norm(a - b) / n if n > 1e-12 else np.linalg.norm(a - b)
 
 
-def _replay(w):
+def _sizes(w):
+    lib = _load()
+    d, keep = _desc64(w)
+    out = (C.c_longlong * 4)()
+    assert lib.kh_sizes(C.byref(d), out) == 0
+    return dict(lam=out[0], seg_floats=out[1], ckpt_floats=out[2], mode=("replay", "segment", "trajectory")[out[3]])
+
+
+def test_reverse_sweep_memory_modes_and_their_sizes():
+    # buffer sizes of the three modes, per env aligned to 64 floats: K_ck
+    # step-start states, K_ck working sets, T working sets and the final position
+    w = W.planar_arms(n_envs=3, T=130)
+    sz = {m: _sizes(_store(w, m)) for m in ("replay", "segment", "trajectory")}
+    assert [sz[m]["mode"] for m in sz] == list(sz)
+    K, nb, lam = w.ckpt_every, 3, 15
+    up = lambda n: (n + 63) // 64 * 64   # noqa: E731
+    assert sz["replay"]["seg_floats"] == 3 * up(K * (18 * nb + lam))
+    ws = sz["segment"]["seg_floats"] // 3 // K
+    assert sz["segment"]["seg_floats"] == 3 * up(K * ws)
+    assert sz["trajectory"]["seg_floats"] == 3 * up(w.T_max * ws + 4)
+    # the automatic choice: trajectory while it fits the limit, then segment, then replay
+    w.extra["grad_store"] = "auto"
+    assert _sizes(w)["mode"] == "trajectory"
+    for lim, mode in ((4 * sz["trajectory"]["seg_floats"] - 4, "segment"),
+                      (4 * sz["segment"]["seg_floats"] - 4, "replay")):
+        w.extra["grad_mem_limit"] = lim
+        assert _sizes(w)["mode"] == mode
+
+
+def _store(w, mode):
     w.extra = dict(w.extra or {})
-    w.extra["grad_replay"] = True
+    w.extra["grad_store"] = mode
     return w
 
 
+# without a grad_store the automatic choice at these sizes is "trajectory"
 @pytest.mark.parametrize("maker,tol", [
-    (lambda: _replay(W.planar_arms(n_envs=4, T=300)), 1e-9),
-    (lambda: _replay(W.uneven_chains(n_envs=6, T=150, seed_salt=2)), 1e-7),
+    (lambda: _store(W.planar_arms(n_envs=4, T=300), "replay"), 1e-9),
+    (lambda: _store(W.uneven_chains(n_envs=6, T=150, seed_salt=2), "replay"), 1e-7),
+    (lambda: _store(W.planar_arms(n_envs=3, T=130), "segment"), 1e-9),
+    (lambda: _store(W.uneven_chains(n_envs=5, T=120, seed_salt=4), "segment"), 1e-7),
     (lambda: W.ball_throw(), 1e-10),
     (lambda: W.planar_arms(n_envs=6, T=1000), 1e-9),
     (lambda: W.uneven_chains(n_envs=10, T=300, seed_salt=2), 1e-7),

@@ -31,7 +31,8 @@ def test_library_exports_every_declared_function():
     assert set(S.EXPORTED) == set(declared), (declared, S.EXPORTED)
     for name in declared:
         assert hasattr(lib, name), name
-    assert lib.sim_abi_version() == 1
+    hdr = open(os.path.join(ROOT, "include", "sim.h")).read()
+    assert lib.sim_abi_version() == S.ABI_VERSION == int(re.search(r"#define SIM_ABI_VERSION (\d+)", hdr).group(1))
 
 
 def _call_init(w, mutate=None):
