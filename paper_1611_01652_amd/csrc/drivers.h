@@ -261,7 +261,7 @@ template <class Team>
 SHD_FLAT void env_rollout_grad(const Team& tm, const DevModel& M, const Env& E, bool valid, const GradArgs& a) {
   if (valid) {
     load_env_static(tm, M, E);
-    for (int i = tm.tl; i < E.nb * BSA; i += tm.ts) E.L[E.lay.bodyA + i] = 0.f;
+    for (int i = tm.tl; i < (E.nb + 1) * BSA; i += tm.ts) E.L[E.lay.bodyA + i] = 0.f;
     for (int i = tm.tl; i < E.lam_size; i += tm.ts) E.wsA()[i] = 0.f;
     for (int i = tm.tl; i < 2 * E.nj; i += tm.ts) E.jA()[i] = 0.f;
     if (tm.tl == 0) E.misc()[MISC_GMU] = E.misc()[MISC_GMUC] = 0.f;

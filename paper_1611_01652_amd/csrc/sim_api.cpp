@@ -309,8 +309,19 @@ sim_status sim_init(const sim_model_desc* d, sim_handle* out) {
 
   h->lam_off = P.lam_off;
   std::vector<int>& team_of = P.team_of;
-  const std::vector<int>& fwd_of = P.fwd_of;
-  const std::vector<int>& adj_of = P.adj_of;
+  // Per-env LDS strides: an odd number of float4.  The envs of a wave then
+  // start on distinct LDS bank groups, so the same field of up to 16 envs is
+  // read in one pass (an even stride, e.g. a multiple of 64 floats, makes
+  // them collide on the same banks).
+  auto lds_stride = [](int f) {
+    f = (f + 3) & ~3;
+    return (f / 4) % 2 == 0 ? f + 4 : f;
+  };
+  std::vector<int> fwd_of(E), adj_of(E);
+  for (int e = 0; e < E; ++e) {
+    fwd_of[e] = lds_stride(P.fwd_of[e]);
+    adj_of[e] = lds_stride(P.adj_of[e]);
+  }
   const long long seg_total = P.seg_total;
   int max_lds = 0;
   for (int e = 0; e < E; ++e) {
@@ -320,7 +331,7 @@ sim_status sim_init(const sim_model_desc* d, sim_handle* out) {
     int team = std::max(team_of[e], d->min_team);
     if (team > 64) team = 64;
     auto need = [&](int t) {
-      return std::max(adj_bytes(t, adj_of[e]), fwd_bytes(M, t, P.fwd_of[e], P.ccap_of[e]));
+      return std::max(adj_bytes(t, adj_of[e]), fwd_bytes(M, t, fwd_of[e], P.ccap_of[e]));
     };
     while (team < 64 && need(team) > h->max_lds) team *= 2;
     if (need(team) > h->max_lds) {

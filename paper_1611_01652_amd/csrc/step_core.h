@@ -141,7 +141,8 @@ enum { XT1 = 0, XT2 = 3, XMT = 6, XGAP = 7, XSTORE = 8, XCODE = 9, XF = 10, XY =
 enum { QJL = 0, QJA = 3, QJB = 6, QWA = 9, QWB = 12, QM = 15, QB = 16, QL = 17, RSA = 20 };
 
 // Sweep plan entries (16 bytes, one LDS load): per live colour (start in the
-// active list, count, -, -); per active constraint (slot, body a, body b, code).
+// active list, count, -, -); per active constraint (slot, body a, body b,
+// code), body a being the world slot nb where the constraint has no body a.
 struct alignas(16) i4 { int x, y, z, w; };
 
 struct Lay {
@@ -159,7 +160,7 @@ SHD Lay make_lay(int nb, int nj, int G, int P, int ncol, int ncand, int nslot, i
                  int mlp_f = 0, int mlp_a = 0, int vs_f = 0) {
   Lay L;
   int o = 0;
-  L.body = o; o += align4(nb * BS);
+  L.body = o; o += align4((nb + 1) * BS);   // bodies and the world slot (index nb)
   L.jc = o; o += align4(nj * JS);
   L.gs = o; o += align4(G * 4);
   L.topo = o; o += align4(2 * nj + G + P + ncol + 1 + ncand);
@@ -176,7 +177,7 @@ SHD Lay make_lay(int nb, int nj, int G, int P, int ncol, int ncand, int nslot, i
   L.vsave = o; o += align4(vs_f);
   L.total_fwd = o;
   if (adj) {
-    L.bodyA = o; o += align4(nb * BSA);
+    L.bodyA = o; o += align4((nb + 1) * BSA);
     L.rowsA = o; o += align4(nslot * RSA);
     L.hist = o; o += align4(n_iters * nslot);
     L.wsA = o; o += align4(lam);
@@ -294,6 +295,9 @@ SHD void load_env_static(const Team& tm, const DevModel& M, const Env& E) {
     for (int k = 0; k < 3; ++k) B[BPO + k] = E.gcst[4 * E.nb + 3 * b + k];
     B[BPR] = E.gcst[7 * E.nb + b];
   }
+  // the world slot: a body at rest with zero inverse mass and inertia, the
+  // second body of world-attached joints and ground contacts in the sweeps
+  for (int i = tm.tl; i < BS; i += tm.ts) E.body(E.nb)[i] = 0.f;
   for (int i = tm.tl; i < JS * E.nj; i += tm.ts) E.L[E.lay.jc + i] = E.gcst[cst_joint(E) + i];
   for (int i = tm.tl; i < 4 * E.G; i += tm.ts) E.L[E.lay.gs + i] = E.gcst[cst_ground(E) + i];
   if (tm.tl == 0) {
@@ -375,6 +379,9 @@ SHD float row_finish(float* r, const float* Ba, const float* Bb, bool has_a) {
     k += dot(ja, wa);
     im += Ba[BIM];
   } else {
+    // no body a: both of its parts are zero (the world slot's velocity is
+    // zero, so these rows act on body b alone)
+    st3(r + RJA, mk3(0.f, 0.f, 0.f));
     st3(r + RWA, mk3(0.f, 0.f, 0.f));
   }
   return k + im * dot(jl, jl);
@@ -667,7 +674,7 @@ SHD void f_rows(const Team& tm, const DevModel& M, const Env& E, bool act) {
         }
         E.act_slot()[li] = s;
         const RowB rb = cand_bodies(E, code);
-        E.vis()[li] = i4{s, rb.a, rb.b, code};
+        E.vis()[li] = i4{s, rb.a >= 0 ? rb.a : E.nb, rb.b, code};
       }
       cnt += total;
       if (!jcol) ncon += total;
@@ -793,6 +800,22 @@ SHD void vr_store(const VR& V, const Env& E, int a, int b) {
     st4(Ba, p0); Ba[4] = V.wa[1]; Ba[5] = V.wa[2];
   }
 }
+// Both bodies of a sweep visit (body a may be the world slot).
+SHD void vr_load_ab(VR& V, const Env& E, int a, int b) {
+  const float* Bb = E.body(b) + BV;
+  const float* Ba = E.body(a) + BV;
+  const f4 q0 = ld4(Bb), p0 = ld4(Ba);
+  V.vb[0] = q0.x; V.vb[1] = q0.y; V.vb[2] = q0.z; V.wb[0] = q0.w; V.wb[1] = Bb[4]; V.wb[2] = Bb[5];
+  V.va[0] = p0.x; V.va[1] = p0.y; V.va[2] = p0.z; V.wa[0] = p0.w; V.wa[1] = Ba[4]; V.wa[2] = Ba[5];
+}
+SHD void vr_store_ab(const VR& V, const Env& E, int a, int b) {
+  float* Bb = E.body(b) + BV;
+  float* Ba = E.body(a) + BV;
+  f4 q0; q0.x = V.vb[0]; q0.y = V.vb[1]; q0.z = V.vb[2]; q0.w = V.wb[0];
+  f4 p0; p0.x = V.va[0]; p0.y = V.va[1]; p0.z = V.va[2]; p0.w = V.wa[0];
+  st4(Bb, q0); Bb[4] = V.wb[1]; Bb[5] = V.wb[2];
+  st4(Ba, p0); Ba[4] = V.wa[1]; Ba[5] = V.wa[2];
+}
 // One row slot in registers: Jl, Ja, Jb, Wa, Wb, m, bias, lam (lam0 not needed).
 struct RR { float jl[3], ja[3], jb[3], wa[3], wb[3], m, bias, lam; };
 SHD void rr_load(RR& R, const float* p) {
@@ -857,32 +880,33 @@ SHD void pgs_hinge_row(const DevModel& M, RR& R, VR& V, bool ha, float ima, floa
 
 // One visit of a hinge (5 unbounded rows) with all data in registers.
 // rmax (tolerance mode): running maximum of |delta lambda| / m over the rows.
+// a: body index or the world slot.
 SHD void pgs_joint(const DevModel& M, const Env& E, int s, int a, int b, float* H, float* rmax = nullptr) {
-  const bool ha = a >= 0;
+  constexpr bool ha = true;
   VR V;
-  vr_load(V, E, a, b);
+  vr_load_ab(V, E, a, b);
   RR R[5];
   for (int q = 0; q < 5; ++q) rr_load(R[q], E.row(s + q));
-  const float ima = ha ? E.body(a)[BIM] : 0.f, imb = E.body(b)[BIM];
+  const float ima = E.body(a)[BIM], imb = E.body(b)[BIM];
   pgs_hinge_row<0>(M, R[0], V, ha, ima, imb, H ? H + s : nullptr, rmax);
   pgs_hinge_row<1>(M, R[1], V, ha, ima, imb, H ? H + s + 1 : nullptr, rmax);
   pgs_hinge_row<2>(M, R[2], V, ha, ima, imb, H ? H + s + 2 : nullptr, rmax);
   pgs_hinge_row<3>(M, R[3], V, ha, ima, imb, H ? H + s + 3 : nullptr, rmax);
   pgs_hinge_row<3>(M, R[4], V, ha, ima, imb, H ? H + s + 4 : nullptr, rmax);
   for (int q = 0; q < 5; ++q) E.row(s + q)[RL] = R[q].lam;
-  vr_store(V, E, a, b);
+  vr_store_ab(V, E, a, b);
 }
 
 // One visit of a contact: normal row clamped at 0, then the friction disk.
 SHD void pgs_contact(const DevModel& M, const Env& E, int s, int a, int b, float mu, float* H,
                      float* rmax = nullptr) {
-  const bool ha = a >= 0;
+  constexpr bool ha = true;
   VR V;
-  vr_load(V, E, a, b);
+  vr_load_ab(V, E, a, b);
   RR R[3];
   for (int q = 0; q < 3; ++q) rr_load(R[q], E.row(s + q));
   const float mt = E.row(s + 3)[XMT];
-  const float ima = ha ? E.body(a)[BIM] : 0.f, imb = E.body(b)[BIM];
+  const float ima = E.body(a)[BIM], imb = E.body(b)[BIM];
   {
     const float sv_ = rr_jv(R[0], V, ha) + R[0].bias + M.gamma * R[0].lam;
     const float lt = R[0].lam - R[0].m * sv_;
@@ -906,7 +930,7 @@ SHD void pgs_contact(const DevModel& M, const Env& E, int s, int a, int b, float
   E.row(s)[RL] = R[0].lam;
   E.row(s + 1)[RL] = n1;
   E.row(s + 2)[RL] = n2;
-  vr_store(V, E, a, b);
+  vr_store_ab(V, E, a, b);
 }
 
 // F6: projected Gauss-Seidel sweeps.  With hist, the pre-projection impulse of
@@ -1272,8 +1296,9 @@ SHD void f_pgs_tol(const Team& tm, const DevModel& M, const Env& E, bool live, i
         if (s < 0) continue;
         const int code = E.act_code()[lo + k];
         const RowB rb = cand_bodies(E, code);
-        if (cand_kind(code) == K_JOINT) pgs_joint(M, E, s, rb.a, rb.b, nullptr, &r);
-        else pgs_contact(M, E, s, rb.a, rb.b, mu, nullptr, &rc);
+        const int a = rb.a >= 0 ? rb.a : E.nb;
+        if (cand_kind(code) == K_JOINT) pgs_joint(M, E, s, a, rb.b, nullptr, &r);
+        else pgs_contact(M, E, s, a, rb.b, mu, nullptr, &rc);
       }
       tm.sync();
     }
@@ -1445,6 +1470,10 @@ template <class Team>
 SHD void a_clear_step(const Team& tm, const Env& E, bool act) {
   const int ns = act ? E.nslot * RSA : 0;
   for (int i = tm.tl; i < ns; i += tm.ts) E.L[E.lay.rowsA + i] = 0.f;
+  // the world slot's adjoint is a sink of the sweeps: cleared every step so
+  // that it stays finite (it only ever meets zero inverse masses)
+  if (act)
+    for (int i = tm.tl; i < BSA; i += tm.ts) E.bodyA(E.nb)[i] = 0.f;
   const int nb = act ? E.nb : 0;
   for (int b = tm.tl; b < nb; b += tm.ts) {
     float* A = E.bodyA(b);
@@ -1580,6 +1609,21 @@ SHD void vra_load(VR& A, const Env& E, int a, int b) {
     for (int k = 0; k < 3; ++k) { A.va[k] = 0.f; A.wa[k] = 0.f; }
   }
 }
+SHD void vra_load_ab(VR& A, const Env& E, int a, int b) {
+  const float* Bb = E.bodyA(b) + AV;
+  const float* Ba = E.bodyA(a) + AV;
+  const f4 q0 = ld4(Bb), p0 = ld4(Ba);
+  A.vb[0] = q0.x; A.vb[1] = q0.y; A.vb[2] = q0.z; A.wb[0] = q0.w; A.wb[1] = Bb[4]; A.wb[2] = Bb[5];
+  A.va[0] = p0.x; A.va[1] = p0.y; A.va[2] = p0.z; A.wa[0] = p0.w; A.wa[1] = Ba[4]; A.wa[2] = Ba[5];
+}
+SHD void vra_store_ab(const VR& A, const Env& E, int a, int b) {
+  float* Bb = E.bodyA(b) + AV;
+  float* Ba = E.bodyA(a) + AV;
+  f4 q0; q0.x = A.vb[0]; q0.y = A.vb[1]; q0.z = A.vb[2]; q0.w = A.wb[0];
+  f4 p0; p0.x = A.va[0]; p0.y = A.va[1]; p0.z = A.va[2]; p0.w = A.wa[0];
+  st4(Bb, q0); Bb[4] = A.wb[1]; Bb[5] = A.wb[2];
+  st4(Ba, p0); Ba[4] = A.wa[1]; Ba[5] = A.wa[2];
+}
 SHD void vra_store(const VR& A, const Env& E, int a, int b) {
   float* Bb = E.bodyA(b) + AV;
   f4 q0; q0.x = A.vb[0]; q0.y = A.vb[1]; q0.z = A.vb[2]; q0.w = A.wb[0];
@@ -1698,12 +1742,13 @@ SHD void rev_hinge_row(const RR& R, QR& Q, VR& V, VR& A, bool ha, float ima, flo
 
 // Reverse of one hinge visit (rows 4..0).  Row data and row adjoint
 // accumulators are streamed: row q-1 is loaded while row q is reversed.
+// a: body index or the world slot (whose adjoint slot is a sink).
 SHD void rev_joint(const DevModel& M, const Env& E, int s, int a, int b, const float* H, const float* Hp) {
-  const bool ha = a >= 0;
+  constexpr bool ha = true;
   VR V, A;
-  vr_load(V, E, a, b);
-  vra_load(A, E, a, b);
-  const float ima = ha ? E.body(a)[BIM] : 0.f, imb = E.body(b)[BIM];
+  vr_load_ab(V, E, a, b);
+  vra_load_ab(A, E, a, b);
+  const float ima = E.body(a)[BIM], imb = E.body(b)[BIM];
   float imA = 0.f, imB = 0.f;
   RR Rc;
   QR Qc;
@@ -1727,19 +1772,19 @@ SHD void rev_joint(const DevModel& M, const Env& E, int s, int a, int b, const f
     qr_store(Qc, E.rowA(s + q));
     if (q > 0) { Rc = Rn; Qc = Qn; ltc = ltn; lpc = lpn; }
   }
-  vr_store(V, E, a, b);
-  vra_store(A, E, a, b);
-  if (ha) E.bodyA(a)[AIM] += imA;
+  vr_store_ab(V, E, a, b);
+  vra_store_ab(A, E, a, b);
+  E.bodyA(a)[AIM] += imA;
   E.bodyA(b)[AIM] += imB;
 }
 
 // Reverse of one contact visit: friction disk, then the normal row.
 SHD void rev_contact(const DevModel& M, const Env& E, int s, int a, int b, float mu, const float* H,
                      const float* Hp, float& gmu) {
-  const bool ha = a >= 0;
+  constexpr bool ha = true;
   VR V, A;
-  vr_load(V, E, a, b);
-  vra_load(A, E, a, b);
+  vr_load_ab(V, E, a, b);
+  vra_load_ab(A, E, a, b);
   RR R1, R2;
   QR Q1, Q2;
   rr_load(R1, E.row(s + 1));
@@ -1748,7 +1793,7 @@ SHD void rev_contact(const DevModel& M, const Env& E, int s, int a, int b, float
   qr_load(Q2, E.rowA(s + 2));
   float* xa = E.rowA(s + 3);
   const float mt = E.row(s + 3)[XMT];
-  const float ima = ha ? E.body(a)[BIM] : 0.f, imb = E.body(b)[BIM];
+  const float ima = E.body(a)[BIM], imb = E.body(b)[BIM];
   float imA = 0.f, imB = 0.f;
   const float ltn = H[s], l1t = H[s + 1], l2t = H[s + 2];
   const float ln = fmaxf(ltn, 0.f);
@@ -1796,9 +1841,9 @@ SHD void rev_contact(const DevModel& M, const Env& E, int s, int a, int b, float
   Q0.l += lnb;
   rev_scalar(R0, Q0, V, A, ha, ima, imb, ltn, lpn, false, M.gamma, imA, imB);
   qr_store(Q0, E.rowA(s));
-  vr_store(V, E, a, b);
-  vra_store(A, E, a, b);
-  if (ha) E.bodyA(a)[AIM] += imA;
+  vr_store_ab(V, E, a, b);
+  vra_store_ab(A, E, a, b);
+  E.bodyA(a)[AIM] += imA;
   E.bodyA(b)[AIM] += imB;
 }
 

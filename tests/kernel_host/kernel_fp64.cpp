@@ -111,6 +111,8 @@ int kh_sizes(const sim_model_desc* d, long long* out) {
   const int n_ckpt = d->T_max > 0 ? (d->T_max - 1) / d->ckpt_every + 1 : 1;
   out[0] = h.M.lam_tot; out[1] = h.P.seg_total; out[2] = (long long)n_ckpt * (18LL * h.M.B + h.M.lam_tot);
   out[3] = h.P.dump;
+  out[4] = *std::max_element(h.P.fwd_of.begin(), h.P.fwd_of.end());
+  out[5] = *std::max_element(h.P.adj_of.begin(), h.P.adj_of.end());
   return 0;
 }
 int kh_rollout_grad(const sim_model_desc* d, const double* x0, const double* u, const double* dloss, double* loss,

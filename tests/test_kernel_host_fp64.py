@@ -134,9 +134,10 @@ def _rel(a, b):
 def _sizes(w):
     lib = _load()
     d, keep = _desc64(w)
-    out = (C.c_longlong * 4)()
+    out = (C.c_longlong * 6)()
     assert lib.kh_sizes(C.byref(d), out) == 0
-    return dict(lam=out[0], seg_floats=out[1], ckpt_floats=out[2], mode=("replay", "segment", "trajectory")[out[3]])
+    return dict(lam=out[0], seg_floats=out[1], ckpt_floats=out[2], mode=("replay", "segment", "trajectory")[out[3]],
+                fwd_floats=out[4], adj_floats=out[5])
 
 
 def test_reverse_sweep_memory_modes_and_their_sizes():
