@@ -65,6 +65,11 @@ struct TeamGPU {
     return v;
   }
   __device__ bool team_any(bool p) const { return (__ballot((int)p) & mask) != 0ull; }
+  // the value of the other lane of this lane's pair (2m, 2m+1): a DPP
+  // quad permutation [1, 0, 3, 2]; both lanes must be active
+  __device__ float pair_swap(float v) const {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, false));
+  }
 };
 
 template <int TEAM>

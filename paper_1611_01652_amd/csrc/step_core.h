@@ -141,8 +141,9 @@ enum { XT1 = 0, XT2 = 3, XMT = 6, XGAP = 7, XSTORE = 8, XCODE = 9, XF = 10, XY =
 enum { QJL = 0, QJA = 3, QJB = 6, QWA = 9, QWB = 12, QM = 15, QB = 16, QL = 17, RSA = 20 };
 
 // Sweep plan entries (16 bytes, one LDS load): per live colour (start in the
-// active list, count, -, -); per active constraint (slot, body a, body b,
-// code), body a being the world slot nb where the constraint has no body a.
+// active list, count, 1 for a colour of hinges, -); per active constraint
+// (slot, body a, body b, code), body a being the world slot nb where the
+// constraint has no body a.
 struct alignas(16) i4 { int x, y, z, w; };
 
 struct Lay {
@@ -686,7 +687,7 @@ SHD void f_rows(const Team& tm, const DevModel& M, const Env& E, bool act) {
     int m = 0;
     for (int c = 0; c < E.ncol; ++c)
       if (E.act_cnt()[c] > 0) {
-        E.plan()[m] = i4{E.colstart(c), E.act_cnt()[c], 0, 0};
+        E.plan()[m] = i4{E.colstart(c), E.act_cnt()[c], cand_kind(E.cand(E.colstart(c))) == K_JOINT ? 1 : 0, 0};
         E.live()[2 + m++] = c;
       }
     E.live()[0] = m;
@@ -706,9 +707,22 @@ struct SweepCursor {
   int cn, c2;     // live colours of the next two visits
   i4 pc, vc, pn;  // plan and this lane's first entry of the current colour, plan of the next
   SHD int step(int c) const { return DIR > 0 ? (c + 1 == nl ? 0 : c + 1) : (c == 0 ? nl - 1 : c - 1); }
+  // Hinges are visited by lane pairs (one body each) when the team has two
+  // lanes or more: lane tl takes constraints l0(tl) + k * step(tl).
+  template <class Team>
+  SHD static bool paired(const Team& tm, const i4& p) { return p.z != 0 && tm.ts >= 2; }
+  template <class Team>
+  SHD static int l0(const Team& tm, const i4& p) { return paired(tm, p) ? tm.tl >> 1 : tm.tl; }
+  template <class Team>
+  SHD static int stride(const Team& tm, const i4& p) { return paired(tm, p) ? tm.ts >> 1 : tm.ts; }
+  // (written with plain branches: a conditional expression over two 16-byte
+  // lvalues makes the compiler keep the cursor in scratch memory)
   template <class Team>
   SHD i4 first(const Team& tm, const Env& E, const i4& p, bool ok) const {
-    return (ok && tm.tl < p.y) ? E.vis()[p.x + tm.tl] : i4{-1, 0, 0, 0};
+    const int i = l0(tm, p);
+    i4 r{-1, 0, 0, 0};
+    if (ok && i < p.y) r = E.vis()[p.x + i];
+    return r;
   }
   template <class Team>
   SHD void start(const Team& tm, const Env& E, int n_iters, int n_live_cols) {
@@ -718,20 +732,31 @@ struct SweepCursor {
     ci = DIR > 0 ? 0 : nl - 1;
     cn = step(ci);
     c2 = step(cn);
-    pc = left > 0 ? E.plan()[ci] : i4{0, 0, 0, 0};
+    pc = i4{0, 0, 0, 0};
+    if (left > 0) pc = E.plan()[ci];
     vc = first(tm, E, pc, left > 0);
-    pn = left > 1 ? E.plan()[cn] : i4{0, 0, 0, 0};
+    pn = i4{0, 0, 0, 0};
+    if (left > 1) pn = E.plan()[cn];
   }
   // loads for the next visit (call before the current one runs)
   template <class Team>
   SHD void prefetch(const Team& tm, const Env& E, i4& vn, i4& p2) const {
     vn = first(tm, E, pn, left > 1);
-    p2 = left > 2 ? E.plan()[c2] : i4{0, 0, 0, 0};
+    p2 = i4{0, 0, 0, 0};
+    if (left > 2) p2 = E.plan()[c2];
   }
-  // this lane's k-th constraint of the current colour, at tl + k ts (k >= 1:
-  // not prefetched)
+  // this lane's k-th constraint of the current colour (k >= 1: not prefetched)
   template <class Team>
-  SHD i4 entry(const Team& tm, const Env& E, int k) const { return k == 0 ? vc : E.vis()[pc.x + tm.tl + k * tm.ts]; }
+  SHD i4 entry(const Team& tm, const Env& E, int k) const {
+    if (k == 0) return vc;
+    return E.vis()[pc.x + l0(tm, pc) + k * stride(tm, pc)];
+  }
+  // constraints of the current colour this lane takes part in
+  template <class Team>
+  SHD int count(const Team& tm) const {
+    const int n = left > 0 ? pc.y : 0, i = l0(tm, pc), st = stride(tm, pc);
+    return i < n ? (n - i + st - 1) / st : 0;
+  }
   SHD void advance(const i4& vn, const i4& p2) {
     if (cn == (DIR > 0 ? 0 : nl - 1)) it += DIR;
     --left;
@@ -844,57 +869,125 @@ SHD void rr_apply(const RR& R, VR& V, bool ha, float ima, float imb, float d) {
   }
 }
 
-// Row shapes of a hinge: its point rows have Jl = e_k (the row's axis k), its
-// angular rows Jl = 0.  The shape-specialised helpers below do the generic
-// row arithmetic with the exact multiplications by 0 and 1 left out (same
-// operations, same order), and skip the adjoint of Jl, which for a hinge is a
-// constant.  S = 0, 1, 2: point row along axis S; S = 3: angular row.
-template <int S>
-SHD float rs_jv(const RR& R, const VR& V, bool ha) {
-  float s = S < 3 ? V.vb[S] : 0.f;
-  s += R.jb[0] * V.wb[0] + R.jb[1] * V.wb[1] + R.jb[2] * V.wb[2];
-  if (ha) {
-    if (S < 3) s -= V.va[S];
-    s += R.ja[0] * V.wa[0] + R.ja[1] * V.wa[1] + R.ja[2] * V.wa[2];
+// ------------------------------------------------------------------ hinge visits
+// A hinge row's arithmetic split by body.  Its point rows have Jl = e_S (axis
+// S = 0, 1, 2) and its angular rows Jl = 0 (S = 3), so the row's J v is the
+// sum of side b's part v_b,S + Jb . w_b and side a's part -v_a,S + Ja . w_a
+// (side a is the world slot when there is no body a), always added as
+// (part b) + (part a); W . vbar in the reverse likewise.  A visit runs with
+// both sides in one lane (NS = 2) or with one side on each lane of a pair
+// (2m: a, 2m+1: b; NS = 1) whose lanes swap their parts.  IEEE addition is
+// commutative and each side's arithmetic applies its sign to one exact
+// leaf (sg = +-1 times a value), so both forms give the same bits: results do
+// not depend on the team width.  The adjoint of Jl, a constant, is skipped.
+struct HS { float v[3], w[3]; };  // a side's body velocity (or its adjoint)
+struct HR { float j[3], W[3]; };  // a side's angular Jacobian part and W = I^-1 j
+struct HQ { float j[3], W[3]; };  // a side's adjoint accumulators of j and W
+
+SHD void hs_load(HS& x, const float* p) {   // p: v(3), w(3), 16-byte aligned
+  const f4 q = ld4(p);
+  x.v[0] = q.x; x.v[1] = q.y; x.v[2] = q.z; x.w[0] = q.w; x.w[1] = p[4]; x.w[2] = p[5];
+}
+SHD void hs_store(const HS& x, float* p) {
+  f4 q; q.x = x.v[0]; q.y = x.v[1]; q.z = x.v[2]; q.w = x.w[0];
+  st4(p, q); p[4] = x.w[1]; p[5] = x.w[2];
+}
+// side 1: body b, side 0: body a
+SHD void hr_load(HR& r, const float* row, int side) {
+  const float* j = row + (side ? RJB : RJA);
+  const float* W = row + (side ? RWB : RWA);
+  for (int k = 0; k < 3; ++k) { r.j[k] = j[k]; r.W[k] = W[k]; }
+}
+SHD void hq_load(HQ& q, const float* rowA, int side) {
+  const float* j = rowA + (side ? QJB : QJA);
+  const float* W = rowA + (side ? QWB : QWA);
+  for (int k = 0; k < 3; ++k) { q.j[k] = j[k]; q.W[k] = W[k]; }
+}
+SHD void hq_store(const HQ& q, float* rowA, int side) {
+  float* j = rowA + (side ? QJB : QJA);
+  float* W = rowA + (side ? QWB : QWA);
+  for (int k = 0; k < 3; ++k) { j[k] = q.j[k]; W[k] = q.W[k]; }
+}
+// The sides of a visit held by this lane: index i has side sd[i] (1 = b),
+// body bd[i], sign sg[i], inverse mass im[i] and signed inverse mass sim[i].
+template <int NS>
+struct HSides {
+  int sd[NS], bd[NS];
+  float sg[NS], im[NS], sim[NS];
+  template <class Team>
+  SHD void init(const Team& tm, const Env& E, int a, int b) {
+    for (int i = 0; i < NS; ++i) {
+      sd[i] = NS == 2 ? 1 - i : (tm.tl & 1);
+      bd[i] = sd[i] ? b : a;
+      sg[i] = sd[i] ? 1.f : -1.f;
+      im[i] = E.body(bd[i])[BIM];
+      sim[i] = sg[i] * im[i];
+    }
   }
-  return s;
+  // this lane writes the visit's shared outputs (the b side)
+  template <class Team>
+  SHD bool writer(const Team& tm) const { return NS == 2 || (tm.tl & 1); }
+};
+// part b + part a: both in this lane, or this lane's part and its partner's
+template <int NS, class Team>
+SHD float h_sum(const Team& tm, const float* p) {
+  if (NS == 2) return p[0] + p[1];
+  return p[0] + tm.pair_swap(p[0]);
 }
 template <int S>
-SHD void rs_apply(const RR& R, VR& V, bool ha, float ima, float imb, float d) {
-  if (S < 3) V.vb[S] += imb * d;
-  for (int k = 0; k < 3; ++k) V.wb[k] += d * R.wb[k];
-  if (ha) {
-    if (S < 3) V.va[S] -= ima * d;
-    for (int k = 0; k < 3; ++k) V.wa[k] += d * R.wa[k];
-  }
+SHD float h_jpart(const HR& r, const HS& x, float sg) {
+  float p = S < 3 ? sg * x.v[S] : 0.f;
+  p += r.j[0] * x.w[0];
+  p += r.j[1] * x.w[1];
+  p += r.j[2] * x.w[2];
+  return p;
 }
 template <int S>
-SHD void pgs_hinge_row(const DevModel& M, RR& R, VR& V, bool ha, float ima, float imb, float* h, float* rmax) {
-  const float sv_ = rs_jv<S>(R, V, ha) + R.bias + M.gamma * R.lam;
-  const float lt = R.lam - R.m * sv_;
+SHD void h_apply(const HR& r, HS& x, float sim, float d) {
+  if (S < 3) x.v[S] += sim * d;
+  for (int k = 0; k < 3; ++k) x.w[k] += d * r.W[k];
+}
+template <int S, int NS, class Team>
+SHD void h_row_fwd(const Team& tm, const DevModel& M, const HR* r, HS* x, const HSides<NS>& sd, float m, float bias,
+                   float& lam, float* h, float* rmax) {
+  float p[NS];
+  for (int i = 0; i < NS; ++i) p[i] = h_jpart<S>(r[i], x[i], sd.sg[i]);
+  const float sv_ = h_sum<NS>(tm, p) + bias + M.gamma * lam;
+  const float lt = lam - m * sv_;
   if (h) *h = lt;
-  if (rmax) *rmax = fmaxf(*rmax, fabsf(lt - R.lam) / R.m);
-  rs_apply<S>(R, V, ha, ima, imb, lt - R.lam);
-  R.lam = lt;
+  if (rmax) *rmax = fmaxf(*rmax, fabsf(lt - lam) / m);
+  const float d = lt - lam;
+  for (int i = 0; i < NS; ++i) h_apply<S>(r[i], x[i], sd.sim[i], d);
+  lam = lt;
 }
 
-// One visit of a hinge (5 unbounded rows) with all data in registers.
-// rmax (tolerance mode): running maximum of |delta lambda| / m over the rows.
-// a: body index or the world slot.
-SHD void pgs_joint(const DevModel& M, const Env& E, int s, int a, int b, float* H, float* rmax = nullptr) {
-  constexpr bool ha = true;
-  VR V;
-  vr_load_ab(V, E, a, b);
-  RR R[5];
-  for (int q = 0; q < 5; ++q) rr_load(R[q], E.row(s + q));
-  const float ima = E.body(a)[BIM], imb = E.body(b)[BIM];
-  pgs_hinge_row<0>(M, R[0], V, ha, ima, imb, H ? H + s : nullptr, rmax);
-  pgs_hinge_row<1>(M, R[1], V, ha, ima, imb, H ? H + s + 1 : nullptr, rmax);
-  pgs_hinge_row<2>(M, R[2], V, ha, ima, imb, H ? H + s + 2 : nullptr, rmax);
-  pgs_hinge_row<3>(M, R[3], V, ha, ima, imb, H ? H + s + 3 : nullptr, rmax);
-  pgs_hinge_row<3>(M, R[4], V, ha, ima, imb, H ? H + s + 4 : nullptr, rmax);
-  for (int q = 0; q < 5; ++q) E.row(s + q)[RL] = R[q].lam;
-  vr_store_ab(V, E, a, b);
+// One forward visit of a hinge (5 unbounded rows) with all data in
+// registers; a: body index or the world slot.  rmax (tolerance mode, NS = 2):
+// running maximum of |delta lambda| / m over the rows.
+template <int NS, class Team>
+SHD void hinge_fwd(const Team& tm, const DevModel& M, const Env& E, int s, int a, int b, float* H,
+                   float* rmax = nullptr) {
+  HSides<NS> sd;
+  sd.init(tm, E, a, b);
+  HS x[NS];
+  for (int i = 0; i < NS; ++i) hs_load(x[i], E.body(sd.bd[i]) + BV);
+  HR r[5][NS];
+  float m[5], bias[5], lam[5];
+  for (int q = 0; q < 5; ++q) {
+    const float* R = E.row(s + q);
+    for (int i = 0; i < NS; ++i) hr_load(r[q][i], R, sd.sd[i]);
+    m[q] = R[RM]; bias[q] = R[RBI]; lam[q] = R[RL];
+  }
+  const bool wr = sd.writer(tm);
+  float* Hw = (H && wr) ? H + s : nullptr;
+  h_row_fwd<0, NS>(tm, M, r[0], x, sd, m[0], bias[0], lam[0], Hw ? Hw : nullptr, rmax);
+  h_row_fwd<1, NS>(tm, M, r[1], x, sd, m[1], bias[1], lam[1], Hw ? Hw + 1 : nullptr, rmax);
+  h_row_fwd<2, NS>(tm, M, r[2], x, sd, m[2], bias[2], lam[2], Hw ? Hw + 2 : nullptr, rmax);
+  h_row_fwd<3, NS>(tm, M, r[3], x, sd, m[3], bias[3], lam[3], Hw ? Hw + 3 : nullptr, rmax);
+  h_row_fwd<3, NS>(tm, M, r[4], x, sd, m[4], bias[4], lam[4], Hw ? Hw + 4 : nullptr, rmax);
+  if (wr)
+    for (int q = 0; q < 5; ++q) E.row(s + q)[RL] = lam[q];
+  for (int i = 0; i < NS; ++i) hs_store(x[i], E.body(sd.bd[i]) + BV);
 }
 
 // One visit of a contact: normal row clamped at 0, then the friction disk.
@@ -944,13 +1037,15 @@ SHD void f_pgs(const Team& tm, const DevModel& M, const Env& E, bool act, float*
   while (tm.any(sw.left > 0)) {
     i4 vn, p2;
     sw.prefetch(tm, E, vn, p2);
-    const int n = sw.left > 0 ? sw.pc.y : 0;
     float* H = hist ? hist + (size_t)sw.it * E.nslot : nullptr;
-    for (int k = 0; tm.tl + k * tm.ts < n; ++k) {
+    const int nk = sw.count(tm);
+    for (int k = 0; k < nk; ++k) {
       const i4 v = sw.entry(tm, E, k);
       if (v.x < 0) continue;
-      if (cand_kind(v.w) == K_JOINT) pgs_joint(M, E, v.x, v.y, v.z, H);
-      else pgs_contact(M, E, v.x, v.y, v.z, mu, H);
+      // a hinge colour is visited by lane pairs whenever the team has two lanes
+      if (cand_kind(v.w) != K_JOINT) pgs_contact(M, E, v.x, v.y, v.z, mu, H);
+      else if (tm.ts >= 2) hinge_fwd<1>(tm, M, E, v.x, v.y, v.z, H);
+      else hinge_fwd<2>(tm, M, E, v.x, v.y, v.z, H);
     }
     tm.sync();
     sw.advance(vn, p2);
@@ -1297,7 +1392,7 @@ SHD void f_pgs_tol(const Team& tm, const DevModel& M, const Env& E, bool live, i
         const int code = E.act_code()[lo + k];
         const RowB rb = cand_bodies(E, code);
         const int a = rb.a >= 0 ? rb.a : E.nb;
-        if (cand_kind(code) == K_JOINT) pgs_joint(M, E, s, a, rb.b, nullptr, &r);
+        if (cand_kind(code) == K_JOINT) hinge_fwd<2>(tm, M, E, s, a, rb.b, nullptr, &r);
         else pgs_contact(M, E, s, a, rb.b, mu, nullptr, &rc);
       }
       tm.sync();
@@ -1688,94 +1783,105 @@ SHD void rev_scalar(const RR& R, QR& Q, VR& V, VR& A, bool ha, float ima, float 
   Q.l = -wv + ltb + gamma * sb;
 }
 
-// Shape-specialised reverse helpers of a hinge row (see rs_jv).
+// Reverse of one hinge row update, by side (see hinge_fwd).
 template <int S>
-SHD float rs_wv(const RR& R, const VR& A, bool ha, float ima, float imb) {
-  float s = S < 3 ? imb * A.vb[S] : 0.f;
-  s += R.wb[0] * A.wb[0] + R.wb[1] * A.wb[1] + R.wb[2] * A.wb[2];
-  if (ha) {
-    if (S < 3) s -= ima * A.va[S];
-    s += R.wa[0] * A.wa[0] + R.wa[1] * A.wa[1] + R.wa[2] * A.wa[2];
-  }
-  return s;
+SHD float h_wpart(const HR& r, const HS& A, float sim) {
+  float p = S < 3 ? sim * A.v[S] : 0.f;
+  p += r.W[0] * A.w[0];
+  p += r.W[1] * A.w[1];
+  p += r.W[2] * A.w[2];
+  return p;
 }
-template <int S>
-SHD void rs_wbar(QR& Q, const VR& A, bool ha, float d, float& imA, float& imB) {
-  for (int k = 0; k < 3; ++k) Q.wb[k] += A.wb[k] * d;
-  if (S < 3) imB += d * A.vb[S];
-  if (ha) {
-    for (int k = 0; k < 3; ++k) Q.wa[k] += A.wa[k] * d;
-    if (S < 3) imA -= d * A.va[S];
+// Row-shared data of one hinge row in the reverse: mass, bias, recorded
+// pre-projection impulse lt and the impulse before the update lp, and the
+// adjoint accumulators of m, bias and lambda.
+struct HRow { float m, bias, lt, lp, qm, qb, ql; };
+template <int S, int NS, class Team>
+SHD void h_row_rev(const Team& tm, const HR* r, HQ* q, HS* x, HS* A, const HSides<NS>& sd, float* imx, HRow& c,
+                   float gamma) {
+  const float d = c.lt - c.lp;
+  for (int i = 0; i < NS; ++i) h_apply<S>(r[i], x[i], sd.sim[i], -d);   // v before the update
+  // adjoint of W from v += W d (the linear part folded into the inverse masses)
+  for (int i = 0; i < NS; ++i) {
+    for (int k = 0; k < 3; ++k) q[i].W[k] += A[i].w[k] * d;
+    if (S < 3) imx[i] += (sd.sg[i] * d) * A[i].v[S];
   }
-}
-template <int S>
-SHD void rs_jbar(QR& Q, const RR& R, VR& A, const VR& V, bool ha, float sb) {
-  if (S < 3) A.vb[S] += sb;
-  for (int k = 0; k < 3; ++k) {
-    A.wb[k] += R.jb[k] * sb;
-    Q.jb[k] += sb * V.wb[k];
-  }
-  if (ha) {
-    if (S < 3) A.va[S] -= sb;
+  float p[NS];
+  for (int i = 0; i < NS; ++i) p[i] = h_wpart<S>(r[i], A[i], sd.sim[i]);
+  const float wv = h_sum<NS>(tm, p);
+  const float ltb = c.ql + wv;
+  const float sb = -c.m * ltb;
+  for (int i = 0; i < NS; ++i) p[i] = h_jpart<S>(r[i], x[i], sd.sg[i]);
+  const float sval = h_sum<NS>(tm, p) + c.bias + gamma * c.lp;
+  c.qm += -sval * ltb;
+  c.qb += sb;
+  // vbar += J^T sb ; Jbar += sb v
+  for (int i = 0; i < NS; ++i) {
+    if (S < 3) A[i].v[S] += sd.sg[i] * sb;
     for (int k = 0; k < 3; ++k) {
-      A.wa[k] += R.ja[k] * sb;
-      Q.ja[k] += sb * V.wa[k];
+      A[i].w[k] += r[i].j[k] * sb;
+      q[i].j[k] += sb * x[i].w[k];
     }
   }
+  c.ql = -wv + ltb + gamma * sb;
 }
-// Reverse of one (unbounded) hinge row update.
-template <int S>
-SHD void rev_hinge_row(const RR& R, QR& Q, VR& V, VR& A, bool ha, float ima, float imb, float lt, float lp,
-                       float gamma, float& imA, float& imB) {
-  const float d = lt - lp;
-  rs_apply<S>(R, V, ha, ima, imb, -d);   // v before the update
-  rs_wbar<S>(Q, A, ha, d, imA, imB);
-  const float wv = rs_wv<S>(R, A, ha, ima, imb);
-  const float ltb = Q.l + wv;
-  const float sb = -R.m * ltb;
-  const float sval = rs_jv<S>(R, V, ha) + R.bias + gamma * lp;
-  Q.m += -sval * ltb;
-  Q.b += sb;
-  rs_jbar<S>(Q, R, A, V, ha, sb);
-  Q.l = -wv + ltb + gamma * sb;
+template <int NS>
+SHD void h_rev_load(const Env& E, const HSides<NS>& sd, int slot, const float* H, const float* Hp, HR* r, HQ* q,
+                    HRow& c) {
+  const float* R = E.row(slot);
+  const float* Q = E.rowA(slot);
+  for (int i = 0; i < NS; ++i) {
+    hr_load(r[i], R, sd.sd[i]);
+    hq_load(q[i], Q, sd.sd[i]);
+  }
+  c.m = R[RM]; c.bias = R[RBI];
+  c.qm = Q[QM]; c.qb = Q[QB]; c.ql = Q[QL];
+  c.lt = H[slot];
+  c.lp = Hp ? Hp[slot] : R[RL0];
 }
 
 // Reverse of one hinge visit (rows 4..0).  Row data and row adjoint
 // accumulators are streamed: row q-1 is loaded while row q is reversed.
 // a: body index or the world slot (whose adjoint slot is a sink).
-SHD void rev_joint(const DevModel& M, const Env& E, int s, int a, int b, const float* H, const float* Hp) {
-  constexpr bool ha = true;
-  VR V, A;
-  vr_load_ab(V, E, a, b);
-  vra_load_ab(A, E, a, b);
-  const float ima = E.body(a)[BIM], imb = E.body(b)[BIM];
-  float imA = 0.f, imB = 0.f;
-  RR Rc;
-  QR Qc;
-  rr_load(Rc, E.row(s + 4));
-  qr_load(Qc, E.rowA(s + 4));
-  float ltc = H[s + 4], lpc = Hp ? Hp[s + 4] : E.row(s + 4)[RL0];
-  for (int q = 4; q >= 0; --q) {
-    RR Rn;
-    QR Qn;
-    float ltn = 0.f, lpn = 0.f;
-    if (q > 0) {
-      rr_load(Rn, E.row(s + q - 1));
-      qr_load(Qn, E.rowA(s + q - 1));
-      ltn = H[s + q - 1];
-      lpn = Hp ? Hp[s + q - 1] : E.row(s + q - 1)[RL0];
-    }
-    if (q >= 3) rev_hinge_row<3>(Rc, Qc, V, A, ha, ima, imb, ltc, lpc, M.gamma, imA, imB);
-    else if (q == 2) rev_hinge_row<2>(Rc, Qc, V, A, ha, ima, imb, ltc, lpc, M.gamma, imA, imB);
-    else if (q == 1) rev_hinge_row<1>(Rc, Qc, V, A, ha, ima, imb, ltc, lpc, M.gamma, imA, imB);
-    else rev_hinge_row<0>(Rc, Qc, V, A, ha, ima, imb, ltc, lpc, M.gamma, imA, imB);
-    qr_store(Qc, E.rowA(s + q));
-    if (q > 0) { Rc = Rn; Qc = Qn; ltc = ltn; lpc = lpn; }
+template <int NS, class Team>
+SHD void hinge_rev(const Team& tm, const DevModel& M, const Env& E, int s, int a, int b, const float* H,
+                   const float* Hp) {
+  HSides<NS> sd;
+  sd.init(tm, E, a, b);
+  HS x[NS], A[NS];
+  float imx[NS];
+  for (int i = 0; i < NS; ++i) {
+    hs_load(x[i], E.body(sd.bd[i]) + BV);
+    hs_load(A[i], E.bodyA(sd.bd[i]) + AV);
+    imx[i] = 0.f;
   }
-  vr_store_ab(V, E, a, b);
-  vra_store_ab(A, E, a, b);
-  E.bodyA(a)[AIM] += imA;
-  E.bodyA(b)[AIM] += imB;
+  const bool wr = sd.writer(tm);
+  HR rc[NS];
+  HQ qc[NS];
+  HRow cc;
+  h_rev_load<NS>(E, sd, s + 4, H, Hp, rc, qc, cc);
+  for (int q = 4; q >= 0; --q) {
+    HR rn[NS];
+    HQ qn[NS];
+    HRow cn;
+    if (q > 0) h_rev_load<NS>(E, sd, s + q - 1, H, Hp, rn, qn, cn);
+    if (q >= 3) h_row_rev<3, NS>(tm, rc, qc, x, A, sd, imx, cc, M.gamma);
+    else if (q == 2) h_row_rev<2, NS>(tm, rc, qc, x, A, sd, imx, cc, M.gamma);
+    else if (q == 1) h_row_rev<1, NS>(tm, rc, qc, x, A, sd, imx, cc, M.gamma);
+    else h_row_rev<0, NS>(tm, rc, qc, x, A, sd, imx, cc, M.gamma);
+    float* Q = E.rowA(s + q);
+    for (int i = 0; i < NS; ++i) hq_store(qc[i], Q, sd.sd[i]);
+    if (wr) { Q[QM] = cc.qm; Q[QB] = cc.qb; Q[QL] = cc.ql; }
+    if (q > 0) {
+      for (int i = 0; i < NS; ++i) { rc[i] = rn[i]; qc[i] = qn[i]; }
+      cc = cn;
+    }
+  }
+  for (int i = 0; i < NS; ++i) {
+    hs_store(x[i], E.body(sd.bd[i]) + BV);
+    hs_store(A[i], E.bodyA(sd.bd[i]) + AV);
+    E.bodyA(sd.bd[i])[AIM] += imx[i];
+  }
 }
 
 // Reverse of one contact visit: friction disk, then the normal row.
@@ -1857,14 +1963,15 @@ SHD void a_pgs(const Team& tm, const DevModel& M, const Env& E, bool act) {
   while (tm.any(sw.left > 0)) {
     i4 vn, p2;
     sw.prefetch(tm, E, vn, p2);
-    const int n = sw.left > 0 ? sw.pc.y : 0;
     const float* H = E.hist(sw.it);
     const float* Hp = sw.it > 0 ? E.hist(sw.it - 1) : nullptr;
-    for (int k = 0; tm.tl + k * tm.ts < n; ++k) {
+    const int nk = sw.count(tm);
+    for (int k = 0; k < nk; ++k) {
       const i4 v = sw.entry(tm, E, k);
       if (v.x < 0) continue;
-      if (cand_kind(v.w) == K_JOINT) rev_joint(M, E, v.x, v.y, v.z, H, Hp);
-      else rev_contact(M, E, v.x, v.y, v.z, mu, H, Hp, gmu);
+      if (cand_kind(v.w) != K_JOINT) rev_contact(M, E, v.x, v.y, v.z, mu, H, Hp, gmu);
+      else if (tm.ts >= 2) hinge_rev<1>(tm, M, E, v.x, v.y, v.z, H, Hp);
+      else hinge_rev<2>(tm, M, E, v.x, v.y, v.z, H, Hp);
     }
     tm.sync();
     sw.advance(vn, p2);

@@ -11,10 +11,13 @@ and compare with the FP64 oracle using the per-env error metrics:
 * non-chaotic horizon T_nc(env): the first step at which the oracle, re-run
   with relative noise of the size of FP32 rounding (2^-24) added to its state
   after every step, departs from the clean oracle by more than half the state
-  tolerance (5e-5).  States are compared at every checkpoint before T_nc;
-  gradients of an env are compared when the gradients of three noisy oracle
-  runs (independent noise seeds) all stay within half the gradient tolerance
-  (5e-4) of the clean one: a near-tie at a clamp, disk or contact threshold,
+  tolerance (5e-5), the earliest over eight independent noise draws (near
+  the edge of chaos the noisy runs spread widely: one chain of the 40-env
+  case departs by 4e-6 to 9e-5 at step 100 depending on the draw, so a few
+  draws undersample it).  States are compared at every checkpoint before
+  T_nc; gradients of an env are compared when the gradients of the noisy
+  oracle runs all stay within half the gradient tolerance (5e-4) of the
+  clean one: a near-tie at a clamp, disk or contact threshold,
   where FP32 and FP64 may take different branches, shows up in one of them.  (Perturbing
   only the inputs under-predicts FP32 error: rounding enters at every step,
   and rounded positions feed the Baumgarte term directly.)  Envs outside these horizons
@@ -143,7 +146,7 @@ def horizons(w, traj, traj_p, thr=0.5 * STATE_TOL):
     return out
 
 
-def compare_with_oracle(w, got, check_grad=True, min_state_frac=0.0, min_grad_frac=1.0, seeds=3,
+def compare_with_oracle(w, got, check_grad=True, min_state_frac=0.0, min_grad_frac=1.0, seeds=8,
                         outlier_frac=0.0):
     """Checkpointed states before T_nc and final states within 1e-4, loss
     within 1e-4, gradients of gradient-stable envs within 1e-3.  With

@@ -41,6 +41,7 @@ struct TeamHost {
   double team_sum(double v) const { return v; }
   double team_max(double v) const { return v; }
   bool team_any(bool p) const { return p; }
+  double pair_swap(double v) const { return v; }   // one-lane teams never pair
   int* shared_cnt() const { return cnt; }
   int* shared_map() const { return map; }
   // the network in plain loops, with the rounding of the matrix-core kernel
