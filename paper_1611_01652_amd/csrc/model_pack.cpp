@@ -193,8 +193,8 @@ sim_status build_env(const sim_model_desc& d, int e, HostEnv& H) {
   if (d.ctrl_kind == 1) {
     if (d.mlp_sizes[3] != H.nj || d.mlp_sizes[0] != 2 * H.nj + 2)
       return fail(SIM_E_SHAPE, "env " + std::to_string(e) + ": controller needs out = joints and in = 2 joints + 2");
-    mf = d.mlp_sizes[0] + d.mlp_sizes[1] + d.mlp_sizes[2];
-    ma = d.mlp_sizes[3] + d.mlp_sizes[2] + d.mlp_sizes[1] + d.mlp_sizes[0];
+    mf = mlp_fwd_floats(d.mlp_sizes[0], d.mlp_sizes[1], d.mlp_sizes[2], d.mlp_sizes[3]);
+    ma = mlp_adj_floats(d.mlp_sizes[0], d.mlp_sizes[1], d.mlp_sizes[2], d.mlp_sizes[3]);
   }
   const int vs = vsave_floats(d.ws_kind, H.nb);
   H.fwd_floats = make_lay(H.nb, H.nj, H.G, H.P, H.ncol, H.ncand, H.nslot, H.lam, d.n_iters, false, mf, ma, vs).total;

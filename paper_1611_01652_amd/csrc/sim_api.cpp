@@ -63,6 +63,7 @@ struct sim_model {
   int n_graphs = 0;             // live step graphs (they hold the tile lists)
   uint16_t* d_wsn = nullptr;    // warm-start network, bfloat16
   hipEvent_t tev[4] = {};       // rollout_grad phase events (sim_time_grad), owned by the caller
+  float* d_wt = nullptr;        // controller weights transposed for the forward products
 };
 
 struct sim_graph_s {
@@ -95,6 +96,7 @@ void release(sim_model* h) {
   if (h->d_tiles) (void)hipFree(h->d_tiles);
   if (h->d_map) (void)hipFree(h->d_map);
   if (h->d_wsn) (void)hipFree(h->d_wsn);
+  if (h->d_wt) (void)hipFree(h->d_wt);
   for (auto sx : h->streams) (void)hipStreamDestroy(sx);
   for (auto ex : h->joins) (void)hipEventDestroy(ex);
   if (h->fork) (void)hipEventDestroy(h->fork);
@@ -130,9 +132,12 @@ sim_status run_buckets(sim_model* h, hipStream_t st, F launch, const char* what)
 // learned warm start, the shared network region.
 long long fwd_bytes(const DevModel& M, int team, int floats_fwd, int ccap_max) {
   const int epw = 64 / team;
-  return 4LL * ((long long)epw * floats_fwd + (M.ws_kind ? wsn_shared_floats(epw * ccap_max) : 0));
+  return 4LL * ((long long)epw * floats_fwd + (M.ctrl ? CTRL_SHARED : 0) +
+                (M.ws_kind ? wsn_shared_floats(epw * ccap_max) : 0));
 }
-long long adj_bytes(int team, int floats_adj) { return 4LL * (64 / team) * floats_adj; }
+long long adj_bytes(const DevModel& M, int team, int floats_adj) {
+  return 4LL * ((long long)(64 / team) * floats_adj + (M.ctrl ? CTRL_SHARED : 0));
+}
 long long fwd_bytes(const sim_model* h, const Bucket& b) { return fwd_bytes(h->M, b.team, b.floats_fwd, b.ccap_max); }
 
 int grid_for(const sim_model* h, long long units, long long bytes) {
@@ -174,18 +179,28 @@ bool bucket_reverse(sim_model* h, size_t i, const DevModel& M, const GradArgs& a
   const Bucket& b = h->buckets[i];
   TileSet ts{b.envs_dev, b.n_tiles, b.floats_adj, h->d_queue + i, 1};
   if (launch_zero(ts.queue, 1, sx) != hipSuccess) return false;
-  const long long lds = adj_bytes(b.team, b.floats_adj);
+  const long long lds = adj_bytes(M, b.team, b.floats_adj);
   return launch_rollout_grad(M, ts, b.team, grid_for(h, b, lds), (size_t)lds, a, sx) == hipSuccess;
 }
 bool bucket_grad(sim_model* h, size_t i, const DevModel& M, const GradArgs& a, hipStream_t sx) {
   return bucket_recompute(h, i, M, a, sx) && bucket_reverse(h, i, M, a, sx);
 }
 
+// The call's controls: the tape or, with a controller, its weights u, of
+// which the forward products read a transposed copy made here on stream st
+// (calls on one handle run one at a time).
+bool prep_controls(sim_model* h, DevModel& M, const float* u, hipStream_t st) {
+  M.W = u;
+  if (!M.ctrl) return true;
+  M.Wt = h->d_wt;
+  return launch_ctrl_transpose(u, h->d_wt, M.mlp_in, M.mlp_h1, M.mlp_h2, M.mlp_out, st) == hipSuccess;
+}
+
 sim_status launch_steps(sim_model* h, const float* x_in, float* x_out, const float* u, const float* lam_in,
                         float* lam_out, int32_t t, uint32_t* env_flags, hipStream_t st) {
   StepArgs a{x_in, x_out, h->M.ctrl ? nullptr : u, lam_in, lam_out, env_flags, t};
   DevModel M = h->M;
-  M.W = u;
+  if (!prep_controls(h, M, u, st)) return check_device("sim_step controls");
   return run_buckets(h, st, [&](size_t i, hipStream_t sx) { return bucket_step(h, i, M, a, sx); },
                      "sim_step launch");
 }
@@ -195,7 +210,7 @@ sim_status launch_steps(sim_model* h, const float* x_in, float* x_out, const flo
 std::vector<int> admissible_teams(const sim_model* h, const Bucket& b) {
   std::vector<int> out;
   for (int t = b.team_min; t <= 64; t *= 2)
-    if (std::max(adj_bytes(t, b.floats_adj), fwd_bytes(h->M, t, b.floats_fwd, b.ccap_max)) <= h->max_lds)
+    if (std::max(adj_bytes(h->M, t, b.floats_adj), fwd_bytes(h->M, t, b.floats_fwd, b.ccap_max)) <= h->max_lds)
       out.push_back(t);
   return out;
 }
@@ -210,7 +225,7 @@ sim_status retile(sim_model* h, Bucket& b, int team) {
   const int n_tiles = ((int)ids.size() + epw - 1) / epw;
   std::vector<int> host((size_t)n_tiles * epw, -1);
   std::copy(ids.begin(), ids.end(), host.begin());
-  const int bytes = (int)std::max(adj_bytes(team, b.floats_adj), fwd_bytes(h->M, team, b.floats_fwd, b.ccap_max));
+  const int bytes = (int)std::max(adj_bytes(h->M, team, b.floats_adj), fwd_bytes(h->M, team, b.floats_fwd, b.ccap_max));
   if (bytes > h->lds_allowed) {
     if (allow_large_lds(std::min(bytes, h->max_lds)) != hipSuccess)
       return fail(SIM_E_DEVICE, "cannot raise the dynamic LDS limit");
@@ -228,7 +243,7 @@ sim_status retile(sim_model* h, Bucket& b, int team) {
   h->info.max_lds_bytes = 0;
   for (const auto& x : h->buckets) {
     h->info.n_tiles += x.n_tiles;
-    h->info.max_lds_bytes = std::max(h->info.max_lds_bytes, (int)std::max(adj_bytes(x.team, x.floats_adj),
+    h->info.max_lds_bytes = std::max(h->info.max_lds_bytes, (int)std::max(adj_bytes(h->M, x.team, x.floats_adj),
                                                                            fwd_bytes(h, x)));
   }
   return SIM_OK;
@@ -306,6 +321,7 @@ sim_status sim_init(const sim_model_desc* d, sim_handle* out) {
   M.beta = d->beta; M.gamma = d->gamma; M.spec = d->spec_margin; M.warm = d->warm;
   M.solve_mode = d->solve_mode; M.tol = d->tol; M.max_iters = d->max_iters;
   M.ws_kind = d->ws_kind; M.fb_iters = d->fb_iters; M.fb_tol = d->fb_tol;
+  M.ctrl = d->ctrl_kind == 1 ? 1 : 0;   // (before the LDS sizes: the controller adds a shared region)
 
   h->lam_off = P.lam_off;
   std::vector<int>& team_of = P.team_of;
@@ -331,7 +347,7 @@ sim_status sim_init(const sim_model_desc* d, sim_handle* out) {
     int team = std::max(team_of[e], d->min_team);
     if (team > 64) team = 64;
     auto need = [&](int t) {
-      return std::max(adj_bytes(t, adj_of[e]), fwd_bytes(M, t, fwd_of[e], P.ccap_of[e]));
+      return std::max(adj_bytes(M, t, adj_of[e]), fwd_bytes(M, t, fwd_of[e], P.ccap_of[e]));
     };
     while (team < 64 && need(team) > h->max_lds) team *= 2;
     if (need(team) > h->max_lds) {
@@ -370,7 +386,7 @@ sim_status sim_init(const sim_model_desc* d, sim_handle* out) {
       bk.floats_adj = std::max(bk.floats_adj, adj_of[ids[i]]);
       bk.ccap_max = std::max(bk.ccap_max, P.ccap_of[ids[i]]);
     }
-    max_lds = std::max(max_lds, (int)std::max(adj_bytes(team, bk.floats_adj),
+    max_lds = std::max(max_lds, (int)std::max(adj_bytes(M, team, bk.floats_adj),
                                               fwd_bytes(M, team, bk.floats_fwd, bk.ccap_max)));
     h->buckets.push_back(bk);
   }
@@ -424,6 +440,10 @@ sim_status sim_init(const sim_model_desc* d, sim_handle* out) {
                            {tape_du(M), no, tape_h2(M), n2, n1 * in + n1 + n2 * n1 + n2,
                             n1 * in + n1 + n2 * n1 + n2 + no * n2}};
     h->n_params = n1 * in + n1 + n2 * n1 + n2 + no * n2 + no;
+    if (hipMalloc((void**)&h->d_wt, sizeof(float) * (size_t)(n1 * in + n2 * n1 + no * n2)) != hipSuccess) {
+      release(h);
+      return fail(SIM_E_NOMEM, "hipMalloc failed");
+    }
     std::vector<WgradTile> tiles;
     std::vector<int> map(h->n_params, 0);
     for (int l = 0; l < 3; ++l) {
@@ -561,7 +581,7 @@ sim_status rollout(sim_handle h, const float* x0, const float* u, float* loss_en
   hipStream_t st = (hipStream_t)stream;
   RolloutArgs a{x0, u, loss_env, x_final, lam_final, ckpt, env_flags, nullptr, nullptr, RecArgs{nullptr, 0, nullptr, 0}};
   DevModel M = h->M;
-  M.W = u;
+  if (!prep_controls(h, M, u, st)) return check_device("rollout controls");
   return run_buckets(h, st, [&](size_t i, hipStream_t sx) { return bucket_rollout(h, i, M, a, sx); },
                      "rollout launch");
 }
@@ -582,7 +602,7 @@ sim_status rollout_solve(sim_handle h, const float* x0, const float* u, float* l
   RolloutArgs a{x0, u, loss_env, x_final, lam_final, nullptr, env_flags, iters_env, fallbacks_env,
                 RecArgs{records, (long long)rec_cap, (unsigned long long*)rec_count, records ? rec_every : 0}};
   DevModel M = h->M;
-  M.W = u;
+  if (!prep_controls(h, M, u, st)) return check_device("rollout_solve controls");
   return run_buckets(h, st, [&](size_t i, hipStream_t sx) { return bucket_rollout(h, i, M, a, sx); },
                      "rollout_solve launch");
 }
@@ -606,7 +626,7 @@ sim_status rollout_grad(sim_handle h, const float* x0, const float* u, const flo
   float* ws = (float*)workspace;
   GradArgs a{x0, u, ckpt, dloss_env, g_x0, g_u, g_inv_mass, g_inv_inertia, g_mu, g_damping, ws, env_flags};
   DevModel M = h->M;
-  M.W = u;
+  if (!prep_controls(h, M, u, st)) return check_device("rollout_grad controls");
   M.tape = ws + h->seg_floats;
   auto mark = [&](int k) { return !h->tev[k] || hipEventRecord(h->tev[k], st) == hipSuccess; };
   if (!mark(0)) return check_device("rollout_grad timing event");
@@ -759,7 +779,7 @@ int32_t sim_tune(sim_handle h, const float* x0, const float* u, int32_t with_gra
     return fail(SIM_E_NOMEM, "sim_tune: cannot allocate temporaries");
   }
   DevModel M = M0;
-  M.W = u;
+  if (!prep_controls(h, M, u, st)) { cleanup(); return check_device("sim_tune controls"); }
   M.tape = ws ? ws + h->seg_floats : nullptr;
   const RolloutArgs ra{x0, u, loss, nullptr, nullptr, ck, nullptr, nullptr, nullptr, RecArgs{nullptr, 0, nullptr, 0}};
   const GradArgs ga{x0, u, ck, dl, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, ws, nullptr};

@@ -22,7 +22,11 @@ struct WgradTile {
   int a_off, b_off, M, K, i0, k0;
 };
 
+// LDS floats after the env tiles for the controller's per-team offsets
+constexpr int CTRL_SHARED = 128;
+
 hipError_t launch_zero(int* p, int n, hipStream_t st);
+hipError_t launch_ctrl_transpose(const float* W, float* Wt, int in, int n1, int n2, int no, hipStream_t st);
 hipError_t launch_wgrad(const float* tape, int stride, int n_rows, int chunk, const WgradTile* tiles, int n_tiles,
                         float* partial, const int* map, int n_params, float* g, hipStream_t st);
 hipError_t launch_rollout(const DevModel& M, const TileSet& ts, int team, int grid, size_t lds,

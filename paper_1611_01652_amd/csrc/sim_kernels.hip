@@ -21,6 +21,9 @@ struct TeamGPU {
   int *cnt, *map;
   WsnNet net;
   uint16_t *H1, *H2;
+  // controller: per team, the offsets (from lds0) of its env's forward and
+  // adjoint controller regions
+  int* coff;
   __device__ void sync() const { __syncthreads(); }
   __device__ float team_max(float v) const {
     for (int o = ts >> 1; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, ts));
@@ -65,6 +68,104 @@ struct TeamGPU {
     return v;
   }
   __device__ bool team_any(bool p) const { return (__ballot((int)p) & mask) != 0ull; }
+
+  // ---- the controller's layers as matrix-core products over the wave's envs
+  // One layer for the envs 4g .. 4g+3 of the wave (team indices; fewer when
+  // the wave has fewer):
+  //   Y_r[n] = f(c[n] + sum_k X_r[k] B[k][n]),  n < N, k < K,
+  // with v_mfma_f32_4x4x1f32 (16 blocks of 4 x 4): each instruction adds one
+  // k for 4 envs x 64 outputs.  Lane l feeds A = X_(l%4)[k] (xa: the
+  // lane's env row in LDS) and B = B[k][n] for n = 64 p + l, and receives
+  // Y_r[64 p + l] for r = 0..3 in its 4 accumulators.  B: row-major [K][N]
+  // in global memory; c: bias (global) or none.  Post-op f: 0 identity,
+  // 1 tanh, 2 multiply by (1 - h^2) with h at lds0[hb[r] + n].  Output to
+  // lds0[yb[r] + n] for the envs with yb[r] >= 0.
+  __device__ void mfma_layer(const float* xa, int K, const float* B, int N, const float* c, const int* yb, int f,
+                             const int* hb) const {
+    for (int p0 = 0; p0 < N; p0 += 128) {
+      const int na = p0 + lane, nb = p0 + 64 + lane;
+      const bool va = na < N, vb = nb < N, two = p0 + 64 < N;
+      const float ca = (c && va) ? c[na] : 0.f, cb = (c && vb) ? c[nb] : 0.f;
+      floatx4 ya = {ca, ca, ca, ca}, yb2 = {cb, cb, cb, cb};
+      for (int k = 0; k < K; ++k) {
+        const float x = xa[k];
+        const float* Bk = B + (size_t)k * N;
+        ya = __builtin_amdgcn_mfma_f32_4x4x1f32(x, va ? Bk[na] : 0.f, ya, 0, 0, 0);
+        if (two) yb2 = __builtin_amdgcn_mfma_f32_4x4x1f32(x, vb ? Bk[nb] : 0.f, yb2, 0, 0, 0);
+      }
+      for (int r = 0; r < 4; ++r) {
+        if (yb[r] < 0) continue;
+        float y0 = ya[r], y1 = yb2[r];
+        if (f == 1) { y0 = tanhf(y0); y1 = tanhf(y1); }
+        if (f == 2) {
+          if (va) { const float h = lds0[hb[r] + na]; y0 *= 1.f - h * h; }
+          if (vb) { const float h = lds0[hb[r] + nb]; y1 *= 1.f - h * h; }
+        }
+        if (va) lds0[yb[r] + na] = y0;
+        if (two && vb) lds0[yb[r] + nb] = y1;
+      }
+    }
+  }
+  // the group's env offsets: region offset + o for envs present, -1 else
+  __device__ void ctrl_group(int g, int which, int o, int* out) const {
+    for (int r = 0; r < 4; ++r) {
+      const int e = 4 * g + r;
+      out[r] = e < n_teams ? coff[2 * e + which] + o : -1;
+    }
+  }
+  __device__ const float* ctrl_row(int g, int which, int o) const {
+    const int e = min(4 * g + (lane & 3), n_teams - 1);
+    return lds0 + coff[2 * e + which] + o;
+  }
+  // h1 = tanh(W1 s + b1), h2 = tanh(W2 h1 + b2), u = W3 h2 + b3 for every
+  // env of the wave; the forward products read the transposed weights
+  __device__ void ctrl_forward(const DevModel& M, const Env& E) const {
+    if (tl == 0) { coff[2 * team] = (int)(E.mlp() - lds0); coff[2 * team + 1] = (int)(E.mlpA() - lds0); }
+    __syncthreads();
+    const int in = M.mlp_in, n1 = M.mlp_h1, n2 = M.mlp_h2, no = M.mlp_out;
+    const float* b1 = M.W + n1 * in;
+    const float* b2 = b1 + n1 + n2 * n1;
+    const float* b3 = b2 + n2 + no * n2;
+    const float* Wt1 = M.Wt;
+    const float* Wt2 = Wt1 + in * n1;
+    const float* Wt3 = Wt2 + n1 * n2;
+    int yb[4];
+    for (int g = 0; 4 * g < n_teams; ++g) {
+      ctrl_group(g, 0, mo_h1(M), yb);
+      mfma_layer(ctrl_row(g, 0, 0), in, Wt1, n1, b1, yb, 1, nullptr);
+      __syncthreads();
+      ctrl_group(g, 0, mo_h2(M), yb);
+      mfma_layer(ctrl_row(g, 0, mo_h1(M)), n1, Wt2, n2, b2, yb, 1, nullptr);
+      __syncthreads();
+      ctrl_group(g, 0, mo_u(M), yb);
+      mfma_layer(ctrl_row(g, 0, mo_h2(M)), n2, Wt3, no, b3, yb, 0, nullptr);
+    }
+    __syncthreads();
+  }
+  // d2 = (W3^T du) (1 - h2^2), d1 = (W2^T d2) (1 - h1^2), sbar = W1^T d1 for
+  // every env of the wave (W rows are the K index: row-major W is B)
+  __device__ void ctrl_backward(const DevModel& M, const Env& E) const {
+    if (tl == 0) { coff[2 * team] = (int)(E.mlp() - lds0); coff[2 * team + 1] = (int)(E.mlpA() - lds0); }
+    __syncthreads();
+    const int in = M.mlp_in, n1 = M.mlp_h1, n2 = M.mlp_h2, no = M.mlp_out;
+    const float* W1 = M.W;
+    const float* W2 = W1 + n1 * in + n1;
+    const float* W3 = W2 + n2 * n1 + n2;
+    int yb[4], hb[4];
+    for (int g = 0; 4 * g < n_teams; ++g) {
+      ctrl_group(g, 1, mo_d2(M), yb);
+      ctrl_group(g, 0, mo_h2(M), hb);
+      mfma_layer(ctrl_row(g, 1, 0), no, W3, n2, nullptr, yb, 2, hb);
+      __syncthreads();
+      ctrl_group(g, 1, mo_d1(M), yb);
+      ctrl_group(g, 0, mo_h1(M), hb);
+      mfma_layer(ctrl_row(g, 1, mo_d2(M)), n2, W2, n1, nullptr, yb, 2, hb);
+      __syncthreads();
+      ctrl_group(g, 1, mo_sb(M), yb);
+      mfma_layer(ctrl_row(g, 1, mo_d1(M)), n1, W1, in, nullptr, yb, 0, nullptr);
+    }
+    __syncthreads();
+  }
   // the value of the other lane of this lane's pair (2m, 2m+1): a DPP
   // quad permutation [1, 0, 3, 2]; both lanes must be active
   __device__ float pair_swap(float v) const {
@@ -85,15 +186,22 @@ __device__ __forceinline__ TeamGPU make_team() {
   t.lds0 = nullptr;
   t.cnt = t.map = nullptr;
   t.H1 = t.H2 = nullptr;
+  t.coff = nullptr;
   return t;
 }
 
-// Shared region of the learned warm start after the env tiles: network
-// image, two activation tiles, per-team counts, contact list.
-__device__ __forceinline__ void setup_ws(TeamGPU& tm, const DevModel& M, float* lds, int env_floats) {
+// Shared region after the env tiles: the controller's per-team offsets
+// (CTRL_SHARED floats, with a controller), then for the learned warm start
+// (forward kernels) the network image, two activation tiles, per-team
+// counts and the contact list.
+__device__ __forceinline__ void setup_shared(TeamGPU& tm, const DevModel& M, float* lds, int env_floats, bool ws) {
   tm.lds0 = lds;
-  if (!M.ws_kind) return;
   float* sh = lds + tm.n_teams * env_floats;
+  if (M.ctrl) {
+    tm.coff = reinterpret_cast<int*>(sh);
+    sh += CTRL_SHARED;
+  }
+  if (!ws || !M.ws_kind) return;
   tm.net = wsn_net_at(sh);
   tm.H1 = reinterpret_cast<uint16_t*>(sh + WSN_NET_FLOATS);
   tm.H2 = tm.H1 + 16 * WSN_SH;
@@ -114,7 +222,7 @@ template <int TEAM, int SOLVE>
 __global__ __launch_bounds__(64) void k_rollout(DevModel M, TileSet ts, RolloutArgs a) {
   extern __shared__ float lds[];
   TeamGPU tm = make_team<TEAM>();
-  if (SOLVE) setup_ws(tm, M, lds, ts.env_floats);
+  setup_shared(tm, M, lds, ts.env_floats, SOLVE != 0);
   const int team = threadIdx.x / TEAM;
   constexpr int EPW = 64 / TEAM;
   for (int tile = next_tile(ts.queue); tile < ts.n_tiles; tile = next_tile(ts.queue)) {
@@ -130,7 +238,7 @@ template <int TEAM, int SOLVE>
 __global__ __launch_bounds__(64) void k_step(DevModel M, TileSet ts, StepArgs a) {
   extern __shared__ float lds[];
   TeamGPU tm = make_team<TEAM>();
-  if (SOLVE) setup_ws(tm, M, lds, ts.env_floats);
+  setup_shared(tm, M, lds, ts.env_floats, SOLVE != 0);
   const int team = threadIdx.x / TEAM;
   constexpr int EPW = 64 / TEAM;
   for (int tile = next_tile(ts.queue); tile < ts.n_tiles; tile = next_tile(ts.queue)) {
@@ -145,7 +253,8 @@ __global__ __launch_bounds__(64) void k_step(DevModel M, TileSet ts, StepArgs a)
 template <int TEAM>
 __global__ __launch_bounds__(64) void k_rollout_grad(DevModel M, TileSet ts, GradArgs a) {
   extern __shared__ float lds[];
-  const TeamGPU tm = make_team<TEAM>();
+  TeamGPU tm = make_team<TEAM>();
+  setup_shared(tm, M, lds, ts.env_floats, false);
   const int team = threadIdx.x / TEAM;
   constexpr int EPW = 64 / TEAM;
   for (int tile = next_tile(ts.queue); tile < ts.n_tiles; tile = next_tile(ts.queue)) {
@@ -163,7 +272,8 @@ __global__ __launch_bounds__(64) void k_rollout_grad(DevModel M, TileSet ts, Gra
 template <int TEAM>
 __global__ __launch_bounds__(64) void k_recompute(DevModel M, TileSet ts, GradArgs a) {
   extern __shared__ float lds[];
-  const TeamGPU tm = make_team<TEAM>();
+  TeamGPU tm = make_team<TEAM>();
+  setup_shared(tm, M, lds, ts.env_floats, false);
   const int team = threadIdx.x / TEAM;
   constexpr int EPW = 64 / TEAM;
   const int n_units = ts.n_tiles * ts.n_seg;
@@ -239,6 +349,28 @@ hipError_t launch_wgrad(const float* tape, int stride, int n_rows, int chunk, co
   }
   hipLaunchKernelGGL(k_wgrad_reduce, dim3((n_params + 255) / 256), dim3(256), 0, st, partial, n_chunks, n_tiles,
                      map, n_params, g);
+  return hipGetLastError();
+}
+
+// Transposed controller weights for the forward products: Wt_l[k][n] = W_l[n][k].
+__global__ void k_ctrl_transpose(const float* W, float* Wt, int in, int n1, int n2, int no) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  const int s1 = n1 * in, s2 = n2 * n1, s3 = no * n2;
+  if (p < s1) {
+    const int k = p / n1, n = p - k * n1;           // Wt1[k][n], k < in
+    Wt[p] = W[n * in + k];
+  } else if (p < s1 + s2) {
+    const int q = p - s1, k = q / n2, n = q - k * n2;   // Wt2[k][n], k < n1
+    Wt[p] = W[s1 + n1 + n * n1 + k];
+  } else if (p < s1 + s2 + s3) {
+    const int q = p - s1 - s2, k = q / no, n = q - k * no;   // Wt3[k][n], k < n2
+    Wt[p] = W[s1 + n1 + s2 + n2 + n * n2 + k];
+  }
+}
+hipError_t launch_ctrl_transpose(const float* W, float* Wt, int in, int n1, int n2, int no, hipStream_t st) {
+  const int n = n1 * in + n2 * n1 + no * n2;
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_ctrl_transpose, dim3((n + 255) / 256), dim3(256), 0, st, W, Wt, in, n1, n2, no);
   return hipGetLastError();
 }
 

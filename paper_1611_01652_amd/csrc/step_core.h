@@ -97,6 +97,7 @@ struct DevModel {
   int ctrl, mlp_in, mlp_h1, mlp_h2, mlp_out, tape_stride;
   const float* clock; // [T_max][2] sin, cos of 2 pi f t dt
   const float* W;     // weights (set per call)
+  const float* Wt;    // their transposes W1^T, W2^T, W3^T (made per call, device)
   float* tape;        // per env-step activations and deltas (reverse only)
   // solve to a residual tolerance (forward only) and learned warm start
   int solve_mode, max_iters, ws_kind, fb_iters;
@@ -241,8 +242,23 @@ struct Env {
   }
 };
 
-SHD int mlp_floats_fwd(const DevModel& M) { return M.ctrl ? M.mlp_in + M.mlp_h1 + M.mlp_h2 : 0; }
-SHD int mlp_floats_adj(const DevModel& M) { return M.ctrl ? M.mlp_out + M.mlp_h2 + M.mlp_h1 + M.mlp_in : 0; }
+// Controller LDS regions of an env, each array starting on a float4:
+//   forward  s[in], h1[h1], h2[h2], u[out]
+//   adjoint  du[out], d2[h2], d1[h1], sbar[in]
+SHD int mlp_fwd_floats(int in, int h1, int h2, int out) { return align4(in) + align4(h1) + align4(h2) + align4(out); }
+SHD int mlp_adj_floats(int in, int h1, int h2, int out) { return align4(out) + align4(h2) + align4(h1) + align4(in); }
+SHD int mlp_floats_fwd(const DevModel& M) {
+  return M.ctrl ? mlp_fwd_floats(M.mlp_in, M.mlp_h1, M.mlp_h2, M.mlp_out) : 0;
+}
+SHD int mlp_floats_adj(const DevModel& M) {
+  return M.ctrl ? mlp_adj_floats(M.mlp_in, M.mlp_h1, M.mlp_h2, M.mlp_out) : 0;
+}
+SHD int mo_h1(const DevModel& M) { return align4(M.mlp_in); }
+SHD int mo_h2(const DevModel& M) { return align4(M.mlp_in) + align4(M.mlp_h1); }
+SHD int mo_u(const DevModel& M) { return mo_h2(M) + align4(M.mlp_h2); }
+SHD int mo_d2(const DevModel& M) { return align4(M.mlp_out); }
+SHD int mo_d1(const DevModel& M) { return align4(M.mlp_out) + align4(M.mlp_h2); }
+SHD int mo_sb(const DevModel& M) { return mo_d1(M) + align4(M.mlp_h1); }
 SHD int vsave_floats(int ws_kind, int nb) { return ws_kind ? 6 * nb : 0; }
 // Floats of one step's saved working set: the forward LDS region, the sweep
 // history and the step-start angular velocities.
@@ -1140,8 +1156,6 @@ SHD void f_controls(const Team& tm, const DevModel& M, const Env& E, const float
     return;
   }
   float* sv_ = E.mlp();
-  float* h1 = sv_ + M.mlp_in;
-  float* h2 = h1 + M.mlp_h1;
   for (int j = tm.tl; j < nj; j += tm.ts) {
     const Sensor S = joint_sensor(E, j, nullptr, nullptr);
     sv_[j] = atan2f(S.y, S.x);
@@ -1151,33 +1165,13 @@ SHD void f_controls(const Team& tm, const DevModel& M, const Env& E, const float
     sv_[2 * E.nj] = M.clock[2 * t];
     sv_[2 * E.nj + 1] = M.clock[2 * t + 1];
   }
+  for (int k = M.mlp_in + tm.tl; k < align4(M.mlp_in); k += tm.ts) sv_[k] = 0.f;
   tm.sync();
-  const int in = M.mlp_in, n1 = M.mlp_h1, n2 = M.mlp_h2;
-  const float* W1 = M.W;
-  const float* b1 = W1 + n1 * in;
-  const float* W2 = b1 + n1;
-  const float* b2 = W2 + n2 * n1;
-  const float* W3 = b2 + n2;
-  const float* b3 = W3 + M.mlp_out * n2;
-  for (int i = tm.tl; i < (act ? n1 : 0); i += tm.ts) {
-    float a = b1[i];
-    for (int k = 0; k < in; ++k) a += W1[i * in + k] * sv_[k];
-    h1[i] = tanhf(a);
-  }
-  tm.sync();
-  for (int i = tm.tl; i < (act ? n2 : 0); i += tm.ts) {
-    float a = b2[i];
-    const float* w = W2 + i * n1;
-    for (int k = 0; k < n1; ++k) a += w[k] * h1[k];
-    h2[i] = tanhf(a);
-  }
-  tm.sync();
-  for (int i = tm.tl; i < nj; i += tm.ts) {
-    float a = b3[i];
-    const float* w = W3 + i * n2;
-    for (int k = 0; k < n2; ++k) a += w[k] * h2[k];
-    E.jc(i)[JU] = a;
-  }
+  // h1 = tanh(W1 s + b1), h2 = tanh(W2 h1 + b2), u = W3 h2 + b3 for every
+  // env of the wave at once (a team whose env is idle gets values it ignores)
+  tm.ctrl_forward(M, E);
+  const float* u = sv_ + mo_u(M);
+  for (int i = tm.tl; i < nj; i += tm.ts) E.jc(i)[JU] = u[i];
 }
 
 // Loss term of the state after step t (1-based) for the loss body.
@@ -2312,41 +2306,26 @@ SHD void a_controller(const Team& tm, const DevModel& M, const Env& E, bool act,
   if (!M.ctrl) return;
   const int in = M.mlp_in, n1 = M.mlp_h1, n2 = M.mlp_h2, no = M.mlp_out;
   const float* sv_ = E.mlp();
-  const float* h1 = sv_ + in;
-  const float* h2 = h1 + n1;
   float* du = E.mlpA();
-  float* d2 = du + no;
-  float* d1 = d2 + n2;
-  float* sb = d1 + n1;
-  const float* W1 = M.W;
-  const float* W2 = W1 + n1 * in + n1;
-  const float* W3 = W2 + n2 * n1 + n2;
+  const float* sb = du + mo_sb(M);
+  for (int k = no + tm.tl; k < align4(no); k += tm.ts) du[k] = 0.f;
   tm.sync();
-  for (int k = tm.tl; k < (act ? n2 : 0); k += tm.ts) {
-    float g = 0.f;
-    for (int i = 0; i < no; ++i) g += W3[i * n2 + k] * du[i];
-    d2[k] = g * (1.f - h2[k] * h2[k]);
-  }
-  tm.sync();
-  for (int k = tm.tl; k < (act ? n1 : 0); k += tm.ts) {
-    float g = 0.f;
-    for (int i = 0; i < n2; ++i) g += W2[i * n1 + k] * d2[i];
-    d1[k] = g * (1.f - h1[k] * h1[k]);
-  }
-  tm.sync();
-  for (int k = tm.tl; k < (act ? in : 0); k += tm.ts) {
-    float g = 0.f;
-    for (int i = 0; i < n1; ++i) g += W1[i * in + k] * d1[i];
-    sb[k] = g;
-  }
+  // d2 = (W3^T du) (1 - h2^2), d1 = (W2^T d2) (1 - h1^2), sbar = W1^T d1 for
+  // every env of the wave at once
+  tm.ctrl_backward(M, E);
   if (act) {
+    // tape row: s, h1, h2, du, d2, d1 (unpadded)
     float* row = M.tape + (size_t)(E.tape_off + t) * M.tape_stride;
     const int len = tape_d1(M) + n1;
     for (int k = tm.tl; k < len; k += tm.ts) {
       float v;
-      if (k < tape_du(M)) v = sv_[k];                 // s, h1, h2 are contiguous in LDS
+      if (k < tape_h1(M)) v = sv_[k];
+      else if (k < tape_h2(M)) v = sv_[mo_h1(M) + k - tape_h1(M)];
+      else if (k < tape_du(M)) v = sv_[mo_h2(M) + k - tape_h2(M)];
       else {
-        v = du[k - tape_du(M)];                       // du, d2, d1 are contiguous in LDS
+        if (k < tape_d2(M)) v = du[k - tape_du(M)];
+        else if (k < tape_d1(M)) v = du[mo_d2(M) + k - tape_d2(M)];
+        else v = du[mo_d1(M) + k - tape_d1(M)];
         a_predict_torques_flag(bad, v);
       }
       row[k] = v;

@@ -42,6 +42,52 @@ struct TeamHost {
   double team_max(double v) const { return v; }
   bool team_any(bool p) const { return p; }
   double pair_swap(double v) const { return v; }   // one-lane teams never pair
+  // the controller's layers in plain loops (the GPU does them as matrix-core
+  // products over the envs of a wave)
+  void ctrl_forward(const DevModel& M, const Env& E) const {
+    const int in = M.mlp_in, n1 = M.mlp_h1, n2 = M.mlp_h2, no = M.mlp_out;
+    const double *W1 = M.W, *b1 = W1 + n1 * in, *W2 = b1 + n1, *b2 = W2 + n2 * n1, *W3 = b2 + n2, *b3 = W3 + no * n2;
+    double* s = E.mlp();
+    double *h1 = s + mo_h1(M), *h2 = s + mo_h2(M), *u = s + mo_u(M);
+    for (int i = 0; i < n1; ++i) {
+      double a = b1[i];
+      for (int k = 0; k < in; ++k) a += W1[i * in + k] * s[k];
+      h1[i] = std::tanh(a);
+    }
+    for (int i = 0; i < n2; ++i) {
+      double a = b2[i];
+      for (int k = 0; k < n1; ++k) a += W2[i * n1 + k] * h1[k];
+      h2[i] = std::tanh(a);
+    }
+    for (int i = 0; i < no; ++i) {
+      double a = b3[i];
+      for (int k = 0; k < n2; ++k) a += W3[i * n2 + k] * h2[k];
+      u[i] = a;
+    }
+  }
+  void ctrl_backward(const DevModel& M, const Env& E) const {
+    const int in = M.mlp_in, n1 = M.mlp_h1, n2 = M.mlp_h2, no = M.mlp_out;
+    const double *W1 = M.W, *W2 = W1 + n1 * in + n1, *W3 = W2 + n2 * n1 + n2;
+    const double* s = E.mlp();
+    const double *h1 = s + mo_h1(M), *h2 = s + mo_h2(M);
+    double* du = E.mlpA();
+    double *d2 = du + mo_d2(M), *d1 = du + mo_d1(M), *sb = du + mo_sb(M);
+    for (int k = 0; k < n2; ++k) {
+      double g = 0.0;
+      for (int i = 0; i < no; ++i) g += W3[i * n2 + k] * du[i];
+      d2[k] = g * (1.0 - h2[k] * h2[k]);
+    }
+    for (int k = 0; k < n1; ++k) {
+      double g = 0.0;
+      for (int i = 0; i < n2; ++i) g += W2[i * n1 + k] * d2[i];
+      d1[k] = g * (1.0 - h1[k] * h1[k]);
+    }
+    for (int k = 0; k < in; ++k) {
+      double g = 0.0;
+      for (int i = 0; i < n1; ++i) g += W1[i * in + k] * d1[i];
+      sb[k] = g;
+    }
+  }
   int* shared_cnt() const { return cnt; }
   int* shared_map() const { return map; }
   // the network in plain loops, with the rounding of the matrix-core kernel
