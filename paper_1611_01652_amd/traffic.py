@@ -96,6 +96,18 @@ def summarize(workload, d, kernel="k_rollout_grad"):
                bytes_per_launch=(kf / sf + kw / sw) * 1024.0,
                fetch_bytes_per_launch=kf / sf * 1024.0, write_bytes_per_launch=kw / sw * 1024.0,
                kernel_source_hash=source_hash())
+    # the other kernels of the gradient and the forward, when the run has them
+    for other in ("k_recompute", "k_rollout<"):
+        try:
+            of, _, _ = per_dispatch(read_counters(os.path.join(d, f"pmc_{workload}_f"), "FETCH_SIZE"),
+                                    lambda k: other in k)
+            ow, _, _ = per_dispatch(read_counters(os.path.join(d, f"pmc_{workload}_w"), "WRITE_SIZE"),
+                                    lambda k: other in k)
+            out["other_kernels"] = out.get("other_kernels", {})
+            out["other_kernels"][other.rstrip("<")] = dict(fetch_bytes_per_launch=of / sf * 1024.0,
+                                                           write_bytes_per_launch=ow / sw * 1024.0)
+        except KeyError:
+            pass
     path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
     with open(path, "w") as fh:
         json.dump(out, fh, indent=1)
