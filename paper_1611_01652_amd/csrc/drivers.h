@@ -133,9 +133,11 @@ SHD_FLAT void env_single_step(const Team& tm, const DevModel& M, const Env& E, b
   }
 }
 
-// loss adjoint into pbar of the loss body for the state after step t1 (1-based)
-SHD void loss_adj(const DevModel& M, const Env& E, int t1, const float* p, float dl, float* pbar) {
-  const float* tg = M.target + 3 * E.e;
+// loss adjoint into pbar of the loss body for the state after step t1
+// (1-based); tg: the env's target (held in registers by the caller: a global
+// load inside the step loop would wait for the reverse sweep's in-flight
+// fetches)
+SHD void loss_adj(const DevModel& M, const Env& E, int t1, const float* p, const float* tg, float dl, float* pbar) {
   if (M.loss_kind == 0) {
     if (t1 != E.T) return;
     for (int k = 0; k < 3; ++k)
@@ -170,7 +172,7 @@ SHD void save_step(const Team& tm, const DevModel& M, const Env& E, float* dst) 
 // Copy n4 float4 from global memory to LDS, skipping float4 [s0, s1): each
 // lane issues LOAD_BATCH loads before it waits for the first, so a copy costs
 // a few memory round trips instead of one per float4.
-constexpr int LOAD_BATCH = 8;
+constexpr int LOAD_BATCH = 16;
 template <class Team>
 SHD void copy_to_lds(const Team& tm, float* dst, const float* src, int n4, int s0 = 0, int s1 = 0) {
   for (int i0 = tm.tl; i0 < n4; i0 += LOAD_BATCH * tm.ts) {
@@ -257,7 +259,10 @@ SHD_FLAT void env_recompute(const Team& tm, const DevModel& M, const Env& E, boo
     for (int k = 0; k < 3; ++k) seg[(size_t)T * sstride + k] = E.body(E.lb)[BP + k];
 }
 
-template <class Team>
+// SAVED: the working sets are saved (segment or trajectory mode, M.dump !=
+// DUMP_REPLAY), else replayed; a separate instantiation each, so neither
+// carries the other's code.
+template <bool SAVED, class Team>
 SHD_FLAT void env_rollout_grad(const Team& tm, const DevModel& M, const Env& E, bool valid, const GradArgs& a) {
   if (valid) {
     load_env_static(tm, M, E);
@@ -270,10 +275,13 @@ SHD_FLAT void env_rollout_grad(const Team& tm, const DevModel& M, const Env& E, 
   const int K = M.ckpt_every;
   const int T = valid ? E.T : 0;
   const float dl = valid ? a.dloss[E.e] : 0.f;
+  float tg[3] = {0.f, 0.f, 0.f};
+  if (valid)
+    for (int k = 0; k < 3; ++k) tg[k] = M.target[3 * E.e + k];
   const int nseg = (T + K - 1) / K;
-  const bool traj = M.dump == DUMP_TRAJECTORY;
-  const int sstride = !valid ? 0 : (M.dump != DUMP_REPLAY ? dump_stride_of(E.lay.total_fwd, M.n_iters, E.nslot, E.nb)
-                                                          : 18 * E.nb + E.lam_size);
+  const bool traj = SAVED && M.dump == DUMP_TRAJECTORY;
+  const int sstride = !valid ? 0 : (SAVED ? dump_stride_of(E.lay.total_fwd, M.n_iters, E.nslot, E.nb)
+                                          : 18 * E.nb + E.lam_size);
   float* seg = valid ? a.seg + E.seg_base() : nullptr;
   // zero the control gradient rows beyond T (and all rows of idle envs)
   if (valid && a.g_u && !M.ctrl)
@@ -290,7 +298,7 @@ SHD_FLAT void env_rollout_grad(const Team& tm, const DevModel& M, const Env& E, 
     // each step's working set after its sweeps; in trajectory mode it is done
     for (int t = t0; !traj && tm.any(t < t1); ++t) {
       const bool act = t < t1;
-      if (M.dump == DUMP_SEGMENT) {
+      if (SAVED) {
         replay_to_sweeps(tm, M, E, a, act, t, E.hist(0), true);
         if (act) save_step(tm, M, E, seg + (size_t)(t - t0) * sstride);
         tm.sync();   // the copy reads bodies and rows that integration rewrites
@@ -309,12 +317,12 @@ SHD_FLAT void env_rollout_grad(const Team& tm, const DevModel& M, const Env& E, 
     }
     tm.sync();
     if (sact && sg == nseg - 1 && tm.tl == 0 && M.loss_kind != 1)
-      loss_adj(M, E, T, traj ? seg + (size_t)T * sstride : E.body(E.lb) + BP, dl, E.bodyA(E.lb) + AP);
+      loss_adj(M, E, T, traj ? seg + (size_t)T * sstride : E.body(E.lb) + BP, tg, dl, E.bodyA(E.lb) + AP);
     tm.sync();
     // reverse the segment's steps
     for (int t = t1 - 1; tm.any(t >= t0 && sact); --t) {
       const bool act = sact && t >= t0;
-      if (M.dump != DUMP_REPLAY) {
+      if (SAVED) {
         // the saved working set of step t replaces its replay
         if (act) load_step(tm, M, E, seg + (size_t)(traj ? t : t - t0) * sstride);
         tm.sync();
@@ -332,7 +340,7 @@ SHD_FLAT void env_rollout_grad(const Team& tm, const DevModel& M, const Env& E, 
       if (act && tm.tl == 0 && M.loss_kind == 1) {
         const float* B = E.body(E.lb);
         const float p1[3] = {B[BP] + M.dt * B[BV], B[BP + 1] + M.dt * B[BV + 1], B[BP + 2] + M.dt * B[BV + 2]};
-        loss_adj(M, E, t + 1, p1, dl, E.bodyA(E.lb) + AP);
+        loss_adj(M, E, t + 1, p1, tg, dl, E.bodyA(E.lb) + AP);
       }
       a_clear_step(tm, E, act);
       tm.sync();

@@ -250,7 +250,7 @@ __global__ __launch_bounds__(64) void k_step(DevModel M, TileSet ts, StepArgs a)
   }
 }
 
-template <int TEAM>
+template <int TEAM, int SAVED>
 __global__ __launch_bounds__(64) void k_rollout_grad(DevModel M, TileSet ts, GradArgs a) {
   extern __shared__ float lds[];
   TeamGPU tm = make_team<TEAM>();
@@ -261,7 +261,7 @@ __global__ __launch_bounds__(64) void k_rollout_grad(DevModel M, TileSet ts, Gra
     const int ie = ts.envs[tile * EPW + team];
     const bool valid = ie >= 0;
     Env E = make_env(M, valid ? ie : 0, lds + team * ts.env_floats, M.n_iters, true);
-    env_rollout_grad(tm, M, E, valid, a);
+    env_rollout_grad<SAVED != 0>(tm, M, E, valid, a);
     __syncthreads();
   }
 }
@@ -429,7 +429,8 @@ hipError_t launch_step(const DevModel& M, const TileSet& ts, int team, int grid,
 }
 hipError_t launch_rollout_grad(const DevModel& M, const TileSet& ts, int team, int grid, size_t lds,
                                const GradArgs& a, hipStream_t st) {
-  SIM_DISPATCH(team, k_rollout_grad, a)
+  if (M.dump != DUMP_REPLAY) { SIM_DISPATCH_S(team, k_rollout_grad, a, 1) }
+  SIM_DISPATCH_S(team, k_rollout_grad, a, 0)
 }
 hipError_t launch_recompute(const DevModel& M, const TileSet& ts, int team, int grid, size_t lds,
                             const GradArgs& a, hipStream_t st) {
@@ -462,7 +463,8 @@ hipError_t allow_large_lds(int bytes) {
   SIM_ALLOW_S(k_rollout, 1)
   SIM_ALLOW_S(k_step, 0)
   SIM_ALLOW_S(k_step, 1)
-  SIM_ALLOW(k_rollout_grad)
+  SIM_ALLOW_S(k_rollout_grad, 0)
+  SIM_ALLOW_S(k_rollout_grad, 1)
   SIM_ALLOW(k_recompute)
 #undef SIM_ALLOW
 #undef SIM_ALLOW_S

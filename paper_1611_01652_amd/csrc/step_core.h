@@ -790,14 +790,15 @@ template <class Team>
 SHD void f_warm(const Team& tm, const Env& E, bool act) {
   const int nl = n_live(E, act);
   for (int ci = 0; tm.any(ci < nl); ++ci) {
-    const int c = ci < nl ? live_col(E, ci) : 0;
-    const int n = ci < nl ? E.act_cnt()[c] : 0;
-    const int lo = ci < nl ? E.colstart(c) : 0;
+    i4 pl{0, 0, 0, 0};
+    if (ci < nl) pl = E.plan()[ci];
+    const int n = pl.y, lo = pl.x;
     for (int k = tm.tl; k < n; k += tm.ts) {
-      const int s = E.act_slot()[lo + k];
+      const i4 v = E.vis()[lo + k];
+      const int s = v.x;
       if (s < 0) continue;
-      const int code = E.act_code()[lo + k];
-      const RowB rb = cand_bodies(E, code);
+      const int code = v.w;
+      const RowB rb{v.y == E.nb ? -1 : v.y, v.z};
       const int nr = cand_kind(code) == K_JOINT ? 5 : 3;
       Vel V;
       vel_load(V, E, rb.a, rb.b);
@@ -1102,13 +1103,14 @@ template <class Team>
 SHD void f_store(const Team& tm, const Env& E, bool act) {
   const int nl = n_live(E, act);
   for (int ci = 0; tm.any(ci < nl); ++ci) {
-    const int c = ci < nl ? live_col(E, ci) : 0;
-    const int n = ci < nl ? E.act_cnt()[c] : 0;
-    const int lo = ci < nl ? E.colstart(c) : 0;
+    i4 pl{0, 0, 0, 0};
+    if (ci < nl) pl = E.plan()[ci];
+    const int n = pl.y, lo = pl.x;
     for (int k = tm.tl; k < n; k += tm.ts) {
-      const int s = E.act_slot()[lo + k];
+      const i4 v = E.vis()[lo + k];
+      const int s = v.x;
       if (s < 0) continue;
-      const int code = E.act_code()[lo + k];
+      const int code = v.w;
       float* w = E.ws() + E.store_of(code);
       if (cand_kind(code) == K_JOINT) {
         for (int q = 0; q < 5; ++q) w[q] = E.row(s + q)[RL];
@@ -1579,13 +1581,14 @@ template <class Team>
 SHD void a_store(const Team& tm, const Env& E, bool act) {
   const int nl = n_live(E, act);
   for (int ci = 0; tm.any(ci < nl); ++ci) {
-    const int c = ci < nl ? live_col(E, ci) : 0;
-    const int n = ci < nl ? E.act_cnt()[c] : 0;
-    const int lo = ci < nl ? E.colstart(c) : 0;
+    i4 pl{0, 0, 0, 0};
+    if (ci < nl) pl = E.plan()[ci];
+    const int n = pl.y, lo = pl.x;
     for (int k = tm.tl; k < n; k += tm.ts) {
-      const int s = E.act_slot()[lo + k];
+      const i4 v = E.vis()[lo + k];
+      const int s = v.x;
       if (s < 0) continue;
-      const int code = E.act_code()[lo + k];
+      const int code = v.w;
       float* wA = E.wsA() + E.store_of(code);
       if (cand_kind(code) == K_JOINT) {
         for (int q = 0; q < 5; ++q) E.rowA(s + q)[QL] = wA[q];
@@ -1981,14 +1984,15 @@ template <class Team>
 SHD void a_warm(const Team& tm, const DevModel& M, const Env& E, bool act) {
   const int nl = n_live(E, act);
   for (int ci = nl - 1; tm.any(ci >= 0); --ci) {
-    const int c = ci >= 0 ? live_col(E, ci) : 0;
-    const int n = ci >= 0 ? E.act_cnt()[c] : 0;
-    const int lo = ci >= 0 ? E.colstart(c) : 0;
+    i4 pl{0, 0, 0, 0};
+    if (ci >= 0) pl = E.plan()[ci];
+    const int n = pl.y, lo = pl.x;
     for (int k = tm.tl; k < n; k += tm.ts) {
-      const int s = E.act_slot()[lo + k];
+      const i4 v = E.vis()[lo + k];
+      const int s = v.x;
       if (s < 0) continue;
-      const int code = E.act_code()[lo + k];
-      const RowB rb = cand_bodies(E, code);
+      const int code = v.w;
+      const RowB rb{v.y == E.nb ? -1 : v.y, v.z};
       const bool ha = rb.a >= 0;
       const int nr = cand_kind(code) == K_JOINT ? 5 : 3;
       VelA A;
@@ -2200,13 +2204,14 @@ template <class Team>
 SHD void a_rows(const Team& tm, const DevModel& M, const Env& E, bool act) {
   const int nl = n_live(E, act);
   for (int ci = nl - 1; tm.any(ci >= 0); --ci) {
-    const int c = ci >= 0 ? live_col(E, ci) : 0;
-    const int n = ci >= 0 ? E.act_cnt()[c] : 0;
-    const int lo = ci >= 0 ? E.colstart(c) : 0;
+    i4 pl{0, 0, 0, 0};
+    if (ci >= 0) pl = E.plan()[ci];
+    const int n = pl.y, lo = pl.x;
     for (int k = tm.tl; k < n; k += tm.ts) {
-      const int s = E.act_slot()[lo + k];
+      const i4 v = E.vis()[lo + k];
+      const int s = v.x;
       if (s < 0) continue;
-      const int code = E.act_code()[lo + k];
+      const int code = v.w;
       if (cand_kind(code) == K_JOINT) a_joint(M, E, cand_idx(code), s);
       else a_contact(M, E, code, s);
     }

@@ -193,7 +193,8 @@ int kh_rollout_grad(const sim_model_desc* d, const double* x0, const double* u, 
       std::fill(lds.begin(), lds.end(), std::nan(""));
     }
     Env EA = make_env(h.M, ie, lds.data(), h.M.n_iters, true);
-    env_rollout_grad(tm, h.M, EA, true, ga);
+    if (h.M.dump != DUMP_REPLAY) env_rollout_grad<true>(tm, h.M, EA, true, ga);
+    else env_rollout_grad<false>(tm, h.M, EA, true, ga);
   }
   if (h.M.ctrl) {
     // dL/dW: the same contraction the GPU does with MFMA, in plain loops
