@@ -133,13 +133,18 @@ enum { AP = 0, AR = 3, AV = 12, AW = 15, AIW = 18, AIM = 27, AII = 28, ATQ = 31,
        ATM = 37, ATI = 38, ACM = 41, ACI = 42, BSA = 48 };
 // joint constants
 enum { JAP = 0, JAC = 3, JXP = 6, JXC = 9, JUP = 12, JUC = 15, JD = 18, JU = 19, JS = 20 };
-// row slot; a contact uses 4 slots: normal, tangent 1, tangent 2, extras
-enum { RJL = 0, RJA = 3, RJB = 6, RWA = 9, RWB = 12, RM = 15, RBI = 16, RL = 17, RL0 = 18, RS = 20 };
+// row slot; a contact uses 4 slots: normal, tangent 1, tangent 2, extras.
+// Each body's part of the row is two aligned float4: (Ja, m) (Wa, bias) for
+// body a and (Jb, m) (Wb, bias) for body b, so a lane that handles one body
+// reads its part with two 16-byte loads; m and bias are kept in both
+// (RMA, RBA: the copies of body a's part).  Then (Jl, lambda), lambda0.
+enum { RJA = 0, RMA = 3, RWA = 4, RBA = 7, RJB = 8, RM = 11, RWB = 12, RBI = 15, RJL = 16, RL = 19, RL0 = 20, RS = 24 };
 // contact extras slot: tangents, friction mass, gap, store offset, code, and
 // (tolerance mode) the warm-start features XF[7] and network outputs XY[3]
 enum { XT1 = 0, XT2 = 3, XMT = 6, XGAP = 7, XSTORE = 8, XCODE = 9, XF = 10, XY = 17 };
-// row adjoint slot
-enum { QJL = 0, QJA = 3, QJB = 6, QWA = 9, QWB = 12, QM = 15, QB = 16, QL = 17, RSA = 20 };
+// row adjoint slot, in the same shape: (Ja-bar, -) (Wa-bar, -) (Jb-bar, m-bar)
+// (Wb-bar, bias-bar) (Jl-bar, lambda-bar)
+enum { QJA = 0, QWA = 4, QJB = 8, QM = 11, QWB = 12, QB = 15, QJL = 16, QL = 19, RSA = 20 };
 
 // Sweep plan entries (16 bytes, one LDS load): per live colour (start in the
 // active list, count, 1 for a colour of hinges, -); per active constraint
@@ -535,7 +540,7 @@ SHD void build_joint(const DevModel& M, const Env& E, int j, int s) {
     st3(r + RJL, e);
     st3(r + RJA, cross(e, ra));
     st3(r + RJB, cross(rb, e));
-    r[RBI] = kb * ev[q];
+    r[RBI] = r[RBA] = kb * ev[q];
   }
   f3 na = ld3(C + JXP), ua = ld3(C + JUP);
   f3 t2 = cross(na, ua);
@@ -548,13 +553,13 @@ SHD void build_joint(const DevModel& M, const Env& E, int j, int s) {
     st3(r + RJL, mk3(0.f, 0.f, 0.f));
     st3(r + RJA, -tk);
     st3(r + RJB, tk);
-    r[RBI] = kb * dot(tk, ax);
+    r[RBI] = r[RBA] = kb * dot(tk, ax);
   }
   const int st = 5 * j;
   for (int q = 0; q < 5; ++q) {
     float* r = E.row(s + q);
     const float K = row_finish(r, Ba, Bb, a >= 0);
-    r[RM] = 1.f / (K + M.gamma);
+    r[RM] = r[RMA] = 1.f / (K + M.gamma);
     const float l0 = M.warm * E.ws()[st + q];
     r[RL] = l0;
     r[RL0] = l0;
@@ -629,17 +634,17 @@ SHD void build_contact(const DevModel& M, const Env& E, int code, int s, const C
   *reinterpret_cast<int*>(x + XSTORE) = st;
   *reinterpret_cast<int*>(x + XCODE) = code;
   float* rn = E.row(s);
-  rn[RM] = 1.f / (K[0] + M.gamma);
-  rn[RBI] = (g.gap > 0.f ? g.gap : M.beta * g.gap) / M.dt;
+  rn[RM] = rn[RMA] = 1.f / (K[0] + M.gamma);
+  rn[RBI] = rn[RBA] = (g.gap > 0.f ? g.gap : M.beta * g.gap) / M.dt;
   const float* w = E.ws() + st;
   const f3 Lt = mk3(w[1], w[2], w[3]);
   rn[RL] = rn[RL0] = M.warm * w[0];
   E.row(s + 1)[RL] = E.row(s + 1)[RL0] = M.warm * dot(t1, Lt);
   E.row(s + 2)[RL] = E.row(s + 2)[RL0] = M.warm * dot(t2, Lt);
-  E.row(s + 1)[RM] = x[XMT];
-  E.row(s + 2)[RM] = x[XMT];
-  E.row(s + 1)[RBI] = 0.f;
-  E.row(s + 2)[RBI] = 0.f;
+  E.row(s + 1)[RM] = E.row(s + 1)[RMA] = x[XMT];
+  E.row(s + 2)[RM] = E.row(s + 2)[RMA] = x[XMT];
+  E.row(s + 1)[RBI] = E.row(s + 1)[RBA] = 0.f;
+  E.row(s + 2)[RBI] = E.row(s + 2)[RBA] = 0.f;
 }
 
 // F4: per colour, test candidates, compact the active ones, build rows.
@@ -861,12 +866,12 @@ SHD void vr_store_ab(const VR& V, const Env& E, int a, int b) {
 // One row slot in registers: Jl, Ja, Jb, Wa, Wb, m, bias, lam (lam0 not needed).
 struct RR { float jl[3], ja[3], jb[3], wa[3], wb[3], m, bias, lam; };
 SHD void rr_load(RR& R, const float* p) {
-  const f4 a = ld4(p), b = ld4(p + 4), c = ld4(p + 8), d = ld4(p + 12), e = ld4(p + 16);
-  R.jl[0] = a.x; R.jl[1] = a.y; R.jl[2] = a.z; R.ja[0] = a.w;
-  R.ja[1] = b.x; R.ja[2] = b.y; R.jb[0] = b.z; R.jb[1] = b.w;
-  R.jb[2] = c.x; R.wa[0] = c.y; R.wa[1] = c.z; R.wa[2] = c.w;
-  R.wb[0] = d.x; R.wb[1] = d.y; R.wb[2] = d.z; R.m = d.w;
-  R.bias = e.x; R.lam = e.y;
+  const f4 a = ld4(p + RJA), b = ld4(p + RWA), c = ld4(p + RJB), d = ld4(p + RWB), e = ld4(p + RJL);
+  R.ja[0] = a.x; R.ja[1] = a.y; R.ja[2] = a.z;
+  R.wa[0] = b.x; R.wa[1] = b.y; R.wa[2] = b.z;
+  R.jb[0] = c.x; R.jb[1] = c.y; R.jb[2] = c.z; R.m = c.w;
+  R.wb[0] = d.x; R.wb[1] = d.y; R.wb[2] = d.z; R.bias = d.w;
+  R.jl[0] = e.x; R.jl[1] = e.y; R.jl[2] = e.z; R.lam = e.w;
 }
 SHD float rr_jv(const RR& R, const VR& V, bool ha) {
   float s = R.jl[0] * V.vb[0] + R.jl[1] * V.vb[1] + R.jl[2] * V.vb[2];
@@ -898,8 +903,8 @@ SHD void rr_apply(const RR& R, VR& V, bool ha, float ima, float imb, float d) {
 // leaf (sg = +-1 times a value), so both forms give the same bits: results do
 // not depend on the team width.  The adjoint of Jl, a constant, is skipped.
 struct HS { float v[3], w[3]; };  // a side's body velocity (or its adjoint)
-struct HR { float j[3], W[3]; };  // a side's angular Jacobian part and W = I^-1 j
-struct HQ { float j[3], W[3]; };  // a side's adjoint accumulators of j and W
+struct HR { float j[3], W[3], m, bias; };  // a side's angular Jacobian part, W = I^-1 j, and the row's m and bias
+struct HQ { float j[3], W[3], m, b; };     // a side's adjoint accumulators of j and W (and, side b, of m and bias)
 
 SHD void hs_load(HS& x, const float* p) {   // p: v(3), w(3), 16-byte aligned
   const f4 q = ld4(p);
@@ -909,21 +914,24 @@ SHD void hs_store(const HS& x, float* p) {
   f4 q; q.x = x.v[0]; q.y = x.v[1]; q.z = x.v[2]; q.w = x.w[0];
   st4(p, q); p[4] = x.w[1]; p[5] = x.w[2];
 }
-// side 1: body b, side 0: body a
+// side 1: body b, side 0: body a; two 16-byte loads or stores each
 SHD void hr_load(HR& r, const float* row, int side) {
-  const float* j = row + (side ? RJB : RJA);
-  const float* W = row + (side ? RWB : RWA);
-  for (int k = 0; k < 3; ++k) { r.j[k] = j[k]; r.W[k] = W[k]; }
+  const f4 a = ld4(row + (side ? RJB : RJA)), b = ld4(row + (side ? RWB : RWA));
+  r.j[0] = a.x; r.j[1] = a.y; r.j[2] = a.z; r.m = a.w;
+  r.W[0] = b.x; r.W[1] = b.y; r.W[2] = b.z; r.bias = b.w;
 }
 SHD void hq_load(HQ& q, const float* rowA, int side) {
-  const float* j = rowA + (side ? QJB : QJA);
-  const float* W = rowA + (side ? QWB : QWA);
-  for (int k = 0; k < 3; ++k) { q.j[k] = j[k]; q.W[k] = W[k]; }
+  const f4 a = ld4(rowA + (side ? QJB : QJA)), b = ld4(rowA + (side ? QWB : QWA));
+  q.j[0] = a.x; q.j[1] = a.y; q.j[2] = a.z; q.m = a.w;
+  q.W[0] = b.x; q.W[1] = b.y; q.W[2] = b.z; q.b = b.w;
 }
+// (side a's slots for m-bar and bias-bar are padding: what is written there is unused)
 SHD void hq_store(const HQ& q, float* rowA, int side) {
-  float* j = rowA + (side ? QJB : QJA);
-  float* W = rowA + (side ? QWB : QWA);
-  for (int k = 0; k < 3; ++k) { j[k] = q.j[k]; W[k] = q.W[k]; }
+  f4 a, b;
+  a.x = q.j[0]; a.y = q.j[1]; a.z = q.j[2]; a.w = q.m;
+  b.x = q.W[0]; b.y = q.W[1]; b.z = q.W[2]; b.w = q.b;
+  st4(rowA + (side ? QJB : QJA), a);
+  st4(rowA + (side ? QWB : QWA), b);
 }
 // The sides of a visit held by this lane: index i has side sd[i] (1 = b),
 // body bd[i], sign sg[i], inverse mass im[i] and signed inverse mass sim[i].
@@ -993,7 +1001,7 @@ SHD void hinge_fwd(const Team& tm, const DevModel& M, const Env& E, int s, int a
   for (int q = 0; q < 5; ++q) {
     const float* R = E.row(s + q);
     for (int i = 0; i < NS; ++i) hr_load(r[q][i], R, sd.sd[i]);
-    m[q] = R[RM]; bias[q] = R[RBI]; lam[q] = R[RL];
+    m[q] = r[q][0].m; bias[q] = r[q][0].bias; lam[q] = R[RL];
   }
   const bool wr = sd.writer(tm);
   float* Hw = (H && wr) ? H + s : nullptr;
@@ -1673,21 +1681,21 @@ SHD void a_integrate(const Team& tm, const DevModel& M, const Env& E, bool act) 
 // Row adjoint accumulators in registers (layout of a row adjoint slot).
 struct QR { float jl[3], ja[3], jb[3], wa[3], wb[3], m, b, l; };
 SHD void qr_load(QR& Q, const float* p) {
-  const f4 a = ld4(p), b = ld4(p + 4), c = ld4(p + 8), d = ld4(p + 12), e = ld4(p + 16);
-  Q.jl[0] = a.x; Q.jl[1] = a.y; Q.jl[2] = a.z; Q.ja[0] = a.w;
-  Q.ja[1] = b.x; Q.ja[2] = b.y; Q.jb[0] = b.z; Q.jb[1] = b.w;
-  Q.jb[2] = c.x; Q.wa[0] = c.y; Q.wa[1] = c.z; Q.wa[2] = c.w;
-  Q.wb[0] = d.x; Q.wb[1] = d.y; Q.wb[2] = d.z; Q.m = d.w;
-  Q.b = e.x; Q.l = e.y;
+  const f4 a = ld4(p + QJA), b = ld4(p + QWA), c = ld4(p + QJB), d = ld4(p + QWB), e = ld4(p + QJL);
+  Q.ja[0] = a.x; Q.ja[1] = a.y; Q.ja[2] = a.z;
+  Q.wa[0] = b.x; Q.wa[1] = b.y; Q.wa[2] = b.z;
+  Q.jb[0] = c.x; Q.jb[1] = c.y; Q.jb[2] = c.z; Q.m = c.w;
+  Q.wb[0] = d.x; Q.wb[1] = d.y; Q.wb[2] = d.z; Q.b = d.w;
+  Q.jl[0] = e.x; Q.jl[1] = e.y; Q.jl[2] = e.z; Q.l = e.w;
 }
 SHD void qr_store(const QR& Q, float* p) {
   f4 a, b, c, d, e;
-  a.x = Q.jl[0]; a.y = Q.jl[1]; a.z = Q.jl[2]; a.w = Q.ja[0];
-  b.x = Q.ja[1]; b.y = Q.ja[2]; b.z = Q.jb[0]; b.w = Q.jb[1];
-  c.x = Q.jb[2]; c.y = Q.wa[0]; c.z = Q.wa[1]; c.w = Q.wa[2];
-  d.x = Q.wb[0]; d.y = Q.wb[1]; d.z = Q.wb[2]; d.w = Q.m;
-  e.x = Q.b; e.y = Q.l; e.z = 0.f; e.w = 0.f;
-  st4(p, a); st4(p + 4, b); st4(p + 8, c); st4(p + 12, d); st4(p + 16, e);
+  a.x = Q.ja[0]; a.y = Q.ja[1]; a.z = Q.ja[2]; a.w = 0.f;
+  b.x = Q.wa[0]; b.y = Q.wa[1]; b.z = Q.wa[2]; b.w = 0.f;
+  c.x = Q.jb[0]; c.y = Q.jb[1]; c.z = Q.jb[2]; c.w = Q.m;
+  d.x = Q.wb[0]; d.y = Q.wb[1]; d.z = Q.wb[2]; d.w = Q.b;
+  e.x = Q.jl[0]; e.y = Q.jl[1]; e.z = Q.jl[2]; e.w = Q.l;
+  st4(p + QJA, a); st4(p + QWA, b); st4(p + QJB, c); st4(p + QWB, d); st4(p + QJL, e);
 }
 SHD void vra_load(VR& A, const Env& E, int a, int b) {
   const float* Bb = E.bodyA(b) + AV;   // vbar(3), wbar(3) contiguous, 16-byte aligned
@@ -1831,8 +1839,11 @@ SHD void h_rev_load(const Env& E, const HSides<NS>& sd, int slot, const float* H
     hr_load(r[i], R, sd.sd[i]);
     hq_load(q[i], Q, sd.sd[i]);
   }
-  c.m = R[RM]; c.bias = R[RBI];
-  c.qm = Q[QM]; c.qb = Q[QB]; c.ql = Q[QL];
+  // m and bias from this lane's part; the m and bias adjoints are side b's
+  // (index 0 is side b in a one-lane visit; a lane of a pair that holds side a
+  // computes nothing from them)
+  c.m = r[0].m; c.bias = r[0].bias;
+  c.qm = q[0].m; c.qb = q[0].b; c.ql = Q[QL];
   c.lt = H[slot];
   c.lp = Hp ? Hp[slot] : R[RL0];
 }
@@ -1867,8 +1878,12 @@ SHD void hinge_rev(const Team& tm, const DevModel& M, const Env& E, int s, int a
     else if (q == 1) h_row_rev<1, NS>(tm, rc, qc, x, A, sd, imx, cc, M.gamma);
     else h_row_rev<0, NS>(tm, rc, qc, x, A, sd, imx, cc, M.gamma);
     float* Q = E.rowA(s + q);
-    for (int i = 0; i < NS; ++i) hq_store(qc[i], Q, sd.sd[i]);
-    if (wr) { Q[QM] = cc.qm; Q[QB] = cc.qb; Q[QL] = cc.ql; }
+    for (int i = 0; i < NS; ++i) {
+      qc[i].m = cc.qm;
+      qc[i].b = cc.qb;
+      hq_store(qc[i], Q, sd.sd[i]);
+    }
+    if (wr) Q[QL] = cc.ql;
     if (q > 0) {
       for (int i = 0; i < NS; ++i) { rc[i] = rn[i]; qc[i] = qn[i]; }
       cc = cn;
