@@ -2074,37 +2074,70 @@ SHD void a_row_finish(const Env& E, const float* r, float* q, int a, int b, floa
   add3(q + QJL, (2.f * Kb * im) * jl);
 }
 
-// Adjoint of build_joint.
+// Adjoint of build_joint.  The five rows' row_finish adjoints (see
+// a_row_finish) are accumulated in registers and added to the bodies once;
+// the rows' Jacobian adjoints stay in registers for the geometry below (the
+// adjoint of Jl, a constant for a hinge, is not formed).
+SHD void outer_acc(float* O, f3 a, f3 b) {
+  O[0] += a.x * b.x; O[1] += a.x * b.y; O[2] += a.x * b.z;
+  O[3] += a.y * b.x; O[4] += a.y * b.y; O[5] += a.y * b.z;
+  O[6] += a.z * b.x; O[7] += a.z * b.y; O[8] += a.z * b.z;
+}
 SHD void a_joint(const DevModel& M, const Env& E, int j, int s) {
   const float* C = E.jc(j);
   const int a = E.jpar(j), b = E.jchi(j);
+  const bool ha = a >= 0;
   const float* Bb = E.body(b);
-  const float* Ba = a >= 0 ? E.body(a) : nullptr;
+  const float* Ba = ha ? E.body(a) : nullptr;
   float* Ab = E.bodyA(b);
-  float* Aa = a >= 0 ? E.bodyA(a) : nullptr;
+  float* Aa = ha ? E.bodyA(a) : nullptr;
+  f3 qja[5], qjb[5];
+  float qbias[5];
+  float Ob[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  float Oa[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  float imb_bar = 0.f, ima_bar = 0.f;
   for (int q = 0; q < 5; ++q) {
     const float* r = E.row(s + q);
-    float* qa = E.rowA(s + q);
+    const float* qa = E.rowA(s + q);
     const float m = r[RM];
-    a_row_finish(E, r, qa, a, b, -m * m * qa[QM]);
+    const float Kb = -m * m * qa[QM];
+    const f3 jl = ld3(r + RJL), jb = ld3(r + RJB);
+    const float jl2 = dot(jl, jl);
+    // Jb: W = Iw Jb, K += Jb.W  ->  Jbbar += Iw (Wbar + 2 Kb Jb); Iwbar += (Wbar + Kb Jb) Jb^T
+    imb_bar += Kb * jl2;
+    const f3 wbb = ld3(qa + QWB);
+    qjb[q] = ld3(qa + QJB) + sv(Bb + BI, wbb + (2.f * Kb) * jb);
+    outer_acc(Ob, wbb + Kb * jb, jb);
+    qja[q] = ld3(qa + QJA);
+    if (ha) {
+      const f3 ja = ld3(r + RJA);
+      ima_bar += Kb * jl2;
+      const f3 wab = ld3(qa + QWA);
+      qja[q] = qja[q] + sv(Ba + BI, wab + (2.f * Kb) * ja);
+      outer_acc(Oa, wab + Kb * ja, ja);
+    }
+    qbias[q] = qa[QB];
+  }
+  Ab[AIM] += imb_bar;
+  for (int k = 0; k < 9; ++k) Ab[AIW + k] += Ob[k];
+  if (ha) {
+    Aa[AIM] += ima_bar;
+    for (int k = 0; k < 9; ++k) Aa[AIW + k] += Oa[k];
   }
   const float kb = M.beta / M.dt;
   const f3 rbl = ld3(C + JAC), ral = ld3(C + JAP);
-  const f3 rb = mv(Bb + BR, rbl);
-  const f3 ra = a >= 0 ? mv(Ba + BR, ral) : mk3(0.f, 0.f, 0.f);
   f3 rbb = mk3(0.f, 0.f, 0.f), rab = mk3(0.f, 0.f, 0.f), errb = mk3(0.f, 0.f, 0.f);
   for (int q = 0; q < 3; ++q) {
-    const float* qa = E.rowA(s + q);
     const f3 e = mk3(q == 0 ? 1.f : 0.f, q == 1 ? 1.f : 0.f, q == 2 ? 1.f : 0.f);
     // Ja = e x ra ; Jb = rb x e
-    rab = rab + cross(ld3(qa + QJA), e);
-    rbb = rbb + cross(e, ld3(qa + QJB));
-    errb = errb + (kb * qa[QB]) * e;
+    rab = rab + cross(qja[q], e);
+    rbb = rbb + cross(e, qjb[q]);
+    errb = errb + (kb * qbias[q]) * e;
   }
   add3(Ab + AP, errb);
   rbb = rbb + errb;
   add_outer(Ab + AR, rbb, rbl);
-  if (a >= 0) {
+  if (ha) {
     add3(Aa + AP, -errb);
     rab = rab - errb;
     add_outer(Aa + AR, rab, ral);
@@ -2114,23 +2147,22 @@ SHD void a_joint(const DevModel& M, const Env& E, int j, int s) {
   const f3 t2l = cross(na, ua);
   f3 t2 = t2l;
   const f3 nal = na, ual = ua;
-  if (a >= 0) { na = mv(Ba + BR, na); ua = mv(Ba + BR, ua); t2 = mv(Ba + BR, t2); }
+  if (ha) { na = mv(Ba + BR, na); ua = mv(Ba + BR, ua); t2 = mv(Ba + BR, t2); }
   const f3 nbl = ld3(C + JXC);
   const f3 nbw = mv(Bb + BR, nbl);
   const f3 ax = cross(na, nbw);
   f3 axb = mk3(0.f, 0.f, 0.f), tb[2];
   for (int q = 0; q < 2; ++q) {
-    const float* qa = E.rowA(s + 3 + q);
-    const float cb = kb * qa[QB];
+    const float cb = kb * qbias[3 + q];
     const f3 tk = q == 0 ? ua : t2;
-    tb[q] = ld3(qa + QJB) - ld3(qa + QJA) + cb * ax;
+    tb[q] = qjb[3 + q] - qja[3 + q] + cb * ax;
     axb = axb + cb * tk;
   }
   // ax = na x nbw
   const f3 nab = cross(nbw, axb);
   const f3 nbb = cross(axb, na);
   add_outer(Ab + AR, nbb, nbl);
-  if (a >= 0) {
+  if (ha) {
     add_outer(Aa + AR, nab, nal);
     add_outer(Aa + AR, tb[0], ual);
     add_outer(Aa + AR, tb[1], t2l);
