@@ -251,7 +251,7 @@ __global__ __launch_bounds__(64) void k_step(DevModel M, TileSet ts, StepArgs a)
 }
 
 template <int TEAM, int SAVED>
-__global__ __launch_bounds__(64) void k_rollout_grad(DevModel M, TileSet ts, GradArgs a) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_rollout_grad(DevModel M, TileSet ts, GradArgs a) {
   extern __shared__ float lds[];
   TeamGPU tm = make_team<TEAM>();
   setup_shared(tm, M, lds, ts.env_floats, false);
@@ -270,7 +270,7 @@ __global__ __launch_bounds__(64) void k_rollout_grad(DevModel M, TileSet ts, Gra
 // segments of all tiles at once, each team recomputing one segment of one env
 // from its checkpoint with the forward LDS layout.
 template <int TEAM>
-__global__ __launch_bounds__(64) void k_recompute(DevModel M, TileSet ts, GradArgs a) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_recompute(DevModel M, TileSet ts, GradArgs a) {
   extern __shared__ float lds[];
   TeamGPU tm = make_team<TEAM>();
   setup_shared(tm, M, lds, ts.env_floats, false);

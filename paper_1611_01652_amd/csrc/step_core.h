@@ -186,6 +186,7 @@ SHD Lay make_lay(int nb, int nj, int G, int P, int ncol, int ncand, int nslot, i
   if (adj) {
     L.bodyA = o; o += align4((nb + 1) * BSA);
     L.rowsA = o; o += align4(nslot * RSA);
+    o += align4(nslot);   // hist(-1): the sweeps' start impulses (reverse only)
     L.hist = o; o += align4(n_iters * nslot);
     L.wsA = o; o += align4(lam);
     L.jA = o; o += align4(2 * nj);   // damping adjoint total and compensation
@@ -772,11 +773,12 @@ struct SweepCursor {
     if (k == 0) return vc;
     return E.vis()[pc.x + l0(tm, pc) + k * stride(tm, pc)];
   }
-  // constraints of the current colour this lane takes part in
+  // constraints of the current colour this lane takes part in (the stride
+  // is a power of two, as team widths are, so the quotient is a shift)
   template <class Team>
   SHD int count(const Team& tm) const {
-    const int n = left > 0 ? pc.y : 0, i = l0(tm, pc), st = stride(tm, pc);
-    return i < n ? (n - i + st - 1) / st : 0;
+    const int n = left > 0 ? pc.y : 0, i = l0(tm, pc), sh = __builtin_ctz(stride(tm, pc));
+    return i < n ? (n - i + (1 << sh) - 1) >> sh : 0;
   }
   SHD void advance(const i4& vn, const i4& p2) {
     if (cn == (DIR > 0 ? 0 : nl - 1)) it += DIR;
@@ -914,44 +916,46 @@ SHD void hs_store(const HS& x, float* p) {
   f4 q; q.x = x.v[0]; q.y = x.v[1]; q.z = x.v[2]; q.w = x.w[0];
   st4(p, q); p[4] = x.w[1]; p[5] = x.w[2];
 }
-// side 1: body b, side 0: body a; two 16-byte loads or stores each
-SHD void hr_load(HR& r, const float* row, int side) {
-  const f4 a = ld4(row + (side ? RJB : RJA)), b = ld4(row + (side ? RWB : RWA));
+// Side b's part of a row or row adjoint sits HSIDE floats after side a's, so
+// a lane addresses its side as (row + HSIDE * side) + the side-a offset.
+constexpr int HSIDE = RJB - RJA;
+static_assert(RWB - RWA == HSIDE && QJB - QJA == HSIDE && QWB - QWA == HSIDE, "side layout");
+// p: a row + HSIDE * side (side 1: body b, side 0: body a); two 16-byte loads or stores each
+SHD void hr_load(HR& r, const float* p) {
+  const f4 a = ld4(p + RJA), b = ld4(p + RWA);
   r.j[0] = a.x; r.j[1] = a.y; r.j[2] = a.z; r.m = a.w;
   r.W[0] = b.x; r.W[1] = b.y; r.W[2] = b.z; r.bias = b.w;
 }
-SHD void hq_load(HQ& q, const float* rowA, int side) {
-  const f4 a = ld4(rowA + (side ? QJB : QJA)), b = ld4(rowA + (side ? QWB : QWA));
+SHD void hq_load(HQ& q, const float* p) {
+  const f4 a = ld4(p + QJA), b = ld4(p + QWA);
   q.j[0] = a.x; q.j[1] = a.y; q.j[2] = a.z; q.m = a.w;
   q.W[0] = b.x; q.W[1] = b.y; q.W[2] = b.z; q.b = b.w;
 }
 // (side a's slots for m-bar and bias-bar are padding: what is written there is unused)
-SHD void hq_store(const HQ& q, float* rowA, int side) {
+SHD void hq_store(const HQ& q, float* p) {
   f4 a, b;
   a.x = q.j[0]; a.y = q.j[1]; a.z = q.j[2]; a.w = q.m;
   b.x = q.W[0]; b.y = q.W[1]; b.z = q.W[2]; b.w = q.b;
-  st4(rowA + (side ? QJB : QJA), a);
-  st4(rowA + (side ? QWB : QWA), b);
+  st4(p + QJA, a);
+  st4(p + QWA, b);
 }
 // The sides of a visit held by this lane: index i has side sd[i] (1 = b),
 // body bd[i], sign sg[i], inverse mass im[i] and signed inverse mass sim[i].
 template <int NS>
 struct HSides {
-  int sd[NS], bd[NS];
+  int sd[NS], bd[NS], so[NS];   // so: HSIDE * sd
   float sg[NS], im[NS], sim[NS];
   template <class Team>
   SHD void init(const Team& tm, const Env& E, int a, int b) {
     for (int i = 0; i < NS; ++i) {
       sd[i] = NS == 2 ? 1 - i : (tm.tl & 1);
       bd[i] = sd[i] ? b : a;
+      so[i] = HSIDE * sd[i];
       sg[i] = sd[i] ? 1.f : -1.f;
       im[i] = E.body(bd[i])[BIM];
       sim[i] = sg[i] * im[i];
     }
   }
-  // this lane writes the visit's shared outputs (the b side)
-  template <class Team>
-  SHD bool writer(const Team& tm) const { return NS == 2 || (tm.tl & 1); }
 };
 // part b + part a: both in this lane, or this lane's part and its partner's
 template <int NS, class Team>
@@ -998,20 +1002,20 @@ SHD void hinge_fwd(const Team& tm, const DevModel& M, const Env& E, int s, int a
   for (int i = 0; i < NS; ++i) hs_load(x[i], E.body(sd.bd[i]) + BV);
   HR r[5][NS];
   float m[5], bias[5], lam[5];
+  float* R0 = E.row(s);
   for (int q = 0; q < 5; ++q) {
-    const float* R = E.row(s + q);
-    for (int i = 0; i < NS; ++i) hr_load(r[q][i], R, sd.sd[i]);
-    m[q] = r[q][0].m; bias[q] = r[q][0].bias; lam[q] = R[RL];
+    for (int i = 0; i < NS; ++i) hr_load(r[q][i], R0 + sd.so[i] + q * RS);
+    m[q] = r[q][0].m; bias[q] = r[q][0].bias; lam[q] = R0[q * RS + RL];
   }
-  const bool wr = sd.writer(tm);
-  float* Hw = (H && wr) ? H + s : nullptr;
+  // The rows' impulses are the same in both lanes of a pair (they are formed
+  // from the same sums in the same order), so both lanes store them.
+  float* Hw = H ? H + s : nullptr;
   h_row_fwd<0, NS>(tm, M, r[0], x, sd, m[0], bias[0], lam[0], Hw ? Hw : nullptr, rmax);
   h_row_fwd<1, NS>(tm, M, r[1], x, sd, m[1], bias[1], lam[1], Hw ? Hw + 1 : nullptr, rmax);
   h_row_fwd<2, NS>(tm, M, r[2], x, sd, m[2], bias[2], lam[2], Hw ? Hw + 2 : nullptr, rmax);
   h_row_fwd<3, NS>(tm, M, r[3], x, sd, m[3], bias[3], lam[3], Hw ? Hw + 3 : nullptr, rmax);
   h_row_fwd<3, NS>(tm, M, r[4], x, sd, m[4], bias[4], lam[4], Hw ? Hw + 4 : nullptr, rmax);
-  if (wr)
-    for (int q = 0; q < 5; ++q) E.row(s + q)[RL] = lam[q];
+  for (int q = 0; q < 5; ++q) R0[q * RS + RL] = lam[q];
   for (int i = 0; i < NS; ++i) hs_store(x[i], E.body(sd.bd[i]) + BV);
 }
 
@@ -1569,6 +1573,11 @@ template <class Team>
 SHD void a_clear_step(const Team& tm, const Env& E, bool act) {
   const int ns = act ? E.nslot * RSA : 0;
   for (int i = tm.tl; i < ns; i += tm.ts) E.L[E.lay.rowsA + i] = 0.f;
+  // hist(-1) = the start impulses, so that in the reversed sweeps a hinge
+  // row's impulse before its update is the previous sweep's record in every
+  // sweep, the first included
+  const int nsl = act ? E.nslot : 0;
+  for (int s = tm.tl; s < nsl; s += tm.ts) E.hist(-1)[s] = E.row(s)[RL0];
   // the world slot's adjoint is a sink of the sweeps: cleared every step so
   // that it stays finite (it only ever meets zero inverse masses)
   if (act)
@@ -1830,27 +1839,31 @@ SHD void h_row_rev(const Team& tm, const HR* r, HQ* q, HS* x, HS* A, const HSide
   }
   c.ql = -wv + ltb + gamma * sb;
 }
+// Row q of a visit whose first row is at R0 / Q0 (row slots and adjoint
+// slots) and whose records start at H and Hp.
 template <int NS>
-SHD void h_rev_load(const Env& E, const HSides<NS>& sd, int slot, const float* H, const float* Hp, HR* r, HQ* q,
-                    HRow& c) {
-  const float* R = E.row(slot);
-  const float* Q = E.rowA(slot);
+SHD void h_rev_load(const HSides<NS>& sd, const float* R0, const float* Q0, int q, const float* H, const float* Hp,
+                    HR* r, HQ* qa, HRow& c) {
+  const float* R = R0 + q * RS;
+  const float* Q = Q0 + q * RSA;
   for (int i = 0; i < NS; ++i) {
-    hr_load(r[i], R, sd.sd[i]);
-    hq_load(q[i], Q, sd.sd[i]);
+    hr_load(r[i], R + sd.so[i]);
+    hq_load(qa[i], Q + sd.so[i]);
   }
   // m and bias from this lane's part; the m and bias adjoints are side b's
   // (index 0 is side b in a one-lane visit; a lane of a pair that holds side a
   // computes nothing from them)
   c.m = r[0].m; c.bias = r[0].bias;
-  c.qm = q[0].m; c.qb = q[0].b; c.ql = Q[QL];
-  c.lt = H[slot];
-  c.lp = Hp ? Hp[slot] : R[RL0];
+  c.qm = qa[0].m; c.qb = qa[0].b; c.ql = Q[QL];
+  c.lt = H[q];
+  c.lp = Hp[q];
 }
 
 // Reverse of one hinge visit (rows 4..0).  Row data and row adjoint
 // accumulators are streamed: row q-1 is loaded while row q is reversed.
-// a: body index or the world slot (whose adjoint slot is a sink).
+// a: body index or the world slot (whose adjoint slot is a sink).  H: this
+// sweep's records, Hp: the previous sweep's (the start impulses before the
+// first sweep).
 template <int NS, class Team>
 SHD void hinge_rev(const Team& tm, const DevModel& M, const Env& E, int s, int a, int b, const float* H,
                    const float* Hp) {
@@ -1863,31 +1876,35 @@ SHD void hinge_rev(const Team& tm, const DevModel& M, const Env& E, int s, int a
     hs_load(A[i], E.bodyA(sd.bd[i]) + AV);
     imx[i] = 0.f;
   }
-  const bool wr = sd.writer(tm);
-  HR rc[NS];
-  HQ qc[NS];
-  HRow cc;
-  h_rev_load<NS>(E, sd, s + 4, H, Hp, rc, qc, cc);
+  const float* R0 = E.row(s);
+  float* Q0 = E.rowA(s);
+  const float* Hs = H + s;
+  const float* Hps = Hp + s;
+  // Rows are loaded AH rows ahead of their reversal: a lane of a pair holds
+  // all five rows from the start of the visit (one LDS round trip), a
+  // one-lane visit (two sides per lane) streams them one row ahead.
+  constexpr int AH = NS == 1 ? 5 : 1;
+  HR rr[5][NS];
+  HQ qq[5][NS];
+  HRow cr[5];
+#pragma unroll
+  for (int q = 4; q > 4 - AH; --q) h_rev_load<NS>(sd, R0, Q0, q, Hs, Hps, rr[q], qq[q], cr[q]);
+#pragma unroll
   for (int q = 4; q >= 0; --q) {
-    HR rn[NS];
-    HQ qn[NS];
-    HRow cn;
-    if (q > 0) h_rev_load<NS>(E, sd, s + q - 1, H, Hp, rn, qn, cn);
-    if (q >= 3) h_row_rev<3, NS>(tm, rc, qc, x, A, sd, imx, cc, M.gamma);
-    else if (q == 2) h_row_rev<2, NS>(tm, rc, qc, x, A, sd, imx, cc, M.gamma);
-    else if (q == 1) h_row_rev<1, NS>(tm, rc, qc, x, A, sd, imx, cc, M.gamma);
-    else h_row_rev<0, NS>(tm, rc, qc, x, A, sd, imx, cc, M.gamma);
-    float* Q = E.rowA(s + q);
+    if (q - AH >= 0) h_rev_load<NS>(sd, R0, Q0, q - AH, Hs, Hps, rr[q - AH], qq[q - AH], cr[q - AH]);
+    HRow& cc = cr[q];
+    if (q >= 3) h_row_rev<3, NS>(tm, rr[q], qq[q], x, A, sd, imx, cc, M.gamma);
+    else if (q == 2) h_row_rev<2, NS>(tm, rr[q], qq[q], x, A, sd, imx, cc, M.gamma);
+    else if (q == 1) h_row_rev<1, NS>(tm, rr[q], qq[q], x, A, sd, imx, cc, M.gamma);
+    else h_row_rev<0, NS>(tm, rr[q], qq[q], x, A, sd, imx, cc, M.gamma);
+    // (the row-shared adjoints are the same in both lanes of a pair)
+    float* Q = Q0 + q * RSA;
     for (int i = 0; i < NS; ++i) {
-      qc[i].m = cc.qm;
-      qc[i].b = cc.qb;
-      hq_store(qc[i], Q, sd.sd[i]);
+      qq[q][i].m = cc.qm;
+      qq[q][i].b = cc.qb;
+      hq_store(qq[q][i], Q + sd.so[i]);
     }
-    if (wr) Q[QL] = cc.ql;
-    if (q > 0) {
-      for (int i = 0; i < NS; ++i) { rc[i] = rn[i]; qc[i] = qn[i]; }
-      cc = cn;
-    }
+    Q[QL] = cc.ql;
   }
   for (int i = 0; i < NS; ++i) {
     hs_store(x[i], E.body(sd.bd[i]) + BV);
@@ -1976,12 +1993,12 @@ SHD void a_pgs(const Team& tm, const DevModel& M, const Env& E, bool act) {
     i4 vn, p2;
     sw.prefetch(tm, E, vn, p2);
     const float* H = E.hist(sw.it);
-    const float* Hp = sw.it > 0 ? E.hist(sw.it - 1) : nullptr;
+    const float* Hp = E.hist(sw.it - 1);
     const int nk = sw.count(tm);
     for (int k = 0; k < nk; ++k) {
       const i4 v = sw.entry(tm, E, k);
       if (v.x < 0) continue;
-      if (cand_kind(v.w) != K_JOINT) rev_contact(M, E, v.x, v.y, v.z, mu, H, Hp, gmu);
+      if (cand_kind(v.w) != K_JOINT) rev_contact(M, E, v.x, v.y, v.z, mu, H, sw.it > 0 ? Hp : nullptr, gmu);
       else if (tm.ts >= 2) hinge_rev<1>(tm, M, E, v.x, v.y, v.z, H, Hp);
       else hinge_rev<2>(tm, M, E, v.x, v.y, v.z, H, Hp);
     }
