@@ -52,6 +52,12 @@ SHD float dot(f3 a, f3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
 SHD f3 cross(f3 a, f3 b) { return mk3(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x); }
 SHD f3 ld3(const float* p) { return mk3(p[0], p[1], p[2]); }
 SHD void st3(float* p, f3 v) { p[0] = v.x; p[1] = v.y; p[2] = v.z; }
+// 16-byte vector for batched LDS access (ds_read_b128 / ds_write_b128)
+struct alignas(16) f4 { float x, y, z, w; };
+SHD f4 ld4(const float* p) { return *reinterpret_cast<const f4*>(p); }
+SHD void st4(float* p, f4 v) { *reinterpret_cast<f4*>(p) = v; }
+struct alignas(8) f2 { float x, y; };
+SHD void st2(float* p, f2 v) { *reinterpret_cast<f2*>(p) = v; }
 SHD void add3(float* p, f3 v) { p[0] += v.x; p[1] += v.y; p[2] += v.z; }
 // R (row-major 9) times v, and R^T times v
 SHD f3 mv(const float* R, f3 v) {
@@ -523,46 +529,73 @@ SHD void f_predict(const Team& tm, const DevModel& M, const Env& E, bool act) {
   }
 }
 
-// Build the rows of one joint into slots s..s+4.
+// Build the rows of one joint into slots s..s+4.  Each row is formed in
+// registers (W = M^-1 J^T, K = J W, m = 1 / (K + gamma), as row_finish forms
+// them, in the same order) and written with 16-byte stores.
+static_assert(RMA == RJA + 3 && RBA == RWA + 3 && RM == RJB + 3 && RBI == RWB + 3 && RL == RJL + 3 &&
+                  RJA % 4 == 0 && RWA % 4 == 0 && RJB % 4 == 0 && RWB % 4 == 0 && RJL % 4 == 0,
+              "row slot layout");
 SHD void build_joint(const DevModel& M, const Env& E, int j, int s) {
   const float* C = E.jc(j);
   const int a = E.jpar(j), b = E.jchi(j);
+  const bool ha = a >= 0;
   const float* Bb = E.body(b);
-  const float* Ba = a >= 0 ? E.body(a) : nullptr;
+  const float* Ba = ha ? E.body(a) : nullptr;
+  float Ib[6], Ia[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  for (int k = 0; k < 6; ++k) Ib[k] = Bb[BI + k];
+  if (ha)
+    for (int k = 0; k < 6; ++k) Ia[k] = Ba[BI + k];
+  const float imb = Bb[BIM], ima = ha ? Ba[BIM] : 0.f;
   const f3 rb = mv(Bb + BR, ld3(C + JAC));
   f3 ra = mk3(0.f, 0.f, 0.f), Pa = ld3(C + JAP);
-  if (a >= 0) { ra = mv(Ba + BR, Pa); Pa = ld3(Ba + BP) + ra; }
+  if (ha) { ra = mv(Ba + BR, Pa); Pa = ld3(Ba + BP) + ra; }
   const f3 err = (ld3(Bb + BP) + rb) - Pa;
   const float kb = M.beta / M.dt;
   const float ev[3] = {err.x, err.y, err.z};
-  for (int q = 0; q < 3; ++q) {
-    float* r = E.row(s + q);
-    const f3 e = mk3(q == 0 ? 1.f : 0.f, q == 1 ? 1.f : 0.f, q == 2 ? 1.f : 0.f);
-    st3(r + RJL, e);
-    st3(r + RJA, cross(e, ra));
-    st3(r + RJB, cross(rb, e));
-    r[RBI] = r[RBA] = kb * ev[q];
-  }
   f3 na = ld3(C + JXP), ua = ld3(C + JUP);
   f3 t2 = cross(na, ua);
-  if (a >= 0) { na = mv(Ba + BR, na); ua = mv(Ba + BR, ua); t2 = mv(Ba + BR, t2); }
+  if (ha) { na = mv(Ba + BR, na); ua = mv(Ba + BR, ua); t2 = mv(Ba + BR, t2); }
   const f3 nbw = mv(Bb + BR, ld3(C + JXC));
   const f3 ax = cross(na, nbw);
-  for (int q = 0; q < 2; ++q) {
-    float* r = E.row(s + 3 + q);
-    const f3 tk = q == 0 ? ua : t2;
-    st3(r + RJL, mk3(0.f, 0.f, 0.f));
-    st3(r + RJA, -tk);
-    st3(r + RJB, tk);
-    r[RBI] = r[RBA] = kb * dot(tk, ax);
-  }
-  const int st = 5 * j;
+  const float* w0 = E.ws() + 5 * j;
   for (int q = 0; q < 5; ++q) {
+    f3 jl, ja, jb;
+    float bias;
+    if (q < 3) {
+      const f3 e = mk3(q == 0 ? 1.f : 0.f, q == 1 ? 1.f : 0.f, q == 2 ? 1.f : 0.f);
+      jl = e;
+      ja = cross(e, ra);
+      jb = cross(rb, e);
+      bias = kb * ev[q];
+    } else {
+      const f3 tk = q == 3 ? ua : t2;
+      jl = mk3(0.f, 0.f, 0.f);
+      ja = -tk;
+      jb = tk;
+      bias = kb * dot(tk, ax);
+    }
+    const f3 wb = sv(Ib, jb);
+    float im = imb;
+    float K = dot(jb, wb);
+    f3 wa = mk3(0.f, 0.f, 0.f);
+    if (ha) {
+      wa = sv(Ia, ja);
+      K += dot(ja, wa);
+      im += ima;
+    } else {
+      // no body a: both of its parts are zero (the world slot's velocity is
+      // zero, so these rows act on body b alone)
+      ja = mk3(0.f, 0.f, 0.f);
+    }
+    K = K + im * dot(jl, jl);
+    const float m = 1.f / (K + M.gamma);
+    const float l0 = M.warm * w0[q];
     float* r = E.row(s + q);
-    const float K = row_finish(r, Ba, Bb, a >= 0);
-    r[RM] = r[RMA] = 1.f / (K + M.gamma);
-    const float l0 = M.warm * E.ws()[st + q];
-    r[RL] = l0;
+    st4(r + RJA, f4{ja.x, ja.y, ja.z, m});
+    st4(r + RWA, f4{wa.x, wa.y, wa.z, bias});
+    st4(r + RJB, f4{jb.x, jb.y, jb.z, m});
+    st4(r + RWB, f4{wb.x, wb.y, wb.z, bias});
+    st4(r + RJL, f4{jl.x, jl.y, jl.z, l0});
     r[RL0] = l0;
   }
 }
@@ -820,10 +853,6 @@ SHD void f_warm(const Team& tm, const Env& E, bool act) {
   }
 }
 
-// 16-byte vector for batched LDS access (ds_read_b128 / ds_write_b128)
-struct alignas(16) f4 { float x, y, z, w; };
-SHD f4 ld4(const float* p) { return *reinterpret_cast<const f4*>(p); }
-SHD void st4(float* p, f4 v) { *reinterpret_cast<f4*>(p) = v; }
 
 // Velocities of a constraint's two bodies in registers.
 struct VR { float va[3], wa[3], vb[3], wb[3]; };
@@ -1571,8 +1600,12 @@ SHD void row_unapply(const float* r, Vel& V, bool ha, float ima, float imb, floa
 // Clear the per-step adjoint accumulators (rows, body extras).
 template <class Team>
 SHD void a_clear_step(const Team& tm, const Env& E, bool act) {
-  const int ns = act ? E.nslot * RSA : 0;
-  for (int i = tm.tl; i < ns; i += tm.ts) E.L[E.lay.rowsA + i] = 0.f;
+  // row adjoints and the world slot's adjoint with 16-byte stores (both
+  // regions start on a float4 boundary and span whole float4)
+  static_assert(RSA % 4 == 0 && BSA % 4 == 0, "float4 spans");
+  const f4 z{0.f, 0.f, 0.f, 0.f};
+  const int ns4 = act ? E.nslot * (RSA / 4) : 0;
+  for (int i = tm.tl; i < ns4; i += tm.ts) st4(E.rowA(0) + 4 * i, z);
   // hist(-1) = the start impulses, so that in the reversed sweeps a hinge
   // row's impulse before its update is the previous sweep's record in every
   // sweep, the first included
@@ -1580,14 +1613,19 @@ SHD void a_clear_step(const Team& tm, const Env& E, bool act) {
   for (int s = tm.tl; s < nsl; s += tm.ts) E.hist(-1)[s] = E.row(s)[RL0];
   // the world slot's adjoint is a sink of the sweeps: cleared every step so
   // that it stays finite (it only ever meets zero inverse masses)
-  if (act)
-    for (int i = tm.tl; i < BSA; i += tm.ts) E.bodyA(E.nb)[i] = 0.f;
+  const int nw4 = act ? BSA / 4 : 0;
+  for (int i = tm.tl; i < nw4; i += tm.ts) st4(E.bodyA(E.nb) + 4 * i, z);
+  // per body: the inverse-inertia, inverse-mass and torque adjoints, floats
+  // AIW .. ATQ + 2, one 8-byte, three 16-byte and one 8-byte store
+  static_assert(AIW % 4 == 2 && AIM == AIW + 9 && AII == AIM + 1 && ATQ == AII + 3, "body adjoint layout");
   const int nb = act ? E.nb : 0;
   for (int b = tm.tl; b < nb; b += tm.ts) {
     float* A = E.bodyA(b);
-    for (int k = 0; k < 9; ++k) A[AIW + k] = 0.f;
-    A[ATQ] = A[ATQ + 1] = A[ATQ + 2] = 0.f;
-    A[AIM] = A[AII] = A[AII + 1] = A[AII + 2] = 0.f;
+    st2(A + AIW, f2{0.f, 0.f});
+    st4(A + AIW + 2, z);
+    st4(A + AIW + 6, z);
+    st4(A + AIW + 10, z);
+    st2(A + AIW + 14, f2{0.f, 0.f});
   }
 }
 
