@@ -384,13 +384,16 @@ SHD float row_jv(const float* r, const float* va, const float* wa, const float* 
 }
 SHD void row_apply(const float* r, float* va, float* wa, float* vb, float* wb, bool has_a, float ima, float imb,
                    float d) {
+  // (row slots are 16-byte aligned: Jl, W_b and W_a are read as float4)
+  const f4 jl = ld4(r + RJL), wr = ld4(r + RWB);
   const float cb = imb * d;
-  vb[0] += cb * r[RJL]; vb[1] += cb * r[RJL + 1]; vb[2] += cb * r[RJL + 2];
-  wb[0] += d * r[RWB]; wb[1] += d * r[RWB + 1]; wb[2] += d * r[RWB + 2];
+  vb[0] += cb * jl.x; vb[1] += cb * jl.y; vb[2] += cb * jl.z;
+  wb[0] += d * wr.x; wb[1] += d * wr.y; wb[2] += d * wr.z;
   if (has_a) {
+    const f4 wl = ld4(r + RWA);
     const float ca = ima * d;
-    va[0] -= ca * r[RJL]; va[1] -= ca * r[RJL + 1]; va[2] -= ca * r[RJL + 2];
-    wa[0] += d * r[RWA]; wa[1] += d * r[RWA + 1]; wa[2] += d * r[RWA + 2];
+    va[0] -= ca * jl.x; va[1] -= ca * jl.y; va[2] -= ca * jl.z;
+    wa[0] += d * wl.x; wa[1] += d * wl.y; wa[2] += d * wl.z;
   }
 }
 // W = M^-1 J^T (angular parts stored), returns K = J W
@@ -2070,11 +2073,39 @@ SHD void a_warm(const Team& tm, const DevModel& M, const Env& E, bool act) {
       float imA = 0.f, imB = 0.f;
       const float ima = ha ? E.body(rb.a)[BIM] : 0.f, imb = E.body(rb.b)[BIM];
       float l0b[5];
-      for (int q = 0; q < nr; ++q) {
-        const float* r = E.row(s + q);
-        float* qa = E.rowA(s + q);
-        row_wbar(qa, r, A, ha, ima, imb, r[RL0], &imA, &imB);
-        l0b[q] = qa[QL] + row_wvbar(r, A, ha, ima, imb);
+      if (nr == 5) {
+        // hinge rows: the same sums as row_wbar / row_wvbar with 16-byte
+        // row accesses; the adjoint of Jl (a constant) is not formed
+        for (int q = 0; q < 5; ++q) {
+          const float* r = E.row(s + q);
+          float* qa = E.rowA(s + q);
+          const f4 jl = ld4(r + RJL), wb = ld4(r + RWB), wa = ld4(r + RWA);
+          const float d = r[RL0];
+          const float jvb = jl.x * A.vb[0] + jl.y * A.vb[1] + jl.z * A.vb[2];
+          f4 qb = ld4(qa + QWB);
+          qb.x += A.wb[0] * d; qb.y += A.wb[1] * d; qb.z += A.wb[2] * d;
+          st4(qa + QWB, qb);
+          imB += d * jvb;
+          float sw = imb * jvb;
+          sw += wb.x * A.wb[0] + wb.y * A.wb[1] + wb.z * A.wb[2];
+          if (ha) {
+            const float jva = jl.x * A.va[0] + jl.y * A.va[1] + jl.z * A.va[2];
+            f4 qw = ld4(qa + QWA);
+            qw.x += A.wa[0] * d; qw.y += A.wa[1] * d; qw.z += A.wa[2] * d;
+            st4(qa + QWA, qw);
+            imA -= d * jva;
+            sw -= ima * jva;
+            sw += wa.x * A.wa[0] + wa.y * A.wa[1] + wa.z * A.wa[2];
+          }
+          l0b[q] = qa[QL] + sw;
+        }
+      } else {
+        for (int q = 0; q < nr; ++q) {
+          const float* r = E.row(s + q);
+          float* qa = E.rowA(s + q);
+          row_wbar(qa, r, A, ha, ima, imb, r[RL0], &imA, &imB);
+          l0b[q] = qa[QL] + row_wvbar(r, A, ha, ima, imb);
+        }
       }
       float* wA = E.wsA() + E.store_of(code);
       if (nr == 5) {
@@ -2151,27 +2182,31 @@ SHD void a_joint(const DevModel& M, const Env& E, int j, int s) {
   float Ob[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   float Oa[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   float imb_bar = 0.f, ima_bar = 0.f;
+  static_assert(QM == QJB + 3 && QB == QWB + 3 && QJA % 4 == 0 && QWA % 4 == 0, "row adjoint layout");
   for (int q = 0; q < 5; ++q) {
     const float* r = E.row(s + q);
     const float* qa = E.rowA(s + q);
-    const float m = r[RM];
-    const float Kb = -m * m * qa[QM];
-    const f3 jl = ld3(r + RJL), jb = ld3(r + RJB);
-    const float jl2 = dot(jl, jl);
+    const f4 rjb = ld4(r + RJB), qjb4 = ld4(qa + QJB), qwb4 = ld4(qa + QWB), qja4 = ld4(qa + QJA);
+    const float m = rjb.w;   // (RM)
+    const float Kb = -m * m * qjb4.w;
+    const f3 jb = mk3(rjb.x, rjb.y, rjb.z);
+    // Jl is a unit axis for the point rows and zero for the angular rows
+    const float jl2 = q < 3 ? 1.f : 0.f;
     // Jb: W = Iw Jb, K += Jb.W  ->  Jbbar += Iw (Wbar + 2 Kb Jb); Iwbar += (Wbar + Kb Jb) Jb^T
     imb_bar += Kb * jl2;
-    const f3 wbb = ld3(qa + QWB);
-    qjb[q] = ld3(qa + QJB) + sv(Bb + BI, wbb + (2.f * Kb) * jb);
+    const f3 wbb = mk3(qwb4.x, qwb4.y, qwb4.z);
+    qjb[q] = mk3(qjb4.x, qjb4.y, qjb4.z) + sv(Bb + BI, wbb + (2.f * Kb) * jb);
     outer_acc(Ob, wbb + Kb * jb, jb);
-    qja[q] = ld3(qa + QJA);
+    qja[q] = mk3(qja4.x, qja4.y, qja4.z);
     if (ha) {
-      const f3 ja = ld3(r + RJA);
+      const f4 rja = ld4(r + RJA), qwa4 = ld4(qa + QWA);
+      const f3 ja = mk3(rja.x, rja.y, rja.z);
       ima_bar += Kb * jl2;
-      const f3 wab = ld3(qa + QWA);
+      const f3 wab = mk3(qwa4.x, qwa4.y, qwa4.z);
       qja[q] = qja[q] + sv(Ba + BI, wab + (2.f * Kb) * ja);
       outer_acc(Oa, wab + Kb * ja, ja);
     }
-    qbias[q] = qa[QB];
+    qbias[q] = qwb4.w;   // (QB)
   }
   Ab[AIM] += imb_bar;
   for (int k = 0; k < 9; ++k) Ab[AIW + k] += Ob[k];
