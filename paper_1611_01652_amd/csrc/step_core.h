@@ -689,6 +689,10 @@ SHD void build_contact(const DevModel& M, const Env& E, int code, int s, const C
 // holds only joints or only contacts.
 template <class Team>
 SHD void f_rows(const Team& tm, const DevModel& M, const Env& E, bool act) {
+  // Joint rows depend only on the step's body state, so all joints are built
+  // at once, lanes over joints; the colour loop below lists them.
+  const int nj = act ? E.nj : 0;
+  for (int j = tm.tl; j < nj; j += tm.ts) build_joint(M, E, j, 5 * j);
   int ncon = 0;  // contacts placed so far (team-uniform)
   for (int c = 0; tm.any(c < E.ncol && act); ++c) {
     int lo = 0, hi = 0;
@@ -719,9 +723,7 @@ SHD void f_rows(const Team& tm, const DevModel& M, const Env& E, bool act) {
         E.act_code()[li] = code;
         int s = -1;
         if (jcol) {
-          const int j = cand_idx(code);
-          s = 5 * j;
-          build_joint(M, E, j, s);
+          s = 5 * cand_idx(code);
         } else if (ncon + pos < E.ccap) {
           s = 5 * E.nj + 4 * (ncon + pos);
           build_contact(M, E, code, s, g);
