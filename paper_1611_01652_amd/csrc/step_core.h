@@ -2166,6 +2166,31 @@ SHD void a_row_finish(const Env& E, const float* r, float* q, int a, int b, floa
 // a_row_finish) are accumulated in registers and added to the bodies once;
 // the rows' Jacobian adjoints stay in registers for the geometry below (the
 // adjoint of Jl, a constant for a hinge, is not formed).
+// The body adjoint's position, rotation, inverse-inertia and inverse-mass
+// parts (floats AP .. AR + 8 and AIW .. AIM), read and written as two
+// aligned runs: three float4, then a float2 and two float4.
+static_assert(AP == 0 && AR == 3 && AIW == 18 && AIM == 27 && BSA % 4 == 0, "body adjoint layout");
+struct BodyAdjHead { float ap[3], ar[9], aiw[9], aim; };
+SHD float f3_at(f3 v, int k) { return k == 0 ? v.x : (k == 1 ? v.y : v.z); }
+SHD void bah_load(BodyAdjHead& h, const float* A) {
+  const f4 a0 = ld4(A), a1 = ld4(A + 4), a2 = ld4(A + 8);
+  const f2 b0 = *reinterpret_cast<const f2*>(A + 18);
+  const f4 b1 = ld4(A + 20), b2 = ld4(A + 24);
+  h.ap[0] = a0.x; h.ap[1] = a0.y; h.ap[2] = a0.z; h.ar[0] = a0.w;
+  h.ar[1] = a1.x; h.ar[2] = a1.y; h.ar[3] = a1.z; h.ar[4] = a1.w;
+  h.ar[5] = a2.x; h.ar[6] = a2.y; h.ar[7] = a2.z; h.ar[8] = a2.w;
+  h.aiw[0] = b0.x; h.aiw[1] = b0.y;
+  h.aiw[2] = b1.x; h.aiw[3] = b1.y; h.aiw[4] = b1.z; h.aiw[5] = b1.w;
+  h.aiw[6] = b2.x; h.aiw[7] = b2.y; h.aiw[8] = b2.z; h.aim = b2.w;
+}
+SHD void bah_store(const BodyAdjHead& h, float* A) {
+  st4(A, f4{h.ap[0], h.ap[1], h.ap[2], h.ar[0]});
+  st4(A + 4, f4{h.ar[1], h.ar[2], h.ar[3], h.ar[4]});
+  st4(A + 8, f4{h.ar[5], h.ar[6], h.ar[7], h.ar[8]});
+  st2(A + 18, f2{h.aiw[0], h.aiw[1]});
+  st4(A + 20, f4{h.aiw[2], h.aiw[3], h.aiw[4], h.aiw[5]});
+  st4(A + 24, f4{h.aiw[6], h.aiw[7], h.aiw[8], h.aim});
+}
 SHD void outer_acc(float* O, f3 a, f3 b) {
   O[0] += a.x * b.x; O[1] += a.x * b.y; O[2] += a.x * b.z;
   O[3] += a.y * b.x; O[4] += a.y * b.y; O[5] += a.y * b.z;
@@ -2210,12 +2235,6 @@ SHD void a_joint(const DevModel& M, const Env& E, int j, int s) {
     }
     qbias[q] = qwb4.w;   // (QB)
   }
-  Ab[AIM] += imb_bar;
-  for (int k = 0; k < 9; ++k) Ab[AIW + k] += Ob[k];
-  if (ha) {
-    Aa[AIM] += ima_bar;
-    for (int k = 0; k < 9; ++k) Aa[AIW + k] += Oa[k];
-  }
   const float kb = M.beta / M.dt;
   const f3 rbl = ld3(C + JAC), ral = ld3(C + JAP);
   f3 rbb = mk3(0.f, 0.f, 0.f), rab = mk3(0.f, 0.f, 0.f), errb = mk3(0.f, 0.f, 0.f);
@@ -2226,14 +2245,8 @@ SHD void a_joint(const DevModel& M, const Env& E, int j, int s) {
     rbb = rbb + cross(e, qjb[q]);
     errb = errb + (kb * qbias[q]) * e;
   }
-  add3(Ab + AP, errb);
   rbb = rbb + errb;
-  add_outer(Ab + AR, rbb, rbl);
-  if (ha) {
-    add3(Aa + AP, -errb);
-    rab = rab - errb;
-    add_outer(Aa + AR, rab, ral);
-  }
+  rab = rab - errb;
   // angular rows
   f3 na = ld3(C + JXP), ua = ld3(C + JUP);
   const f3 t2l = cross(na, ua);
@@ -2253,11 +2266,27 @@ SHD void a_joint(const DevModel& M, const Env& E, int j, int s) {
   // ax = na x nbw
   const f3 nab = cross(nbw, axb);
   const f3 nbb = cross(axb, na);
-  add_outer(Ab + AR, nbb, nbl);
+  // The bodies' adjoints, each read and written once with 16-byte accesses;
+  // every element takes its additions in the order of the adjoint's terms.
+  BodyAdjHead hb;
+  bah_load(hb, Ab);
+  hb.aim += imb_bar;
+  for (int k = 0; k < 9; ++k) hb.aiw[k] += Ob[k];
+  for (int k = 0; k < 3; ++k) hb.ap[k] += f3_at(errb, k);
+  outer_acc(hb.ar, rbb, rbl);
+  outer_acc(hb.ar, nbb, nbl);
+  bah_store(hb, Ab);
   if (ha) {
-    add_outer(Aa + AR, nab, nal);
-    add_outer(Aa + AR, tb[0], ual);
-    add_outer(Aa + AR, tb[1], t2l);
+    BodyAdjHead ha_;
+    bah_load(ha_, Aa);
+    ha_.aim += ima_bar;
+    for (int k = 0; k < 9; ++k) ha_.aiw[k] += Oa[k];
+    for (int k = 0; k < 3; ++k) ha_.ap[k] += -f3_at(errb, k);
+    outer_acc(ha_.ar, rab, ral);
+    outer_acc(ha_.ar, nab, nal);
+    outer_acc(ha_.ar, tb[0], ual);
+    outer_acc(ha_.ar, tb[1], t2l);
+    bah_store(ha_, Aa);
   }
 }
 
