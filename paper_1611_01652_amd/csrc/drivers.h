@@ -172,7 +172,7 @@ SHD void save_step(const Team& tm, const DevModel& M, const Env& E, float* dst) 
 // Copy n4 float4 from global memory to LDS, skipping float4 [s0, s1): each
 // lane issues LOAD_BATCH loads before it waits for the first, so a copy costs
 // a few memory round trips instead of one per float4.
-constexpr int LOAD_BATCH = 16;
+constexpr int LOAD_BATCH = 20;
 template <class Team>
 SHD void copy_to_lds(const Team& tm, float* dst, const float* src, int n4, int s0 = 0, int s1 = 0) {
   for (int i0 = tm.tl; i0 < n4; i0 += LOAD_BATCH * tm.ts) {
@@ -194,9 +194,16 @@ SHD void copy_to_lds(const Team& tm, float* dst, const float* src, int n4, int s
 template <class Team>
 SHD void load_step(const Team& tm, const DevModel& M, const Env& E, const float* src) {
   const int nf = E.lay.total_fwd, nh = align4(M.n_iters * E.nslot);
+  // the first body's step-start angular velocity is loaded before the copies
+  const bool b0 = tm.tl < E.nb;
+  float w[3] = {0.f, 0.f, 0.f};
+  if (b0)
+    for (int k = 0; k < 3; ++k) w[k] = src[nf + nh + 3 * tm.tl + k];
   copy_to_lds(tm, E.L, src, nf / 4, E.lay.misc / 4, (E.lay.misc + MISC_N) / 4);
   copy_to_lds(tm, E.L + E.lay.hist, src + nf, nh / 4);
-  for (int b = tm.tl; b < E.nb; b += tm.ts) {
+  if (b0)
+    for (int k = 0; k < 3; ++k) E.bodyA(tm.tl)[AW0 + k] = w[k];
+  for (int b = tm.tl + tm.ts; b < E.nb; b += tm.ts) {
     const float w0 = src[nf + nh + 3 * b], w1 = src[nf + nh + 3 * b + 1], w2 = src[nf + nh + 3 * b + 2];
     float* A = E.bodyA(b);
     A[AW0] = w0; A[AW0 + 1] = w1; A[AW0 + 2] = w2;
