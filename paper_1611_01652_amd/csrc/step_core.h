@@ -2414,7 +2414,10 @@ SHD void a_predict_torques(const Team& tm, const DevModel& M, const Env& E, bool
     // w* = w + dt Iw tq
     const f3 tqb = M.dt * sv(B + BI, wb);
     st3(A + ATQ, tqb);
-    add_outer(A + AIW, M.dt * wb, ld3(B + BTQ));
+    BodyAdjHead h;
+    bah_load(h, A);
+    outer_acc(h.aiw, M.dt * wb, ld3(B + BTQ));
+    bah_store(h, A);
   }
   tm.sync();
   const int njc = n_joint_cols(E, act);
@@ -2454,23 +2457,34 @@ SHD void a_predict_torques(const Team& tm, const DevModel& M, const Env& E, bool
   for (int b = tm.tl; b < nb; b += tm.ts) {
     const float* B = E.body(b);
     float* A = E.bodyA(b);
-    const float* R = B + BR;
-    const float* G = A + AIW;
+    // (the body's position and rotation are floats 0..11 of its record, the
+    // adjoint's likewise: read and written as float4)
+    static_assert(BP == 0 && BR == 3 && BS % 4 == 0 && AII % 4 == 0, "body record layout");
+    BodyAdjHead h;
+    bah_load(h, A);
+    const f4 r0 = ld4(B), r1 = ld4(B + 4), r2 = ld4(B + 8);
+    const float R[9] = {r0.w, r1.x, r1.y, r1.z, r1.w, r2.x, r2.y, r2.z, r2.w};
+    const float* G = h.aiw;
     float Sy[9];
     for (int i = 0; i < 3; ++i)
       for (int j = 0; j < 3; ++j) Sy[3 * i + j] = G[3 * i + j] + G[3 * j + i];
     for (int i = 0; i < 3; ++i)
       for (int k = 0; k < 3; ++k) {
         const float srk = Sy[3 * i] * R[k] + Sy[3 * i + 1] * R[3 + k] + Sy[3 * i + 2] * R[6 + k];
-        A[AR + 3 * i + k] += srk * B[BII + k];
+        h.ar[3 * i + k] += srk * B[BII + k];
       }
+    bah_store(h, A);
+    f4 ii = ld4(A + AII);   // the inverse-inertia adjoint (and, untouched, the torque adjoint's x)
+    float acc3[3];
     for (int k = 0; k < 3; ++k) {
       // (R^T G R)_kk = sum_ij R_ik G_ij R_jk
       float acc = 0.f;
       for (int i = 0; i < 3; ++i)
         for (int j = 0; j < 3; ++j) acc += R[3 * i + k] * G[3 * i + j] * R[3 * j + k];
-      A[AII + k] += acc;
+      acc3[k] = acc;
     }
+    ii.x += acc3[0]; ii.y += acc3[1]; ii.z += acc3[2];
+    st4(A + AII, ii);
     kahan_add(A + ATM, A + ACM, A[AIM]);
     for (int k = 0; k < 3; ++k) kahan_add(A + ATI + k, A + ACI + k, A[AII + k]);
   }
