@@ -2168,10 +2168,6 @@ SHD void a_row_finish(const Env& E, const float* r, float* q, int a, int b, floa
   add3(q + QJL, (2.f * Kb * im) * jl);
 }
 
-// Adjoint of build_joint.  The five rows' row_finish adjoints (see
-// a_row_finish) are accumulated in registers and added to the bodies once;
-// the rows' Jacobian adjoints stay in registers for the geometry below (the
-// adjoint of Jl, a constant for a hinge, is not formed).
 // The body adjoint's position, rotation, inverse-inertia and inverse-mass
 // parts (floats AP .. AR + 8 and AIW .. AIM), read and written as two
 // aligned runs: three float4, then a float2 and two float4.
@@ -2202,57 +2198,74 @@ SHD void outer_acc(float* O, f3 a, f3 b) {
   O[3] += a.y * b.x; O[4] += a.y * b.y; O[5] += a.y * b.z;
   O[6] += a.z * b.x; O[7] += a.z * b.y; O[8] += a.z * b.z;
 }
-SHD void a_joint(const DevModel& M, const Env& E, int j, int s) {
+// Adjoint of build_joint.  The five rows' row_finish adjoints (see
+// a_row_finish) are accumulated in registers and added to the bodies once;
+// the rows' Jacobian adjoints stay in registers for the geometry below (the
+// adjoint of Jl, a constant for a hinge, is not formed).  Like the sweeps, a
+// hinge colour can be taken by lane pairs: each lane of a pair forms its own
+// body's terms (NS = 1), and one lane alone forms both (NS = 2, index 0 =
+// body b), with the same expressions in the same order, so the results do
+// not depend on the form.  Side a needs side b's Jacobian adjoints of the
+// two angular rows, which a pair exchanges with the DPP swap.
+template <int NS, class Team>
+SHD void a_joint(const Team& tm, const DevModel& M, const Env& E, int j, int s) {
   const float* C = E.jc(j);
   const int a = E.jpar(j), b = E.jchi(j);
   const bool ha = a >= 0;
   const float* Bb = E.body(b);
   const float* Ba = ha ? E.body(a) : nullptr;
-  float* Ab = E.bodyA(b);
-  float* Aa = ha ? E.bodyA(a) : nullptr;
-  f3 qja[5], qjb[5];
-  float qbias[5];
-  float Ob[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-  float Oa[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-  float imb_bar = 0.f, ima_bar = 0.f;
   static_assert(QM == QJB + 3 && QB == QWB + 3 && QJA % 4 == 0 && QWA % 4 == 0, "row adjoint layout");
+  int sd[NS];        // 1: body b's side
+  bool on[NS];       // the side has a body (side a of a world-attached joint has none)
+  float I[NS][6];    // the side's body inverse inertia (world frame)
+  for (int i = 0; i < NS; ++i) {
+    sd[i] = NS == 2 ? 1 - i : (tm.tl & 1);
+    on[i] = sd[i] || ha;
+    // (side a of a world-attached joint reads the world slot: zero inertia)
+    const float* B = sd[i] ? Bb : (ha ? Ba : E.body(E.nb));
+    for (int k = 0; k < 6; ++k) I[i][k] = B[BI + k];
+  }
+  f3 qj[NS][5];
+  float qbias[5];
+  float O[NS][9];
+  float imx[NS];
+  for (int i = 0; i < NS; ++i) {
+    imx[i] = 0.f;
+    for (int k = 0; k < 9; ++k) O[i][k] = 0.f;
+  }
   for (int q = 0; q < 5; ++q) {
     const float* r = E.row(s + q);
     const float* qa = E.rowA(s + q);
-    const f4 rjb = ld4(r + RJB), qjb4 = ld4(qa + QJB), qwb4 = ld4(qa + QWB), qja4 = ld4(qa + QJA);
-    const float m = rjb.w;   // (RM)
-    const float Kb = -m * m * qjb4.w;
-    const f3 jb = mk3(rjb.x, rjb.y, rjb.z);
+    const float qm = qa[QM];
+    qbias[q] = qa[QB];
     // Jl is a unit axis for the point rows and zero for the angular rows
     const float jl2 = q < 3 ? 1.f : 0.f;
-    // Jb: W = Iw Jb, K += Jb.W  ->  Jbbar += Iw (Wbar + 2 Kb Jb); Iwbar += (Wbar + Kb Jb) Jb^T
-    imb_bar += Kb * jl2;
-    const f3 wbb = mk3(qwb4.x, qwb4.y, qwb4.z);
-    qjb[q] = mk3(qjb4.x, qjb4.y, qjb4.z) + sv(Bb + BI, wbb + (2.f * Kb) * jb);
-    outer_acc(Ob, wbb + Kb * jb, jb);
-    qja[q] = mk3(qja4.x, qja4.y, qja4.z);
-    if (ha) {
-      const f4 rja = ld4(r + RJA), qwa4 = ld4(qa + QWA);
-      const f3 ja = mk3(rja.x, rja.y, rja.z);
-      ima_bar += Kb * jl2;
-      const f3 wab = mk3(qwa4.x, qwa4.y, qwa4.z);
-      qja[q] = qja[q] + sv(Ba + BI, wab + (2.f * Kb) * ja);
-      outer_acc(Oa, wab + Kb * ja, ja);
+    for (int i = 0; i < NS; ++i) {
+      const int so = HSIDE * sd[i];
+      const f4 rj = ld4(r + RJA + so), qj4 = ld4(qa + QJA + so), qw4 = ld4(qa + QWA + so);
+      const float m = rj.w;   // (RMA / RM: the same value)
+      const float Kb = -m * m * qm;
+      qj[i][q] = mk3(qj4.x, qj4.y, qj4.z);
+      if (on[i]) {
+        // J: W = Iw J, K += J.W  ->  Jbar += Iw (Wbar + 2 Kb J); Iwbar += (Wbar + Kb J) J^T
+        const f3 jx = mk3(rj.x, rj.y, rj.z), wx = mk3(qw4.x, qw4.y, qw4.z);
+        imx[i] += Kb * jl2;
+        qj[i][q] = qj[i][q] + sv(I[i], wx + (2.f * Kb) * jx);
+        outer_acc(O[i], wx + Kb * jx, jx);
+      }
     }
-    qbias[q] = qwb4.w;   // (QB)
   }
   const float kb = M.beta / M.dt;
   const f3 rbl = ld3(C + JAC), ral = ld3(C + JAP);
-  f3 rbb = mk3(0.f, 0.f, 0.f), rab = mk3(0.f, 0.f, 0.f), errb = mk3(0.f, 0.f, 0.f);
+  f3 rx[NS], errb = mk3(0.f, 0.f, 0.f);
+  for (int i = 0; i < NS; ++i) rx[i] = mk3(0.f, 0.f, 0.f);
   for (int q = 0; q < 3; ++q) {
     const f3 e = mk3(q == 0 ? 1.f : 0.f, q == 1 ? 1.f : 0.f, q == 2 ? 1.f : 0.f);
     // Ja = e x ra ; Jb = rb x e
-    rab = rab + cross(qja[q], e);
-    rbb = rbb + cross(e, qjb[q]);
+    for (int i = 0; i < NS; ++i) rx[i] = rx[i] + (sd[i] ? cross(e, qj[i][q]) : cross(qj[i][q], e));
     errb = errb + (kb * qbias[q]) * e;
   }
-  rbb = rbb + errb;
-  rab = rab - errb;
+  for (int i = 0; i < NS; ++i) rx[i] = sd[i] ? rx[i] + errb : rx[i] - errb;
   // angular rows
   f3 na = ld3(C + JXP), ua = ld3(C + JUP);
   const f3 t2l = cross(na, ua);
@@ -2262,11 +2275,24 @@ SHD void a_joint(const DevModel& M, const Env& E, int j, int s) {
   const f3 nbl = ld3(C + JXC);
   const f3 nbw = mv(Bb + BR, nbl);
   const f3 ax = cross(na, nbw);
+  // side b's and side a's Jacobian adjoints of the angular rows
+  f3 qjb[2], qja[2];
+  for (int q = 0; q < 2; ++q) {
+    if (NS == 2) {
+      qjb[q] = qj[0][3 + q];
+      qja[q] = qj[NS - 1][3 + q];
+    } else {
+      const f3 own = qj[0][3 + q];
+      const f3 other = mk3(tm.pair_swap(own.x), tm.pair_swap(own.y), tm.pair_swap(own.z));
+      qjb[q] = sd[0] ? own : other;
+      qja[q] = sd[0] ? other : own;
+    }
+  }
   f3 axb = mk3(0.f, 0.f, 0.f), tb[2];
   for (int q = 0; q < 2; ++q) {
     const float cb = kb * qbias[3 + q];
     const f3 tk = q == 0 ? ua : t2;
-    tb[q] = qjb[3 + q] - qja[3 + q] + cb * ax;
+    tb[q] = qjb[q] - qja[q] + cb * ax;
     axb = axb + cb * tk;
   }
   // ax = na x nbw
@@ -2274,25 +2300,25 @@ SHD void a_joint(const DevModel& M, const Env& E, int j, int s) {
   const f3 nbb = cross(axb, na);
   // The bodies' adjoints, each read and written once with 16-byte accesses;
   // every element takes its additions in the order of the adjoint's terms.
-  BodyAdjHead hb;
-  bah_load(hb, Ab);
-  hb.aim += imb_bar;
-  for (int k = 0; k < 9; ++k) hb.aiw[k] += Ob[k];
-  for (int k = 0; k < 3; ++k) hb.ap[k] += f3_at(errb, k);
-  outer_acc(hb.ar, rbb, rbl);
-  outer_acc(hb.ar, nbb, nbl);
-  bah_store(hb, Ab);
-  if (ha) {
-    BodyAdjHead ha_;
-    bah_load(ha_, Aa);
-    ha_.aim += ima_bar;
-    for (int k = 0; k < 9; ++k) ha_.aiw[k] += Oa[k];
-    for (int k = 0; k < 3; ++k) ha_.ap[k] += -f3_at(errb, k);
-    outer_acc(ha_.ar, rab, ral);
-    outer_acc(ha_.ar, nab, nal);
-    outer_acc(ha_.ar, tb[0], ual);
-    outer_acc(ha_.ar, tb[1], t2l);
-    bah_store(ha_, Aa);
+  for (int i = 0; i < NS; ++i) {
+    if (!on[i]) continue;
+    float* A = E.bodyA(sd[i] ? b : a);
+    BodyAdjHead h;
+    bah_load(h, A);
+    h.aim += imx[i];
+    for (int k = 0; k < 9; ++k) h.aiw[k] += O[i][k];
+    if (sd[i]) {
+      for (int k = 0; k < 3; ++k) h.ap[k] += f3_at(errb, k);
+      outer_acc(h.ar, rx[i], rbl);
+      outer_acc(h.ar, nbb, nbl);
+    } else {
+      for (int k = 0; k < 3; ++k) h.ap[k] += -f3_at(errb, k);
+      outer_acc(h.ar, rx[i], ral);
+      outer_acc(h.ar, nab, nal);
+      outer_acc(h.ar, tb[0], ual);
+      outer_acc(h.ar, tb[1], t2l);
+    }
+    bah_store(h, A);
   }
 }
 
@@ -2381,13 +2407,18 @@ SHD void a_rows(const Team& tm, const DevModel& M, const Env& E, bool act) {
     i4 pl{0, 0, 0, 0};
     if (ci >= 0) pl = E.plan()[ci];
     const int n = pl.y, lo = pl.x;
-    for (int k = tm.tl; k < n; k += tm.ts) {
+    // a hinge colour is taken by lane pairs (one body each) when the team has
+    // a pair of lanes for each of its joints; otherwise one lane per joint
+    const bool pr = pl.z != 0 && tm.ts >= 2 && 2 * n <= tm.ts;
+    const int k0 = pr ? tm.tl >> 1 : tm.tl, kst = pr ? tm.ts >> 1 : tm.ts;
+    for (int k = k0; k < n; k += kst) {
       const i4 v = E.vis()[lo + k];
       const int s = v.x;
       if (s < 0) continue;
       const int code = v.w;
-      if (cand_kind(code) == K_JOINT) a_joint(M, E, cand_idx(code), s);
-      else a_contact(M, E, code, s);
+      if (cand_kind(code) != K_JOINT) a_contact(M, E, code, s);
+      else if (pr) a_joint<1>(tm, M, E, cand_idx(code), s);
+      else a_joint<2>(tm, M, E, cand_idx(code), s);
     }
     tm.sync();
   }
