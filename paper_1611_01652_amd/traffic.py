@@ -3,17 +3,18 @@
 Each counter is read in its own profiled run (FETCH_SIZE, then WRITE_SIZE),
 for the benchmark and for a plain device copy of known size; the copy gives
 the scale of each counter (KiB it reports per KiB really moved), which turns
-the kernel's counts into bytes:
+the kernel's counts into bytes ($R: the repository root, $OUT: a directory for
+the profiler's output):
 
     cd /tmp && export TMPDIR=/tmp
-    rocprofv3 --pmc FETCH_SIZE --output-format csv -d $R/gpurun_out/pmc_copy_f -o c -- \\
+    rocprofv3 --pmc FETCH_SIZE --output-format csv -d $OUT/pmc_copy_f -o c -- \\
         python3 -m paper_1611_01652_amd.traffic copy
-    rocprofv3 --pmc WRITE_SIZE --output-format csv -d $R/gpurun_out/pmc_copy_w -o c -- \\
+    rocprofv3 --pmc WRITE_SIZE --output-format csv -d $OUT/pmc_copy_w -o c -- \\
         python3 -m paper_1611_01652_amd.traffic copy
-    rocprofv3 --pmc FETCH_SIZE --output-format csv -d $R/gpurun_out/pmc_arms_f -o b -- \\
+    rocprofv3 --pmc FETCH_SIZE --output-format csv -d $OUT/pmc_arms_f -o b -- \\
         python3 $R/bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-check
     rocprofv3 --pmc WRITE_SIZE ... (same, pmc_arms_w)
-    python3 -m paper_1611_01652_amd.traffic summarize --workload arms --dir $R/gpurun_out
+    python3 -m paper_1611_01652_amd.traffic summarize --workload arms --dir $OUT
 
 The summary (profiles/traffic_<workload>.json) holds the bytes per launch of
 k_rollout_grad and a hash of the kernel sources it was measured with; the
@@ -133,11 +134,13 @@ if __name__ == "__main__":
     ap = argparse.ArgumentParser()
     ap.add_argument("cmd", choices=["copy", "summarize", "hash"])
     ap.add_argument("--workload", default="arms")
-    ap.add_argument("--dir", default=os.path.join(ROOT, "gpurun_out"))
+    ap.add_argument("--dir", help="directory holding the profiler's pmc_* output folders")
     a = ap.parse_args()
     if a.cmd == "copy":
         copy_main()
     elif a.cmd == "summarize":
+        if not a.dir:
+            ap.error("summarize needs --dir")
         summarize(a.workload, a.dir)
     else:
         print(source_hash())
