@@ -836,35 +836,6 @@ struct SweepCursor {
   }
 };
 
-// F5: warm start, v += W lambda0 for every row, colour by colour.
-template <class Team>
-SHD void f_warm(const Team& tm, const Env& E, bool act) {
-  const int nl = n_live(E, act);
-  for (int ci = 0; tm.any(ci < nl); ++ci) {
-    i4 pl{0, 0, 0, 0};
-    if (ci < nl) pl = E.plan()[ci];
-    const int n = pl.y, lo = pl.x;
-    for (int k = tm.tl; k < n; k += tm.ts) {
-      const i4 v = E.vis()[lo + k];
-      const int s = v.x;
-      if (s < 0) continue;
-      const int code = v.w;
-      const RowB rb{v.y == E.nb ? -1 : v.y, v.z};
-      const int nr = cand_kind(code) == K_JOINT ? 5 : 3;
-      Vel V;
-      vel_load(V, E, rb.a, rb.b);
-      const float ima = rb.a >= 0 ? E.body(rb.a)[BIM] : 0.f, imb = E.body(rb.b)[BIM];
-      for (int q = 0; q < nr; ++q) {
-        const float* r = E.row(s + q);
-        row_apply(r, V.va, V.wa, V.vb, V.wb, rb.a >= 0, ima, imb, r[RL0]);
-      }
-      vel_store(V, E, rb.a, rb.b);
-    }
-    tm.sync();
-  }
-}
-
-
 // Velocities of a constraint's two bodies in registers.
 struct VR { float va[3], wa[3], vb[3], wb[3]; };
 SHD void vr_load(VR& V, const Env& E, int a, int b) {
@@ -1057,6 +1028,63 @@ SHD void hinge_fwd(const Team& tm, const DevModel& M, const Env& E, int s, int a
   h_row_fwd<3, NS>(tm, M, r[4], x, sd, m[4], bias[4], lam[4], Hw ? Hw + 4 : nullptr, rmax);
   for (int q = 0; q < 5; ++q) R0[q * RS + RL] = lam[q];
   for (int i = 0; i < NS; ++i) hs_store(x[i], E.body(sd.bd[i]) + BV);
+}
+
+// A hinge's warm start v += W lambda0 over its five rows, by side (see
+// hinge_fwd): a lane of a pair updates its own body, one lane alone both, with
+// the same arithmetic.  a: body index or the world slot.
+template <int NS, class Team>
+SHD void hinge_warm(const Team& tm, const Env& E, int s, int a, int b) {
+  HSides<NS> sd;
+  sd.init(tm, E, a, b);
+  const float* R0 = E.row(s);
+  for (int i = 0; i < NS; ++i) {
+    HS x;
+    hs_load(x, E.body(sd.bd[i]) + BV);
+    HR r[5];
+    for (int q = 0; q < 5; ++q) hr_load(r[q], R0 + sd.so[i] + q * RS);
+    h_apply<0>(r[0], x, sd.sim[i], R0[RL0]);
+    h_apply<1>(r[1], x, sd.sim[i], R0[RS + RL0]);
+    h_apply<2>(r[2], x, sd.sim[i], R0[2 * RS + RL0]);
+    h_apply<3>(r[3], x, sd.sim[i], R0[3 * RS + RL0]);
+    h_apply<3>(r[4], x, sd.sim[i], R0[4 * RS + RL0]);
+    hs_store(x, E.body(sd.bd[i]) + BV);
+  }
+}
+
+// F5: warm start, v += W lambda0 for every row, colour by colour; a hinge
+// colour is taken by lane pairs when the team has two lanes, as in the sweeps.
+template <class Team>
+SHD void f_warm(const Team& tm, const Env& E, bool act) {
+  const int nl = n_live(E, act);
+  for (int ci = 0; tm.any(ci < nl); ++ci) {
+    i4 pl{0, 0, 0, 0};
+    if (ci < nl) pl = E.plan()[ci];
+    const int n = pl.y, lo = pl.x;
+    const bool pr = pl.z != 0 && tm.ts >= 2;
+    const int k0 = pr ? tm.tl >> 1 : tm.tl, kst = pr ? tm.ts >> 1 : tm.ts;
+    for (int k = k0; k < n; k += kst) {
+      const i4 v = E.vis()[lo + k];
+      const int s = v.x;
+      if (s < 0) continue;
+      const int code = v.w;
+      if (cand_kind(code) == K_JOINT) {
+        if (pr) hinge_warm<1>(tm, E, s, v.y, v.z);
+        else hinge_warm<2>(tm, E, s, v.y, v.z);
+        continue;
+      }
+      const RowB rb{v.y == E.nb ? -1 : v.y, v.z};
+      Vel V;
+      vel_load(V, E, rb.a, rb.b);
+      const float ima = rb.a >= 0 ? E.body(rb.a)[BIM] : 0.f, imb = E.body(rb.b)[BIM];
+      for (int q = 0; q < 3; ++q) {
+        const float* r = E.row(s + q);
+        row_apply(r, V.va, V.wa, V.vb, V.wb, rb.a >= 0, ima, imb, r[RL0]);
+      }
+      vel_store(V, E, rb.a, rb.b);
+    }
+    tm.sync();
+  }
 }
 
 // One visit of a contact: normal row clamped at 0, then the friction disk.
@@ -2060,6 +2088,50 @@ SHD void a_pgs(const Team& tm, const DevModel& M, const Env& E, bool act) {
   tm.sync();
 }
 
+// Adjoint of a hinge's warm start (see hinge_warm), by side: each side adds
+// its part of W-bar and of its body's inverse-mass adjoint; a row's impulse
+// adjoint takes (part b) + (part a) of W^T v-bar, exchanged within a pair, so
+// both lanes hold the same value.
+template <int S, int NS, class Team>
+SHD float hinge_warm_row(const Team& tm, const HSides<NS>& sd, const float* R, float* Q, const HS* A, float* imx) {
+  const float d = R[RL0];
+  float p[NS];
+  for (int i = 0; i < NS; ++i) {
+    HR r;
+    hr_load(r, R + sd.so[i]);
+    float* qw = Q + QWA + sd.so[i];
+    f4 w4 = ld4(qw);
+    w4.x += A[i].w[0] * d; w4.y += A[i].w[1] * d; w4.z += A[i].w[2] * d;
+    st4(qw, w4);
+    if (S < 3) imx[i] += (sd.sg[i] * d) * A[i].v[S];
+    p[i] = h_wpart<S>(r, A[i], sd.sim[i]);
+  }
+  return Q[QL] + h_sum<NS>(tm, p);
+}
+template <int NS, class Team>
+SHD void hinge_warm_rev(const Team& tm, const DevModel& M, const Env& E, int s, int a, int b, int code) {
+  HSides<NS> sd;
+  sd.init(tm, E, a, b);
+  const float* R0 = E.row(s);
+  float* Q0 = E.rowA(s);
+  HS A[NS];
+  float imx[NS];
+  for (int i = 0; i < NS; ++i) {
+    hs_load(A[i], E.bodyA(sd.bd[i]) + AV);
+    imx[i] = 0.f;
+  }
+  float l0b[5];
+  l0b[0] = hinge_warm_row<0, NS>(tm, sd, R0, Q0, A, imx);
+  l0b[1] = hinge_warm_row<1, NS>(tm, sd, R0 + RS, Q0 + RSA, A, imx);
+  l0b[2] = hinge_warm_row<2, NS>(tm, sd, R0 + 2 * RS, Q0 + 2 * RSA, A, imx);
+  l0b[3] = hinge_warm_row<3, NS>(tm, sd, R0 + 3 * RS, Q0 + 3 * RSA, A, imx);
+  l0b[4] = hinge_warm_row<3, NS>(tm, sd, R0 + 4 * RS, Q0 + 4 * RSA, A, imx);
+  // (both lanes of a pair add the same value to the same entries)
+  float* wA = E.wsA() + E.store_of(code);
+  for (int q = 0; q < 5; ++q) wA[q] += M.warm * l0b[q];
+  for (int i = 0; i < NS; ++i) E.bodyA(sd.bd[i])[AIM] += imx[i];
+}
+
 // B5: adjoint of the warm start v += W lambda0 and of lambda0 = warm * store.
 template <class Team>
 SHD void a_warm(const Team& tm, const DevModel& M, const Env& E, bool act) {
@@ -2068,57 +2140,34 @@ SHD void a_warm(const Team& tm, const DevModel& M, const Env& E, bool act) {
     i4 pl{0, 0, 0, 0};
     if (ci >= 0) pl = E.plan()[ci];
     const int n = pl.y, lo = pl.x;
-    for (int k = tm.tl; k < n; k += tm.ts) {
+    const bool pr = pl.z != 0 && tm.ts >= 2;
+    const int k0 = pr ? tm.tl >> 1 : tm.tl, kst = pr ? tm.ts >> 1 : tm.ts;
+    for (int k = k0; k < n; k += kst) {
       const i4 v = E.vis()[lo + k];
       const int s = v.x;
       if (s < 0) continue;
       const int code = v.w;
+      if (cand_kind(code) == K_JOINT) {
+        if (pr) hinge_warm_rev<1>(tm, M, E, s, v.y, v.z, code);
+        else hinge_warm_rev<2>(tm, M, E, s, v.y, v.z, code);
+        continue;
+      }
       const RowB rb{v.y == E.nb ? -1 : v.y, v.z};
       const bool ha = rb.a >= 0;
-      const int nr = cand_kind(code) == K_JOINT ? 5 : 3;
+      const int nr = 3;
       VelA A;
       vela_load(A, E, rb.a, rb.b);
       float imA = 0.f, imB = 0.f;
       const float ima = ha ? E.body(rb.a)[BIM] : 0.f, imb = E.body(rb.b)[BIM];
       float l0b[5];
-      if (nr == 5) {
-        // hinge rows: the same sums as row_wbar / row_wvbar with 16-byte
-        // row accesses; the adjoint of Jl (a constant) is not formed
-        for (int q = 0; q < 5; ++q) {
-          const float* r = E.row(s + q);
-          float* qa = E.rowA(s + q);
-          const f4 jl = ld4(r + RJL), wb = ld4(r + RWB), wa = ld4(r + RWA);
-          const float d = r[RL0];
-          const float jvb = jl.x * A.vb[0] + jl.y * A.vb[1] + jl.z * A.vb[2];
-          f4 qb = ld4(qa + QWB);
-          qb.x += A.wb[0] * d; qb.y += A.wb[1] * d; qb.z += A.wb[2] * d;
-          st4(qa + QWB, qb);
-          imB += d * jvb;
-          float sw = imb * jvb;
-          sw += wb.x * A.wb[0] + wb.y * A.wb[1] + wb.z * A.wb[2];
-          if (ha) {
-            const float jva = jl.x * A.va[0] + jl.y * A.va[1] + jl.z * A.va[2];
-            f4 qw = ld4(qa + QWA);
-            qw.x += A.wa[0] * d; qw.y += A.wa[1] * d; qw.z += A.wa[2] * d;
-            st4(qa + QWA, qw);
-            imA -= d * jva;
-            sw -= ima * jva;
-            sw += wa.x * A.wa[0] + wa.y * A.wa[1] + wa.z * A.wa[2];
-          }
-          l0b[q] = qa[QL] + sw;
-        }
-      } else {
-        for (int q = 0; q < nr; ++q) {
-          const float* r = E.row(s + q);
-          float* qa = E.rowA(s + q);
-          row_wbar(qa, r, A, ha, ima, imb, r[RL0], &imA, &imB);
-          l0b[q] = qa[QL] + row_wvbar(r, A, ha, ima, imb);
-        }
+      for (int q = 0; q < nr; ++q) {
+        const float* r = E.row(s + q);
+        float* qa = E.rowA(s + q);
+        row_wbar(qa, r, A, ha, ima, imb, r[RL0], &imA, &imB);
+        l0b[q] = qa[QL] + row_wvbar(r, A, ha, ima, imb);
       }
       float* wA = E.wsA() + E.store_of(code);
-      if (nr == 5) {
-        for (int q = 0; q < 5; ++q) wA[q] += M.warm * l0b[q];
-      } else {
+      {
         const float* x = E.row(s + 3);
         float* xa = E.rowA(s + 3);
         const float* w = E.ws() + E.store_of(code);
