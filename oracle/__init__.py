@@ -55,6 +55,7 @@ def _load():
         _lib.oracle_bf16.restype = C.c_double
         _lib.oracle_wsn_forward.argtypes = [dp, dp, C.c_int, C.c_int, dp]
         _lib.oracle_wsn_forward.restype = None
+        _lib.oracle_controls.argtypes = [C.c_void_p, C.c_int, dp, C.c_int, dp]
     return _lib
 
 
@@ -246,6 +247,17 @@ class Oracle:
         if gw is not None:
             out["g_w"] = gw
         return out
+
+    def controls(self, x, env=0, t=0):
+        """Controller outputs u^t of one env at state x [B][18] (eq. (g))."""
+        w = self.w
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        n = int(w.env_joint_off[env + 1] - w.env_joint_off[env])
+        u = np.zeros(max(n, 1))
+        r = self.lib.oracle_controls(C.byref(self._m), int(env), _dp(x), int(t), _dp(u))
+        if r < 0:
+            raise ValueError("the workload has no controller")
+        return u[:n]
 
     def count_flops(self, env=0, x=None, lam=None, u=None, t=0):
         w = self.w

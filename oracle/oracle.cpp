@@ -24,7 +24,12 @@
 // Parity pins live in tests/test_oracle_*.py: free fall and ballistic closed
 // forms, a ball at rest, sliding-to-rolling at 5/7 of the initial speed,
 // momentum conservation, pendulum period, spin angle n*atan(dt*w), LCP brute
-// force, and central finite differences of the gradient.
+// force, central finite differences of the gradient; the controller's
+// sensor and clock inputs read back through routing weights, the loss kinds
+// on straight-line flight (values and gradients), motor torque, damping decay
+// and the world inertia about a hinge, the angular-momentum balance of a
+// free chain, and pair friction (momentum, the Coulomb disk, independence of
+// the tangent basis).
 #include <algorithm>
 #include <array>
 #include <atomic>
@@ -870,6 +875,28 @@ long long oracle_rollout_ex(const oracle_model* m, const double* x0, double* los
     for (size_t k = 0; k < r.size(); k += ORACLE_REC, ++n)
       if (recs && n < rec_cap) std::copy(r.begin() + k, r.begin() + k + ORACLE_REC, recs + n * ORACLE_REC);
   return n;
+}
+
+// The controller's outputs u^t for env `env` at state x (global [B][18]) and
+// step t: eq. (g) evaluated on the joint sensors and the clock.  A test hook
+// for pinning the sensor and clock inputs.
+int oracle_controls(const oracle_model* m, int env, const double* x, int t, double* u_out) {
+  if (m->ctrl_kind != 1 || env < 0 || env >= m->n_envs) return -1;
+  Ctx C;
+  build_ctx(m, C);
+  const EnvTopo& E = C.topo[env];
+  Bodies<double> B;
+  B.p.resize(E.nb); B.v.resize(E.nb); B.w.resize(E.nb); B.R.resize(E.nb); B.Iw.resize(E.nb); B.invm.resize(E.nb);
+  for (int b = 0; b < E.nb; ++b) {
+    const double* xb = x + 18 * (E.b0 + b);
+    B.p[b] = {xb[0], xb[1], xb[2]};
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) B.R[b].m[i][j] = xb[3 + 3 * i + j];
+    B.v[b] = {xb[12], xb[13], xb[14]};
+    B.w[b] = {xb[15], xb[16], xb[17]};
+  }
+  mlp_controls<double>(C.M, E, t, B, m->mlp_w, u_out);
+  return E.nj;
 }
 
 double oracle_bf16(double x) { return bf16(x); }

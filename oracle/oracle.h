@@ -85,6 +85,9 @@ int oracle_rollout_grad(const oracle_model* m, const double* x0, const double* d
 long long oracle_rollout_ex(const oracle_model* m, const double* x0, double* loss_env, double* x_final,
                             double* lam_final, int* iters_env, int* fallbacks_env, int rec_every, double* recs,
                             long long rec_cap, int n_threads);
+/* controller outputs u^t (J_env values) of env `env` at state x [B][18] and
+   step t; returns J_env, or -1 without a controller */
+int oracle_controls(const oracle_model* m, int env, const double* x, int t, double* u_out);
 /* bfloat16 rounding (nearest, ties to even) of a double */
 double oracle_bf16(double x);
 /* the warm-start network as used by the learned warm start (bfloat16
