@@ -44,7 +44,7 @@ def _load():
         _lib.oracle_order.argtypes = [C.c_void_p, C.c_int, ip, ip, C.c_int]
         _lib.oracle_step.argtypes = [C.c_void_p, dp, dp, dp, dp, dp, C.c_int]
         _lib.oracle_rollout.argtypes = [C.c_void_p, dp, dp, dp, dp, dp, C.c_int]
-        _lib.oracle_rollout_grad.argtypes = [C.c_void_p, dp, dp, dp, dp, dp, dp, dp, dp, dp, dp, C.c_int]
+        _lib.oracle_rollout_grad.argtypes = [C.c_void_p, dp, dp, dp, dp, dp, dp, dp, dp, dp, dp, dp, dp, C.c_int]
         _lib.oracle_count_flops.argtypes = [C.c_void_p, C.c_int, dp, dp, dp, C.c_int]
         _lib.oracle_count_flops.restype = C.c_longlong
         _lib.oracle_count_tape_edges.argtypes = [C.c_void_p, C.c_int, dp, dp, dp, C.c_int]
@@ -236,14 +236,17 @@ class Oracle:
         out = dict(loss=np.zeros(w.n_envs), g_x0=np.zeros_like(x0),
                    g_u=np.zeros((w.T_max, max(w.n_joints, 1))),
                    g_inv_mass=np.zeros(w.n_bodies), g_inv_inertia=np.zeros((w.n_bodies, 3)),
-                   g_mu=np.zeros(w.n_envs), g_damping=np.zeros(max(w.n_joints, 1)))
+                   g_mu=np.zeros(w.n_envs), g_damping=np.zeros(max(w.n_joints, 1)),
+                   g_anchor_p=np.zeros((max(w.n_joints, 1), 3)), g_anchor_c=np.zeros((max(w.n_joints, 1), 3)))
         gw = np.zeros(self._m.mlp_n_params) if self._m.ctrl_kind == 1 else None
         self.lib.oracle_rollout_grad(C.byref(self._m), _dp(x0), _dp(dloss), _dp(out["loss"]), _dp(out["g_x0"]),
                                      _dp(out["g_u"]), _dp(out["g_inv_mass"]), _dp(out["g_inv_inertia"]),
-                                     _dp(out["g_mu"]), _dp(out["g_damping"]), _dp(gw),
-                                     threads or os.cpu_count() or 1)
+                                     _dp(out["g_mu"]), _dp(out["g_damping"]), _dp(gw), _dp(out["g_anchor_p"]),
+                                     _dp(out["g_anchor_c"]), threads or os.cpu_count() or 1)
         out["g_u"] = out["g_u"][:, : w.n_joints]
         out["g_damping"] = out["g_damping"][: w.n_joints]
+        out["g_anchor_p"] = out["g_anchor_p"][: w.n_joints]
+        out["g_anchor_c"] = out["g_anchor_c"][: w.n_joints]
         if gw is not None:
             out["g_w"] = gw
         return out

@@ -336,7 +336,8 @@ void mlp_controls(const Model& M, const EnvTopo& E, int t, const Bodies<S>& B, c
 
 // ------------------------------------------------------------------ one step
 // Differentiable inputs of one env step: state, warm-start block, controls and
-// the per-body / per-joint / per-env model parameters.
+// the per-body / per-joint / per-env model parameters (the hinge anchors are
+// the model's link lengths, section 4).
 template <class S> struct StepIn {
   const S* x;      // [nb][18]
   const S* lam;    // [lam_size]
@@ -345,6 +346,8 @@ template <class S> struct StepIn {
   const S* invI;   // [nb][3]
   const S* damp;   // [nj]
   S mu;
+  const S* anc_p;  // [nj][3] hinge point in the parent (or world) frame
+  const S* anc_c;  // [nj][3] hinge point in the child frame
 };
 
 template <class S>
@@ -410,8 +413,8 @@ void step_env(const Model& M, const EnvTopo& E, const StepIn<S>& in, S* xn, S* l
       const int pa = c.joint_parent[gj], b = c.joint_child[gj] - E.b0;
       const int a = pa >= 0 ? pa - E.b0 : -1;
       C.kind = 0; C.nrows = 5; C.store = 5 * jl;
-      const V3<S> rb = B.R[b] * cvt<S>(c.anchor_c + 3 * gj);
-      V3<S> ra, Pa = cvt<S>(c.anchor_p + 3 * gj);
+      const V3<S> rb = B.R[b] * V3<S>(in.anc_c[3 * jl], in.anc_c[3 * jl + 1], in.anc_c[3 * jl + 2]);
+      V3<S> ra, Pa = V3<S>(in.anc_p[3 * jl], in.anc_p[3 * jl + 1], in.anc_p[3 * jl + 2]);
       if (a >= 0) { ra = B.R[a] * Pa; Pa = B.p[a] + ra; }
       const V3<S> err = (B.p[b] + rb) - Pa;
       const V3<S> e3[3] = {ex, ey, ez};
@@ -767,6 +770,8 @@ static S rollout_env(const Ctx& C, int e, std::vector<S>& x, std::vector<S>& lam
   const std::vector<S> invm = to_s<S>(c.inv_mass + E.b0, E.nb);
   const std::vector<S> invI = to_s<S>(c.inv_inertia + 3 * E.b0, 3 * E.nb);
   const std::vector<S> damp = to_s<S>(c.damping + E.j0, E.nj);
+  const std::vector<S> ap = to_s<S>(c.anchor_p + 3 * E.j0, 3 * E.nj);
+  const std::vector<S> ac = to_s<S>(c.anchor_c + 3 * E.j0, 3 * E.nj);
   std::vector<S> W;
   if (c.ctrl_kind == 1) W = to_s<S>(c.mlp_w, c.mlp_n_params);
   S L = S(0.0);
@@ -776,7 +781,8 @@ static S rollout_env(const Ctx& C, int e, std::vector<S>& x, std::vector<S>& lam
     std::vector<S> u(E.nj);
     if (c.ctrl_kind == 0)
       for (int j = 0; j < E.nj; ++j) u[j] = S(c.u[(size_t)t * c.u_stride + E.j0 + j]);
-    StepIn<S> in{x.data(), lam.data(), u.data(), invm.data(), invI.data(), damp.data(), S(c.mu[e])};
+    StepIn<S> in{x.data(), lam.data(), u.data(), invm.data(), invI.data(), damp.data(), S(c.mu[e]),
+                 ap.data(), ac.data()};
     step_env(C.M, E, in, xn.data(), ln.data(), W.data(), t, stats);
     if (c.noise > 0.0)
       for (int i = 0; i < n; ++i) xn[i] = xn[i] * S(1.0 + c.noise * noise_r(c.noise_seed, e, t, i));
@@ -825,7 +831,7 @@ int oracle_step(const oracle_model* m, const double* x, const double* lam, const
   for (int e = 0; e < m->n_envs; ++e) {
     const EnvTopo& E = C.topo[e];
     StepIn<double> in{x + 18 * E.b0, lam + E.lam_off, u + E.j0, m->inv_mass + E.b0, m->inv_inertia + 3 * E.b0,
-                      m->damping + E.j0, m->mu[e]};
+                      m->damping + E.j0, m->mu[e], m->anchor_p + 3 * E.j0, m->anchor_c + 3 * E.j0};
     step_env<double>(C.M, E, in, xn + 18 * E.b0, lamn + E.lam_off, m->mlp_w, t);
   }
   return 0;
@@ -910,7 +916,7 @@ void oracle_wsn_forward(const double* w, const double* x, int stride, int n, dou
 // the state and of the warm-start impulses.
 int oracle_rollout_grad(const oracle_model* m, const double* x0, const double* dloss, double* loss_env,
                         double* g_x0, double* g_u, double* g_inv_mass, double* g_inv_inertia, double* g_mu,
-                        double* g_damping, double* g_w, int n_threads) {
+                        double* g_damping, double* g_w, double* g_anchor_p, double* g_anchor_c, int n_threads) {
   if (m->solve_mode != 0) return -1;  // the gradient is of the fixed-sweep map
   Ctx C;
   build_ctx(m, C);
@@ -929,14 +935,15 @@ int oracle_rollout_grad(const oracle_model* m, const double* x0, const double* d
     if (loss_env) loss_env[e] = L;
     const double dl = dloss ? dloss[e] : 1.0;
     std::vector<double> xbar(n, 0.0), lbar(E.lam_size, 0.0);
-    std::vector<double> gm(E.nb, 0.0), gI(3 * E.nb, 0.0), gd(E.nj, 0.0), gW;
+    std::vector<double> gm(E.nb, 0.0), gI(3 * E.nb, 0.0), gd(E.nj, 0.0), gap(3 * E.nj, 0.0), gac(3 * E.nj, 0.0), gW;
     double gmu = 0.0;
     if (c.ctrl_kind == 1) gW.assign(c.mlp_n_params, 0.0);
     Tape tp;
     tape() = &tp;
     for (int t = T - 1; t >= 0; --t) {
       tp.clear();
-      std::vector<Var> xv(n), lv(E.lam_size), uv(E.nj), mv(E.nb), Iv(3 * E.nb), dv(E.nj), Wv;
+      std::vector<Var> xv(n), lv(E.lam_size), uv(E.nj), mv(E.nb), Iv(3 * E.nb), dv(E.nj), apv(3 * E.nj),
+          acv(3 * E.nj), Wv;
       for (int i = 0; i < n; ++i) xv[i] = Var::input(xs[(size_t)t * n + i]);
       for (int i = 0; i < E.lam_size; ++i) lv[i] = Var::input(ls[(size_t)t * E.lam_size + i]);
       for (int j = 0; j < E.nj; ++j)
@@ -944,6 +951,8 @@ int oracle_rollout_grad(const oracle_model* m, const double* x0, const double* d
       for (int b = 0; b < E.nb; ++b) mv[b] = Var::input(c.inv_mass[E.b0 + b]);
       for (int i = 0; i < 3 * E.nb; ++i) Iv[i] = Var::input(c.inv_inertia[3 * E.b0 + i]);
       for (int j = 0; j < E.nj; ++j) dv[j] = Var::input(c.damping[E.j0 + j]);
+      for (int i = 0; i < 3 * E.nj; ++i) apv[i] = Var::input(c.anchor_p[3 * E.j0 + i]);
+      for (int i = 0; i < 3 * E.nj; ++i) acv[i] = Var::input(c.anchor_c[3 * E.j0 + i]);
       const Var muv = Var::input(c.mu[e]);
       if (c.ctrl_kind == 1) {
         Wv.resize(c.mlp_n_params);
@@ -953,7 +962,7 @@ int oracle_rollout_grad(const oracle_model* m, const double* x0, const double* d
       std::vector<Var> x0v(n);
       for (int i = 0; i < n; ++i) x0v[i] = Var(x0[18 * E.b0 + i]);
       std::vector<Var> xn(n), ln(E.lam_size);
-      StepIn<Var> in{xv.data(), lv.data(), uv.data(), mv.data(), Iv.data(), dv.data(), muv};
+      StepIn<Var> in{xv.data(), lv.data(), uv.data(), mv.data(), Iv.data(), dv.data(), muv, apv.data(), acv.data()};
       step_env<Var>(C.M, E, in, xn.data(), ln.data(), Wv.data(), t);
       const Var lt = loss_term<Var>(C.M, E, e, t + 1, T, xn.data(), x0v.data());
       tp.adj.assign(tp.nodes.size(), 0.0);
@@ -968,6 +977,8 @@ int oracle_rollout_grad(const oracle_model* m, const double* x0, const double* d
       for (int b = 0; b < E.nb; ++b) gm[b] += tp.adj[mv[b].id];
       for (int i = 0; i < 3 * E.nb; ++i) gI[i] += tp.adj[Iv[i].id];
       for (int j = 0; j < E.nj; ++j) gd[j] += tp.adj[dv[j].id];
+      for (int i = 0; i < 3 * E.nj; ++i) gap[i] += tp.adj[apv[i].id];
+      for (int i = 0; i < 3 * E.nj; ++i) gac[i] += tp.adj[acv[i].id];
       gmu += tp.adj[muv.id];
       if (c.ctrl_kind == 1)
         for (int i = 0; i < c.mlp_n_params; ++i) gW[i] += tp.adj[Wv[i].id];
@@ -982,6 +993,8 @@ int oracle_rollout_grad(const oracle_model* m, const double* x0, const double* d
     if (g_inv_mass) std::copy(gm.begin(), gm.end(), g_inv_mass + E.b0);
     if (g_inv_inertia) std::copy(gI.begin(), gI.end(), g_inv_inertia + 3 * E.b0);
     if (g_damping) std::copy(gd.begin(), gd.end(), g_damping + E.j0);
+    if (g_anchor_p) std::copy(gap.begin(), gap.end(), g_anchor_p + 3 * E.j0);
+    if (g_anchor_c) std::copy(gac.begin(), gac.end(), g_anchor_c + 3 * E.j0);
     if (g_mu) g_mu[e] = gmu;
     if (c.ctrl_kind == 1) gw_env[e] = std::move(gW);
   });
@@ -1007,7 +1020,10 @@ long long oracle_count_flops(const oracle_model* m, int env, const double* x, co
   for (int j = 0; j < E.nj; ++j) dv[j] = m->damping[E.j0 + j];
   if (m->ctrl_kind == 1) Wv.assign(m->mlp_w, m->mlp_w + m->mlp_n_params);
   std::vector<Cnt> xn(18 * E.nb), ln(E.lam_size);
-  StepIn<Cnt> in{xv.data(), lv.data(), uv.data(), mv.data(), Iv.data(), dv.data(), Cnt(m->mu[env])};
+  std::vector<Cnt> apv(m->anchor_p + 3 * E.j0, m->anchor_p + 3 * (E.j0 + E.nj));
+  std::vector<Cnt> acv(m->anchor_c + 3 * E.j0, m->anchor_c + 3 * (E.j0 + E.nj));
+  StepIn<Cnt> in{xv.data(), lv.data(), uv.data(), mv.data(), Iv.data(), dv.data(), Cnt(m->mu[env]), apv.data(),
+                 acv.data()};
   flop_counter() = 0;
   step_env<Cnt>(C.M, E, in, xn.data(), ln.data(), Wv.data(), t);
   return (long long)flop_counter();
@@ -1033,8 +1049,11 @@ long long oracle_count_tape_edges(const oracle_model* m, int env, const double* 
     Wv.resize(m->mlp_n_params);
     for (int i = 0; i < m->mlp_n_params; ++i) Wv[i] = Var::input(m->mlp_w[i]);
   }
-  std::vector<Var> xn(18 * E.nb), ln(E.lam_size);
-  StepIn<Var> in{xv.data(), lv.data(), uv.data(), mv.data(), Iv.data(), dv.data(), Var::input(m->mu[env])};
+  std::vector<Var> xn(18 * E.nb), ln(E.lam_size), apv(3 * E.nj), acv(3 * E.nj);
+  for (int i = 0; i < 3 * E.nj; ++i) apv[i] = Var::input(m->anchor_p[3 * E.j0 + i]);
+  for (int i = 0; i < 3 * E.nj; ++i) acv[i] = Var::input(m->anchor_c[3 * E.j0 + i]);
+  StepIn<Var> in{xv.data(), lv.data(), uv.data(), mv.data(), Iv.data(), dv.data(), Var::input(m->mu[env]),
+                 apv.data(), acv.data()};
   step_env<Var>(C.M, E, in, xn.data(), ln.data(), Wv.data(), t);
   long long edges = 0;
   for (const auto& n : tp.nodes) edges += (n.a >= 0) + (n.b >= 0);

@@ -74,9 +74,14 @@ int oracle_step(const oracle_model* m, const double* x, const double* lam, const
                 double* lamn, int t);
 int oracle_rollout(const oracle_model* m, const double* x0, double* loss_env, double* x_final,
                    double* lam_final, double* traj /* [T_max+1][B][18] or NULL */, int n_threads);
+/* reverse mode: gradients of sum_e dloss[e] L_e with respect to x0, the
+   torque tape (or the controller weights g_w), 1/m, 1/I, mu, damping and the
+   hinge anchors in the parent and child frames (g_anchor_p, g_anchor_c [J][3]);
+   any output may be NULL */
 int oracle_rollout_grad(const oracle_model* m, const double* x0, const double* dloss, double* loss_env,
                         double* g_x0, double* g_u, double* g_inv_mass, double* g_inv_inertia,
-                        double* g_mu, double* g_damping, double* g_w, int n_threads);
+                        double* g_mu, double* g_damping, double* g_w, double* g_anchor_p, double* g_anchor_c,
+                        int n_threads);
 /* Forward rollout with solver statistics: sweeps per env summed over its
    steps (sweeps discarded by a fallback included), fallbacks per env, and,
    with recs, one record per active contact of every converged step t with

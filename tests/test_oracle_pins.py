@@ -19,7 +19,9 @@ them:
 * frictionless sphere pile with K -> infinity sweeps equals the LCP solution
   found by brute-force enumeration of active sets (projected Gauss-Seidel,
   normal Jacobians, speculative / Baumgarte bias)
-* the reverse-mode gradient equals central finite differences (tape)
+* the reverse-mode gradient equals central finite differences (tape), for
+  the controls, the initial state and the model parameters (masses,
+  inertias, damping, friction and the hinge anchors, i.e. the link lengths)
 * MLP parameter counts printed in the paper (sections 3.2.1, 3.2.2)
 """
 import itertools
@@ -296,6 +298,13 @@ def test_gradient_matches_central_differences_arm():
     assert abs(gr["g_inv_mass"][2] - fd_param("inv_mass", 2)) < 1e-6 * max(1, abs(gr["g_inv_mass"][2]))
     got = gr["g_inv_inertia"].flat[5]
     assert abs(got - fd_param("inv_inertia", 5)) < 1e-6 * max(1, abs(got))
+    # link lengths (section 4): the hinge anchors, the base joint's world
+    # anchor included
+    for name, i in (("anchor_p", 0), ("anchor_p", 1), ("anchor_p", 4), ("anchor_c", 0), ("anchor_c", 7),
+                    ("anchor_c", 3)):
+        got = gr["g_" + name].flat[i]
+        fd = fd_param(name, i)
+        assert abs(got - fd) < 1e-6 * max(1, abs(fd)), (name, i, got, fd)
 
 
 def test_gradient_matches_central_differences_contact_chain():
@@ -323,6 +332,17 @@ def test_gradient_matches_central_differences_contact_chain():
     mm_[0] -= h
     fd = (loss_with(mu=mp) - loss_with(mu=mm_)) / (2 * h)
     assert abs(gr["g_mu"][0] - fd) <= 1e-5 * max(abs(fd), 1e-3), (gr["g_mu"][0], fd)
+    # (contact activations lie within 1e-5 of some anchor values here, so the
+    # anchors take a smaller step; the differences converge to the tape's
+    # value as the step shrinks from 1e-5 to 1e-7)
+    ha = 1e-7
+    for name, i in (("anchor_p", 1), ("anchor_p", 6), ("anchor_c", 2), ("anchor_c", 3)):
+        ap, am = getattr(w, name).copy(), getattr(w, name).copy()
+        ap.flat[i] += ha
+        am.flat[i] -= ha
+        fd = (loss_with(**{name: ap}) - loss_with(**{name: am})) / (2 * ha)
+        got = gr["g_" + name].flat[i]
+        assert abs(got - fd) <= 1e-5 * max(abs(fd), 1e-3), (name, i, got, fd)
     for (b, k) in [(0, 2), (3, 12), (1, 16)]:
         xp, xm = w.x0.copy(), w.x0.copy()
         xp[b, k] += h
@@ -338,3 +358,27 @@ def test_paper_mlp_parameter_counts():
     assert W.mlp_param_count([3, 1024, 1024, 1024, 4]) == 2107396
     # the quadruped controller of the configs: 18 -> 128 -> 128 -> 8
     assert W.mlp_param_count([18, 128, 128, 8]) == 19976
+
+
+def test_anchor_gradient_closed_form():
+    # a sphere at rest centred on a world hinge, no gravity: each point row
+    # acts alone on one velocity component (no lever arm), so one sweep
+    # solves it and the joint error shrinks by (1 - beta) per step.  Moving
+    # the world anchor by d moves the final position by (1 - (1 - beta)^T) d;
+    # moving the child anchor by d moves it by -(1 - (1 - beta)^T) d.
+    T = 40
+    w = W.pendulum(L=1.0, theta0=0.0, T=T)
+    w.gravity = (0.0, 0.0, 0.0)
+    w.anchor_c[:] = 0.0
+    w.x0 = w.x0.copy()
+    w.x0[0, :3] = w.anchor_p[0]
+    w.x0[0, 3:12] = np.eye(3).ravel()
+    w.u = np.zeros((T, 1))
+    w.target = W.f32([[0.3, -0.4, 1.2]])
+    o = Oracle(w)
+    gr = o.rollout_grad()
+    beta = F32(w.beta)
+    k = 1 - (1 - beta) ** T
+    dLdp = 2 * (w.anchor_p[0] - w.target[0])
+    np.testing.assert_allclose(gr["g_anchor_p"][0], k * dLdp, rtol=1e-12, atol=1e-14)
+    np.testing.assert_allclose(gr["g_anchor_c"][0], -k * dLdp, rtol=1e-12, atol=1e-14)
