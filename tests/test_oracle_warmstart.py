@@ -204,7 +204,7 @@ def test_gradient_is_refused_in_tolerance_mode():
     dp = z.ctypes.data_as(C.POINTER(C.c_double))
     x0 = np.ascontiguousarray(o.w.x0, dtype=np.float64)
     rc = lib.oracle_rollout_grad(C.byref(o._m), x0.ctypes.data_as(C.POINTER(C.c_double)), dp, dp, dp, dp, dp,
-                                 dp, dp, dp, None, 1)
+                                 dp, dp, dp, None, None, None, 1)
     assert rc == -1
 
 
