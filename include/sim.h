@@ -14,8 +14,10 @@
  * `rollout` unrolls T steps and accumulates the loss L = sum_t l(x^t, p)
  * (eq. (L)); `rollout_grad` returns the exact reverse-mode derivative of the
  * unrolled discrete map (back-propagation through time, section 2.1.1) with
- * respect to the initial state, the control tape and model parameters
- * (section 4: "masses and lengths" and friction).
+ * respect to the initial state, the control tape (or the controller's
+ * weights) and the model parameters section 4 names, masses and lengths:
+ * inverse masses and inertias, the hinge anchors (the link lengths), joint
+ * damping and the friction coefficient.
  *
  * Conventions for every call:
  *  - Arrays marked (device) are device pointers (hipMalloc / torch CUDA
@@ -53,7 +55,7 @@
 extern "C" {
 #endif
 
-#define SIM_ABI_VERSION 2
+#define SIM_ABI_VERSION 3
 
 typedef struct sim_model* sim_handle;
 
@@ -257,7 +259,9 @@ sim_status rollout_solve(sim_handle h, const float* x0, const float* u, float* l
  * x0 and u, and dL/dloss_env (device [E]), writes (each may be NULL):
  *   g_x0[18][B], g_u[T_max][J] (entries beyond an env's T_e are zero) or,
  *   for SIM_CTRL_MLP, dL/dW [n_params] summed over envs (the paper's dL/dW,
- *   section 2.2), g_inv_mass[B], g_inv_inertia[B][3], g_mu[E], g_damping[J]
+ *   section 2.2), g_inv_mass[B], g_inv_inertia[B][3], g_mu[E], g_damping[J],
+ *   g_anchor_p[J][3] and g_anchor_c[J][3] (the hinge anchors in the parent,
+ *   or world, frame and in the child frame: the link lengths of section 4)
  *   (device).
  * env_flags[E] (device, may be NULL) is overwritten: SIM_FLAG_GRAD_NONFINITE
  * for an env whose adjoint overflowed or exceeded 1e30 (the gradient of a
@@ -272,8 +276,9 @@ sim_status rollout_solve(sim_handle h, const float* x0, const float* u, float* l
  * of all segments (k_recompute), then the reverse sweep (k_rollout_grad). */
 sim_status rollout_grad(sim_handle h, const float* x0, const float* u, const float* ckpt,
                         const float* dloss_env, float* g_x0, float* g_u, float* g_inv_mass,
-                        float* g_inv_inertia, float* g_mu, float* g_damping, void* workspace,
-                        size_t workspace_bytes, uint32_t* env_flags, void* stream);
+                        float* g_inv_inertia, float* g_mu, float* g_damping, float* g_anchor_p,
+                        float* g_anchor_c, void* workspace, size_t workspace_bytes, uint32_t* env_flags,
+                        void* stream);
 
 /* Device timing of rollout_grad's phases.  While set, every rollout_grad call
  * on h records, on its stream, ev[0] and ev[1] around the recompute of all

@@ -22,18 +22,23 @@ HIPCC_FLAGS = [
 
 def build(verbose: bool = False) -> str:
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    objs = []
     bdir = os.path.join(HERE, "_build")
     os.makedirs(bdir, exist_ok=True)
+    cmds, objs = [], []
     for src in SOURCES:
         obj = os.path.join(bdir, src + ".o")
-        lang = ["-x", "hip"] if src.endswith(".hip") else ["-x", "hip"]
-        cmd = [hipcc] + HIPCC_FLAGS + lang + ["-I", os.path.join(ROOT, "include"), "-c",
-                                               os.path.join(CSRC, src), "-o", obj]
+        cmds.append([hipcc] + HIPCC_FLAGS + ["-x", "hip", "-I", os.path.join(ROOT, "include"), "-c",
+                                             os.path.join(CSRC, src), "-o", obj])
+        objs.append(obj)
+    # the translation units are independent: compile them at once
+    procs = []
+    for cmd in cmds:
         if verbose:
             print(" ".join(cmd), flush=True)
-        subprocess.check_call(cmd)
-        objs.append(obj)
+        procs.append(subprocess.Popen(cmd))
+    failed = [c for c, p in zip(cmds, procs) if p.wait() != 0]
+    if failed:
+        raise subprocess.CalledProcessError(1, failed[0])
     tmp = OUT + ".tmp"
     cmd = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
     if verbose:

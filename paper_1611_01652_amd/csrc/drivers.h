@@ -35,6 +35,8 @@ struct GradArgs {
   float* g_invI;       // [B][3]
   float* g_mu;         // [E]
   float* g_damp;       // [J]
+  float* g_anc_p;      // [J][3] hinge anchors in the parent (world) frame
+  float* g_anc_c;      // [J][3] hinge anchors in the child frame
   float* seg;          // per-env segment buffers
   uint32_t* flags;     // [E] or null: SIM_FLAG_GRAD_NONFINITE for envs whose adjoint overflowed
 };
@@ -275,7 +277,7 @@ SHD_FLAT void env_rollout_grad(const Team& tm, const DevModel& M, const Env& E, 
     load_env_static(tm, M, E);
     for (int i = tm.tl; i < (E.nb + 1) * BSA; i += tm.ts) E.L[E.lay.bodyA + i] = 0.f;
     for (int i = tm.tl; i < E.lam_size; i += tm.ts) E.wsA()[i] = 0.f;
-    for (int i = tm.tl; i < 2 * E.nj; i += tm.ts) E.jA()[i] = 0.f;
+    for (int i = tm.tl; i < JA_FLOATS * E.nj; i += tm.ts) E.jA()[i] = 0.f;
     if (tm.tl == 0) E.misc()[MISC_GMU] = E.misc()[MISC_GMUC] = 0.f;
   }
   tm.sync();
@@ -377,7 +379,12 @@ SHD_FLAT void env_rollout_grad(const Team& tm, const DevModel& M, const Env& E, 
       for (int k = 0; k < 18; ++k) bad = bad || !(fabsf(A[k]) <= ADJ_LIMIT);
       for (int k = 0; k < 4; ++k) bad = bad || !(fabsf(A[ATM + k]) <= ADJ_LIMIT);
     }
-    for (int j = tm.tl; j < E.nj; j += tm.ts) bad = bad || !(fabsf(E.jA()[j]) <= ADJ_LIMIT);
+    for (int j = tm.tl; j < E.nj; j += tm.ts) {
+      bad = bad || !(fabsf(E.jA()[JA_DAMP * E.nj + j]) <= ADJ_LIMIT);
+      for (int k = 0; k < 3; ++k)
+        bad = bad || !(fabsf(E.jA()[JA_ANCP * E.nj + 3 * j + k]) <= ADJ_LIMIT) ||
+              !(fabsf(E.jA()[JA_ANCC * E.nj + 3 * j + k]) <= ADJ_LIMIT);
+    }
     if (tm.tl == 0) bad = bad || !(fabsf(E.misc()[MISC_GMU]) <= ADJ_LIMIT);
   }
   bad = tm.team_any(bad);
@@ -391,7 +398,11 @@ SHD_FLAT void env_rollout_grad(const Team& tm, const DevModel& M, const Env& E, 
         for (int k = 0; k < 3; ++k) a.g_invI[3 * (E.b0 + b) + k] = bad ? 0.f : A[ATI + k];
     }
     if (a.g_damp)
-      for (int j = tm.tl; j < E.nj; j += tm.ts) a.g_damp[E.j0 + j] = bad ? 0.f : E.jA()[j];
+      for (int j = tm.tl; j < E.nj; j += tm.ts) a.g_damp[E.j0 + j] = bad ? 0.f : E.jA()[JA_DAMP * E.nj + j];
+    if (a.g_anc_p)
+      for (int i = tm.tl; i < 3 * E.nj; i += tm.ts) a.g_anc_p[3 * E.j0 + i] = bad ? 0.f : E.jA()[JA_ANCP * E.nj + i];
+    if (a.g_anc_c)
+      for (int i = tm.tl; i < 3 * E.nj; i += tm.ts) a.g_anc_c[3 * E.j0 + i] = bad ? 0.f : E.jA()[JA_ANCC * E.nj + i];
     if (tm.tl == 0 && a.g_mu) a.g_mu[E.e] = bad ? 0.f : E.misc()[MISC_GMU];
     if (tm.tl == 0 && a.flags) a.flags[E.e] = bad ? 4u : 0u;
     if (bad && a.g_u && !M.ctrl)

@@ -609,8 +609,8 @@ sim_status rollout_solve(sim_handle h, const float* x0, const float* u, float* l
 
 sim_status rollout_grad(sim_handle h, const float* x0, const float* u, const float* ckpt, const float* dloss_env,
                         float* g_x0, float* g_u, float* g_inv_mass, float* g_inv_inertia, float* g_mu,
-                        float* g_damping, void* workspace, size_t workspace_bytes, uint32_t* env_flags,
-                        void* stream) {
+                        float* g_damping, float* g_anchor_p, float* g_anchor_c, void* workspace,
+                        size_t workspace_bytes, uint32_t* env_flags, void* stream) {
   if (!h) return fail(SIM_E_ARG, "rollout_grad: null handle");
   if (h->M.n_envs == 0) return SIM_OK;
   if (h->M.solve_mode != SIM_SOLVE_FIXED)
@@ -624,7 +624,8 @@ sim_status rollout_grad(sim_handle h, const float* x0, const float* u, const flo
   if (s != SIM_OK) return s;
   hipStream_t st = (hipStream_t)stream;
   float* ws = (float*)workspace;
-  GradArgs a{x0, u, ckpt, dloss_env, g_x0, g_u, g_inv_mass, g_inv_inertia, g_mu, g_damping, ws, env_flags};
+  GradArgs a{x0,   u,    ckpt,          dloss_env, g_x0,      g_u,        g_inv_mass,
+             g_inv_inertia, g_mu, g_damping, g_anchor_p, g_anchor_c, ws, env_flags};
   DevModel M = h->M;
   if (!prep_controls(h, M, u, st)) return check_device("rollout_grad controls");
   M.tape = ws + h->seg_floats;
@@ -782,7 +783,7 @@ int32_t sim_tune(sim_handle h, const float* x0, const float* u, int32_t with_gra
   if (!prep_controls(h, M, u, st)) { cleanup(); return check_device("sim_tune controls"); }
   M.tape = ws ? ws + h->seg_floats : nullptr;
   const RolloutArgs ra{x0, u, loss, nullptr, nullptr, ck, nullptr, nullptr, nullptr, RecArgs{nullptr, 0, nullptr, 0}};
-  const GradArgs ga{x0, u, ck, dl, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, ws, nullptr};
+  const GradArgs ga{x0, u, ck, dl, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, ws, nullptr};
   // every bucket once at its current width: warms the code and writes the checkpoints
   for (int i = 0; i < n; ++i)
     if (!bucket_rollout(h, i, M, ra, st)) { cleanup(); return check_device("sim_tune rollout"); }

@@ -69,6 +69,10 @@ SHD f3 mv(const float* R, f3 v) {
   return mk3(R[0] * v.x + R[1] * v.y + R[2] * v.z, R[3] * v.x + R[4] * v.y + R[5] * v.z,
              R[6] * v.x + R[7] * v.y + R[8] * v.z);
 }
+SHD f3 mtv(const float* R, f3 v) {
+  return mk3(R[0] * v.x + R[3] * v.y + R[6] * v.z, R[1] * v.x + R[4] * v.y + R[7] * v.z,
+             R[2] * v.x + R[5] * v.y + R[8] * v.z);
+}
 // symmetric 3x3 stored as xx yy zz xy xz yz
 SHD f3 sv(const float* S, f3 v) {
   return mk3(S[0] * v.x + S[3] * v.y + S[4] * v.z, S[3] * v.x + S[1] * v.y + S[5] * v.z,
@@ -172,6 +176,12 @@ enum { MISC_LOSS = 0, MISC_FLAGS = 1, MISC_NCON = 2, MISC_MU = 3, MISC_GMU = 4, 
        MISC_FB = 7, MISC_N = 8 };
 
 SHD int align4(int x) { return (x + 3) & ~3; }
+// Per-joint parameter adjoints of the reverse sweep, running totals over the
+// trajectory with their compensation terms (Kahan), in units of nj floats:
+// damping total [0, 1), damping compensation [1, 2), anchor in the parent
+// frame (3 per joint) [2, 5), anchor in the child frame [5, 8), and the
+// compensations of the anchors [8, 11) and [11, 14).
+enum { JA_DAMP = 0, JA_DAMPC = 1, JA_ANCP = 2, JA_ANCC = 5, JA_ANC_COMP = 6, JA_FLOATS = 14 };
 // mlp_f / mlp_a: controller floats per env (s, h1, h2 / du, d2, d1, sbar), 0 without one
 // vs_f: floats of saved predicted velocities (learned warm start), 0 without
 SHD Lay make_lay(int nb, int nj, int G, int P, int ncol, int ncand, int nslot, int lam, int n_iters, bool adj,
@@ -200,7 +210,7 @@ SHD Lay make_lay(int nb, int nj, int G, int P, int ncol, int ncand, int nslot, i
     o += align4(nslot);   // hist(-1): the sweeps' start impulses (reverse only)
     L.hist = o; o += align4(n_iters * nslot);
     L.wsA = o; o += align4(lam);
-    L.jA = o; o += align4(2 * nj);   // damping adjoint total and compensation
+    L.jA = o; o += align4(JA_FLOATS * nj);   // per-joint parameter adjoint totals and compensations
     L.mlpA = o; o += align4(mlp_a);
   } else {
     L.bodyA = L.rowsA = L.hist = L.wsA = L.jA = L.mlpA = o;
@@ -2347,6 +2357,18 @@ SHD void a_joint(const Team& tm, const DevModel& M, const Env& E, int j, int s) 
   // ax = na x nbw
   const f3 nab = cross(nbw, axb);
   const f3 nbb = cross(axb, na);
+  // The anchors (the link lengths): r_b = R_b a_c and r_a = R_a a_p give
+  // a_c-bar = R_b^T r_b-bar and a_p-bar = R_a^T r_a-bar; a world-attached
+  // joint's point a_p enters the error alone, -errbar.  Each side adds its
+  // own anchor's totals (a lane of a pair: its side only).
+  for (int i = 0; i < NS; ++i) {
+    const f3 g = sd[i] ? mtv(Bb + BR, rx[i]) : (ha ? mtv(Ba + BR, rx[i]) : -errb);
+    float* tot = E.jA() + (sd[i] ? JA_ANCC : JA_ANCP) * E.nj + 3 * j;
+    float* cmp = tot + JA_ANC_COMP * E.nj;
+    kahan_add(tot, cmp, g.x);
+    kahan_add(tot + 1, cmp + 1, g.y);
+    kahan_add(tot + 2, cmp + 2, g.z);
+  }
   // The bodies' adjoints, each read and written once with 16-byte accesses;
   // every element takes its additions in the order of the adjoint's terms.
   for (int i = 0; i < NS; ++i) {
@@ -2522,7 +2544,7 @@ SHD void a_predict_torques(const Team& tm, const DevModel& M, const Env& E, bool
         g_u_row[E.j0 + j] = taub;
         a_predict_torques_flag(bad, taub);
       }
-      kahan_add(E.jA() + j, E.jA() + E.nj + j, -taub * dot(wrel, n));
+      kahan_add(E.jA() + JA_DAMP * E.nj + j, E.jA() + JA_DAMPC * E.nj + j, -taub * dot(wrel, n));
       add3(Ab + AW, -(taub * dmp) * n);
       if (a >= 0) {
         float* Aa = E.bodyA(a);

@@ -20,7 +20,7 @@ FLAG_NONFINITE = 1
 FLAG_CONTACT_OVERFLOW = 2
 
 # layout of the descriptor and info structs below (SIM_ABI_VERSION)
-ABI_VERSION = 2
+ABI_VERSION = 3
 
 # reverse sweep memory modes (sim_model_desc.grad_store)
 GRAD_STORE = {"auto": 0, "replay": 1, "segment": 2, "trajectory": 3}
@@ -146,7 +146,7 @@ def library():
     lib.sim_lambda_offsets.argtypes = [vp, _I32P]
     lib.sim_step.argtypes = [vp, vp, vp, vp, vp, vp, C.c_int32, vp, vp]
     lib.rollout.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp]
-    lib.rollout_grad.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, C.c_size_t, vp, vp]
+    lib.rollout_grad.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, C.c_size_t, vp, vp]
     lib.rollout_solve.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, C.c_int64, vp, C.c_int32, vp]
     lib.sim_describe_order.argtypes = [C.POINTER(SimDesc), C.c_int32, _I32P, _I32P, C.c_int32]
     lib.sim_describe_order.restype = C.c_int32
@@ -303,10 +303,12 @@ class Simulator:
         nu = self.info.n_params if self.info.n_params else self.w.T_max * J
         g = dict(g_x0=self._f32(18 * B).view(18, -1), g_u=self._f32(nu),
                  g_inv_mass=self._f32(B), g_inv_inertia=self._f32(3 * B), g_mu=self._f32(E), g_damping=self._f32(J),
+                 g_anchor_p=self._f32(3 * J), g_anchor_c=self._f32(3 * J),
                  flags=self.torch.zeros(max(E, 1), dtype=self.torch.int32, device="cuda"))
         st = self.lib.rollout_grad(self.h, _ptr(x0), _ptr(u), _ptr(ckpt), _ptr(dloss), _ptr(g["g_x0"]),
                                    _ptr(g["g_u"]), _ptr(g["g_inv_mass"]), _ptr(g["g_inv_inertia"]), _ptr(g["g_mu"]),
-                                   _ptr(g["g_damping"]), _ptr(ws), ws.numel() * 4, _ptr(g["flags"]), self._stream())
+                                   _ptr(g["g_damping"]), _ptr(g["g_anchor_p"]), _ptr(g["g_anchor_c"]), _ptr(ws),
+                                   ws.numel() * 4, _ptr(g["flags"]), self._stream())
         _check(self.lib, st, "rollout_grad")
         if self.info.n_params:
             g["g_u"] = g["g_u"][: self.info.n_params]
@@ -317,6 +319,8 @@ class Simulator:
         g["g_mu"] = g["g_mu"][:E]
         g["flags"] = g["flags"][:E]
         g["g_damping"] = g["g_damping"][:J]
+        g["g_anchor_p"] = g["g_anchor_p"][: 3 * J].view(J, 3)
+        g["g_anchor_c"] = g["g_anchor_c"][: 3 * J].view(J, 3)
         return g
 
     def time_grad(self, events):

@@ -34,7 +34,7 @@ GRAD_TOL = 1e-3
 # point-mass spheres of the arm it is a long sum of nearly cancelling terms
 # whose FP32 evaluation loses about three more digits than the others.
 GRAD_TOL_INERTIA = 3e-3
-GRAD_KEYS = ("g_x0", "g_u", "g_inv_mass", "g_mu", "g_damping")
+GRAD_KEYS = ("g_x0", "g_u", "g_inv_mass", "g_mu", "g_damping", "g_anchor_p", "g_anchor_c")
 GROUPS = {"p": slice(0, 3), "R": slice(3, 12), "v": slice(12, 15), "w": slice(15, 18)}
 FLOORS = np.array([1e-2, 1e-2, 0.2, 1.0])
 
@@ -71,6 +71,8 @@ def gpu_run(w, grad=True, dloss=None, sim=None):
         out["g_inv_inertia"] = g["g_inv_inertia"].cpu().numpy().astype(np.float64)
         out["g_mu"] = g["g_mu"].cpu().numpy().astype(np.float64)
         out["g_damping"] = g["g_damping"].cpu().numpy().astype(np.float64)
+        out["g_anchor_p"] = g["g_anchor_p"].cpu().numpy().astype(np.float64)
+        out["g_anchor_c"] = g["g_anchor_c"].cpu().numpy().astype(np.float64)
     torch.cuda.synchronize()
     return out
 
@@ -98,7 +100,8 @@ def state_errors(w, got, ref):
     return err.max(axis=1)
 
 
-def grad_errors(w, got, ref, keys=("g_x0", "g_u", "g_inv_mass", "g_inv_inertia", "g_mu", "g_damping")):
+def grad_errors(w, got, ref, keys=("g_x0", "g_u", "g_inv_mass", "g_inv_inertia", "g_mu", "g_damping", "g_anchor_p",
+                                   "g_anchor_c")):
     """[E] worst per-array relative gradient error of each env."""
     out = np.zeros(w.n_envs)
     for e in range(w.n_envs):
@@ -116,7 +119,7 @@ def grad_errors(w, got, ref, keys=("g_x0", "g_u", "g_inv_mass", "g_inv_inertia",
                 errs.append(rel(got[k][b0:b1], ref[k][b0:b1]))
             elif k == "g_mu":
                 errs.append(rel(got[k][e:e + 1], ref[k][e:e + 1]))
-            elif k == "g_damping" and j1 > j0:
+            elif k in ("g_damping", "g_anchor_p", "g_anchor_c") and j1 > j0:
                 errs.append(rel(got[k][j0:j1], ref[k][j0:j1]))
         out[e] = max(errs) if errs else 0.0
     return out

@@ -163,7 +163,8 @@ int kh_sizes(const sim_model_desc* d, long long* out) {
   return 0;
 }
 int kh_rollout_grad(const sim_model_desc* d, const double* x0, const double* u, const double* dloss, double* loss,
-                    double* xf, double* gx0, double* gu, double* gm, double* gI, double* gmu, double* gd) {
+                    double* xf, double* gx0, double* gu, double* gm, double* gI, double* gmu, double* gd,
+                    double* gap, double* gac) {
   Host h;
   if (!make(d, h)) return -1;
   const int n_ckpt = d->T_max > 0 ? (d->T_max - 1) / d->ckpt_every + 1 : 1;
@@ -176,7 +177,7 @@ int kh_rollout_grad(const sim_model_desc* d, const double* x0, const double* u, 
     h.M.tape = tape.data();
   }
   RolloutArgs ra{x0, u, loss, xf, lf.data(), ckpt.data(), nullptr, nullptr, nullptr, RecArgs{nullptr, 0, nullptr, 0}};
-  GradArgs ga{x0, u, ckpt.data(), dloss, gx0, gu, gm, gI, gmu, gd, seg.data(), nullptr};
+  GradArgs ga{x0, u, ckpt.data(), dloss, gx0, gu, gm, gI, gmu, gd, gap, gac, seg.data(), nullptr};
   for (int ie = 0; ie < d->n_envs; ++ie) {
     std::vector<double> lds(h.P.adj_of[ie] + 16);
     Env E = make_env(h.M, ie, lds.data(), h.M.n_iters, false);

@@ -111,10 +111,11 @@ def host_fp64(w):
         gu0 = np.zeros((max(w.T_max, 1), max(J, 1)))
     out = dict(loss=np.zeros(E), x_final=np.zeros((18, B)), g_x0=np.zeros((18, B)),
                g_u=gu0, g_inv_mass=np.zeros(B), g_inv_inertia=np.zeros((B, 3)),
-               g_mu=np.zeros(E), g_damping=np.zeros(max(J, 1)))
+               g_mu=np.zeros(E), g_damping=np.zeros(max(J, 1)), g_anchor_p=np.zeros((max(J, 1), 3)),
+               g_anchor_c=np.zeros((max(J, 1), 3)))
     st = lib.kh_rollout_grad(C.byref(d), p(x0), p(u), p(np.ones(E)), p(out["loss"]), p(out["x_final"]),
                              p(out["g_x0"]), p(out["g_u"]), p(out["g_inv_mass"]), p(out["g_inv_inertia"]),
-                             p(out["g_mu"]), p(out["g_damping"]))
+                             p(out["g_mu"]), p(out["g_damping"]), p(out["g_anchor_p"]), p(out["g_anchor_c"]))
     assert st == 0
     out["x_final"] = out["x_final"].T
     out["g_x0"] = out["g_x0"].T
@@ -123,6 +124,8 @@ def host_fp64(w):
     else:
         out["g_u"] = out["g_u"][:, :J]
     out["g_damping"] = out["g_damping"][:J]
+    out["g_anchor_p"] = out["g_anchor_p"][:J]
+    out["g_anchor_c"] = out["g_anchor_c"][:J]
     return out
 
 
@@ -188,7 +191,7 @@ def test_kernel_source_in_fp64_equals_oracle(maker, tol):
     roll = o.rollout()
     assert _rel(got["loss"], ref["loss"]) < tol
     assert _rel(got["x_final"], roll["x_final"]) < tol
-    for k in ("g_x0", "g_u", "g_inv_mass", "g_inv_inertia", "g_mu", "g_damping", "g_w"):
+    for k in ("g_x0", "g_u", "g_inv_mass", "g_inv_inertia", "g_mu", "g_damping", "g_w", "g_anchor_p", "g_anchor_c"):
         if k in ref and k in got and ref[k].size:
             assert _rel(got[k], ref[k]) < tol, (k, _rel(got[k], ref[k]))
 
