@@ -80,6 +80,7 @@ class _Model(C.Structure):
         ("warm", C.c_double), ("noise", C.c_double), ("noise_seed", C.c_int),
         ("solve_mode", C.c_int), ("tol", C.c_double), ("max_iters", C.c_int),
         ("ws_kind", C.c_int), ("ws_w", C.c_void_p), ("fb_iters", C.c_int), ("fb_tol", C.c_double),
+        ("lam0", C.c_void_p),
     ]
 
 
@@ -93,7 +94,9 @@ def _dp(a):
 class Oracle:
     """Wraps one workload; arrays are converted to float64/int32 once."""
 
-    def __init__(self, w, mlp=None, noise=0.0, noise_seed=0, ws_w=None):
+    def __init__(self, w, mlp=None, noise=0.0, noise_seed=0, ws_w=None, lam0=None):
+        """lam0: warm-start impulses at the start of every rollout ([lam_size],
+        the layout of lam_offsets), zeros if None."""
         self.w = w
         keep = {}
 
@@ -166,6 +169,8 @@ class Oracle:
             m.fb_tol = float((ws or {}).get("fb_tol", 1e-3))
         else:
             m.ws_w = d("wsw", np.zeros(1))
+        if lam0 is not None:
+            m.lam0 = d("lam0", lam0)
         self._m = m
         self._keep = keep
         self.lib = _load()

@@ -795,6 +795,12 @@ static S rollout_env(const Ctx& C, int e, std::vector<S>& x, std::vector<S>& lam
   return L;
 }
 
+// Warm-start impulses of an env at the start of a rollout: given, or zeros.
+static std::vector<double> start_impulses(const oracle_model& m, const EnvTopo& E) {
+  if (!m.lam0) return std::vector<double>(E.lam_size, 0.0);
+  return std::vector<double>(m.lam0 + E.lam_off, m.lam0 + E.lam_off + E.lam_size);
+}
+
 }  // namespace orc
 
 using namespace orc;
@@ -846,7 +852,7 @@ int oracle_rollout(const oracle_model* m, const double* x0, double* loss_env, do
   parallel_envs(m->n_envs, n_threads, [&](int e) {
     const EnvTopo& E = C.topo[e];
     std::vector<double> x(x0 + 18 * E.b0, x0 + 18 * (E.b0 + E.nb));
-    std::vector<double> lam(E.lam_size, 0.0);
+    std::vector<double> lam = start_impulses(*m, E);
     const double L = rollout_env<double>(C, e, x, lam, nullptr, nullptr, traj);
     if (loss_env) loss_env[e] = L;
     if (x_final) std::copy(x.begin(), x.end(), x_final + 18 * E.b0);
@@ -864,7 +870,7 @@ long long oracle_rollout_ex(const oracle_model* m, const double* x0, double* los
   parallel_envs(m->n_envs, n_threads, [&](int e) {
     const EnvTopo& E = C.topo[e];
     std::vector<double> x(x0 + 18 * E.b0, x0 + 18 * (E.b0 + E.nb));
-    std::vector<double> lam(E.lam_size, 0.0);
+    std::vector<double> lam = start_impulses(*m, E);
     StepStats st;
     st.env = e;
     st.rec_every = recs ? rec_every : 0;
@@ -928,7 +934,7 @@ int oracle_rollout_grad(const oracle_model* m, const double* x0, const double* d
     const EnvTopo& E = C.topo[e];
     const int n = 18 * E.nb, T = c.T_env[e];
     std::vector<double> xs, ls;
-    std::vector<double> x(x0 + 18 * E.b0, x0 + 18 * (E.b0 + E.nb)), lam(E.lam_size, 0.0);
+    std::vector<double> x(x0 + 18 * E.b0, x0 + 18 * (E.b0 + E.nb)), lam = start_impulses(*m, E);
     xs.reserve((size_t)T * n);
     ls.reserve((size_t)T * E.lam_size);
     const double L = rollout_env<double>(C, e, x, lam, &xs, &ls, nullptr);

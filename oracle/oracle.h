@@ -54,6 +54,10 @@ typedef struct {
   const double *ws_w;         /* W1[64][7] b1[64] W2[64][64] b2[64] W3[3][64] b3[3] */
   int fb_iters;
   double fb_tol;
+  /* warm-start impulses at the start of a rollout ([lam_total], the layout
+     of oracle_lambda_size's offsets); NULL: zeros.  A rollout started from a
+     saved state and impulses continues the trajectory it was saved from. */
+  const double *lam0;
 } oracle_model;
 
 /* Warm-start network shape and training-record layout. */

@@ -382,3 +382,26 @@ def test_anchor_gradient_closed_form():
     dLdp = 2 * (w.anchor_p[0] - w.target[0])
     np.testing.assert_allclose(gr["g_anchor_p"][0], k * dLdp, rtol=1e-12, atol=1e-14)
     np.testing.assert_allclose(gr["g_anchor_c"][0], -k * dLdp, rtol=1e-12, atol=1e-14)
+
+
+def test_rollout_from_a_saved_state_and_impulses_continues_the_trajectory():
+    # stepping k times, then rolling out the remaining T - k steps from the
+    # saved state and carried impulses, reaches the same final state as one
+    # T-step rollout (the split the reverse sweep's segments rely on)
+    w = W.uneven_chains(n_envs=3, T=60, seed_salt=6, sizes=[5, 3, 8])
+    o = Oracle(w)
+    full = o.rollout()
+    x, lam = w.x0.copy(), np.zeros(o.lam_size)
+    k = 37
+    for t in range(k):
+        x, lam = o.step(x, lam, w.u[t], t)
+    assert np.abs(lam).max() > 0
+    rest = w.with_steps(w.T_max - k)
+    rest.u = w.u[k:].copy()
+    rest.x0 = x
+    r = Oracle(rest, lam0=lam).rollout()
+    np.testing.assert_array_equal(r["x_final"], full["x_final"])
+    np.testing.assert_array_equal(r["lam_final"], full["lam_final"])
+    # without the impulses the continuation differs (warm start is part of the state)
+    r0 = Oracle(rest).rollout()
+    assert np.abs(r0["x_final"] - full["x_final"]).max() > 1e-9
