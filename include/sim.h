@@ -288,6 +288,16 @@ sim_status rollout_grad(sim_handle h, const float* x0, const float* u, const flo
  * them alive while they are set; ev = NULL stops the recording. */
 sim_status sim_time_grad(sim_handle h, void* const* ev);
 
+/* Device timing of each size bucket's reverse sweep.  While set, every
+ * rollout_grad call records ev[2 i] and ev[2 i + 1] just before and after
+ * bucket i's reverse sweep kernel, on the stream that kernel runs on.  ev:
+ * 2 n hipEvent_t created by the caller, which keeps them alive while they
+ * are set; n must be the bucket count (sim_get_teams); ev = NULL stops it. */
+sim_status sim_time_buckets(sim_handle h, void* const* ev, int32_t n);
+/* Host: the bucket (0 .. n-1, the order of sim_get_teams) that each env is
+ * scheduled in; bucket_of_env[E]. */
+sim_status sim_env_buckets(sim_handle h, int32_t* bucket_of_env);
+
 /* ---- Replayable step sequences (HIP graphs). ----
  * Captures n_steps consecutive sim_step calls into a HIP graph, for callers
  * that step the simulation in a loop (a policy in the loop, serving): one

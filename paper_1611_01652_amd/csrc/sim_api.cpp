@@ -63,6 +63,7 @@ struct sim_model {
   int n_graphs = 0;             // live step graphs (they hold the tile lists)
   uint16_t* d_wsn = nullptr;    // warm-start network, bfloat16
   hipEvent_t tev[4] = {};       // rollout_grad phase events (sim_time_grad), owned by the caller
+  std::vector<hipEvent_t> bev;  // per-bucket reverse launch events (sim_time_buckets), owned by the caller
   float* d_wt = nullptr;        // controller weights transposed for the forward products
 };
 
@@ -180,7 +181,10 @@ bool bucket_reverse(sim_model* h, size_t i, const DevModel& M, const GradArgs& a
   TileSet ts{b.envs_dev, b.n_tiles, b.floats_adj, h->d_queue + i, 1};
   if (launch_zero(ts.queue, 1, sx) != hipSuccess) return false;
   const long long lds = adj_bytes(M, b.team, b.floats_adj);
-  return launch_rollout_grad(M, ts, b.team, grid_for(h, b, lds), (size_t)lds, a, sx) == hipSuccess;
+  const bool timed = h->bev.size() == 2 * h->buckets.size();
+  if (timed && hipEventRecord(h->bev[2 * i], sx) != hipSuccess) return false;
+  if (launch_rollout_grad(M, ts, b.team, grid_for(h, b, lds), (size_t)lds, a, sx) != hipSuccess) return false;
+  return !timed || hipEventRecord(h->bev[2 * i + 1], sx) == hipSuccess;
 }
 bool bucket_grad(sim_model* h, size_t i, const DevModel& M, const GradArgs& a, hipStream_t sx) {
   return bucket_recompute(h, i, M, a, sx) && bucket_reverse(h, i, M, a, sx);
@@ -654,6 +658,31 @@ sim_status sim_time_grad(sim_handle h, void* const* ev) {
     if (ev && !ev[k]) return fail(SIM_E_ARG, "sim_time_grad: null event");
     h->tev[k] = ev ? (hipEvent_t)ev[k] : nullptr;
   }
+  return SIM_OK;
+}
+
+sim_status sim_time_buckets(sim_handle h, void* const* ev, int32_t n) {
+  if (!h) return fail(SIM_E_ARG, "sim_time_buckets: null handle");
+  if (!ev) {
+    h->bev.clear();
+    return SIM_OK;
+  }
+  if (n != (int32_t)h->buckets.size())
+    return fail(SIM_E_SHAPE, "sim_time_buckets: expected " + std::to_string(h->buckets.size()) + " buckets");
+  std::vector<hipEvent_t> v(2 * (size_t)n);
+  for (size_t k = 0; k < v.size(); ++k) {
+    if (!ev[k]) return fail(SIM_E_ARG, "sim_time_buckets: null event");
+    v[k] = (hipEvent_t)ev[k];
+  }
+  h->bev.swap(v);
+  return SIM_OK;
+}
+
+sim_status sim_env_buckets(sim_handle h, int32_t* bucket_of_env) {
+  if (!h || !bucket_of_env) return fail(SIM_E_ARG, "sim_env_buckets: null argument");
+  for (size_t i = 0; i < h->buckets.size(); ++i)
+    for (int e : h->buckets[i].envs_host)
+      if (e >= 0) bucket_of_env[e] = (int32_t)i;
   return SIM_OK;
 }
 

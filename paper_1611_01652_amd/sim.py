@@ -167,8 +167,10 @@ def library():
     lib.sim_adam.argtypes = [vp, vp, vp, vp, C.c_int64, C.c_int32, C.c_float, C.c_float, C.c_float, C.c_float,
                              C.c_float, vp, vp, vp]
     lib.sim_time_grad.argtypes = [vp, C.POINTER(vp)]
+    lib.sim_time_buckets.argtypes = [vp, C.POINTER(vp), C.c_int32]
+    lib.sim_env_buckets.argtypes = [vp, _I32P]
     for fn in ("sim_time_grad", "sim_init", "sim_destroy", "sim_get_info", "sim_lambda_offsets", "sim_step", "rollout",
-               "rollout_grad", "sim_step_graph", "sim_graph_launch", "sim_graph_destroy", "sim_set_teams",
+               "rollout_grad", "sim_time_buckets", "sim_env_buckets", "sim_step_graph", "sim_graph_launch", "sim_graph_destroy", "sim_set_teams",
                "wsn_to_bf16", "wsn_forward", "wsn_loss_grad", "wsn_adam", "rollout_solve", "sim_adam"):
         getattr(lib, fn).restype = C.c_int
     if lib.sim_abi_version() != ABI_VERSION:
@@ -182,7 +184,7 @@ EXPORTED = ["sim_abi_version", "sim_last_error", "sim_init", "sim_destroy", "sim
             "sim_lambda_offsets", "sim_describe_order", "sim_step", "rollout", "rollout_grad",
             "sim_step_graph", "sim_graph_launch", "sim_graph_destroy", "sim_tune", "sim_get_teams",
             "sim_set_teams", "wsn_to_bf16", "wsn_forward", "wsn_workspace_bytes", "wsn_loss_grad", "wsn_adam",
-            "rollout_solve", "sim_adam", "sim_time_grad"]
+            "rollout_solve", "sim_adam", "sim_time_grad", "sim_time_buckets", "sim_env_buckets"]
 
 
 def describe_order(w, env):
@@ -337,6 +339,26 @@ class Simulator:
             arr = (C.c_void_p * 4)(*raw)
             st = self.lib.sim_time_grad(self.h, arr)
         _check(self.lib, st, "sim_time_grad")
+
+    def time_buckets(self, events):
+        """Record each bucket's reverse sweep kernel on events[2 i], events[2 i + 1]
+        (torch.cuda.Events, recorded once first, alive while set) in every
+        later rollout_grad; None stops it."""
+        if events is None:
+            st = self.lib.sim_time_buckets(self.h, None, 0)
+        else:
+            raw = [int(e.cuda_event) for e in events]
+            if not all(raw):
+                raise ValueError("time_buckets needs created events (record each once first)")
+            arr = (C.c_void_p * len(raw))(*raw)
+            st = self.lib.sim_time_buckets(self.h, arr, len(raw) // 2)
+        _check(self.lib, st, "sim_time_buckets")
+
+    def env_buckets(self):
+        """Bucket index of every env ([E] numpy int32)."""
+        out = np.zeros(max(self.info.n_envs, 1), np.int32)
+        _check(self.lib, self.lib.sim_env_buckets(self.h, out.ctypes.data_as(_I32P)), "sim_env_buckets")
+        return out[: self.info.n_envs]
 
     def step(self, x, u, lam, t_index=0):
         t = self.torch
