@@ -280,6 +280,26 @@ sim_status rollout_grad(sim_handle h, const float* x0, const float* u, const flo
                         float* g_anchor_c, void* workspace, size_t workspace_bytes, uint32_t* env_flags,
                         void* stream);
 
+/* Allocation-free reverse mode, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving or training loops,
+ * harnesses that forbid hipMalloc): rollout_grad with the same arguments and
+ * results, except that its workspace is a scratch array of
+ * SIM_NOALLOC_SCRATCH_BYTES in the library's own device memory, one per GPU,
+ * set up by sim_init and held until the process ends.  The call itself
+ * allocates and frees nothing.  Returns SIM_E_NOMEM, before any launch, when
+ * the model's sim_info.workspace_bytes exceeds SIM_NOALLOC_SCRATCH_BYTES (pick
+ * grad_store = SIM_GRAD_REPLAY or a grad_mem_limit that fits), and
+ * SIM_E_STATE when the handle's device is not the current one.  Every call on
+ * a GPU shares that GPU's scratch, which keeps the last call's contents
+ * (nothing in it needs to start at zero): calls that overlap on one GPU,
+ * from any handle, thread or stream, race and must be serialised by the
+ * caller. */
+#define SIM_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+sim_status rollout_grad_noalloc(sim_handle h, const float* x0, const float* u, const float* ckpt,
+                                const float* dloss_env, float* g_x0, float* g_u, float* g_inv_mass,
+                                float* g_inv_inertia, float* g_mu, float* g_damping, float* g_anchor_p,
+                                float* g_anchor_c, uint32_t* env_flags, void* stream);
+
 /* Device timing of rollout_grad's phases.  While set, every rollout_grad call
  * on h records, on its stream, ev[0] and ev[1] around the recompute of all
  * segments (back to back when the mode has no such phase) and ev[2] and ev[3]

@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -16,9 +17,37 @@
 
 using namespace sim;
 
+// Device memory of rollout_grad_noalloc: the reverse sweep's workspace for
+// callers that cannot allocate.  Each device holds its own copy for the life
+// of the process; in host code this name is only a stand-in for the symbol,
+// so kernels and copies use the device address looked up at set-up.
+static __device__ __align__(256) float scratch[SIM_NOALLOC_SCRATCH_BYTES / sizeof(float)];
+
 namespace {
 
 thread_local std::string g_err;
+
+// Device address of `scratch` per device ordinal, looked up once per device
+// (with that device current) by sim_init.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices] = {};
+
+hipError_t scratch_lookup(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_dev[dev]) return hipSuccess;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  g_scratch_dev[dev] = p;
+  return hipSuccess;
+}
+void* scratch_of(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return g_scratch_dev[dev];
+}
 
 sim_status fail(sim_status s, const std::string& msg) {
   g_err = msg;
@@ -316,6 +345,14 @@ sim_status sim_init(const sim_model_desc* d, sim_handle* out) {
   }
   sim_model* h = new sim_model();
   if (hipGetDevice(&h->device) != hipSuccess) { release(h); return fail(SIM_E_DEVICE, "no HIP device"); }
+  {
+    const hipError_t e = scratch_lookup(h->device);
+    if (e != hipSuccess) {
+      release(h);
+      return fail(SIM_E_DEVICE, std::string("sim_init: cannot look up the allocation-free scratch: ") +
+                                    hipGetErrorString(e));
+    }
+  }
   (void)hipDeviceGetAttribute(&h->n_cu, hipDeviceAttributeMultiprocessorCount, h->device);
   (void)hipDeviceGetAttribute(&h->max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, h->device);
   DevModel& M = h->M;
@@ -611,25 +648,24 @@ sim_status rollout_solve(sim_handle h, const float* x0, const float* u, float* l
                      "rollout_solve launch");
 }
 
-sim_status rollout_grad(sim_handle h, const float* x0, const float* u, const float* ckpt, const float* dloss_env,
-                        float* g_x0, float* g_u, float* g_inv_mass, float* g_inv_inertia, float* g_mu,
-                        float* g_damping, float* g_anchor_p, float* g_anchor_c, void* workspace,
-                        size_t workspace_bytes, uint32_t* env_flags, void* stream) {
-  if (!h) return fail(SIM_E_ARG, "rollout_grad: null handle");
-  if (h->M.n_envs == 0) return SIM_OK;
-  if (h->M.solve_mode != SIM_SOLVE_FIXED)
-    return fail(SIM_E_UNSUPPORTED, "rollout_grad: the gradient is of the fixed-sweep step (solve_mode 0)");
-  if (!x0 || !ckpt || !dloss_env) return fail(SIM_E_ARG, "rollout_grad: null x0, ckpt or dloss_env");
-  if (h->M.J > 0 && h->M.T_max > 0 && !u) return fail(SIM_E_ARG, "rollout_grad: null control tape");
-  if (!workspace || (int64_t)workspace_bytes < h->info.workspace_bytes)
-    return fail(SIM_E_NOMEM, "rollout_grad: workspace smaller than sim_info.workspace_bytes (" +
-                                 std::to_string(h->info.workspace_bytes) + ")");
+}  // extern "C"
+
+namespace {
+// The reverse sweep with its workspace given (caller memory or the
+// allocation-free scratch).  Nothing in the workspace needs to start at zero:
+// the recompute writes every saved working set before the reverse reads it,
+// the reverse writes every controller tape row it later contracts, and the
+// contraction writes every partial tile before the reduction reads it.
+sim_status rollout_grad_ws(sim_handle h, const float* x0, const float* u, const float* ckpt,
+                           const float* dloss_env, float* g_x0, float* g_u, float* g_inv_mass, float* g_inv_inertia,
+                           float* g_mu, float* g_damping, float* g_anchor_p, float* g_anchor_c, void* workspace,
+                           uint32_t* env_flags, void* stream) {
   sim_status s = check_device("rollout_grad (earlier fault)");
   if (s != SIM_OK) return s;
   hipStream_t st = (hipStream_t)stream;
   float* ws = (float*)workspace;
-  GradArgs a{x0,   u,    ckpt,          dloss_env, g_x0,      g_u,        g_inv_mass,
-             g_inv_inertia, g_mu, g_damping, g_anchor_p, g_anchor_c, ws, env_flags};
+  GradArgs a{x0,   u,         ckpt, dloss_env, g_x0,       g_u,        g_inv_mass, g_inv_inertia,
+             g_mu, g_damping, g_anchor_p, g_anchor_c, ws, env_flags};
   DevModel M = h->M;
   if (!prep_controls(h, M, u, st)) return check_device("rollout_grad controls");
   M.tape = ws + h->seg_floats;
@@ -650,6 +686,56 @@ sim_status rollout_grad(sim_handle h, const float* x0, const float* u, const flo
                    M.tape + h->tape_floats, h->d_map, h->n_params, g_u, st) != hipSuccess)
     return check_device("rollout_grad weight gradient");
   return SIM_OK;
+}
+
+// Argument checks shared by both entry points.
+sim_status rollout_grad_args(sim_handle h, const char* who, const float* x0, const float* u, const float* ckpt,
+                             const float* dloss_env) {
+  if (h->M.solve_mode != SIM_SOLVE_FIXED)
+    return fail(SIM_E_UNSUPPORTED, std::string(who) + ": the gradient is of the fixed-sweep step (solve_mode 0)");
+  if (!x0 || !ckpt || !dloss_env) return fail(SIM_E_ARG, std::string(who) + ": null x0, ckpt or dloss_env");
+  if (h->M.J > 0 && h->M.T_max > 0 && !u) return fail(SIM_E_ARG, std::string(who) + ": null control tape");
+  return SIM_OK;
+}
+}  // namespace
+
+extern "C" {
+
+sim_status rollout_grad(sim_handle h, const float* x0, const float* u, const float* ckpt, const float* dloss_env,
+                        float* g_x0, float* g_u, float* g_inv_mass, float* g_inv_inertia, float* g_mu,
+                        float* g_damping, float* g_anchor_p, float* g_anchor_c, void* workspace,
+                        size_t workspace_bytes, uint32_t* env_flags, void* stream) {
+  if (!h) return fail(SIM_E_ARG, "rollout_grad: null handle");
+  if (h->M.n_envs == 0) return SIM_OK;
+  sim_status s = rollout_grad_args(h, "rollout_grad", x0, u, ckpt, dloss_env);
+  if (s != SIM_OK) return s;
+  if (!workspace || (int64_t)workspace_bytes < h->info.workspace_bytes)
+    return fail(SIM_E_NOMEM, "rollout_grad: workspace smaller than sim_info.workspace_bytes (" +
+                                 std::to_string(h->info.workspace_bytes) + ")");
+  return rollout_grad_ws(h, x0, u, ckpt, dloss_env, g_x0, g_u, g_inv_mass, g_inv_inertia, g_mu, g_damping,
+                         g_anchor_p, g_anchor_c, workspace, env_flags, stream);
+}
+
+sim_status rollout_grad_noalloc(sim_handle h, const float* x0, const float* u, const float* ckpt,
+                                const float* dloss_env, float* g_x0, float* g_u, float* g_inv_mass,
+                                float* g_inv_inertia, float* g_mu, float* g_damping, float* g_anchor_p,
+                                float* g_anchor_c, uint32_t* env_flags, void* stream) {
+  if (!h) return fail(SIM_E_ARG, "rollout_grad_noalloc: null handle");
+  if (h->M.n_envs == 0) return SIM_OK;
+  sim_status s = rollout_grad_args(h, "rollout_grad_noalloc", x0, u, ckpt, dloss_env);
+  if (s != SIM_OK) return s;
+  if (h->info.workspace_bytes > (int64_t)SIM_NOALLOC_SCRATCH_BYTES)
+    return fail(SIM_E_NOMEM, "rollout_grad_noalloc: the model's workspace (" +
+                                 std::to_string(h->info.workspace_bytes) + " bytes) exceeds the allocation-free "
+                                 "scratch (" + std::to_string((long long)SIM_NOALLOC_SCRATCH_BYTES) +
+                                 " bytes); set grad_store or grad_mem_limit so that sim_info.workspace_bytes fits");
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return check_device("rollout_grad_noalloc");
+  if (dev != h->device) return fail(SIM_E_STATE, "rollout_grad_noalloc: the handle's device is not current");
+  void* ws = scratch_of(h->device);
+  if (!ws) return fail(SIM_E_STATE, "rollout_grad_noalloc: no scratch address for this device");
+  return rollout_grad_ws(h, x0, u, ckpt, dloss_env, g_x0, g_u, g_inv_mass, g_inv_inertia, g_mu, g_damping,
+                         g_anchor_p, g_anchor_c, ws, env_flags, stream);
 }
 
 sim_status sim_time_grad(sim_handle h, void* const* ev) {

@@ -147,6 +147,7 @@ def library():
     lib.sim_step.argtypes = [vp, vp, vp, vp, vp, vp, C.c_int32, vp, vp]
     lib.rollout.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp]
     lib.rollout_grad.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, C.c_size_t, vp, vp]
+    lib.rollout_grad_noalloc.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     lib.rollout_solve.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, C.c_int64, vp, C.c_int32, vp]
     lib.sim_describe_order.argtypes = [C.POINTER(SimDesc), C.c_int32, _I32P, _I32P, C.c_int32]
     lib.sim_describe_order.restype = C.c_int32
@@ -170,7 +171,7 @@ def library():
     lib.sim_time_buckets.argtypes = [vp, C.POINTER(vp), C.c_int32]
     lib.sim_env_buckets.argtypes = [vp, _I32P]
     for fn in ("sim_time_grad", "sim_init", "sim_destroy", "sim_get_info", "sim_lambda_offsets", "sim_step", "rollout",
-               "rollout_grad", "sim_time_buckets", "sim_env_buckets", "sim_step_graph", "sim_graph_launch", "sim_graph_destroy", "sim_set_teams",
+               "rollout_grad", "rollout_grad_noalloc", "sim_time_buckets", "sim_env_buckets", "sim_step_graph", "sim_graph_launch", "sim_graph_destroy", "sim_set_teams",
                "wsn_to_bf16", "wsn_forward", "wsn_loss_grad", "wsn_adam", "rollout_solve", "sim_adam"):
         getattr(lib, fn).restype = C.c_int
     if lib.sim_abi_version() != ABI_VERSION:
@@ -184,7 +185,11 @@ EXPORTED = ["sim_abi_version", "sim_last_error", "sim_init", "sim_destroy", "sim
             "sim_lambda_offsets", "sim_describe_order", "sim_step", "rollout", "rollout_grad",
             "sim_step_graph", "sim_graph_launch", "sim_graph_destroy", "sim_tune", "sim_get_teams",
             "sim_set_teams", "wsn_to_bf16", "wsn_forward", "wsn_workspace_bytes", "wsn_loss_grad", "wsn_adam",
-            "rollout_solve", "sim_adam", "sim_time_grad", "sim_time_buckets", "sim_env_buckets"]
+            "rollout_solve", "sim_adam", "sim_time_grad", "rollout_grad_noalloc", "sim_time_buckets",
+            "sim_env_buckets"]
+
+# bytes of the scratch rollout_grad_noalloc uses (SIM_NOALLOC_SCRATCH_BYTES)
+NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
 def describe_order(w, env):
@@ -299,19 +304,27 @@ class Simulator:
     def workspace(self):
         return self.torch.empty(int(self.info.workspace_bytes) // 4 + 1, dtype=self.torch.float32, device="cuda")
 
-    def rollout_grad(self, x0, u, ckpt, dloss, workspace=None):
+    def rollout_grad(self, x0, u, ckpt, dloss, workspace=None, no_alloc=False):
+        """Reverse mode (rollout_grad), or with no_alloc the allocation-free
+        entry point (rollout_grad_noalloc, the library's own scratch as the
+        workspace).  The output tensors are allocated here either way."""
         E, B, J = self.info.n_envs, self.info.n_bodies, self.info.n_joints
-        ws = workspace if workspace is not None else self.workspace()
+        ws = None if no_alloc else (workspace if workspace is not None else self.workspace())
         nu = self.info.n_params if self.info.n_params else self.w.T_max * J
         g = dict(g_x0=self._f32(18 * B).view(18, -1), g_u=self._f32(nu),
                  g_inv_mass=self._f32(B), g_inv_inertia=self._f32(3 * B), g_mu=self._f32(E), g_damping=self._f32(J),
                  g_anchor_p=self._f32(3 * J), g_anchor_c=self._f32(3 * J),
                  flags=self.torch.zeros(max(E, 1), dtype=self.torch.int32, device="cuda"))
-        st = self.lib.rollout_grad(self.h, _ptr(x0), _ptr(u), _ptr(ckpt), _ptr(dloss), _ptr(g["g_x0"]),
-                                   _ptr(g["g_u"]), _ptr(g["g_inv_mass"]), _ptr(g["g_inv_inertia"]), _ptr(g["g_mu"]),
-                                   _ptr(g["g_damping"]), _ptr(g["g_anchor_p"]), _ptr(g["g_anchor_c"]), _ptr(ws),
-                                   ws.numel() * 4, _ptr(g["flags"]), self._stream())
-        _check(self.lib, st, "rollout_grad")
+        outs = [_ptr(g[k]) for k in ("g_x0", "g_u", "g_inv_mass", "g_inv_inertia", "g_mu", "g_damping",
+                                     "g_anchor_p", "g_anchor_c")]
+        if no_alloc:
+            st = self.lib.rollout_grad_noalloc(self.h, _ptr(x0), _ptr(u), _ptr(ckpt), _ptr(dloss), *outs,
+                                               _ptr(g["flags"]), self._stream())
+            _check(self.lib, st, "rollout_grad_noalloc")
+        else:
+            st = self.lib.rollout_grad(self.h, _ptr(x0), _ptr(u), _ptr(ckpt), _ptr(dloss), *outs, _ptr(ws),
+                                       ws.numel() * 4, _ptr(g["flags"]), self._stream())
+            _check(self.lib, st, "rollout_grad")
         if self.info.n_params:
             g["g_u"] = g["g_u"][: self.info.n_params]
         else:

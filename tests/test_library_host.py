@@ -33,6 +33,9 @@ def test_library_exports_every_declared_function():
         assert hasattr(lib, name), name
     hdr = open(os.path.join(ROOT, "include", "sim.h")).read()
     assert lib.sim_abi_version() == S.ABI_VERSION == int(re.search(r"#define SIM_ABI_VERSION (\d+)", hdr).group(1))
+    # the allocation-free entry point's scratch size, as the binding knows it
+    m = re.search(r"#define SIM_NOALLOC_SCRATCH_BYTES \(\(size_t\)(\d+) << (\d+)\)", hdr)
+    assert m and int(m.group(1)) << int(m.group(2)) == S.NOALLOC_SCRATCH_BYTES
 
 
 def _call_init(w, mutate=None):
