@@ -15,13 +15,19 @@ and compare with the FP64 oracle using the per-env error metrics:
   the edge of chaos the noisy runs spread widely: one chain of the 40-env
   case departs by 4e-6 to 9e-5 at step 100 depending on the draw, so a few
   draws undersample it).  States are compared at every checkpoint before
-  T_nc; gradients of an env are compared when the gradients of the noisy
-  oracle runs all stay within half the gradient tolerance (5e-4) of the
-  clean one: a near-tie at a clamp, disk or contact threshold,
-  where FP32 and FP64 may take different branches, shows up in one of them.  (Perturbing
-  only the inputs under-predicts FP32 error: rounding enters at every step,
-  and rounded positions feed the Baumgarte term directly.)  Envs outside these horizons
-  are counted and reported by the tests, not silently dropped.
+  T_nc.
+* gradient-stable envs: the gradients of eight oracle runs with 4-ulp noise
+  (2^-22) added to the state after every step all stay within half the
+  gradient tolerance (5e-4) of the clean one.  A near-tie at a clamp, the
+  friction disk or a contact threshold, where FP32 and FP64 may take
+  different branches, shows up in one of them.  The FP32 step perturbs the
+  state by more than one ulp (rounding inside twenty sweeps; rounded
+  positions feed the Baumgarte term): a 9-body chain of the 40-env case
+  whose gradient moves by 5e-5 under 1-ulp noise moves by exactly the GPU's
+  3.9e-3 in 5 of 8 draws at 4 ulp, and 4-ulp screening leaves no envs
+  beyond the tolerance on any case.  Every gradient-stable env must be
+  within the tolerance; envs outside these horizons are counted and
+  reported by the tests, not silently dropped.
 """
 from __future__ import annotations
 
@@ -29,12 +35,7 @@ import numpy as np
 
 STATE_TOL = 1e-4
 GRAD_TOL = 1e-3
-# The inverse-inertia gradient is checked at 3e-3: no workload asks for it
-# (they name controls, initial state, mass and friction), and for the
-# point-mass spheres of the arm it is a long sum of nearly cancelling terms
-# whose FP32 evaluation loses about three more digits than the others.
-GRAD_TOL_INERTIA = 3e-3
-GRAD_KEYS = ("g_x0", "g_u", "g_inv_mass", "g_mu", "g_damping", "g_anchor_p", "g_anchor_c")
+GRAD_KEYS = ("g_x0", "g_u", "g_inv_mass", "g_inv_inertia", "g_mu", "g_damping", "g_anchor_p", "g_anchor_c")
 GROUPS = {"p": slice(0, 3), "R": slice(3, 12), "v": slice(12, 15), "w": slice(15, 18)}
 FLOORS = np.array([1e-2, 1e-2, 0.2, 1.0])
 
@@ -48,10 +49,15 @@ def to_dev(w):
 
 
 def gpu_run(w, grad=True, dloss=None, sim=None):
+    """Rollout (and gradient) through the C ABI; a controller workload's
+    control input is its weights, and its dL/dW comes back as g_w."""
     import torch
     from paper_1611_01652_amd.sim import Simulator
     s = sim or Simulator(w)
     x0, u = to_dev(w)
+    mlp = (getattr(w, "extra", None) or {}).get("mlp")
+    if mlp is not None:
+        u = torch.tensor(np.asarray(mlp["w"], np.float32), device="cuda")
     r = s.rollout(x0, u)
     ck = r["ckpt"].cpu().numpy().astype(np.float64)
     stride = 18 * w.n_bodies + s.info.lam_size
@@ -66,7 +72,7 @@ def gpu_run(w, grad=True, dloss=None, sim=None):
                                                                                      device="cuda")
         g = s.rollout_grad(x0, u, r["ckpt"], dl)
         out["g_x0"] = g["g_x0"].cpu().numpy().T.astype(np.float64)
-        out["g_u"] = g["g_u"].cpu().numpy().astype(np.float64)
+        out["g_w" if mlp is not None else "g_u"] = g["g_u"].cpu().numpy().astype(np.float64)
         out["g_inv_mass"] = g["g_inv_mass"].cpu().numpy().astype(np.float64)
         out["g_inv_inertia"] = g["g_inv_inertia"].cpu().numpy().astype(np.float64)
         out["g_mu"] = g["g_mu"].cpu().numpy().astype(np.float64)
@@ -125,16 +131,8 @@ def grad_errors(w, got, ref, keys=("g_x0", "g_u", "g_inv_mass", "g_inv_inertia",
     return out
 
 
-def perturbed(w, eps=1e-7):
-    wp = w.with_steps(w.T_max)
-    wp.x0 = w.x0.copy()
-    wp.x0[:, 12:18] = w.x0[:, 12:18] * (1 + eps)
-    if w.u is not None and w.u.size:
-        wp.u = w.u * (1 + eps)
-    return wp
-
-
-NOISE = 2.0 ** -24
+NOISE = 2.0 ** -24        # state horizon screening: 1 ulp
+GRAD_NOISE = 2.0 ** -22   # gradient screening: 4 ulp
 
 
 def horizons(w, traj, traj_p, thr=0.5 * STATE_TOL):
@@ -149,14 +147,23 @@ def horizons(w, traj, traj_p, thr=0.5 * STATE_TOL):
     return out
 
 
+def grad_stable(w, ref, seeds=8):
+    """[E] envs whose oracle gradient stays within half the tolerance under
+    4-ulp noise in every draw."""
+    from oracle import Oracle
+    stable = np.ones(w.n_envs, bool)
+    for k in range(seeds):
+        stable &= grad_errors(w, Oracle(w, noise=GRAD_NOISE, noise_seed=k).rollout_grad(), ref) < 0.5 * GRAD_TOL
+    return stable
+
+
 def compare_with_oracle(w, got, check_grad=True, min_state_frac=0.0, min_grad_frac=1.0, seeds=8,
-                        outlier_frac=0.0):
+                        min_checkpoints=0):
     """Checkpointed states before T_nc and final states within 1e-4, loss
-    within 1e-4, gradients of gradient-stable envs within 1e-3.  With
-    contacts, FP32 and FP64 can branch differently at a near-tie (a clamp,
-    the friction disk or the activation threshold) that no noise draw hit;
-    `outlier_frac` allows that many gradient-stable envs to miss, and the
-    report lists them."""
+    within 1e-4, gradients of every gradient-stable env within 1e-3; at
+    least min_checkpoints (env, checkpoint) state comparisons, min_state_frac
+    of the envs non-chaotic over their whole horizon and min_grad_frac
+    gradient-stable."""
     from oracle import Oracle
     o = Oracle(w)
     roll = o.rollout(traj=True)
@@ -178,20 +185,15 @@ def compare_with_oracle(w, got, check_grad=True, min_state_frac=0.0, min_grad_fr
     lo = np.abs(got["loss"] - roll["loss"]) <= STATE_TOL * np.abs(roll["loss"]) + 1e-6
     assert lo[full].all(), ("loss", np.where(full & ~lo)[0])
     assert full.mean() >= min_state_frac, ("envs beyond their non-chaotic horizon", full.mean())
+    assert n_checked >= min_checkpoints, ("state comparisons", n_checked)
     report = dict(envs=w.n_envs, state_full_frac=float(full.mean()), checkpoints_checked=n_checked,
                   median_tnc=float(np.median(tnc)))
     if check_grad:
         ref = o.rollout_grad()
-        stable = np.ones(w.n_envs, bool)
-        for op in noisy:
-            stable &= grad_errors(w, op.rollout_grad(), ref) < 0.5 * GRAD_TOL
+        stable = grad_stable(w, ref, seeds)
         ge = grad_errors(w, got, ref, keys=GRAD_KEYS)
-        gi = grad_errors(w, got, ref, keys=("g_inv_inertia",))
-        miss = stable & ((ge > GRAD_TOL) | (gi > GRAD_TOL_INERTIA))
-        allowed = int(np.floor(outlier_frac * w.n_envs))
-        assert miss.sum() <= allowed, ("grad", ge[stable].max(), np.where(miss)[0], allowed)
-        report.update(grad_outliers=np.where(miss)[0].tolist())
+        miss = stable & (ge > GRAD_TOL)
+        assert not miss.any(), ("grad", ge[stable].max(), np.where(miss)[0])
         assert stable.mean() >= min_grad_frac, ("gradient-stable fraction", stable.mean())
-        ok = stable & ~miss
-        report.update(grad_stable_frac=float(stable.mean()), grad_max_err=float(ge[ok].max(initial=0)))
+        report.update(grad_stable_frac=float(stable.mean()), grad_max_err=float(ge[stable].max(initial=0)))
     return report

@@ -1,16 +1,18 @@
 """GPU parity: the HIP path through the C ABI against the FP64 oracle.
 
-Tolerances: final states within 1e-4 and gradients within 1e-3 relative
-(per env, per group / array), on each env's non-chaotic horizon (see
-gpu_helpers.well_conditioned).  Sizes span several tiles and a ragged tail;
-the full-size launches are compared on sampled envs computed one by one by
-the oracle.
+Tolerances: states within 1e-4 and gradients within 1e-3 relative (per env,
+per group / array), on each env's non-chaotic horizon (gpu_helpers: states at
+every checkpoint before the env's horizon, gradients of every env whose oracle
+gradient is stable under 4-ulp noise; no env may miss).  The coverage floors
+of each case sit just below what the criterion yields on it.  Sizes span
+several tiles and a ragged tail; the full-size launches are compared on
+sampled envs computed one by one by the oracle.
 """
 import numpy as np
 import pytest
 
-from gpu_helpers import (GRAD_TOL, STATE_TOL, compare_with_oracle, gpu_run, grad_errors, rel, state_errors,
-                         to_dev)
+from gpu_helpers import (GRAD_TOL, STATE_TOL, compare_with_oracle, gpu_run, grad_errors, grad_stable, rel,
+                         state_errors, to_dev)
 from oracle import Oracle
 from paper_1611_01652_amd import workloads as W
 
@@ -21,9 +23,9 @@ def _say(*a):
     print(*a, flush=True)
 
 
-def _compare(w, got, check_grad=True, state_frac=0.0, grad_frac=1.0, outliers=0.0):
+def _compare(w, got, check_grad=True, state_frac=0.0, grad_frac=1.0, checkpoints=0):
     rep = compare_with_oracle(w, got, check_grad=check_grad, min_state_frac=state_frac, min_grad_frac=grad_frac,
-                              outlier_frac=outliers)
+                              min_checkpoints=checkpoints)
     _say("  ", rep)
     return rep
 
@@ -39,37 +41,29 @@ def test_planar_arms_subset_all_steps():
     w = W.planar_arms(n_envs=96, T=1000)      # 3 tiles of 32 at the narrowest team
     _say("case planar-arms 96 x 1000")
     got = gpu_run(w)
-    _compare(w, got, grad_frac=0.9)
+    # no arm stays non-chaotic over all 1000 steps; the criterion yields 413
+    # (env, checkpoint) state comparisons and 61.5 % gradient-stable arms
+    _compare(w, got, grad_frac=0.55, checkpoints=380)
 
 
 def test_planar_arms_quarter_horizon_every_env():
     w = W.planar_arms(n_envs=96, T=250)
     _say("case planar-arms 96 x 250")
-    # coverage floors sit below what the eight-draw criterion yields on this
-    # case (20 % of the arms stay non-chaotic for 250 steps, 99 % have stable
-    # gradients); every env is still compared at its checkpoints before T_nc
-    _compare(w, gpu_run(w), state_frac=0.15, grad_frac=0.95)
+    # the criterion yields 19.8 % of the arms non-chaotic over the 250 steps,
+    # 386 checkpoint comparisons and 77 % gradient-stable arms
+    _compare(w, gpu_run(w), state_frac=0.18, grad_frac=0.7, checkpoints=360)
 
 
 def test_planar_arms_full_size_sampled():
+    # the arm benchmark's launch; 16 evenly spaced envs by the per-env protocol
+    # (8 of them gradient-stable over the 1000 steps)
+    import bench
     w = W.planar_arms(n_envs=4096, T=1000)
-    _say("case planar-arms 4096 x 1000 (bench launch), sampled")
+    _say("case planar-arms 4096 x 1000 (the arm benchmark's launch), sampled")
     got = gpu_run(w)
-    sample = [0, 1, 777, 2048, 3001, 4095]
+    sample = bench.stratified(w, 16)
     ws = w.subset(sample)
-    o = Oracle(ws)
-    ref = o.rollout_grad()
-    b = np.concatenate([np.arange(w.env_body_off[e], w.env_body_off[e + 1]) for e in sample])
-    j = np.concatenate([np.arange(w.env_joint_off[e], w.env_joint_off[e + 1]) for e in sample])
-    sub = dict(loss=got["loss"][sample], x_final=got["x_final"][b], g_x0=got["g_x0"][b], g_u=got["g_u"][:, j],
-               g_inv_mass=got["g_inv_mass"][b], g_inv_inertia=got["g_inv_inertia"][b], g_mu=got["g_mu"][sample],
-               g_damping=got["g_damping"][j])
-    np.testing.assert_allclose(sub["loss"], ref["loss"], rtol=STATE_TOL)
-    import gpu_helpers as H
-    refp = Oracle(ws, noise=H.NOISE).rollout_grad()
-    stable = grad_errors(ws, refp, ref) < 0.5 * GRAD_TOL
-    assert stable.sum() >= 3
-    assert (grad_errors(ws, sub, ref, keys=H.GRAD_KEYS)[stable] <= GRAD_TOL).all()
+    _compare(ws, _sampled(got, w, sample), grad_frac=7 / 16, checkpoints=50)
 
 
 def test_uneven_chains_subset():
@@ -77,26 +71,46 @@ def test_uneven_chains_subset():
     _say("case uneven-chains 40 x 100")
     got = gpu_run(w)
     assert (got["flags"] == 0).all()
-    _compare(w, got, state_frac=0.2, grad_frac=0.7, outliers=0.1)   # yields 22.5 % and 80 %
+    # yields 22.5 % non-chaotic, 78 checkpoint comparisons, 55 % gradient-stable
+    _compare(w, got, state_frac=0.2, grad_frac=0.5, checkpoints=70)
+
+
+def _sampled(got, w, sample):
+    """The arrays of the sampled envs, as their own workload lays them out."""
+    b = np.concatenate([np.arange(w.env_body_off[e], w.env_body_off[e + 1]) for e in sample])
+    j = np.concatenate([np.arange(w.env_joint_off[e], w.env_joint_off[e + 1]) for e in sample])
+    out = dict(loss=got["loss"][sample], x_final=got["x_final"][b], flags=got["flags"][sample],
+               ckpt_states=got["ckpt_states"][:, b])
+    for k in ("g_x0", "g_inv_mass", "g_inv_inertia"):
+        if k in got:
+            out[k] = got[k][b]
+    for k in ("g_damping", "g_anchor_p", "g_anchor_c"):
+        if k in got:
+            out[k] = got[k][j]
+    if "g_u" in got:
+        out["g_u"] = got["g_u"][:, j]
+    if "g_mu" in got:
+        out["g_mu"] = got["g_mu"][sample]
+    return out
 
 
 def test_uneven_chains_full_size_sampled():
+    # the benchmark's launch: 16384 chains x 500 steps in the mode the memory
+    # limit picks (segment: the reverse kernel recomputes each segment), all
+    # size buckets; 64 envs at evenly spaced quantiles of the body count are
+    # compared by the per-env protocol.  Over 500 steps the criterion yields
+    # 142 checkpoint comparisons and 4 gradient-stable envs of the 64.
+    import bench
     w = W.uneven_chains(n_envs=16384, T=500)
-    _say("case uneven-chains 16384 x 500 (full size), sampled forward")
-    got = gpu_run(w, grad=False)
+    _say("case uneven-chains 16384 x 500 (full size, the benchmark's launch), sampled")
+    from paper_1611_01652_amd.sim import Simulator
+    s = Simulator(w)
+    assert s.info.grad_store == 2
+    got = gpu_run(w, sim=s)
     assert (got["flags"] == 0).mean() > 0.99
-    rng = np.random.default_rng(0)
-    sample = sorted(rng.choice(w.n_envs, 24, replace=False).tolist())
+    sample = bench.stratified(w, 64)
     ws = w.subset(sample)
-    o = Oracle(ws)
-    roll = o.rollout()
-    b = np.concatenate([np.arange(w.env_body_off[e], w.env_body_off[e + 1]) for e in sample])
-    se = state_errors(ws, got["x_final"][b], roll["x_final"])
-    # compare where the oracle is stable over the whole horizon
-    import gpu_helpers as H
-    ok = state_errors(ws, Oracle(ws, noise=H.NOISE).rollout()["x_final"], roll["x_final"]) < 0.25 * STATE_TOL
-    assert ok.sum() >= 4
-    assert (se[ok] <= STATE_TOL).all(), se[ok].max()
+    _compare(ws, _sampled(got, w, sample), grad_frac=3 / 64, checkpoints=130)
 
 
 def test_sim_step_from_contact_state():
@@ -128,7 +142,7 @@ def test_ragged_lengths_and_degenerate_envs():
     a.T_env = np.array([90, 0, 37, 1, 64, 90], np.int32)
     _say("case ragged episode lengths")
     got = gpu_run(a)
-    _compare(a, got, grad_frac=0.6)   # 4 of the 6 envs have stable gradients
+    _compare(a, got, grad_frac=0.5)   # 3 of the 6 envs have stable gradients
     assert np.all(got["g_u"][37:, a.env_joint_off[2]:a.env_joint_off[3]] == 0)
     assert np.all(got["g_x0"][a.env_body_off[1]:a.env_body_off[2]] == 0)
     b = W.single_sphere(p=(0, 0, 1.0), v=(0.3, 0, 0), ground=False, T=40)
@@ -171,15 +185,21 @@ def test_contact_overflow_is_flagged():
     assert got["flags"][0] & 2
 
 
-def test_bitwise_determinism_and_team_invariance():
-    w = W.uneven_chains(n_envs=20, T=60, seed_salt=7)
-    _say("case determinism")
+@pytest.mark.parametrize("make", [lambda: W.uneven_chains(n_envs=20, T=60, seed_salt=7),
+                                  lambda: W.planar_arms(n_envs=40, T=120)])
+def test_bitwise_determinism_and_team_invariance(make):
+    # chains (free floating) and arms (world-attached base joints: the paired
+    # hinge forms with the world slot as side a) at their default team widths
+    # and at 64 lanes per env give the same bits
+    w = make()
+    _say("case determinism", w.name)
     a = gpu_run(w)
     b = gpu_run(w)
     w2 = w.with_steps(w.T_max)
     w2.min_team = 64
     c = gpu_run(w2)
-    for k in ("loss", "x_final", "g_x0", "g_u", "g_mu"):
+    for k in ("loss", "x_final", "g_x0", "g_u", "g_mu", "g_inv_mass", "g_inv_inertia", "g_damping", "g_anchor_p",
+              "g_anchor_c"):
         assert np.array_equal(a[k], b[k]), k
         assert np.array_equal(a[k], c[k]), k
 
@@ -240,28 +260,36 @@ def _quadruped_run(w, grad=True):
     return s, out
 
 
-def test_quadruped_controller_forward_and_weight_gradient():
-    # ragged episode lengths; controller output layer small but non-zero so
-    # that every layer's gradient is exercised
-    w = W.quadruped(n_envs=64, T_min=30, T_max=60, mlp_w=W.mlp_init(zero_output=False, out_scale=0.1))
-    _say("case quadruped + MLP controller 64 envs, T 30..60")
-    s, got = _quadruped_run(w)
-    assert s.info.n_params == 19976
-    o = Oracle(w)
-    roll = o.rollout()
-    ref = o.rollout_grad()
-    se = state_errors(w, got["x_final"], roll["x_final"])
-    assert np.median(se) <= STATE_TOL and (se <= 10 * STATE_TOL).mean() >= 0.9, (np.median(se), se.max())
-    np.testing.assert_allclose(got["loss"], roll["loss"], rtol=1e-3, atol=1e-5)
-    # dL/dW summed over envs: every layer and bias block within 1e-3
+def _weight_gradient_blocks(w, got_w, ref_w):
     sizes = w.extra["mlp"]["sizes"]
     off = 0
     for a_, b_ in zip(sizes[:-1], sizes[1:]):
         for n in (a_ * b_, b_):
             blk = slice(off, off + n)
-            assert rel(got["g_w"][blk], ref["g_w"][blk]) <= GRAD_TOL, (off, rel(got["g_w"][blk], ref["g_w"][blk]))
+            assert rel(got_w[blk], ref_w[blk]) <= GRAD_TOL, (off, rel(got_w[blk], ref_w[blk]))
             off += n
-    assert off == len(ref["g_w"])
+    assert off == len(ref_w)
+
+
+def test_quadruped_controller_forward_and_weight_gradient():
+    # ragged episode lengths; controller output layer small but non-zero so
+    # that every layer's gradient is exercised.  States, losses and per-env
+    # gradients by the per-env protocol (the criterion yields 95 % of the
+    # robots non-chaotic over their episodes and 64 % gradient-stable); the
+    # weight gradient, a sum over envs, over the gradient-stable robots as a
+    # launch of their own
+    w = W.quadruped(n_envs=64, T_min=30, T_max=60, mlp_w=W.mlp_init(zero_output=False, out_scale=0.1))
+    _say("case quadruped + MLP controller 64 envs, T 30..60")
+    from paper_1611_01652_amd.sim import Simulator
+    s = Simulator(w)
+    assert s.info.n_params == 19976
+    got = gpu_run(w, sim=s)
+    _compare(w, got, state_frac=0.9, grad_frac=0.55)
+    stable = np.where(grad_stable(w, Oracle(w).rollout_grad()))[0].tolist()
+    ws = w.subset(stable)
+    _say("   weight gradient over", len(stable), "gradient-stable robots")
+    sub = gpu_run(ws)
+    _weight_gradient_blocks(ws, sub["g_w"], Oracle(ws).rollout_grad()["g_w"])
 
 
 def test_quadruped_zero_policy_gradient_reaches_output_layer_only():
@@ -294,3 +322,4 @@ def test_quadruped_sim_step_with_controller():
     torch.cuda.synchronize()
     se = state_errors(w, xo.cpu().numpy().T.astype(np.float64), xn)
     assert (se <= STATE_TOL).all(), se.max()
+
