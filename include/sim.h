@@ -55,7 +55,7 @@
 extern "C" {
 #endif
 
-#define SIM_ABI_VERSION 3
+#define SIM_ABI_VERSION 4
 
 typedef struct sim_model* sim_handle;
 
@@ -177,6 +177,15 @@ typedef struct {
      result bits; they trade memory for recomputation. */
   int32_t grad_store;
   int64_t grad_mem_limit;
+  /* Gradient decay (section 3.2, a training aid against exploding gradients):
+     with use_grad_decay != 0, rollout_grad multiplies the adjoints carried
+     back from step t+1 to step t (the state's and the carried impulses') by
+     grad_decay, in [0, 1], before reversing step t; the loss term of x^{t+1}
+     enters undecayed.  The result is then not the exact derivative.
+     use_grad_decay = 0 (a zero-initialised description): the exact
+     derivative. */
+  int32_t use_grad_decay;
+  float grad_decay;
 } sim_model_desc;
 
 /* Sizes derived by sim_init. */

@@ -80,7 +80,7 @@ class _Model(C.Structure):
         ("warm", C.c_double), ("noise", C.c_double), ("noise_seed", C.c_int),
         ("solve_mode", C.c_int), ("tol", C.c_double), ("max_iters", C.c_int),
         ("ws_kind", C.c_int), ("ws_w", C.c_void_p), ("fb_iters", C.c_int), ("fb_tol", C.c_double),
-        ("lam0", C.c_void_p),
+        ("lam0", C.c_void_p), ("grad_decay", C.c_double),
     ]
 
 
@@ -171,6 +171,7 @@ class Oracle:
             m.ws_w = d("wsw", np.zeros(1))
         if lam0 is not None:
             m.lam0 = d("lam0", lam0)
+        m.grad_decay = f(getattr(w, "grad_decay", 1.0))
         self._m = m
         self._keep = keep
         self.lib = _load()

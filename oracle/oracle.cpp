@@ -947,6 +947,12 @@ int oracle_rollout_grad(const oracle_model* m, const double* x0, const double* d
     Tape tp;
     tape() = &tp;
     for (int t = T - 1; t >= 0; --t) {
+      // gradient decay: the carry from the later steps shrinks by alpha per
+      // step (section 3.2); at t = T - 1 there is no carry yet
+      if (t < T - 1 && c.grad_decay != 1.0) {
+        for (double& v : xbar) v *= c.grad_decay;
+        for (double& v : lbar) v *= c.grad_decay;
+      }
       tp.clear();
       std::vector<Var> xv(n), lv(E.lam_size), uv(E.nj), mv(E.nb), Iv(3 * E.nb), dv(E.nj), apv(3 * E.nj),
           acv(3 * E.nj), Wv;

@@ -58,6 +58,11 @@ typedef struct {
      of oracle_lambda_size's offsets); NULL: zeros.  A rollout started from a
      saved state and impulses continues the trajectory it was saved from. */
   const double *lam0;
+  /* gradient decay (section 3.2): the adjoints carried back from step t+1
+     to step t (state and warm-start impulses) are multiplied by grad_decay
+     before step t is reversed; the loss term of x^{t+1} enters undecayed.
+     1: the exact derivative. */
+  double grad_decay;
 } oracle_model;
 
 /* Warm-start network shape and training-record layout. */

@@ -345,6 +345,11 @@ SHD_FLAT void env_rollout_grad(const Team& tm, const DevModel& M, const Env& E, 
         // replay step t with recording (no integration, no store)
         replay_to_sweeps(tm, M, E, a, act, t, E.hist(0), true);
       }
+      // gradient decay of the carry from the later steps (none before the last step)
+      if (M.decay != 1.f) {
+        a_decay(tm, M, E, act && t < T - 1);
+        tm.sync();
+      }
       // loss on x^{t+1}: p(t+1) = p(t) + dt v'
       if (act && tm.tl == 0 && M.loss_kind == 1) {
         const float* B = E.body(E.lb);

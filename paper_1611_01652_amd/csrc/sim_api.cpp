@@ -326,6 +326,8 @@ sim_status sim_init(const sim_model_desc* d, sim_handle* out) {
   if (d->ws_kind == SIM_WS_LEARNED && (d->solve_mode != SIM_SOLVE_TOL || !d->ws_net || d->fb_iters < 0 ||
                                        !(d->fb_tol == d->fb_tol)))
     return fail(SIM_E_ARG, "the learned warm start needs tolerance mode, ws_net, fb_iters >= 0 and a fb_tol");
+  if (d->use_grad_decay && !(d->grad_decay >= 0.f && d->grad_decay <= 1.f))
+    return fail(SIM_E_ARG, "grad_decay must lie in [0, 1]");
   if (d->grad_store < SIM_GRAD_AUTO || d->grad_store > SIM_GRAD_TRAJECTORY || d->grad_mem_limit < 0)
     return fail(SIM_E_ARG, "grad_store must be one of SIM_GRAD_* and grad_mem_limit >= 0");
   for (int e = 0; e < E; ++e) {
@@ -362,6 +364,7 @@ sim_status sim_init(const sim_model_desc* d, sim_handle* out) {
   M.beta = d->beta; M.gamma = d->gamma; M.spec = d->spec_margin; M.warm = d->warm;
   M.solve_mode = d->solve_mode; M.tol = d->tol; M.max_iters = d->max_iters;
   M.ws_kind = d->ws_kind; M.fb_iters = d->fb_iters; M.fb_tol = d->fb_tol;
+  M.decay = d->use_grad_decay ? d->grad_decay : 1.f;
   M.ctrl = d->ctrl_kind == 1 ? 1 : 0;   // (before the LDS sizes: the controller adds a shared region)
 
   h->lam_off = P.lam_off;

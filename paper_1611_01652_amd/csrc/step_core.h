@@ -119,6 +119,7 @@ struct DevModel {
   float tol, fb_tol;
   const uint16_t* wsn; // warm-start network, bfloat16 [4867]
   int dump;           // reverse sweep buffer: DUMP_REPLAY, DUMP_SEGMENT or DUMP_TRAJECTORY
+  float decay;        // gradient decay per reversed step (1: the exact derivative)
 };
 // Reverse sweep buffer modes: step-start states of one segment (each step is
 // replayed), saved working sets of one segment, or of the whole trajectory
@@ -1676,6 +1677,16 @@ SHD void a_clear_step(const Team& tm, const Env& E, bool act) {
     st4(A + AIW + 10, z);
     st2(A + AIW + 14, f2{0.f, 0.f});
   }
+}
+
+// Gradient decay (section 3.2): the adjoints carried back from the later
+// steps, the state's and the carried impulses', shrink by M.decay.
+template <class Team>
+SHD void a_decay(const Team& tm, const DevModel& M, const Env& E, bool act) {
+  const int nb = act ? E.nb : 0;
+  for (int i = tm.tl; i < 18 * nb; i += tm.ts) E.bodyA(i / 18)[AP + i % 18] *= M.decay;
+  const int nl = act ? E.lam_size : 0;
+  for (int i = tm.tl; i < nl; i += tm.ts) E.wsA()[i] *= M.decay;
 }
 
 // B8: adjoint of the impulse store; lambda bar of each active row starts from

@@ -20,7 +20,7 @@ FLAG_NONFINITE = 1
 FLAG_CONTACT_OVERFLOW = 2
 
 # layout of the descriptor and info structs below (SIM_ABI_VERSION)
-ABI_VERSION = 3
+ABI_VERSION = 4
 
 # reverse sweep memory modes (sim_model_desc.grad_store)
 GRAD_STORE = {"auto": 0, "replay": 1, "segment": 2, "trajectory": 3}
@@ -47,6 +47,7 @@ class SimDesc(C.Structure):
         ("solve_mode", C.c_int32), ("tol", C.c_float), ("max_iters", C.c_int32),
         ("ws_kind", C.c_int32), ("ws_net", _F32P), ("fb_iters", C.c_int32), ("fb_tol", C.c_float),
         ("grad_store", C.c_int32), ("grad_mem_limit", C.c_int64),
+        ("use_grad_decay", C.c_int32), ("grad_decay", C.c_float),
     ]
 
 
@@ -112,6 +113,9 @@ def make_desc(w):
     extra = getattr(w, "extra", None) or {}
     d.grad_store = GRAD_STORE[extra.get("grad_store", "auto")]
     d.grad_mem_limit = int(extra.get("grad_mem_limit", 0))
+    alpha = float(getattr(w, "grad_decay", 1.0))
+    d.use_grad_decay = int(alpha != 1.0)
+    d.grad_decay = alpha
     solve = extra.get("solve")
     if solve is not None:
         d.solve_mode = int(solve.get("mode", 1))

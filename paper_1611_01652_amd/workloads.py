@@ -120,6 +120,7 @@ class Workload:
     T_max: int = 0
     ckpt_every: int = 50
     min_team: int = 0
+    grad_decay: float = 1.0   # alpha: carried adjoints shrink by this per step (1: exact gradient)
     extra: Dict = field(default_factory=dict)
 
     @property
@@ -167,7 +168,7 @@ class Workload:
             dt=self.dt, gravity=self.gravity, beta=self.beta, gamma=self.gamma,
             spec_margin=self.spec_margin, n_iters=self.n_iters, warm=self.warm, ground=self.ground,
             loss_kind=self.loss_kind, loss_mask=self.loss_mask, T_max=self.T_max,
-            ckpt_every=self.ckpt_every, min_team=self.min_team, extra=dict(self.extra))
+            ckpt_every=self.ckpt_every, min_team=self.min_team, grad_decay=self.grad_decay, extra=dict(self.extra))
 
     def with_steps(self, T: int) -> "Workload":
         """Same model, horizon cut to T steps (tape truncated)."""

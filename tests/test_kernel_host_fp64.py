@@ -79,6 +79,8 @@ def _desc64(w):
     d.ckpt_every, d.min_team = w.ckpt_every, 0
     d.grad_store = GRAD_STORE[(getattr(w, "extra", None) or {}).get("grad_store", "auto")]
     d.grad_mem_limit = int((getattr(w, "extra", None) or {}).get("grad_mem_limit", 0))
+    alpha = f(getattr(w, "grad_decay", 1.0))
+    d.use_grad_decay, d.grad_decay = int(alpha != 1.0), alpha
     mlp = w.extra.get("mlp") if getattr(w, "extra", None) else None
     if mlp is not None:
         d.ctrl_kind = 1
@@ -164,6 +166,11 @@ def test_reverse_sweep_memory_modes_and_their_sizes():
         assert _sizes(w)["mode"] == mode
 
 
+def _decayed(w, alpha):
+    w.grad_decay = alpha
+    return w
+
+
 def _store(w, mode):
     w.extra = dict(w.extra or {})
     w.extra["grad_store"] = mode
@@ -182,6 +189,10 @@ def _store(w, mode):
     (lambda: W.free_spheres(np.array([[0, 0, .1], [.19, 0, .1], [.095, 0, .27]]), [.1] * 3, [1., 2., .7],
                             mu=0.5, T=80), 1e-9),
     (lambda: W.quadruped(n_envs=3, T_min=30, T_max=45, mlp_w=W.mlp_init(zero_output=False, out_scale=0.3)), 1e-8),
+    (lambda: _decayed(W.planar_arms(n_envs=3, T=130), 0.93), 1e-9),
+    (lambda: _decayed(_store(W.uneven_chains(n_envs=5, T=120, seed_salt=4), "replay"), 0.8), 1e-7),
+    (lambda: _decayed(W.quadruped(n_envs=3, T_min=30, T_max=45, mlp_w=W.mlp_init(zero_output=False,
+                                                                                   out_scale=0.3)), 0.9), 1e-8),
 ])
 def test_kernel_source_in_fp64_equals_oracle(maker, tol):
     w = maker()

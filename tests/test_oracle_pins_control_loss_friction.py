@@ -347,3 +347,58 @@ def test_hinge_torque_on_an_anisotropic_body_uses_the_world_inertia():
     expect = F32(w.dt) * F32(u) / (y @ I_w @ y)
     assert abs(y @ R @ np.diag(Ib) @ R.T @ y - 0.3) > 0.05   # the rotation matters
     np.testing.assert_allclose(xn[0, 15:18], expect * y, rtol=0, atol=1e-9 * abs(expect))
+
+
+def test_gradient_decay_closed_form_on_free_flight():
+    # section 3.2: the gradient shrinks by alpha at every time step.  Free
+    # flight, final-position loss: the state adjoint after reversing step t
+    # is alpha^(T-1-t) (g, (T - t) dt g), so dL/dp0 = alpha^(T-1) g and
+    # dL/dv0 = alpha^(T-1) T dt g with g = 2 (p_T - target)
+    T, alpha = 30, 0.9
+    w = W.single_sphere(p=(0.3, -0.2, 2.0), v=(1.5, 0.2, -0.7), ground=False, gravity=(0.0, 0.0, 0.0), T=T,
+                        dt=0.01)
+    w.target = W.f32([[0.1, 0.5, 1.0]])
+    w.grad_decay = alpha
+    o = Oracle(w)
+    a = F32(alpha) ** (T - 1)
+    dt = F32(w.dt)
+    pT = w.x0[0, :3] + T * dt * w.x0[0, 12:15]
+    g = 2 * (pT - w.target[0])
+    gr = o.rollout_grad()
+    np.testing.assert_allclose(gr["g_x0"][0, :3], a * g, rtol=1e-12)
+    np.testing.assert_allclose(gr["g_x0"][0, 12:15], a * T * dt * g, rtol=1e-12)
+    w.grad_decay = 1.0
+    np.testing.assert_allclose(Oracle(w).rollout_grad()["g_x0"][0, 12:15], T * dt * g, rtol=1e-12)
+
+
+def test_gradient_decay_zero_keeps_only_the_next_step():
+    # with alpha = 0 and a loss on every step (time-averaged distance), the
+    # gradient of control u_t is that of l(x^{t+1}) through the single step
+    # t: central differences of one oracle step from the trajectory's x^t
+    T = 25
+    w = W.planar_arms(n_envs=1, T=T)
+    w.grad_decay = 0.0
+    o = Oracle(w)
+    gr = o.rollout_grad()
+    tr = o.rollout(traj=True)["traj"]
+    lam = np.zeros(o.lam_size)
+    x = w.x0.copy()
+    lams = []
+    for t in range(T):
+        lams.append(lam.copy())
+        x, lam = o.step(x, lam, w.u[t], t)
+    tg = w.target[0]
+    lb = w.loss_body[0]
+
+    def l_next(t, u):
+        xn, _ = o.step(tr[t], lams[t], u, t)
+        return np.linalg.norm(xn[lb, :3] - tg) / T
+
+    h = 1e-6
+    for t in (0, 7, 24):
+        for j in range(3):
+            up, um = w.u[t].copy(), w.u[t].copy()
+            up[j] += h
+            um[j] -= h
+            fd = (l_next(t, up) - l_next(t, um)) / (2 * h)
+            assert abs(gr["g_u"][t, j] - fd) <= 1e-7 * max(abs(fd), 1e-3), (t, j, gr["g_u"][t, j], fd)
