@@ -28,8 +28,9 @@
  *    at x[k*B + b]; components p(0..2), R(3..11, row-major), v(12..14),
  *    omega(15..17).  B = total bodies over all envs, bodies of an env are
  *    contiguous (CSR offsets env_body_off).
- *  - Warm-start impulse state ("lambda"), per env a contiguous block of
- *    5*J_e + 4*G_e + 4*P_e floats at the offset sim_info.lam_off[e]:
+ *  - Carried state besides x ("lambda"), per env a contiguous block of
+ *    5*J_e + 4*G_e + 4*P_e warm-start impulses (then, with a recurrent
+ *    controller, its mlp_rec units h^t) at the offset sim_info.lam_off[e]:
  *    5 hinge rows per joint (point x, y, z, angular t1, t2), then per ground
  *    sphere (sphere order) [lambda_n, Lambda_t.x, .y, .z], then per sphere
  *    pair candidate [lambda_n, Lambda_t(3)] in (body a, body b) lexicographic
@@ -55,7 +56,7 @@
 extern "C" {
 #endif
 
-#define SIM_ABI_VERSION 4
+#define SIM_ABI_VERSION 5
 
 typedef struct sim_model* sim_handle;
 
@@ -81,9 +82,11 @@ typedef enum {
 
 /* control kinds (eq. (g) of section 2.2 without the recurrent state) */
 #define SIM_CTRL_TAPE 0 /* open-loop torques u[T_max][J] */
-#define SIM_CTRL_MLP 1  /* u^t = g(s(x^t)) shared by all envs: s = [joint angles (J_e), joint rates
-                           (J_e), sin, cos of 2 pi f t dt]; tanh hidden layers, linear output (J_e);
-                           weights W1[h1][in] b1 W2[h2][h1] b2 W3[out][h2] b3 */
+#define SIM_CTRL_MLP 1  /* [u^t, a^t] = g(s(x^t), h^t) shared by all envs (eq. (g)): s = [joint angles
+                           (J_e), joint rates (J_e), sin, cos of 2 pi f t dt]; h^t the controller's
+                           mlp_rec recurrent units, h^0 = 0, h^{t+1} = tanh(a^t); tanh hidden layers,
+                           linear outputs u^t (J_e) and a^t (mlp_rec); weights W1[h1][in] b1
+                           W2[h2][h1] b2 W3[out][h2] b3 */
 
 /* solver and warm-start kinds */
 #define SIM_SOLVE_FIXED 0 /* n_iters sweeps per step */
@@ -149,8 +152,8 @@ typedef struct {
   int32_t min_team;              /* 0: automatic; else lanes per env are at least this
                                     (power of two <= 64).  Results do not depend on it. */
   int32_t ctrl_kind;             /* SIM_CTRL_* */
-  int32_t mlp_sizes[4];          /* in, h1, h2, out; every env has out = J_e, in = 2 J_e + 2;
-                                    h1, h2 <= 256 */
+  int32_t mlp_sizes[4];          /* in, h1, h2, out; every env has out = J_e + mlp_rec,
+                                    in = 2 J_e + 2 + mlp_rec; h1, h2 <= 256 */
   float clock_hz;                /* clock frequency f of the controller inputs */
   /* Solve to a residual tolerance (forward only; rollout_grad refuses): after
      each sweep the residual is the largest |change of impulse| / effective
@@ -186,6 +189,10 @@ typedef struct {
      derivative. */
   int32_t use_grad_decay;
   float grad_decay;
+  /* SIM_CTRL_MLP: recurrent units of the controller (0: none); then
+     mlp_sizes in = 2 J_e + 2 + mlp_rec and out = J_e + mlp_rec, and h^t rides
+     at the end of each env's carried-state block */
+  int32_t mlp_rec;
 } sim_model_desc;
 
 /* Sizes derived by sim_init. */

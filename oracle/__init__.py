@@ -76,7 +76,7 @@ class _Model(C.Structure):
         ("n_iters", C.c_int), ("ground", C.c_int), ("loss_kind", C.c_int), ("loss_mask", C.c_int),
         ("ctrl_kind", C.c_int),
         ("mlp_in", C.c_int), ("mlp_h1", C.c_int), ("mlp_h2", C.c_int), ("mlp_out", C.c_int),
-        ("mlp_n_params", C.c_int), ("mlp_w", C.c_void_p), ("clock_hz", C.c_double),
+        ("mlp_n_params", C.c_int), ("mlp_w", C.c_void_p), ("mlp_rec", C.c_int), ("clock_hz", C.c_double),
         ("warm", C.c_double), ("noise", C.c_double), ("noise_seed", C.c_int),
         ("solve_mode", C.c_int), ("tol", C.c_double), ("max_iters", C.c_int),
         ("ws_kind", C.c_int), ("ws_w", C.c_void_p), ("fb_iters", C.c_int), ("fb_tol", C.c_double),
@@ -148,6 +148,7 @@ class Oracle:
             m.mlp_n_params = len(mlp["w"])
             m.mlp_w = d("mlpw", mlp["w"])
             m.clock_hz = mlp.get("clock_hz", 1.5)
+            m.mlp_rec = int(mlp.get("rec", 0))
         else:
             m.ctrl_kind = 0
             m.mlp_w = d("mlpw", np.zeros(1))

@@ -105,7 +105,8 @@ struct EnvTopo {
   std::vector<int> ground;      // global sphere ids with the ground flag, sphere order
   std::vector<PairCand> pairs;  // candidate pairs, (local a, local b) lexicographic
   std::vector<Con> order;       // canonical colour-major order of all candidate constraints
-  int lam_off, lam_size;        // warm-start state block
+  int lam_off, lam_size;        // carried-state block: warm-start impulses, then the controller's h
+  int lam_imp;                  // impulses in it (the rest is h)
 };
 
 static bool joined(const Model& M, const EnvTopo& E, int ga, int gb) {
@@ -194,7 +195,8 @@ static EnvTopo build_topo(const Model& M, int e, int lam_off) {
     }
   }
   E.lam_off = lam_off;
-  E.lam_size = 5 * E.nj + 4 * (int)E.ground.size() + 4 * (int)E.pairs.size();
+  E.lam_imp = 5 * E.nj + 4 * (int)E.ground.size() + 4 * (int)E.pairs.size();
+  E.lam_size = E.lam_imp + (c.ctrl_kind == 1 ? c.mlp_rec : 0);
   return E;
 }
 
@@ -290,10 +292,13 @@ template <class S> S finish_row(Row<S>& r, const Bodies<S>& B) {
 }
 
 // ------------------------------------------------------------------ controller
-// eq. (g) without the recurrent state: u = g_deep(s(x)) with s = joint angles,
-// joint rates and a sine/cosine clock; tanh hidden layers, linear output.
+// eq. (g): u^t = g_deep(s(x^t), h^t) with s = joint angles, joint rates and a
+// sine/cosine clock; tanh hidden layers; the output's first J entries are the
+// torques (linear), the rest give the next recurrent state h^{t+1} = tanh(.)
+// (h and hn: the controller's recurrent state before and after the step).
 template <class S>
-void mlp_controls(const Model& M, const EnvTopo& E, int t, const Bodies<S>& B, const S* W, S* u) {
+void mlp_controls(const Model& M, const EnvTopo& E, int t, const Bodies<S>& B, const S* W, S* u, const S* h = nullptr,
+                  S* hn = nullptr) {
   const oracle_model& c = M.c;
   const int nin = c.mlp_in, h1 = c.mlp_h1, h2 = c.mlp_h2, nout = c.mlp_out;
   std::vector<S> s(nin, S(0.0));
@@ -310,6 +315,7 @@ void mlp_controls(const Model& M, const EnvTopo& E, int t, const Bodies<S>& B, c
   const double ph = 2.0 * M_PI * c.clock_hz * (t * c.dt);
   s[2 * E.nj] = S(std::sin(ph));
   s[2 * E.nj + 1] = S(std::cos(ph));
+  for (int i = 0; i < c.mlp_rec; ++i) s[2 * E.nj + 2 + i] = h[i];
   const S* W1 = W;
   const S* b1 = W1 + h1 * nin;
   const S* W2 = b1 + h1;
@@ -330,7 +336,8 @@ void mlp_controls(const Model& M, const EnvTopo& E, int t, const Bodies<S>& B, c
   for (int i = 0; i < nout; ++i) {
     S a = b3[i];
     for (int k = 0; k < h2; ++k) a = a + W3[i * h2 + k] * z2[k];
-    u[i] = a;
+    if (i < E.nj) u[i] = a;
+    else hn[i - E.nj] = tanh(a);
   }
 }
 
@@ -368,8 +375,8 @@ void step_env(const Model& M, const EnvTopo& E, const StepIn<S>& in, S* xn, S* l
     B.invm[b] = in.invm[b];
   }
   // S0 controls: tape, or the controller evaluated on x^t
-  std::vector<S> u(E.nj);
-  if (c.ctrl_kind == 1) mlp_controls(M, E, t, B, W, u.data());
+  std::vector<S> u(E.nj), hn(c.ctrl_kind == 1 ? c.mlp_rec : 0);
+  if (c.ctrl_kind == 1) mlp_controls(M, E, t, B, W, u.data(), in.lam + E.lam_imp, hn.data());
   else for (int j = 0; j < E.nj; ++j) u[j] = in.u[j];
   // S1 world inverse inertia R diag(1/I) R^T and sphere centres
   for (int b = 0; b < nb; ++b) {
@@ -661,8 +668,10 @@ void step_env(const Model& M, const EnvTopo& E, const StepIn<S>& in, S* xn, S* l
     xb[12] = B.v[b].x; xb[13] = B.v[b].y; xb[14] = B.v[b].z;
     xb[15] = B.w[b].x; xb[16] = B.w[b].y; xb[17] = B.w[b].z;
   }
-  // S9 store impulses for the next step's warm start (zero when inactive)
-  for (int i = 0; i < E.lam_size; ++i) lamn[i] = S(0.0);
+  // S9 store impulses for the next step's warm start (zero when inactive),
+  // and the controller's next recurrent state
+  for (int i = 0; i < E.lam_imp; ++i) lamn[i] = S(0.0);
+  for (size_t i = 0; i < hn.size(); ++i) lamn[E.lam_imp + i] = hn[i];
   for (auto& C : cons) {
     if (C.kind == 0) {
       for (int q = 0; q < 5; ++q) lamn[C.store + q] = C.r[q].lam;
@@ -890,8 +899,9 @@ long long oracle_rollout_ex(const oracle_model* m, const double* x0, double* los
 }
 
 // The controller's outputs u^t for env `env` at state x (global [B][18]) and
-// step t: eq. (g) evaluated on the joint sensors and the clock.  A test hook
-// for pinning the sensor and clock inputs.
+// step t, with the recurrent state h^t from lam0 (zeros without): eq. (g)
+// evaluated on the joint sensors, the clock and h^t.  A test hook for pinning
+// the controller's inputs.
 int oracle_controls(const oracle_model* m, int env, const double* x, int t, double* u_out) {
   if (m->ctrl_kind != 1 || env < 0 || env >= m->n_envs) return -1;
   Ctx C;
@@ -907,7 +917,10 @@ int oracle_controls(const oracle_model* m, int env, const double* x, int t, doub
     B.v[b] = {xb[12], xb[13], xb[14]};
     B.w[b] = {xb[15], xb[16], xb[17]};
   }
-  mlp_controls<double>(C.M, E, t, B, m->mlp_w, u_out);
+  std::vector<double> h(m->mlp_rec, 0.0), hn(m->mlp_rec, 0.0);
+  if (m->lam0)
+    for (int i = 0; i < m->mlp_rec; ++i) h[i] = m->lam0[E.lam_off + E.lam_imp + i];
+  mlp_controls<double>(C.M, E, t, B, m->mlp_w, u_out, h.data(), hn.data());
   return E.nj;
 }
 

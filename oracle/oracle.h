@@ -33,6 +33,11 @@ typedef struct {
   int ctrl_kind;              /* 0 tape, 1 MLP controller shared by all envs */
   int mlp_in, mlp_h1, mlp_h2, mlp_out, mlp_n_params;
   const double *mlp_w;        /* W1[h1][in] b1 W2[h2][h1] b2 W3[out][h2] b3 */
+  int mlp_rec;                /* recurrent state h^t of the controller (eq. (g)): the
+                                 network reads [sensors, clock, h^t] (in = 2 J + 2 + rec)
+                                 and emits [u^t, a] (out = J + rec), h^{t+1} = tanh(a),
+                                 h^0 = 0; h^t is carried after the env's warm-start
+                                 impulses in its carried-state block */
   double clock_hz;
   double warm;                /* warm-start factor applied to carried impulses */
   double noise;               /* test aid: relative rounding-sized noise added to the state after every step */

@@ -191,8 +191,11 @@ sim_status build_env(const sim_model_desc& d, int e, HostEnv& H) {
   H.team = std::min(64, next_pow2(std::max({1, max_col, (H.nb + 1) / 2})));
   int mf = 0, ma = 0;
   if (d.ctrl_kind == 1) {
-    if (d.mlp_sizes[3] != H.nj || d.mlp_sizes[0] != 2 * H.nj + 2)
-      return fail(SIM_E_SHAPE, "env " + std::to_string(e) + ": controller needs out = joints and in = 2 joints + 2");
+    const int rec = d.mlp_rec;
+    if (d.mlp_sizes[3] != H.nj + rec || d.mlp_sizes[0] != 2 * H.nj + 2 + rec)
+      return fail(SIM_E_SHAPE, "env " + std::to_string(e) +
+                                   ": controller needs out = joints + rec and in = 2 joints + 2 + rec");
+    H.lam += rec;   // the recurrent state rides after the impulses
     mf = mlp_fwd_floats(d.mlp_sizes[0], d.mlp_sizes[1], d.mlp_sizes[2], d.mlp_sizes[3]);
     ma = mlp_adj_floats(d.mlp_sizes[0], d.mlp_sizes[1], d.mlp_sizes[2], d.mlp_sizes[3]);
   }
@@ -224,6 +227,7 @@ sim_status pack_model(const sim_model_desc* d, PackedModel& P, std::string& err)
     for (int k = 0; k < 4; ++k)
       if (d->mlp_sizes[k] <= 0) { g_msg = nullptr; err = "controller sizes must be > 0"; return SIM_E_ARG; }
     if (d->mlp_sizes[1] > 256 || d->mlp_sizes[2] > 256) { g_msg = nullptr; err = "controller hidden width > 256"; return SIM_E_UNSUPPORTED; }
+    if (d->mlp_rec < 0) { g_msg = nullptr; err = "mlp_rec < 0"; return SIM_E_ARG; }
   }
   // per-env buffer sizes of the three reverse sweep modes
   std::vector<long long> sz_replay(E), sz_segment(E), sz_traj(E);

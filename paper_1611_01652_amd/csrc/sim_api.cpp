@@ -468,7 +468,7 @@ sim_status sim_init(const sim_model_desc* d, sim_handle* out) {
   // controller: clock table, weight-gradient tiles and parameter map
   if (d->ctrl_kind == 1) {
     const int in = d->mlp_sizes[0], n1 = d->mlp_sizes[1], n2 = d->mlp_sizes[2], no = d->mlp_sizes[3];
-    M.ctrl = 1; M.mlp_in = in; M.mlp_h1 = n1; M.mlp_h2 = n2; M.mlp_out = no;
+    M.ctrl = 1; M.mlp_in = in; M.mlp_h1 = n1; M.mlp_h2 = n2; M.mlp_out = no; M.mlp_rec = d->mlp_rec;
     M.tape_stride = tape_len(in, n1, n2, no);
     std::vector<float> clock(2 * (size_t)std::max(d->T_max, 1));
     for (int t = 0; t < d->T_max; ++t) {

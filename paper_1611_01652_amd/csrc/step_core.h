@@ -108,8 +108,10 @@ struct DevModel {
   const int* topo;    // per-env topology ints
   const float* cst;   // per-env constants
   const float* target;// [E][3]
-  // controller (ctrl == 1): u = MLP(s(x)), weights W shared by all envs
-  int ctrl, mlp_in, mlp_h1, mlp_h2, mlp_out, tape_stride;
+  // controller (ctrl == 1): [u, a] = MLP(s(x), h), weights W shared by all
+  // envs; mlp_rec recurrent units h^{t+1} = tanh(a), carried after the
+  // impulses in the env's carried-state block
+  int ctrl, mlp_in, mlp_h1, mlp_h2, mlp_out, tape_stride, mlp_rec;
   const float* clock; // [T_max][2] sin, cos of 2 pi f t dt
   const float* W;     // weights (set per call)
   const float* Wt;    // their transposes W1^T, W2^T, W3^T (made per call, device)
@@ -223,6 +225,7 @@ SHD Lay make_lay(int nb, int nj, int G, int P, int ncol, int ncand, int nslot, i
 // ------------------------------------------------------------------ env view
 struct Env {
   int b0, nb, j0, nj, lam_off, lam_size, G, P, ncol, T, lb, ccap, ncand, e, nslot, seg_off, tape_off;
+  int lam_imp;        // impulses in the carried-state block (the rest: the controller's h)
   const int* gtopo;   // global topology of the env
   const float* gcst;  // global constants of the env
   float* L;           // LDS base of the env
@@ -300,6 +303,7 @@ SHD Env make_env(const DevModel& M, int ie, float* lds, int n_iters, bool adj) {
   Env E;
   E.b0 = h[H_B0]; E.nb = h[H_NB]; E.j0 = h[H_J0]; E.nj = h[H_NJ];
   E.lam_off = h[H_LAMOFF]; E.lam_size = h[H_LAMSZ]; E.G = h[H_G]; E.P = h[H_P]; E.ncol = h[H_NCOL];
+  E.lam_imp = E.lam_size - (M.ctrl ? M.mlp_rec : 0);
   E.T = h[H_T]; E.lb = h[H_LB]; E.ccap = h[H_CCAP]; E.ncand = h[H_NCAND]; E.e = h[H_ENV];
   E.nslot = h[H_NSLOT]; E.seg_off = h[H_SEG]; E.tape_off = h[H_TAPE];
   E.gtopo = M.topo + h[H_TOPO];
@@ -1258,13 +1262,20 @@ SHD void f_controls(const Team& tm, const DevModel& M, const Env& E, const float
     sv_[2 * E.nj] = M.clock[2 * t];
     sv_[2 * E.nj + 1] = M.clock[2 * t + 1];
   }
+  // the recurrent state h^t
+  const int rec = act ? M.mlp_rec : 0;
+  for (int i = tm.tl; i < rec; i += tm.ts) sv_[2 * E.nj + 2 + i] = E.ws()[E.lam_imp + i];
   for (int k = M.mlp_in + tm.tl; k < align4(M.mlp_in); k += tm.ts) sv_[k] = 0.f;
   tm.sync();
-  // h1 = tanh(W1 s + b1), h2 = tanh(W2 h1 + b2), u = W3 h2 + b3 for every
-  // env of the wave at once (a team whose env is idle gets values it ignores)
+  // h1 = tanh(W1 s + b1), h2 = tanh(W2 h1 + b2), [u, a] = W3 h2 + b3 for
+  // every env of the wave at once (a team whose env is idle gets values it
+  // ignores)
   tm.ctrl_forward(M, E);
   const float* u = sv_ + mo_u(M);
   for (int i = tm.tl; i < nj; i += tm.ts) E.jc(i)[JU] = u[i];
+  // h^{t+1} = tanh(a) replaces h^t in the carried state (nothing later in the
+  // step reads h)
+  for (int i = tm.tl; i < rec; i += tm.ts) E.ws()[E.lam_imp + i] = tanhf(u[E.nj + i]);
 }
 
 // Loss term of the state after step t (1-based) for the loss body.
@@ -1723,7 +1734,9 @@ SHD void a_store(const Team& tm, const Env& E, bool act) {
   }
   tm.sync();
   // the adjoint of the incoming store is rebuilt by the warm-start reverse
-  const int nls = act ? E.lam_size : 0;
+  // (the recurrent state's adjoint, after the impulses', stays: it is the
+  // carry of the controller's reverse)
+  const int nls = act ? E.lam_imp : 0;
   for (int i = tm.tl; i < nls; i += tm.ts) E.wsA()[i] = 0.f;
   tm.sync();
 }
@@ -2614,6 +2627,13 @@ SHD void a_controller(const Team& tm, const DevModel& M, const Env& E, bool act,
   const float* sv_ = E.mlp();
   float* du = E.mlpA();
   const float* sb = du + mo_sb(M);
+  // the recurrent head: a-bar = h-bar^{t+1} (1 - (h^{t+1})^2); the carried
+  // state holds h^{t+1} after the step's controls
+  const int rec = act ? M.mlp_rec : 0;
+  for (int i = tm.tl; i < rec; i += tm.ts) {
+    const float hn = E.ws()[E.lam_imp + i];
+    du[E.nj + i] = E.wsA()[E.lam_imp + i] * (1.f - hn * hn);
+  }
   for (int k = no + tm.tl; k < align4(no); k += tm.ts) du[k] = 0.f;
   tm.sync();
   // d2 = (W3^T du) (1 - h2^2), d1 = (W2^T d2) (1 - h1^2), sbar = W1^T d1 for
@@ -2637,6 +2657,8 @@ SHD void a_controller(const Team& tm, const DevModel& M, const Env& E, bool act,
       row[k] = v;
     }
   }
+  // h-bar^t, carried to the reverse of step t - 1
+  for (int i = tm.tl; i < rec; i += tm.ts) E.wsA()[E.lam_imp + i] = sb[2 * E.nj + 2 + i];
   tm.sync();
   // sensors: theta = atan2(y, x), y = (ua x ub).na, x = ua.ub ; rate = wrel.na
   const int njc = n_joint_cols(E, act);

@@ -20,7 +20,7 @@ FLAG_NONFINITE = 1
 FLAG_CONTACT_OVERFLOW = 2
 
 # layout of the descriptor and info structs below (SIM_ABI_VERSION)
-ABI_VERSION = 4
+ABI_VERSION = 5
 
 # reverse sweep memory modes (sim_model_desc.grad_store)
 GRAD_STORE = {"auto": 0, "replay": 1, "segment": 2, "trajectory": 3}
@@ -47,7 +47,7 @@ class SimDesc(C.Structure):
         ("solve_mode", C.c_int32), ("tol", C.c_float), ("max_iters", C.c_int32),
         ("ws_kind", C.c_int32), ("ws_net", _F32P), ("fb_iters", C.c_int32), ("fb_tol", C.c_float),
         ("grad_store", C.c_int32), ("grad_mem_limit", C.c_int64),
-        ("use_grad_decay", C.c_int32), ("grad_decay", C.c_float),
+        ("use_grad_decay", C.c_int32), ("grad_decay", C.c_float), ("mlp_rec", C.c_int32),
     ]
 
 
@@ -110,6 +110,7 @@ def make_desc(w):
         d.ctrl_kind = 1
         d.mlp_sizes = (C.c_int32 * 4)(*[int(v) for v in mlp["sizes"]])
         d.clock_hz = float(mlp.get("clock_hz", 1.5))
+        d.mlp_rec = int(mlp.get("rec", 0))
     extra = getattr(w, "extra", None) or {}
     d.grad_store = GRAD_STORE[extra.get("grad_store", "auto")]
     d.grad_mem_limit = int(extra.get("grad_mem_limit", 0))

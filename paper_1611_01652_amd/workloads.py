@@ -500,7 +500,7 @@ def mlp_init(sizes=MLP_SIZES, seed_salt=0, zero_output=True, scale=1.0, out_scal
 
 
 def quadruped(n_envs: int = 1024, T_min: int = 500, T_max: int = 2000, seed_salt: int = 0,
-              mlp_w=None) -> Workload:
+              mlp_w=None, rec: int = 0) -> Workload:
     """Box torso (1 kg, 0.30 x 0.15 x 0.06 m) and four legs of two 0.10 m
     cylinders (r 0.025, 0.125 kg each), hips and knees hinged about the body y
     axis with damping 0.01, sphere feet r = 0.05 touching the ground; legs
@@ -536,6 +536,13 @@ def quadruped(n_envs: int = 1024, T_min: int = 500, T_max: int = 2000, seed_salt
                  loss_body=a["env_body_off"][:-1].astype(np.int32), target=f32(np.zeros((n_envs, 3))),
                  T_env=T_env, u=None, dt=0.01, ground=1, loss_kind=LOSS_NEG_MEAN_VELX, loss_mask=1,
                  T_max=int(T_env.max()), ckpt_every=50)
-    w.extra["mlp"] = dict(sizes=MLP_SIZES, w=mlp_init() if mlp_w is None else np.asarray(mlp_w, np.float64),
-                          clock_hz=1.5)
+    sizes = rec_sizes(MLP_SIZES, rec)
+    w.extra["mlp"] = dict(sizes=sizes, w=mlp_init(sizes) if mlp_w is None else np.asarray(mlp_w, np.float64),
+                          clock_hz=1.5, rec=int(rec))
     return w
+
+
+def rec_sizes(sizes, rec):
+    """Layer sizes of the controller with `rec` recurrent units (eq. (g)): the
+    input gains h^t, the output gains the pre-activation of h^{t+1}."""
+    return (sizes[0] + rec, sizes[1], sizes[2], sizes[3] + rec)

@@ -140,6 +140,7 @@ bool make(const sim_model_desc* d, Host& h) {
   M.ws_kind = d->ws_kind; M.fb_iters = d->fb_iters; M.fb_tol = d->fb_tol;
   if (M.ctrl) {
     M.mlp_in = d->mlp_sizes[0]; M.mlp_h1 = d->mlp_sizes[1]; M.mlp_h2 = d->mlp_sizes[2]; M.mlp_out = d->mlp_sizes[3];
+    M.mlp_rec = d->mlp_rec;
     M.tape_stride = tape_len(M.mlp_in, M.mlp_h1, M.mlp_h2, M.mlp_out);
     h.clock.assign(2 * (size_t)std::max(d->T_max, 1), 0.0);
     for (int t = 0; t < d->T_max; ++t) {

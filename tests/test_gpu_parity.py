@@ -304,16 +304,20 @@ def test_quadruped_zero_policy_gradient_reaches_output_layer_only():
     assert rel(got["g_w"][n_hidden:], ref["g_w"][n_hidden:]) <= GRAD_TOL
 
 
-def test_quadruped_sim_step_with_controller():
+@pytest.mark.parametrize("rec", [0, 4])
+def test_quadruped_sim_step_with_controller(rec):
+    # with a recurrent controller the carried block holds h^t after the
+    # impulses; one step from a state reached by the oracle
     import torch
-    w = W.quadruped(n_envs=8, T_min=40, T_max=40, mlp_w=W.mlp_init(zero_output=False, out_scale=0.1))
+    w = W.quadruped(n_envs=8, T_min=40, T_max=40, rec=rec,
+                    mlp_w=W.mlp_init(W.rec_sizes(W.MLP_SIZES, rec), zero_output=False, out_scale=0.1))
     o = Oracle(w)
     x, lam = w.x0.copy(), np.zeros(o.lam_size)
     for t in range(25):
         x, lam = o.step(x, lam, None, t)
     xn, ln = o.step(x, lam, None, 25)
     from paper_1611_01652_amd.sim import Simulator
-    _say("case quadruped sim_step t=25")
+    _say("case quadruped sim_step t=25, recurrent units", rec)
     s = Simulator(w)
     xd = torch.tensor(np.ascontiguousarray(x.T), dtype=torch.float32, device="cuda")
     wt = torch.tensor(w.extra["mlp"]["w"], dtype=torch.float32, device="cuda")
@@ -322,6 +326,9 @@ def test_quadruped_sim_step_with_controller():
     torch.cuda.synchronize()
     se = state_errors(w, xo.cpu().numpy().T.astype(np.float64), xn)
     assert (se <= STATE_TOL).all(), se.max()
+    if rec:
+        assert np.abs(lam[-rec:]).max() > 0.01
+        assert rel(lo.cpu().numpy()[: o.lam_size], ln) <= 1e-4
 
 
 @pytest.mark.parametrize("make,alpha,frac", [(lambda: W.planar_arms(n_envs=48, T=300), 0.95, 0.9),
@@ -339,3 +346,24 @@ def test_gradient_decay_matches_oracle(make, alpha, frac):
     exact.grad_decay = 1.0
     g1 = gpu_run(exact)
     assert np.abs(got["g_x0"]).sum() < np.abs(g1["g_x0"]).sum()   # the decay shrinks the far-past terms
+
+
+def test_recurrent_controller_matches_oracle():
+    # eq. (g) with memory: 8 recurrent units carried after the impulses.
+    # States and losses by the per-env protocol (96 % of the robots
+    # non-chaotic over their episodes); the per-env dL/dx0 of these robots
+    # moves by up to 4e-3 under 4-ulp noise (stick-slip of the feet), so the
+    # gradient compared is dL/dW over the batch, whose noisy oracle runs stay
+    # within 3e-5 of the clean one
+    import gpu_helpers as H
+    rec = 8
+    sizes = W.rec_sizes(W.MLP_SIZES, rec)
+    w = W.quadruped(n_envs=48, T_min=20, T_max=45, rec=rec, mlp_w=W.mlp_init(sizes, zero_output=False, out_scale=0.1))
+    _say("case recurrent controller, quadruped 48 envs, 8 units")
+    got = gpu_run(w)
+    _compare(w, got, state_frac=0.9, grad_frac=0.0)
+    ref = Oracle(w).rollout_grad()["g_w"]
+    for k in range(4):
+        noisy = Oracle(w, noise=H.GRAD_NOISE, noise_seed=k).rollout_grad()["g_w"]
+        assert rel(noisy, ref) < 0.5 * GRAD_TOL
+    _weight_gradient_blocks(w, got["g_w"], ref)

@@ -86,6 +86,7 @@ def _desc64(w):
         d.ctrl_kind = 1
         d.mlp_sizes = (C.c_int32 * 4)(*[int(v) for v in mlp["sizes"]])
         d.clock_hz = float(mlp.get("clock_hz", 1.5))
+        d.mlp_rec = int(mlp.get("rec", 0))
     solve = w.extra.get("solve") if getattr(w, "extra", None) else None
     if solve is not None:
         d.solve_mode, d.tol, d.max_iters = 1, f(solve["tol"]), int(solve["max_iters"])
@@ -190,6 +191,13 @@ def _store(w, mode):
                             mu=0.5, T=80), 1e-9),
     (lambda: W.quadruped(n_envs=3, T_min=30, T_max=45, mlp_w=W.mlp_init(zero_output=False, out_scale=0.3)), 1e-8),
     (lambda: _decayed(W.planar_arms(n_envs=3, T=130), 0.93), 1e-9),
+    # (the recurrent robots are more chaotic: FP64 rounding-order differences
+    # grow from 1e-16 to 1e-13 over 10 steps and 1e-7 over 30)
+    (lambda: W.quadruped(n_envs=3, T_min=10, T_max=16, rec=5,
+                         mlp_w=W.mlp_init(W.rec_sizes(W.MLP_SIZES, 5), zero_output=False, out_scale=0.3)), 1e-8),
+    (lambda: _decayed(_store(W.quadruped(n_envs=3, T_min=10, T_max=16, rec=3,
+                                         mlp_w=W.mlp_init(W.rec_sizes(W.MLP_SIZES, 3), zero_output=False,
+                                                          out_scale=0.3)), "replay"), 0.9), 1e-8),
     (lambda: _decayed(_store(W.uneven_chains(n_envs=5, T=120, seed_salt=4), "replay"), 0.8), 1e-7),
     (lambda: _decayed(W.quadruped(n_envs=3, T_min=30, T_max=45, mlp_w=W.mlp_init(zero_output=False,
                                                                                    out_scale=0.3)), 0.9), 1e-8),

@@ -402,3 +402,84 @@ def test_gradient_decay_zero_keeps_only_the_next_step():
             um[j] -= h
             fd = (l_next(t, up) - l_next(t, um)) / (2 * h)
             assert abs(gr["g_u"][t, j] - fd) <= 1e-7 * max(abs(fd), 1e-3), (t, j, gr["g_u"][t, j], fd)
+
+
+def _recurrent_pair(route_in, route_out_h, c_scale=0.5, rec=2):
+    """The hinged pair with a recurrent controller (rec units): input
+    `route_in` feeds h1[1] -> h2[2]; h2[2] feeds output `route_out_h` (0: the
+    torque; 1..rec: the pre-activation of h^{t+1})."""
+    w = _hinged_pair(0.7, (0.1, 0.2, -0.3), (0.5, -0.4, 0.9), c_scale, route=0)
+    n_in, n1, n2, n_out = 4 + rec, 5, 3, 1 + rec
+    W1 = np.zeros((n1, n_in))
+    W1[1, route_in] = c_scale
+    W2 = np.zeros((n2, n1))
+    W2[2, 1] = 1.0
+    W3 = np.zeros((n_out, n2))
+    W3[route_out_h, 2] = 1.0
+    wv = np.concatenate([W1.ravel(), np.zeros(n1), W2.ravel(), np.zeros(n2), W3.ravel(), np.zeros(n_out)])
+    w.extra["mlp"] = dict(sizes=(n_in, n1, n2, n_out), w=wv, clock_hz=1.5, rec=rec)
+    return w
+
+
+def test_recurrent_controller_reads_its_state():
+    # eq. (g): the network reads h^t, the state carried after the env's
+    # impulses; with routing weights the torque is tanh(tanh(c h_k))
+    for k in range(2):
+        w = _recurrent_pair(route_in=4 + k, route_out_h=0)
+        o = Oracle(w)
+        lam0 = np.zeros(o.lam_size)
+        h = np.array([0.37, -0.81])
+        lam0[o.lam_size - 2:] = h
+        u = Oracle(w, lam0=lam0).controls(w.x0, env=0, t=3)
+        assert abs(math.atanh(math.atanh(u[0])) / 0.5 - h[k]) < 1e-12
+        assert Oracle(w).controls(w.x0, env=0, t=3)[0] == 0.0   # h^0 = 0
+
+
+@pytest.mark.parametrize("T", [1, 17])
+def test_recurrent_state_is_computed_from_the_steps_inputs(T):
+    # h^{t+1} = tanh(a^t): routing the sine clock of step t into the second
+    # unit, after T steps the carried state holds
+    # tanh(tanh(tanh(c sin(2 pi f (T - 1) dt)))) (and the first unit tanh(0))
+    w = _recurrent_pair(route_in=2, route_out_h=2)
+    w.T_max = T
+    w.T_env = np.array([T], np.int32)
+    r = Oracle(w).rollout()
+    h = r["lam_final"][-2:]
+    s = math.sin(2 * math.pi * 1.5 * (T - 1) * F32(w.dt))
+    assert h[0] == 0.0
+    assert abs(h[1] - math.tanh(math.tanh(math.tanh(0.5 * s)))) < 1e-15
+
+
+def test_recurrent_controller_gradients_match_central_differences():
+    rec = 6
+    sizes = W.rec_sizes(W.MLP_SIZES, rec)
+    w = W.quadruped(n_envs=2, T_min=25, T_max=25, rec=rec,
+                    mlp_w=W.mlp_init(sizes, zero_output=False, out_scale=0.3))
+    o = Oracle(w)
+    gr = o.rollout_grad()
+    base = np.asarray(w.extra["mlp"]["w"], np.float64)
+    n_in, n1 = sizes[0], sizes[1]
+    # W1 entries reading h^t, a hidden weight, an h-head weight and bias
+    idx = [3 * n_in + 18, 7 * n_in + 18 + rec - 1, n1 * n_in + n1 + 5 * n1 + 9,
+           len(base) - sizes[3] - sizes[3] * sizes[2] + 10 * sizes[2] + 4, len(base) - 1]
+
+    def loss(wv):
+        w2 = w.with_steps(w.T_max)
+        w2.extra = dict(w.extra)
+        w2.extra["mlp"] = dict(w.extra["mlp"], w=wv)
+        return Oracle(w2).rollout()["loss"].sum()
+
+    # (the summed loss is of order 10: a step of 1e-5 keeps the differences'
+    # rounding near 1e-10)
+    h = 1e-5
+    for i in idx:
+        wp, wm = base.copy(), base.copy()
+        wp[i] += h
+        wm[i] -= h
+        fd = (loss(wp) - loss(wm)) / (2 * h)
+        assert abs(gr["g_w"][i] - fd) <= 1e-5 * abs(fd) + 5e-9, (i, gr["g_w"][i], fd)
+    # the recurrence carries information: with the h-head zeroed the loss moves
+    wz = base.copy()
+    off_h = len(base) - sizes[3] - sizes[3] * sizes[2] + 8 * sizes[2]
+    wz[off_h:off_h + rec * sizes[2]] = 0.0
+    assert abs(loss(wz) - loss(base)) > 1e-9
