@@ -81,6 +81,7 @@ class _Model(C.Structure):
         ("solve_mode", C.c_int), ("tol", C.c_double), ("max_iters", C.c_int),
         ("ws_kind", C.c_int), ("ws_w", C.c_void_p), ("fb_iters", C.c_int), ("fb_tol", C.c_double),
         ("lam0", C.c_void_p), ("grad_decay", C.c_double),
+        ("restitution", C.c_void_p), ("rest_threshold", C.c_double),
     ]
 
 
@@ -173,6 +174,10 @@ class Oracle:
         if lam0 is not None:
             m.lam0 = d("lam0", lam0)
         m.grad_decay = f(getattr(w, "grad_decay", 1.0))
+        rest = getattr(w, "restitution", None)
+        if rest is not None:
+            m.restitution = d("rest", rest)
+        m.rest_threshold = f(getattr(w, "rest_threshold", 0.5))
         self._m = m
         self._keep = keep
         self.lib = _load()

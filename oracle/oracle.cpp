@@ -355,6 +355,7 @@ template <class S> struct StepIn {
   S mu;
   const S* anc_p;  // [nj][3] hinge point in the parent (or world) frame
   const S* anc_c;  // [nj][3] hinge point in the child frame
+  double rest = 0.0;  // restitution coefficient of the env's contacts
 };
 
 template <class S>
@@ -501,10 +502,20 @@ void step_env(const Model& M, const EnvTopo& E, const StepIn<S>& in, S* xn, S* l
         K[q] = finish_row(r, B);
       }
       // normal row: speculative when separated, Baumgarte when penetrating
-      // (C = 0 takes the penetrating branch)
+      // (C = 0 takes the penetrating branch).  Restitution: a contact that
+      // the predicted velocities would close within this step (touching ones
+      // included) and that approaches faster than the threshold aims at e
+      // times its approach speed, unless the Baumgarte push-out is faster.
       Row<S>& rn = C.r[0];
       rn.m = S(1.0) / (K[0] + gam);
       rn.bias = (val(gap) > 0.0 ? gap : beta * gap) / dt;
+      if (in.rest > 0.0) {
+        const S vn = jdotv(rn, B);   // at the predicted velocities (before the warm start)
+        if (val(vn) < -c.rest_threshold && val(vn) * c.dt + val(gap) < 0.0) {
+          const S rb = S(in.rest) * vn;
+          if (val(rb) < val(rn.bias)) rn.bias = rb;
+        }
+      }
       rn.lo = 0.0; rn.hi = INFINITY;
       C.mt = S(2.0) / (K[1] + K[2]);
       // warm start: previous normal impulse and the tangent impulse carried as
@@ -707,6 +718,13 @@ S loss_term(const Model& M, const EnvTopo& E, int e, int t, int T, const S* xt, 
     return sqrt(q) / S(double(T));
   }
   if (t != T) return S(0.0);
+  if (c.loss_kind == 3) {
+    S L = S(0.0);
+    for (int k = 0; k < 3; ++k)
+      if (c.loss_mask & (1 << k)) { const S d = p[k] - S(tg[k]); L = L + d * d; }
+    for (int k = 12; k < 18; ++k) L = L + p[k] * p[k];   // |v|^2 + |omega|^2 (p = the body's record)
+    return L;
+  }
   const S* p0 = x0 + 18 * lb;
   return -(p[0] - p0[0]) / S(T * c.dt);
 }
@@ -792,6 +810,7 @@ static S rollout_env(const Ctx& C, int e, std::vector<S>& x, std::vector<S>& lam
       for (int j = 0; j < E.nj; ++j) u[j] = S(c.u[(size_t)t * c.u_stride + E.j0 + j]);
     StepIn<S> in{x.data(), lam.data(), u.data(), invm.data(), invI.data(), damp.data(), S(c.mu[e]),
                  ap.data(), ac.data()};
+    in.rest = c.restitution ? c.restitution[e] : 0.0;
     step_env(C.M, E, in, xn.data(), ln.data(), W.data(), t, stats);
     if (c.noise > 0.0)
       for (int i = 0; i < n; ++i) xn[i] = xn[i] * S(1.0 + c.noise * noise_r(c.noise_seed, e, t, i));
@@ -847,6 +866,7 @@ int oracle_step(const oracle_model* m, const double* x, const double* lam, const
     const EnvTopo& E = C.topo[e];
     StepIn<double> in{x + 18 * E.b0, lam + E.lam_off, u + E.j0, m->inv_mass + E.b0, m->inv_inertia + 3 * E.b0,
                       m->damping + E.j0, m->mu[e], m->anchor_p + 3 * E.j0, m->anchor_c + 3 * E.j0};
+    in.rest = m->restitution ? m->restitution[e] : 0.0;
     step_env<double>(C.M, E, in, xn + 18 * E.b0, lamn + E.lam_off, m->mlp_w, t);
   }
   return 0;
@@ -988,6 +1008,7 @@ int oracle_rollout_grad(const oracle_model* m, const double* x0, const double* d
       for (int i = 0; i < n; ++i) x0v[i] = Var(x0[18 * E.b0 + i]);
       std::vector<Var> xn(n), ln(E.lam_size);
       StepIn<Var> in{xv.data(), lv.data(), uv.data(), mv.data(), Iv.data(), dv.data(), muv, apv.data(), acv.data()};
+      in.rest = c.restitution ? c.restitution[e] : 0.0;
       step_env<Var>(C.M, E, in, xn.data(), ln.data(), Wv.data(), t);
       const Var lt = loss_term<Var>(C.M, E, e, t + 1, T, xn.data(), x0v.data());
       tp.adj.assign(tp.nodes.size(), 0.0);
@@ -1049,6 +1070,7 @@ long long oracle_count_flops(const oracle_model* m, int env, const double* x, co
   std::vector<Cnt> acv(m->anchor_c + 3 * E.j0, m->anchor_c + 3 * (E.j0 + E.nj));
   StepIn<Cnt> in{xv.data(), lv.data(), uv.data(), mv.data(), Iv.data(), dv.data(), Cnt(m->mu[env]), apv.data(),
                  acv.data()};
+  in.rest = m->restitution ? m->restitution[env] : 0.0;
   flop_counter() = 0;
   step_env<Cnt>(C.M, E, in, xn.data(), ln.data(), Wv.data(), t);
   return (long long)flop_counter();
@@ -1079,6 +1101,7 @@ long long oracle_count_tape_edges(const oracle_model* m, int env, const double* 
   for (int i = 0; i < 3 * E.nj; ++i) acv[i] = Var::input(m->anchor_c[3 * E.j0 + i]);
   StepIn<Var> in{xv.data(), lv.data(), uv.data(), mv.data(), Iv.data(), dv.data(), Var::input(m->mu[env]),
                  apv.data(), acv.data()};
+  in.rest = m->restitution ? m->restitution[env] : 0.0;
   step_env<Var>(C.M, E, in, xn.data(), ln.data(), Wv.data(), t);
   long long edges = 0;
   for (const auto& n : tp.nodes) edges += (n.a >= 0) + (n.b >= 0);

@@ -29,7 +29,8 @@ typedef struct {
   const double *u;            /* [T_max][u_stride] torque tape (ctrl_kind 0) */
   int u_stride, T_max;
   double dt, gravity[3], beta, gamma, spec_margin;
-  int n_iters, ground, loss_kind, loss_mask;
+  int n_iters, ground, loss_kind, loss_mask;   /* loss_kind 3: final state: masked squared
+                                                 position error + |v|^2 + |omega|^2 at T */
   int ctrl_kind;              /* 0 tape, 1 MLP controller shared by all envs */
   int mlp_in, mlp_h1, mlp_h2, mlp_out, mlp_n_params;
   const double *mlp_w;        /* W1[h1][in] b1 W2[h2][h1] b2 W3[out][h2] b3 */
@@ -68,6 +69,14 @@ typedef struct {
      before step t is reversed; the loss term of x^{t+1} enters undecayed.
      1: the exact derivative. */
   double grad_decay;
+  /* restitution (section 2.1.1's ball): per env e [E] or NULL (0).  A contact
+     whose approach speed at the predicted velocities v* (before the warm
+     start), v_n = J_n v* < -rest_threshold, would close its gap within the
+     step (gap + dt v_n < 0) gets the normal-row bias min(b, e v_n), b the
+     speculative or Baumgarte bias: it separates at e times its approach
+     speed unless the push-out is faster. */
+  const double *restitution;
+  double rest_threshold;
 } oracle_model;
 
 /* Warm-start network shape and training-record layout. */

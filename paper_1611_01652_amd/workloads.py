@@ -57,6 +57,7 @@ SEED_BASE = 1611016520
 LOSS_FINAL_SQDIST = 0   # sum_k mask_k (p_k(T) - target_k)^2
 LOSS_MEAN_DIST = 1      # (1/T) sum_{t=1..T} |mask*(p(t) - target)|
 LOSS_NEG_MEAN_VELX = 2  # -(p_x(T) - p_x(0)) / (T dt)
+LOSS_FINAL_STATE = 3    # sum_k mask_k (p_k(T) - target_k)^2 + |v(T)|^2 + |omega(T)|^2
 
 SPHERE_GROUND = 1
 SPHERE_PAIR = 2
@@ -121,6 +122,8 @@ class Workload:
     ckpt_every: int = 50
     min_team: int = 0
     grad_decay: float = 1.0   # alpha: carried adjoints shrink by this per step (1: exact gradient)
+    restitution: Optional[np.ndarray] = None   # [E] coefficient e per env (None: 0)
+    rest_threshold: float = 0.5                # approach speed (m/s) below which no bounce
     extra: Dict = field(default_factory=dict)
 
     @property
@@ -168,7 +171,9 @@ class Workload:
             dt=self.dt, gravity=self.gravity, beta=self.beta, gamma=self.gamma,
             spec_margin=self.spec_margin, n_iters=self.n_iters, warm=self.warm, ground=self.ground,
             loss_kind=self.loss_kind, loss_mask=self.loss_mask, T_max=self.T_max,
-            ckpt_every=self.ckpt_every, min_team=self.min_team, grad_decay=self.grad_decay, extra=dict(self.extra))
+            ckpt_every=self.ckpt_every, min_team=self.min_team, grad_decay=self.grad_decay,
+            restitution=None if self.restitution is None else self.restitution[envs],
+            rest_threshold=self.rest_threshold, extra=dict(self.extra))
 
     def with_steps(self, T: int) -> "Workload":
         """Same model, horizon cut to T steps (tape truncated)."""
@@ -264,6 +269,48 @@ def ball_throw(seed_salt: int = 0, T: int = 300) -> Workload:
                     target=f32(tgt[None]), T_env=np.array([T], np.int32), u=np.zeros((T, 0)),
                     dt=0.01, ground=1, loss_kind=LOSS_FINAL_SQDIST, loss_mask=3, T_max=T,
                     ckpt_every=50)
+
+
+def shell_inertia(m, r):
+    return [2.0 / 3.0 * m * r * r] * 3
+
+
+def paper_ball(v0=(0.0, 0.0, 0.0), w0=(0.0, 0.0, 0.0), n_envs: int = 1, T: int = 500, dt: float = 0.01,
+               e: float = 0.5, mu: float = 1.0, target=(10.0, 0.0)) -> Workload:
+    """The ball of section 2.1.1: 1 m diameter, friction 1, restitution 0.5,
+    starting at rest on the ground at (0, 0) and asked to lie still at (10, 0)
+    after 5 s (T = 500 steps of 10 ms).  The six parameters are the initial
+    velocity and angular velocity.  Mass 1 kg with a thin-shell inertia
+    (2/3 m r^2), as a soccer ball.  The loss is the squared xy distance to
+    the target plus |v|^2 + |omega|^2 at T.  v0 and w0 are [3] or [n_envs, 3]."""
+    r, m = 0.5, 1.0
+    v0 = np.broadcast_to(np.asarray(v0, np.float64), (n_envs, 3))
+    w0 = np.broadcast_to(np.asarray(w0, np.float64), (n_envs, 3))
+    b = _Builder()
+    for k in range(n_envs):
+        b.body(m, shell_inertia(m, r), p=(0, 0, r), R=np.eye(3), v=v0[k], w=w0[k])
+        b.sphere(k, (0, 0, 0), r, SPHERE_GROUND)
+        b.end_env()
+    a = b.arrays()
+    tg = np.array([target[0], target[1], 0.0])
+    return Workload(name="paper-ball", n_envs=n_envs, **a, mu=f32(np.full(n_envs, mu)),
+                    loss_body=np.arange(n_envs, dtype=np.int32), target=f32(np.tile(tg, (n_envs, 1))),
+                    T_env=np.full(n_envs, T, np.int32), u=np.zeros((T, 0)), dt=dt, ground=1,
+                    loss_kind=LOSS_FINAL_STATE, loss_mask=3, T_max=T, ckpt_every=50,
+                    restitution=f32(np.full(n_envs, e)))
+
+
+def paper_ball_throws(n_envs: int = 256, T: int = 500, seed_salt: int = 0) -> Workload:
+    """A batch of the section 2.1.1 ball with seeded throws: initial velocity
+    (U(2, 10), U(-2, 2), U(0, 6)) m/s and angular velocity (U(-5, 5),
+    U(-25, 5), U(-5, 5)) rad/s (mostly backspin), each asked to lie still at
+    (10, 0) after T steps."""
+    rng = rng_for(11, seed_salt)
+    v0 = np.stack([rng.uniform(2, 10, n_envs), rng.uniform(-2, 2, n_envs), rng.uniform(0, 6, n_envs)], 1)
+    w0 = np.stack([rng.uniform(-5, 5, n_envs), rng.uniform(-25, 5, n_envs), rng.uniform(-5, 5, n_envs)], 1)
+    w = paper_ball(v0=v0, w0=w0, n_envs=n_envs, T=T)
+    w.name = "paper-ball-throws"
+    return w
 
 
 # --------------------------------------------------------------------------
