@@ -7,7 +7,7 @@
  * x^{t+1} = f_ph(x^t, u^t) (paper, section 2.1 and eq. (L)) is:
  *   joint torques u and damping -> velocity prediction with gravity ->
  *   contact candidates and gap test -> constraint rows (Jacobians, effective
- *   masses, Baumgarte / speculative bias) -> warm start from the previous
+ *   masses, Baumgarte / speculative bias, restitution) -> warm start from the previous
  *   step's impulses -> a fixed number of projected Gauss-Seidel sweeps in a
  *   fixed colour-major order -> semi-implicit Euler and rotation
  *   renormalisation N(A) = (3A - A A^T A)/2 (eq. (1)).
@@ -56,7 +56,7 @@
 extern "C" {
 #endif
 
-#define SIM_ABI_VERSION 5
+#define SIM_ABI_VERSION 6
 
 typedef struct sim_model* sim_handle;
 
@@ -79,6 +79,8 @@ typedef enum {
 #define SIM_LOSS_FINAL_SQDIST 0  /* sum_k mask_k (p_k(T_e) - target_k)^2                */
 #define SIM_LOSS_MEAN_DIST 1     /* (1/T_e) sum_{t=1..T_e} |mask*(p(t) - target)|          */
 #define SIM_LOSS_NEG_MEAN_VELX 2 /* -(p_x(T_e) - p_x(0)) / (T_e dt)  (mean forward speed) */
+#define SIM_LOSS_FINAL_STATE 3   /* sum_k mask_k (p_k(T_e) - target_k)^2 + |v(T_e)|^2 + |omega(T_e)|^2
+                                    (the ball of section 2.1.1: at rest on the target) */
 
 /* control kinds (eq. (g) of section 2.2 without the recurrent state) */
 #define SIM_CTRL_TAPE 0 /* open-loop torques u[T_max][J] */
@@ -193,6 +195,16 @@ typedef struct {
      mlp_sizes in = 2 J_e + 2 + mlp_rec and out = J_e + mlp_rec, and h^t rides
      at the end of each env's carried-state block */
   int32_t mlp_rec;
+  /* Restitution (the ball of section 2.1.1 has e = 0.5): restitution[e] in
+     [0, 1] per env (host, NULL: 0 everywhere).  A contact whose normal
+     velocity at the predicted velocities v* (gravity and torques applied,
+     before the warm start), v_n = J_n v*, is below -rest_threshold and would
+     close its gap within the step (gap + dt v_n < 0) takes the normal-row
+     bias min(b, e v_n), b its speculative or Baumgarte bias: it leaves at e
+     times its approach speed unless the push-out is faster.  The threshold
+     (m/s, >= 0) keeps resting contacts from bouncing. */
+  const float* restitution;
+  float rest_threshold;
 } sim_model_desc;
 
 /* Sizes derived by sim_init. */

@@ -135,8 +135,9 @@ SHD_FLAT void env_single_step(const Team& tm, const DevModel& M, const Env& E, b
   }
 }
 
-// loss adjoint into pbar of the loss body for the state after step t1
-// (1-based); tg: the env's target (held in registers by the caller: a global
+// loss adjoint into the adjoint record pbar of the loss body for the state
+// after step t1 (1-based), p its record (the final-state kind reads the
+// velocities; the others the position only); tg: the env's target (held in registers by the caller: a global
 // load inside the step loop would wait for the reverse sweep's in-flight
 // fetches)
 SHD void loss_adj(const DevModel& M, const Env& E, int t1, const float* p, const float* tg, float dl, float* pbar) {
@@ -156,6 +157,12 @@ SHD void loss_adj(const DevModel& M, const Env& E, int t1, const float* p, const
     return;
   }
   if (t1 != E.T) return;
+  if (M.loss_kind == 3) {
+    for (int k = 0; k < 3; ++k)
+      if (M.loss_mask & (1 << k)) pbar[k] += dl * 2.f * (p[k] - tg[k]);
+    for (int k = BV; k < BW + 3; ++k) pbar[k] += dl * 2.f * p[k];
+    return;
+  }
   pbar[0] += -dl / ((float)E.T * M.dt);
 }
 
@@ -224,6 +231,7 @@ SHD void replay_to_sweeps(const Team& tm, const DevModel& M, const Env& E, const
   f_torques(tm, E, act);
   f_predict(tm, M, E, act);
   tm.sync();
+  if (M.has_rest) f_save_vel(tm, E, act);
   f_rows(tm, M, E, act);
   f_warm(tm, E, act);
   f_pgs(tm, M, E, act, hist);
@@ -265,7 +273,7 @@ SHD_FLAT void env_recompute(const Team& tm, const DevModel& M, const Env& E, boo
     tm.sync();
   }
   if (live && t1 == T && tm.tl == 0)
-    for (int k = 0; k < 3; ++k) seg[(size_t)T * sstride + k] = E.body(E.lb)[BP + k];
+    for (int k = 0; k < 18; ++k) seg[(size_t)T * sstride + k] = E.body(E.lb)[k];
 }
 
 // SAVED: the working sets are saved (segment or trajectory mode, M.dump !=

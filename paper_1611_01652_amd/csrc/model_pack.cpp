@@ -38,7 +38,7 @@ sim_status fail(sim_status s, const std::string& m) {
 //  ground: colour = rank of the sphere among its body's ground spheres;
 //  pairs:  round-robin edge colouring of the env's bodies (padded to even);
 // empty colours are dropped (they do not change the order).
-sim_status build_env(const sim_model_desc& d, int e, HostEnv& H) {
+sim_status build_env(const sim_model_desc& d, int e, bool keep_v, HostEnv& H) {
   const int b0 = d.env_body_off[e], b1 = d.env_body_off[e + 1];
   const int j0 = d.env_joint_off[e], j1 = d.env_joint_off[e + 1];
   const int s0 = d.env_sphere_off[e], s1 = d.env_sphere_off[e + 1];
@@ -187,6 +187,7 @@ sim_status build_env(const sim_model_desc& d, int e, HostEnv& H) {
     c[3] = d.sphere_radius[gsph[g]];
   }
   H.cst[8 * H.nb + JS * H.nj + 4 * H.G] = d.mu[e];
+  H.cst[8 * H.nb + JS * H.nj + 4 * H.G + 1] = d.restitution ? d.restitution[e] : 0.f;
   // team size: enough lanes for the widest joint colour and half the bodies
   H.team = std::min(64, next_pow2(std::max({1, max_col, (H.nb + 1) / 2})));
   int mf = 0, ma = 0;
@@ -199,7 +200,7 @@ sim_status build_env(const sim_model_desc& d, int e, HostEnv& H) {
     mf = mlp_fwd_floats(d.mlp_sizes[0], d.mlp_sizes[1], d.mlp_sizes[2], d.mlp_sizes[3]);
     ma = mlp_adj_floats(d.mlp_sizes[0], d.mlp_sizes[1], d.mlp_sizes[2], d.mlp_sizes[3]);
   }
-  const int vs = vsave_floats(d.ws_kind, H.nb);
+  const int vs = vsave_floats(keep_v, H.nb);
   H.fwd_floats = make_lay(H.nb, H.nj, H.G, H.P, H.ncol, H.ncand, H.nslot, H.lam, d.n_iters, false, mf, ma, vs).total;
   H.adj_floats = make_lay(H.nb, H.nj, H.G, H.P, H.ncol, H.ncand, H.nslot, H.lam, d.n_iters, true, mf, ma, vs).total;
   H.dump_floats = dump_stride_of(H.fwd_floats, d.n_iters, H.nslot, H.nb);
@@ -231,9 +232,10 @@ sim_status pack_model(const sim_model_desc* d, PackedModel& P, std::string& err)
   }
   // per-env buffer sizes of the three reverse sweep modes
   std::vector<long long> sz_replay(E), sz_segment(E), sz_traj(E);
+  const bool keep_v = d->ws_kind || desc_has_rest(d);   // as make_env sizes the LDS layout
   for (int e = 0; e < E; ++e) {
     HostEnv H;
-    const sim_status st = build_env(*d, e, H);
+    const sim_status st = build_env(*d, e, keep_v, H);
     if (st != SIM_OK) { g_msg = nullptr; return st; }
     int* hd = &P.hdr[(size_t)e * H_COUNT];
     hd[H_B0] = d->env_body_off[e]; hd[H_NB] = H.nb; hd[H_J0] = d->env_joint_off[e]; hd[H_NJ] = H.nj;

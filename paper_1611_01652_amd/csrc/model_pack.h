@@ -25,4 +25,13 @@ constexpr long long kGradMemDefault = 32LL << 30;
 // (offsets, scalars) are done by the caller.
 sim_status pack_model(const sim_model_desc* d, PackedModel& P, std::string& err);
 
+// Some env has a restitution coefficient > 0: the steps then keep the
+// predicted velocities in LDS for the restitution adjoint.
+inline bool desc_has_rest(const sim_model_desc* d) {
+  if (!d->restitution) return false;
+  for (int e = 0; e < d->n_envs; ++e)
+    if (d->restitution[e] > 0.f) return true;
+  return false;
+}
+
 }  // namespace sim

@@ -315,7 +315,9 @@ sim_status sim_init(const sim_model_desc* d, sim_handle* out) {
   if (d->n_iters < 0) return fail(SIM_E_ARG, "n_iters < 0");
   if (d->ckpt_every < 1) return fail(SIM_E_ARG, "ckpt_every < 1");
   if (d->T_max < 0) return fail(SIM_E_ARG, "T_max < 0");
-  if (d->loss_kind < 0 || d->loss_kind > 2) return fail(SIM_E_ARG, "unknown loss_kind");
+  if (d->loss_kind < 0 || d->loss_kind > 3) return fail(SIM_E_ARG, "unknown loss_kind");
+  if (!(d->rest_threshold >= 0.f) || !std::isfinite(d->rest_threshold))
+    return fail(SIM_E_ARG, "rest_threshold must be finite and >= 0");
   if (!(d->gamma >= 0.f)) return fail(SIM_E_ARG, "gamma < 0");
   if (d->min_team < 0 || d->min_team > 64 || (d->min_team & (d->min_team - 1)) != 0)
     return fail(SIM_E_ARG, "min_team must be 0 or a power of two <= 64");
@@ -337,6 +339,10 @@ sim_status sim_init(const sim_model_desc* d, sim_handle* out) {
   }
   for (int j = 0; j < J; ++j)
     if (!(d->damping[j] >= 0.f) || !std::isfinite(d->damping[j])) return fail(SIM_E_ARG, "damping < 0");
+  if (d->restitution)
+    for (int e = 0; e < E; ++e)
+      if (!(d->restitution[e] >= 0.f && d->restitution[e] <= 1.f))
+        return fail(SIM_E_ARG, "restitution outside [0, 1] (env " + std::to_string(e) + ")");
 
   // per-env validation and packing happen on the host before any device call
   PackedModel P;
@@ -365,6 +371,8 @@ sim_status sim_init(const sim_model_desc* d, sim_handle* out) {
   M.solve_mode = d->solve_mode; M.tol = d->tol; M.max_iters = d->max_iters;
   M.ws_kind = d->ws_kind; M.fb_iters = d->fb_iters; M.fb_tol = d->fb_tol;
   M.decay = d->use_grad_decay ? d->grad_decay : 1.f;
+  M.has_rest = desc_has_rest(d) ? 1 : 0;
+  M.rest_th = d->rest_threshold;
   M.ctrl = d->ctrl_kind == 1 ? 1 : 0;   // (before the LDS sizes: the controller adds a shared region)
 
   h->lam_off = P.lam_off;

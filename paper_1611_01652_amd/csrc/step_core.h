@@ -122,14 +122,16 @@ struct DevModel {
   const uint16_t* wsn; // warm-start network, bfloat16 [4867]
   int dump;           // reverse sweep buffer: DUMP_REPLAY, DUMP_SEGMENT or DUMP_TRAJECTORY
   float decay;        // gradient decay per reversed step (1: the exact derivative)
+  int has_rest;       // some env has restitution > 0 (the predicted velocities are kept)
+  float rest_th;      // approach speed below which contacts do not bounce
 };
 // Reverse sweep buffer modes: step-start states of one segment (each step is
 // replayed), saved working sets of one segment, or of the whole trajectory
 // (all segments recomputed in a separate launch).  An env's block starts on a
 // SEG_UNIT-float boundary; in trajectory mode its last SEG_TAIL floats hold
-// the loss body's final position.
+// the loss body's final state record.
 enum { DUMP_REPLAY = 0, DUMP_SEGMENT = 1, DUMP_TRAJECTORY = 2 };
-enum { SEG_UNIT = 64, SEG_TAIL = 4 };
+enum { SEG_UNIT = 64, SEG_TAIL = 20 };
 // tape row: s, h1, h2, du, d2, d1 (pre-activation adjoints)
 SHD int tape_s(const DevModel&) { return 0; }
 SHD int tape_h1(const DevModel& M) { return M.mlp_in; }
@@ -157,9 +159,10 @@ enum { JAP = 0, JAC = 3, JXP = 6, JXC = 9, JUP = 12, JUC = 15, JD = 18, JU = 19,
 // reads its part with two 16-byte loads; m and bias are kept in both
 // (RMA, RBA: the copies of body a's part).  Then (Jl, lambda), lambda0.
 enum { RJA = 0, RMA = 3, RWA = 4, RBA = 7, RJB = 8, RM = 11, RWB = 12, RBI = 15, RJL = 16, RL = 19, RL0 = 20, RS = 24 };
-// contact extras slot: tangents, friction mass, gap, store offset, code, and
-// (tolerance mode) the warm-start features XF[7] and network outputs XY[3]
-enum { XT1 = 0, XT2 = 3, XMT = 6, XGAP = 7, XSTORE = 8, XCODE = 9, XF = 10, XY = 17 };
+// contact extras slot: tangents, friction mass, gap, store offset, code,
+// (tolerance mode) the warm-start features XF[7] and network outputs XY[3],
+// and 1 where restitution set the normal bias
+enum { XT1 = 0, XT2 = 3, XMT = 6, XGAP = 7, XSTORE = 8, XCODE = 9, XF = 10, XY = 17, XREST = 20 };
 // row adjoint slot, in the same shape: (Ja-bar, -) (Wa-bar, -) (Jb-bar, m-bar)
 // (Wb-bar, bias-bar) (Jl-bar, lambda-bar)
 enum { QJA = 0, QWA = 4, QJB = 8, QM = 11, QWB = 12, QB = 15, QJL = 16, QL = 19, RSA = 20 };
@@ -176,7 +179,7 @@ struct Lay {
   int total_fwd, total;
 };
 enum { MISC_LOSS = 0, MISC_FLAGS = 1, MISC_NCON = 2, MISC_MU = 3, MISC_GMU = 4, MISC_GMUC = 5, MISC_ITERS = 6,
-       MISC_FB = 7, MISC_N = 8 };
+       MISC_FB = 7, MISC_REST = 8, MISC_N = 12 };
 
 SHD int align4(int x) { return (x + 3) & ~3; }
 // Per-joint parameter adjoints of the reverse sweep, running totals over the
@@ -186,7 +189,7 @@ SHD int align4(int x) { return (x + 3) & ~3; }
 // compensations of the anchors [8, 11) and [11, 14).
 enum { JA_DAMP = 0, JA_DAMPC = 1, JA_ANCP = 2, JA_ANCC = 5, JA_ANC_COMP = 6, JA_FLOATS = 14 };
 // mlp_f / mlp_a: controller floats per env (s, h1, h2 / du, d2, d1, sbar), 0 without one
-// vs_f: floats of saved predicted velocities (learned warm start), 0 without
+// vs_f: floats of saved predicted velocities (learned warm start, restitution), 0 without
 SHD Lay make_lay(int nb, int nj, int G, int P, int ncol, int ncand, int nslot, int lam, int n_iters, bool adj,
                  int mlp_f = 0, int mlp_a = 0, int vs_f = 0) {
   Lay L;
@@ -291,7 +294,7 @@ SHD int mo_u(const DevModel& M) { return mo_h2(M) + align4(M.mlp_h2); }
 SHD int mo_d2(const DevModel& M) { return align4(M.mlp_out); }
 SHD int mo_d1(const DevModel& M) { return align4(M.mlp_out) + align4(M.mlp_h2); }
 SHD int mo_sb(const DevModel& M) { return mo_d1(M) + align4(M.mlp_h1); }
-SHD int vsave_floats(int ws_kind, int nb) { return ws_kind ? 6 * nb : 0; }
+SHD int vsave_floats(bool keep, int nb) { return keep ? 6 * nb : 0; }
 // Floats of one step's saved working set: the forward LDS region, the sweep
 // history and the step-start angular velocities.
 SHD int dump_stride_of(int total_fwd, int n_iters, int nslot, int nb) {
@@ -310,7 +313,7 @@ SHD Env make_env(const DevModel& M, int ie, float* lds, int n_iters, bool adj) {
   E.gcst = M.cst + h[H_CST];
   E.L = lds;
   E.lay = make_lay(E.nb, E.nj, E.G, E.P, E.ncol, E.ncand, E.nslot, E.lam_size, n_iters, adj, mlp_floats_fwd(M),
-                   mlp_floats_adj(M), vsave_floats(M.ws_kind, E.nb));
+                   mlp_floats_adj(M), vsave_floats(M.ws_kind || M.has_rest, E.nb));
   return E;
 }
 
@@ -325,7 +328,7 @@ SHD int n_joint_cols(const Env& E, bool act) { return act ? E.live()[1] : 0; }
 //   bodies  invm[nb], invI[3][nb], pair-sphere offset[3][nb], pair-sphere radius[nb]
 //   joints  20 floats each (JAP..JD layout, JU unused)
 //   ground  offset(3), radius  per ground sphere
-//   env     mu
+//   env     mu, restitution
 SHD int cst_joint(const Env& E) { return 8 * E.nb; }
 SHD int cst_ground(const Env& E) { return 8 * E.nb + JS * E.nj; }
 SHD int cst_env(const Env& E) { return 8 * E.nb + JS * E.nj + 4 * E.G; }
@@ -358,6 +361,7 @@ SHD void load_env_static(const Team& tm, const DevModel& M, const Env& E) {
     E.live()[0] = 0;
     E.live()[1] = m;
     E.misc()[MISC_MU] = E.gcst[cst_env(E)];
+    E.misc()[MISC_REST] = E.gcst[cst_env(E) + 1];
     E.misc()[MISC_LOSS] = 0.f;
     (*reinterpret_cast<int*>(E.misc() + MISC_FLAGS)) = 0;
     (*reinterpret_cast<int*>(E.misc() + MISC_ITERS)) = 0;
@@ -693,7 +697,21 @@ SHD void build_contact(const DevModel& M, const Env& E, int code, int s, const C
   *reinterpret_cast<int*>(x + XCODE) = code;
   float* rn = E.row(s);
   rn[RM] = rn[RMA] = 1.f / (K[0] + M.gamma);
-  rn[RBI] = rn[RBA] = (g.gap > 0.f ? g.gap : M.beta * g.gap) / M.dt;
+  float bias = (g.gap > 0.f ? g.gap : M.beta * g.gap) / M.dt;
+  // restitution: a contact that the predicted velocities (the body records
+  // now) would close within the step, approaching faster than the threshold,
+  // leaves at e times its approach speed unless the push-out is faster
+  float rest = 0.f;
+  const float e = E.misc()[MISC_REST];
+  if (e > 0.f) {
+    const float vn = row_jv(rn, Ba ? Ba + BV : nullptr, Ba ? Ba + BW : nullptr, Bb + BV, Bb + BW, !ground);
+    if (vn < -M.rest_th && vn * M.dt + g.gap < 0.f && e * vn < bias) {
+      bias = e * vn;
+      rest = 1.f;
+    }
+  }
+  x[XREST] = rest;
+  rn[RBI] = rn[RBA] = bias;
   const float* w = E.ws() + st;
   const f3 Lt = mk3(w[1], w[2], w[3]);
   rn[RL] = rn[RL0] = M.warm * w[0];
@@ -1278,7 +1296,8 @@ SHD void f_controls(const Team& tm, const DevModel& M, const Env& E, const float
   for (int i = tm.tl; i < rec; i += tm.ts) E.ws()[E.lam_imp + i] = tanhf(u[E.nj + i]);
 }
 
-// Loss term of the state after step t (1-based) for the loss body.
+// Loss term of the state after step t (1-based) for the loss body; p is its
+// record (position, rotation, velocity, angular velocity).
 SHD float loss_term(const DevModel& M, const Env& E, int t1, const float* p, const float* p0) {
   const float* tg = M.target + 3 * E.e;
   if (M.loss_kind == 0) {
@@ -1295,6 +1314,13 @@ SHD float loss_term(const DevModel& M, const Env& E, int t1, const float* p, con
     return q > 0.f ? sqrtf(q) / (float)E.T : 0.f;
   }
   if (t1 != E.T) return 0.f;
+  if (M.loss_kind == 3) {
+    float L = 0.f;
+    for (int k = 0; k < 3; ++k)
+      if (M.loss_mask & (1 << k)) { const float d = p[k] - tg[k]; L += d * d; }
+    for (int k = BV; k < BW + 3; ++k) L += p[k] * p[k];
+    return L;
+  }
   return -(p[0] - p0[0]) / ((float)E.T * M.dt);
 }
 
@@ -1307,6 +1333,7 @@ SHD void env_step(const Team& tm, const DevModel& M, const Env& E, const float* 
   f_torques(tm, E, act);
   f_predict(tm, M, E, act);
   tm.sync();
+  if (M.has_rest) f_save_vel(tm, E, act);
   f_rows(tm, M, E, act);
   f_warm(tm, E, act);
   f_pgs(tm, M, E, act, nullptr);
@@ -1365,7 +1392,8 @@ SHD void f_features(const Team& tm, const DevModel& M, const Env& E, bool act) {
   tm.sync();
 }
 
-// Predicted velocities, kept for a restart from the plain warm start.
+// Predicted velocities, kept for a restart from the plain warm start and for
+// the adjoint of restitution.
 template <class Team>
 SHD void f_save_vel(const Team& tm, const Env& E, bool act) {
   if (act)
@@ -1551,13 +1579,11 @@ SHD void env_step_solve(const Team& tm, const DevModel& M, const Env& E, const f
   f_torques(tm, E, act);
   f_predict(tm, M, E, act);
   tm.sync();
+  if (M.ws_kind || M.has_rest) f_save_vel(tm, E, act);
   f_rows(tm, M, E, act);
   const bool rec = ra && ra->rec && ra->every > 0 && t % ra->every == 0;
   if (M.ws_kind || rec) f_features(tm, M, E, act);
-  if (M.ws_kind) {
-    f_save_vel(tm, E, act);
-    f_learned_ws(tm, M, E, act);
-  }
+  if (M.ws_kind) f_learned_ws(tm, M, E, act);
   f_warm(tm, E, act);
   int nrows = 0;
   for (int c = 0; c < E.ncol && act; ++c) nrows += E.act_cnt()[c];
@@ -2425,6 +2451,32 @@ SHD void a_contact(const DevModel& M, const Env& E, int code, int s) {
   const CGeo g = contact_geo(E, code);
   const float* x = E.row(s + 3);
   const float* xa = E.rowA(s + 3);
+  const bool rest = x[XREST] != 0.f;
+  if (rest) {
+    // bias = e v_n, v_n = Jl.(vb - va) + Ja.wa + Jb.wb at the predicted
+    // velocities: adjoints of the normal row's Jacobian and of v*, w*
+    float* q = E.rowA(s);
+    const float* r = E.row(s);
+    const float vnb = E.misc()[MISC_REST] * q[QB];
+    const float* sb = E.vsave(rb.b);
+    float* Ab = E.bodyA(rb.b);
+    for (int k = 0; k < 3; ++k) {
+      q[QJL + k] += vnb * sb[k];
+      q[QJB + k] += vnb * sb[3 + k];
+      Ab[AV + k] += vnb * r[RJL + k];
+      Ab[AW + k] += vnb * r[RJB + k];
+    }
+    if (!ground) {
+      const float* sa = E.vsave(rb.a);
+      float* Aa = E.bodyA(rb.a);
+      for (int k = 0; k < 3; ++k) {
+        q[QJL + k] -= vnb * sa[k];
+        q[QJA + k] += vnb * sa[3 + k];
+        Aa[AV + k] -= vnb * r[RJL + k];
+        Aa[AW + k] += vnb * r[RJA + k];
+      }
+    }
+  }
   // row_finish adjoints: normal via m, tangents via mt = 2/(K1+K2)
   {
     const float m = E.row(s)[RM];
@@ -2450,7 +2502,7 @@ SHD void a_contact(const DevModel& M, const Env& E, int code, int s) {
       rab = rab + cross(jab, dirs[q]);
     }
   }
-  const float gapb = E.rowA(s)[QB] * (g.gap > 0.f ? 1.f : M.beta) / M.dt;
+  const float gapb = rest ? 0.f : E.rowA(s)[QB] * (g.gap > 0.f ? 1.f : M.beta) / M.dt;
   float* Ab = E.bodyA(rb.b);
   const float* Bb = E.body(rb.b);
   if (ground) {

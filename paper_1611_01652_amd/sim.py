@@ -20,7 +20,7 @@ FLAG_NONFINITE = 1
 FLAG_CONTACT_OVERFLOW = 2
 
 # layout of the descriptor and info structs below (SIM_ABI_VERSION)
-ABI_VERSION = 5
+ABI_VERSION = 6
 
 # reverse sweep memory modes (sim_model_desc.grad_store)
 GRAD_STORE = {"auto": 0, "replay": 1, "segment": 2, "trajectory": 3}
@@ -48,6 +48,7 @@ class SimDesc(C.Structure):
         ("ws_kind", C.c_int32), ("ws_net", _F32P), ("fb_iters", C.c_int32), ("fb_tol", C.c_float),
         ("grad_store", C.c_int32), ("grad_mem_limit", C.c_int64),
         ("use_grad_decay", C.c_int32), ("grad_decay", C.c_float), ("mlp_rec", C.c_int32),
+        ("restitution", _F32P), ("rest_threshold", C.c_float),
     ]
 
 
@@ -117,6 +118,9 @@ def make_desc(w):
     alpha = float(getattr(w, "grad_decay", 1.0))
     d.use_grad_decay = int(alpha != 1.0)
     d.grad_decay = alpha
+    if getattr(w, "restitution", None) is not None:
+        d.restitution = f(w.restitution)
+    d.rest_threshold = float(getattr(w, "rest_threshold", 0.5))
     solve = extra.get("solve")
     if solve is not None:
         d.solve_mode = int(solve.get("mode", 1))

@@ -65,7 +65,7 @@ def _desc64(w):
             a = a if a.size else np.zeros(1, np.int32)
             keep.append(a)
             setattr(d, name, a.ctypes.data_as(C.POINTER(C.c_int32)))
-        elif typ == C.POINTER(C.c_double) and hasattr(w, name):
+        elif typ == C.POINTER(C.c_double) and getattr(w, name, None) is not None:
             a = np.ascontiguousarray(np.asarray(getattr(w, name), np.float64)).reshape(-1)
             a = a if a.size else np.zeros(1)
             keep.append(a)
@@ -81,6 +81,7 @@ def _desc64(w):
     d.grad_mem_limit = int((getattr(w, "extra", None) or {}).get("grad_mem_limit", 0))
     alpha = f(getattr(w, "grad_decay", 1.0))
     d.use_grad_decay, d.grad_decay = int(alpha != 1.0), alpha
+    d.rest_threshold = f(getattr(w, "rest_threshold", 0.5))
     mlp = w.extra.get("mlp") if getattr(w, "extra", None) else None
     if mlp is not None:
         d.ctrl_kind = 1
@@ -148,7 +149,8 @@ def _sizes(w):
 
 def test_reverse_sweep_memory_modes_and_their_sizes():
     # buffer sizes of the three modes, per env aligned to 64 floats: K_ck
-    # step-start states, K_ck working sets, T working sets and the final position
+    # step-start states, K_ck working sets, T working sets and the loss
+    # body's final state record (18 floats, 20 with the alignment)
     w = W.planar_arms(n_envs=3, T=130)
     sz = {m: _sizes(_store(w, m)) for m in ("replay", "segment", "trajectory")}
     assert [sz[m]["mode"] for m in sz] == list(sz)
@@ -157,7 +159,7 @@ def test_reverse_sweep_memory_modes_and_their_sizes():
     assert sz["replay"]["seg_floats"] == 3 * up(K * (18 * nb + lam))
     ws = sz["segment"]["seg_floats"] // 3 // K
     assert sz["segment"]["seg_floats"] == 3 * up(K * ws)
-    assert sz["trajectory"]["seg_floats"] == 3 * up(w.T_max * ws + 4)
+    assert sz["trajectory"]["seg_floats"] == 3 * up(w.T_max * ws + 20)
     # the automatic choice: trajectory while it fits the limit, then segment, then replay
     w.extra["grad_store"] = "auto"
     assert _sizes(w)["mode"] == "trajectory"
@@ -169,6 +171,14 @@ def test_reverse_sweep_memory_modes_and_their_sizes():
 
 def _decayed(w, alpha):
     w.grad_decay = alpha
+    return w
+
+
+def _bouncy(w, e, seed=0):
+    """Restitution e (scalar) or uniform in [0, e) per env (seeded)."""
+    if seed:
+        e = np.random.default_rng(seed).uniform(0.0, e, size=w.n_envs)
+    w.restitution = np.broadcast_to(np.asarray(e, np.float32), (w.n_envs,)).copy()
     return w
 
 
@@ -201,6 +211,19 @@ def _store(w, mode):
     (lambda: _decayed(_store(W.uneven_chains(n_envs=5, T=120, seed_salt=4), "replay"), 0.8), 1e-7),
     (lambda: _decayed(W.quadruped(n_envs=3, T_min=30, T_max=45, mlp_w=W.mlp_init(zero_output=False,
                                                                                    out_scale=0.3)), 0.9), 1e-8),
+    # restitution: the ball of section 2.1.1 (bounces, sliding, rolling) in
+    # the three reverse modes, thrown balls, a bouncing pile of spheres (pair
+    # contacts) and contact-rich chains
+    (lambda: W.paper_ball(v0=(8.565, 0, 5.796), w0=(0, -25.714, 0)), 1e-10),
+    (lambda: _store(W.paper_ball(v0=(8.565, 0, 5.796), w0=(0, -25.714, 0)), "segment"), 1e-10),
+    (lambda: _store(W.paper_ball(v0=(8.565, 0, 5.796), w0=(0, -25.714, 0)), "replay"), 1e-10),
+    (lambda: W.paper_ball(v0=[(3, 1, 4), (5, 0, 6), (1, -2, 3)], w0=[(2, -5, 1), (0, -10, 0), (3, 3, 3)],
+                          n_envs=3, T=300), 1e-10),
+    (lambda: _bouncy(W.free_spheres(np.array([[0, 0, .4], [.19, 0, .1], [.095, 0, .6]]), [.1] * 3, [1., 2., .7],
+                                    velocities=np.array([[0, 0, -2.], [0, 0, 0], [.5, 0, -3.]]), mu=0.5, T=120),
+                     0.7), 1e-9),
+    (lambda: _bouncy(W.uneven_chains(n_envs=6, T=150, seed_salt=2), 0.8, seed=5), 1e-7),
+    (lambda: _bouncy(_store(W.uneven_chains(n_envs=5, T=120, seed_salt=4), "replay"), 0.8, seed=6), 1e-7),
 ])
 def test_kernel_source_in_fp64_equals_oracle(maker, tol):
     w = maker()
@@ -235,12 +258,16 @@ def host_fp64_solve(w, rec_every=0, rec_cap=0):
     return dict(loss=loss, x_final=xf.T, iters=it, fallbacks=fb, records=rec, n_records=n)
 
 
-@pytest.mark.parametrize("learned,fb_tol", [(False, 1e-3), (True, 1e-3), (True, -1.0)])
-def test_tolerance_mode_kernel_source_in_fp64_equals_oracle(learned, fb_tol):
+@pytest.mark.parametrize("learned,fb_tol,rest", [(False, 1e-3, 0.0), (True, 1e-3, 0.0), (True, -1.0, 0.0),
+                                                 (False, 1e-3, 0.8), (True, 1e-3, 0.8)])
+def test_tolerance_mode_kernel_source_in_fp64_equals_oracle(learned, fb_tol, rest):
     # plain, learned (random network: rejected or accepted by its residual),
-    # and learned with every start rejected after five sweeps
+    # and learned with every start rejected after five sweeps; with and
+    # without restitution
     ws = W.wsn_init(seed_salt=2) if learned else None
     w = W.warm_start_chains(n_envs=5, T=90, seed_salt=3, ws_w=ws, fb_tol=fb_tol)
+    if rest:
+        _bouncy(w, rest, seed=7)
     got = host_fp64_solve(w, rec_every=3, rec_cap=20000)
     ref = Oracle(w).rollout_ex(rec_every=3, rec_cap=20000)
     assert _rel(got["x_final"], ref["x_final"]) < 1e-8
