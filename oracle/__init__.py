@@ -82,6 +82,7 @@ class _Model(C.Structure):
         ("ws_kind", C.c_int), ("ws_w", C.c_void_p), ("fb_iters", C.c_int), ("fb_tol", C.c_double),
         ("lam0", C.c_void_p), ("grad_decay", C.c_double),
         ("restitution", C.c_void_p), ("rest_threshold", C.c_double),
+        ("servo", C.c_int), ("servo_gain", C.c_void_p), ("servo_torque", C.c_void_p), ("servo_vmax", C.c_void_p),
     ]
 
 
@@ -178,6 +179,11 @@ class Oracle:
         if rest is not None:
             m.restitution = d("rest", rest)
         m.rest_threshold = f(getattr(w, "rest_threshold", 0.5))
+        if getattr(w, "servo_gain", None) is not None:
+            m.servo = 1
+            m.servo_gain = d("sg", w.servo_gain)
+            m.servo_torque = d("st", w.servo_torque)
+            m.servo_vmax = d("sv", w.servo_vmax)
         self._m = m
         self._keep = keep
         self.lib = _load()

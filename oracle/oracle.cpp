@@ -107,6 +107,7 @@ struct EnvTopo {
   std::vector<Con> order;       // canonical colour-major order of all candidate constraints
   int lam_off, lam_size;        // carried-state block: warm-start impulses, then the controller's h
   int lam_imp;                  // impulses in it (the rest is h)
+  int jr;                       // rows (and carried impulses) per joint: 5, 6 with servos
 };
 
 static bool joined(const Model& M, const EnvTopo& E, int ga, int gb) {
@@ -195,7 +196,8 @@ static EnvTopo build_topo(const Model& M, int e, int lam_off) {
     }
   }
   E.lam_off = lam_off;
-  E.lam_imp = 5 * E.nj + 4 * (int)E.ground.size() + 4 * (int)E.pairs.size();
+  E.jr = c.servo ? 6 : 5;
+  E.lam_imp = E.jr * E.nj + 4 * (int)E.ground.size() + 4 * (int)E.pairs.size();
   E.lam_size = E.lam_imp + (c.ctrl_kind == 1 ? c.mlp_rec : 0);
   return E;
 }
@@ -209,10 +211,10 @@ template <class S> struct Row {
   double lo = -INFINITY, hi = INFINITY;
 };
 template <class S> struct ConRows {
-  int kind;       // 0 joint (5 scalar rows), 1 contact (normal + friction block)
+  int kind;       // 0 joint (5 scalar rows, 6 with a servo), 1 contact (normal + friction block)
   int store;      // offset into the warm-start block
   int nrows;
-  Row<S> r[5];
+  Row<S> r[6];
   V3<S> t1, t2;   // contact tangents (for the tangent impulse carry)
   S mt = S(0.0);  // friction block effective mass
   S gap = S(0.0); // contact gap
@@ -399,7 +401,8 @@ void step_env(const Model& M, const EnvTopo& E, const StepIn<S>& in, S* xn, S* l
     const int a = pa >= 0 ? pa - E.b0 : -1;
     V3<S> n = cvt<S>(c.axis_p + 3 * gj), wa;
     if (a >= 0) { n = B.R[a] * n; wa = B.w[a]; }
-    const S tau = u[j] - in.damp[j] * dot(B.w[b] - wa, n);
+    // (a servo's target angle is not a torque: its joint takes the damping alone)
+    const S tau = (c.servo ? S(0.0) : u[j]) - in.damp[j] * dot(B.w[b] - wa, n);
     tq[b] = tq[b] + tau * n;
     if (a >= 0) tq[a] = tq[a] - tau * n;
   }
@@ -420,7 +423,7 @@ void step_env(const Model& M, const EnvTopo& E, const StepIn<S>& in, S* xn, S* l
       const int gj = k.idx, jl = gj - E.j0;
       const int pa = c.joint_parent[gj], b = c.joint_child[gj] - E.b0;
       const int a = pa >= 0 ? pa - E.b0 : -1;
-      C.kind = 0; C.nrows = 5; C.store = 5 * jl;
+      C.kind = 0; C.nrows = E.jr; C.store = E.jr * jl;
       const V3<S> rb = B.R[b] * V3<S>(in.anc_c[3 * jl], in.anc_c[3 * jl + 1], in.anc_c[3 * jl + 2]);
       V3<S> ra, Pa = V3<S>(in.anc_p[3 * jl], in.anc_p[3 * jl + 1], in.anc_p[3 * jl + 2]);
       if (a >= 0) { ra = B.R[a] * Pa; Pa = B.p[a] + ra; }
@@ -445,7 +448,23 @@ void step_env(const Model& M, const EnvTopo& E, const StepIn<S>& in, S* xn, S* l
         r.aa = -tk[q]; r.ab = tk[q];
         r.bias = beta * dot(tk[q], ax) / dt;
       }
-      for (int q = 0; q < 5; ++q) {
+      if (c.servo) {
+        // velocity motor: target rate from the hinge angle, clipped; impulse
+        // within the torque limit over the step
+        const V3<S> ub = B.R[b] * cvt<S>(c.perp_c + 3 * gj);
+        const S theta = atan2(dot(cross(ua, ub), na), dot(ua, ub));
+        S rate = S(c.servo_gain[gj]) * (u[jl] - theta);
+        const double vmax = c.servo_vmax[gj];
+        if (val(rate) > vmax) rate = S(vmax);
+        else if (val(rate) < -vmax) rate = S(-vmax);
+        Row<S>& r = C.r[5];
+        r.a = a; r.b = b;
+        r.aa = -na; r.ab = na;
+        r.bias = -rate;
+        r.hi = c.servo_torque[gj] * c.dt;
+        r.lo = -r.hi;
+      }
+      for (int q = 0; q < C.nrows; ++q) {
         Row<S>& r = C.r[q];
         r.m = S(1.0) / (finish_row(r, B) + gam);
         r.lam = S(c.warm) * in.lam[C.store + q];  // joints are always active: plain warm start
@@ -464,7 +483,7 @@ void step_env(const Model& M, const EnvTopo& E, const StepIn<S>& in, S* xn, S* l
         active_ground[k.idx] = 1;
         n = ez;
         rb_ = (cen[s] - rad * n) - B.p[b];
-        store = 5 * E.nj + 4 * k.idx;
+        store = E.jr * E.nj + 4 * k.idx;
         C.code = (1 << 24) | k.idx;
       } else {
         const PairCand& pc = E.pairs[k.idx];
@@ -480,7 +499,7 @@ void step_env(const Model& M, const EnvTopo& E, const StepIn<S>& in, S* xn, S* l
         n = val(L) < 1e-9 ? ez : (S(1.0) / L) * d;
         ra_ = (ca + raa * n) - B.p[a];
         rb_ = (cb - rbb * n) - B.p[b];
-        store = 5 * E.nj + 4 * (int)E.ground.size() + 4 * k.idx;
+        store = E.jr * E.nj + 4 * (int)E.ground.size() + 4 * k.idx;
       }
       C.kind = 1; C.nrows = 3; C.store = store; C.gap = gap;
       // tangent basis
@@ -533,7 +552,7 @@ void step_env(const Model& M, const EnvTopo& E, const StepIn<S>& in, S* xn, S* l
   const S mu = in.mu;
   const bool tolmode = c.solve_mode == 1;
   const size_t nc = cons.size();
-  std::vector<std::array<S, 5>> plain(nc);
+  std::vector<std::array<S, 6>> plain(nc);
   for (size_t i = 0; i < nc; ++i)
     for (int q = 0; q < cons[i].nrows; ++q) plain[i][q] = cons[i].r[q].lam;
   std::vector<V3<S>> v_pred, w_pred;
@@ -576,7 +595,7 @@ void step_env(const Model& M, const EnvTopo& E, const StepIn<S>& in, S* xn, S* l
     double res = 0.0;
     res_c = 0.0;
     for (auto& C : cons) {
-      const int nscalar = C.kind == 0 ? 5 : 1;
+      const int nscalar = C.kind == 0 ? C.nrows : 1;
       for (int q = 0; q < nscalar; ++q) {
         Row<S>& r = C.r[q];
         const S s = jdotv(r, B) + r.bias + gam * r.lam;
@@ -685,7 +704,7 @@ void step_env(const Model& M, const EnvTopo& E, const StepIn<S>& in, S* xn, S* l
   for (size_t i = 0; i < hn.size(); ++i) lamn[E.lam_imp + i] = hn[i];
   for (auto& C : cons) {
     if (C.kind == 0) {
-      for (int q = 0; q < 5; ++q) lamn[C.store + q] = C.r[q].lam;
+      for (int q = 0; q < C.nrows; ++q) lamn[C.store + q] = C.r[q].lam;
     } else {
       const V3<S> Lt = C.r[1].lam * C.t1 + C.r[2].lam * C.t2;
       lamn[C.store] = C.r[0].lam;

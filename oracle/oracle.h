@@ -77,6 +77,16 @@ typedef struct {
      speed unless the push-out is faster. */
   const double *restitution;
   double rest_threshold;
+  /* servo motors (section 2.1: gain, maximal torque, maximal velocity).  With
+     servo != 0 every hinge is driven by a velocity motor and u^t_j is its
+     target angle: a sixth row of the joint, angular about the parent's world
+     hinge axis n_a (J w = n_a . (w_b - w_a)), aims at the rate
+     clip(gain_j (u_j - theta_j), -vmax_j, vmax_j), theta_j the hinge angle
+     (the controller's angle sensor), with its impulse clamped to
+     [-torque_j dt, torque_j dt]; the joint's direct torque is then the
+     viscous damping alone.  Arrays [J]. */
+  int servo;
+  const double *servo_gain, *servo_torque, *servo_vmax;
 } oracle_model;
 
 /* Warm-start network shape and training-record layout. */

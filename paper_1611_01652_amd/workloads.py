@@ -124,6 +124,11 @@ class Workload:
     grad_decay: float = 1.0   # alpha: carried adjoints shrink by this per step (1: exact gradient)
     restitution: Optional[np.ndarray] = None   # [E] coefficient e per env (None: 0)
     rest_threshold: float = 0.5                # approach speed (m/s) below which no bounce
+    # servo motors: with servo_gain set, every hinge is a velocity motor and u
+    # holds target angles; gain (1/s), maximal torque (N m), maximal rate (rad/s) [J]
+    servo_gain: Optional[np.ndarray] = None
+    servo_torque: Optional[np.ndarray] = None
+    servo_vmax: Optional[np.ndarray] = None
     extra: Dict = field(default_factory=dict)
 
     @property
@@ -173,7 +178,10 @@ class Workload:
             loss_kind=self.loss_kind, loss_mask=self.loss_mask, T_max=self.T_max,
             ckpt_every=self.ckpt_every, min_team=self.min_team, grad_decay=self.grad_decay,
             restitution=None if self.restitution is None else self.restitution[envs],
-            rest_threshold=self.rest_threshold, extra=dict(self.extra))
+            rest_threshold=self.rest_threshold,
+            servo_gain=None if self.servo_gain is None else self.servo_gain[jidx],
+            servo_torque=None if self.servo_torque is None else self.servo_torque[jidx],
+            servo_vmax=None if self.servo_vmax is None else self.servo_vmax[jidx], extra=dict(self.extra))
 
     def with_steps(self, T: int) -> "Workload":
         """Same model, horizon cut to T steps (tape truncated)."""
@@ -503,6 +511,31 @@ def free_spheres(positions, radii, masses, velocities=None, mu=0.0, ground=True,
                     target=f32(np.zeros((1, 3))), T_env=np.array([T], np.int32), u=np.zeros((T, 0)),
                     dt=dt, gravity=tuple(gravity), ground=int(ground), loss_kind=LOSS_FINAL_SQDIST,
                     loss_mask=7, T_max=T, n_iters=n_iters)
+
+
+def with_servos(w: Workload, gain=30.0, torque=30.0, vmax=math.radians(45.0), targets=None) -> Workload:
+    """A copy of a workload whose hinges are all servo motors (section 2.1;
+    the arm of section 3.2 has gain 30 1/s, 30 N m and 45 deg/s): the control
+    tape then holds target angles (rad), `targets` [T, J] or the given
+    workload's tape as it stands."""
+    import copy
+    s = copy.copy(w)
+    J = w.n_joints
+    s.servo_gain = f32(np.broadcast_to(np.asarray(gain, np.float64), (J,)))
+    s.servo_torque = f32(np.broadcast_to(np.asarray(torque, np.float64), (J,)))
+    s.servo_vmax = f32(np.broadcast_to(np.asarray(vmax, np.float64), (J,)))
+    if targets is not None:
+        s.u = f32(targets)
+    s.name = w.name + "-servo"
+    return s
+
+
+def servo_targets(T: int, J: int, seed_salt: int = 0, amp: float = 0.6, hold: int = 40) -> np.ndarray:
+    """Seeded target-angle tape [T, J]: uniform targets in [-amp, amp] rad,
+    each held for `hold` steps."""
+    rng = rng_for(12, seed_salt)
+    n = (T + hold - 1) // hold
+    return f32(np.repeat(rng.uniform(-amp, amp, size=(n, J)), hold, axis=0)[:T])
 
 
 def mlp_param_count(sizes, skip_input_to_output=False):
