@@ -120,10 +120,17 @@ def algorithmic_bytes_per_env_step(w):
 GRAD_KEYS = ("g_x0", "g_u", "g_inv_mass", "g_inv_inertia", "g_mu", "g_damping", "g_anchor_p", "g_anchor_c")
 
 
-def _rel(a, b):
-    n = np.linalg.norm(b)
+def _rel(a, b, floor=0.0):
+    """|a - b| / max(|b|, floor), absolute below 1e-8."""
+    n = max(float(np.linalg.norm(b)), floor)
     d = np.linalg.norm(np.asarray(a) - np.asarray(b))
     return d / n if n >= 1e-8 else d
+
+
+# An array far below the env's state gradient |dL/dx0| (e.g. dL/du of a servo
+# at its limit on all but a few steps) is compared against 1e-5 of that scale:
+# FP32 forms every array from adjoints of that size.
+GRAD_SCALE_FLOOR = 1e-5
 
 
 def _env_grads(g, w, e, local_b, local_j, local_e):
@@ -158,14 +165,15 @@ def grad_check(w, envs, got, ref, noisy):
         lb = np.arange(ws.env_body_off[i], ws.env_body_off[i + 1])
         lj = np.arange(ws.env_joint_off[i], ws.env_joint_off[i + 1])
         r = _env_grads(ref, ws, i, lb, lj, i)
-        if any(max((_rel(_env_grads(g, ws, i, lb, lj, i)[k], r[k]) for k in r if r[k].size), default=0.0)
+        fl = GRAD_SCALE_FLOOR * float(np.linalg.norm(r["g_x0"]))
+        if any(max((_rel(_env_grads(g, ws, i, lb, lj, i)[k], r[k], fl) for k in r if r[k].size), default=0.0)
                >= 0.5 * GRAD_TOL for g in noisy):
             continue
         gb = np.arange(w.env_body_off[e], w.env_body_off[e + 1])
         gj = np.arange(w.env_joint_off[e], w.env_joint_off[e + 1])
         a = _env_grads(got, w, e, gb, gj, e)
         stable.append(e)
-        errs.append(max((_rel(a[k], r[k]) for k in r if r[k].size), default=0.0))
+        errs.append(max((_rel(a[k], r[k], fl) for k in r if r[k].size), default=0.0))
     worst = max(errs) if errs else None
     errs = np.array(errs)
     beyond = [(int(stable[i]), int(nb[stable[i]]), float(errs[i])) for i in np.argsort(-errs) if errs[i] > GRAD_TOL]
