@@ -29,9 +29,10 @@
  *    omega(15..17).  B = total bodies over all envs, bodies of an env are
  *    contiguous (CSR offsets env_body_off).
  *  - Carried state besides x ("lambda"), per env a contiguous block of
- *    5*J_e + 4*G_e + 4*P_e warm-start impulses (then, with a recurrent
- *    controller, its mlp_rec units h^t) at the offset sim_info.lam_off[e]:
- *    5 hinge rows per joint (point x, y, z, angular t1, t2), then per ground
+ *    5*J_e + 4*G_e + 4*P_e warm-start impulses (6*J_e + ... with servo
+ *    motors; then, with a recurrent controller, its mlp_rec units h^t) at the
+ *    offset sim_info.lam_off[e]: 5 hinge rows per joint (point x, y, z,
+ *    angular t1, t2; then the servo's motor row), then per ground
  *    sphere (sphere order) [lambda_n, Lambda_t.x, .y, .z], then per sphere
  *    pair candidate [lambda_n, Lambda_t(3)] in (body a, body b) lexicographic
  *    order of the env's local body indices; Lambda_t is the tangent impulse
@@ -56,7 +57,7 @@
 extern "C" {
 #endif
 
-#define SIM_ABI_VERSION 6
+#define SIM_ABI_VERSION 7
 
 typedef struct sim_model* sim_handle;
 
@@ -205,6 +206,23 @@ typedef struct {
      (m/s, >= 0) keeps resting contacts from bouncing. */
   const float* restitution;
   float rest_threshold;
+  /* Servo motors (section 2.1: gain, maximal torque, maximal velocity; the
+     arm of section 3.2 has 30 1/s, 30 N m, 45 deg/s).  servo = 1: every hinge
+     is a velocity motor and the control u^t_j (tape or controller output) is
+     its target angle theta*_j in rad, not a torque.  The motor is a sixth
+     row of the joint, angular about the parent's world hinge axis n_a
+     (J w = n_a . (w_b - w_a)), visited after the five hinge rows; it aims at
+     the rate clip(servo_gain_j (theta*_j - theta_j), -servo_vmax_j,
+     servo_vmax_j), theta_j the hinge angle (the controller's angle sensor),
+     and its impulse is clamped to [-servo_torque_j dt, servo_torque_j dt].
+     The joint's direct torque is then its viscous damping alone.  The
+     carried state has 6 impulses per joint (the motor's last).  rollout_grad
+     differentiates through the clip and the clamp (zero where active).
+     Arrays [J] (host), finite and >= 0; servo = 0: plain torques. */
+  int32_t servo;
+  const float* servo_gain;
+  const float* servo_torque;
+  const float* servo_vmax;
 } sim_model_desc;
 
 /* Sizes derived by sim_init. */
@@ -245,7 +263,8 @@ int32_t sim_describe_order(const sim_model_desc* desc, int32_t env, int32_t* cod
                            int32_t cap);
 
 /* One step for all envs: x_out = f_ph(x_in, u) (device pointers, x[18][B],
- * u[J] torques or, for SIM_CTRL_MLP, the controller weights [n_params];
+ * u[J] torques (servo targets with servo motors) or, for SIM_CTRL_MLP, the
+ * controller weights [n_params];
  * lambda[lam_size]).  t is the step index (it selects the clock input of a
  * controller; 0 <= t < T_max then).  lam_in may equal lam_out; x_in must not
  * alias x_out.  env_flags[E] (device, may be NULL) is overwritten. */

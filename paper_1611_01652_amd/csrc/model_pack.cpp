@@ -141,10 +141,11 @@ sim_status build_env(const sim_model_desc& d, int e, bool keep_v, HostEnv& H) {
   H.ncol = (int)colstart.size();
   colstart.push_back((int)cand.size());
   H.ncand = (int)cand.size();
-  H.lam = 5 * H.nj + 4 * H.G + 4 * H.P;
+  const int jr = d.servo ? 6 : 5;   // rows per joint (a servo adds its motor row)
+  H.lam = jr * H.nj + 4 * H.G + 4 * H.P;
   // contact capacity per env: every candidate when few, else 2 per body + 4
   H.ccap = std::min(H.G + H.P, 2 * H.nb + 4);
-  H.nslot = 5 * H.nj + 4 * H.ccap;
+  H.nslot = jr * H.nj + 4 * H.ccap;
   H.topo.clear();
   H.topo.insert(H.topo.end(), jpar.begin(), jpar.end());
   H.topo.insert(H.topo.end(), jchi.begin(), jchi.end());
@@ -180,6 +181,12 @@ sim_status build_env(const sim_model_desc& d, int e, bool keep_v, HostEnv& H) {
       c[JUC + k] = d.perp_c[3 * gj + k];
     }
     c[JD] = d.damping[gj];
+    if (d.servo) {
+      const float g = d.servo_gain[gj], tq = d.servo_torque[gj], vm = d.servo_vmax[gj];
+      if (!(g >= 0.f && tq >= 0.f && vm >= 0.f) || !std::isfinite(g) || !std::isfinite(tq) || !std::isfinite(vm))
+        return fail(SIM_E_ARG, "joint " + std::to_string(gj) + ": servo gain, torque and vmax must be finite and >= 0");
+      c[JG] = g; c[JT] = tq; c[JV] = vm;
+    }
   }
   for (int g = 0; g < H.G; ++g) {
     float* c = H.cst.data() + 8 * H.nb + JS * H.nj + 4 * g;

@@ -339,6 +339,9 @@ sim_status sim_init(const sim_model_desc* d, sim_handle* out) {
   }
   for (int j = 0; j < J; ++j)
     if (!(d->damping[j] >= 0.f) || !std::isfinite(d->damping[j])) return fail(SIM_E_ARG, "damping < 0");
+  if (d->servo != 0 && d->servo != 1) return fail(SIM_E_ARG, "servo must be 0 or 1");
+  if (d->servo && J > 0 && (!d->servo_gain || !d->servo_torque || !d->servo_vmax))
+    return fail(SIM_E_ARG, "servo motors need servo_gain, servo_torque and servo_vmax");
   if (d->restitution)
     for (int e = 0; e < E; ++e)
       if (!(d->restitution[e] >= 0.f && d->restitution[e] <= 1.f))
@@ -372,6 +375,7 @@ sim_status sim_init(const sim_model_desc* d, sim_handle* out) {
   M.ws_kind = d->ws_kind; M.fb_iters = d->fb_iters; M.fb_tol = d->fb_tol;
   M.decay = d->use_grad_decay ? d->grad_decay : 1.f;
   M.has_rest = desc_has_rest(d) ? 1 : 0;
+  M.servo = d->servo;
   M.rest_th = d->rest_threshold;
   M.ctrl = d->ctrl_kind == 1 ? 1 : 0;   // (before the LDS sizes: the controller adds a shared region)
 

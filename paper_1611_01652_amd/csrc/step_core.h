@@ -123,6 +123,7 @@ struct DevModel {
   int dump;           // reverse sweep buffer: DUMP_REPLAY, DUMP_SEGMENT or DUMP_TRAJECTORY
   float decay;        // gradient decay per reversed step (1: the exact derivative)
   int has_rest;       // some env has restitution > 0 (the predicted velocities are kept)
+  int servo;          // every hinge is a servo motor: u holds target angles, 6 rows per joint
   float rest_th;      // approach speed below which contacts do not bounce
 };
 // Reverse sweep buffer modes: step-start states of one segment (each step is
@@ -151,14 +152,18 @@ enum { BP = 0, BR = 3, BV = 12, BW = 15, BI = 18, BIM = 24, BII = 25, BTQ = 28, 
 // that largely cancel).
 enum { AP = 0, AR = 3, AV = 12, AW = 15, AIW = 18, AIM = 27, AII = 28, ATQ = 31, AW0 = 34,
        ATM = 37, ATI = 38, ACM = 41, ACI = 42, BSA = 48 };
-// joint constants
-enum { JAP = 0, JAC = 3, JXP = 6, JXC = 9, JUP = 12, JUC = 15, JD = 18, JU = 19, JS = 20 };
+// joint constants: anchors, axes and perpendiculars (parent, child frames),
+// damping, the step's control, and the servo's gain, torque and rate limits
+enum { JAP = 0, JAC = 3, JXP = 6, JXC = 9, JUP = 12, JUC = 15, JD = 18, JU = 19, JG = 20, JT = 21, JV = 22, JS = 24 };
 // row slot; a contact uses 4 slots: normal, tangent 1, tangent 2, extras.
 // Each body's part of the row is two aligned float4: (Ja, m) (Wa, bias) for
 // body a and (Jb, m) (Wb, bias) for body b, so a lane that handles one body
 // reads its part with two 16-byte loads; m and bias are kept in both
 // (RMA, RBA: the copies of body a's part).  Then (Jl, lambda), lambda0.
 enum { RJA = 0, RMA = 3, RWA = 4, RBA = 7, RJB = 8, RM = 11, RWB = 12, RBI = 15, RJL = 16, RL = 19, RL0 = 20, RS = 24 };
+// a servo's motor row (a hinge's sixth) also holds its impulse bound
+// torque * dt and 1 where the target rate was clipped to the rate limit
+enum { RHI = 21, RCLIP = 22 };
 // contact extras slot: tangents, friction mass, gap, store offset, code,
 // (tolerance mode) the warm-start features XF[7] and network outputs XY[3],
 // and 1 where restitution set the normal bias
@@ -229,6 +234,7 @@ SHD Lay make_lay(int nb, int nj, int G, int P, int ncol, int ncand, int nslot, i
 struct Env {
   int b0, nb, j0, nj, lam_off, lam_size, G, P, ncol, T, lb, ccap, ncand, e, nslot, seg_off, tape_off;
   int lam_imp;        // impulses in the carried-state block (the rest: the controller's h)
+  int jr;             // rows (and carried impulses) per joint: 5, 6 with servo motors
   const int* gtopo;   // global topology of the env
   const float* gcst;  // global constants of the env
   float* L;           // LDS base of the env
@@ -271,9 +277,9 @@ struct Env {
   // warm-start store offset of a candidate
   SHD int store_of(int code) const {
     const int k = cand_kind(code), i = cand_idx(code);
-    if (k == K_JOINT) return 5 * i;
-    if (k == K_GROUND) return 5 * nj + 4 * i;
-    return 5 * nj + 4 * G + 4 * i;
+    if (k == K_JOINT) return jr * i;
+    if (k == K_GROUND) return jr * nj + 4 * i;
+    return jr * nj + 4 * G + 4 * i;
   }
 };
 
@@ -307,6 +313,7 @@ SHD Env make_env(const DevModel& M, int ie, float* lds, int n_iters, bool adj) {
   E.b0 = h[H_B0]; E.nb = h[H_NB]; E.j0 = h[H_J0]; E.nj = h[H_NJ];
   E.lam_off = h[H_LAMOFF]; E.lam_size = h[H_LAMSZ]; E.G = h[H_G]; E.P = h[H_P]; E.ncol = h[H_NCOL];
   E.lam_imp = E.lam_size - (M.ctrl ? M.mlp_rec : 0);
+  E.jr = M.servo ? 6 : 5;
   E.T = h[H_T]; E.lb = h[H_LB]; E.ccap = h[H_CCAP]; E.ncand = h[H_NCAND]; E.e = h[H_ENV];
   E.nslot = h[H_NSLOT]; E.seg_off = h[H_SEG]; E.tape_off = h[H_TAPE];
   E.gtopo = M.topo + h[H_TOPO];
@@ -537,7 +544,8 @@ SHD void f_torques(const Team& tm, const Env& E, bool act) {
       float* Bb = E.body(b);
       f3 wrel = ld3(Bb + BW);
       if (a >= 0) wrel = wrel - ld3(E.body(a) + BW);
-      const float tau = C[JU] - C[JD] * dot(wrel, n);
+      // (a servo's control is its target angle, not a torque)
+      const float tau = (E.jr == 6 ? 0.f : C[JU]) - C[JD] * dot(wrel, n);
       add3(Bb + BTQ, tau * n);
       if (a >= 0) add3(E.body(a) + BTQ, -(tau * n));
     }
@@ -557,7 +565,7 @@ SHD void f_predict(const Team& tm, const DevModel& M, const Env& E, bool act) {
   }
 }
 
-// Build the rows of one joint into slots s..s+4.  Each row is formed in
+// Build the rows of one joint into slots s..s+4 (s+5: a servo's motor row).  Each row is formed in
 // registers (W = M^-1 J^T, K = J W, m = 1 / (K + gamma), as row_finish forms
 // them, in the same order) and written with 16-byte stores.
 static_assert(RMA == RJA + 3 && RBA == RWA + 3 && RM == RJB + 3 && RBI == RWB + 3 && RL == RJL + 3 &&
@@ -585,11 +593,24 @@ SHD void build_joint(const DevModel& M, const Env& E, int j, int s) {
   if (ha) { na = mv(Ba + BR, na); ua = mv(Ba + BR, ua); t2 = mv(Ba + BR, t2); }
   const f3 nbw = mv(Bb + BR, ld3(C + JXC));
   const f3 ax = cross(na, nbw);
-  const float* w0 = E.ws() + 5 * j;
-  for (int q = 0; q < 5; ++q) {
+  const float* w0 = E.ws() + E.jr * j;
+  for (int q = 0; q < E.jr; ++q) {
     f3 jl, ja, jb;
     float bias;
-    if (q < 3) {
+    float clip = 0.f;
+    if (q == 5) {
+      // servo: relative rate about the parent's axis driven toward
+      // gain (theta* - theta), clipped to the rate limit
+      const f3 ub = mv(Bb + BR, ld3(C + JUC));
+      const float th = atan2f(dot(cross(ua, ub), na), dot(ua, ub));
+      float rate = C[JG] * (C[JU] - th);
+      if (rate > C[JV]) { rate = C[JV]; clip = 1.f; }
+      else if (rate < -C[JV]) { rate = -C[JV]; clip = 1.f; }
+      jl = mk3(0.f, 0.f, 0.f);
+      ja = -na;
+      jb = na;
+      bias = -rate;
+    } else if (q < 3) {
       const f3 e = mk3(q == 0 ? 1.f : 0.f, q == 1 ? 1.f : 0.f, q == 2 ? 1.f : 0.f);
       jl = e;
       ja = cross(e, ra);
@@ -625,6 +646,10 @@ SHD void build_joint(const DevModel& M, const Env& E, int j, int s) {
     st4(r + RWB, f4{wb.x, wb.y, wb.z, bias});
     st4(r + RJL, f4{jl.x, jl.y, jl.z, l0});
     r[RL0] = l0;
+    if (q == 5) {
+      r[RHI] = C[JT] * M.dt;
+      r[RCLIP] = clip;
+    }
   }
 }
 
@@ -731,7 +756,7 @@ SHD void f_rows(const Team& tm, const DevModel& M, const Env& E, bool act) {
   // Joint rows depend only on the step's body state, so all joints are built
   // at once, lanes over joints; the colour loop below lists them.
   const int nj = act ? E.nj : 0;
-  for (int j = tm.tl; j < nj; j += tm.ts) build_joint(M, E, j, 5 * j);
+  for (int j = tm.tl; j < nj; j += tm.ts) build_joint(M, E, j, E.jr * j);
   int ncon = 0;  // contacts placed so far (team-uniform)
   for (int c = 0; tm.any(c < E.ncol && act); ++c) {
     int lo = 0, hi = 0;
@@ -762,9 +787,9 @@ SHD void f_rows(const Team& tm, const DevModel& M, const Env& E, bool act) {
         E.act_code()[li] = code;
         int s = -1;
         if (jcol) {
-          s = 5 * cand_idx(code);
+          s = E.jr * cand_idx(code);
         } else if (ncon + pos < E.ccap) {
-          s = 5 * E.nj + 4 * (ncon + pos);
+          s = E.jr * E.nj + 4 * (ncon + pos);
           build_contact(M, E, code, s, g);
         } else {
           // beyond the env's contact capacity: dropped, env flagged
@@ -1034,7 +1059,25 @@ SHD void h_row_fwd(const Team& tm, const DevModel& M, const HR* r, HS* x, const 
   lam = lt;
 }
 
-// One forward visit of a hinge (5 unbounded rows) with all data in
+// A servo's motor row: as h_row_fwd, the impulse clamped to [-hi, hi]
+// (the recorded value is the impulse before the clamp).
+template <int NS, class Team>
+SHD void h_row_box(const Team& tm, const DevModel& M, const HR* r, HS* x, const HSides<NS>& sd, float m, float bias,
+                   float hi, float& lam, float* h, float* rmax) {
+  float p[NS];
+  for (int i = 0; i < NS; ++i) p[i] = h_jpart<3>(r[i], x[i], sd.sg[i]);
+  const float sv_ = h_sum<NS>(tm, p) + bias + M.gamma * lam;
+  const float lt = lam - m * sv_;
+  const float ln = lt <= -hi ? -hi : (lt >= hi ? hi : lt);
+  if (h) *h = lt;
+  if (rmax) *rmax = fmaxf(*rmax, fabsf(ln - lam) / m);
+  const float d = ln - lam;
+  for (int i = 0; i < NS; ++i) h_apply<3>(r[i], x[i], sd.sim[i], d);
+  lam = ln;
+}
+
+// One forward visit of a hinge (5 unbounded rows, then a servo's clamped
+// motor row) with all data in
 // registers; a: body index or the world slot.  rmax (tolerance mode, NS = 2):
 // running maximum of |delta lambda| / m over the rows.
 template <int NS, class Team>
@@ -1060,6 +1103,14 @@ SHD void hinge_fwd(const Team& tm, const DevModel& M, const Env& E, int s, int a
   h_row_fwd<3, NS>(tm, M, r[3], x, sd, m[3], bias[3], lam[3], Hw ? Hw + 3 : nullptr, rmax);
   h_row_fwd<3, NS>(tm, M, r[4], x, sd, m[4], bias[4], lam[4], Hw ? Hw + 4 : nullptr, rmax);
   for (int q = 0; q < 5; ++q) R0[q * RS + RL] = lam[q];
+  if (E.jr == 6) {
+    const float* R5 = R0 + 5 * RS;
+    HR r5[NS];
+    for (int i = 0; i < NS; ++i) hr_load(r5[i], R5 + sd.so[i]);
+    float l5 = R5[RL];
+    h_row_box<NS>(tm, M, r5, x, sd, r5[0].m, r5[0].bias, R5[RHI], l5, Hw ? Hw + 5 : nullptr, rmax);
+    R0[5 * RS + RL] = l5;
+  }
   for (int i = 0; i < NS; ++i) hs_store(x[i], E.body(sd.bd[i]) + BV);
 }
 
@@ -1081,6 +1132,11 @@ SHD void hinge_warm(const Team& tm, const Env& E, int s, int a, int b) {
     h_apply<2>(r[2], x, sd.sim[i], R0[2 * RS + RL0]);
     h_apply<3>(r[3], x, sd.sim[i], R0[3 * RS + RL0]);
     h_apply<3>(r[4], x, sd.sim[i], R0[4 * RS + RL0]);
+    if (E.jr == 6) {
+      HR r5;
+      hr_load(r5, R0 + 5 * RS + sd.so[i]);
+      h_apply<3>(r5, x, sd.sim[i], R0[5 * RS + RL0]);
+    }
     hs_store(x, E.body(sd.bd[i]) + BV);
   }
 }
@@ -1226,7 +1282,7 @@ SHD void f_store(const Team& tm, const Env& E, bool act) {
       const int code = v.w;
       float* w = E.ws() + E.store_of(code);
       if (cand_kind(code) == K_JOINT) {
-        for (int q = 0; q < 5; ++q) w[q] = E.row(s + q)[RL];
+        for (int q = 0; q < E.jr; ++q) w[q] = E.row(s + q)[RL];
       } else {
         const float* x = E.row(s + 3);
         const float l1 = E.row(s + 1)[RL], l2 = E.row(s + 2)[RL];
@@ -1481,7 +1537,7 @@ SHD void f_restart(const Team& tm, const DevModel& M, const Env& E, bool act) {
       const int s = E.act_slot()[lo + k];
       if (s < 0) continue;
       if (cand_kind(E.act_code()[lo + k]) == K_JOINT) {
-        for (int q = 0; q < 5; ++q) E.row(s + q)[RL] = E.row(s + q)[RL0];
+        for (int q = 0; q < E.jr; ++q) E.row(s + q)[RL] = E.row(s + q)[RL0];
       } else {
         const float* x = E.row(s + 3);
         const float* w = E.ws() + *reinterpret_cast<const int*>(x + XSTORE);
@@ -1743,7 +1799,7 @@ SHD void a_store(const Team& tm, const Env& E, bool act) {
       const int code = v.w;
       float* wA = E.wsA() + E.store_of(code);
       if (cand_kind(code) == K_JOINT) {
-        for (int q = 0; q < 5; ++q) E.rowA(s + q)[QL] = wA[q];
+        for (int q = 0; q < E.jr; ++q) E.rowA(s + q)[QL] = wA[q];
       } else {
         const float* x = E.row(s + 3);
         float* xa = E.rowA(s + 3);
@@ -1996,14 +2052,44 @@ SHD void h_rev_load(const HSides<NS>& sd, const float* R0, const float* Q0, int 
   c.lp = Hp[q];
 }
 
+// Reverse of a servo's motor row update (see h_row_box): c.lp is the impulse
+// before the update, c.lt the recorded one before the clamp; the adjoint
+// passes the clamp only strictly inside the bounds.
+template <int NS, class Team>
+SHD void h_row_rev_box(const Team& tm, const HR* r, HQ* q, HS* x, HS* A, const HSides<NS>& sd, HRow& c, float gamma,
+                       float hi) {
+  const float ln = c.lt <= -hi ? -hi : (c.lt >= hi ? hi : c.lt);
+  const float d = ln - c.lp;
+  for (int i = 0; i < NS; ++i) h_apply<3>(r[i], x[i], sd.sim[i], -d);   // v before the update
+  for (int i = 0; i < NS; ++i)
+    for (int k = 0; k < 3; ++k) q[i].W[k] += A[i].w[k] * d;
+  float p[NS];
+  for (int i = 0; i < NS; ++i) p[i] = h_wpart<3>(r[i], A[i], sd.sim[i]);
+  const float wv = h_sum<NS>(tm, p);
+  const float g = c.ql + wv;
+  const float ltb = (c.lt > -hi && c.lt < hi) ? g : 0.f;
+  const float sb = -c.m * ltb;
+  for (int i = 0; i < NS; ++i) p[i] = h_jpart<3>(r[i], x[i], sd.sg[i]);
+  const float sval = h_sum<NS>(tm, p) + c.bias + gamma * c.lp;
+  c.qm += -sval * ltb;
+  c.qb += sb;
+  for (int i = 0; i < NS; ++i)
+    for (int k = 0; k < 3; ++k) {
+      A[i].w[k] += r[i].j[k] * sb;
+      q[i].j[k] += sb * x[i].w[k];
+    }
+  c.ql = -wv + ltb + gamma * sb;
+}
+
 // Reverse of one hinge visit (rows 4..0).  Row data and row adjoint
 // accumulators are streamed: row q-1 is loaded while row q is reversed.
+// A servo's motor row (clamped to [-hi, hi]) is reversed first, on its own.
 // a: body index or the world slot (whose adjoint slot is a sink).  H: this
 // sweep's records, Hp: the previous sweep's (the start impulses before the
 // first sweep).
 template <int NS, class Team>
 SHD void hinge_rev(const Team& tm, const DevModel& M, const Env& E, int s, int a, int b, const float* H,
-                   const float* Hp) {
+                   const float* Hp, bool first) {
   HSides<NS> sd;
   sd.init(tm, E, a, b);
   HS x[NS], A[NS];
@@ -2017,6 +2103,24 @@ SHD void hinge_rev(const Team& tm, const DevModel& M, const Env& E, int s, int a
   float* Q0 = E.rowA(s);
   const float* Hs = H + s;
   const float* Hps = Hp + s;
+  if (E.jr == 6) {
+    HR r5[NS];
+    HQ q5[NS];
+    HRow c5;
+    h_rev_load<NS>(sd, R0, Q0, 5, Hs, Hps, r5, q5, c5);
+    const float hi = R0[5 * RS + RHI];
+    // the impulse before this sweep's update: the previous sweep's clamped
+    // result, or the start impulse
+    if (!first) c5.lp = c5.lp <= -hi ? -hi : (c5.lp >= hi ? hi : c5.lp);
+    h_row_rev_box<NS>(tm, r5, q5, x, A, sd, c5, M.gamma, hi);
+    float* Q = Q0 + 5 * RSA;
+    for (int i = 0; i < NS; ++i) {
+      q5[i].m = c5.qm;
+      q5[i].b = c5.qb;
+      hq_store(q5[i], Q + sd.so[i]);
+    }
+    Q[QL] = c5.ql;
+  }
   // Rows are loaded AH rows ahead of their reversal: a lane of a pair holds
   // all five rows from the start of the visit (one LDS round trip), a
   // one-lane visit (two sides per lane) streams them one row ahead.
@@ -2136,8 +2240,8 @@ SHD void a_pgs(const Team& tm, const DevModel& M, const Env& E, bool act) {
       const i4 v = sw.entry(tm, E, k);
       if (v.x < 0) continue;
       if (cand_kind(v.w) != K_JOINT) rev_contact(M, E, v.x, v.y, v.z, mu, H, sw.it > 0 ? Hp : nullptr, gmu);
-      else if (tm.ts >= 2) hinge_rev<1>(tm, M, E, v.x, v.y, v.z, H, Hp);
-      else hinge_rev<2>(tm, M, E, v.x, v.y, v.z, H, Hp);
+      else if (tm.ts >= 2) hinge_rev<1>(tm, M, E, v.x, v.y, v.z, H, Hp, sw.it == 0);
+      else hinge_rev<2>(tm, M, E, v.x, v.y, v.z, H, Hp, sw.it == 0);
     }
     tm.sync();
     sw.advance(vn, p2);
@@ -2180,15 +2284,16 @@ SHD void hinge_warm_rev(const Team& tm, const DevModel& M, const Env& E, int s, 
     hs_load(A[i], E.bodyA(sd.bd[i]) + AV);
     imx[i] = 0.f;
   }
-  float l0b[5];
+  float l0b[6];
   l0b[0] = hinge_warm_row<0, NS>(tm, sd, R0, Q0, A, imx);
   l0b[1] = hinge_warm_row<1, NS>(tm, sd, R0 + RS, Q0 + RSA, A, imx);
   l0b[2] = hinge_warm_row<2, NS>(tm, sd, R0 + 2 * RS, Q0 + 2 * RSA, A, imx);
   l0b[3] = hinge_warm_row<3, NS>(tm, sd, R0 + 3 * RS, Q0 + 3 * RSA, A, imx);
   l0b[4] = hinge_warm_row<3, NS>(tm, sd, R0 + 4 * RS, Q0 + 4 * RSA, A, imx);
+  if (E.jr == 6) l0b[5] = hinge_warm_row<3, NS>(tm, sd, R0 + 5 * RS, Q0 + 5 * RSA, A, imx);
   // (both lanes of a pair add the same value to the same entries)
   float* wA = E.wsA() + E.store_of(code);
-  for (int q = 0; q < 5; ++q) wA[q] += M.warm * l0b[q];
+  for (int q = 0; q < E.jr; ++q) wA[q] += M.warm * l0b[q];
   for (int i = 0; i < NS; ++i) E.bodyA(sd.bd[i])[AIM] += imx[i];
 }
 
@@ -2334,15 +2439,15 @@ SHD void a_joint(const Team& tm, const DevModel& M, const Env& E, int j, int s) 
     const float* B = sd[i] ? Bb : (ha ? Ba : E.body(E.nb));
     for (int k = 0; k < 6; ++k) I[i][k] = B[BI + k];
   }
-  f3 qj[NS][5];
-  float qbias[5];
+  f3 qj[NS][6];
+  float qbias[6];
   float O[NS][9];
   float imx[NS];
   for (int i = 0; i < NS; ++i) {
     imx[i] = 0.f;
     for (int k = 0; k < 9; ++k) O[i][k] = 0.f;
   }
-  for (int q = 0; q < 5; ++q) {
+  for (int q = 0; q < E.jr; ++q) {
     const float* r = E.row(s + q);
     const float* qa = E.rowA(s + q);
     const float qm = qa[QM];
@@ -2385,8 +2490,10 @@ SHD void a_joint(const Team& tm, const DevModel& M, const Env& E, int j, int s) 
   const f3 nbw = mv(Bb + BR, nbl);
   const f3 ax = cross(na, nbw);
   // side b's and side a's Jacobian adjoints of the angular rows
-  f3 qjb[2], qja[2];
-  for (int q = 0; q < 2; ++q) {
+  // (index 2: a servo's motor row, J = (-na, na))
+  f3 qjb[3], qja[3];
+  const int nq = E.jr == 6 ? 3 : 2;
+  for (int q = 0; q < nq; ++q) {
     if (NS == 2) {
       qjb[q] = qj[0][3 + q];
       qja[q] = qj[NS - 1][3 + q];
@@ -2404,8 +2511,9 @@ SHD void a_joint(const Team& tm, const DevModel& M, const Env& E, int j, int s) 
     tb[q] = qjb[q] - qja[q] + cb * ax;
     axb = axb + cb * tk;
   }
-  // ax = na x nbw
-  const f3 nab = cross(nbw, axb);
+  // ax = na x nbw ; a motor row's Jacobian is na itself
+  f3 nab = cross(nbw, axb);
+  if (nq == 3) nab = nab + (qjb[2] - qja[2]);
   const f3 nbb = cross(axb, na);
   // The anchors (the link lengths): r_b = R_b a_c and r_a = R_a a_p give
   // a_c-bar = R_b^T r_b-bar and a_p-bar = R_a^T r_a-bar; a world-attached
@@ -2612,13 +2720,34 @@ SHD void a_predict_torques(const Team& tm, const DevModel& M, const Env& E, bool
       f3 tqd = ld3(Ab + ATQ);
       if (a >= 0) { wrel = wrel - ld3(E.bodyA(a) + AW0); tqd = tqd - ld3(E.bodyA(a) + ATQ); }
       const float dmp = C[JD];
-      const float tau = C[JU] - dmp * dot(wrel, n);
+      const bool servo = E.jr == 6;
+      const float tau = (servo ? 0.f : C[JU]) - dmp * dot(wrel, n);
       const float taub = dot(n, tqd);
       f3 nb_ = tau * tqd - (taub * dmp) * wrel;
-      if (M.ctrl) E.mlpA()[j] = taub;
+      // the control's adjoint: the torque's, or a servo's through the target
+      // rate of its motor row, bias = -gain (u - theta) where not clipped
+      float cb = taub;
+      if (servo) {
+        const int s5 = E.jr * j + 5;
+        const float bb = E.row(s5)[RCLIP] != 0.f ? 0.f : E.rowA(s5)[QB];
+        cb = -C[JG] * bb;
+        // theta = atan2(y, x), y = (ua x ub).na, x = ua.ub, at x^t
+        const float thb = C[JG] * bb;
+        const Sensor S = joint_sensor(E, j, nullptr, nullptr);
+        const float r2 = S.x * S.x + S.y * S.y;
+        const float yb = r2 > 0.f ? thb * S.x / r2 : 0.f;
+        const float xb = r2 > 0.f ? -thb * S.y / r2 : 0.f;
+        add_outer(Ab + AR, yb * cross(S.na, S.ua) + xb * S.ua, ld3(C + JUC));
+        if (a >= 0) {
+          float* Aa = E.bodyA(a);
+          add_outer(Aa + AR, yb * cross(S.ub, S.na) + xb * S.ub, ld3(C + JUP));
+          add_outer(Aa + AR, yb * cross(S.ua, S.ub), ld3(C + JXP));
+        }
+      }
+      if (M.ctrl) E.mlpA()[j] = cb;
       else if (g_u_row) {
-        g_u_row[E.j0 + j] = taub;
-        a_predict_torques_flag(bad, taub);
+        g_u_row[E.j0 + j] = cb;
+        a_predict_torques_flag(bad, cb);
       }
       kahan_add(E.jA() + JA_DAMP * E.nj + j, E.jA() + JA_DAMPC * E.nj + j, -taub * dot(wrel, n));
       add3(Ab + AW, -(taub * dmp) * n);

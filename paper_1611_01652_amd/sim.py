@@ -20,7 +20,7 @@ FLAG_NONFINITE = 1
 FLAG_CONTACT_OVERFLOW = 2
 
 # layout of the descriptor and info structs below (SIM_ABI_VERSION)
-ABI_VERSION = 6
+ABI_VERSION = 7
 
 # reverse sweep memory modes (sim_model_desc.grad_store)
 GRAD_STORE = {"auto": 0, "replay": 1, "segment": 2, "trajectory": 3}
@@ -49,6 +49,7 @@ class SimDesc(C.Structure):
         ("grad_store", C.c_int32), ("grad_mem_limit", C.c_int64),
         ("use_grad_decay", C.c_int32), ("grad_decay", C.c_float), ("mlp_rec", C.c_int32),
         ("restitution", _F32P), ("rest_threshold", C.c_float),
+        ("servo", C.c_int32), ("servo_gain", _F32P), ("servo_torque", _F32P), ("servo_vmax", _F32P),
     ]
 
 
@@ -121,6 +122,9 @@ def make_desc(w):
     if getattr(w, "restitution", None) is not None:
         d.restitution = f(w.restitution)
     d.rest_threshold = float(getattr(w, "rest_threshold", 0.5))
+    if getattr(w, "servo_gain", None) is not None:
+        d.servo = 1
+        d.servo_gain, d.servo_torque, d.servo_vmax = f(w.servo_gain), f(w.servo_torque), f(w.servo_vmax)
     solve = extra.get("solve")
     if solve is not None:
         d.solve_mode = int(solve.get("mode", 1))

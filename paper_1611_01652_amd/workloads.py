@@ -538,6 +538,25 @@ def servo_targets(T: int, J: int, seed_salt: int = 0, amp: float = 0.6, hold: in
     return f32(np.repeat(rng.uniform(-amp, amp, size=(n, J)), hold, axis=0)[:T])
 
 
+def servo_arms(n_envs: int = 96, T: int = 300, gain: float = 10.0, torque: float = 50.0, vmax: float = 3.0,
+               seed_salt: int = 3) -> Workload:
+    """3-link arms with gravity in their plane, every hinge a servo following
+    seeded targets held for 30 steps."""
+    base = planar_arms(n_envs=n_envs, T=T, seed_salt=seed_salt)
+    base.gravity = (0.0, -9.81, 0.0)
+    return with_servos(base, gain=gain, torque=torque, vmax=vmax,
+                       targets=servo_targets(T, base.n_joints, seed_salt=seed_salt, amp=0.8, hold=30))
+
+
+def servo_chains(n_envs: int = 40, T: int = 100, gain: float = 20.0, torque: float = 5.0, vmax: float = 3.0,
+                 seed_salt: int = 2) -> Workload:
+    """The uneven chains with every hinge a servo following seeded targets
+    held for 25 steps."""
+    base = uneven_chains(n_envs=n_envs, T=T, seed_salt=seed_salt)
+    return with_servos(base, gain=gain, torque=torque, vmax=vmax,
+                       targets=servo_targets(T, base.n_joints, seed_salt=seed_salt, amp=0.5, hold=25))
+
+
 def mlp_param_count(sizes, skip_input_to_output=False):
     """Parameters of a dense net with biases (optionally the output layer also
     reads the input layer, as the gait controller of section 3.3 does)."""

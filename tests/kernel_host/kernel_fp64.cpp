@@ -137,6 +137,7 @@ bool make(const sim_model_desc* d, Host& h) {
   M.dump = h.P.dump;
   M.decay = d->use_grad_decay ? d->grad_decay : 1.0;
   M.has_rest = desc_has_rest(d) ? 1 : 0;
+  M.servo = d->servo;
   M.rest_th = d->rest_threshold;
   M.solve_mode = d->solve_mode; M.tol = d->tol; M.max_iters = d->max_iters;
   M.ws_kind = d->ws_kind; M.fb_iters = d->fb_iters; M.fb_tol = d->fb_tol;

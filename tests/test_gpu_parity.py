@@ -186,11 +186,13 @@ def test_contact_overflow_is_flagged():
 
 
 @pytest.mark.parametrize("make", [lambda: W.uneven_chains(n_envs=20, T=60, seed_salt=7),
-                                  lambda: W.planar_arms(n_envs=40, T=120)])
+                                  lambda: W.planar_arms(n_envs=40, T=120),
+                                  lambda: W.servo_chains(20, 60, seed_salt=7)])
 def test_bitwise_determinism_and_team_invariance(make):
     # chains (free floating) and arms (world-attached base joints: the paired
-    # hinge forms with the world slot as side a) at their default team widths
-    # and at 64 lanes per env give the same bits
+    # hinge forms with the world slot as side a), and chains on servos (the
+    # motor row's pair exchange), at their default team widths and at 64
+    # lanes per env give the same bits
     w = make()
     _say("case determinism", w.name)
     a = gpu_run(w)

@@ -82,6 +82,7 @@ def _desc64(w):
     alpha = f(getattr(w, "grad_decay", 1.0))
     d.use_grad_decay, d.grad_decay = int(alpha != 1.0), alpha
     d.rest_threshold = f(getattr(w, "rest_threshold", 0.5))
+    d.servo = int(getattr(w, "servo_gain", None) is not None)
     mlp = w.extra.get("mlp") if getattr(w, "extra", None) else None
     if mlp is not None:
         d.ctrl_kind = 1
@@ -157,9 +158,10 @@ def test_reverse_sweep_memory_modes_and_their_sizes():
     K, nb, lam = w.ckpt_every, 3, 15
     up = lambda n: (n + 63) // 64 * 64   # noqa: E731
     assert sz["replay"]["seg_floats"] == 3 * up(K * (18 * nb + lam))
-    ws = sz["segment"]["seg_floats"] // 3 // K
-    assert sz["segment"]["seg_floats"] == 3 * up(K * ws)
-    assert sz["trajectory"]["seg_floats"] == 3 * up(w.T_max * ws + 20)
+    # one working-set size ws fits both the segment and the trajectory buffer
+    ws = [v for v in range(1, 4096) if sz["segment"]["seg_floats"] == 3 * up(K * v)
+          and sz["trajectory"]["seg_floats"] == 3 * up(w.T_max * v + 20)]
+    assert len(ws) == 1 and ws[0] > sz["replay"]["fwd_floats"], ws
     # the automatic choice: trajectory while it fits the limit, then segment, then replay
     w.extra["grad_store"] = "auto"
     assert _sizes(w)["mode"] == "trajectory"
@@ -224,6 +226,18 @@ def _store(w, mode):
                      0.7), 1e-9),
     (lambda: _bouncy(W.uneven_chains(n_envs=6, T=150, seed_salt=2), 0.8, seed=5), 1e-7),
     (lambda: _bouncy(_store(W.uneven_chains(n_envs=5, T=120, seed_salt=4), "replay"), 0.8, seed=6), 1e-7),
+    # servo motors: limits never reached, sometimes, nearly always; the
+    # reverse modes; chains with contacts; the quadruped's controller
+    # driving target angles
+    (lambda: W.servo_arms(3, 120, gain=5.0, torque=200.0, vmax=10.0), 1e-9),
+    (lambda: W.servo_arms(3, 120), 1e-9),
+    (lambda: W.servo_arms(3, 120, gain=30.0, torque=0.4, vmax=0.6), 1e-9),
+    (lambda: _store(W.servo_arms(3, 120), "replay"), 1e-9),
+    (lambda: _store(W.servo_arms(3, 120), "segment"), 1e-9),
+    (lambda: W.servo_chains(5, 100), 1e-7),
+    (lambda: W.with_servos(W.quadruped(n_envs=3, T_min=10, T_max=16,
+                                       mlp_w=W.mlp_init(zero_output=False, out_scale=0.3)),
+                           gain=30.0, torque=4.0, vmax=4.0), 1e-8),
 ])
 def test_kernel_source_in_fp64_equals_oracle(maker, tol):
     w = maker()
