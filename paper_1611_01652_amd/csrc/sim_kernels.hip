@@ -228,7 +228,9 @@ __global__ __launch_bounds__(64) void k_rollout(DevModel M, TileSet ts, RolloutA
   for (int tile = next_tile(ts.queue); tile < ts.n_tiles; tile = next_tile(ts.queue)) {
     const int ie = ts.envs[tile * EPW + team];
     const bool valid = ie >= 0;
-    Env E = make_env(M, valid ? ie : 0, lds + team * ts.env_floats, M.n_iters, false);
+    // (a team without an env takes the layout of the tile's first env, which
+    // the bucket's LDS stride covers, and does no work)
+    Env E = make_env(M, valid ? ie : ts.envs[tile * EPW], lds + team * ts.env_floats, M.n_iters, false);
     env_rollout<TeamGPU, SOLVE != 0>(tm, M, E, valid, a);
     __syncthreads();
   }
@@ -244,7 +246,7 @@ __global__ __launch_bounds__(64) void k_step(DevModel M, TileSet ts, StepArgs a)
   for (int tile = next_tile(ts.queue); tile < ts.n_tiles; tile = next_tile(ts.queue)) {
     const int ie = ts.envs[tile * EPW + team];
     const bool valid = ie >= 0;
-    Env E = make_env(M, valid ? ie : 0, lds + team * ts.env_floats, M.n_iters, false);
+    Env E = make_env(M, valid ? ie : ts.envs[tile * EPW], lds + team * ts.env_floats, M.n_iters, false);
     env_single_step<TeamGPU, SOLVE != 0>(tm, M, E, valid, a);
     __syncthreads();
   }
@@ -260,7 +262,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1))) void
   for (int tile = next_tile(ts.queue); tile < ts.n_tiles; tile = next_tile(ts.queue)) {
     const int ie = ts.envs[tile * EPW + team];
     const bool valid = ie >= 0;
-    Env E = make_env(M, valid ? ie : 0, lds + team * ts.env_floats, M.n_iters, true);
+    Env E = make_env(M, valid ? ie : ts.envs[tile * EPW], lds + team * ts.env_floats, M.n_iters, true);
     env_rollout_grad<SAVED != 0>(tm, M, E, valid, a);
     __syncthreads();
   }
@@ -281,7 +283,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1))) void
     const int sg = u / ts.n_tiles, tile = u - sg * ts.n_tiles;
     const int ie = ts.envs[tile * EPW + team];
     const bool valid = ie >= 0;
-    Env E = make_env(M, valid ? ie : 0, lds + team * ts.env_floats, M.n_iters, false);
+    Env E = make_env(M, valid ? ie : ts.envs[tile * EPW], lds + team * ts.env_floats, M.n_iters, false);
     env_recompute(tm, M, E, valid, a, sg);
     __syncthreads();
   }

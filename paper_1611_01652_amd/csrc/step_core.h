@@ -2291,9 +2291,13 @@ SHD void hinge_warm_rev(const Team& tm, const DevModel& M, const Env& E, int s, 
   l0b[3] = hinge_warm_row<3, NS>(tm, sd, R0 + 3 * RS, Q0 + 3 * RSA, A, imx);
   l0b[4] = hinge_warm_row<3, NS>(tm, sd, R0 + 4 * RS, Q0 + 4 * RSA, A, imx);
   if (E.jr == 6) l0b[5] = hinge_warm_row<3, NS>(tm, sd, R0 + 5 * RS, Q0 + 5 * RSA, A, imx);
-  // (both lanes of a pair add the same value to the same entries)
-  float* wA = E.wsA() + E.store_of(code);
-  for (int q = 0; q < E.jr; ++q) wA[q] += M.warm * l0b[q];
+  // Both lanes of a pair hold the same values; one of them (side b's) adds
+  // them: a read-modify-write by both lanes would count them once only where
+  // the two lanes' reads precede both writes, as in a wave's lockstep.
+  if (NS == 2 || sd.sd[0] == 1) {
+    float* wA = E.wsA() + E.store_of(code);
+    for (int q = 0; q < E.jr; ++q) wA[q] += M.warm * l0b[q];
+  }
   for (int i = 0; i < NS; ++i) E.bodyA(sd.bd[i])[AIM] += imx[i];
 }
 

@@ -30,8 +30,9 @@ _lib = None
 def _load():
     global _lib
     if _lib is None:
-        deps = [SRC] + [os.path.join(ROOT, "paper_1611_01652_amd", "csrc", f)
-                        for f in ("step_core.h", "drivers.h", "model_pack.cpp", "model_pack.h")]
+        deps = [SRC, os.path.join(HERE, "kernel_host", "host_common.h")] + [
+            os.path.join(ROOT, "paper_1611_01652_amd", "csrc", f)
+            for f in ("step_core.h", "drivers.h", "model_pack.cpp", "model_pack.h")]
         if not os.path.exists(LIB) or os.path.getmtime(LIB) < max(os.path.getmtime(p) for p in deps):
             tmp = f"{LIB}.{os.getpid()}.tmp"   # parallel test workers each build their own, then swap it in
             subprocess.check_call(["g++", "-O1", "-std=c++17", "-fPIC", "-shared", "-w", "-o", tmp, SRC])
