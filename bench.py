@@ -240,6 +240,9 @@ def main():
     ap.add_argument("--workload", default="chains", choices=["arms", "chains", "quadruped"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
+    ap.add_argument("--grad-mem-gib", type=float, default=None,
+                    help="memory for the reverse sweep's saved working sets (default: what the device has free "
+                         "less a 12 GiB margin)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
@@ -251,6 +254,12 @@ def main():
     from paper_1611_01652_amd.sim import Simulator
 
     w = make_workload(args.workload)
+    # the reverse sweep keeps every step's working set when the device's memory
+    # allows (recomputed in one parallel pass), else one segment's at a time
+    free, _ = torch.cuda.mem_get_info()
+    gib = args.grad_mem_gib if args.grad_mem_gib is not None else max(1.0, free / 2**30 - 12.0)
+    w.extra = dict(w.extra or {})
+    w.extra["grad_mem_limit"] = int(gib * 2**30)
     sim = Simulator(w)
     print(f"bench: {args.workload} {w.n_envs} envs x {w.T_max} steps, {len(sim.teams())} buckets", file=sys.stderr,
           flush=True)

@@ -173,8 +173,10 @@ template <class Team>
 SHD void save_step(const Team& tm, const DevModel& M, const Env& E, float* dst) {
   const int nf = E.lay.total_fwd, nh = align4(M.n_iters * E.nslot);
   for (int i = tm.tl; i < nf / 4; i += tm.ts) st4(dst + 4 * i, ld4(E.L + 4 * i));
+  // (with a history ring the sweeps wrote the history to dst themselves)
   const float* hs = E.L + E.lay.hist;
-  for (int i = tm.tl; i < nh / 4; i += tm.ts) st4(dst + nf + 4 * i, ld4(hs + 4 * i));
+  const int nh4 = E.lay.hring ? 0 : nh / 4;
+  for (int i = tm.tl; i < nh4; i += tm.ts) st4(dst + nf + 4 * i, ld4(hs + 4 * i));
   for (int b = tm.tl; b < E.nb; b += tm.ts)
     for (int k = 0; k < 3; ++k) dst[nf + nh + 3 * b + k] = E.bodyA(b)[AW0 + k];
 }
@@ -209,7 +211,8 @@ SHD void load_step(const Team& tm, const DevModel& M, const Env& E, const float*
   if (b0)
     for (int k = 0; k < 3; ++k) w[k] = src[nf + nh + 3 * tm.tl + k];
   copy_to_lds(tm, E.L, src, nf / 4, E.lay.misc / 4, (E.lay.misc + MISC_N) / 4);
-  copy_to_lds(tm, E.L + E.lay.hist, src + nf, nh / 4);
+  // (a history ring is filled sweep by sweep by the sweeps' reverse)
+  if (!E.lay.hring) copy_to_lds(tm, E.L + E.lay.hist, src + nf, nh / 4);
   if (b0)
     for (int k = 0; k < 3; ++k) E.bodyA(tm.tl)[AW0 + k] = w[k];
   for (int b = tm.tl + tm.ts; b < E.nb; b += tm.ts) {
@@ -316,8 +319,12 @@ SHD_FLAT void env_rollout_grad(const Team& tm, const DevModel& M, const Env& E, 
     for (int t = t0; !traj && tm.any(t < t1); ++t) {
       const bool act = t < t1;
       if (SAVED) {
-        replay_to_sweeps(tm, M, E, a, act, t, E.hist(0), true);
-        if (act) save_step(tm, M, E, seg + (size_t)(t - t0) * sstride);
+        // (with a history ring the sweeps write the history to the step's
+        // saved working set directly)
+        float* dst = act ? seg + (size_t)(t - t0) * sstride : nullptr;
+        replay_to_sweeps(tm, M, E, a, act, t, E.lay.hring ? (dst ? dst + E.lay.total_fwd : nullptr) : E.hist(0),
+                         true);
+        if (act) save_step(tm, M, E, dst);
         tm.sync();   // the copy reads bodies and rows that integration rewrites
         f_integrate(tm, M, E, act);
         f_store(tm, E, act);
@@ -368,7 +375,8 @@ SHD_FLAT void env_rollout_grad(const Team& tm, const DevModel& M, const Env& E, 
       tm.sync();
       a_store(tm, E, act);
       a_integrate(tm, M, E, act);
-      a_pgs(tm, M, E, act);
+      a_pgs(tm, M, E, act,
+            (SAVED && act) ? seg + (size_t)(traj ? t : t - t0) * sstride + E.lay.total_fwd : nullptr);
       a_warm(tm, M, E, act);
       a_rows(tm, M, E, act);
       // an overflow can later be dropped by a clamp's or a contact's select,

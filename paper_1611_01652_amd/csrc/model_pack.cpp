@@ -21,7 +21,7 @@ struct HostEnv {
   std::vector<int> topo;   // jpar, jchi, gbody, pcode, colstart, cand
   std::vector<float> cst;
   int team = 1;
-  int fwd_floats = 0, adj_floats = 0;
+  int fwd_floats = 0, adj_floats = 0, adj_floats_ring = 0;
   int dump_floats = 0;     // one step's saved working set (see drivers.h)
 };
 
@@ -210,6 +210,8 @@ sim_status build_env(const sim_model_desc& d, int e, bool keep_v, HostEnv& H) {
   const int vs = vsave_floats(keep_v, H.nb);
   H.fwd_floats = make_lay(H.nb, H.nj, H.G, H.P, H.ncol, H.ncand, H.nslot, H.lam, d.n_iters, false, mf, ma, vs).total;
   H.adj_floats = make_lay(H.nb, H.nj, H.G, H.P, H.ncol, H.ncand, H.nslot, H.lam, d.n_iters, true, mf, ma, vs).total;
+  H.adj_floats_ring =
+      make_lay(H.nb, H.nj, H.G, H.P, H.ncol, H.ncand, H.nslot, H.lam, d.n_iters, true, mf, ma, vs, true).total;
   H.dump_floats = dump_stride_of(H.fwd_floats, d.n_iters, H.nslot, H.nb);
   return SIM_OK;
 }
@@ -227,6 +229,7 @@ sim_status pack_model(const sim_model_desc* d, PackedModel& P, std::string& err)
   P.team_of.assign(E, 1);
   P.fwd_of.assign(E, 0);
   P.adj_of.assign(E, 0);
+  P.adj_ring_of.assign(E, 0);
   P.ccap_of.assign(E, 0);
   P.seg_total = 0;
   P.tape_rows = 0;
@@ -262,6 +265,7 @@ sim_status pack_model(const sim_model_desc* d, PackedModel& P, std::string& err)
     P.team_of[e] = H.team;
     P.fwd_of[e] = H.fwd_floats;
     P.adj_of[e] = H.adj_floats;
+    P.adj_ring_of[e] = H.adj_floats_ring;
     P.ccap_of[e] = H.ccap;
   }
   // Each env's block starts on a SEG_UNIT boundary; the header holds its

@@ -10,6 +10,7 @@ namespace sim {
 
 struct PackedModel {
   std::vector<int> hdr, topo, lam_off, team_of, fwd_of, adj_of, ccap_of;
+  std::vector<int> adj_ring_of;   // adjoint LDS floats with a ring of the impulse history (saved working sets)
   std::vector<float> cst, target;
   long long seg_total = 0;   // floats of the reverse sweep's buffer (all envs)
   long long tape_rows = 0;   // env-steps of the controller tape (sum of T_e)

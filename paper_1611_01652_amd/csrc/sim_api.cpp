@@ -158,6 +158,10 @@ sim_status run_buckets(sim_model* h, hipStream_t st, F launch, const char* what)
   return SIM_OK;
 }
 
+// The CU's LDS and its SIMDs (gfx950): the reverse kernel runs one wave per SIMD.
+constexpr long long kLdsPerCu = 160 * 1024;
+constexpr long long kSimdsPerCu = 4;
+
 // LDS bytes of a workgroup: the env tiles and, for the forward kernels of a
 // learned warm start, the shared network region.
 long long fwd_bytes(const DevModel& M, int team, int floats_fwd, int ccap_max) {
@@ -171,7 +175,7 @@ long long adj_bytes(const DevModel& M, int team, int floats_adj) {
 long long fwd_bytes(const sim_model* h, const Bucket& b) { return fwd_bytes(h->M, b.team, b.floats_fwd, b.ccap_max); }
 
 int grid_for(const sim_model* h, long long units, long long bytes) {
-  int per_cu = bytes > 0 ? (int)((160 * 1024) / bytes) : 8;
+  int per_cu = bytes > 0 ? (int)(kLdsPerCu / bytes) : 8;
   per_cu = std::max(1, std::min(per_cu, 8));
   return (int)std::max(1LL, std::min(units, (long long)h->n_cu * per_cu));
 }
@@ -389,24 +393,42 @@ sim_status sim_init(const sim_model_desc* d, sim_handle* out) {
     f = (f + 3) & ~3;
     return (f / 4) % 2 == 0 ? f + 4 : f;
   };
-  std::vector<int> fwd_of(E), adj_of(E);
+  std::vector<int> fwd_of(E), adj_of(E), adj_ring_of(E);
   for (int e = 0; e < E; ++e) {
     fwd_of[e] = lds_stride(P.fwd_of[e]);
     adj_of[e] = lds_stride(P.adj_of[e]);
+    adj_ring_of[e] = lds_stride(P.adj_ring_of[e]);
   }
   const long long seg_total = P.seg_total;
   int max_lds = 0;
   for (int e = 0; e < E; ++e) {
-    // widen the team while the tile does not fit in LDS
-    // narrowest team the topology allows: a wave's step time is set by its
-    // latency chain, not by how many envs share the wave
-    int team = std::max(team_of[e], d->min_team);
-    if (team > 64) team = 64;
-    auto need = [&](int t) {
-      return std::max(adj_bytes(M, t, adj_of[e]), fwd_bytes(M, t, fwd_of[e], P.ccap_of[e]));
-    };
-    while (team < 64 && need(team) > h->max_lds) team *= 2;
-    if (need(team) > h->max_lds) {
+    // The team width: a wave's step time is set by its env's latency chain,
+    // not by how many envs share the wave, so what counts is how many envs a
+    // CU holds at once in the reverse sweep, the costlier pass: envs per wave
+    // times the waves whose tiles fit the CU's LDS, at most one per SIMD (the
+    // reverse kernel's registers allow no more).  Of the widths the topology
+    // allows whose tile fits, the narrowest that holds the most envs.
+    // The reverse of saved working sets may keep only a ring of the impulse
+    // history in LDS (the rest is read from the working set sweep by sweep):
+    // taken where it lets a CU hold more envs.
+    const int team0 = std::min(64, std::max(team_of[e], d->min_team));
+    int team = -1, ring = 0;
+    long long best = 0;
+    for (int r = 0; r < (P.dump != DUMP_REPLAY ? 2 : 1); ++r) {
+      const int fa = r ? adj_ring_of[e] : adj_of[e];
+      for (int t = team0; t <= 64; t *= 2) {
+        if (std::max(adj_bytes(M, t, fa), fwd_bytes(M, t, fwd_of[e], P.ccap_of[e])) > h->max_lds) continue;
+        const long long waves =
+            std::min<long long>(kSimdsPerCu, kLdsPerCu / std::max<long long>(1, adj_bytes(M, t, fa)));
+        const long long envs_cu = (64 / t) * std::max<long long>(1, waves);
+        if (envs_cu > best) { best = envs_cu; team = t; ring = r; }
+      }
+    }
+    if (ring) {
+      adj_of[e] = adj_ring_of[e];
+      P.hdr[(size_t)e * H_COUNT + H_RING] = 1;
+    }
+    if (team < 0) {
       release(h);
       return fail(SIM_E_UNSUPPORTED, "env " + std::to_string(e) + " needs " + std::to_string(adj_of[e] * 4) +
                                          " bytes of LDS, more than the device's " + std::to_string(h->max_lds));

@@ -95,7 +95,7 @@ SHD void kahan_add(float* sum, float* c, float x) {
 
 // ------------------------------------------------------------------ model in global memory
 enum { H_B0, H_NB, H_J0, H_NJ, H_LAMOFF, H_LAMSZ, H_G, H_P, H_NCOL, H_TOPO, H_CST, H_T, H_LB, H_CCAP,
-       H_NCAND, H_ENV, H_SEG, H_NSLOT, H_TAPE, H_COUNT };
+       H_NCAND, H_ENV, H_SEG, H_NSLOT, H_TAPE, H_RING, H_COUNT };
 // candidate code: kind in the top byte
 enum { K_JOINT = 0, K_GROUND = 1, K_PAIR = 2 };
 SHD int cand_kind(int c) { return c >> 24; }
@@ -181,8 +181,12 @@ struct alignas(16) i4 { int x, y, z, w; };
 struct Lay {
   int body, jc, gs, topo, ws, rows, act_cnt, act_slot, act_code, live, plan, vis, misc, mlp, vsave;  // forward
   int bodyA, rowsA, hist, wsA, jA, mlpA;                                     // adjoint
+  int hring;   // 0: the sweep history of the step in LDS; HRING: a ring of sweeps (the rest in global memory)
   int total_fwd, total;
 };
+// Sweeps of the impulse history held in LDS when the reverse reads the saved
+// working sets: the current sweep's, the previous one's and the one loaded next.
+constexpr int HRING = 3;
 enum { MISC_LOSS = 0, MISC_FLAGS = 1, MISC_NCON = 2, MISC_MU = 3, MISC_GMU = 4, MISC_GMUC = 5, MISC_ITERS = 6,
        MISC_FB = 7, MISC_REST = 8, MISC_N = 12 };
 
@@ -195,9 +199,12 @@ SHD int align4(int x) { return (x + 3) & ~3; }
 enum { JA_DAMP = 0, JA_DAMPC = 1, JA_ANCP = 2, JA_ANCC = 5, JA_ANC_COMP = 6, JA_FLOATS = 14 };
 // mlp_f / mlp_a: controller floats per env (s, h1, h2 / du, d2, d1, sbar), 0 without one
 // vs_f: floats of saved predicted velocities (learned warm start, restitution), 0 without
+// ring: the adjoint layout holds HRING sweeps of the impulse history instead
+// of all of them and the start impulses
 SHD Lay make_lay(int nb, int nj, int G, int P, int ncol, int ncand, int nslot, int lam, int n_iters, bool adj,
-                 int mlp_f = 0, int mlp_a = 0, int vs_f = 0) {
+                 int mlp_f = 0, int mlp_a = 0, int vs_f = 0, bool ring = false) {
   Lay L;
+  L.hring = adj && ring ? HRING : 0;
   int o = 0;
   L.body = o; o += align4((nb + 1) * BS);   // bodies and the world slot (index nb)
   L.jc = o; o += align4(nj * JS);
@@ -218,8 +225,12 @@ SHD Lay make_lay(int nb, int nj, int G, int P, int ncol, int ncand, int nslot, i
   if (adj) {
     L.bodyA = o; o += align4((nb + 1) * BSA);
     L.rowsA = o; o += align4(nslot * RSA);
-    o += align4(nslot);   // hist(-1): the sweeps' start impulses (reverse only)
-    L.hist = o; o += align4(n_iters * nslot);
+    if (L.hring) {
+      L.hist = o; o += align4(HRING * nslot);
+    } else {
+      o += align4(nslot);   // hist(-1): the sweeps' start impulses (reverse only)
+      L.hist = o; o += align4(n_iters * nslot);
+    }
     L.wsA = o; o += align4(lam);
     L.jA = o; o += align4(JA_FLOATS * nj);   // per-joint parameter adjoint totals and compensations
     L.mlpA = o; o += align4(mlp_a);
@@ -255,8 +266,16 @@ struct Env {
   SHD float* wsA() const { return L + lay.wsA; }
   SHD float* row(int s) const { return L + lay.rows + mul24(s, RS); }
   SHD float* rowA(int s) const { return L + lay.rowsA + mul24(s, RSA); }
-  // (it >= -1: the row before the first sweep's holds the start impulses)
-  SHD float* hist(int it) const { return L + lay.hist + it * nslot; }
+  // (it >= -1: the row before the first sweep's holds the start impulses; in
+  // a ring, sweep it sits in slot it mod HRING)
+  SHD float* hist(int it) const {
+    if (lay.hring) {
+      int k = it % HRING;
+      if (k < 0) k += HRING;
+      return L + lay.hist + k * nslot;
+    }
+    return L + lay.hist + it * nslot;
+  }
   SHD int* act_cnt() const { return (int*)(L + lay.act_cnt); }
   SHD int* act_slot() const { return (int*)(L + lay.act_slot); }
   SHD int* act_code() const { return (int*)(L + lay.act_code); }
@@ -319,8 +338,11 @@ SHD Env make_env(const DevModel& M, int ie, float* lds, int n_iters, bool adj) {
   E.gtopo = M.topo + h[H_TOPO];
   E.gcst = M.cst + h[H_CST];
   E.L = lds;
+  // (the reverse of saved working sets may keep a ring of the impulse
+  // history: an env flagged for it in its header)
   E.lay = make_lay(E.nb, E.nj, E.G, E.P, E.ncol, E.ncand, E.nslot, E.lam_size, n_iters, adj, mlp_floats_fwd(M),
-                   mlp_floats_adj(M), vsave_floats(M.ws_kind || M.has_rest, E.nb));
+                   mlp_floats_adj(M), vsave_floats(M.ws_kind || M.has_rest, E.nb),
+                   M.dump != DUMP_REPLAY && h[H_RING] != 0);
   return E;
 }
 
@@ -1752,7 +1774,8 @@ SHD void a_clear_step(const Team& tm, const Env& E, bool act) {
   // hist(-1) = the start impulses, so that in the reversed sweeps a hinge
   // row's impulse before its update is the previous sweep's record in every
   // sweep, the first included
-  const int nsl = act ? E.nslot : 0;
+  // (a ring takes them when it is filled)
+  const int nsl = act && !E.lay.hring ? E.nslot : 0;
   for (int s = tm.tl; s < nsl; s += tm.ts) E.hist(-1)[s] = E.row(s)[RL0];
   // the world slot's adjoint is a sink of the sweeps: cleared every step so
   // that it stays finite (it only ever meets zero inverse masses)
@@ -2223,16 +2246,42 @@ SHD void rev_contact(const DevModel& M, const Env& E, int s, int a, int b, float
   E.bodyA(b)[AIM] += imB;
 }
 
-// B6: adjoint of the sweeps (iterations, colours and rows exactly reversed).
+// Sweep it of the impulse history into its ring slot: from the step's
+// history in global memory, or (it = -1) the start impulses.
 template <class Team>
-SHD void a_pgs(const Team& tm, const DevModel& M, const Env& E, bool act) {
+SHD void hist_fill(const Team& tm, const Env& E, const float* gh, int it) {
+  float* dst = E.hist(it);
+  if (it >= 0) {
+    const float* src = gh + (size_t)it * E.nslot;
+    for (int s = tm.tl; s < E.nslot; s += tm.ts) dst[s] = src[s];
+  } else {
+    for (int s = tm.tl; s < E.nslot; s += tm.ts) dst[s] = E.row(s)[RL0];
+  }
+}
+
+// B6: adjoint of the sweeps (iterations, colours and rows exactly reversed).
+// gh: the step's impulse history in global memory, n_iters rows of nslot
+// floats, when the env keeps only a ring of it in LDS: the last two sweeps
+// are loaded first, and at the start of each reversed sweep it the sweep it-2
+// (or the start impulses) takes the slot sweep it+1 no longer needs.
+template <class Team>
+SHD void a_pgs(const Team& tm, const DevModel& M, const Env& E, bool act, const float* gh = nullptr) {
   const float mu = E.misc()[MISC_MU];
   float gmu = 0.f;
+  const bool ring = E.lay.hring != 0 && act && M.n_iters > 0;
+  if (ring) {
+    hist_fill(tm, E, gh, M.n_iters - 1);
+    hist_fill(tm, E, gh, M.n_iters - 2);
+  }
+  tm.sync();
   SweepCursor<-1> sw;
   sw.start(tm, E, M.n_iters, n_live(E, act));
   while (tm.any(sw.left > 0)) {
     i4 vn, p2;
     sw.prefetch(tm, E, vn, p2);
+    // (the slot is read by no visit of this sweep; the barrier after the
+    // visit orders the writes before the next sweep's reads)
+    if (ring && sw.left > 0 && sw.ci == sw.nl - 1 && sw.it >= 1) hist_fill(tm, E, gh, sw.it - 2);
     const float* H = E.hist(sw.it);
     const float* Hp = E.hist(sw.it - 1);
     const int nk = sw.count(tm);

@@ -101,9 +101,17 @@ inline void host_wsn_rows(double* lds0, const double* net, int total, const int*
   }
 }
 struct Host { PackedModel P; DevModel M; std::vector<double> clock; };
+// 1: every env of a model whose reverse reads saved working sets keeps a ring
+// of the impulse history (the library takes it where it lets a CU hold more
+// envs); 0: none does
+int g_force_ring = 0;
 bool make(const sim_model_desc* d, Host& h) {
   std::string err;
   if (pack_model(d, h.P, err) != SIM_OK) { fprintf(stderr, "pack: %s\n", err.c_str()); return false; }
+  if (g_force_ring && h.P.dump != DUMP_REPLAY) {
+    for (int e = 0; e < d->n_envs; ++e) h.P.hdr[(size_t)e * H_COUNT + H_RING] = 1;
+    h.P.adj_of = h.P.adj_ring_of;
+  }
   DevModel& M = h.M;
   M.n_envs = d->n_envs; M.B = d->env_body_off[d->n_envs]; M.J = d->env_joint_off[d->n_envs];
   M.T_max = d->T_max; M.n_iters = d->n_iters; M.ground = d->ground; M.loss_kind = d->loss_kind;

@@ -34,6 +34,7 @@ struct TeamHost {
 };
 }  // namespace
 extern "C" {
+void kh_set_ring(int on) { g_force_ring = on; }
 int kh_sizes(const sim_model_desc* d, long long* out) {
   Host h;
   if (!make(d, h)) return -1;

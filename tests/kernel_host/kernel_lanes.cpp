@@ -370,6 +370,7 @@ std::vector<std::pair<int, std::vector<int>>> make_tiles(const Launch& L, int n_
 }  // namespace
 
 extern "C" {
+void kl_set_ring(int on) { g_force_ring = on; }
 // Forward rollout, trajectory recompute (every segment) and reverse sweep of
 // every env, with the given schedule (0 ascending, 1 descending, 2 random
 // with `seed`), teams of at least `min_team` lanes and `teams_per_wave` envs

@@ -60,6 +60,7 @@ def _lib(path):
     lib = C.CDLL(path)
     lib.kl_rollout_grad.restype = C.c_longlong
     lib.kl_rollout_solve.restype = C.c_longlong
+    lib.kl_set_ring.argtypes = [C.c_int]
     return lib
 
 
@@ -123,6 +124,9 @@ def main():
     min_team = int(sys.argv[2])
     tpw = int(sys.argv[3])
     names = sys.argv[4:]
+    if names and names[0] == "--ring":   # every env keeps a ring of the impulse history
+        lib.kl_set_ring(1)
+        names = names[1:]
     for name in names:
         solve = name in SOLVE_CASES
         w = (SOLVE_CASES if solve else CASES)[name]()

@@ -298,3 +298,27 @@ def test_tolerance_mode_kernel_source_in_fp64_equals_oracle(learned, fb_tol, res
     Rf = ref["records"][key(ref["records"])]
     np.testing.assert_array_equal(G[:, 12:15], Rf[:, 12:15])
     assert _rel(G[:, :12], Rf[:, :12]) < 1e-8
+
+
+@pytest.mark.parametrize("maker", [
+    lambda: _store(W.uneven_chains(n_envs=5, T=120, seed_salt=4), "segment"),
+    lambda: W.uneven_chains(n_envs=6, T=110, seed_salt=2),
+    lambda: W.quadruped(n_envs=3, T_min=20, T_max=30, mlp_w=W.mlp_init(zero_output=False, out_scale=0.3)),
+    lambda: _store(W.servo_arms(3, 120), "segment"),
+    lambda: _bouncy(W.uneven_chains(n_envs=4, T=90, seed_salt=6), 0.8, seed=5),
+])
+def test_history_ring_gives_the_same_bits(maker):
+    # the reverse of saved working sets with only a ring of the impulse
+    # history in LDS (the rest read from the working set sweep by sweep)
+    # takes the same arithmetic as with the whole history in LDS
+    w = maker()
+    lib = _load()
+    lib.kh_set_ring(0)
+    a = host_fp64(w)
+    lib.kh_set_ring(1)
+    try:
+        b = host_fp64(w)
+    finally:
+        lib.kh_set_ring(0)
+    for k in a:
+        np.testing.assert_array_equal(a[k], b[k], err_msg=k)
