@@ -268,10 +268,13 @@ def main():
     dl = torch.ones(w.n_envs, dtype=torch.float32, device="cuda")
     ws_buf = sim.workspace()
     env_steps = float(np.sum(w.T_env))
+    # trajectory mode: the rollout keeps every step's working set in the
+    # workspace and the reverse reads them without recomputing them
+    keep = ws_buf if sim.info.grad_store == 3 else None
 
     for _ in range(args.warmup):
-        r = sim.rollout(x0, u, want_ckpt=True, want_final=False)
-        sim.rollout_grad(x0, u, r["ckpt"], dl, workspace=ws_buf)
+        r = sim.rollout(x0, u, want_ckpt=True, want_final=False, keep=keep)
+        sim.rollout_grad(x0, u, r["ckpt"], dl, workspace=ws_buf, kept=keep)
     torch.cuda.synchronize()
     mk = lambda: torch.cuda.Event(enable_timing=True)   # noqa: E731
     n_b = len(sim.teams())
@@ -287,12 +290,12 @@ def main():
     t0 = time.perf_counter()
     for k in range(args.steps):
         fwd_evs[k][0].record()
-        r = sim.rollout(x0, u, want_ckpt=True, want_final=False)
+        r = sim.rollout(x0, u, want_ckpt=True, want_final=False, keep=keep)
         fwd_evs[k][1].record()
         sim.time_grad(phase_evs[k])
         sim.time_buckets(bucket_evs[k])
         evs[k][0].record()
-        g = sim.rollout_grad(x0, u, r["ckpt"], dl, workspace=ws_buf)
+        g = sim.rollout_grad(x0, u, r["ckpt"], dl, workspace=ws_buf, kept=keep)
         evs[k][1].record()
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
@@ -356,6 +359,7 @@ def main():
         "fwd_ms": fwd_ms,
         "grad_ms": grad_ms,
         "grad_store": mode,
+        "forward_keeps_working_sets": keep is not None,
         "grad_phases_ms": {"recompute": rec_ms, "reverse": rev_ms},
         "grad_check": None,
         "env_flags_nonzero": int((flags != 0).sum()),

@@ -57,7 +57,7 @@
 extern "C" {
 #endif
 
-#define SIM_ABI_VERSION 7
+#define SIM_ABI_VERSION 8
 
 typedef struct sim_model* sim_handle;
 
@@ -326,6 +326,26 @@ sim_status rollout_grad(sim_handle h, const float* x0, const float* u, const flo
                         float* g_inv_inertia, float* g_mu, float* g_damping, float* g_anchor_p,
                         float* g_anchor_c, void* workspace, size_t workspace_bytes, uint32_t* env_flags,
                         void* stream);
+
+/* Forward rollout that keeps its working sets (trajectory mode only: the
+ * model's sim_info.grad_store is SIM_GRAD_TRAJECTORY, else SIM_E_UNSUPPORTED;
+ * fixed-sweep models).  As `rollout`, and it also writes every step's saved
+ * working set into `workspace` (device, at least sim_info.workspace_bytes),
+ * exactly what rollout_grad's recompute would write from the checkpoints, so
+ * that rollout_grad_kept can skip that recompute.  ckpt may be NULL. */
+sim_status rollout_keep(sim_handle h, const float* x0, const float* u, float* loss_env, float* x_final,
+                        float* lam_final, float* ckpt, uint32_t* env_flags, void* workspace, size_t workspace_bytes,
+                        void* stream);
+
+/* Reverse mode after rollout_keep: as rollout_grad without its recompute,
+ * reading the working sets that the last rollout_keep on this handle wrote to
+ * `workspace` with the same x0 and u (the caller keeps the workspace
+ * untouched in between).  The results are those of rollout_grad, bit for
+ * bit. */
+sim_status rollout_grad_kept(sim_handle h, const float* x0, const float* u, const float* dloss_env, float* g_x0,
+                             float* g_u, float* g_inv_mass, float* g_inv_inertia, float* g_mu, float* g_damping,
+                             float* g_anchor_p, float* g_anchor_c, void* workspace, size_t workspace_bytes,
+                             uint32_t* env_flags, void* stream);
 
 /* Allocation-free reverse mode, for callers that cannot allocate device
  * memory (code under HIP graph capture, tight serving or training loops,

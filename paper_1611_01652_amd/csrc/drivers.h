@@ -22,6 +22,9 @@ struct RolloutArgs {
   int* iters;          // [E] or null
   int* fallbacks;      // [E] or null
   RecArgs rec;
+  // the reverse sweep's buffer in trajectory mode: the rollout writes every
+  // step's saved working set there as it goes (null: it does not)
+  float* seg;
 };
 
 struct GradArgs {
@@ -224,11 +227,11 @@ SHD void load_step(const Team& tm, const DevModel& M, const Env& E, const float*
 
 // Step t up to the end of its sweeps, recording what the reverse needs: the
 // sweep history at hist and, with rec_w0, the step-start angular velocities
-// in the adjoint body slots.
+// in the adjoint body slots.  u: the control tape (null with a controller).
 template <class Team>
-SHD void replay_to_sweeps(const Team& tm, const DevModel& M, const Env& E, const GradArgs& a, bool act, int t,
+SHD void replay_to_sweeps(const Team& tm, const DevModel& M, const Env& E, const float* u, bool act, int t,
                           float* hist, bool rec_w0) {
-  f_controls(tm, M, E, (a.u && !M.ctrl) ? a.u + (size_t)t * M.J : nullptr, act, t);
+  f_controls(tm, M, E, (u && !M.ctrl) ? u + (size_t)t * M.J : nullptr, act, t);
   f_body_setup(tm, E, act, rec_w0);
   tm.sync();
   f_torques(tm, E, act);
@@ -240,11 +243,31 @@ SHD void replay_to_sweeps(const Team& tm, const DevModel& M, const Env& E, const
   f_pgs(tm, M, E, act, hist);
 }
 
+// One step of the env with its working set saved at dst (trajectory layout:
+// the forward LDS region after the sweeps, the sweep history, written by the
+// sweeps themselves, and the step-start angular velocities); dst is null for
+// a lane whose env takes no step.
+template <class Team>
+SHD void recorded_step(const Team& tm, const DevModel& M, const Env& E, const float* u, bool act, int t, float* dst) {
+  const int nf = E.lay.total_fwd, nh = align4(M.n_iters * E.nslot);
+  if (act)
+    for (int b = tm.tl; b < E.nb; b += tm.ts)
+      for (int k = 0; k < 3; ++k) dst[nf + nh + 3 * b + k] = E.body(b)[BW + k];
+  replay_to_sweeps(tm, M, E, u, act, t, dst ? dst + nf : nullptr, false);
+  tm.sync();
+  if (act)
+    for (int i = tm.tl; i < nf / 4; i += tm.ts) st4(dst + 4 * i, ld4(E.L + 4 * i));
+  tm.sync();   // the copy reads bodies and rows that integration rewrites
+  f_integrate(tm, M, E, act);
+  f_store(tm, E, act);
+  tm.sync();
+}
+
 // Trajectory mode: recompute segment sg of the env from its checkpoint with
 // the forward LDS layout, writing each step's working set straight into the
 // env's block (the sweep history and step-start angular velocities go to
 // global memory as they are produced), and, for the last segment, the loss
-// body's final position after it.
+// body's final record after it.
 template <class Team>
 SHD_FLAT void env_recompute(const Team& tm, const DevModel& M, const Env& E, bool valid, const GradArgs& a, int sg) {
   const int K = M.ckpt_every;
@@ -257,26 +280,58 @@ SHD_FLAT void env_recompute(const Team& tm, const DevModel& M, const Env& E, boo
   }
   tm.sync();
   const int t1 = live ? (t0 + K < T ? t0 + K : T) : 0;
-  const int nf = E.lay.total_fwd, nh = align4(M.n_iters * E.nslot);
-  const int sstride = live ? dump_stride_of(nf, M.n_iters, E.nslot, E.nb) : 0;
+  const int sstride = live ? dump_stride_of(E.lay.total_fwd, M.n_iters, E.nslot, E.nb) : 0;
   float* seg = live ? a.seg + E.seg_base() : nullptr;
   for (int t = t0; tm.any(t < t1); ++t) {
     const bool act = t < t1;
-    float* dst = act ? seg + (size_t)t * sstride : nullptr;
-    if (act)
-      for (int b = tm.tl; b < E.nb; b += tm.ts)
-        for (int k = 0; k < 3; ++k) dst[nf + nh + 3 * b + k] = E.body(b)[BW + k];
-    replay_to_sweeps(tm, M, E, a, act, t, dst ? dst + nf : nullptr, false);
-    tm.sync();
-    if (act)
-      for (int i = tm.tl; i < nf / 4; i += tm.ts) st4(dst + 4 * i, ld4(E.L + 4 * i));
-    tm.sync();   // the copy reads bodies and rows that integration rewrites
-    f_integrate(tm, M, E, act);
-    f_store(tm, E, act);
-    tm.sync();
+    recorded_step(tm, M, E, a.u, act, t, act ? seg + (size_t)t * sstride : nullptr);
   }
   if (live && t1 == T && tm.tl == 0)
     for (int k = 0; k < 18; ++k) seg[(size_t)T * sstride + k] = E.body(E.lb)[k];
+}
+
+// The fixed-sweep rollout of env_rollout that also writes, in trajectory
+// mode, every step's saved working set to the reverse sweep's buffer a.seg as
+// the recompute would (the same arithmetic: the recompute starts from the
+// checkpoints this rollout writes), so that the reverse needs no recompute.
+template <class Team>
+SHD_FLAT void env_rollout_keep(const Team& tm, const DevModel& M, const Env& E, bool valid, const RolloutArgs& a) {
+  if (valid) {
+    load_env_static(tm, M, E);
+    load_state(tm, E, a.x0, M.B);
+    for (int i = tm.tl; i < E.lam_size; i += tm.ts) E.ws()[i] = 0.f;
+  }
+  tm.sync();
+  float p0x = valid ? E.body(E.lb)[BP] : 0.f;
+  float loss = 0.f;
+  const int K = M.ckpt_every;
+  const int T = valid ? E.T : 0;
+  const int sstride = valid ? dump_stride_of(E.lay.total_fwd, M.n_iters, E.nslot, E.nb) : 0;
+  float* seg = valid ? a.seg + E.seg_base() : nullptr;
+  for (int t = 0; tm.any(t < T); ++t) {
+    const bool act = t < T;
+    if (act && a.ckpt && t % K == 0) write_ckpt(tm, M, E, a.ckpt + (size_t)(t / K) * ckpt_stride(M));
+    tm.sync();
+    recorded_step(tm, M, E, a.u, act, t, act ? seg + (size_t)t * sstride : nullptr);
+    if (act && tm.tl == 0) {
+      const float* p = E.body(E.lb) + BP;
+      const float p0[3] = {p0x, 0.f, 0.f};
+      loss += loss_term(M, E, t + 1, p, p0);
+    }
+  }
+  if (valid && T > 0 && tm.tl == 0)
+    for (int k = 0; k < 18; ++k) seg[(size_t)T * sstride + k] = E.body(E.lb)[k];
+  tm.sync();
+  uint32_t fl = valid ? nonfinite_flag(tm, E) : 0u;
+  if (valid) {
+    if (a.x_final) store_state(tm, E, a.x_final, M.B);
+    if (a.lam_final) store_ws(tm, E, a.lam_final);
+    if (tm.tl == 0) {
+      a.loss[E.e] = loss;
+      fl |= (uint32_t)(*reinterpret_cast<int*>(E.misc() + MISC_FLAGS));
+      if (a.flags) a.flags[E.e] = fl;
+    }
+  }
 }
 
 // SAVED: the working sets are saved (segment or trajectory mode, M.dump !=
@@ -322,7 +377,7 @@ SHD_FLAT void env_rollout_grad(const Team& tm, const DevModel& M, const Env& E, 
         // (with a history ring the sweeps write the history to the step's
         // saved working set directly)
         float* dst = act ? seg + (size_t)(t - t0) * sstride : nullptr;
-        replay_to_sweeps(tm, M, E, a, act, t, E.lay.hring ? (dst ? dst + E.lay.total_fwd : nullptr) : E.hist(0),
+        replay_to_sweeps(tm, M, E, a.u, act, t, E.lay.hring ? (dst ? dst + E.lay.total_fwd : nullptr) : E.hist(0),
                          true);
         if (act) save_step(tm, M, E, dst);
         tm.sync();   // the copy reads bodies and rows that integration rewrites
@@ -358,7 +413,7 @@ SHD_FLAT void env_rollout_grad(const Team& tm, const DevModel& M, const Env& E, 
         }
         tm.sync();
         // replay step t with recording (no integration, no store)
-        replay_to_sweeps(tm, M, E, a, act, t, E.hist(0), true);
+        replay_to_sweeps(tm, M, E, a.u, act, t, E.hist(0), true);
       }
       // gradient decay of the carry from the later steps (none before the last step)
       if (M.decay != 1.f) {

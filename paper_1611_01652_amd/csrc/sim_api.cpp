@@ -194,6 +194,7 @@ bool bucket_rollout(sim_model* h, size_t i, const DevModel& M, const RolloutArgs
   TileSet ts{b.envs_dev, b.n_tiles, b.floats_fwd, h->d_queue + i, 1};
   if (launch_zero(ts.queue, 1, sx) != hipSuccess) return false;
   const long long lds = fwd_bytes(h, b);
+  if (a.seg) return launch_rollout_keep(M, ts, b.team, grid_for(h, b, lds), (size_t)lds, a, sx) == hipSuccess;
   return launch_rollout(M, ts, b.team, grid_for(h, b, lds), (size_t)lds, a, sx) == hipSuccess;
 }
 // Trajectory mode: the recompute of every segment of one bucket's envs into
@@ -693,10 +694,11 @@ namespace {
 // the recompute writes every saved working set before the reverse reads it,
 // the reverse writes every controller tape row it later contracts, and the
 // contraction writes every partial tile before the reduction reads it.
+// kept: the workspace holds the working sets rollout_keep wrote (no recompute).
 sim_status rollout_grad_ws(sim_handle h, const float* x0, const float* u, const float* ckpt,
                            const float* dloss_env, float* g_x0, float* g_u, float* g_inv_mass, float* g_inv_inertia,
                            float* g_mu, float* g_damping, float* g_anchor_p, float* g_anchor_c, void* workspace,
-                           uint32_t* env_flags, void* stream) {
+                           uint32_t* env_flags, void* stream, bool kept = false) {
   sim_status s = check_device("rollout_grad (earlier fault)");
   if (s != SIM_OK) return s;
   hipStream_t st = (hipStream_t)stream;
@@ -708,7 +710,7 @@ sim_status rollout_grad_ws(sim_handle h, const float* x0, const float* u, const 
   M.tape = ws + h->seg_floats;
   auto mark = [&](int k) { return !h->tev[k] || hipEventRecord(h->tev[k], st) == hipSuccess; };
   if (!mark(0)) return check_device("rollout_grad timing event");
-  if (M.dump == DUMP_TRAJECTORY)
+  if (M.dump == DUMP_TRAJECTORY && !kept)
     s = run_buckets(h, st, [&](size_t i, hipStream_t sx) { return bucket_recompute(h, i, M, a, sx); },
                     "rollout_grad recompute launch");
   if (s != SIM_OK) return s;
@@ -773,6 +775,51 @@ sim_status rollout_grad_noalloc(sim_handle h, const float* x0, const float* u, c
   if (!ws) return fail(SIM_E_STATE, "rollout_grad_noalloc: no scratch address for this device");
   return rollout_grad_ws(h, x0, u, ckpt, dloss_env, g_x0, g_u, g_inv_mass, g_inv_inertia, g_mu, g_damping,
                          g_anchor_p, g_anchor_c, ws, env_flags, stream);
+}
+
+sim_status rollout_keep(sim_handle h, const float* x0, const float* u, float* loss_env, float* x_final,
+                        float* lam_final, float* ckpt, uint32_t* env_flags, void* workspace, size_t workspace_bytes,
+                        void* stream) {
+  if (!h) return fail(SIM_E_ARG, "rollout_keep: null handle");
+  if (h->M.solve_mode != SIM_SOLVE_FIXED)
+    return fail(SIM_E_UNSUPPORTED, "rollout_keep: the working sets are of the fixed-sweep step (solve_mode 0)");
+  if (h->M.dump != DUMP_TRAJECTORY)
+    return fail(SIM_E_UNSUPPORTED, "rollout_keep: the model's reverse sweep is not in trajectory mode "
+                                   "(sim_info.grad_store; raise grad_mem_limit or set SIM_GRAD_TRAJECTORY)");
+  if (h->M.n_envs == 0) return SIM_OK;
+  if (!x0 || !loss_env) return fail(SIM_E_ARG, "rollout_keep: null x0 or loss_env");
+  if (h->M.J > 0 && h->M.T_max > 0 && !u) return fail(SIM_E_ARG, "rollout_keep: null control tape");
+  if (!workspace || (int64_t)workspace_bytes < h->info.workspace_bytes)
+    return fail(SIM_E_NOMEM, "rollout_keep: workspace smaller than sim_info.workspace_bytes (" +
+                                 std::to_string(h->info.workspace_bytes) + ")");
+  sim_status s = check_device("rollout_keep (earlier fault)");
+  if (s != SIM_OK) return s;
+  hipStream_t st = (hipStream_t)stream;
+  RolloutArgs a{x0, u, loss_env, x_final, lam_final, ckpt, env_flags, nullptr, nullptr, RecArgs{nullptr, 0, nullptr, 0},
+                (float*)workspace};
+  DevModel M = h->M;
+  if (!prep_controls(h, M, u, st)) return check_device("rollout_keep controls");
+  return run_buckets(h, st, [&](size_t i, hipStream_t sx) { return bucket_rollout(h, i, M, a, sx); },
+                     "rollout_keep launch");
+}
+
+sim_status rollout_grad_kept(sim_handle h, const float* x0, const float* u, const float* dloss_env, float* g_x0,
+                             float* g_u, float* g_inv_mass, float* g_inv_inertia, float* g_mu, float* g_damping,
+                             float* g_anchor_p, float* g_anchor_c, void* workspace, size_t workspace_bytes,
+                             uint32_t* env_flags, void* stream) {
+  if (!h) return fail(SIM_E_ARG, "rollout_grad_kept: null handle");
+  if (h->M.dump != DUMP_TRAJECTORY)
+    return fail(SIM_E_UNSUPPORTED, "rollout_grad_kept: the model's reverse sweep is not in trajectory mode");
+  if (h->M.n_envs == 0) return SIM_OK;
+  if (h->M.solve_mode != SIM_SOLVE_FIXED)
+    return fail(SIM_E_UNSUPPORTED, "rollout_grad_kept: the gradient is of the fixed-sweep step (solve_mode 0)");
+  if (!x0 || !dloss_env) return fail(SIM_E_ARG, "rollout_grad_kept: null x0 or dloss_env");
+  if (h->M.J > 0 && h->M.T_max > 0 && !u) return fail(SIM_E_ARG, "rollout_grad_kept: null control tape");
+  if (!workspace || (int64_t)workspace_bytes < h->info.workspace_bytes)
+    return fail(SIM_E_NOMEM, "rollout_grad_kept: workspace smaller than sim_info.workspace_bytes (" +
+                                 std::to_string(h->info.workspace_bytes) + ")");
+  return rollout_grad_ws(h, x0, u, nullptr, dloss_env, g_x0, g_u, g_inv_mass, g_inv_inertia, g_mu, g_damping,
+                         g_anchor_p, g_anchor_c, workspace, env_flags, stream, true);
 }
 
 sim_status sim_time_grad(sim_handle h, void* const* ev) {

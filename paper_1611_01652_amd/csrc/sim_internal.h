@@ -37,6 +37,8 @@ hipError_t launch_rollout_grad(const DevModel& M, const TileSet& ts, int team, i
                                const GradArgs& a, hipStream_t st);
 hipError_t launch_recompute(const DevModel& M, const TileSet& ts, int team, int grid, size_t lds,
                             const GradArgs& a, hipStream_t st);
+hipError_t launch_rollout_keep(const DevModel& M, const TileSet& ts, int team, int grid, size_t lds,
+                               const RolloutArgs& a, hipStream_t st);
 hipError_t allow_large_lds(int bytes);
 
 // warm-start network (wsn_kernels.hip)

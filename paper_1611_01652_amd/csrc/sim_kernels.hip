@@ -236,6 +236,24 @@ __global__ __launch_bounds__(64) void k_rollout(DevModel M, TileSet ts, RolloutA
   }
 }
 
+// The fixed-sweep rollout that also writes every step's saved working set
+// (trajectory mode), so that the reverse sweep needs no recompute.
+template <int TEAM>
+__global__ __launch_bounds__(64) void k_rollout_keep(DevModel M, TileSet ts, RolloutArgs a) {
+  extern __shared__ float lds[];
+  TeamGPU tm = make_team<TEAM>();
+  setup_shared(tm, M, lds, ts.env_floats, false);
+  const int team = threadIdx.x / TEAM;
+  constexpr int EPW = 64 / TEAM;
+  for (int tile = next_tile(ts.queue); tile < ts.n_tiles; tile = next_tile(ts.queue)) {
+    const int ie = ts.envs[tile * EPW + team];
+    const bool valid = ie >= 0;
+    Env E = make_env(M, valid ? ie : ts.envs[tile * EPW], lds + team * ts.env_floats, M.n_iters, false);
+    env_rollout_keep(tm, M, E, valid, a);
+    __syncthreads();
+  }
+}
+
 template <int TEAM, int SOLVE>
 __global__ __launch_bounds__(64) void k_step(DevModel M, TileSet ts, StepArgs a) {
   extern __shared__ float lds[];
@@ -438,6 +456,10 @@ hipError_t launch_recompute(const DevModel& M, const TileSet& ts, int team, int 
                             const GradArgs& a, hipStream_t st) {
   SIM_DISPATCH(team, k_recompute, a)
 }
+hipError_t launch_rollout_keep(const DevModel& M, const TileSet& ts, int team, int grid, size_t lds,
+                               const RolloutArgs& a, hipStream_t st) {
+  SIM_DISPATCH(team, k_rollout_keep, a)
+}
 
 template <class K>
 static hipError_t allow_lds(K kern, int bytes) {
@@ -468,6 +490,7 @@ hipError_t allow_large_lds(int bytes) {
   SIM_ALLOW_S(k_rollout_grad, 0)
   SIM_ALLOW_S(k_rollout_grad, 1)
   SIM_ALLOW(k_recompute)
+  SIM_ALLOW(k_rollout_keep)
 #undef SIM_ALLOW
 #undef SIM_ALLOW_S
   return e;

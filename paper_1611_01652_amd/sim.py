@@ -20,7 +20,7 @@ FLAG_NONFINITE = 1
 FLAG_CONTACT_OVERFLOW = 2
 
 # layout of the descriptor and info structs below (SIM_ABI_VERSION)
-ABI_VERSION = 7
+ABI_VERSION = 8
 
 # reverse sweep memory modes (sim_model_desc.grad_store)
 GRAD_STORE = {"auto": 0, "replay": 1, "segment": 2, "trajectory": 3}
@@ -161,6 +161,8 @@ def library():
     lib.rollout.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp]
     lib.rollout_grad.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, C.c_size_t, vp, vp]
     lib.rollout_grad_noalloc.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.rollout_keep.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, C.c_size_t, vp]
+    lib.rollout_grad_kept.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, C.c_size_t, vp, vp]
     lib.rollout_solve.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, C.c_int64, vp, C.c_int32, vp]
     lib.sim_describe_order.argtypes = [C.POINTER(SimDesc), C.c_int32, _I32P, _I32P, C.c_int32]
     lib.sim_describe_order.restype = C.c_int32
@@ -184,7 +186,8 @@ def library():
     lib.sim_time_buckets.argtypes = [vp, C.POINTER(vp), C.c_int32]
     lib.sim_env_buckets.argtypes = [vp, _I32P]
     for fn in ("sim_time_grad", "sim_init", "sim_destroy", "sim_get_info", "sim_lambda_offsets", "sim_step", "rollout",
-               "rollout_grad", "rollout_grad_noalloc", "sim_time_buckets", "sim_env_buckets", "sim_step_graph", "sim_graph_launch", "sim_graph_destroy", "sim_set_teams",
+               "rollout_grad", "rollout_grad_noalloc", "rollout_keep", "rollout_grad_kept", "sim_time_buckets",
+               "sim_env_buckets", "sim_step_graph", "sim_graph_launch", "sim_graph_destroy", "sim_set_teams",
                "wsn_to_bf16", "wsn_forward", "wsn_loss_grad", "wsn_adam", "rollout_solve", "sim_adam"):
         getattr(lib, fn).restype = C.c_int
     if lib.sim_abi_version() != ABI_VERSION:
@@ -199,7 +202,7 @@ EXPORTED = ["sim_abi_version", "sim_last_error", "sim_init", "sim_destroy", "sim
             "sim_step_graph", "sim_graph_launch", "sim_graph_destroy", "sim_tune", "sim_get_teams",
             "sim_set_teams", "wsn_to_bf16", "wsn_forward", "wsn_workspace_bytes", "wsn_loss_grad", "wsn_adam",
             "rollout_solve", "sim_adam", "sim_time_grad", "rollout_grad_noalloc", "sim_time_buckets",
-            "sim_env_buckets"]
+            "sim_env_buckets", "rollout_keep", "rollout_grad_kept"]
 
 # bytes of the scratch rollout_grad_noalloc uses (SIM_NOALLOC_SCRATCH_BYTES)
 NOALLOC_SCRATCH_BYTES = 64 << 20
@@ -275,17 +278,25 @@ class Simulator:
     def _f32(self, n):
         return self.torch.zeros(max(int(n), 1), dtype=self.torch.float32, device="cuda")
 
-    def rollout(self, x0, u, want_ckpt=True, want_final=True):
-        """x0 [18,B] and u [T_max,J] CUDA float32 tensors."""
+    def rollout(self, x0, u, want_ckpt=True, want_final=True, keep=None):
+        """x0 [18,B] and u [T_max,J] CUDA float32 tensors.  keep: a workspace
+        (trajectory mode) into which the rollout also writes every step's
+        saved working set (rollout_keep), for rollout_grad(kept=...)."""
         t = self.torch
         E = self.info.n_envs
         out = dict(loss=self._f32(E), flags=t.zeros(max(E, 1), dtype=t.int32, device="cuda"))
         out["x_final"] = self._f32(18 * self.info.n_bodies).view(18, -1) if want_final else None
         out["lam_final"] = self._f32(self.info.lam_size) if want_final else None
         out["ckpt"] = self._f32(self.info.ckpt_floats) if want_ckpt else None
-        st = self.lib.rollout(self.h, _ptr(x0), _ptr(u), _ptr(out["loss"]), _ptr(out["x_final"]),
-                              _ptr(out["lam_final"]), _ptr(out["ckpt"]), _ptr(out["flags"]), self._stream())
-        _check(self.lib, st, "rollout")
+        if keep is not None:
+            st = self.lib.rollout_keep(self.h, _ptr(x0), _ptr(u), _ptr(out["loss"]), _ptr(out["x_final"]),
+                                       _ptr(out["lam_final"]), _ptr(out["ckpt"]), _ptr(out["flags"]), _ptr(keep),
+                                       keep.numel() * 4, self._stream())
+            _check(self.lib, st, "rollout_keep")
+        else:
+            st = self.lib.rollout(self.h, _ptr(x0), _ptr(u), _ptr(out["loss"]), _ptr(out["x_final"]),
+                                  _ptr(out["lam_final"]), _ptr(out["ckpt"]), _ptr(out["flags"]), self._stream())
+            _check(self.lib, st, "rollout")
         out["loss"] = out["loss"][:E]
         return out
 
@@ -317,12 +328,16 @@ class Simulator:
     def workspace(self):
         return self.torch.empty(int(self.info.workspace_bytes) // 4 + 1, dtype=self.torch.float32, device="cuda")
 
-    def rollout_grad(self, x0, u, ckpt, dloss, workspace=None, no_alloc=False):
+    def rollout_grad(self, x0, u, ckpt, dloss, workspace=None, no_alloc=False, kept=None):
         """Reverse mode (rollout_grad), or with no_alloc the allocation-free
         entry point (rollout_grad_noalloc, the library's own scratch as the
-        workspace).  The output tensors are allocated here either way."""
+        workspace), or with kept the workspace a rollout(keep=...) filled
+        (rollout_grad_kept, no recompute).  The output tensors are allocated
+        here either way."""
         E, B, J = self.info.n_envs, self.info.n_bodies, self.info.n_joints
-        ws = None if no_alloc else (workspace if workspace is not None else self.workspace())
+        ws = None
+        if not no_alloc and kept is None:
+            ws = workspace if workspace is not None else self.workspace()
         nu = self.info.n_params if self.info.n_params else self.w.T_max * J
         g = dict(g_x0=self._f32(18 * B).view(18, -1), g_u=self._f32(nu),
                  g_inv_mass=self._f32(B), g_inv_inertia=self._f32(3 * B), g_mu=self._f32(E), g_damping=self._f32(J),
@@ -330,7 +345,11 @@ class Simulator:
                  flags=self.torch.zeros(max(E, 1), dtype=self.torch.int32, device="cuda"))
         outs = [_ptr(g[k]) for k in ("g_x0", "g_u", "g_inv_mass", "g_inv_inertia", "g_mu", "g_damping",
                                      "g_anchor_p", "g_anchor_c")]
-        if no_alloc:
+        if kept is not None:
+            st = self.lib.rollout_grad_kept(self.h, _ptr(x0), _ptr(u), _ptr(dloss), *outs, _ptr(kept),
+                                            kept.numel() * 4, _ptr(g["flags"]), self._stream())
+            _check(self.lib, st, "rollout_grad_kept")
+        elif no_alloc:
             st = self.lib.rollout_grad_noalloc(self.h, _ptr(x0), _ptr(u), _ptr(ckpt), _ptr(dloss), *outs,
                                                _ptr(g["flags"]), self._stream())
             _check(self.lib, st, "rollout_grad_noalloc")

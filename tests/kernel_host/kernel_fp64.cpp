@@ -35,6 +35,10 @@ struct TeamHost {
 }  // namespace
 extern "C" {
 void kh_set_ring(int on) { g_force_ring = on; }
+// 1: in trajectory mode the rollout keeps the working sets (rollout_keep) and
+// the reverse reads them without a recompute (rollout_grad_kept)
+static int g_keep = 0;
+void kh_set_keep(int on) { g_keep = on; }
 int kh_sizes(const sim_model_desc* d, long long* out) {
   Host h;
   if (!make(d, h)) return -1;
@@ -59,13 +63,16 @@ int kh_rollout_grad(const sim_model_desc* d, const double* x0, const double* u, 
     h.M.W = u;
     h.M.tape = tape.data();
   }
-  RolloutArgs ra{x0, u, loss, xf, lf.data(), ckpt.data(), nullptr, nullptr, nullptr, RecArgs{nullptr, 0, nullptr, 0}};
+  const bool keep = g_keep && h.M.dump == DUMP_TRAJECTORY;
+  RolloutArgs ra{x0, u, loss, xf, lf.data(), ckpt.data(), nullptr, nullptr, nullptr, RecArgs{nullptr, 0, nullptr, 0},
+                 keep ? seg.data() : nullptr};
   GradArgs ga{x0, u, ckpt.data(), dloss, gx0, gu, gm, gI, gmu, gd, gap, gac, seg.data(), nullptr};
   for (int ie = 0; ie < d->n_envs; ++ie) {
     std::vector<double> lds(h.P.adj_of[ie] + 16);
     Env E = make_env(h.M, ie, lds.data(), h.M.n_iters, false);
-    env_rollout(tm, h.M, E, true, ra);
-    if (h.M.dump == DUMP_TRAJECTORY) {
+    if (keep) env_rollout_keep(tm, h.M, E, true, ra);
+    else env_rollout(tm, h.M, E, true, ra);
+    if (h.M.dump == DUMP_TRAJECTORY && !keep) {
       // every segment recomputed on its own from its checkpoint (last first:
       // the order must not matter)
       const int K = h.M.ckpt_every, nseg = (d->T_env[ie] + K - 1) / K;

@@ -322,3 +322,26 @@ def test_history_ring_gives_the_same_bits(maker):
         lib.kh_set_ring(0)
     for k in a:
         np.testing.assert_array_equal(a[k], b[k], err_msg=k)
+
+
+@pytest.mark.parametrize("maker", [
+    lambda: W.planar_arms(n_envs=4, T=130),
+    lambda: W.uneven_chains(n_envs=6, T=110, seed_salt=2),
+    lambda: W.quadruped(n_envs=3, T_min=20, T_max=30, mlp_w=W.mlp_init(zero_output=False, out_scale=0.3)),
+    lambda: W.servo_chains(4, 60),
+])
+def test_rollout_keeping_working_sets_gives_the_same_bits(maker):
+    # a rollout that writes every step's saved working set as it goes, then the
+    # reverse without a recompute, equals the rollout and the reverse that
+    # recomputes them from the checkpoints (trajectory mode)
+    w = _store(maker(), "trajectory")
+    lib = _load()
+    lib.kh_set_keep(0)
+    a = host_fp64(w)
+    lib.kh_set_keep(1)
+    try:
+        b = host_fp64(w)
+    finally:
+        lib.kh_set_keep(0)
+    for k in a:
+        np.testing.assert_array_equal(a[k], b[k], err_msg=k)
