@@ -18,7 +18,10 @@ the profiler's output):
 
 The summary (profiles/traffic_<workload>.json) holds the bytes per launch of
 k_rollout_grad and a hash of the kernel sources it was measured with; the
-benchmark reports it only while the sources are unchanged.
+benchmark reports it only while the sources are unchanged.  With --buckets n
+(a workload whose envs run in n size buckets, one reverse kernel launch each
+per call, launched in bucket order) it also holds the bytes of each bucket's
+launch.
 """
 from __future__ import annotations
 
@@ -72,6 +75,25 @@ def read_counters(d, counter):
     return out
 
 
+def read_dispatches(d, counter):
+    """[(dispatch id, kernel name, value)] in dispatch order."""
+    out = []
+    for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+        with open(f) as fh:
+            for row in csv.DictReader(fh):
+                if row.get("Counter_Name") == counter:
+                    out.append((int(row["Dispatch_Id"]), row["Kernel_Name"], float(row["Counter_Value"])))
+    return sorted(out)
+
+
+def by_bucket(d, counter, kernel, n_b):
+    """Mean value of each bucket's launches of `kernel` (launch j is bucket j mod n_b)."""
+    v = [x for _, k, x in read_dispatches(d, counter) if kernel in k]
+    if not v or len(v) % n_b:
+        raise ValueError(f"{len(v)} dispatches of {kernel} do not split into {n_b} buckets")
+    return [sum(v[i::n_b]) / len(v[i::n_b]) for i in range(n_b)]
+
+
 def per_dispatch(vals, match):
     ks = [k for k in vals if match(k)]
     if not ks:
@@ -80,7 +102,7 @@ def per_dispatch(vals, match):
     return sum(v) / len(v), len(v), ks
 
 
-def summarize(workload, d, kernel="k_rollout_grad"):
+def summarize(workload, d, kernel="k_rollout_grad", buckets=None):
     expect_kib = COPY_MIB * 1024.0
     is_copy = lambda k: "copy" in k.lower() or "elementwise" in k.lower()   # noqa: E731
     cf, ncf, _ = per_dispatch(read_counters(os.path.join(d, "pmc_copy_f"), "FETCH_SIZE"), is_copy)
@@ -97,8 +119,12 @@ def summarize(workload, d, kernel="k_rollout_grad"):
                bytes_per_launch=(kf / sf + kw / sw) * 1024.0,
                fetch_bytes_per_launch=kf / sf * 1024.0, write_bytes_per_launch=kw / sw * 1024.0,
                kernel_source_hash=source_hash())
+    if buckets:
+        bf = by_bucket(os.path.join(d, f"pmc_{workload}_f"), "FETCH_SIZE", kernel, buckets)
+        bw = by_bucket(os.path.join(d, f"pmc_{workload}_w"), "WRITE_SIZE", kernel, buckets)
+        out["bytes_per_launch_by_bucket"] = [(f / sf + w / sw) * 1024.0 for f, w in zip(bf, bw)]
     # the other kernels of the gradient and the forward, when the run has them
-    for other in ("k_recompute", "k_rollout<"):
+    for other in ("k_recompute", "k_rollout<", "k_rollout_keep"):
         try:
             of, _, _ = per_dispatch(read_counters(os.path.join(d, f"pmc_{workload}_f"), "FETCH_SIZE"),
                                     lambda k: other in k)
@@ -116,8 +142,10 @@ def summarize(workload, d, kernel="k_rollout_grad"):
     return out
 
 
-def load(workload):
-    """Bytes per launch, or None when missing or measured on other kernel sources."""
+def load(workload, bucket=None, all_buckets=False):
+    """Bytes per launch (of `bucket`'s launch, or with all_buckets the sum
+    over the buckets' launches of one call, where measured by bucket), or
+    None when missing or measured on other kernel sources."""
     path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
     if not os.path.exists(path):
         return None
@@ -127,6 +155,11 @@ def load(workload):
         return None
     if t.get("kernel_source_hash") != source_hash():
         return None
+    b = t.get("bytes_per_launch_by_bucket")
+    if b and all_buckets:
+        return float(sum(b))
+    if b and bucket is not None:
+        return b[bucket] if 0 <= bucket < len(b) else None
     return t.get("bytes_per_launch")
 
 
@@ -135,13 +168,14 @@ if __name__ == "__main__":
     ap.add_argument("cmd", choices=["copy", "summarize", "hash"])
     ap.add_argument("--workload", default="arms")
     ap.add_argument("--dir", help="directory holding the profiler's pmc_* output folders")
+    ap.add_argument("--buckets", type=int, default=None, help="size buckets of the workload (one launch each per call)")
     a = ap.parse_args()
     if a.cmd == "copy":
         copy_main()
     elif a.cmd == "summarize":
         if not a.dir:
             ap.error("summarize needs --dir")
-        summarize(a.workload, a.dir)
+        summarize(a.workload, a.dir, buckets=a.buckets)
     else:
         print(source_hash())
     sys.exit(0)
