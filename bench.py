@@ -11,10 +11,11 @@ x 1000 steps, `--workload quadruped` the 1024 legged robots with an MLP
 controller.
 
 Printed: one JSON line with the throughput, a roofline object for the
-dominant kernel (the size bucket whose reverse sweep kernel takes longest,
-timed by events the library records around each bucket's launch on its own
-stream), a gradient check of the timed launch's own gradients against the
-FP64 oracle, and the oracle's own CPU throughput on a bounded sample.  The
+reverse sweep kernel of one call (one launch per size bucket, all running at
+once; timed by events the library records around them, and each bucket's
+launch on its own stream), a gradient check of the timed launch's own
+gradients against the FP64 oracle, and the oracle's own CPU throughput on a
+bounded sample.  The
 oracle runs only in the CPU-baseline leg: its timed full-horizon run over the
 sampled envs is also the reference of the gradient check.
 """
@@ -32,6 +33,13 @@ import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
+
+# The size buckets of an uneven workload run at once, one stream each.  HIP
+# maps streams onto GPU_MAX_HW_QUEUES hardware queues (4 unless set), and the
+# kernels of streams that share a queue run one after another: with 17
+# buckets, 4 queues serialise them into 4 chains.  Unless the caller set it,
+# give every bucket a queue of its own (read once, when HIP starts).
+os.environ.setdefault("GPU_MAX_HW_QUEUES", "32")
 
 METRIC = "fwd+adjoint env-steps/s at grad rel-err<=1e-3 vs FP64 oracle; % HBM roofline"
 HBM_PEAK_GBS = 8000.0

@@ -609,14 +609,17 @@ SHD void build_joint(const DevModel& M, const Env& E, int j, int s) {
   if (ha) { ra = mv(Ba + BR, Pa); Pa = ld3(Ba + BP) + ra; }
   const f3 err = (ld3(Bb + BP) + rb) - Pa;
   const float kb = M.beta / M.dt;
-  const float ev[3] = {err.x, err.y, err.z};
   f3 na = ld3(C + JXP), ua = ld3(C + JUP);
   f3 t2 = cross(na, ua);
   if (ha) { na = mv(Ba + BR, na); ua = mv(Ba + BR, ua); t2 = mv(Ba + BR, t2); }
   const f3 nbw = mv(Bb + BR, ld3(C + JXC));
   const f3 ax = cross(na, nbw);
   const float* w0 = E.ws() + E.jr * j;
-  for (int q = 0; q < E.jr; ++q) {
+  // (unrolled: the row index is a constant in each copy, so nothing indexed
+  // by it leaves the registers; the sixth row only with a servo)
+#pragma unroll
+  for (int q = 0; q < 6; ++q) {
+    if (q == 5 && E.jr != 6) break;
     f3 jl, ja, jb;
     float bias;
     float clip = 0.f;
@@ -637,7 +640,7 @@ SHD void build_joint(const DevModel& M, const Env& E, int j, int s) {
       jl = e;
       ja = cross(e, ra);
       jb = cross(rb, e);
-      bias = kb * ev[q];
+      bias = kb * (q == 0 ? err.x : (q == 1 ? err.y : err.z));
     } else {
       const f3 tk = q == 3 ? ua : t2;
       jl = mk3(0.f, 0.f, 0.f);
@@ -2345,7 +2348,9 @@ SHD void hinge_warm_rev(const Team& tm, const DevModel& M, const Env& E, int s, 
   // the two lanes' reads precede both writes, as in a wave's lockstep.
   if (NS == 2 || sd.sd[0] == 1) {
     float* wA = E.wsA() + E.store_of(code);
-    for (int q = 0; q < E.jr; ++q) wA[q] += M.warm * l0b[q];
+#pragma unroll
+    for (int q = 0; q < 6; ++q)
+      if (q < 5 || E.jr == 6) wA[q] += M.warm * l0b[q];
   }
   for (int i = 0; i < NS; ++i) E.bodyA(sd.bd[i])[AIM] += imx[i];
 }
@@ -2500,7 +2505,10 @@ SHD void a_joint(const Team& tm, const DevModel& M, const Env& E, int j, int s) 
     imx[i] = 0.f;
     for (int k = 0; k < 9; ++k) O[i][k] = 0.f;
   }
-  for (int q = 0; q < E.jr; ++q) {
+  // (unrolled: qj and qbias stay in registers; the sixth row only with a servo)
+#pragma unroll
+  for (int q = 0; q < 6; ++q) {
+    if (q == 5 && E.jr != 6) break;
     const float* r = E.row(s + q);
     const float* qa = E.rowA(s + q);
     const float qm = qa[QM];
@@ -2546,7 +2554,9 @@ SHD void a_joint(const Team& tm, const DevModel& M, const Env& E, int j, int s) 
   // (index 2: a servo's motor row, J = (-na, na))
   f3 qjb[3], qja[3];
   const int nq = E.jr == 6 ? 3 : 2;
-  for (int q = 0; q < nq; ++q) {
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    if (q == 2 && nq != 3) break;
     if (NS == 2) {
       qjb[q] = qj[0][3 + q];
       qja[q] = qj[NS - 1][3 + q];
