@@ -248,6 +248,9 @@ def main():
     ap.add_argument("--workload", default="chains", choices=["arms", "chains", "quadruped"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
+    ap.add_argument("--no-keep", action="store_true",
+                    help="in trajectory mode, recompute the working sets from the checkpoints instead of keeping "
+                         "them in the rollout")
     ap.add_argument("--grad-mem-gib", type=float, default=None,
                     help="memory for the reverse sweep's saved working sets (default: what the device has free "
                          "less a 12 GiB margin)")
@@ -278,7 +281,7 @@ def main():
     env_steps = float(np.sum(w.T_env))
     # trajectory mode: the rollout keeps every step's working set in the
     # workspace and the reverse reads them without recomputing them
-    keep = ws_buf if sim.info.grad_store == 3 else None
+    keep = ws_buf if sim.info.grad_store == 3 and not args.no_keep else None
 
     for _ in range(args.warmup):
         r = sim.rollout(x0, u, want_ckpt=True, want_final=False, keep=keep)

@@ -407,11 +407,13 @@ sim_status sim_init(const sim_model_desc* d, sim_handle* out) {
     // not by how many envs share the wave, so what counts is how many envs a
     // CU holds at once in the reverse sweep, the costlier pass: envs per wave
     // times the waves whose tiles fit the CU's LDS, at most one per SIMD (the
-    // reverse kernel's registers allow no more).  Of the widths the topology
-    // allows whose tile fits, the narrowest that holds the most envs.
+    // reverse kernel's registers allow no more).  More envs per CU pay only
+    // while the model's envs do not all fit on the device at once: the
+    // choice minimises the rounds ceil(E / (CUs x envs per CU)), then takes
+    // no ring over a ring and the narrowest width (the ring costs a read per
+    // sweep and a wider team longer steps).
     // The reverse of saved working sets may keep only a ring of the impulse
-    // history in LDS (the rest is read from the working set sweep by sweep):
-    // taken where it lets a CU hold more envs.
+    // history in LDS (the rest is read from the working set sweep by sweep).
     const int team0 = std::min(64, std::max(team_of[e], d->min_team));
     int team = -1, ring = 0;
     long long best = 0;
@@ -422,7 +424,8 @@ sim_status sim_init(const sim_model_desc* d, sim_handle* out) {
         const long long waves =
             std::min<long long>(kSimdsPerCu, kLdsPerCu / std::max<long long>(1, adj_bytes(M, t, fa)));
         const long long envs_cu = (64 / t) * std::max<long long>(1, waves);
-        if (envs_cu > best) { best = envs_cu; team = t; ring = r; }
+        const long long rounds = ((long long)E + (long long)h->n_cu * envs_cu - 1) / ((long long)h->n_cu * envs_cu);
+        if (team < 0 || rounds < best) { best = rounds; team = t; ring = r; }
       }
     }
     if (ring) {
