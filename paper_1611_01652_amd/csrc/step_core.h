@@ -179,7 +179,7 @@ enum { QJA = 0, QWA = 4, QJB = 8, QM = 11, QWB = 12, QB = 15, QJL = 16, QL = 19,
 struct alignas(16) i4 { int x, y, z, w; };
 
 struct Lay {
-  int body, jc, gs, topo, ws, rows, act_cnt, act_slot, act_code, live, plan, vis, misc, mlp, vsave;  // forward
+  int body, jc, gs, topo, ws, rows, act_cnt, act_slot, act_code, live, plan, vis, misc, grp, mlp, vsave;  // forward
   int bodyA, rowsA, hist, wsA, jA, mlpA;                                     // adjoint
   int hring;   // 0: the sweep history of the step in LDS; HRING: a ring of sweeps (the rest in global memory)
   int total_fwd, total;
@@ -215,10 +215,11 @@ SHD Lay make_lay(int nb, int nj, int G, int P, int ncol, int ncand, int nslot, i
   L.act_cnt = o; o += align4(ncol);
   L.act_slot = o; o += align4(ncand);
   L.act_code = o; o += align4(ncand);
-  L.live = o; o += align4(ncol + 2);
+  L.live = o; o += align4(ncol + 3);
   L.plan = o; o += 4 * ncol;
   L.vis = o; o += 4 * ncand;
   L.misc = o; o += MISC_N;
+  L.grp = o; o += align4(nb + 1);
   L.mlp = o; o += align4(mlp_f);
   L.vsave = o; o += align4(vs_f);
   L.total_fwd = o;
@@ -280,12 +281,17 @@ struct Env {
   SHD int* act_slot() const { return (int*)(L + lay.act_slot); }
   SHD int* act_code() const { return (int*)(L + lay.act_code); }
   // [0] colours with an active constraint this step, [1] joint colours (the
-  // first colours of the canonical order), [2..] the active colours in order
+  // first colours of the canonical order), [2..2+ncol) the active colours in
+  // order, [2+ncol] the entries of the sweep plan
   SHD int* live() const { return (int*)(L + lay.live); }
-  // sweep plan of the step (built with the live list): plan()[ci] for live
-  // colour ci, vis()[i] parallel to act_slot / act_code
+  // sweep plan of the step (built with the live list): plan()[g] = (start in
+  // vis, count, 1 for hinges, -) for its g-th visit; vis() the step's active
+  // constraints, visit by visit
   SHD i4* plan() const { return (i4*)(L + lay.plan); }
   SHD i4* vis() const { return (i4*)(L + lay.vis); }
+  // (row set-up) the plan entry that last took each body, the world slot's
+  // included
+  SHD int* grp() const { return (int*)(L + lay.grp); }
   SHD float* misc() const { return L + lay.misc; }
   SHD float* jA() const { return L + lay.jA; }
   SHD float* mlp() const { return L + lay.mlp; }
@@ -350,6 +356,7 @@ SHD Env make_env(const DevModel& M, int ie, float* lds, int n_iters, bool adj) {
 // the sweeps visit only these, in canonical order, which changes nothing but
 // the number of (empty) colour passes.
 SHD int n_live(const Env& E, bool act) { return act ? E.live()[0] : 0; }
+SHD int n_plan(const Env& E, bool act) { return act ? E.live()[2 + E.ncol] : 0; }
 SHD int live_col(const Env& E, int i) { return E.live()[2 + i]; }
 SHD int n_joint_cols(const Env& E, bool act) { return act ? E.live()[1] : 0; }
 
@@ -389,6 +396,7 @@ SHD void load_env_static(const Team& tm, const DevModel& M, const Env& E) {
       ++m;
     E.live()[0] = 0;
     E.live()[1] = m;
+    E.live()[2 + E.ncol] = 0;
     E.misc()[MISC_MU] = E.gcst[cst_env(E)];
     E.misc()[MISC_REST] = E.gcst[cst_env(E) + 1];
     E.misc()[MISC_LOSS] = 0.f;
@@ -776,18 +784,34 @@ SHD void build_contact(const DevModel& M, const Env& E, int code, int s, const C
 // F4: per colour, test candidates, compact the active ones, build rows.
 // Inactive contact candidates have their stored impulses cleared.  A colour
 // holds only joints or only contacts.
+//
+// The sweep plan lists the step's visits: each joint colour with an active
+// constraint, and runs of consecutive live contact colours merged into one
+// visit where no constraint of a later colour touches a body that an earlier
+// colour of the run touches (the world slot aside).  Such constraints commute
+// with everything before them in the run (each update reads and writes only
+// its own row and its two bodies), so a merged visit gives the same bits as
+// the colours one after another, with fewer visits per sweep: a long chain's
+// pair contacts fall into many colours with one or two active pairs each.
+// vis() holds the active constraints contiguously, visit by visit.
 template <class Team>
 SHD void f_rows(const Team& tm, const DevModel& M, const Env& E, bool act) {
   // Joint rows depend only on the step's body state, so all joints are built
   // at once, lanes over joints; the colour loop below lists them.
   const int nj = act ? E.nj : 0;
   for (int j = tm.tl; j < nj; j += tm.ts) build_joint(M, E, j, E.jr * j);
-  int ncon = 0;  // contacts placed so far (team-uniform)
+  for (int b = tm.tl; b <= (act ? E.nb : -1); b += tm.ts) E.grp()[b] = -2;
+  tm.sync();
+  int ncon = 0;                    // contacts placed so far (team-uniform)
+  int voff = 0;                    // entries of vis() so far
+  int np = 0;                      // plan entries opened so far
+  int gstart = 0, gcnt = 0, gkind = -1;   // the open plan entry
   for (int c = 0; tm.any(c < E.ncol && act); ++c) {
     int lo = 0, hi = 0;
     if (act && c < E.ncol) { lo = E.colstart(c); hi = E.colstart(c + 1); }
     const bool jcol = hi > lo && cand_kind(E.cand(lo)) == K_JOINT;
     int cnt = 0;
+    bool clash = false;   // this lane's constraints touch a body of the open entry
     for (int base = lo; tm.any(base < hi); base += tm.ts) {
       const int i = base + tm.tl;
       const bool live = i < hi;
@@ -824,21 +848,41 @@ SHD void f_rows(const Team& tm, const DevModel& M, const Env& E, bool act) {
         }
         E.act_slot()[li] = s;
         const RowB rb = cand_bodies(E, code);
-        E.vis()[li] = i4{s, rb.a >= 0 ? rb.a : E.nb, rb.b, code};
+        E.vis()[voff + cnt + pos] = i4{s, rb.a >= 0 ? rb.a : E.nb, rb.b, code};
+        if (!jcol) clash = clash || (rb.a >= 0 && E.grp()[rb.a] == np - 1) || E.grp()[rb.b] == np - 1;
       }
       cnt += total;
       if (!jcol) ncon += total;
     }
     if (act && c < E.ncol) E.act_cnt()[c] = cnt;
+    const bool merge = !tm.team_any(clash) && !jcol && gkind == 0;
+    if (cnt > 0) {
+      if (!merge) {
+        if (gcnt > 0 && tm.tl == 0) E.plan()[np - 1] = i4{gstart, gcnt, gkind, 0};
+        ++np;
+        gstart = voff;
+        gcnt = 0;
+        gkind = jcol ? 1 : 0;
+      }
+      gcnt += cnt;
+      // the open entry's bodies: this colour's constraints touch distinct
+      // bodies (the world slot aside, which is not marked)
+      if (!jcol)
+        for (int k = tm.tl; k < cnt; k += tm.ts) {
+          const i4 v = E.vis()[voff + k];
+          E.grp()[v.z] = np - 1;
+          if (v.y < E.nb) E.grp()[v.y] = np - 1;
+        }
+      voff += cnt;
+    }
+    tm.sync();
   }
-  tm.sync();
   if (act && tm.tl == 0) {
+    if (gcnt > 0) E.plan()[np - 1] = i4{gstart, gcnt, gkind, 0};
+    E.live()[2 + E.ncol] = np;
     int m = 0;
     for (int c = 0; c < E.ncol; ++c)
-      if (E.act_cnt()[c] > 0) {
-        E.plan()[m] = i4{E.colstart(c), E.act_cnt()[c], cand_kind(E.cand(E.colstart(c))) == K_JOINT ? 1 : 0, 0};
-        E.live()[2 + m++] = c;
-      }
+      if (E.act_cnt()[c] > 0) E.live()[2 + m++] = c;
     E.live()[0] = m;
   }
   tm.sync();
@@ -1170,7 +1214,7 @@ SHD void hinge_warm(const Team& tm, const Env& E, int s, int a, int b) {
 // colour is taken by lane pairs when the team has two lanes, as in the sweeps.
 template <class Team>
 SHD void f_warm(const Team& tm, const Env& E, bool act) {
-  const int nl = n_live(E, act);
+  const int nl = n_plan(E, act);
   for (int ci = 0; tm.any(ci < nl); ++ci) {
     i4 pl{0, 0, 0, 0};
     if (ci < nl) pl = E.plan()[ci];
@@ -1244,7 +1288,7 @@ template <class Team>
 SHD void f_pgs(const Team& tm, const DevModel& M, const Env& E, bool act, float* hist) {
   const float mu = E.misc()[MISC_MU];
   SweepCursor<1> sw;
-  sw.start(tm, E, M.n_iters, n_live(E, act));
+  sw.start(tm, E, M.n_iters, n_plan(E, act));
   while (tm.any(sw.left > 0)) {
     i4 vn, p2;
     sw.prefetch(tm, E, vn, p2);
@@ -1295,7 +1339,7 @@ SHD void f_integrate(const Team& tm, const DevModel& M, const Env& E, bool act) 
 // F8: store impulses for the next warm start.
 template <class Team>
 SHD void f_store(const Team& tm, const Env& E, bool act) {
-  const int nl = n_live(E, act);
+  const int nl = n_plan(E, act);
   for (int ci = 0; tm.any(ci < nl); ++ci) {
     i4 pl{0, 0, 0, 0};
     if (ci < nl) pl = E.plan()[ci];
@@ -1813,7 +1857,7 @@ SHD void a_decay(const Team& tm, const DevModel& M, const Env& E, bool act) {
 // constants (zeros): their adjoint is dropped here.
 template <class Team>
 SHD void a_store(const Team& tm, const Env& E, bool act) {
-  const int nl = n_live(E, act);
+  const int nl = n_plan(E, act);
   for (int ci = 0; tm.any(ci < nl); ++ci) {
     i4 pl{0, 0, 0, 0};
     if (ci < nl) pl = E.plan()[ci];
@@ -2278,7 +2322,7 @@ SHD void a_pgs(const Team& tm, const DevModel& M, const Env& E, bool act, const 
   }
   tm.sync();
   SweepCursor<-1> sw;
-  sw.start(tm, E, M.n_iters, n_live(E, act));
+  sw.start(tm, E, M.n_iters, n_plan(E, act));
   while (tm.any(sw.left > 0)) {
     i4 vn, p2;
     sw.prefetch(tm, E, vn, p2);
@@ -2358,7 +2402,7 @@ SHD void hinge_warm_rev(const Team& tm, const DevModel& M, const Env& E, int s, 
 // B5: adjoint of the warm start v += W lambda0 and of lambda0 = warm * store.
 template <class Team>
 SHD void a_warm(const Team& tm, const DevModel& M, const Env& E, bool act) {
-  const int nl = n_live(E, act);
+  const int nl = n_plan(E, act);
   for (int ci = nl - 1; tm.any(ci >= 0); --ci) {
     i4 pl{0, 0, 0, 0};
     if (ci >= 0) pl = E.plan()[ci];
@@ -2720,7 +2764,7 @@ SHD void a_contact(const DevModel& M, const Env& E, int code, int s) {
 // B4: adjoint of the row set-up, colour by colour (disjoint bodies).
 template <class Team>
 SHD void a_rows(const Team& tm, const DevModel& M, const Env& E, bool act) {
-  const int nl = n_live(E, act);
+  const int nl = n_plan(E, act);
   for (int ci = nl - 1; tm.any(ci >= 0); --ci) {
     i4 pl{0, 0, 0, 0};
     if (ci >= 0) pl = E.plan()[ci];
