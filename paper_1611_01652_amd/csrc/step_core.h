@@ -995,6 +995,19 @@ SHD void vr_load_ab(VR& V, const Env& E, int a, int b) {
   V.vb[0] = q0.x; V.vb[1] = q0.y; V.vb[2] = q0.z; V.wb[0] = q0.w; V.wb[1] = Bb[4]; V.wb[2] = Bb[5];
   V.va[0] = p0.x; V.va[1] = p0.y; V.va[2] = p0.z; V.wa[0] = p0.w; V.wa[1] = Ba[4]; V.wa[2] = Ba[5];
 }
+// Body b alone (a ground contact: body a is the world slot, whose velocity
+// is zero and stays zero).
+SHD void vr_load_b(VR& V, const Env& E, int b) {
+  const float* Bb = E.body(b) + BV;
+  const f4 q0 = ld4(Bb);
+  V.vb[0] = q0.x; V.vb[1] = q0.y; V.vb[2] = q0.z; V.wb[0] = q0.w; V.wb[1] = Bb[4]; V.wb[2] = Bb[5];
+  for (int k = 0; k < 3; ++k) { V.va[k] = 0.f; V.wa[k] = 0.f; }
+}
+SHD void vr_store_b(const VR& V, const Env& E, int b) {
+  float* Bb = E.body(b) + BV;
+  f4 q0; q0.x = V.vb[0]; q0.y = V.vb[1]; q0.z = V.vb[2]; q0.w = V.wb[0];
+  st4(Bb, q0); Bb[4] = V.wb[1]; Bb[5] = V.wb[2];
+}
 SHD void vr_store_ab(const VR& V, const Env& E, int a, int b) {
   float* Bb = E.body(b) + BV;
   float* Ba = E.body(a) + BV;
@@ -1246,15 +1259,19 @@ SHD void f_warm(const Team& tm, const Env& E, bool act) {
 }
 
 // One visit of a contact: normal row clamped at 0, then the friction disk.
+// HA = false: a ground contact (body a is the world slot), whose body-a terms
+// are zeros and are skipped (the same bits: x - 0 + 0 is x).
+template <bool HA = true>
 SHD void pgs_contact(const DevModel& M, const Env& E, int s, int a, int b, float mu, float* H,
                      float* rmax = nullptr) {
-  constexpr bool ha = true;
+  constexpr bool ha = HA;
   VR V;
-  vr_load_ab(V, E, a, b);
+  if constexpr (HA) vr_load_ab(V, E, a, b);
+  else vr_load_b(V, E, b);
   RR R[3];
   for (int q = 0; q < 3; ++q) rr_load(R[q], E.row(s + q));
   const float mt = E.row(s + 3)[XMT];
-  const float ima = E.body(a)[BIM], imb = E.body(b)[BIM];
+  const float ima = HA ? E.body(a)[BIM] : 0.f, imb = E.body(b)[BIM];
   {
     const float sv_ = rr_jv(R[0], V, ha) + R[0].bias + M.gamma * R[0].lam;
     const float lt = R[0].lam - R[0].m * sv_;
@@ -1278,7 +1295,8 @@ SHD void pgs_contact(const DevModel& M, const Env& E, int s, int a, int b, float
   E.row(s)[RL] = R[0].lam;
   E.row(s + 1)[RL] = n1;
   E.row(s + 2)[RL] = n2;
-  vr_store_ab(V, E, a, b);
+  if constexpr (HA) vr_store_ab(V, E, a, b);
+  else vr_store_b(V, E, b);
 }
 
 // F6: projected Gauss-Seidel sweeps.  With hist, the pre-projection impulse of
@@ -1298,7 +1316,10 @@ SHD void f_pgs(const Team& tm, const DevModel& M, const Env& E, bool act, float*
       const i4 v = sw.entry(tm, E, k);
       if (v.x < 0) continue;
       // a hinge colour is visited by lane pairs whenever the team has two lanes
-      if (cand_kind(v.w) != K_JOINT) pgs_contact(M, E, v.x, v.y, v.z, mu, H);
+      if (cand_kind(v.w) != K_JOINT) {
+        if (v.y == E.nb) pgs_contact<false>(M, E, v.x, v.y, v.z, mu, H);
+        else pgs_contact<true>(M, E, v.x, v.y, v.z, mu, H);
+      }
       else if (tm.ts >= 2) hinge_fwd<1>(tm, M, E, v.x, v.y, v.z, H);
       else hinge_fwd<2>(tm, M, E, v.x, v.y, v.z, H);
     }
@@ -1988,6 +2009,17 @@ SHD void vra_load_ab(VR& A, const Env& E, int a, int b) {
   A.vb[0] = q0.x; A.vb[1] = q0.y; A.vb[2] = q0.z; A.wb[0] = q0.w; A.wb[1] = Bb[4]; A.wb[2] = Bb[5];
   A.va[0] = p0.x; A.va[1] = p0.y; A.va[2] = p0.z; A.wa[0] = p0.w; A.wa[1] = Ba[4]; A.wa[2] = Ba[5];
 }
+SHD void vra_load_b(VR& A, const Env& E, int b) {
+  const float* Bb = E.bodyA(b) + AV;
+  const f4 q0 = ld4(Bb);
+  A.vb[0] = q0.x; A.vb[1] = q0.y; A.vb[2] = q0.z; A.wb[0] = q0.w; A.wb[1] = Bb[4]; A.wb[2] = Bb[5];
+  for (int k = 0; k < 3; ++k) { A.va[k] = 0.f; A.wa[k] = 0.f; }
+}
+SHD void vra_store_b(const VR& A, const Env& E, int b) {
+  float* Bb = E.bodyA(b) + AV;
+  f4 q0; q0.x = A.vb[0]; q0.y = A.vb[1]; q0.z = A.vb[2]; q0.w = A.wb[0];
+  st4(Bb, q0); Bb[4] = A.wb[1]; Bb[5] = A.wb[2];
+}
 SHD void vra_store_ab(const VR& A, const Env& E, int a, int b) {
   float* Bb = E.bodyA(b) + AV;
   float* Ba = E.bodyA(a) + AV;
@@ -2224,13 +2256,22 @@ SHD void hinge_rev(const Team& tm, const DevModel& M, const Env& E, int s, int a
   }
 }
 
-// Reverse of one contact visit: friction disk, then the normal row.
+// Reverse of one contact visit: friction disk, then the normal row.  HA =
+// false: a ground contact, body a's terms skipped (they go to the world
+// slot's velocity, zero, and its adjoint, a sink, and to the row's body-a
+// Jacobian adjoints, which a ground contact's set-up adjoint does not read).
+template <bool HA = true>
 SHD void rev_contact(const DevModel& M, const Env& E, int s, int a, int b, float mu, const float* H,
                      const float* Hp, float& gmu) {
-  constexpr bool ha = true;
+  constexpr bool ha = HA;
   VR V, A;
-  vr_load_ab(V, E, a, b);
-  vra_load_ab(A, E, a, b);
+  if constexpr (HA) {
+    vr_load_ab(V, E, a, b);
+    vra_load_ab(A, E, a, b);
+  } else {
+    vr_load_b(V, E, b);
+    vra_load_b(A, E, b);
+  }
   RR R1, R2;
   QR Q1, Q2;
   rr_load(R1, E.row(s + 1));
@@ -2239,7 +2280,7 @@ SHD void rev_contact(const DevModel& M, const Env& E, int s, int a, int b, float
   qr_load(Q2, E.rowA(s + 2));
   float* xa = E.rowA(s + 3);
   const float mt = E.row(s + 3)[XMT];
-  const float ima = E.body(a)[BIM], imb = E.body(b)[BIM];
+  const float ima = HA ? E.body(a)[BIM] : 0.f, imb = E.body(b)[BIM];
   float imA = 0.f, imB = 0.f;
   const float ltn = H[s], l1t = H[s + 1], l2t = H[s + 2];
   const float ln = fmaxf(ltn, 0.f);
@@ -2287,9 +2328,14 @@ SHD void rev_contact(const DevModel& M, const Env& E, int s, int a, int b, float
   Q0.l += lnb;
   rev_scalar(R0, Q0, V, A, ha, ima, imb, ltn, lpn, false, M.gamma, imA, imB);
   qr_store(Q0, E.rowA(s));
-  vr_store_ab(V, E, a, b);
-  vra_store_ab(A, E, a, b);
-  E.bodyA(a)[AIM] += imA;
+  if constexpr (HA) {
+    vr_store_ab(V, E, a, b);
+    vra_store_ab(A, E, a, b);
+    E.bodyA(a)[AIM] += imA;
+  } else {
+    vr_store_b(V, E, b);
+    vra_store_b(A, E, b);
+  }
   E.bodyA(b)[AIM] += imB;
 }
 
@@ -2335,7 +2381,10 @@ SHD void a_pgs(const Team& tm, const DevModel& M, const Env& E, bool act, const 
     for (int k = 0; k < nk; ++k) {
       const i4 v = sw.entry(tm, E, k);
       if (v.x < 0) continue;
-      if (cand_kind(v.w) != K_JOINT) rev_contact(M, E, v.x, v.y, v.z, mu, H, sw.it > 0 ? Hp : nullptr, gmu);
+      if (cand_kind(v.w) != K_JOINT) {
+        if (v.y == E.nb) rev_contact<false>(M, E, v.x, v.y, v.z, mu, H, sw.it > 0 ? Hp : nullptr, gmu);
+        else rev_contact<true>(M, E, v.x, v.y, v.z, mu, H, sw.it > 0 ? Hp : nullptr, gmu);
+      }
       else if (tm.ts >= 2) hinge_rev<1>(tm, M, E, v.x, v.y, v.z, H, Hp, sw.it == 0);
       else hinge_rev<2>(tm, M, E, v.x, v.y, v.z, H, Hp, sw.it == 0);
     }
