@@ -3,8 +3,11 @@
 A captured step sequence must reproduce the eager sim_step loop bit for bit
 on every replay (the graph holds only kernels: queue resets are fill
 kernels, not memsets), with the program's own eager work and
-synchronisations between replays.  Re-tiling by the autotuner must not change
-any result bit, since the sweep order does not depend on the team width.
+synchronisations between replays, and the eager loop matches the FP64
+oracle's steps.  rollout and rollout_grad (several buckets on forked
+streams) captured together in one graph by stream capture replay bit for bit
+too.  Re-tiling by the autotuner must not change any result bit, since the
+sweep order does not depend on the team width.
 """
 from __future__ import annotations
 
@@ -13,7 +16,8 @@ import sys
 import numpy as np
 import pytest
 
-from gpu_helpers import to_dev
+from gpu_helpers import STATE_TOL, state_errors, to_dev
+from oracle import Oracle
 from paper_1611_01652_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
@@ -69,6 +73,14 @@ def test_step_graph_matches_eager_steps_on_several_buckets():
     x0, u = to_dev(w)
     _say("case step graph, chains 160 envs x 12 steps, buckets", s.teams().tolist())
     _check_graph_replays(s, x0, u[:12].contiguous(), 0, 12)
+    # the eager steps (the graph's bits) against the oracle's
+    xe, _, _ = _eager_steps(s, x0, u[:12].contiguous(), torch.zeros(max(s.info.lam_size, 1), device="cuda"), 0, 12)
+    o = Oracle(w)
+    x, lam = np.asarray(w.x0, np.float64), np.zeros(o.lam_size)
+    for t in range(12):
+        x, lam = o.step(x, lam, w.u[t], t)
+    se = state_errors(w, xe.cpu().numpy().T.astype(np.float64), x)
+    assert (se <= STATE_TOL).all(), se.max()
     _say("case step graph, odd step count 5 from row 3")
     _check_graph_replays(s, x0, u[3:8].contiguous(), 3, 5)
     s.close()
@@ -88,6 +100,55 @@ def test_step_graph_with_controller_and_clock_offset():
     lam = torch.zeros(max(s.info.lam_size, 1), device="cuda")
     with pytest.raises(SimError):
         s.step_graph(5, xbuf, wt, lam, t0=38)     # t0 + n_steps > T_max
+    s.close()
+
+
+@pytest.mark.parametrize("keep", [False, True])
+def test_rollout_and_gradient_captured_in_one_graph(keep):
+    # one call of rollout (or rollout with kept working sets) and rollout_grad
+    # captured by torch's stream capture: every replay equals the eager calls
+    # bit for bit, with eager calls and synchronisations between replays
+    import torch
+    from paper_1611_01652_amd.sim import Simulator
+    w = W.uneven_chains(n_envs=96, T=40, seed_salt=24)
+    s = Simulator(w)
+    assert len(s.teams()) > 1, "want several buckets (forked streams inside the capture)"
+    assert s.info.grad_store == 3
+    x0, u = to_dev(w)
+    dl = torch.ones(w.n_envs, device="cuda")
+    ws = s.workspace()
+
+    def calls():
+        r = s.rollout(x0, u, keep=ws if keep else None)
+        g = s.rollout_grad(x0, u, r["ckpt"], dl, workspace=None if keep else ws, kept=ws if keep else None)
+        return [r["loss"], r["x_final"], r["ckpt"]] + [g[k] for k in sorted(g)]
+
+    ref = [t.clone() for t in calls()]
+    torch.cuda.synchronize()
+    _say("case captured rollout + rollout_grad, chains 96 envs x 40 steps, keep", keep)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        calls()   # warm-up on the capture's stream, as torch asks
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        outs = calls()
+    try:
+        for rep_ in range(3):
+            for t in outs:
+                t.fill_(float("nan") if t.is_floating_point() else -1)
+            graph.replay()
+            torch.cuda.synchronize()
+            for k, (a, b) in enumerate(zip(outs, ref)):
+                assert torch.equal(a, b), ("replay", rep_, k)
+            eager = calls()
+            torch.cuda.synchronize()
+            for a, b in zip(eager, ref):
+                assert torch.equal(a, b)
+    finally:
+        del graph
     s.close()
 
 
