@@ -54,9 +54,12 @@ def to_dev(w):
     return x0, u
 
 
-def gpu_run(w, grad=True, dloss=None, sim=None):
+def gpu_run(w, grad=True, dloss=None, sim=None, keep=False):
     """Rollout (and gradient) through the C ABI; a controller workload's
-    control input is its weights, and its dL/dW comes back as g_w."""
+    control input is its weights, and its dL/dW comes back as g_w.  keep (a
+    model in trajectory mode): the rollout keeps every step's working set in
+    the workspace and the gradient reverses from them (rollout_keep and
+    rollout_grad_kept), as the benchmark runs it."""
     import torch
     from paper_1611_01652_amd.sim import Simulator
     s = sim or Simulator(w)
@@ -64,7 +67,11 @@ def gpu_run(w, grad=True, dloss=None, sim=None):
     mlp = (getattr(w, "extra", None) or {}).get("mlp")
     if mlp is not None:
         u = torch.tensor(np.asarray(mlp["w"], np.float32), device="cuda")
-    r = s.rollout(x0, u)
+    ws = None
+    if keep:
+        assert s.info.grad_store == 3, "keeping the working sets needs trajectory mode"
+        ws = s.workspace()
+    r = s.rollout(x0, u, keep=ws)
     ck = r["ckpt"].cpu().numpy().astype(np.float64)
     stride = 18 * w.n_bodies + s.info.lam_size
     ck = ck[: s.info.n_ckpt * stride].reshape(s.info.n_ckpt, stride)[:, : 18 * w.n_bodies]
@@ -76,7 +83,7 @@ def gpu_run(w, grad=True, dloss=None, sim=None):
     if grad:
         dl = torch.ones(w.n_envs, device="cuda") if dloss is None else torch.tensor(dloss, dtype=torch.float32,
                                                                                      device="cuda")
-        g = s.rollout_grad(x0, u, r["ckpt"], dl)
+        g = s.rollout_grad(x0, u, r["ckpt"], dl, kept=ws)
         out["g_x0"] = g["g_x0"].cpu().numpy().T.astype(np.float64)
         out["g_w" if mlp is not None else "g_u"] = g["g_u"].cpu().numpy().astype(np.float64)
         out["g_inv_mass"] = g["g_inv_mass"].cpu().numpy().astype(np.float64)

@@ -55,12 +55,13 @@ def test_planar_arms_quarter_horizon_every_env():
 
 
 def test_planar_arms_full_size_sampled():
-    # the arm benchmark's launch; 16 evenly spaced envs by the per-env protocol
-    # (8 of them gradient-stable over the 1000 steps)
+    # the arm benchmark's launch (trajectory mode, the rollout keeping the
+    # working sets); 16 evenly spaced envs by the per-env protocol (12 of
+    # them gradient-stable over the 1000 steps)
     import bench
     w = W.planar_arms(n_envs=4096, T=1000)
     _say("case planar-arms 4096 x 1000 (the arm benchmark's launch), sampled")
-    got = gpu_run(w)
+    got = gpu_run(w, keep=True)
     sample = bench.stratified(w, 16)
     ws = w.subset(sample)
     _compare(ws, _sampled(got, w, sample), grad_frac=7 / 16, checkpoints=50)
@@ -95,18 +96,27 @@ def _sampled(got, w, sample):
 
 
 def test_uneven_chains_full_size_sampled():
-    # the benchmark's launch: 16384 chains x 500 steps in the mode the memory
-    # limit picks (segment: the reverse kernel recomputes each segment), all
-    # size buckets; 64 envs at evenly spaced quantiles of the body count are
-    # compared by the per-env protocol.  Over 500 steps the criterion yields
-    # 142 checkpoint comparisons and 4 gradient-stable envs of the 64.
+    # the benchmark's launch: 16384 chains x 500 steps with the benchmark's
+    # memory limit (the free device memory less 12 GiB), which gives
+    # trajectory mode, the rollout keeping every step's working set and the
+    # reverse reading them, all size buckets; 64 envs at evenly spaced
+    # quantiles of the body count are compared by the per-env protocol.  Over
+    # 500 steps the criterion yields 142 checkpoint comparisons and 4
+    # gradient-stable envs of the 64.
+    import torch
     import bench
     w = W.uneven_chains(n_envs=16384, T=500)
+    free, _ = torch.cuda.mem_get_info()
+    w.extra = dict(w.extra or {}, grad_mem_limit=int(max(1.0, free / 2**30 - 12.0) * 2**30))
     _say("case uneven-chains 16384 x 500 (full size, the benchmark's launch), sampled")
     from paper_1611_01652_amd.sim import Simulator
     s = Simulator(w)
-    assert s.info.grad_store == 2
-    got = gpu_run(w, sim=s)
+    try:
+        assert s.info.grad_store == 3
+        got = gpu_run(w, sim=s, keep=True)
+    finally:
+        s.close()
+        torch.cuda.empty_cache()
     assert (got["flags"] == 0).mean() > 0.99
     sample = bench.stratified(w, 64)
     ws = w.subset(sample)
