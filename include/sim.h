@@ -246,7 +246,13 @@ const char* sim_last_error(void);
 /* Validate the description, build per-env topology (contact candidates,
  * colour-major sweep order), size-bucket and tile the envs, and upload all
  * constants to the current device (synchronous).  On success *out owns the
- * device copies; release with sim_destroy. */
+ * device copies; release with sim_destroy.
+ * With several buckets, each call forks them onto streams of their own and
+ * joins them back to the caller's stream.  HIP maps streams onto
+ * GPU_MAX_HW_QUEUES hardware queues (4 unless the process sets it before HIP
+ * starts) and runs the kernels of streams that share a queue one after
+ * another: for the buckets to run at once, set it to at least the bucket
+ * count (sim_get_teams). */
 sim_status sim_init(const sim_model_desc* desc, sim_handle* out);
 sim_status sim_destroy(sim_handle h);
 sim_status sim_get_info(sim_handle h, sim_info* info);
