@@ -256,7 +256,7 @@ def main():
                          "less a 12 GiB margin)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
+        print(json.dumps({"error": "the benchmark runs on one GPU; --gpus must be 1 "
                                    "(sharding over GPUs is a design note, not implemented)",
                           "n_gpus": args.gpus}))
         sys.exit(2)

@@ -5,7 +5,7 @@ chain distribution solved to 1e-5 (tolerance mode, cap 1000 sweeps):
    every converged contact on 8192 training envs x 500 steps;
 2. train: the per-contact network on those records (BF16 matrix-core
    forward/backward, FP32 Adam, Huber loss on corrections);
-3. judge: on records of 1024 held-out envs, the network's start lies closer
+3. check: on records of 1024 held-out envs, the network's start lies closer
    to the converged impulses than the carried impulses do;
 4. evaluate: sweeps per env-step to 1e-5 and env-steps/s on the held-out
    envs, with the plain and with the learned start (fallback to the plain
@@ -33,7 +33,7 @@ def _say(*a):
     print(*a, flush=True)
 
 
-def test_label_train_judge_and_evaluate_on_held_out_envs():
+def test_label_train_check_and_evaluate_on_held_out_envs():
     import torch
     from paper_1611_01652_amd import warmstart as WS
 
@@ -52,7 +52,7 @@ def test_label_train_judge_and_evaluate_on_held_out_envs():
     assert log[-1][1] < 0.7 * log[0][1]
     del rec
 
-    # the judge: held-out records (converged impulses of the plain solve)
+    # the check: held-out records (converged impulses of the plain solve)
     held, _ = WS.label(1024, 500, seed_salt=200, rec_every=5, cap=2_000_000, tol=1e-5)
     with torch.no_grad():
         y = net.forward(held)
@@ -60,7 +60,7 @@ def test_label_train_judge_and_evaluate_on_held_out_envs():
         e_plain = torch.linalg.vector_norm(carried - target, dim=1)
         e_learned = torch.linalg.vector_norm(carried + y - target, dim=1)
     rp, rl = float(e_plain.square().mean().sqrt()), float(e_learned.square().mean().sqrt())
-    _say(f"judge: {held.shape[0]} held-out records, RMS distance to the converged impulses "
+    _say(f"check: {held.shape[0]} held-out records, RMS distance to the converged impulses "
          f"(velocity units) carried {rp:.4g}, learned {rl:.4g}")
     assert rl < 0.9 * rp
     del held
