@@ -425,7 +425,11 @@ sim_status sim_init(const sim_model_desc* d, sim_handle* out) {
             std::min<long long>(kSimdsPerCu, kLdsPerCu / std::max<long long>(1, adj_bytes(M, t, fa)));
         const long long envs_cu = (64 / t) * std::max<long long>(1, waves);
         const long long rounds = ((long long)E + (long long)h->n_cu * envs_cu - 1) / ((long long)h->n_cu * envs_cu);
-        if (team < 0 || rounds < best) { best = rounds; team = t; ring = r; }
+        // (equal rounds, more than one: the smaller tile, which packs among
+        // the other buckets' workgroups)
+        if (team < 0 || rounds < best || (rounds == best && rounds > 1 && r == ring && t > team)) {
+          best = rounds; team = t; ring = r;
+        }
       }
     }
     if (ring) {
