@@ -27,7 +27,7 @@ def build(force: bool = True) -> str:
     """Compile the oracle with the host compiler (g++, -O2, FP64)."""
     if force or not os.path.exists(_LIB):
         cmd = ["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-fno-fast-math", "-o", _LIB + ".tmp",
-               os.path.join(_HERE, "oracle.cpp"), "-lpthread"]
+               os.path.join(_HERE, "oracle.cpp"), os.path.join(_HERE, "render.cpp"), "-lpthread"]
         subprocess.check_call(cmd)
         os.replace(_LIB + ".tmp", _LIB)
     return _LIB
@@ -56,7 +56,23 @@ def _load():
         _lib.oracle_wsn_forward.argtypes = [dp, dp, C.c_int, C.c_int, dp]
         _lib.oracle_wsn_forward.restype = None
         _lib.oracle_controls.argtypes = [C.c_void_p, C.c_int, dp, C.c_int, dp]
+        _lib.oracle_render.argtypes = [C.c_void_p, dp, C.c_void_p, C.c_void_p, dp]
+        _lib.oracle_render_grad.argtypes = [C.c_void_p, dp, C.c_void_p, C.c_void_p, dp, dp]
     return _lib
+
+
+class Camera(C.Structure):
+    """Pinhole camera of the renderer (section 3.4): position, axes (rows:
+    right, up, optical axis), distance of the projection plane, pixel pitch
+    on it, image size."""
+    _fields_ = [("pos", C.c_double * 3), ("axes", C.c_double * 9), ("focal", C.c_double), ("pitch", C.c_double),
+                ("width", C.c_int), ("height", C.c_int)]
+
+
+class _Textures(C.Structure):
+    _fields_ = [("sphere", C.c_void_p), ("sphere_nx", C.c_int), ("sphere_ny", C.c_int),
+                ("ground", C.c_void_p), ("ground_nx", C.c_int), ("ground_ny", C.c_int),
+                ("ground_cell", C.c_double)]
 
 
 class _Model(C.Structure):
@@ -268,6 +284,33 @@ class Oracle:
         if gw is not None:
             out["g_w"] = gw
         return out
+
+    def render(self, cam, tex_sphere, tex_ground, cell, x=None):
+        """Image [E, H, W] of the state x ([B, 18], default x0) seen by the
+        camera (see render.cpp)."""
+        w = self.w
+        x = np.ascontiguousarray(w.x0 if x is None else x, dtype=np.float64)
+        t = self._tex(tex_sphere, tex_ground, cell)
+        img = np.zeros((w.n_envs, cam.height, cam.width))
+        self.lib.oracle_render(C.byref(self._m), _dp(x), C.byref(cam), C.byref(t[0]), _dp(img))
+        return img
+
+    def render_grad(self, cam, tex_sphere, tex_ground, cell, weights, x=None):
+        """dL/dx [B, 18] for L = sum(weights * image)."""
+        w = self.w
+        x = np.ascontiguousarray(w.x0 if x is None else x, dtype=np.float64)
+        t = self._tex(tex_sphere, tex_ground, cell)
+        wt = np.ascontiguousarray(weights, dtype=np.float64)
+        g = np.zeros_like(x)
+        self.lib.oracle_render_grad(C.byref(self._m), _dp(x), C.byref(cam), C.byref(t[0]), _dp(wt), _dp(g))
+        return g
+
+    @staticmethod
+    def _tex(ts, tg, cell):
+        ts = np.ascontiguousarray(ts, dtype=np.float64)
+        tg = np.ascontiguousarray(tg, dtype=np.float64)
+        t = _Textures(ts.ctypes.data, ts.shape[1], ts.shape[0], tg.ctypes.data, tg.shape[1], tg.shape[0], float(cell))
+        return t, ts, tg
 
     def controls(self, x, env=0, t=0):
         """Controller outputs u^t of one env at state x [B][18] (eq. (g))."""

@@ -138,6 +138,29 @@ long long oracle_count_flops(const oracle_model* m, int env, const double* x, co
 long long oracle_count_tape_edges(const oracle_model* m, int env, const double* x, const double* lam,
                                   const double* u, int t);
 
+/* The differentiable camera (render.cpp; section 3.4).  axes: rows e_x
+   (right), e_y (up), e_z (optical axis); focal: distance of the projection
+   plane; pitch: pixel size on it. */
+typedef struct {
+  double pos[3], axes[9], focal, pitch;
+  int width, height;
+} oracle_camera;
+/* grayscale textures, row-major: the spheres' (nx x ny) and the ground's,
+   whose texel coordinates are the hit's (x, y) / cell */
+typedef struct {
+  const double* sphere;
+  int sphere_nx, sphere_ny;
+  const double* ground;
+  int ground_nx, ground_ny;
+  double ground_cell;
+} oracle_textures;
+/* image [E][H][W] of the state x [B][18] */
+int oracle_render(const oracle_model* m, const double* x, const oracle_camera* cam, const oracle_textures* tex,
+                  double* image);
+/* g_x [B][18] = dL/dx for L = sum of w * image (w [E][H][W]) */
+int oracle_render_grad(const oracle_model* m, const double* x, const oracle_camera* cam, const oracle_textures* tex,
+                       const double* w, double* g_x);
+
 #ifdef __cplusplus
 }
 #endif

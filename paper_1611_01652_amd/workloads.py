@@ -645,3 +645,34 @@ def rec_sizes(sizes, rec):
     """Layer sizes of the controller with `rec` recurrent units (eq. (g)): the
     input gains h^t, the output gains the pre-activation of h^{t+1}."""
     return (sizes[0] + rec, sizes[1], sizes[2], sizes[3] + rec)
+
+
+# --------------------------------------------------------------------------
+# the differentiable camera (section 3.4): camera poses and textures
+# --------------------------------------------------------------------------
+def pinhole_camera(pos, look_at, up=(0.0, 0.0, 1.0), focal=1.0, pitch=1.0 / 144, width=288, height=96) -> dict:
+    """A camera at `pos` whose optical axis points at `look_at`: axes rows
+    (right, up, optical axis), the projection plane at `focal`, pixels of
+    `pitch` on it (the paper's frames are 288 x 96).  Values rounded to
+    float32 so both sides see the same camera."""
+    pos = np.asarray(pos, np.float64)
+    ez = np.asarray(look_at, np.float64) - pos
+    ez /= np.linalg.norm(ez)
+    ex = np.cross(ez, np.asarray(up, np.float64))
+    ex /= np.linalg.norm(ex)
+    ey = np.cross(ex, ez)
+    return dict(pos=f32(pos), axes=f32(np.stack([ex, ey, ez])), focal=float(f32(focal)), pitch=float(f32(pitch)),
+                width=int(width), height=int(height))
+
+
+def synthetic_texture(nx: int, ny: int, seed_salt: int = 0, n_waves: int = 6) -> np.ndarray:
+    """A seeded smooth grayscale texture [ny, nx] in [0, 1]: a sum of plane
+    waves that tile the texture (stand-in for the paper's photographs,
+    which are not available)."""
+    rng = rng_for(13, seed_salt)
+    a, b = np.meshgrid(np.arange(nx), np.arange(ny))
+    t = np.full((ny, nx), 0.5)
+    for _ in range(n_waves):
+        kx, ky = rng.integers(-4, 5), rng.integers(-4, 5)
+        t += rng.uniform(0.02, 0.08) * np.sin(2 * np.pi * (kx * a / nx + ky * b / ny) + rng.uniform(0, 2 * np.pi))
+    return f32(np.clip(t, 0.0, 1.0))
