@@ -57,7 +57,7 @@
 extern "C" {
 #endif
 
-#define SIM_ABI_VERSION 8
+#define SIM_ABI_VERSION 9
 
 typedef struct sim_model* sim_handle;
 
@@ -415,6 +415,57 @@ sim_status sim_step_graph(sim_handle h, int32_t n_steps, float* x, const float* 
                           uint32_t* env_flags, sim_graph* out);
 sim_status sim_graph_launch(sim_graph g, void* stream);
 sim_status sim_graph_destroy(sim_graph g);
+
+/* ---- The differentiable camera (paper section 3.4). ----
+ * A pinhole camera at pos with axes (rows of axes: e_x right, e_y up, e_z the
+ * optical axis) and its projection plane at distance focal; pixel (i, j) of a
+ * width x height image (i to the right, j down) has its centre on the plane
+ * at (u, v) = ((i + 1/2 - width/2) pitch, (height/2 - j - 1/2) pitch), and its
+ * ray is pos + s d with d = focal e_z + u e_x + v e_y (the plane is s = 1).
+ * The ray is intersected with every sphere of the env (the model's spheres:
+ * centre p_b + R_b offset, the radius) and, when the model has a ground, the
+ * plane z = 0; of all intersections the one closest in front of the
+ * projection plane (the smallest s >= 1) is kept and its colour is a
+ * bilinear sample of the object's texture (bilinear so that the image has
+ * non-zero derivatives with respect to the state, as section 3.4 explains).
+ * A sphere hit at h reads the sphere texture at texel coordinates
+ * ((l_x + 1)(nx - 1)/2, (l_y + 1)(ny - 1)/2) for l = R_b^T (h - c) / r, its
+ * direction in the body frame; the ground reads the ground texture at
+ * (h_x, h_y) / ground_cell.  Texel (a, b) sits at integer coordinates
+ * (texture[b * nx + a], row-major), indices wrap around.  A ray that hits
+ * nothing has colour 0.  The camera and texture structs are read on the host
+ * during the call (the caller keeps them); the textures stay on the device.
+ * Both calls return SIM_E_ARG, before any launch, for a null pointer, a
+ * width, height, focal length or pitch that is not positive, an image of more
+ * than 2^28 pixels, a texture of fewer than 2 x 2 texels or a cell that is
+ * not positive; SIM_E_DEVICE when a launch fails. */
+typedef struct {
+  float pos[3];
+  float axes[9];       /* rows: right, up, optical axis (unit, orthogonal) */
+  float focal, pitch;  /* > 0 */
+  int32_t width, height;
+} sim_camera;
+typedef struct {
+  const float* sphere;   /* device [sphere_ny][sphere_nx], nx, ny >= 2 */
+  int32_t sphere_nx, sphere_ny;
+  const float* ground;   /* device [ground_ny][ground_nx], nx, ny >= 2 */
+  int32_t ground_nx, ground_ny;
+  float ground_cell;     /* > 0 */
+} sim_textures;
+/* image (device [E][height][width], overwritten): every env seen by the
+ * camera in the state x (device [18][B], as sim_step's).  Asynchronous on
+ * stream. */
+sim_status sim_render(sim_handle h, const float* x, const sim_camera* cam, const sim_textures* tex, float* image,
+                      void* stream);
+/* g_x (device [18][B], overwritten): dL/dx of every body's position (rows
+ * 0..2) and rotation (rows 3..11) for L = sum of w * image, w device
+ * [E][height][width]; the velocity rows are 0.  The hit object of each ray is
+ * decided on the values (the silhouettes carry no derivative).  Every env
+ * may hold at most SIM_RENDER_MAX_SPHERES spheres (else SIM_E_UNSUPPORTED).
+ * Reduced per env in a fixed order: bitwise reproducible. */
+#define SIM_RENDER_MAX_SPHERES 16
+sim_status sim_render_grad(sim_handle h, const float* x, const sim_camera* cam, const sim_textures* tex,
+                           const float* w, float* g_x, void* stream);
 
 /* ---- Tile autotuning. ----
  * Envs are scheduled in buckets of equal team width (lanes per env) and LDS

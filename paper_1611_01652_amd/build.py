@@ -10,7 +10,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libsim_hip.so")
 
-SOURCES = ["sim_kernels.hip", "wsn_kernels.hip", "sim_api.cpp", "model_pack.cpp"]
+SOURCES = ["sim_kernels.hip", "wsn_kernels.hip", "render_kernels.hip", "sim_api.cpp", "model_pack.cpp"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -94,6 +94,12 @@ struct sim_model {
   hipEvent_t tev[4] = {};       // rollout_grad phase events (sim_time_grad), owned by the caller
   std::vector<hipEvent_t> bev;  // per-bucket reverse launch events (sim_time_buckets), owned by the caller
   float* d_wt = nullptr;        // controller weights transposed for the forward products
+  // the camera's scene: spheres per env, their bodies, offsets and radii
+  int* d_env_sph = nullptr;
+  int* d_env_body = nullptr;
+  int* d_sph_body = nullptr;
+  float4* d_sph = nullptr;
+  int max_env_spheres = 0;
 };
 
 struct sim_graph_s {
@@ -127,6 +133,10 @@ void release(sim_model* h) {
   if (h->d_map) (void)hipFree(h->d_map);
   if (h->d_wsn) (void)hipFree(h->d_wsn);
   if (h->d_wt) (void)hipFree(h->d_wt);
+  if (h->d_env_sph) (void)hipFree(h->d_env_sph);
+  if (h->d_env_body) (void)hipFree(h->d_env_body);
+  if (h->d_sph_body) (void)hipFree(h->d_sph_body);
+  if (h->d_sph) (void)hipFree(h->d_sph);
   for (auto sx : h->streams) (void)hipStreamDestroy(sx);
   for (auto ex : h->joins) (void)hipEventDestroy(ex);
   if (h->fork) (void)hipEventDestroy(h->fork);
@@ -496,6 +506,23 @@ sim_status sim_init(const sim_model_desc* d, sim_handle* out) {
     }
   }
   sim_status st = SIM_OK;
+  {
+    // the camera's scene
+    const int S = d->env_sphere_off[E];
+    std::vector<int> env_sph(d->env_sphere_off, d->env_sphere_off + E + 1);
+    std::vector<int> env_body(d->env_body_off, d->env_body_off + E + 1);
+    std::vector<int> sph_body(d->sphere_body, d->sphere_body + S);
+    std::vector<float4> sph(S);
+    for (int k = 0; k < S; ++k)
+      sph[k] = make_float4(d->sphere_offset[3 * k], d->sphere_offset[3 * k + 1], d->sphere_offset[3 * k + 2],
+                           d->sphere_radius[k]);
+    for (int e = 0; e < E; ++e) h->max_env_spheres = std::max(h->max_env_spheres, env_sph[e + 1] - env_sph[e]);
+    if ((st = upload(&h->d_env_sph, env_sph)) != SIM_OK || (st = upload(&h->d_env_body, env_body)) != SIM_OK ||
+        (st = upload(&h->d_sph_body, sph_body)) != SIM_OK || (st = upload(&h->d_sph, sph)) != SIM_OK) {
+      release(h);
+      return st;
+    }
+  }
   if ((st = upload(&h->d_hdr, P.hdr)) != SIM_OK || (st = upload(&h->d_topo, P.topo)) != SIM_OK ||
       (st = upload(&h->d_cst, P.cst)) != SIM_OK || (st = upload(&h->d_target, P.target)) != SIM_OK) {
     release(h);
@@ -860,6 +887,61 @@ sim_status sim_env_buckets(sim_handle h, int32_t* bucket_of_env) {
   for (size_t i = 0; i < h->buckets.size(); ++i)
     for (int e : h->buckets[i].envs_host)
       if (e >= 0) bucket_of_env[e] = (int32_t)i;
+  return SIM_OK;
+}
+
+// ------------------------------------------------------------- the camera
+namespace {
+sim_status render_args(sim_handle h, const float* x, const sim_camera* cam, const sim_textures* tex, const char* what,
+                       RenderScene& sc, RenderCam& rc, RenderTex& rt) {
+  if (!h || !x || !cam || !tex || !tex->sphere || !tex->ground)
+    return fail(SIM_E_ARG, std::string(what) + ": null argument");
+  if (cam->width < 1 || cam->height < 1 || !(cam->focal > 0.f) || !(cam->pitch > 0.f))
+    return fail(SIM_E_ARG, std::string(what) + ": image size, focal length and pixel pitch must be positive");
+  if ((long long)cam->width * cam->height > (1LL << 28))
+    return fail(SIM_E_ARG, std::string(what) + ": image larger than 2^28 pixels");
+  if (tex->sphere_nx < 2 || tex->sphere_ny < 2 || tex->ground_nx < 2 || tex->ground_ny < 2 ||
+      !(tex->ground_cell > 0.f))
+    return fail(SIM_E_ARG, std::string(what) + ": textures need at least 2 x 2 texels and a positive cell");
+  sc = RenderScene{h->M.n_envs, h->M.B, h->M.ground, h->d_env_sph, h->d_env_body, h->d_sph_body, h->d_sph};
+  for (int k = 0; k < 3; ++k) rc.pos[k] = cam->pos[k];
+  for (int k = 0; k < 9; ++k) rc.axes[k] = cam->axes[k];
+  rc.focal = cam->focal;
+  rc.pitch = cam->pitch;
+  rc.width = cam->width;
+  rc.height = cam->height;
+  rt = RenderTex{tex->sphere, tex->sphere_nx, tex->sphere_ny, tex->ground, tex->ground_nx, tex->ground_ny,
+                 tex->ground_cell};
+  return SIM_OK;
+}
+}  // namespace
+
+sim_status sim_render(sim_handle h, const float* x, const sim_camera* cam, const sim_textures* tex, float* image,
+                      void* stream) {
+  RenderScene sc;
+  RenderCam rc;
+  RenderTex rt;
+  sim_status st = render_args(h, x, cam, tex, "sim_render", sc, rc, rt);
+  if (st != SIM_OK) return st;
+  if (!image) return fail(SIM_E_ARG, "sim_render: null image");
+  if (launch_render(sc, x, rc, rt, image, (hipStream_t)stream) != hipSuccess) return check_device("sim_render");
+  return SIM_OK;
+}
+
+sim_status sim_render_grad(sim_handle h, const float* x, const sim_camera* cam, const sim_textures* tex,
+                           const float* w, float* g_x, void* stream) {
+  RenderScene sc;
+  RenderCam rc;
+  RenderTex rt;
+  sim_status st = render_args(h, x, cam, tex, "sim_render_grad", sc, rc, rt);
+  if (st != SIM_OK) return st;
+  if (!w || !g_x) return fail(SIM_E_ARG, "sim_render_grad: null weights or gradient");
+  static_assert(kRenderMaxSpheres == SIM_RENDER_MAX_SPHERES, "render sphere limit");
+  if (h->max_env_spheres > kRenderMaxSpheres)
+    return fail(SIM_E_UNSUPPORTED, "sim_render_grad: an env has " + std::to_string(h->max_env_spheres) +
+                                       " spheres, more than " + std::to_string(kRenderMaxSpheres));
+  if (launch_render_grad(sc, x, rc, rt, w, g_x, (hipStream_t)stream) != hipSuccess)
+    return check_device("sim_render_grad");
   return SIM_OK;
 }
 

@@ -41,6 +41,31 @@ hipError_t launch_rollout_keep(const DevModel& M, const TileSet& ts, int team, i
                                const RolloutArgs& a, hipStream_t st);
 hipError_t allow_large_lds(int bytes);
 
+// the differentiable camera (render_kernels.hip)
+constexpr int kRenderMaxSpheres = 16;   // spheres per env the gradient reduction holds
+struct RenderScene {
+  int E, B, ground;
+  const int* env_sph;    // [E+1] first sphere of each env
+  const int* env_body;   // [E+1] first body of each env
+  const int* sph_body;   // [S] body (global index)
+  const float4* sph;     // [S] offset in the body frame (x, y, z), radius (w)
+};
+struct RenderCam {
+  float pos[3], axes[9], focal, pitch;
+  int width, height;
+};
+struct RenderTex {
+  const float* sphere;
+  int snx, sny;
+  const float* ground;
+  int gnx, gny;
+  float cell;
+};
+hipError_t launch_render(const RenderScene& sc, const float* x, const RenderCam& cam, const RenderTex& tex,
+                         float* image, hipStream_t st);
+hipError_t launch_render_grad(const RenderScene& sc, const float* x, const RenderCam& cam, const RenderTex& tex,
+                              const float* w, float* g_x, hipStream_t st);
+
 // warm-start network (wsn_kernels.hip)
 int wsn_parts(long long n, int n_cu);
 // LDS floats of the shared region a forward workgroup needs for the learned

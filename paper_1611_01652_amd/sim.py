@@ -20,7 +20,7 @@ FLAG_NONFINITE = 1
 FLAG_CONTACT_OVERFLOW = 2
 
 # layout of the descriptor and info structs below (SIM_ABI_VERSION)
-ABI_VERSION = 8
+ABI_VERSION = 9
 
 # reverse sweep memory modes (sim_model_desc.grad_store)
 GRAD_STORE = {"auto": 0, "replay": 1, "segment": 2, "trajectory": 3}
@@ -185,10 +185,13 @@ def library():
     lib.sim_time_grad.argtypes = [vp, C.POINTER(vp)]
     lib.sim_time_buckets.argtypes = [vp, C.POINTER(vp), C.c_int32]
     lib.sim_env_buckets.argtypes = [vp, _I32P]
+    lib.sim_render.argtypes = [vp, vp, C.POINTER(SimCamera), C.POINTER(SimTextures), vp, vp]
+    lib.sim_render_grad.argtypes = [vp, vp, C.POINTER(SimCamera), C.POINTER(SimTextures), vp, vp, vp]
     for fn in ("sim_time_grad", "sim_init", "sim_destroy", "sim_get_info", "sim_lambda_offsets", "sim_step", "rollout",
                "rollout_grad", "rollout_grad_noalloc", "rollout_keep", "rollout_grad_kept", "sim_time_buckets",
                "sim_env_buckets", "sim_step_graph", "sim_graph_launch", "sim_graph_destroy", "sim_set_teams",
-               "wsn_to_bf16", "wsn_forward", "wsn_loss_grad", "wsn_adam", "rollout_solve", "sim_adam"):
+               "wsn_to_bf16", "wsn_forward", "wsn_loss_grad", "wsn_adam", "rollout_solve", "sim_adam", "sim_render",
+               "sim_render_grad"):
         getattr(lib, fn).restype = C.c_int
     if lib.sim_abi_version() != ABI_VERSION:
         raise RuntimeError(f"{LIB_PATH} has ABI version {lib.sim_abi_version()}, this binding expects "
@@ -202,7 +205,29 @@ EXPORTED = ["sim_abi_version", "sim_last_error", "sim_init", "sim_destroy", "sim
             "sim_step_graph", "sim_graph_launch", "sim_graph_destroy", "sim_tune", "sim_get_teams",
             "sim_set_teams", "wsn_to_bf16", "wsn_forward", "wsn_workspace_bytes", "wsn_loss_grad", "wsn_adam",
             "rollout_solve", "sim_adam", "sim_time_grad", "rollout_grad_noalloc", "sim_time_buckets",
-            "sim_env_buckets", "rollout_keep", "rollout_grad_kept"]
+            "sim_env_buckets", "rollout_keep", "rollout_grad_kept", "sim_render", "sim_render_grad"]
+
+
+class SimCamera(C.Structure):
+    """sim_camera: pinhole at pos, axes rows (right, up, optical axis), the
+    projection plane at focal, pixel pitch on it, image size."""
+    _fields_ = [("pos", C.c_float * 3), ("axes", C.c_float * 9), ("focal", C.c_float), ("pitch", C.c_float),
+                ("width", C.c_int32), ("height", C.c_int32)]
+
+
+class SimTextures(C.Structure):
+    _fields_ = [("sphere", C.c_void_p), ("sphere_nx", C.c_int32), ("sphere_ny", C.c_int32),
+                ("ground", C.c_void_p), ("ground_nx", C.c_int32), ("ground_ny", C.c_int32),
+                ("ground_cell", C.c_float)]
+
+
+def camera(c):
+    """A SimCamera from a dict as workloads.pinhole_camera makes."""
+    s = SimCamera()
+    s.pos[:] = [float(v) for v in np.asarray(c["pos"]).reshape(3)]
+    s.axes[:] = [float(v) for v in np.asarray(c["axes"]).reshape(9)]
+    s.focal, s.pitch, s.width, s.height = float(c["focal"]), float(c["pitch"]), int(c["width"]), int(c["height"])
+    return s
 
 # bytes of the scratch rollout_grad_noalloc uses (SIM_NOALLOC_SCRATCH_BYTES)
 NOALLOC_SCRATCH_BYTES = 64 << 20
@@ -369,6 +394,35 @@ class Simulator:
         g["g_anchor_p"] = g["g_anchor_p"][: 3 * J].view(J, 3)
         g["g_anchor_c"] = g["g_anchor_c"][: 3 * J].view(J, 3)
         return g
+
+    def render(self, x, cam, tex_sphere, tex_ground, cell):
+        """Image [E, H, W] (CUDA float32) of the state x ([18, B] CUDA
+        float32) seen by cam (a dict as workloads.pinhole_camera makes);
+        textures are CUDA float32 [ny, nx] tensors (sim_render)."""
+        c = camera(cam)
+        t = self._textures(tex_sphere, tex_ground, cell)
+        img = self.torch.empty((self.info.n_envs, c.height, c.width), dtype=self.torch.float32, device="cuda")
+        _check(self.lib, self.lib.sim_render(self.h, _ptr(x), C.byref(c), C.byref(t), _ptr(img), self._stream()),
+               "sim_render")
+        return img
+
+    def render_grad(self, x, cam, tex_sphere, tex_ground, cell, weights):
+        """dL/dx [18, B] for L = sum(weights * image) (sim_render_grad)."""
+        c = camera(cam)
+        t = self._textures(tex_sphere, tex_ground, cell)
+        g = self.torch.empty_like(x)
+        _check(self.lib, self.lib.sim_render_grad(self.h, _ptr(x), C.byref(c), C.byref(t), _ptr(weights), _ptr(g),
+                                                  self._stream()), "sim_render_grad")
+        return g
+
+    @staticmethod
+    def _textures(ts, tg, cell):
+        import torch
+        for t in (ts, tg):
+            if t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous() or t.dim() != 2:
+                raise ValueError("textures must be contiguous 2-D CUDA float32 tensors")
+        return SimTextures(ts.data_ptr(), ts.shape[1], ts.shape[0], tg.data_ptr(), tg.shape[1], tg.shape[0],
+                           float(cell))
 
     def time_grad(self, events):
         """Record rollout_grad's phases on 4 torch.cuda.Events (recompute start
