@@ -8,7 +8,9 @@ the timed region.  The default workload is the largest single-GPU one: 16384
 uneven 3D hinge chains of 2..32 spheres with ground and self contact, 500
 steps (synthetic, seeded).  `--workload arms` runs the 4096 planar 3-link arms
 x 1000 steps, `--workload quadruped` the 1024 legged robots with an MLP
-controller.
+controller.  `--workload camera` measures the differentiable camera instead
+(section 3.4): one step is an image of every env at the paper's frame size
+and the gradient of a weighted sum of it with respect to the bodies' poses.
 
 Printed: one JSON line with the throughput, a roofline object for the
 reverse sweep kernel of one call (one launch per size bucket, all running at
@@ -239,13 +241,111 @@ def cpu_baseline(w, n_envs=256, per_core_seconds=5.0, noisy_draws=8):
     return base, envs, ref, noisy
 
 
+# ---------------------------------------------------------------- camera
+# Operations of a pixel's ray as the renderer defines it, counted from its
+# arithmetic: the ray through the pixel centre and |d|^2 (26), then per
+# sphere of the env the centre p + R o (18), the ray's closest approach to it
+# and the discriminant (24), the root (3); the ground's hit parameter (1).
+# Shading the hit (<= 55, the gradient's adjoint <= 139) is not counted, so
+# the achieved rate is a lower bound.
+CAM_RAY_FLOPS, CAM_SPHERE_FLOPS = 27, 45
+
+
+def camera_scene(n_envs=1024, seed_salt=12):
+    """Envs of the chain distribution with 2..16 spheres at their initial
+    poses, seen from the side and above at the paper's 288 x 96 frame, with
+    seeded smooth textures."""
+    from paper_1611_01652_amd import workloads as W
+    rng = np.random.default_rng(seed_salt)
+    w = W.uneven_chains(n_envs=n_envs, T=4, seed_salt=seed_salt, sizes=rng.integers(2, 17, n_envs))
+    cam = W.pinhole_camera((0.3, -3.5, 1.6), (0.0, 0.0, 0.3), focal=1.0, pitch=1.6 / 288, width=288, height=96)
+    return w, cam, W.synthetic_texture(64, 32, 5), W.synthetic_texture(64, 64, 6), 0.25
+
+
+def camera_cpu_baseline(w, cam, ts, tg, cell, n_envs=16):
+    """The oracle's image and gradient (FP64, tape reverse mode) on n_envs
+    envs at evenly spaced quantiles of the sphere count, one thread."""
+    from oracle import Camera, Oracle
+    envs = stratified(w, n_envs)
+    ws = w.subset(envs)
+    o = Oracle(ws)
+    c = Camera()
+    c.pos[:] = [float(v) for v in cam["pos"]]
+    c.axes[:] = [float(v) for v in np.asarray(cam["axes"]).reshape(9)]
+    c.focal, c.pitch, c.width, c.height = cam["focal"], cam["pitch"], cam["width"], cam["height"]
+    t0 = time.time()
+    img = o.render(c, ts, tg, cell)
+    o.render_grad(c, ts, tg, cell, np.ones_like(img))
+    el = time.time() - t0
+    return {"value": img.size / el, "unit": "pixels/s", "cores": 1, "kind": "oracle",
+            "sample": f"{len(envs)} envs at evenly spaced quantiles of the sphere count, image and gradient of "
+                      f"the sum of the image, {cam['width']} x {cam['height']}, FP64, one thread",
+            "seconds": el, "nproc": os.cpu_count(), "physical_cores": physical_cores()}
+
+
+def bench_camera(args):
+    import torch
+    from paper_1611_01652_amd.sim import Simulator
+    w, cam, ts, tg, cell = camera_scene()
+    sim = Simulator(w)
+    xd = torch.tensor(np.ascontiguousarray(w.x0.T), dtype=torch.float32, device="cuda")
+    tsd = torch.tensor(ts, dtype=torch.float32, device="cuda")
+    tgd = torch.tensor(tg, dtype=torch.float32, device="cuda")
+    print(f"bench: camera {w.n_envs} envs x {cam['width']} x {cam['height']}", file=sys.stderr, flush=True)
+    img = sim.render(xd, cam, tsd, tgd, cell)
+    wd = torch.ones_like(img)
+    g = sim.render_grad(xd, cam, tsd, tgd, cell, wd)
+    for _ in range(args.warmup):
+        sim.render(xd, cam, tsd, tgd, cell, out=img)
+        sim.render_grad(xd, cam, tsd, tgd, cell, wd, out=g)
+    torch.cuda.synchronize()
+    mk = lambda: torch.cuda.Event(enable_timing=True)   # noqa: E731
+    evs = [[mk() for _ in range(3)] for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        # both calls launch on torch's current stream, where the events sit
+        evs[k][0].record()
+        sim.render(xd, cam, tsd, tgd, cell, out=img)
+        evs[k][1].record()
+        g = sim.render_grad(xd, cam, tsd, tgd, cell, wd, out=g)
+        evs[k][2].record()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    print("bench: timed region done", file=sys.stderr, flush=True)
+    render_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
+    grad_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in evs]))
+    n_pix = img.numel()
+    ns = np.diff(w.env_sphere_off)
+    flops = float(cam["width"] * cam["height"] * (CAM_RAY_FLOPS + CAM_SPHERE_FLOPS * ns).sum())
+    roof = lambda ms, name: {   # noqa: E731
+        "bound": "alu", "kernel": name, "achieved": flops / (ms * 1e-3) / 1e12, "peak": FP32_VECTOR_PEAK_TFLOPS,
+        "unit": "TFLOP/s", "frac": flops / (ms * 1e-3) / 1e12 / FP32_VECTOR_PEAK_TFLOPS, "traffic": None,
+        "flops_per_launch": flops, "kernel_ms": ms}
+    line = {
+        "metric": "camera image + gradient pixels/s", "value": n_pix / (el / args.steps), "unit": "pixels/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": el * 1e3 / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "camera", "envs": w.n_envs, "width": cam["width"], "height": cam["height"],
+                   "spheres": int(ns.sum()), "pixels": n_pix},
+        "render_ms": render_ms, "render_grad_ms": grad_ms,
+        "image_pixels_per_s": n_pix / (render_ms * 1e-3), "gradient_pixels_per_s": n_pix / (grad_ms * 1e-3),
+        "roofline": roof(grad_ms, "k_render_grad") if grad_ms >= render_ms else roof(render_ms, "k_render"),
+        "render_roofline": roof(render_ms, "k_render"),
+        "render_grad_roofline": roof(grad_ms, "k_render_grad"),
+        "finite": bool(torch.isfinite(img).all().item() and torch.isfinite(g).all().item()),
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = camera_cpu_baseline(w, cam, ts, tg, cell)
+    print(json.dumps(line), flush=True)
+
+
 # ---------------------------------------------------------------- main
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="chains", choices=["arms", "chains", "quadruped"])
+    ap.add_argument("--workload", default="chains", choices=["arms", "chains", "quadruped", "camera"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--no-keep", action="store_true",
@@ -260,6 +360,10 @@ def main():
                                    "(sharding over GPUs is a design note, not implemented)",
                           "n_gpus": args.gpus}))
         sys.exit(2)
+
+    if args.workload == "camera":
+        bench_camera(args)
+        return
 
     import torch
     from paper_1611_01652_amd.sim import Simulator

@@ -108,45 +108,74 @@ __device__ __forceinline__ void sphere_centre(const float* x, int B, int b, cons
            x[(5 + 3 * r) * B + b] * o[2];
 }
 
-// The roots of |m + s d|^2 = r^2 (m = C - c) are s = t0 -/+ sqrt(D) with t0 =
-// -(d . m) / a and D = (r^2 - |m + t0 d|^2) / a, a = |d|^2: the distance of
-// the ray from the centre, m + t0 d, is formed first, so D does not come
-// from the difference of two terms of the size |m|^2 |d|^2 (which loses
-// every digit of a small D in FP32).
-__device__ RHit trace(const RenderScene& sc, const float* x, int e, const Ray& ray) {
-  const float a = ray.d[0] * ray.d[0] + ray.d[1] * ray.d[1] + ray.d[2] * ray.d[2];
-  RHit h{-2, INFINITY};
-  const int s0 = sc.env_sph[e], s1 = sc.env_sph[e + 1];
-  for (int g = s0; g < s1; ++g) {
+// Spheres [g0, g1) of env order staged in LDS: centre p + R o and radius,
+// one float4 each, made once per workgroup instead of once per pixel.
+__device__ __forceinline__ void stage_spheres(const RenderScene& sc, const float* x, int g0, int g1, float4* cs) {
+  for (int g = g0 + (int)threadIdx.x; g < g1; g += (int)blockDim.x) {
     const float4 so = sc.sph[g];
     const float o[3] = {so.x, so.y, so.z};
     float c[3];
     sphere_centre(x, sc.B, sc.sph_body[g], o, c);
-    const float m0 = ray.c[0] - c[0], m1 = ray.c[1] - c[1], m2 = ray.c[2] - c[2];
+    cs[g - g0] = make_float4(c[0], c[1], c[2], so.w);
+  }
+}
+
+// The roots of |m + s d|^2 = r^2 (m = C - c) are s = t0 -/+ sqrt(D) with t0 =
+// -(d . m) / a and D = (r^2 - |m + t0 d|^2) / a, a = |d|^2: the distance of
+// the ray from the centre, m + t0 d, is formed first, so D does not come
+// from the difference of two terms of the size |m|^2 |d|^2 (which loses
+// every digit of a small D in FP32).  The staged spheres are tested in env
+// order (index k0 + k); the first of equal nearest roots is kept.
+__device__ __forceinline__ void trace_spheres(const float4* cs, int n, int k0, const Ray& ray, float a, RHit& h) {
+  for (int k = 0; k < n; ++k) {
+    const float4 cc = cs[k];
+    const float m0 = ray.c[0] - cc.x, m1 = ray.c[1] - cc.y, m2 = ray.c[2] - cc.z;
     const float t0 = -(ray.d[0] * m0 + ray.d[1] * m1 + ray.d[2] * m2) / a;
     const float p0 = m0 + t0 * ray.d[0], p1 = m1 + t0 * ray.d[1], p2 = m2 + t0 * ray.d[2];
-    const float D = (so.w * so.w - (p0 * p0 + p1 * p1 + p2 * p2)) / a;
+    const float D = (cc.w * cc.w - (p0 * p0 + p1 * p1 + p2 * p2)) / a;
     if (D < 0.f) continue;
     const float sq = sqrtf(D);
     const float s = t0 - sq >= 1.f ? t0 - sq : t0 + sq;
-    if (s >= 1.f && s < h.s) { h.s = s; h.k = g - s0; }
+    if (s >= 1.f && s < h.s) { h.s = s; h.k = k0 + k; }
   }
+}
+
+__device__ __forceinline__ void trace_ground(const RenderScene& sc, const Ray& ray, RHit& h) {
   if (sc.ground) {
     const double s = ground_s(ray);
     if (s >= 1.0 && s < (double)h.s) { h.s = (float)s; h.k = -1; }
   }
-  return h;
 }
 
+__device__ __forceinline__ float ray_a(const Ray& ray) {
+  return ray.d[0] * ray.d[0] + ray.d[1] * ray.d[1] + ray.d[2] * ray.d[2];
+}
+
+constexpr int kStage = 64;   // spheres staged in LDS at a time by k_render
+
+// One thread per pixel, a workgroup 256 pixels of one env; the env's spheres
+// are staged kStage at a time (every thread of the workgroup takes part in
+// the staging, so no thread leaves before the last chunk).
 __global__ __launch_bounds__(256) void k_render(RenderScene sc, const float* x, RenderCam cam, RenderTex tex,
                                                 float* image) {
+  __shared__ float4 cs[kStage];
   const int e = blockIdx.y;
   const int n = cam.width * cam.height;
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= n) return;
-  const int i = p % cam.width, j = p / cam.width;
-  const Ray ray = pixel_ray(cam, i, j);
-  const RHit h = trace(sc, x, e, ray);
+  const bool live = p < n;
+  const Ray ray = pixel_ray(cam, live ? p % cam.width : 0, live ? p / cam.width : 0);
+  const float a = ray_a(ray);
+  RHit h{-2, INFINITY};
+  const int s0 = sc.env_sph[e], s1 = sc.env_sph[e + 1];
+  for (int g0 = s0; g0 < s1; g0 += kStage) {
+    const int g1 = g0 + kStage < s1 ? g0 + kStage : s1;
+    __syncthreads();
+    stage_spheres(sc, x, g0, g1, cs);
+    __syncthreads();
+    trace_spheres(cs, g1 - g0, g0 - s0, ray, a, h);
+  }
+  if (!live) return;
+  trace_ground(sc, ray, h);
   float col = 0.f;
   if (h.k == -1) {
     const double sg = ground_s(ray);
@@ -154,7 +183,7 @@ __global__ __launch_bounds__(256) void k_render(RenderScene sc, const float* x, 
     const double gv = ((double)ray.c[1] + sg * ray.d64[1]) / (double)tex.cell;
     col = ground_sample(tex, gu, gv);
   } else if (h.k >= 0) {
-    const int g = sc.env_sph[e] + h.k, b = sc.sph_body[g];
+    const int g = s0 + h.k, b = sc.sph_body[g];
     const float4 so = sc.sph[g];
     const float o[3] = {so.x, so.y, so.z};
     float c[3], q[3];
@@ -169,78 +198,109 @@ __global__ __launch_bounds__(256) void k_render(RenderScene sc, const float* x, 
   image[(size_t)e * n + p] = col;
 }
 
-constexpr int kGradThreads = 64;
+constexpr int kGradWaves = 4;
+constexpr int kGradThreads = 64 * kGradWaves;
 
-// One workgroup per env: thread t takes pixels t, t + 64, ...; each keeps
-// its sums per sphere (12 values: the body's position 3, rotation 9) in LDS,
-// then the 64 rows are added in order and the spheres' sums go to their
-// bodies in sphere order.
+// One workgroup of four waves per env.  In each pass the workgroup takes 256
+// consecutive pixels, wave v the v-th 64 of them, one per lane.  A lane whose
+// pixel shows sphere k forms that pixel's 12 terms (the body's position 3,
+// rotation 9); then, for each sphere that some lane of the wave shows (in
+// the order of the lowest such lane), the wave adds those lanes' terms by a
+// butterfly over the 64 lanes (a fixed tree) and lane 0 adds the sums to the
+// wave's row for that sphere in LDS.  At the end the four waves' rows are
+// added in wave order and each sphere's sums go to its body, spheres in env
+// order.  Every sum runs in an order fixed by the inputs, so the gradient is
+// bitwise reproducible.
 __global__ __launch_bounds__(kGradThreads) void k_render_grad(RenderScene sc, const float* x, RenderCam cam,
                                                               RenderTex tex, const float* w, float* g_x) {
-  __shared__ float acc[kGradThreads][kRenderMaxSpheres][12];
-  const int e = blockIdx.x, t = threadIdx.x;
+  __shared__ float4 cs[kRenderMaxSpheres];
+  __shared__ float acc[kGradWaves][kRenderMaxSpheres][12];
+  __shared__ float tot[kRenderMaxSpheres][12];
+  const int e = blockIdx.x, t = threadIdx.x, lane = t & 63, wv = t >> 6;
   const int n = cam.width * cam.height;
   const int s0 = sc.env_sph[e], ns = sc.env_sph[e + 1] - s0;
-  for (int k = 0; k < kRenderMaxSpheres; ++k)
-    for (int c = 0; c < 12; ++c) acc[t][k][c] = 0.f;
+  for (int u = t; u < kGradWaves * kRenderMaxSpheres * 12; u += kGradThreads) (&acc[0][0][0])[u] = 0.f;
+  stage_spheres(sc, x, s0, s0 + ns, cs);
+  __syncthreads();
   const float kx = 0.5f * (float)(tex.snx - 1), ky = 0.5f * (float)(tex.sny - 1);
-  for (int p = t; p < n; p += kGradThreads) {
-    const float wt = w[(size_t)e * n + p];
-    if (wt == 0.f) continue;
-    const int i = p % cam.width, j = p / cam.width;
-    const Ray ray = pixel_ray(cam, i, j);
-    const RHit h = trace(sc, x, e, ray);
-    if (h.k < 0) continue;   // the ground and the background do not depend on the state
-    const int g = s0 + h.k, b = sc.sph_body[g];
-    const float4 so = sc.sph[g];
-    const float o[3] = {so.x, so.y, so.z};
-    const float r = so.w;
-    float c[3], q[3], R[9];
-    sphere_centre(x, sc.B, b, o, c);
-    for (int k = 0; k < 9; ++k) R[k] = x[(3 + k) * sc.B + b];
-    for (int k = 0; k < 3; ++k) q[k] = ray.c[k] + h.s * ray.d[k] - c[k];
-    const float lx = (R[0] * q[0] + R[3] * q[1] + R[6] * q[2]) / r;
-    const float ly = (R[1] * q[0] + R[4] * q[1] + R[7] * q[2]) / r;
-    float du, dv;
-    (void)bilinear(tex.sphere, tex.snx, tex.sny, (lx + 1.f) * kx, (ly + 1.f) * ky, &du, &dv);
-    const float lbx = wt * du * kx, lby = wt * dv * ky;
-    float* A = acc[t][h.k];
-    // R-bar_{k i} += q_k l-bar_i / r (i = x, y); q-bar_k = (R_k0 l-bar_x + R_k1 l-bar_y) / r
-    float qb[3];
-    for (int k = 0; k < 3; ++k) {
-      A[3 + 3 * k] += q[k] * lbx / r;
-      A[4 + 3 * k] += q[k] * lby / r;
-      qb[k] = (R[3 * k] * lbx + R[3 * k + 1] * lby) / r;
+  for (int base = 0; base < n; base += kGradThreads) {
+    const int p = base + t;
+    int hk = -1;
+    float v[12];
+    for (int c = 0; c < 12; ++c) v[c] = 0.f;
+    const float wt = p < n ? w[(size_t)e * n + p] : 0.f;
+    if (wt != 0.f) {
+      const Ray ray = pixel_ray(cam, p % cam.width, p / cam.width);
+      RHit h{-2, INFINITY};
+      trace_spheres(cs, ns, 0, ray, ray_a(ray), h);
+      trace_ground(sc, ray, h);
+      // the ground and the background do not depend on the state
+      if (h.k >= 0) {
+        hk = h.k;
+        const int g = s0 + h.k, b = sc.sph_body[g];
+        const float4 so = sc.sph[g];
+        const float o[3] = {so.x, so.y, so.z};
+        const float r = so.w;
+        const float4 cc = cs[h.k];
+        const float c[3] = {cc.x, cc.y, cc.z};
+        float q[3], R[9];
+        for (int k = 0; k < 9; ++k) R[k] = x[(3 + k) * sc.B + b];
+        for (int k = 0; k < 3; ++k) q[k] = ray.c[k] + h.s * ray.d[k] - c[k];
+        const float lx = (R[0] * q[0] + R[3] * q[1] + R[6] * q[2]) / r;
+        const float ly = (R[1] * q[0] + R[4] * q[1] + R[7] * q[2]) / r;
+        float du, dv;
+        (void)bilinear(tex.sphere, tex.snx, tex.sny, (lx + 1.f) * kx, (ly + 1.f) * ky, &du, &dv);
+        const float lbx = wt * du * kx, lby = wt * dv * ky;
+        // R-bar_{k i} = q_k l-bar_i / r (i = x, y); q-bar_k = (R_k0 l-bar_x + R_k1 l-bar_y) / r
+        float qb[3];
+        for (int k = 0; k < 3; ++k) {
+          v[3 + 3 * k] = q[k] * lbx / r;
+          v[4 + 3 * k] = q[k] * lby / r;
+          qb[k] = (R[3 * k] * lbx + R[3 * k + 1] * lby) / r;
+        }
+        // h-bar = q-bar, c-bar = -q-bar + (d . h-bar) q / (d . q)
+        const float dh = ray.d[0] * qb[0] + ray.d[1] * qb[1] + ray.d[2] * qb[2];
+        const float dq = ray.d[0] * q[0] + ray.d[1] * q[1] + ray.d[2] * q[2];
+        float cb[3];
+        for (int k = 0; k < 3; ++k) cb[k] = -qb[k] + dh * q[k] / dq;
+        // c = p + R o
+        for (int k = 0; k < 3; ++k) {
+          v[k] = cb[k];
+          for (int m = 0; m < 3; ++m) v[3 + 3 * k + m] += cb[k] * o[m];
+        }
+      }
     }
-    // h-bar = q-bar, c-bar = -q-bar + (d . h-bar) q / (d . q)
-    const float dh = ray.d[0] * qb[0] + ray.d[1] * qb[1] + ray.d[2] * qb[2];
-    const float dq = ray.d[0] * q[0] + ray.d[1] * q[1] + ray.d[2] * q[2];
-    float cb[3];
-    for (int k = 0; k < 3; ++k) cb[k] = -qb[k] + dh * q[k] / dq;
-    // c = p + R o
-    for (int k = 0; k < 3; ++k) {
-      A[k] += cb[k];
-      for (int m = 0; m < 3; ++m) A[3 + 3 * k + m] += cb[k] * o[m];
+    // (wave-uniform: the ballots are the same in every lane)
+    unsigned long long todo = __ballot(hk >= 0);
+    while (todo) {
+      const int kk = __shfl(hk, __ffsll(todo) - 1);
+      const bool mine = hk == kk;
+      float r[12];
+      for (int c = 0; c < 12; ++c) r[c] = mine ? v[c] : 0.f;
+      for (int m = 32; m >= 1; m >>= 1)
+        for (int c = 0; c < 12; ++c) r[c] += __shfl_xor(r[c], m);
+      if (lane == 0)
+        for (int c = 0; c < 12; ++c) acc[wv][kk][c] += r[c];
+      todo &= ~__ballot(mine);
     }
   }
   __syncthreads();
-  // sums over the threads in order, per (sphere, value)
   for (int u = t; u < ns * 12; u += kGradThreads) {
     const int k = u / 12, c = u % 12;
-    float s = 0.f;
-    for (int r = 0; r < kGradThreads; ++r) s += acc[r][k][c];
-    acc[0][k][c] = s;
+    float s = acc[0][k][c];
+    for (int q = 1; q < kGradWaves; ++q) s += acc[q][k][c];
+    tot[k][c] = s;
   }
   __syncthreads();
-  // the env's bodies: zero, then each sphere's sums added to its body in
-  // sphere order (one thread per value)
+  // the env's bodies: each sphere's sums added to its body in sphere order
+  // (one thread per value)
   const int b0 = sc.env_body[e], b1 = sc.env_body[e + 1];
   for (int u = t; u < (b1 - b0) * 18; u += kGradThreads) {
     const int b = b0 + u / 18, c = u % 18;
     float s = 0.f;
     if (c < 12)
       for (int k = 0; k < ns; ++k)
-        if (sc.sph_body[s0 + k] == b) s += acc[0][k][c];
+        if (sc.sph_body[s0 + k] == b) s += tot[k][c];
     g_x[(size_t)c * sc.B + b] = s;
   }
 }

@@ -395,22 +395,29 @@ class Simulator:
         g["g_anchor_c"] = g["g_anchor_c"][: 3 * J].view(J, 3)
         return g
 
-    def render(self, x, cam, tex_sphere, tex_ground, cell):
+    def render(self, x, cam, tex_sphere, tex_ground, cell, out=None):
         """Image [E, H, W] (CUDA float32) of the state x ([18, B] CUDA
         float32) seen by cam (a dict as workloads.pinhole_camera makes);
-        textures are CUDA float32 [ny, nx] tensors (sim_render)."""
+        textures are CUDA float32 [ny, nx] tensors (sim_render).  `out`, if
+        given, is the image tensor to write."""
         c = camera(cam)
         t = self._textures(tex_sphere, tex_ground, cell)
-        img = self.torch.empty((self.info.n_envs, c.height, c.width), dtype=self.torch.float32, device="cuda")
+        shape = (self.info.n_envs, c.height, c.width)
+        img = self.torch.empty(shape, dtype=self.torch.float32, device="cuda") if out is None else out
+        if tuple(img.shape) != shape or img.dtype != self.torch.float32 or not img.is_cuda or not img.is_contiguous():
+            raise ValueError(f"out must be a contiguous CUDA float32 tensor of shape {shape}")
         _check(self.lib, self.lib.sim_render(self.h, _ptr(x), C.byref(c), C.byref(t), _ptr(img), self._stream()),
                "sim_render")
         return img
 
-    def render_grad(self, x, cam, tex_sphere, tex_ground, cell, weights):
-        """dL/dx [18, B] for L = sum(weights * image) (sim_render_grad)."""
+    def render_grad(self, x, cam, tex_sphere, tex_ground, cell, weights, out=None):
+        """dL/dx [18, B] for L = sum(weights * image) (sim_render_grad);
+        `out`, if given, is the tensor to write (x's shape)."""
         c = camera(cam)
         t = self._textures(tex_sphere, tex_ground, cell)
-        g = self.torch.empty_like(x)
+        g = self.torch.empty_like(x) if out is None else out
+        if g.shape != x.shape or g.dtype != x.dtype or not g.is_cuda or not g.is_contiguous():
+            raise ValueError("out must be a contiguous CUDA tensor shaped like x")
         _check(self.lib, self.lib.sim_render_grad(self.h, _ptr(x), C.byref(c), C.byref(t), _ptr(weights), _ptr(g),
                                                   self._stream()), "sim_render_grad")
         return g
