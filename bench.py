@@ -37,11 +37,13 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 # The size buckets of an uneven workload run at once, one stream each.  HIP
-# maps streams onto GPU_MAX_HW_QUEUES hardware queues (4 unless set), and the
-# kernels of streams that share a queue run one after another: with 17
-# buckets, 4 queues serialise them into 4 chains.  Unless the caller set it,
-# give every bucket a queue of its own (read once, when HIP starts).
-os.environ.setdefault("GPU_MAX_HW_QUEUES", "32")
+# maps streams onto GPU_MAX_HW_QUEUES hardware queues (4 unless set, and
+# machines may export 4), and the kernels of streams that share a queue run
+# one after another: 16 buckets on 4 queues run as 4 serial chains (measured:
+# 1988 ms per chains step against 1896 ms with a queue per bucket).  Give
+# every bucket a queue of its own: at least 32 (read once, when HIP starts).
+if int(os.environ.get("GPU_MAX_HW_QUEUES", "0") or 0) < 32:
+    os.environ["GPU_MAX_HW_QUEUES"] = "32"
 
 METRIC = "fwd+adjoint env-steps/s at grad rel-err<=1e-3 vs FP64 oracle; % HBM roofline"
 HBM_PEAK_GBS = 8000.0
@@ -351,6 +353,9 @@ def main():
     ap.add_argument("--no-keep", action="store_true",
                     help="in trajectory mode, recompute the working sets from the checkpoints instead of keeping "
                          "them in the rollout")
+    ap.add_argument("--fuse", action="store_true",
+                    help="with kept working sets, call rollout_and_grad (each bucket's reverse right after its own "
+                         "forward) instead of rollout_keep and rollout_grad_kept one after the other")
     ap.add_argument("--grad-mem-gib", type=float, default=None,
                     help="memory for the reverse sweep's saved working sets (default: what the device has free "
                          "less a 12 GiB margin)")
@@ -386,10 +391,16 @@ def main():
     # trajectory mode: the rollout keeps every step's working set in the
     # workspace and the reverse reads them without recomputing them
     keep = ws_buf if sim.info.grad_store == 3 and not args.no_keep else None
+    fused = keep is not None and args.fuse
+
+    def one_step():
+        if fused:
+            return sim.rollout_and_grad(x0, u, dl, keep)
+        r = sim.rollout(x0, u, want_ckpt=True, want_final=False, keep=keep)
+        return r, sim.rollout_grad(x0, u, r["ckpt"], dl, workspace=ws_buf, kept=keep)
 
     for _ in range(args.warmup):
-        r = sim.rollout(x0, u, want_ckpt=True, want_final=False, keep=keep)
-        sim.rollout_grad(x0, u, r["ckpt"], dl, workspace=ws_buf, kept=keep)
+        one_step()
     torch.cuda.synchronize()
     mk = lambda: torch.cuda.Event(enable_timing=True)   # noqa: E731
     n_b = len(sim.teams())
@@ -404,14 +415,22 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
-        fwd_evs[k][0].record()
-        r = sim.rollout(x0, u, want_ckpt=True, want_final=False, keep=keep)
-        fwd_evs[k][1].record()
         sim.time_grad(phase_evs[k])
         sim.time_buckets(bucket_evs[k])
-        evs[k][0].record()
-        g = sim.rollout_grad(x0, u, r["ckpt"], dl, workspace=ws_buf, kept=keep)
-        evs[k][1].record()
+        if fused:
+            # one call: the "reverse" phase events span it
+            fwd_evs[k][0].record()
+            r, g = sim.rollout_and_grad(x0, u, dl, keep)
+            fwd_evs[k][1].record()
+            evs[k][0].record()
+            evs[k][1].record()
+        else:
+            fwd_evs[k][0].record()
+            r = sim.rollout(x0, u, want_ckpt=True, want_final=False, keep=keep)
+            fwd_evs[k][1].record()
+            evs[k][0].record()
+            g = sim.rollout_grad(x0, u, r["ckpt"], dl, workspace=ws_buf, kept=keep)
+            evs[k][1].record()
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     sim.time_grad(None)
@@ -420,6 +439,17 @@ def main():
     ms_per_step = el * 1e3 / args.steps
     grad_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
     fwd_ms = float(np.mean([a.elapsed_time(b) for a, b in fwd_evs]))
+    call_ms = fwd_ms if fused else None
+    if fused:
+        # the forward's own rate: the keeping rollout alone, after the timed
+        # region (the fused call cannot separate it)
+        fe = [(mk(), mk()) for _ in range(args.steps)]
+        for a_, b_ in fe:
+            a_.record()
+            sim.rollout(x0, u, want_ckpt=False, want_final=False, keep=keep)
+            b_.record()
+        torch.cuda.synchronize()
+        fwd_ms, grad_ms = float(np.mean([a.elapsed_time(b) for a, b in fe])), None
     rec_ms = float(np.mean([p[0].elapsed_time(p[1]) for p in phase_evs]))
     rev_ms = float(np.mean([p[2].elapsed_time(p[3]) for p in phase_evs]))
     bucket_ms = np.array([[p[2 * i].elapsed_time(p[2 * i + 1]) for i in range(n_b)] for p in bucket_evs]).mean(0)
@@ -437,12 +467,14 @@ def main():
     # mode) the forward besides reversing it
     k_fwd = {"trajectory": 0, "segment": 1, "replay": 2}[mode]
     kern_flops_env = (f_rev + k_fwd * f_fwd) * T_env
+    # the fused call's span holds the forward kernels too
+    call_flops_env = kern_flops_env + (f_fwd * T_env if fused else 0.0)
     of_env = sim.env_buckets()
     bucket_flops = np.array([kern_flops_env[of_env == i].sum() for i in range(n_b)])
     dom = int(np.argmax(bucket_ms))
     teams = sim.teams()
     achieved = bucket_flops[dom] / (bucket_ms[dom] * 1e-3) / 1e12
-    phase_tflops = kern_flops_env.sum() / (rev_ms * 1e-3) / 1e12
+    phase_tflops = call_flops_env.sum() / (rev_ms * 1e-3) / 1e12
     # (a forward that keeps the working sets leaves the reverse no recompute)
     rec_tflops = float((f_fwd * T_env).sum() / (rec_ms * 1e-3) / 1e12) if mode == "trajectory" and keep is None \
         else None
@@ -452,6 +484,10 @@ def main():
     # (None unless measured on the current kernel sources)
     traffic = TR.load(args.workload, all_buckets=True)
     traffic_dom = TR.load(args.workload, bucket=dom)
+    if fused and traffic is not None:
+        # the fused call's span holds the forward kernels' launches too
+        fwd_traffic = TR.load_other(args.workload, "k_rollout_keep", n_b)
+        traffic = None if fwd_traffic is None else traffic + fwd_traffic
 
     got = None
     if not args.no_check and args.workload != "quadruped":
@@ -479,17 +515,21 @@ def main():
         "grad_ms": grad_ms,
         "grad_store": mode,
         "forward_keeps_working_sets": keep is not None,
+        "fused_call": fused,
+        "fused_call_ms": call_ms,
         "grad_phases_ms": {"recompute": rec_ms, "reverse": rev_ms},
         "grad_check": None,
         "env_flags_nonzero": int((flags != 0).sum()),
         # the reverse kernel of one call: one launch per size bucket, all
         # running at once on forked streams and sharing the CUs, timed from
         # the first launch's start to the last one's end
-        "roofline": {"bound": "alu", "kernel": f"k_rollout_grad ({n_b} concurrent bucket launches)"
+        "roofline": {"bound": "alu", "kernel": (f"k_rollout_keep + k_rollout_grad ({n_b} concurrent bucket "
+                                                "pipelines, one rollout_and_grad call)") if fused else
+                     f"k_rollout_grad ({n_b} concurrent bucket launches)"
                      if n_b > 1 else f"k_rollout_grad<{int(teams[0])}, {0 if mode == 'replay' else 1}>",
                      "achieved": phase_tflops, "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": phase_tflops / FP32_VECTOR_PEAK_TFLOPS, "traffic": traffic,
-                     "flops_per_launch": float(kern_flops_env.sum()), "kernel_ms": rev_ms},
+                     "flops_per_launch": float(call_flops_env.sum()), "kernel_ms": rev_ms},
         # the longest of those launches, timed on its own stream (its share
         # of the CUs varies as the other buckets start and finish)
         "dominant_launch": {"kernel": f"k_rollout_grad<{int(teams[dom])}, {0 if mode == 'replay' else 1}>",

@@ -57,7 +57,7 @@
 extern "C" {
 #endif
 
-#define SIM_ABI_VERSION 9
+#define SIM_ABI_VERSION 10
 
 typedef struct sim_model* sim_handle;
 
@@ -352,6 +352,22 @@ sim_status rollout_grad_kept(sim_handle h, const float* x0, const float* u, cons
                              float* g_u, float* g_inv_mass, float* g_inv_inertia, float* g_mu, float* g_damping,
                              float* g_anchor_p, float* g_anchor_c, void* workspace, size_t workspace_bytes,
                              uint32_t* env_flags, void* stream);
+
+/* Forward and reverse mode in one call (trajectory mode, fixed-sweep
+ * models): rollout_keep followed by rollout_grad_kept, with the same
+ * arguments and the same results bit for bit, except that each size bucket's
+ * reverse sweep starts as soon as that bucket's own forward has finished
+ * instead of after the slowest bucket's (the buckets join once, at the end).
+ * The upstream dL/dloss_env must therefore be known before the call (e.g. a
+ * sum or mean of the envs' losses).  env_flags (nullable) receives the
+ * forward's flags, grad_flags (nullable) the reverse's, as the two calls
+ * write them.  While sim_time_grad events are set, the "reverse" pair spans
+ * the whole call and the recompute pair is empty. */
+sim_status rollout_and_grad(sim_handle h, const float* x0, const float* u, float* loss_env, float* x_final,
+                            float* lam_final, float* ckpt, uint32_t* env_flags, const float* dloss_env, float* g_x0,
+                            float* g_u, float* g_inv_mass, float* g_inv_inertia, float* g_mu, float* g_damping,
+                            float* g_anchor_p, float* g_anchor_c, void* workspace, size_t workspace_bytes,
+                            uint32_t* grad_flags, void* stream);
 
 /* Allocation-free reverse mode, for callers that cannot allocate device
  * memory (code under HIP graph capture, tight serving or training loops,

@@ -856,6 +856,51 @@ sim_status rollout_grad_kept(sim_handle h, const float* x0, const float* u, cons
                          g_anchor_p, g_anchor_c, workspace, env_flags, stream, true);
 }
 
+sim_status rollout_and_grad(sim_handle h, const float* x0, const float* u, float* loss_env, float* x_final,
+                            float* lam_final, float* ckpt, uint32_t* env_flags, const float* dloss_env, float* g_x0,
+                            float* g_u, float* g_inv_mass, float* g_inv_inertia, float* g_mu, float* g_damping,
+                            float* g_anchor_p, float* g_anchor_c, void* workspace, size_t workspace_bytes,
+                            uint32_t* grad_flags, void* stream) {
+  if (!h) return fail(SIM_E_ARG, "rollout_and_grad: null handle");
+  if (h->M.solve_mode != SIM_SOLVE_FIXED)
+    return fail(SIM_E_UNSUPPORTED, "rollout_and_grad: the gradient is of the fixed-sweep step (solve_mode 0)");
+  if (h->M.dump != DUMP_TRAJECTORY)
+    return fail(SIM_E_UNSUPPORTED, "rollout_and_grad: the model's reverse sweep is not in trajectory mode "
+                                   "(sim_info.grad_store; raise grad_mem_limit or set SIM_GRAD_TRAJECTORY)");
+  if (h->M.n_envs == 0) return SIM_OK;
+  if (!x0 || !loss_env || !dloss_env) return fail(SIM_E_ARG, "rollout_and_grad: null x0, loss_env or dloss_env");
+  if (h->M.J > 0 && h->M.T_max > 0 && !u) return fail(SIM_E_ARG, "rollout_and_grad: null control tape");
+  if (!workspace || (int64_t)workspace_bytes < h->info.workspace_bytes)
+    return fail(SIM_E_NOMEM, "rollout_and_grad: workspace smaller than sim_info.workspace_bytes (" +
+                                 std::to_string(h->info.workspace_bytes) + ")");
+  sim_status s = check_device("rollout_and_grad (earlier fault)");
+  if (s != SIM_OK) return s;
+  hipStream_t st = (hipStream_t)stream;
+  float* ws = (float*)workspace;
+  RolloutArgs ra{x0, u, loss_env, x_final, lam_final, ckpt, env_flags, nullptr, nullptr, RecArgs{nullptr, 0, nullptr, 0},
+                 ws};
+  GradArgs ga{x0,   u,         nullptr,    dloss_env,  g_x0, g_u, g_inv_mass, g_inv_inertia,
+              g_mu, g_damping, g_anchor_p, g_anchor_c, ws,   grad_flags};
+  DevModel Mf = h->M;
+  if (!prep_controls(h, Mf, u, st)) return check_device("rollout_and_grad controls");
+  DevModel Mg = Mf;
+  Mg.tape = ws + h->seg_floats;
+  auto mark = [&](int k) { return !h->tev[k] || hipEventRecord(h->tev[k], st) == hipSuccess; };
+  if (!mark(0) || !mark(1) || !mark(2)) return check_device("rollout_and_grad timing event");
+  // a bucket's reverse follows its own forward on its stream; the buckets
+  // join once, after both
+  s = run_buckets(h, st, [&](size_t i, hipStream_t sx) {
+        return bucket_rollout(h, i, Mf, ra, sx) && bucket_reverse(h, i, Mg, ga, sx);
+      }, "rollout_and_grad launch");
+  if (s != SIM_OK) return s;
+  if (!mark(3)) return check_device("rollout_and_grad timing event");
+  if (!Mg.ctrl || !g_u) return s;
+  if (launch_wgrad(Mg.tape, Mg.tape_stride, (int)h->tape_rows, h->chunk, h->d_tiles, h->n_wtiles,
+                   Mg.tape + h->tape_floats, h->d_map, h->n_params, g_u, st) != hipSuccess)
+    return check_device("rollout_and_grad weight gradient");
+  return SIM_OK;
+}
+
 sim_status sim_time_grad(sim_handle h, void* const* ev) {
   if (!h) return fail(SIM_E_ARG, "sim_time_grad: null handle");
   for (int k = 0; k < 4; ++k) {

@@ -20,7 +20,7 @@ FLAG_NONFINITE = 1
 FLAG_CONTACT_OVERFLOW = 2
 
 # layout of the descriptor and info structs below (SIM_ABI_VERSION)
-ABI_VERSION = 9
+ABI_VERSION = 10
 
 # reverse sweep memory modes (sim_model_desc.grad_store)
 GRAD_STORE = {"auto": 0, "replay": 1, "segment": 2, "trajectory": 3}
@@ -163,6 +163,7 @@ def library():
     lib.rollout_grad_noalloc.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     lib.rollout_keep.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, C.c_size_t, vp]
     lib.rollout_grad_kept.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, C.c_size_t, vp, vp]
+    lib.rollout_and_grad.argtypes = [vp] * 18 + [C.c_size_t, vp, vp]
     lib.rollout_solve.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, C.c_int64, vp, C.c_int32, vp]
     lib.sim_describe_order.argtypes = [C.POINTER(SimDesc), C.c_int32, _I32P, _I32P, C.c_int32]
     lib.sim_describe_order.restype = C.c_int32
@@ -191,7 +192,7 @@ def library():
                "rollout_grad", "rollout_grad_noalloc", "rollout_keep", "rollout_grad_kept", "sim_time_buckets",
                "sim_env_buckets", "sim_step_graph", "sim_graph_launch", "sim_graph_destroy", "sim_set_teams",
                "wsn_to_bf16", "wsn_forward", "wsn_loss_grad", "wsn_adam", "rollout_solve", "sim_adam", "sim_render",
-               "sim_render_grad"):
+               "sim_render_grad", "rollout_and_grad"):
         getattr(lib, fn).restype = C.c_int
     if lib.sim_abi_version() != ABI_VERSION:
         raise RuntimeError(f"{LIB_PATH} has ABI version {lib.sim_abi_version()}, this binding expects "
@@ -205,7 +206,8 @@ EXPORTED = ["sim_abi_version", "sim_last_error", "sim_init", "sim_destroy", "sim
             "sim_step_graph", "sim_graph_launch", "sim_graph_destroy", "sim_tune", "sim_get_teams",
             "sim_set_teams", "wsn_to_bf16", "wsn_forward", "wsn_workspace_bytes", "wsn_loss_grad", "wsn_adam",
             "rollout_solve", "sim_adam", "sim_time_grad", "rollout_grad_noalloc", "sim_time_buckets",
-            "sim_env_buckets", "rollout_keep", "rollout_grad_kept", "sim_render", "sim_render_grad"]
+            "sim_env_buckets", "rollout_keep", "rollout_grad_kept", "sim_render", "sim_render_grad",
+            "rollout_and_grad"]
 
 
 class SimCamera(C.Structure):
@@ -300,6 +302,17 @@ class Simulator:
     def _stream(self):
         return C.c_void_p(self.torch.cuda.current_stream().cuda_stream)
 
+    def _controls(self, u):
+        """The control input must hold what the library reads from it: the
+        controller's weights (n_params floats) or the tape [T_max][J]."""
+        need = self.info.n_params if self.info.n_params else self.w.T_max * self.info.n_joints
+        if need and (u is None or u.numel() < need or u.dtype != self.torch.float32 or not u.is_cuda
+                     or not u.is_contiguous()):
+            what = "controller weights" if self.info.n_params else "torque tape [T_max, J]"
+            raise ValueError(f"the control input must be a contiguous CUDA float32 tensor of at least {need} "
+                             f"floats (the {what})")
+        return _ptr(u)
+
     def _f32(self, n):
         return self.torch.zeros(max(int(n), 1), dtype=self.torch.float32, device="cuda")
 
@@ -314,12 +327,12 @@ class Simulator:
         out["lam_final"] = self._f32(self.info.lam_size) if want_final else None
         out["ckpt"] = self._f32(self.info.ckpt_floats) if want_ckpt else None
         if keep is not None:
-            st = self.lib.rollout_keep(self.h, _ptr(x0), _ptr(u), _ptr(out["loss"]), _ptr(out["x_final"]),
+            st = self.lib.rollout_keep(self.h, _ptr(x0), self._controls(u), _ptr(out["loss"]), _ptr(out["x_final"]),
                                        _ptr(out["lam_final"]), _ptr(out["ckpt"]), _ptr(out["flags"]), _ptr(keep),
                                        keep.numel() * 4, self._stream())
             _check(self.lib, st, "rollout_keep")
         else:
-            st = self.lib.rollout(self.h, _ptr(x0), _ptr(u), _ptr(out["loss"]), _ptr(out["x_final"]),
+            st = self.lib.rollout(self.h, _ptr(x0), self._controls(u), _ptr(out["loss"]), _ptr(out["x_final"]),
                                   _ptr(out["lam_final"]), _ptr(out["ckpt"]), _ptr(out["flags"]), self._stream())
             _check(self.lib, st, "rollout")
         out["loss"] = out["loss"][:E]
@@ -338,7 +351,7 @@ class Simulator:
         out["lam_final"] = self._f32(self.info.lam_size) if want_final else None
         rec = t.zeros((max(int(rec_cap), 1), 16), device="cuda") if rec_cap > 0 else None
         cnt = t.zeros(1, dtype=t.int64, device="cuda")
-        st = self.lib.rollout_solve(self.h, _ptr(x0), _ptr(u), _ptr(out["loss"]), _ptr(out["x_final"]),
+        st = self.lib.rollout_solve(self.h, _ptr(x0), self._controls(u), _ptr(out["loss"]), _ptr(out["x_final"]),
                                     _ptr(out["lam_final"]), _ptr(out["flags"]), _ptr(out["iters"]),
                                     _ptr(out["fallbacks"]), _ptr(rec), int(rec_cap), _ptr(cnt), int(rec_every),
                                     self._stream())
@@ -359,10 +372,26 @@ class Simulator:
         workspace), or with kept the workspace a rollout(keep=...) filled
         (rollout_grad_kept, no recompute).  The output tensors are allocated
         here either way."""
-        E, B, J = self.info.n_envs, self.info.n_bodies, self.info.n_joints
         ws = None
         if not no_alloc and kept is None:
             ws = workspace if workspace is not None else self.workspace()
+        g, outs = self._grad_outputs()
+        if kept is not None:
+            st = self.lib.rollout_grad_kept(self.h, _ptr(x0), self._controls(u), _ptr(dloss), *outs, _ptr(kept),
+                                            kept.numel() * 4, _ptr(g["flags"]), self._stream())
+            _check(self.lib, st, "rollout_grad_kept")
+        elif no_alloc:
+            st = self.lib.rollout_grad_noalloc(self.h, _ptr(x0), self._controls(u), _ptr(ckpt), _ptr(dloss), *outs,
+                                               _ptr(g["flags"]), self._stream())
+            _check(self.lib, st, "rollout_grad_noalloc")
+        else:
+            st = self.lib.rollout_grad(self.h, _ptr(x0), self._controls(u), _ptr(ckpt), _ptr(dloss), *outs, _ptr(ws),
+                                       ws.numel() * 4, _ptr(g["flags"]), self._stream())
+            _check(self.lib, st, "rollout_grad")
+        return self._grad_views(g)
+
+    def _grad_outputs(self):
+        E, B, J = self.info.n_envs, self.info.n_bodies, self.info.n_joints
         nu = self.info.n_params if self.info.n_params else self.w.T_max * J
         g = dict(g_x0=self._f32(18 * B).view(18, -1), g_u=self._f32(nu),
                  g_inv_mass=self._f32(B), g_inv_inertia=self._f32(3 * B), g_mu=self._f32(E), g_damping=self._f32(J),
@@ -370,18 +399,10 @@ class Simulator:
                  flags=self.torch.zeros(max(E, 1), dtype=self.torch.int32, device="cuda"))
         outs = [_ptr(g[k]) for k in ("g_x0", "g_u", "g_inv_mass", "g_inv_inertia", "g_mu", "g_damping",
                                      "g_anchor_p", "g_anchor_c")]
-        if kept is not None:
-            st = self.lib.rollout_grad_kept(self.h, _ptr(x0), _ptr(u), _ptr(dloss), *outs, _ptr(kept),
-                                            kept.numel() * 4, _ptr(g["flags"]), self._stream())
-            _check(self.lib, st, "rollout_grad_kept")
-        elif no_alloc:
-            st = self.lib.rollout_grad_noalloc(self.h, _ptr(x0), _ptr(u), _ptr(ckpt), _ptr(dloss), *outs,
-                                               _ptr(g["flags"]), self._stream())
-            _check(self.lib, st, "rollout_grad_noalloc")
-        else:
-            st = self.lib.rollout_grad(self.h, _ptr(x0), _ptr(u), _ptr(ckpt), _ptr(dloss), *outs, _ptr(ws),
-                                       ws.numel() * 4, _ptr(g["flags"]), self._stream())
-            _check(self.lib, st, "rollout_grad")
+        return g, outs
+
+    def _grad_views(self, g):
+        E, B, J = self.info.n_envs, self.info.n_bodies, self.info.n_joints
         if self.info.n_params:
             g["g_u"] = g["g_u"][: self.info.n_params]
         else:
@@ -394,6 +415,27 @@ class Simulator:
         g["g_anchor_p"] = g["g_anchor_p"][: 3 * J].view(J, 3)
         g["g_anchor_c"] = g["g_anchor_c"][: 3 * J].view(J, 3)
         return g
+
+    def rollout_and_grad(self, x0, u, dloss, workspace, want_ckpt=False, want_final=False):
+        """Forward and reverse mode in one call (rollout_and_grad, trajectory
+        mode): each size bucket's reverse follows its own forward.  Returns
+        (the rollout's outputs, the gradients), as rollout(keep=workspace)
+        and rollout_grad(kept=workspace) would."""
+        t = self.torch
+        E = self.info.n_envs
+        out = dict(loss=self._f32(E), flags=t.zeros(max(E, 1), dtype=t.int32, device="cuda"))
+        out["x_final"] = self._f32(18 * self.info.n_bodies).view(18, -1) if want_final else None
+        out["lam_final"] = self._f32(self.info.lam_size) if want_final else None
+        out["ckpt"] = self._f32(self.info.ckpt_floats) if want_ckpt else None
+        g, outs = self._grad_outputs()
+        st = self.lib.rollout_and_grad(self.h, _ptr(x0), self._controls(u), _ptr(out["loss"]), _ptr(out["x_final"]),
+                                       _ptr(out["lam_final"]), _ptr(out["ckpt"]), _ptr(out["flags"]), _ptr(dloss),
+                                       *outs, _ptr(workspace), workspace.numel() * 4, _ptr(g["flags"]),
+                                       self._stream())
+        _check(self.lib, st, "rollout_and_grad")
+        out["loss"] = out["loss"][:E]
+        out["flags"] = out["flags"][:E]
+        return out, self._grad_views(g)
 
     def render(self, x, cam, tex_sphere, tex_ground, cell, out=None):
         """Image [E, H, W] (CUDA float32) of the state x ([18, B] CUDA
@@ -505,7 +547,7 @@ class Simulator:
         returns the chosen widths.  Results do not depend on them."""
         n = self.lib.sim_get_teams(self.h, None, 0)
         out = np.zeros(max(n, 1), np.int32)
-        r = self.lib.sim_tune(self.h, _ptr(x0), _ptr(u), int(bool(with_grad)), int(max_candidates),
+        r = self.lib.sim_tune(self.h, _ptr(x0), self._controls(u), int(bool(with_grad)), int(max_candidates),
                               out.ctypes.data_as(_I32P), n, self._stream())
         _check(self.lib, min(r, 0), "sim_tune")
         return out[:n].copy()

@@ -163,6 +163,22 @@ def load(workload, bucket=None, all_buckets=False):
     return t.get("bytes_per_launch")
 
 
+def load_other(workload, kernel, launches):
+    """Bytes of `launches` launches of another kernel of the same run (the
+    mean per launch times the count), or None as load()."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        t = json.load(open(path))
+    except Exception:
+        return None
+    o = (t.get("other_kernels") or {}).get(kernel)
+    if t.get("kernel_source_hash") != source_hash() or not o:
+        return None
+    return float(launches * (o["fetch_bytes_per_launch"] + o["write_bytes_per_launch"]))
+
+
 if __name__ == "__main__":
     ap = argparse.ArgumentParser()
     ap.add_argument("cmd", choices=["copy", "summarize", "hash"])

@@ -407,6 +407,40 @@ def test_rollout_keep_and_grad_kept_equal_rollout_and_grad(make):
         assert torch.equal(g[k], gk[k]), k
 
 
+@pytest.mark.parametrize("make", [lambda: W.planar_arms(n_envs=40, T=130),
+                                  lambda: W.uneven_chains(n_envs=48, T=110, seed_salt=5),
+                                  lambda: W.quadruped(n_envs=24, T_min=20, T_max=45,
+                                                      mlp_w=W.mlp_init(zero_output=False, out_scale=0.1))])
+def test_rollout_and_grad_equals_rollout_keep_and_grad_kept(make):
+    # the fused call (each bucket's reverse right after its own forward, one
+    # join) gives the bits of rollout_keep + rollout_grad_kept, including the
+    # controller's weight gradient; run twice to see that nothing depends on
+    # what an earlier call left in the workspace
+    import torch
+    from paper_1611_01652_amd.sim import Simulator
+    w = make()
+    w.extra = dict(w.extra or {}, grad_store="trajectory")
+    s = Simulator(w)
+    _say("case rollout_and_grad", w.name, w.n_envs, "buckets", len(s.teams()))
+    x0, u = to_dev(w)
+    mlp = (w.extra or {}).get("mlp")
+    if mlp is not None:
+        u = torch.tensor(np.asarray(mlp["w"], np.float32), device="cuda")
+    dl = torch.linspace(0.5, 1.5, w.n_envs, device="cuda")
+    ws = s.workspace()
+    rk = s.rollout(x0, u, keep=ws)
+    gk = s.rollout_grad(x0, u, None, dl, kept=ws)
+    ws2 = s.workspace()
+    for _ in range(2):
+        rf, gf = s.rollout_and_grad(x0, u, dl, ws2, want_ckpt=True, want_final=True)
+        torch.cuda.synchronize()
+        for k in ("loss", "x_final", "lam_final", "ckpt", "flags"):
+            assert torch.equal(rk[k][: rf[k].numel()].reshape(rf[k].shape), rf[k]), k
+        for k in ("g_x0", "g_u", "g_inv_mass", "g_inv_inertia", "g_mu", "g_damping", "g_anchor_p", "g_anchor_c",
+                  "flags"):
+            assert torch.equal(gk[k], gf[k]), k
+
+
 def test_rollout_keep_is_refused_outside_trajectory_mode():
     import torch
     from paper_1611_01652_amd.sim import SimError, Simulator
@@ -419,3 +453,5 @@ def test_rollout_keep_is_refused_outside_trajectory_mode():
         s.rollout(x0, u, keep=ws)
     with pytest.raises(SimError, match="trajectory"):
         s.rollout_grad(x0, u, None, torch.ones(w.n_envs, device="cuda"), kept=ws)
+    with pytest.raises(SimError, match="trajectory"):
+        s.rollout_and_grad(x0, u, torch.ones(w.n_envs, device="cuda"), ws)
