@@ -319,9 +319,13 @@ def bench_camera(args):
     n_pix = img.numel()
     ns = np.diff(w.env_sphere_off)
     flops = float(cam["width"] * cam["height"] * (CAM_RAY_FLOPS + CAM_SPHERE_FLOPS * ns).sum())
+    from paper_1611_01652_amd import traffic as TR
+    # HBM bytes per launch from the counters (None unless measured on the
+    # current kernel sources)
+    traffic = {"k_render_grad": TR.load("camera"), "k_render": TR.load_other("camera", "k_render", 1)}
     roof = lambda ms, name: {   # noqa: E731
         "bound": "alu", "kernel": name, "achieved": flops / (ms * 1e-3) / 1e12, "peak": FP32_VECTOR_PEAK_TFLOPS,
-        "unit": "TFLOP/s", "frac": flops / (ms * 1e-3) / 1e12 / FP32_VECTOR_PEAK_TFLOPS, "traffic": None,
+        "unit": "TFLOP/s", "frac": flops / (ms * 1e-3) / 1e12 / FP32_VECTOR_PEAK_TFLOPS, "traffic": traffic[name],
         "flops_per_launch": flops, "kernel_ms": ms}
     line = {
         "metric": "camera image + gradient pixels/s", "value": n_pix / (el / args.steps), "unit": "pixels/s",

@@ -17,7 +17,9 @@ the profiler's output):
     python3 -m paper_1611_01652_amd.traffic summarize --workload arms --dir $OUT
 
 The summary (profiles/traffic_<workload>.json) holds the bytes per launch of
-k_rollout_grad and a hash of the kernel sources it was measured with; the
+k_rollout_grad (or, with --kernel, another kernel: the camera's workload
+`camera` takes k_render_grad) and a hash of the kernel sources it was
+measured with; the
 benchmark reports it only while the sources are unchanged.  With --buckets n
 (a workload whose envs run in n size buckets, one reverse kernel launch each
 per call, launched in bucket order) it also holds the bytes of each bucket's
@@ -36,12 +38,14 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 KERNEL_SOURCES = ["csrc/sim_kernels.hip", "csrc/step_core.h", "csrc/drivers.h"]
+# the sources of a workload's kernels where they are not the step's
+WORKLOAD_SOURCES = {"camera": ["csrc/render_kernels.hip"]}
 COPY_MIB = 1024
 
 
-def source_hash():
+def source_hash(workload=None):
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in WORKLOAD_SOURCES.get(workload, KERNEL_SOURCES):
         with open(os.path.join(HERE, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -118,20 +122,20 @@ def summarize(workload, d, kernel="k_rollout_grad", buckets=None):
                fetch_scale=sf, write_scale=sw,
                bytes_per_launch=(kf / sf + kw / sw) * 1024.0,
                fetch_bytes_per_launch=kf / sf * 1024.0, write_bytes_per_launch=kw / sw * 1024.0,
-               kernel_source_hash=source_hash())
+               kernel_source_hash=source_hash(workload))
     if buckets:
         bf = by_bucket(os.path.join(d, f"pmc_{workload}_f"), "FETCH_SIZE", kernel, buckets)
         bw = by_bucket(os.path.join(d, f"pmc_{workload}_w"), "WRITE_SIZE", kernel, buckets)
         out["bytes_per_launch_by_bucket"] = [(f / sf + w / sw) * 1024.0 for f, w in zip(bf, bw)]
     # the other kernels of the gradient and the forward, when the run has them
-    for other in ("k_recompute", "k_rollout<", "k_rollout_keep"):
+    for other in ("k_recompute", "k_rollout<", "k_rollout_keep", "k_render("):
         try:
             of, _, _ = per_dispatch(read_counters(os.path.join(d, f"pmc_{workload}_f"), "FETCH_SIZE"),
                                     lambda k: other in k)
             ow, _, _ = per_dispatch(read_counters(os.path.join(d, f"pmc_{workload}_w"), "WRITE_SIZE"),
                                     lambda k: other in k)
             out["other_kernels"] = out.get("other_kernels", {})
-            out["other_kernels"][other.rstrip("<")] = dict(fetch_bytes_per_launch=of / sf * 1024.0,
+            out["other_kernels"][other.rstrip("<(")] = dict(fetch_bytes_per_launch=of / sf * 1024.0,
                                                            write_bytes_per_launch=ow / sw * 1024.0)
         except KeyError:
             pass
@@ -153,7 +157,7 @@ def load(workload, bucket=None, all_buckets=False):
         t = json.load(open(path))
     except Exception:
         return None
-    if t.get("kernel_source_hash") != source_hash():
+    if t.get("kernel_source_hash") != source_hash(workload):
         return None
     b = t.get("bytes_per_launch_by_bucket")
     if b and all_buckets:
@@ -174,7 +178,7 @@ def load_other(workload, kernel, launches):
     except Exception:
         return None
     o = (t.get("other_kernels") or {}).get(kernel)
-    if t.get("kernel_source_hash") != source_hash() or not o:
+    if t.get("kernel_source_hash") != source_hash(workload) or not o:
         return None
     return float(launches * (o["fetch_bytes_per_launch"] + o["write_bytes_per_launch"]))
 
@@ -185,13 +189,14 @@ if __name__ == "__main__":
     ap.add_argument("--workload", default="arms")
     ap.add_argument("--dir", help="directory holding the profiler's pmc_* output folders")
     ap.add_argument("--buckets", type=int, default=None, help="size buckets of the workload (one launch each per call)")
+    ap.add_argument("--kernel", default="k_rollout_grad", help="the kernel whose launches are summarized")
     a = ap.parse_args()
     if a.cmd == "copy":
         copy_main()
     elif a.cmd == "summarize":
         if not a.dir:
             ap.error("summarize needs --dir")
-        summarize(a.workload, a.dir, buckets=a.buckets)
+        summarize(a.workload, a.dir, kernel=a.kernel, buckets=a.buckets)
     else:
-        print(source_hash())
+        print(source_hash(a.workload))
     sys.exit(0)
