@@ -2,7 +2,7 @@
 chain distribution solved to 1e-5 (tolerance mode, cap 1000 sweeps):
 
 1. label: the plain solver writes (features, converged impulse) records of
-   every converged contact on 8192 training envs x 500 steps;
+   every converged contact on 10752 training envs x 500 steps (10 M records);
 2. train: the per-contact network on those records (BF16 matrix-core
    forward/backward, FP32 Adam, Huber loss on corrections);
 3. check: on records of 1024 held-out envs, the network's start lies closer
@@ -38,11 +38,11 @@ def test_label_train_check_and_evaluate_on_held_out_envs():
     from paper_1611_01652_amd import warmstart as WS
 
     t0 = time.time()
-    rec, plain_label_sweeps = WS.label(8192, 500, seed_salt=100, rec_every=1, cap=10_000_000, tol=1e-5)
+    rec, plain_label_sweeps = WS.label(10752, 500, seed_salt=100, rec_every=1, cap=12_000_000, tol=1e-5)
     n = rec.shape[0]
-    _say(f"label: {n} records from 8192 envs x 500 steps in {time.time() - t0:.1f} s, "
+    _say(f"label: {n} records from 10752 envs x 500 steps in {time.time() - t0:.1f} s, "
          f"plain {plain_label_sweeps:.1f} sweeps per env-step")
-    assert n >= 5_000_000
+    assert 10_000_000 <= n < 12_000_000
     assert torch.isfinite(rec[:, :12]).all()
 
     t1 = time.time()
