@@ -360,6 +360,12 @@ def main():
     ap.add_argument("--fuse", action="store_true",
                     help="with kept working sets, call rollout_and_grad (each bucket's reverse right after its own "
                          "forward) instead of rollout_keep and rollout_grad_kept one after the other")
+    ap.add_argument("--tune", metavar="CACHE", default=None,
+                    help="team widths from the tune cache at CACHE (JSON); when the model is not in it yet, tuned "
+                         "on the whole forward + gradient call (one bucket's width at a time) and stored there")
+    ap.add_argument("--tune-steps", type=int, default=None,
+                    help="time the tuning trials on a copy of the workload cut to this many steps (default: the "
+                         "full horizon; shorter copies measured to mislead for the chains)")
     ap.add_argument("--grad-mem-gib", type=float, default=None,
                     help="memory for the reverse sweep's saved working sets (default: what the device has free "
                          "less a 12 GiB margin)")
@@ -385,8 +391,16 @@ def main():
     w.extra = dict(w.extra or {})
     w.extra["grad_mem_limit"] = int(gib * 2**30)
     sim = Simulator(w)
-    print(f"bench: {args.workload} {w.n_envs} envs x {w.T_max} steps, {len(sim.teams())} buckets", file=sys.stderr,
-          flush=True)
+    teams_from = "default"
+    if args.tune:
+        from paper_1611_01652_amd import tune_cache as TC
+        dev_u = lambda ws: torch.tensor(np.ascontiguousarray(controls(ws)), dtype=torch.float32,  # noqa: E731
+                                        device="cuda")
+        _, teams_from = TC.tuned_teams(
+            sim, dev_u, args.tune, short_T=args.tune_steps,
+            log=lambda t, ms: print(f"bench: tune trial {t}: {ms:.1f} ms", file=sys.stderr, flush=True))
+    print(f"bench: {args.workload} {w.n_envs} envs x {w.T_max} steps, {len(sim.teams())} buckets, teams "
+          f"{sim.teams().tolist()} ({teams_from})", file=sys.stderr, flush=True)
     x0 = torch.tensor(np.ascontiguousarray(w.x0.T), dtype=torch.float32, device="cuda")
     u = torch.tensor(np.ascontiguousarray(controls(w)), dtype=torch.float32, device="cuda")
     dl = torch.ones(w.n_envs, dtype=torch.float32, device="cuda")
@@ -513,7 +527,8 @@ def main():
         "config": {"workload": WORKLOAD_NAMES[args.workload],
                    "envs": w.n_envs, "T": int(w.T_max), "bodies": w.n_bodies, "joints": w.n_joints,
                    "pgs_iters": w.n_iters, "dt": w.dt, "ckpt_every": w.ckpt_every,
-                   "parallelism": "single GPU, envs over one-wave workgroups, size buckets on concurrent streams"},
+                   "parallelism": "single GPU, envs over one-wave workgroups, size buckets on concurrent streams",
+                   "teams": teams_from},
         "fwd_env_steps_per_s": env_steps / (fwd_ms * 1e-3),
         "fwd_ms": fwd_ms,
         "grad_ms": grad_ms,

@@ -230,3 +230,48 @@ def test_reverse_sweep_memory_modes_give_the_same_gradient_bits():
         for o in outs[1:]:
             for k in outs[0]:
                 assert torch.equal(outs[0][k], o[k]), k
+
+
+def test_tune_cache_tunes_once_then_reuses(tmp_path):
+    # the first model is tuned on a short copy of itself and stored; a second
+    # handle of the same model gets the stored widths without timing; results
+    # keep every bit
+    import torch
+    from paper_1611_01652_amd import tune_cache as TC
+    from paper_1611_01652_amd.sim import Simulator
+    w = W.uneven_chains(n_envs=256, T=120, seed_salt=23)
+    x0, u = to_dev(w)
+    dl = torch.ones(w.n_envs, device="cuda")
+    path = str(tmp_path / "tune.json")
+    make_u = lambda ws: to_dev(ws)[1]   # noqa: E731
+
+    def run(s):
+        r = s.rollout(x0, u)
+        g = s.rollout_grad(x0, u, r["ckpt"], dl)
+        torch.cuda.synchronize()
+        return [r["loss"], r["x_final"]] + [g[k] for k in sorted(g)]
+
+    s = Simulator(w)
+    default = s.teams()
+    ref = run(s)
+    teams, how = TC.tuned_teams(s, make_u, path, short_T=30, objective="bucket")
+    _say("case tune cache, chains 256 envs x 120 steps: default", default.tolist(), "tuned", teams.tolist(), how)
+    assert how == "tuned" and np.array_equal(s.teams(), teams)
+    assert (teams >= default).all()
+    for a, b in zip(run(s), ref):
+        assert torch.equal(a, b)
+    s.close()
+    s2 = Simulator(w)
+    teams2, how2 = TC.tuned_teams(s2, make_u, path, short_T=30, objective="bucket")
+    assert how2 == "cache" and np.array_equal(teams2, teams) and np.array_equal(s2.teams(), teams)
+    for a, b in zip(run(s2), ref):
+        assert torch.equal(a, b)
+    # the whole-call objective: its own cache entry, widths never below the
+    # default, every result bit kept
+    s2.set_teams(default)
+    teams3, how3 = TC.tuned_teams(s2, make_u, path, short_T=30, objective="call")
+    _say("   whole-call objective:", teams3.tolist(), how3)
+    assert how3 == "tuned" and (teams3 >= default).all() and np.array_equal(s2.teams(), teams3)
+    for a, b in zip(run(s2), ref):
+        assert torch.equal(a, b)
+    s2.close()
