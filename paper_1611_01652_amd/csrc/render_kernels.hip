@@ -124,15 +124,16 @@ __device__ __forceinline__ void stage_spheres(const RenderScene& sc, const float
 // -(d . m) / a and D = (r^2 - |m + t0 d|^2) / a, a = |d|^2: the distance of
 // the ray from the centre, m + t0 d, is formed first, so D does not come
 // from the difference of two terms of the size |m|^2 |d|^2 (which loses
-// every digit of a small D in FP32).  The staged spheres are tested in env
+// every digit of a small D in FP32).  Both quotients by a use one
+// reciprocal of a per pixel (ia).  The staged spheres are tested in env
 // order (index k0 + k); the first of equal nearest roots is kept.
-__device__ __forceinline__ void trace_spheres(const float4* cs, int n, int k0, const Ray& ray, float a, RHit& h) {
+__device__ __forceinline__ void trace_spheres(const float4* cs, int n, int k0, const Ray& ray, float ia, RHit& h) {
   for (int k = 0; k < n; ++k) {
     const float4 cc = cs[k];
     const float m0 = ray.c[0] - cc.x, m1 = ray.c[1] - cc.y, m2 = ray.c[2] - cc.z;
-    const float t0 = -(ray.d[0] * m0 + ray.d[1] * m1 + ray.d[2] * m2) / a;
+    const float t0 = -(ray.d[0] * m0 + ray.d[1] * m1 + ray.d[2] * m2) * ia;
     const float p0 = m0 + t0 * ray.d[0], p1 = m1 + t0 * ray.d[1], p2 = m2 + t0 * ray.d[2];
-    const float D = (cc.w * cc.w - (p0 * p0 + p1 * p1 + p2 * p2)) / a;
+    const float D = (cc.w * cc.w - (p0 * p0 + p1 * p1 + p2 * p2)) * ia;
     if (D < 0.f) continue;
     const float sq = sqrtf(D);
     const float s = t0 - sq >= 1.f ? t0 - sq : t0 + sq;
@@ -147,8 +148,9 @@ __device__ __forceinline__ void trace_ground(const RenderScene& sc, const Ray& r
   }
 }
 
-__device__ __forceinline__ float ray_a(const Ray& ray) {
-  return ray.d[0] * ray.d[0] + ray.d[1] * ray.d[1] + ray.d[2] * ray.d[2];
+// 1 / |d|^2 of the ray
+__device__ __forceinline__ float ray_ia(const Ray& ray) {
+  return 1.f / (ray.d[0] * ray.d[0] + ray.d[1] * ray.d[1] + ray.d[2] * ray.d[2]);
 }
 
 constexpr int kStage = 64;   // spheres staged in LDS at a time by k_render
@@ -164,7 +166,7 @@ __global__ __launch_bounds__(256) void k_render(RenderScene sc, const float* x, 
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   const bool live = p < n;
   const Ray ray = pixel_ray(cam, live ? p % cam.width : 0, live ? p / cam.width : 0);
-  const float a = ray_a(ray);
+  const float ia = ray_ia(ray);
   RHit h{-2, INFINITY};
   const int s0 = sc.env_sph[e], s1 = sc.env_sph[e + 1];
   for (int g0 = s0; g0 < s1; g0 += kStage) {
@@ -172,7 +174,7 @@ __global__ __launch_bounds__(256) void k_render(RenderScene sc, const float* x, 
     __syncthreads();
     stage_spheres(sc, x, g0, g1, cs);
     __syncthreads();
-    trace_spheres(cs, g1 - g0, g0 - s0, ray, a, h);
+    trace_spheres(cs, g1 - g0, g0 - s0, ray, ia, h);
   }
   if (!live) return;
   trace_ground(sc, ray, h);
@@ -232,7 +234,7 @@ __global__ __launch_bounds__(kGradThreads) void k_render_grad(RenderScene sc, co
     if (wt != 0.f) {
       const Ray ray = pixel_ray(cam, p % cam.width, p / cam.width);
       RHit h{-2, INFINITY};
-      trace_spheres(cs, ns, 0, ray, ray_a(ray), h);
+      trace_spheres(cs, ns, 0, ray, ray_ia(ray), h);
       trace_ground(sc, ray, h);
       // the ground and the background do not depend on the state
       if (h.k >= 0) {
