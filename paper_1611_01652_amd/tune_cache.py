@@ -38,8 +38,8 @@ def cache_key(sim) -> str:
     h = hashlib.sha256()
     for a in (sim.teams(), sim.env_buckets(), np.diff(np.asarray(w.env_body_off))):
         h.update(np.ascontiguousarray(a, dtype=np.int64).tobytes())
-    h.update(json.dumps([int(w.n_iters), int(sim.info.grad_store), S.ABI_VERSION,
-                         torch.cuda.get_device_name(torch.cuda.current_device())]).encode())
+    dev = torch.cuda.get_device_name(torch.cuda.current_device()) if torch.cuda.is_available() else "none"
+    h.update(json.dumps([int(w.n_iters), int(sim.info.grad_store), S.ABI_VERSION, dev]).encode())
     return h.hexdigest()[:24]
 
 
