@@ -60,7 +60,8 @@ def _stable_mask(o, cam, ts, tg, cell, x, eps=1e-4):
     return base, stable
 
 
-@pytest.mark.parametrize("width,height", [(96, 48), (288, 96)])
+# (50 x 31 = 1550 pixels: six full workgroups of 256 and a ragged tail of 14)
+@pytest.mark.parametrize("width,height", [(96, 48), (288, 96), (50, 31)])
 def test_images_and_gradients_match_oracle(width, height):
     import torch
     from paper_1611_01652_amd.sim import Simulator
