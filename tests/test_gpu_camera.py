@@ -103,6 +103,34 @@ def test_images_and_gradients_match_oracle(width, height):
     assert np.abs(g[:, 12:]).max() == 0.0
 
 
+def test_image_of_an_env_with_more_spheres_than_one_staging_chunk():
+    # 70 unjointed spheres in one env (no pair contacts, so the model fits the
+    # step's LDS): the image kernel stages an env's spheres 64 at a time, and
+    # the nearest hit must be found across the chunks; a ragged frame
+    import torch
+    from paper_1611_01652_amd.sim import Simulator
+    rng = np.random.default_rng(41)
+    n = 70
+    pos = np.column_stack([rng.uniform(-1.0, 1.0, n), rng.uniform(-1.0, 1.0, n), rng.uniform(0.1, 0.9, n)])
+    w = W.free_spheres(pos, rng.uniform(0.05, 0.15, n), rng.uniform(0.5, 2.0, n), T=1)
+    w.sphere_flags = (np.asarray(w.sphere_flags) & ~2).astype(np.int32)
+    cam = W.pinhole_camera((0.2, -3.0, 1.2), (0.0, 0.0, 0.4), focal=1.0, pitch=1.6 / 40, width=40, height=27)
+    ts, tg, cell = W.synthetic_texture(32, 16, 8), W.synthetic_texture(24, 24, 9), 0.25
+    o = Oracle(w)
+    ref, stable = _stable_mask(o, _ocam(cam), ts, tg, cell, W.f32(np.asarray(w.x0, np.float64)))
+    _say(f"case camera {n} spheres in one env, 40x27, stable pixels {stable.mean():.3f}, "
+         f"pixels that show a sphere or the ground {(ref > 0).mean():.3f}")
+    assert stable.mean() >= 0.85
+    s = Simulator(w)
+    xd = torch.tensor(np.ascontiguousarray(w.x0.T), dtype=torch.float32, device="cuda")
+    tsd = torch.tensor(ts, dtype=torch.float32, device="cuda")
+    tgd = torch.tensor(tg, dtype=torch.float32, device="cuda")
+    img = s.render(xd, cam, tsd, tgd, cell)
+    err = np.abs(img.cpu().numpy().astype(np.float64) - ref)[stable]
+    _say("   image: max error on stable pixels", err.max())
+    assert err.max() <= 1e-4
+
+
 def test_too_many_spheres_for_the_gradient_is_refused():
     import torch
     from paper_1611_01652_amd.sim import SimError, Simulator
