@@ -36,10 +36,12 @@ def _ocam(c):
     return o
 
 
-def _scene(n_envs=6, steps=40, seed_salt=31):
+def _scene(n_envs=6, steps=40, seed_salt=31, sizes=None):
     # chains of 3..12 spheres after some steps of falling and tumbling (turned
     # bodies), seen from the side and above
-    sizes = np.random.default_rng(seed_salt).integers(3, 13, n_envs)
+    if sizes is None:
+        sizes = np.random.default_rng(seed_salt).integers(3, 13, n_envs)
+    n_envs = len(sizes)
     w = W.uneven_chains(n_envs=n_envs, T=steps, seed_salt=seed_salt, sizes=sizes)
     o = Oracle(w)
     x, lam = np.asarray(w.x0, np.float64), np.zeros(o.lam_size)
@@ -60,12 +62,14 @@ def _stable_mask(o, cam, ts, tg, cell, x, eps=1e-4):
     return base, stable
 
 
-# (50 x 31 = 1550 pixels: six full workgroups of 256 and a ragged tail of 14)
-@pytest.mark.parametrize("width,height", [(96, 48), (288, 96), (50, 31)])
-def test_images_and_gradients_match_oracle(width, height):
+# (50 x 31 = 1550 pixels: six full workgroups of 256 and a ragged tail of 14;
+# the last case puts envs at the gradient's limit of 16 spheres)
+@pytest.mark.parametrize("width,height,sizes", [(96, 48, None), (288, 96, None), (50, 31, None),
+                                                (96, 48, (16, 2, 16, 9))])
+def test_images_and_gradients_match_oracle(width, height, sizes):
     import torch
     from paper_1611_01652_amd.sim import Simulator
-    w, x = _scene()
+    w, x = _scene(sizes=None if sizes is None else np.array(sizes))
     cam = W.pinhole_camera((0.3, -3.5, 1.6), (0.0, 0.0, 0.3), focal=1.0, pitch=1.6 / width, width=width,
                            height=height)
     ts, tg, cell = W.synthetic_texture(32, 16, 3), W.synthetic_texture(24, 24, 4), 0.25
