@@ -208,10 +208,10 @@ sim_status build_env(const sim_model_desc& d, int e, bool keep_v, HostEnv& H) {
     ma = mlp_adj_floats(d.mlp_sizes[0], d.mlp_sizes[1], d.mlp_sizes[2], d.mlp_sizes[3]);
   }
   const int vs = vsave_floats(keep_v, H.nb);
-  H.fwd_floats = make_lay(H.nb, H.nj, H.G, H.P, H.ncol, H.ncand, H.nslot, H.lam, d.n_iters, false, mf, ma, vs).total;
-  H.adj_floats = make_lay(H.nb, H.nj, H.G, H.P, H.ncol, H.ncand, H.nslot, H.lam, d.n_iters, true, mf, ma, vs).total;
+  H.fwd_floats = make_lay(H.nb, H.nj, H.G, H.P, H.ncol, H.ncand, H.nj + H.ccap, H.nslot, H.lam, d.n_iters, false, mf, ma, vs).total;
+  H.adj_floats = make_lay(H.nb, H.nj, H.G, H.P, H.ncol, H.ncand, H.nj + H.ccap, H.nslot, H.lam, d.n_iters, true, mf, ma, vs).total;
   H.adj_floats_ring =
-      make_lay(H.nb, H.nj, H.G, H.P, H.ncol, H.ncand, H.nslot, H.lam, d.n_iters, true, mf, ma, vs, true).total;
+      make_lay(H.nb, H.nj, H.G, H.P, H.ncol, H.ncand, H.nj + H.ccap, H.nslot, H.lam, d.n_iters, true, mf, ma, vs, true).total;
   H.dump_floats = dump_stride_of(H.fwd_floats, d.n_iters, H.nslot, H.nb);
   return SIM_OK;
 }

@@ -201,7 +201,8 @@ enum { JA_DAMP = 0, JA_DAMPC = 1, JA_ANCP = 2, JA_ANCC = 5, JA_ANC_COMP = 6, JA_
 // vs_f: floats of saved predicted velocities (learned warm start, restitution), 0 without
 // ring: the adjoint layout holds HRING sweeps of the impulse history instead
 // of all of them and the start impulses
-SHD Lay make_lay(int nb, int nj, int G, int P, int ncol, int ncand, int nslot, int lam, int n_iters, bool adj,
+SHD Lay make_lay(int nb, int nj, int G, int P, int ncol, int ncand, int nvis, int nslot, int lam, int n_iters,
+                 bool adj,
                  int mlp_f = 0, int mlp_a = 0, int vs_f = 0, bool ring = false) {
   Lay L;
   L.hring = adj && ring ? HRING : 0;
@@ -217,7 +218,7 @@ SHD Lay make_lay(int nb, int nj, int G, int P, int ncol, int ncand, int nslot, i
   L.act_code = o; o += align4(ncand);
   L.live = o; o += align4(ncol + 3);
   L.plan = o; o += 4 * ncol;
-  L.vis = o; o += 4 * ncand;
+  L.vis = o; o += 4 * nvis;   // the constraints a step places: every joint and up to ccap contacts
   L.misc = o; o += MISC_N;
   L.grp = o; o += align4(nb + 1);
   L.mlp = o; o += align4(mlp_f);
@@ -346,7 +347,8 @@ SHD Env make_env(const DevModel& M, int ie, float* lds, int n_iters, bool adj) {
   E.L = lds;
   // (the reverse of saved working sets may keep a ring of the impulse
   // history: an env flagged for it in its header)
-  E.lay = make_lay(E.nb, E.nj, E.G, E.P, E.ncol, E.ncand, E.nslot, E.lam_size, n_iters, adj, mlp_floats_fwd(M),
+  E.lay = make_lay(E.nb, E.nj, E.G, E.P, E.ncol, E.ncand, E.nj + E.ccap, E.nslot, E.lam_size, n_iters, adj,
+                   mlp_floats_fwd(M),
                    mlp_floats_adj(M), vsave_floats(M.ws_kind || M.has_rest, E.nb),
                    M.dump != DUMP_REPLAY && h[H_RING] != 0);
   return E;
@@ -793,7 +795,11 @@ SHD void build_contact(const DevModel& M, const Env& E, int code, int s, const C
 // its own row and its two bodies), so a merged visit gives the same bits as
 // the colours one after another, with fewer visits per sweep: a long chain's
 // pair contacts fall into many colours with one or two active pairs each.
-// vis() holds the active constraints contiguously, visit by visit.
+// vis() holds the placed constraints contiguously, visit by visit: every
+// active joint and the active contacts that found a row slot (a contact
+// beyond the env's capacity is dropped and the env flagged, and gets no
+// entry), so it needs nj + ccap entries; the colour's active lists
+// (act_code, act_slot, act_cnt) keep every active constraint.
 template <class Team>
 SHD void f_rows(const Team& tm, const DevModel& M, const Env& E, bool act) {
   // Joint rows depend only on the step's body state, so all joints are built
@@ -802,7 +808,7 @@ SHD void f_rows(const Team& tm, const DevModel& M, const Env& E, bool act) {
   for (int j = tm.tl; j < nj; j += tm.ts) build_joint(M, E, j, E.jr * j);
   for (int b = tm.tl; b <= (act ? E.nb : -1); b += tm.ts) E.grp()[b] = -2;
   tm.sync();
-  int ncon = 0;                    // contacts placed so far (team-uniform)
+  int ncon = 0;                    // active contacts so far, placed while below ccap (team-uniform)
   int voff = 0;                    // entries of vis() so far
   int np = 0;                      // plan entries opened so far
   int gstart = 0, gcnt = 0, gkind = -1;   // the open plan entry
@@ -810,7 +816,8 @@ SHD void f_rows(const Team& tm, const DevModel& M, const Env& E, bool act) {
     int lo = 0, hi = 0;
     if (act && c < E.ncol) { lo = E.colstart(c); hi = E.colstart(c + 1); }
     const bool jcol = hi > lo && cand_kind(E.cand(lo)) == K_JOINT;
-    int cnt = 0;
+    int cnt = 0;          // active constraints of this colour
+    int vcnt = 0;         // of them placed (vis entries)
     bool clash = false;   // this lane's constraints touch a body of the open entry
     for (int base = lo; tm.any(base < hi); base += tm.ts) {
       const int i = base + tm.tl;
@@ -831,13 +838,16 @@ SHD void f_rows(const Team& tm, const DevModel& M, const Env& E, bool act) {
       }
       int total = 0;
       const int pos = tm.prefix(on, total);
+      // placed: every joint; the contacts while the capacity lasts, i.e. the
+      // first `room` active ones of this pass (team-uniform)
+      const int room = jcol ? total : (E.ccap - ncon <= 0 ? 0 : (E.ccap - ncon < total ? E.ccap - ncon : total));
       if (on) {
         const int li = lo + cnt + pos;   // position in the colour's active list
         E.act_code()[li] = code;
         int s = -1;
         if (jcol) {
           s = E.jr * cand_idx(code);
-        } else if (ncon + pos < E.ccap) {
+        } else if (pos < room) {
           s = E.jr * E.nj + 4 * (ncon + pos);
           build_contact(M, E, code, s, g);
         } else {
@@ -847,16 +857,19 @@ SHD void f_rows(const Team& tm, const DevModel& M, const Env& E, bool act) {
           (*reinterpret_cast<int*>(E.misc() + MISC_FLAGS)) |= 2;
         }
         E.act_slot()[li] = s;
-        const RowB rb = cand_bodies(E, code);
-        E.vis()[voff + cnt + pos] = i4{s, rb.a >= 0 ? rb.a : E.nb, rb.b, code};
-        if (!jcol) clash = clash || (rb.a >= 0 && E.grp()[rb.a] == np - 1) || E.grp()[rb.b] == np - 1;
+        if (pos < room) {
+          const RowB rb = cand_bodies(E, code);
+          E.vis()[voff + vcnt + pos] = i4{s, rb.a >= 0 ? rb.a : E.nb, rb.b, code};
+          if (!jcol) clash = clash || (rb.a >= 0 && E.grp()[rb.a] == np - 1) || E.grp()[rb.b] == np - 1;
+        }
       }
       cnt += total;
+      vcnt += room;
       if (!jcol) ncon += total;
     }
     if (act && c < E.ncol) E.act_cnt()[c] = cnt;
     const bool merge = !tm.team_any(clash) && !jcol && gkind == 0;
-    if (cnt > 0) {
+    if (vcnt > 0) {
       if (!merge) {
         if (gcnt > 0 && tm.tl == 0) E.plan()[np - 1] = i4{gstart, gcnt, gkind, 0};
         ++np;
@@ -864,16 +877,16 @@ SHD void f_rows(const Team& tm, const DevModel& M, const Env& E, bool act) {
         gcnt = 0;
         gkind = jcol ? 1 : 0;
       }
-      gcnt += cnt;
+      gcnt += vcnt;
       // the open entry's bodies: this colour's constraints touch distinct
       // bodies (the world slot aside, which is not marked)
       if (!jcol)
-        for (int k = tm.tl; k < cnt; k += tm.ts) {
+        for (int k = tm.tl; k < vcnt; k += tm.ts) {
           const i4 v = E.vis()[voff + k];
           E.grp()[v.z] = np - 1;
           if (v.y < E.nb) E.grp()[v.y] = np - 1;
         }
-      voff += cnt;
+      voff += vcnt;
     }
     tm.sync();
   }

@@ -28,6 +28,12 @@ def _bouncy(w, e, seed):
     return w
 
 
+def _pile(n, T):
+    rng = np.random.default_rng(1)
+    pos = np.c_[rng.uniform(-0.1, 0.1, (n, 2)), rng.uniform(0.05, 0.2, n)]
+    return W.free_spheres(pos, [0.1] * n, [1.0] * n, T=T)
+
+
 def _store(w, mode):
     w.extra = dict(w.extra or {})
     w.extra["grad_store"] = mode
@@ -49,6 +55,8 @@ CASES = {
     "servo-chains": lambda: W.servo_chains(3, 20),
     "bouncy-chains": lambda: _bouncy(W.uneven_chains(n_envs=2, T=70, seed_salt=6), 0.8, 3),
     "balls": lambda: W.paper_ball_throws(n_envs=3, T=80),
+    # 12 overlapping spheres: more active contacts than the env's capacity
+    "overflow": lambda: _pile(12, 5),
 }
 SOLVE_CASES = {
     "solve-learned": lambda: W.warm_start_chains(n_envs=4, T=25, seed_salt=3, ws_w=W.wsn_init(seed_salt=2),
